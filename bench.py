@@ -1,0 +1,156 @@
+"""Throughput of the full hierarchy build on one MI355X.
+
+One step = one complete build of the adaptive density hierarchy (Morton keys,
+stable sort, per-level counts, refinement flags, TSC deposit, FP64 totals,
+grid-tree labels) of the 16.8M-particle lattice + NFW-halo snapshot (256^3
+particles, 128^3 domain grid, threshold 5, up to 10 levels), with the input
+already resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particles/s through full hierarchy build (1 GPU, % HBM peak); p50/p99 latency"
+
+
+def algorithmic_bytes(n, levels, sp=24):
+    """Bytes the method itself must move per build (inputs read once, one
+    read+write of the key/index pairs, the sorted payload written once, and
+    per level the particles of S_L read once plus the cell arrays written)."""
+    b = n * sp + 24 * n + n * sp
+    for d in levels:
+        b += d["n_particles"] * sp + d["n_cells"] * 16 + 8 * d["n_bricks"] * 4 + d["n_cells"] * 4
+    return b
+
+
+def cpu_baseline(snap, seconds_target=20.0):
+    """The FP64 oracle on a bounded random sample of the same workload."""
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(12345))
+    n = min(snap.n, 1 << 20)
+    idx = np.sort(rng.choice(snap.n, n, replace=False))
+    sub = snap.subset(idx, "sample")
+    t0 = time.perf_counter()
+    oracle.build(sub)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} particles drawn at random (seed 12345) from the 16.8M snapshot, "
+                      f"same grid parameters, single-threaded FP64 oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="16m", choices=["16m", "32k"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0904_3662_amd import ahf, synth
+
+    t0 = time.perf_counter()
+    snap = synth.snapshot_16m(1) if args.workload == "16m" else synth.small_mixed(0)
+    print(f"# generated {snap.name}: {snap.n} particles in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    dev = ahf.snapshot_to_device(snap)
+    torch.cuda.synchronize()
+    ctx = ahf.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        h, _ = ahf.build_snapshot(ctx, snap, dev=dev, stream=stream)
+        return h
+
+    for i in range(args.warmup):
+        h = step()
+        if i == 0:
+            levels = [h.view(L) for L in range(h.num_levels())]
+            lv_info = [dict(n_particles=v.n_particles, n_cells=v.n_cells, n_bricks=v.n_bricks,
+                            n_refined=v.n_refined, n_patches=v.n_patches) for v in levels]
+        h.free()
+        print(f"# warmup {i} done", file=sys.stderr, flush=True)
+    if args.warmup == 0:
+        h = step()
+        lv_info = [dict(n_particles=h.view(L).n_particles, n_cells=h.view(L).n_cells,
+                        n_bricks=h.view(L).n_bricks, n_refined=h.view(L).n_refined,
+                        n_patches=h.view(L).n_patches) for L in range(h.num_levels())]
+        h.free()
+
+    ctx.set_profiling(True)
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        h = step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+        h.free()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    kstats = {}
+    for name in ("rs_scatter", "rs_hist", "keys", "gather", "level0_start", "child_ranges",
+                 "heavy_chunk", "patches", "combine", "mark", "uf_hook"):
+        kstats[name] = ctx.kernel_time(name)
+    ctx.set_profiling(False)
+    print(f"# steps done: {args.steps} in {total:.3f} s", file=sys.stderr, flush=True)
+
+    n = snap.n
+    ms_per_step = total * 1e3 / args.steps
+    value = n * args.steps / total
+    launches, tms = kstats["rs_scatter"]
+    avg_ms = tms / max(launches, 1)
+    alg_bytes_launch = 24.0 * n          # one read + one write of (uint64 key, uint32 index)
+    achieved = alg_bytes_launch / (avg_ms * 1e-3) / 1e9 if launches else None
+    b_alg = algorithmic_bytes(n, lv_info)
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": snap.name, "particles": n, "domain_grid": 1 << snap.g,
+                   "threshold": snap.dom_ref, "max_levels": snap.max_levels,
+                   "levels_built": len(lv_info)},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "end_to_end_hbm_frac": b_alg / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "roofline": {"bound": "hbm", "kernel": "rs_scatter", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
+                     "traffic": None, "avg_launch_ms": avg_ms, "launches": launches},
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kstats.items()},
+        "levels": lv_info,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(snap)
+    ctx.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * ahf.h -- C ABI of the MI355X adaptive density hierarchy library (libahf.so).
+ *
+ * The library builds the grid hierarchy of AHF (Knollmann & Knebe, "AHF:
+ * AMIGA's Halo Finder", Sect. 2.1): a domain grid covering the periodic box,
+ * particle-density assignment with triangular-shaped-cloud (TSC) weights,
+ * refinement of every cell whose particle count exceeds the threshold into
+ * 8 half-size cells, repeated until no cell needs refinement, and the grid
+ * tree of isolated refinements linked to the coarser volume that holds them.
+ *
+ * Conventions shared by every entry point
+ *  - Positions: a particle at unit-box coordinate x is given as X + f quanta
+ *    of 2^-21 per axis, X a uint32 below 2^21 and f a float in [0, 1).
+ *  - Levels: level 0 is the domain grid with 2^g cells per axis; level L has
+ *    b = g + L bits per axis.  Cell (x, y, z) of level L has the Morton key
+ *    with bit 3j+2 = x_j, bit 3j+1 = y_j, bit 3j = z_j (j < b).
+ *  - S_L: the cells of level L (level 0: all 2^{3g}; level L >= 1: the 8
+ *    children of every refined cell of level L-1, empty children included).
+ *    A cell is refined when its particle count is strictly greater than the
+ *    threshold (dom_ref on level 0, ref_ref above), below the level cap.
+ *  - The mass field of level L holds, for every particle inside S_L, its TSC
+ *    share on the cells within one cell of it (periodic).  It is stored as
+ *    bricks of 2x2x2 cells; each brick is keyed by its parent cell of level
+ *    L-1 and the bricks cover every cell within one cell of S_L.  Cells of a
+ *    brick that lie farther from S_L hold 0.  Level 0 has every brick.
+ *  - Device pointers are HIP device addresses; host pointers are marked.
+ *  - Every call returns an ahf_status; on failure *out parameters are set to
+ *    NULL/0 and ahf_last_error() describes the failure.  No call throws.
+ *  - Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef AHF_H
+#define AHF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ahf_status;
+enum {
+    AHF_OK = 0,
+    AHF_PENDING = 1,       /* ahf_poll only: the request has not finished  */
+    AHF_EINVAL = -1,       /* bad argument or out-of-range particle coordinate */
+    AHF_ENOMEM = -2,       /* device or host allocation failed              */
+    AHF_EDEVICE = -3,      /* a HIP runtime call failed                     */
+    AHF_ELIMIT = -4,       /* size beyond what the library or budget allows  */
+    AHF_EBUSY = -5,        /* server queue full                             */
+    AHF_ENOTFOUND = -6,    /* unknown ticket                                */
+    AHF_ECANCELED = -7     /* request released before it finished           */
+};
+
+/* flags of ahf_params */
+#define AHF_NO_LABELS 1u   /* ahf_build_hierarchy skips the grid tree        */
+
+typedef struct ahf_ctx ahf_ctx;
+typedef struct ahf_hierarchy ahf_hierarchy;
+typedef struct ahf_server ahf_server;
+
+/* Device memory callbacks.  alloc returns a device pointer of at least
+ * `bytes` usable in stream order on `stream`, or NULL; free releases it. */
+typedef void *(*ahf_alloc_fn)(void *user, size_t bytes, void *stream);
+typedef void (*ahf_free_fn)(void *user, void *ptr, size_t bytes, void *stream);
+
+typedef struct {
+    uint32_t struct_size;  /* sizeof(ahf_ctx_desc) */
+    int32_t device;        /* HIP device ordinal */
+    ahf_alloc_fn alloc;    /* NULL: the library's own caching pool on hipMalloc */
+    ahf_free_fn free;
+    void *user;
+} ahf_ctx_desc;
+
+/* Parameters (Sect. 2.1 and 2.3 of the paper: DomGrid, DomRef, RefRef). */
+typedef struct {
+    uint32_t struct_size;    /* sizeof(ahf_params) */
+    uint32_t dom_grid_log2;  /* g: DomGrid = 2^g cells per axis, 1..10      */
+    double dom_ref;          /* level-0 threshold: refine if count > dom_ref */
+    double ref_ref;          /* threshold on refined levels                  */
+    uint32_t max_levels;     /* refinement levels beyond the domain grid;
+                                g + max_levels <= 21                         */
+    uint32_t connectivity;   /* 6, 18 or 26 (0 means 26): adjacency of the
+                                isolated refinements                          */
+    uint32_t flags;          /* AHF_NO_LABELS                                 */
+} ahf_params;
+
+/* Particle snapshot.  All arrays are device pointers of n elements, borrowed:
+ * they must stay valid and unchanged until the build has passed on its stream
+ * (or, for the server, until ahf_poll returns something other than PENDING).
+ * fx/fy/fz may be NULL (offsets 0).  mass may be NULL (every particle weighs
+ * mass_scalar). */
+typedef struct {
+    uint64_t n;              /* < 2^32 */
+    const uint32_t *x, *y, *z;
+    const float *fx, *fy, *fz;
+    const float *mass;
+    double mass_scalar;
+} ahf_particles;
+
+/* One level of a built hierarchy.  Device pointers stay valid until the
+ * hierarchy is freed; NULL marks data that is not there (see each field). */
+typedef struct {
+    uint32_t level;
+    uint32_t bits;                 /* b = g + level                              */
+    uint64_t n_cells;              /* |S_L|                                      */
+    uint64_t n_refined;            /* cells of S_L that are refined              */
+    uint64_t n_particles;          /* particles inside S_L                       */
+    uint64_t n_bricks;             /* bricks of the mass field                   */
+    uint64_t n_patches;            /* isolated refinements (level >= 1, labelled) */
+    const uint64_t *cell_key;      /* [n_cells] ascending; NULL on level 0, where
+                                      cell i has key i                          */
+    const uint32_t *cell_start;    /* [n_cells] first position in the particle
+                                      order (ahf_hierarchy_order)               */
+    const uint32_t *cell_count;    /* [n_cells]                                  */
+    const uint8_t *cell_refined;   /* [n_cells] 1 if refined                     */
+    const int32_t *cell_patch;     /* [n_cells] patch id; NULL on level 0 or
+                                      before labelling                          */
+    const uint64_t *brick_key;     /* [n_bricks] ascending parent keys (level
+                                      L-1); NULL on level 0 (brick i has key i) */
+    const int32_t *brick_cell;     /* [n_bricks] index in S_L of the brick's
+                                      first cell, or -1 when the brick holds only
+                                      ghost cells; NULL on level 0 (8 i)        */
+    const float *brick_mass;       /* [8 n_bricks] TSC mass per cell; cell d of
+                                      a brick has key 8*brick_key + d           */
+    const int32_t *patch_parent;   /* [n_patches] patch id on level L-1, -1 on
+                                      level 1 (the domain grid is the root)      */
+    const uint32_t *patch_ncells;  /* [n_patches] cells of S_L in the patch      */
+    const uint64_t *patch_nparticles; /* [n_patches]                            */
+    const double *patch_mass;      /* [n_patches] particle mass in the patch     */
+    double total_cell_mass;        /* sum of brick_mass (FP64 sum)               */
+    double total_particle_mass;    /* mass of the particles inside S_L (FP64)    */
+} ahf_level_view;
+
+const char *ahf_last_error(void);
+
+ahf_status ahf_ctx_create(const ahf_ctx_desc *desc, ahf_ctx **out);
+void ahf_ctx_destroy(ahf_ctx *ctx);
+
+/*
+ * Build the hierarchy of one snapshot on `stream` (a hipStream_t; NULL =
+ * the default stream).  Steps: Morton keys and their stable sort; per
+ * level, cell counts, refinement flags, TSC deposit, FP64 totals; the
+ * grid tree unless AHF_NO_LABELS.  Returns when the hierarchy is complete
+ * on the stream (the call synchronises the stream).  Errors: AHF_EINVAL for
+ * bad parameters (checked before any launch) or a coordinate >= 2^21
+ * (detected on the device), AHF_ENOMEM, AHF_EDEVICE.
+ */
+ahf_status ahf_build_hierarchy(ahf_ctx *ctx, const ahf_particles *particles,
+                               const ahf_params *params, void *stream,
+                               ahf_hierarchy **out);
+
+/*
+ * Grid tree of Sect. 2.1: on every level L >= 1 the connected components of
+ * S_L (params.connectivity, periodic) are the isolated refinements.  Patch
+ * ids follow the smallest Morton key of each component; a patch's parent is
+ * the patch of level L-1 containing its parent cells.  Fills cell_patch and
+ * the patch arrays of every level view.  Idempotent.
+ */
+ahf_status ahf_label_refinements(ahf_ctx *ctx, ahf_hierarchy *h, void *stream);
+
+ahf_status ahf_hierarchy_num_levels(const ahf_hierarchy *h, uint32_t *out);
+ahf_status ahf_level_get(const ahf_hierarchy *h, uint32_t level, ahf_level_view *out);
+
+/* Particle order: sorted_idx[i] is the input index of the i-th particle in
+ * ascending B-bit Morton key (B = g + max_levels), ties by input index.  The
+ * particles of every cell of every level are contiguous in this order. */
+ahf_status ahf_hierarchy_order(const ahf_hierarchy *h, const uint32_t **sorted_idx);
+
+/* Per-build stage times in milliseconds (host clock around the stream work),
+ * for profiling: [0] keys+sort, [1] levels, [2] labels, [3] total.  n <= 4. */
+ahf_status ahf_hierarchy_timings(const ahf_hierarchy *h, double *ms, uint32_t n);
+
+void ahf_hierarchy_free(ahf_hierarchy *h);
+
+/*
+ * Kernel timing for profiling.  While enabled, the context records a pair of
+ * HIP events on the build stream around every launch of its main kernels
+ * ("keys", "rs_hist", "rs_scatter", "gather", "level0_start", "child_ranges",
+ * "heavy_chunk", "patches", "combine", "mark", "uf_hook").  Enabling or
+ * disabling clears the accumulated times.  ahf_ctx_kernel_time returns the
+ * number of launches and their summed device time (ms) for one name, reading
+ * the events of finished builds.
+ */
+ahf_status ahf_ctx_set_profiling(ahf_ctx *ctx, int enable);
+ahf_status ahf_ctx_kernel_time(ahf_ctx *ctx, const char *kernel, uint64_t *launches,
+                               double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AHF_H */

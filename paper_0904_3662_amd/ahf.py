@@ -1,0 +1,304 @@
+"""Python binding of libahf.so (ctypes; argument marshalling only).
+
+Every step of the hierarchy runs in the library's HIP kernels.  PyTorch only
+provides device memory (input tensors) and streams.  If the library has not
+been built, every call raises: there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libahf.so")
+
+AHF_OK, AHF_PENDING = 0, 1
+AHF_EINVAL, AHF_ENOMEM, AHF_EDEVICE, AHF_ELIMIT = -1, -2, -3, -4
+AHF_EBUSY, AHF_ENOTFOUND, AHF_ECANCELED = -5, -6, -7
+AHF_NO_LABELS = 1
+
+# every symbol declared in include/ahf.h
+EXPORTS = [
+    "ahf_last_error", "ahf_ctx_create", "ahf_ctx_destroy", "ahf_build_hierarchy",
+    "ahf_label_refinements", "ahf_hierarchy_num_levels", "ahf_level_get",
+    "ahf_hierarchy_order", "ahf_hierarchy_timings", "ahf_hierarchy_free",
+    "ahf_ctx_set_profiling", "ahf_ctx_kernel_time",
+]
+
+
+class AhfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ahf error {code}: {msg}")
+        self.code = code
+
+
+class CtxDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("device", C.c_int32), ("alloc", C.c_void_p),
+                ("free", C.c_void_p), ("user", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("dom_grid_log2", C.c_uint32),
+                ("dom_ref", C.c_double), ("ref_ref", C.c_double), ("max_levels", C.c_uint32),
+                ("connectivity", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class Particles(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("fx", C.c_void_p), ("fy", C.c_void_p), ("fz", C.c_void_p),
+                ("mass", C.c_void_p), ("mass_scalar", C.c_double)]
+
+
+class LevelView(C.Structure):
+    _fields_ = [("level", C.c_uint32), ("bits", C.c_uint32), ("n_cells", C.c_uint64),
+                ("n_refined", C.c_uint64), ("n_particles", C.c_uint64),
+                ("n_bricks", C.c_uint64), ("n_patches", C.c_uint64),
+                ("cell_key", C.c_void_p), ("cell_start", C.c_void_p),
+                ("cell_count", C.c_void_p), ("cell_refined", C.c_void_p),
+                ("cell_patch", C.c_void_p), ("brick_key", C.c_void_p),
+                ("brick_cell", C.c_void_p), ("brick_mass", C.c_void_p),
+                ("patch_parent", C.c_void_p), ("patch_ncells", C.c_void_p),
+                ("patch_nparticles", C.c_void_p), ("patch_mass", C.c_void_p),
+                ("total_cell_mass", C.c_double), ("total_particle_mass", C.c_double)]
+
+
+_lib = None
+_hip = None
+
+
+def load():
+    """Load libahf.so; raises if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: the HIP library must be built first")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.ahf_last_error.restype = C.c_char_p
+    L.ahf_ctx_create.argtypes = [C.POINTER(CtxDesc), C.POINTER(vp)]
+    L.ahf_ctx_destroy.argtypes = [vp]
+    L.ahf_ctx_destroy.restype = None
+    L.ahf_build_hierarchy.argtypes = [vp, C.POINTER(Particles), C.POINTER(Params), vp, C.POINTER(vp)]
+    L.ahf_label_refinements.argtypes = [vp, vp, vp]
+    L.ahf_hierarchy_num_levels.argtypes = [vp, C.POINTER(C.c_uint32)]
+    L.ahf_level_get.argtypes = [vp, C.c_uint32, C.POINTER(LevelView)]
+    L.ahf_hierarchy_order.argtypes = [vp, C.POINTER(vp)]
+    L.ahf_hierarchy_timings.argtypes = [vp, C.POINTER(C.c_double), C.c_uint32]
+    L.ahf_ctx_set_profiling.argtypes = [vp, C.c_int]
+    L.ahf_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
+    L.ahf_hierarchy_free.argtypes = [vp]
+    L.ahf_hierarchy_free.restype = None
+    for name in EXPORTS:
+        if name not in ("ahf_ctx_destroy", "ahf_hierarchy_free", "ahf_last_error"):
+            getattr(L, name).restype = C.c_int32
+    _lib = L
+    return L
+
+
+def _hip_runtime():
+    """libamdhip64 for device-to-host copies of the level arrays."""
+    global _hip
+    if _hip is None:
+        for name in ("libamdhip64.so", "/opt/rocm/lib/libamdhip64.so"):
+            try:
+                _hip = C.CDLL(name)
+                break
+            except OSError:
+                continue
+        if _hip is None:
+            raise RuntimeError("libamdhip64.so not found")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    return _hip
+
+
+def to_host(ptr: int | None, n: int, dtype) -> np.ndarray | None:
+    """Copy n elements at device address ptr into a new numpy array."""
+    if not ptr:
+        return None
+    out = np.empty(int(n), dtype=dtype)
+    if n:
+        rc = _hip_runtime().hipMemcpy(out.ctypes.data, ptr, out.nbytes, 2)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy failed with {rc}")
+    return out
+
+
+def _check(rc):
+    if rc != AHF_OK:
+        msg = load().ahf_last_error()
+        raise AhfError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        L = load()
+        d = CtxDesc(C.sizeof(CtxDesc), int(device), None, None, None)
+        h = C.c_void_p()
+        _check(L.ahf_ctx_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load().ahf_ctx_destroy(self._h)
+            self._h = None
+
+    def set_profiling(self, on: bool):
+        _check(load().ahf_ctx_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_time(self, name: str):
+        """(launches, total device ms) of one kernel while profiling."""
+        n = C.c_uint64()
+        t = C.c_double()
+        _check(load().ahf_ctx_kernel_time(self._h, name.encode(), C.byref(n), C.byref(t)))
+        return int(n.value), float(t.value)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def make_params(g, dom_ref, ref_ref, max_levels, connectivity=26, flags=0) -> Params:
+    return Params(C.sizeof(Params), int(g), float(dom_ref), float(ref_ref), int(max_levels),
+                  int(connectivity), int(flags))
+
+
+def make_particles(x, y, z, fx=None, fy=None, fz=None, mass=None, mass_scalar=1.0) -> Particles:
+    for t in (x, y, z):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("x, y, z must be contiguous device tensors")
+    return Particles(int(x.numel()), _ptr(x), _ptr(y), _ptr(z), _ptr(fx), _ptr(fy), _ptr(fz),
+                     _ptr(mass), float(mass_scalar))
+
+
+class Hierarchy:
+    """A built hierarchy; level arrays stay on the device until copied."""
+
+    def __init__(self, handle, keep=None):
+        self._h = handle
+        self._keep = keep  # input tensors stay alive while the build may read them
+
+    @property
+    def handle(self):
+        return self._h
+
+    def num_levels(self) -> int:
+        n = C.c_uint32()
+        _check(load().ahf_hierarchy_num_levels(self._h, C.byref(n)))
+        return int(n.value)
+
+    def view(self, level: int) -> LevelView:
+        v = LevelView()
+        _check(load().ahf_level_get(self._h, int(level), C.byref(v)))
+        return v
+
+    def order_ptr(self) -> int:
+        p = C.c_void_p()
+        _check(load().ahf_hierarchy_order(self._h, C.byref(p)))
+        return p.value or 0
+
+    def timings(self):
+        a = (C.c_double * 4)()
+        _check(load().ahf_hierarchy_timings(self._h, a, 4))
+        return list(a)
+
+    def order_numpy(self, n: int) -> np.ndarray:
+        out = to_host(self.order_ptr(), n, np.uint32)
+        return np.zeros(0, np.uint32) if out is None else out
+
+    def level_numpy(self, level: int) -> dict:
+        v = self.view(level)
+        nS, nB, nP = v.n_cells, v.n_bricks, v.n_patches
+        d = dict(level=v.level, bits=v.bits, n_cells=nS, n_refined=v.n_refined,
+                 n_particles=v.n_particles, n_bricks=nB, n_patches=nP,
+                 total_cell_mass=v.total_cell_mass,
+                 total_particle_mass=v.total_particle_mass)
+        d["cell_key"] = to_host(v.cell_key, nS, np.uint64)
+        if d["cell_key"] is None:
+            d["cell_key"] = np.arange(nS, dtype=np.uint64)
+        d["cell_start"] = to_host(v.cell_start, nS, np.uint32)
+        d["cell_count"] = to_host(v.cell_count, nS, np.uint32)
+        d["cell_refined"] = to_host(v.cell_refined, nS, np.uint8)
+        d["cell_patch"] = to_host(v.cell_patch, nS, np.int32)
+        bk = to_host(v.brick_key, nB, np.uint64)
+        d["brick_key"] = np.arange(nB, dtype=np.uint64) if bk is None else bk
+        bc = to_host(v.brick_cell, nB, np.int32)
+        d["brick_cell"] = (np.arange(nB, dtype=np.int64) * 8).astype(np.int32) if bc is None else bc
+        d["brick_mass"] = to_host(v.brick_mass, 8 * nB, np.float32)
+        d["patch_parent"] = to_host(v.patch_parent, nP, np.int32)
+        d["patch_ncells"] = to_host(v.patch_ncells, nP, np.uint32)
+        d["patch_nparticles"] = to_host(v.patch_nparticles, nP, np.uint64)
+        d["patch_mass"] = to_host(v.patch_mass, nP, np.float64)
+        return d
+
+    def label(self, ctx: Context, stream=None):
+        _check(load().ahf_label_refinements(ctx.handle, self._h, _stream_handle(stream)))
+
+    def free(self):
+        if self._h:
+            load().ahf_hierarchy_free(self._h)
+            self._h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_hierarchy(ctx: Context, x, y, z, fx=None, fy=None, fz=None, mass=None, *,
+                    g: int, dom_ref: float, ref_ref: float, max_levels: int,
+                    connectivity: int = 26, labels: bool = True, mass_scalar: float = 1.0,
+                    stream=None) -> Hierarchy:
+    parts = make_particles(x, y, z, fx, fy, fz, mass, mass_scalar)
+    prm = make_params(g, dom_ref, ref_ref, max_levels, connectivity,
+                      0 if labels else AHF_NO_LABELS)
+    h = C.c_void_p()
+    _check(load().ahf_build_hierarchy(ctx.handle, C.byref(parts), C.byref(prm),
+                                      _stream_handle(stream), C.byref(h)))
+    return Hierarchy(h, keep=(x, y, z, fx, fy, fz, mass))
+
+
+def snapshot_to_device(s, device="cuda"):
+    """numpy snapshot arrays -> device tensors (x, y, z, fx, fy, fz, mass or None)."""
+    import torch
+    def t(a):
+        return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    # uint32 coordinates travel as int32 bit patterns (torch has no uint32 kernels)
+    X = t(s.X.view(np.int32)); Y = t(s.Y.view(np.int32)); Z = t(s.Z.view(np.int32))
+    return X, Y, Z, t(s.fx), t(s.fy), t(s.fz), t(s.mass)
+
+
+def build_snapshot(ctx: Context, s, labels=True, connectivity=26, stream=None, dev=None):
+    """Build the hierarchy of a synth.Snapshot (copies it to the device first
+    unless `dev` already holds its device tensors)."""
+    dev = dev if dev is not None else snapshot_to_device(s)
+    return build_hierarchy(ctx, *dev[:6], dev[6], g=s.g, dom_ref=s.dom_ref, ref_ref=s.ref_ref,
+                           max_levels=s.max_levels, connectivity=connectivity, labels=labels,
+                           stream=stream), dev

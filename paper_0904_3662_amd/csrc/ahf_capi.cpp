@@ -1,0 +1,425 @@
+// ahf_capi.cpp -- the extern "C" boundary: contexts, memory, validation, views.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ahf_internal.h"
+
+namespace ahf {
+
+static thread_local std::string g_last_error;
+
+static ahf_status fail(ahf_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// ---------------------------------------------------------------- memory
+
+static size_t round_size(size_t b) {
+  if (b < 4096) return (b + 255) & ~size_t(255);
+  if (b < (size_t(2) << 20)) {
+    size_t r = 4096;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  const size_t q = size_t(2) << 20;
+  return (b + q - 1) / q * q;
+}
+
+void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 1;
+  if (c->alloc) {
+    void* p = c->alloc(c->user, bytes, (void*)s);
+    if (!p) throw Error{AHF_ENOMEM, "device allocation callback failed"};
+    return p;
+  }
+  const size_t r = round_size(bytes);
+  auto& fb = c->pool.free_blocks;
+  for (size_t i = 0; i < fb.size(); ++i) {
+    if (fb[i].first == r) {
+      void* p = fb[i].second;
+      fb[i] = fb.back();
+      fb.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, r) != hipSuccess) {
+    (void)hipGetLastError();
+    // give cached blocks back and retry once
+    ctx_release_pool(c);
+    if (hipMalloc(&p, r) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{AHF_ENOMEM, "hipMalloc of " + std::to_string(r) + " bytes failed"};
+    }
+  }
+  c->pool.all.emplace_back(r, p);
+  return p;
+}
+
+void ctx_free(Ctx* c, void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  if (bytes == 0) bytes = 1;
+  if (c->free) {
+    c->free(c->user, p, bytes, (void*)s);
+    return;
+  }
+  c->pool.free_blocks.emplace_back(round_size(bytes), p);
+}
+
+void ctx_release_pool(Ctx* c) {
+  auto& fb = c->pool.free_blocks;
+  for (auto& b : fb) {
+    (void)hipFree(b.second);
+    for (size_t i = 0; i < c->pool.all.size(); ++i)
+      if (c->pool.all[i].second == b.second) {
+        c->pool.all[i] = c->pool.all.back();
+        c->pool.all.pop_back();
+        break;
+      }
+  }
+  fb.clear();
+}
+
+void* Ws::raw(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  while (cur_ < chunks_.size()) {
+    Chunk& c = chunks_[cur_];
+    if (c.used + bytes <= c.size) {
+      void* p = c.p + c.used;
+      c.used += bytes;
+      size_t tot = 0;
+      for (size_t i = 0; i < cur_; ++i) tot += chunks_[i].size;
+      if (tot + c.used > high_) high_ = tot + c.used;
+      return p;
+    }
+    if (cur_ + 1 < chunks_.size()) {
+      ++cur_;
+      chunks_[cur_].used = 0;
+      continue;
+    }
+    break;
+  }
+  size_t want = bytes;
+  size_t have = 0;
+  for (auto& c : chunks_) have += c.size;
+  if (want < have) want = have;            // grow geometrically
+  if (want < (size_t(64) << 20)) want = size_t(64) << 20;
+  Chunk c{static_cast<char*>(ctx_alloc(ctx_, want, st_)), want, bytes};
+  chunks_.push_back(c);
+  cur_ = chunks_.size() - 1;
+  if (have + bytes > high_) high_ = have + bytes;
+  return c.p;
+}
+
+void Ws::release(Mark m) {
+  if (chunks_.empty()) return;
+  for (size_t i = m.chunk + 1; i < chunks_.size() && i <= cur_; ++i) chunks_[i].used = 0;
+  cur_ = m.chunk;
+  chunks_[cur_].used = m.off;
+}
+
+void Ws::reset() {
+  // fold several chunks into one so that the next build needs a single one
+  if (chunks_.size() > 1) {
+    size_t tot = 0;
+    for (auto& c : chunks_) tot += c.size;
+    free_all();
+    Chunk c{static_cast<char*>(ctx_alloc(ctx_, tot, st_)), tot, 0};
+    chunks_.push_back(c);
+  }
+  for (auto& c : chunks_) c.used = 0;
+  cur_ = 0;
+}
+
+void Ws::free_all() {
+  for (auto& c : chunks_) ctx_free(ctx_, c.p, c.size, st_);
+  chunks_.clear();
+  cur_ = 0;
+}
+
+hipEvent_t Prof::take() {
+  if (!spare.empty()) {
+    hipEvent_t e = spare.back();
+    spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  HIP_CHECK(hipEventCreate(&e));
+  return e;
+}
+
+void Prof::begin(const char* name, hipStream_t st, hipEvent_t* a) {
+  (void)name;
+  *a = take();
+  HIP_CHECK(hipEventRecord(*a, st));
+}
+
+void Prof::end(const char* name, hipStream_t st, hipEvent_t a) {
+  hipEvent_t b = take();
+  HIP_CHECK(hipEventRecord(b, st));
+  pending.push_back(Rec{name, a, b});
+}
+
+void Prof::collect() {
+  for (auto& r : pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      bool found = false;
+      for (auto& x : acc)
+        if (x.first == r.name) {
+          x.second.first += 1;
+          x.second.second += ms;
+          found = true;
+          break;
+        }
+      if (!found) acc.push_back({r.name, {1, (double)ms}});
+    } else {
+      (void)hipGetLastError();
+    }
+    spare.push_back(r.a);
+    spare.push_back(r.b);
+  }
+  pending.clear();
+}
+
+void Prof::clear() {
+  collect();
+  acc.clear();
+}
+
+}  // namespace ahf
+
+struct ahf_ctx {
+  ahf::Ctx c;
+  ahf::Ws ws;
+};
+
+struct ahf_hierarchy {
+  ahf::Hier h;
+};
+
+using namespace ahf;
+
+extern "C" {
+
+const char* ahf_last_error(void) { return g_last_error.c_str(); }
+
+ahf_status ahf_ctx_create(const ahf_ctx_desc* desc, ahf_ctx** out) {
+  if (!out) return fail(AHF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc || desc->struct_size < sizeof(ahf_ctx_desc)) return fail(AHF_EINVAL, "bad ahf_ctx_desc");
+  if ((desc->alloc == nullptr) != (desc->free == nullptr))
+    return fail(AHF_EINVAL, "alloc and free callbacks must be given together");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(AHF_EDEVICE, "no HIP device available");
+  }
+  if (desc->device < 0 || desc->device >= ndev) return fail(AHF_EINVAL, "device ordinal out of range");
+  ahf_ctx* c = new (std::nothrow) ahf_ctx();
+  if (!c) return fail(AHF_ENOMEM, "host allocation failed");
+  c->c.device = desc->device;
+  c->c.alloc = desc->alloc;
+  c->c.free = desc->free;
+  c->c.user = desc->user;
+  c->ws.bind(&c->c, nullptr);
+  *out = c;
+  return AHF_OK;
+}
+
+void ahf_ctx_destroy(ahf_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
+  (void)hipDeviceSynchronize();
+  ctx->ws.free_all();
+  ctx->c.prof.collect();
+  for (auto e : ctx->c.prof.spare) (void)hipEventDestroy(e);
+  ctx_release_pool(&ctx->c);
+  for (auto& b : ctx->c.pool.all) (void)hipFree(b.second);
+  delete ctx;
+}
+
+static ahf_status check_params(const ahf_params* prm, Params* out) {
+  if (!prm || prm->struct_size < sizeof(ahf_params)) return fail(AHF_EINVAL, "bad ahf_params");
+  const int g = (int)prm->dom_grid_log2;
+  if (g < 1 || g > 10) return fail(AHF_EINVAL, "dom_grid_log2 must be in 1..10");
+  if ((uint64_t)prm->dom_grid_log2 + prm->max_levels > 21)
+    return fail(AHF_EINVAL, "dom_grid_log2 + max_levels must be <= 21");
+  if (std::isnan(prm->dom_ref) || std::isnan(prm->ref_ref))
+    return fail(AHF_EINVAL, "thresholds must not be NaN");
+  const uint32_t conn = prm->connectivity ? prm->connectivity : 26;
+  if (conn != 6 && conn != 18 && conn != 26) return fail(AHF_EINVAL, "connectivity must be 6, 18 or 26");
+  out->g = g;
+  out->Lmax = (int)prm->max_levels;
+  out->conn = (int)conn;
+  out->dom_ref = prm->dom_ref;
+  out->ref_ref = prm->ref_ref;
+  out->flags = prm->flags;
+  return AHF_OK;
+}
+
+static ahf_status check_particles(const ahf_particles* p) {
+  if (!p) return fail(AHF_EINVAL, "particles is NULL");
+  if (p->n >= (1ull << 32)) return fail(AHF_EINVAL, "at most 2^32 - 1 particles");
+  if (p->n > 0 && (!p->x || !p->y || !p->z)) return fail(AHF_EINVAL, "x, y and z are required");
+  if (!p->mass && !(std::isfinite(p->mass_scalar))) return fail(AHF_EINVAL, "mass_scalar must be finite");
+  return AHF_OK;
+}
+
+ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, const ahf_params* params,
+                               void* stream, ahf_hierarchy** out) {
+  if (!out) return fail(AHF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(AHF_EINVAL, "ctx is NULL");
+  Params prm;
+  ahf_status s = check_params(params, &prm);
+  if (s != AHF_OK) return s;
+  s = check_particles(particles);
+  if (s != AHF_OK) return s;
+  ahf_hierarchy* h = new (std::nothrow) ahf_hierarchy();
+  if (!h) return fail(AHF_ENOMEM, "host allocation failed");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    HIP_CHECK(hipSetDevice(ctx->c.device));
+    h->h.ctx = &ctx->c;
+    h->h.mem.ctx = &ctx->c;
+    h->h.mem.st = st;
+    ctx->ws.bind(&ctx->c, st);
+    ctx->ws.reset();
+    build_hierarchy(&ctx->c, ctx->ws, *particles, prm, st, &h->h);
+    if (!(prm.flags & AHF_NO_LABELS)) label_hierarchy(&ctx->c, ctx->ws, &h->h, st);
+    ctx->ws.reset();
+  } catch (const Error& e) {
+    (void)hipStreamSynchronize(st);
+    h->h.mem.release_all();
+    delete h;
+    ctx->ws.reset();
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(st);
+    h->h.mem.release_all();
+    delete h;
+    return fail(AHF_ENOMEM, "host allocation failed");
+  }
+  *out = h;
+  return AHF_OK;
+}
+
+ahf_status ahf_label_refinements(ahf_ctx* ctx, ahf_hierarchy* h, void* stream) {
+  if (!ctx || !h) return fail(AHF_EINVAL, "ctx and h are required");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    HIP_CHECK(hipSetDevice(ctx->c.device));
+    ctx->ws.bind(&ctx->c, st);
+    ctx->ws.reset();
+    h->h.mem.st = st;
+    label_hierarchy(&ctx->c, ctx->ws, &h->h, st);
+    ctx->ws.reset();
+  } catch (const Error& e) {
+    (void)hipStreamSynchronize(st);
+    ctx->ws.reset();
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(AHF_ENOMEM, "host allocation failed");
+  }
+  return AHF_OK;
+}
+
+ahf_status ahf_hierarchy_num_levels(const ahf_hierarchy* h, uint32_t* out) {
+  if (!out) return fail(AHF_EINVAL, "out is NULL");
+  *out = 0;
+  if (!h) return fail(AHF_EINVAL, "h is NULL");
+  *out = (uint32_t)h->h.lev.size();
+  return AHF_OK;
+}
+
+ahf_status ahf_level_get(const ahf_hierarchy* h, uint32_t level, ahf_level_view* v) {
+  if (!v) return fail(AHF_EINVAL, "out is NULL");
+  std::memset(v, 0, sizeof(*v));
+  if (!h) return fail(AHF_EINVAL, "h is NULL");
+  if (level >= h->h.lev.size()) return fail(AHF_EINVAL, "level out of range");
+  const Level& L = h->h.lev[level];
+  v->level = level;
+  v->bits = L.b;
+  v->n_cells = L.nS;
+  v->n_refined = L.nF;
+  v->n_particles = L.nP;
+  v->n_bricks = L.nB;
+  v->n_patches = (level >= 1 && h->h.labelled) ? L.nPatch : 0;
+  v->cell_key = L.Skey;
+  v->cell_start = L.Sstart;
+  v->cell_count = L.Scount;
+  v->cell_refined = L.Sflag;
+  v->cell_patch = (level >= 1 && h->h.labelled) ? L.Spatch : nullptr;
+  v->brick_key = L.Bkey;
+  v->brick_cell = L.Bcell;
+  v->brick_mass = L.mass;
+  if (level >= 1 && h->h.labelled) {
+    v->patch_parent = L.patch_parent;
+    v->patch_ncells = L.patch_ncells;
+    v->patch_nparticles = L.patch_npart;
+    v->patch_mass = L.patch_mass;
+  }
+  v->total_cell_mass = L.tot_cell;
+  v->total_particle_mass = L.tot_part;
+  return AHF_OK;
+}
+
+ahf_status ahf_hierarchy_order(const ahf_hierarchy* h, const uint32_t** sorted_idx) {
+  if (!sorted_idx) return fail(AHF_EINVAL, "out is NULL");
+  *sorted_idx = nullptr;
+  if (!h) return fail(AHF_EINVAL, "h is NULL");
+  *sorted_idx = h->h.order;
+  return AHF_OK;
+}
+
+ahf_status ahf_hierarchy_timings(const ahf_hierarchy* h, double* ms, uint32_t n) {
+  if (!h || !ms || n > 4) return fail(AHF_EINVAL, "bad arguments");
+  for (uint32_t i = 0; i < n; ++i) ms[i] = h->h.ms[i];
+  return AHF_OK;
+}
+
+ahf_status ahf_ctx_set_profiling(ahf_ctx* ctx, int enable) {
+  if (!ctx) return fail(AHF_EINVAL, "ctx is NULL");
+  try {
+    HIP_CHECK(hipSetDevice(ctx->c.device));
+    ctx->c.prof.clear();
+    ctx->c.prof.on = enable != 0;
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
+  return AHF_OK;
+}
+
+ahf_status ahf_ctx_kernel_time(ahf_ctx* ctx, const char* kernel, uint64_t* launches,
+                               double* total_ms) {
+  if (!ctx || !kernel || !launches || !total_ms) return fail(AHF_EINVAL, "bad arguments");
+  *launches = 0;
+  *total_ms = 0.0;
+  try {
+    HIP_CHECK(hipSetDevice(ctx->c.device));
+    ctx->c.prof.collect();
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
+  for (auto& x : ctx->c.prof.acc)
+    if (x.first == kernel) {
+      *launches = x.second.first;
+      *total_ms = x.second.second;
+    }
+  return AHF_OK;
+}
+
+void ahf_hierarchy_free(ahf_hierarchy* h) {
+  if (!h) return;
+  // builds finish on their stream before they return, and the blocks go back
+  // to the context's pool (or its free callback), so no wait is needed here
+  h->h.mem.release_all();
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// ahf_dev.h -- device-side helpers of the hierarchy library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ahf {
+
+constexpr int kQBits = 21;          // bits per axis of the quantized positions
+constexpr int kMaxLevels = 22;      // levels 0..21
+constexpr int kHeavy = 64;          // cells with more particles take the chunked path
+constexpr int kChunk = 16384;       // particles per chunk of a heavy cell (256 x 64)
+
+// device error flags (bit mask in a uint32 the host reads after the build)
+constexpr uint32_t kErrCoord = 1u;     // a coordinate >= 2^21
+constexpr uint32_t kErrLookup = 2u;    // a cell that must exist was not found
+constexpr uint32_t kErrInternal = 4u;
+
+// 21-bit value -> every third bit of a 63-bit word (Morton spreading)
+__host__ __device__ inline uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__host__ __device__ inline uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+  x = (x ^ (x >> 32)) & 0x1fffffull;
+  return (uint32_t)x;
+}
+
+// Morton key: bit 3j+2 = x_j, bit 3j+1 = y_j, bit 3j = z_j
+__host__ __device__ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
+__host__ __device__ inline void unmorton3(uint64_t k, uint32_t& x, uint32_t& y, uint32_t& z) {
+  x = compact3(k >> 2);
+  y = compact3(k >> 1);
+  z = compact3(k);
+}
+
+// key of the cell displaced by (dx,dy,dz), periodic on a grid of `bits` bits per axis
+__host__ __device__ inline uint64_t shift_key(uint64_t k, int bits, int dx, int dy, int dz) {
+  uint32_t x, y, z;
+  unmorton3(k, x, y, z);
+  const uint32_t m = bits >= 32 ? 0xffffffffu : ((1u << bits) - 1u);
+  x = (uint32_t)((int32_t)x + dx) & m;
+  y = (uint32_t)((int32_t)y + dy) & m;
+  z = (uint32_t)((int32_t)z + dz) & m;
+  return morton3(x, y, z);
+}
+
+// Per-level descent table: slot_child[l][s] is the brick (of level l+1) made
+// of the children of slot s of level l, or -1.  Level-0 slots are level-0 keys.
+struct Tree {
+  const int32_t* slot_child[kMaxLevels];
+};
+
+// slot of the level-L cell with key `key` in its level's brick field, or -1
+__device__ inline int64_t tree_lookup(const Tree& t, int L, uint64_t key) {
+  int64_t slot = (int64_t)(key >> (3 * L));
+  for (int l = 1; l <= L; ++l) {
+    const int32_t d = t.slot_child[l - 1][slot];
+    if (d < 0) return -1;
+    slot = (int64_t)d * 8 + (int64_t)((key >> (3 * (L - l))) & 7u);
+  }
+  return slot;
+}
+
+__device__ inline uint64_t lanemask_lt() {
+  const uint32_t lane = __lane_id();
+  return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+}  // namespace ahf

@@ -1,0 +1,184 @@
+// ahf_internal.h -- host-side internals shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ahf.h"
+#include "ahf_dev.h"
+
+namespace ahf {
+
+struct Error {
+  ahf_status code;
+  std::string msg;
+};
+
+#define HIP_CHECK(x)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      throw ::ahf::Error{AHF_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+#define HIP_LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
+
+// device memory through the context's callbacks or its own caching pool
+struct Pool {
+  std::vector<std::pair<size_t, void*>> free_blocks;  // (size, ptr)
+  std::vector<std::pair<size_t, void*>> all;          // everything hipMalloc'd
+};
+
+// HIP-event timing of selected kernels (profiling mode of a context)
+struct Prof {
+  bool on = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<std::pair<std::string, std::pair<uint64_t, double>>> acc;
+  std::vector<hipEvent_t> spare;
+  hipEvent_t take();
+  void begin(const char* name, hipStream_t st, hipEvent_t* a);
+  void end(const char* name, hipStream_t st, hipEvent_t a);
+  void collect();   // fold finished events into acc
+  void clear();
+};
+
+struct Ctx {
+  int device = 0;
+  ahf_alloc_fn alloc = nullptr;
+  ahf_free_fn free = nullptr;
+  void* user = nullptr;
+  Pool pool;
+  Prof prof;
+};
+
+// times one launch when the context profiles
+#define AHF_TIMED(ctxp, name, st, launch)                  \
+  do {                                                     \
+    hipEvent_t ev_a_ = nullptr;                            \
+    if ((ctxp)->prof.on) (ctxp)->prof.begin(name, st, &ev_a_); \
+    launch;                                                \
+    HIP_LAUNCH_CHECK();                                    \
+    if ((ctxp)->prof.on) (ctxp)->prof.end(name, st, ev_a_);    \
+  } while (0)
+
+void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s);  // throws AHF_ENOMEM
+void ctx_free(Ctx* c, void* p, size_t bytes, hipStream_t s);
+void ctx_release_pool(Ctx* c);
+
+// Stack-like scratch space for one build: chunks are never moved, so every
+// pointer handed out stays valid until released.
+class Ws {
+ public:
+  struct Mark {
+    size_t chunk, off;
+  };
+  Ws() = default;
+  void bind(Ctx* c, hipStream_t s) {
+    ctx_ = c;
+    st_ = s;
+  }
+  template <class T>
+  T* get(uint64_t n) {
+    return static_cast<T*>(raw(n * sizeof(T)));
+  }
+  void* raw(size_t bytes);
+  Mark mark() const { return Mark{cur_, chunks_.empty() ? 0 : chunks_[cur_].used}; }
+  void release(Mark m);
+  void reset();        // drop every allocation (memory kept for the next build)
+  void free_all();     // give the memory back to the context
+  size_t high_water() const { return high_; }
+  Ctx* ctx() const { return ctx_; }
+
+ private:
+  struct Chunk {
+    char* p;
+    size_t size, used;
+  };
+  Ctx* ctx_ = nullptr;
+  hipStream_t st_ = nullptr;
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0;
+  size_t high_ = 0;
+};
+
+// Owned device allocations of one hierarchy.
+struct Owned {
+  Ctx* ctx = nullptr;
+  hipStream_t st = nullptr;
+  std::vector<std::pair<void*, size_t>> list;
+  template <class T>
+  T* get(uint64_t n) {
+    const size_t b = (n ? n : 1) * sizeof(T);
+    void* p = ctx_alloc(ctx, b, st);
+    list.emplace_back(p, b);
+    return static_cast<T*>(p);
+  }
+  void release_all() {
+    for (auto& a : list) ctx_free(ctx, a.first, a.second, st);
+    list.clear();
+  }
+};
+
+// ---------------------------------------------------------------- primitives
+void scan_u32(Ws& ws, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
+              hipStream_t st);
+void sort_pairs(Ws& ws, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp,
+                uint64_t n, int bits, hipStream_t st);
+template <typename T>
+void sum_to_f64(Ws& ws, const T* a, uint64_t n, double* out, hipStream_t st);
+
+// ---------------------------------------------------------------- hierarchy
+struct Level {
+  uint32_t b = 0;
+  uint64_t nS = 0, nF = 0, nB = 0, nP = 0, nPatch = 0;
+  uint64_t* Skey = nullptr;     // [nS], null on level 0 (identity)
+  uint32_t* Sstart = nullptr;   // [nS] (+1 sentinel on level 0)
+  uint32_t* Scount = nullptr;   // [nS]
+  uint8_t* Sflag = nullptr;     // [nS]
+  double* Spmass = nullptr;     // [nS] particle mass per cell
+  int32_t* Spatch = nullptr;    // [nS] after labelling (level >= 1)
+  uint32_t* Fs = nullptr;       // [nF] S index of the refined cells
+  uint64_t* Bkey = nullptr;     // [nB] parent key of each brick, null on level 0
+  int32_t* Bcell = nullptr;     // [nB] S index of the brick's first cell or -1, null on level 0
+  int32_t* Pbrick = nullptr;    // [nF of level-1] brick of each parent, null on level 0
+  float* mass = nullptr;        // [8 nB]
+  int32_t* slot_child = nullptr;  // [8 nB] brick of the next level made of the slot's children
+  int32_t* slot_f = nullptr;      // [8 nB] index in F of the slot's cell, or -1
+  int32_t* patch_parent = nullptr;
+  uint32_t* patch_ncells = nullptr;
+  uint64_t* patch_npart = nullptr;
+  double* patch_mass = nullptr;
+  double tot_cell = 0.0, tot_part = 0.0;
+};
+
+struct Params {
+  int g = 0, Lmax = 0, conn = 26;
+  double dom_ref = 0, ref_ref = 0;
+  uint32_t flags = 0;
+};
+
+struct Hier {
+  Ctx* ctx = nullptr;
+  Owned mem;
+  Params prm;
+  uint64_t n = 0;
+  int B = 0;
+  uint32_t* order = nullptr;
+  bool has_mass = false;
+  double mass_scalar = 1.0;
+  bool labelled = false;
+  std::vector<Level> lev;
+  double ms[4] = {0, 0, 0, 0};
+};
+
+void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm, hipStream_t st,
+                     Hier* h);
+void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
+
+}  // namespace ahf

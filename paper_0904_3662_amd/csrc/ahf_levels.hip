@@ -1,0 +1,872 @@
+// ahf_levels.hip -- the adaptive density hierarchy on the device.
+//
+// Method: Knollmann & Knebe, "AHF: AMIGA's Halo Finder", Sect. 2.1.  A domain
+// grid covers the periodic box; every cell gets its triangular-shaped-cloud
+// (TSC) particle density; a cell with more particles than the threshold is
+// covered by 8 cells of half the size, where the density is computed again,
+// and so on until no cell needs refinement.  The isolated refinements of each
+// level, linked to the coarser volume that holds them, form the grid tree.
+//
+// Layout on the device (level L, b = g + L bits per axis):
+//  * particles are sorted once by their Morton key at B = g + max_levels bits,
+//    so every cell of every level owns one contiguous range of them;
+//  * S_L (the cells of level L) are the 8 children of each refined cell of
+//    level L-1, stored in key order: cell s is child s & 7 of parent s >> 3.
+//    Level 0 is dense: cell s has key s;
+//  * the mass field of level L is stored as 2x2x2 bricks; the bricks are the
+//    children of every level-(L-1) cell within one cell of a refined cell, in
+//    key order.  Level 0 bricks are all children of the (virtual) level -1;
+//  * every brick slot (a level-L cell) knows the brick of level L+1 made of its
+//    children (slot_child), so any cell of any level is found by descending
+//    from the dense level 0 (tree_lookup), without hashing or searching.
+//
+// Deposit without float atomics: each thread owns one cell of S_L, sums the
+// 27 TSC products of that cell's particles in registers (cells holding more
+// than kHeavy particles are summed by whole blocks in fixed chunks and a fixed
+// pairwise tree), the 8 cells of a refined parent are combined in LDS into
+// the 4x4x4 patch they touch, and each brick cell gathers the at most 8 patches
+// that cover it, in a fixed order.  Every float sum therefore has a fixed
+// order and the result is bit-reproducible.
+#include <chrono>
+#include <cmath>
+
+#include "ahf_internal.h"
+
+namespace ahf {
+
+constexpr int kT = 256;
+
+static inline unsigned grid_for(uint64_t n, int t = kT) {
+  uint64_t b = (n + t - 1) / t;
+  if (b < 1) b = 1;
+  if (b > (1u << 20)) b = 1u << 20;
+  return (unsigned)b;
+}
+
+#define GRID_STRIDE(i, n)                                                       \
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+       i += (uint64_t)gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void k_fill_i32(int32_t* a, uint64_t n, int32_t v) {
+  GRID_STRIDE(i, n) a[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t* a, uint64_t n, uint32_t v) {
+  GRID_STRIDE(i, n) a[i] = v;
+}
+
+// Morton keys at B bits per axis and the identity permutation
+__global__ void k_keys(const uint32_t* __restrict__ X, const uint32_t* __restrict__ Y,
+                       const uint32_t* __restrict__ Z, uint64_t n, int B,
+                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                       uint32_t* __restrict__ err) {
+  const int s = kQBits - B;
+  GRID_STRIDE(i, n) {
+    const uint32_t x = X[i], y = Y[i], z = Z[i];
+    if ((x | y | z) >= (1u << kQBits)) atomicOr(err, kErrCoord);
+    keys[i] = morton3((x & 0x1fffffu) >> s, (y & 0x1fffffu) >> s, (z & 0x1fffffu) >> s);
+    vals[i] = (uint32_t)i;
+  }
+}
+
+// payload in sorted order
+__global__ void k_gather(const uint32_t* __restrict__ order, uint64_t n,
+                         const uint32_t* __restrict__ X, const uint32_t* __restrict__ Y,
+                         const uint32_t* __restrict__ Z, const float* __restrict__ fx,
+                         const float* __restrict__ fy, const float* __restrict__ fz,
+                         const float* __restrict__ m, uint32_t* __restrict__ sx,
+                         uint32_t* __restrict__ sy, uint32_t* __restrict__ sz,
+                         float* __restrict__ sfx, float* __restrict__ sfy,
+                         float* __restrict__ sfz, float* __restrict__ sm) {
+  GRID_STRIDE(i, n) {
+    const uint32_t j = order[i];
+    sx[i] = X[j] & 0x1fffffu;
+    sy[i] = Y[j] & 0x1fffffu;
+    sz[i] = Z[j] & 0x1fffffu;
+    sfx[i] = fx ? fx[j] : 0.0f;
+    sfy[i] = fy ? fy[j] : 0.0f;
+    sfz[i] = fz ? fz[j] : 0.0f;
+    if (m) sm[i] = m[j];
+  }
+}
+
+// level 0: start of every dense cell from the sorted keys (start[ncell] = n)
+__global__ void k_l0_start(const uint64_t* __restrict__ skey, uint64_t n, int sh,
+                           uint64_t ncell, uint32_t* __restrict__ start) {
+  GRID_STRIDE(i, n + 1) {
+    const uint64_t ci = (i < n) ? (skey[i] >> sh) : ncell;
+    const uint64_t c0 = (i > 0) ? (skey[i - 1] >> sh) + 1 : 0;
+    for (uint64_t c = c0; c <= ci; ++c) start[c] = (uint32_t)i;
+  }
+}
+
+__global__ void k_l0_count(const uint32_t* __restrict__ start, uint64_t ncell,
+                           uint32_t* __restrict__ count) {
+  GRID_STRIDE(c, ncell) count[c] = start[c + 1] - start[c];
+}
+
+__device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ a, uint32_t lo, uint32_t hi,
+                                           uint64_t key) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// level L >= 1: the 8 children of every refined cell of level L-1 and their
+// particle ranges (binary searches inside the parent's range)
+__global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
+                               const uint32_t* __restrict__ pFs,
+                               const uint32_t* __restrict__ pSstart,
+                               const uint32_t* __restrict__ pScount,
+                               const uint64_t* __restrict__ pSkey, int sh,
+                               uint64_t* __restrict__ Skey, uint32_t* __restrict__ Sstart,
+                               uint32_t* __restrict__ Scount) {
+  GRID_STRIDE(s, nS) {
+    const uint32_t ps = pFs[s >> 3];
+    const uint32_t d = (uint32_t)(s & 7);
+    const uint32_t a = pSstart[ps];
+    const uint32_t e = a + pScount[ps];
+    const uint64_t pk = pSkey ? pSkey[ps] : (uint64_t)ps;
+    const uint64_t ck = (pk << 3) | d;
+    const uint32_t lo = (d == 0) ? a : lower_bound_key(skey, a, e, ck << sh);
+    const uint32_t hi = (d == 7) ? e : lower_bound_key(skey, lo, e, (ck + 1) << sh);
+    Skey[s] = ck;
+    Sstart[s] = lo;
+    Scount[s] = hi - lo;
+  }
+}
+
+__global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double thr,
+                        int can_refine, uint8_t* __restrict__ flag, uint32_t* __restrict__ predF,
+                        uint32_t* __restrict__ predH) {
+  GRID_STRIDE(s, nS) {
+    const uint32_t c = count[s];
+    const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
+    flag[s] = (uint8_t)f;
+    predF[s] = f;
+    predH[s] = c > (uint32_t)kHeavy ? 1u : 0u;
+  }
+}
+
+__global__ void k_compact(const uint32_t* __restrict__ pred, const uint32_t* __restrict__ ofs,
+                          uint64_t n, uint32_t* __restrict__ out) {
+  GRID_STRIDE(i, n) if (pred[i]) out[ofs[i]] = (uint32_t)i;
+}
+
+// ------------------------------------------------------------ TSC weights
+
+// per-axis TSC weights of coordinate (X, f) on a grid with k = 21 - b sub-bits:
+// u is the in-cell offset; 1-u is formed from the integer complement so that
+// both tails keep full relative precision.
+__device__ inline void tsc_axis(uint32_t X, float f, uint32_t mask, float scale, float w[3]) {
+  const uint32_t lo = X & mask;
+  const float u = ((float)lo + f) * scale;
+  const float v = ((float)(mask - lo) + (1.0f - f)) * scale;
+  const float c = u - 0.5f;
+  w[0] = 0.5f * v * v;
+  w[1] = 0.75f - c * c;
+  w[2] = 0.5f * u * u;
+}
+
+struct Parts {
+  const uint32_t *x, *y, *z;
+  const float *fx, *fy, *fz, *m;
+  float mscalar;
+};
+
+__device__ inline void add_particle(const Parts& P, uint32_t p, uint32_t mask, float scale,
+                                    float T[27], double& msum) {
+  float wx[3], wy[3], wz[3];
+  tsc_axis(P.x[p], P.fx[p], mask, scale, wx);
+  tsc_axis(P.y[p], P.fy[p], mask, scale, wy);
+  tsc_axis(P.z[p], P.fz[p], mask, scale, wz);
+  const float m = P.m ? P.m[p] : P.mscalar;
+  msum += (double)m;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float ma = m * wx[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float mab = ma * wy[b];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T[a * 9 + b * 3 + c] = fmaf(mab, wz[c], T[a * 9 + b * 3 + c]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ heavy cells
+
+__global__ void k_heavy_nchunks(const uint32_t* __restrict__ Hs, uint64_t nH,
+                                const uint32_t* __restrict__ Scount, uint32_t* __restrict__ nch) {
+  GRID_STRIDE(h, nH) nch[h] = (Scount[Hs[h]] + kChunk - 1) / kChunk;
+}
+
+__global__ void k_chunk_list(const uint32_t* __restrict__ nch, const uint32_t* __restrict__ chofs,
+                             uint64_t nH, uint32_t* __restrict__ ch_h, uint32_t* __restrict__ ch_j) {
+  GRID_STRIDE(h, nH) {
+    const uint32_t o = chofs[h];
+    for (uint32_t j = 0; j < nch[h]; ++j) {
+      ch_h[o + j] = (uint32_t)h;
+      ch_j[o + j] = j;
+    }
+  }
+}
+
+// one block per chunk of <= kChunk particles of one heavy cell; every thread
+// sums at most kChunk/256 = 64 particles, then a fixed tree over the block
+__global__ __launch_bounds__(256) void k_heavy_chunk(
+    const uint32_t* __restrict__ nchunks, const uint32_t* __restrict__ ch_h,
+    const uint32_t* __restrict__ ch_j, const uint32_t* __restrict__ Hs,
+    const uint32_t* __restrict__ Sstart, const uint32_t* __restrict__ Scount, Parts P,
+    uint32_t mask, float scale, float* __restrict__ chT, double* __restrict__ chM) {
+  __shared__ float red[4][27];
+  __shared__ double redm[4];
+  const uint32_t c = blockIdx.x;
+  if (c >= *nchunks) return;
+  const uint32_t s = Hs[ch_h[c]];
+  const uint32_t j = ch_j[c];
+  const uint32_t n = Scount[s];
+  const uint32_t a = Sstart[s] + j * kChunk;
+  const uint32_t len = min((uint32_t)kChunk, n - j * kChunk);
+  float T[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) T[k] = 0.0f;
+  double ms = 0.0;
+  for (uint32_t i = threadIdx.x; i < len; i += 256) add_particle(P, a + i, mask, scale, T, ms);
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 27; ++k) {
+    float v = T[k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) red[w][k] = v;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) ms += __shfl_xor(ms, d, 64);
+  if ((threadIdx.x & 63) == 0) redm[w] = ms;
+  __syncthreads();
+  if (threadIdx.x < 27) {
+    const int k = threadIdx.x;
+    chT[(uint64_t)c * 27 + k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+  }
+  if (threadIdx.x == 27) chM[c] = (redm[0] + redm[1]) + (redm[2] + redm[3]);
+}
+
+// pairwise (binary-counter) sum over the chunks of each heavy cell
+__global__ void k_heavy_reduce(const uint32_t* __restrict__ nch, const uint32_t* __restrict__ chofs,
+                               uint64_t nH, const float* __restrict__ chT,
+                               const double* __restrict__ chM, float* __restrict__ hT,
+                               double* __restrict__ hM) {
+  GRID_STRIDE(i, nH * 28) {
+    const uint64_t h = i / 28;
+    const int k = (int)(i % 28);
+    const uint32_t o = chofs[h], m = nch[h];
+    if (k < 27) {
+      float st[33];
+      int top = 0;
+      for (uint32_t q = 0; q < m; ++q) {
+        float v = chT[(uint64_t)(o + q) * 27 + k];
+        for (uint32_t c = q + 1; (c & 1u) == 0u; c >>= 1) v = st[--top] + v;
+        st[top++] = v;
+      }
+      float s = 0.0f;
+      while (top > 0) s = st[--top] + s;
+      hT[h * 27 + k] = s;
+    } else {
+      double st[33];
+      int top = 0;
+      for (uint32_t q = 0; q < m; ++q) {
+        double v = chM[o + q];
+        for (uint32_t c = q + 1; (c & 1u) == 0u; c >>= 1) v = st[--top] + v;
+        st[top++] = v;
+      }
+      double s = 0.0;
+      while (top > 0) s = st[--top] + s;
+      hM[h] = s;
+    }
+  }
+}
+
+__global__ void k_set_hidx(const uint32_t* __restrict__ Hs, uint64_t nH, int32_t* __restrict__ hidx) {
+  GRID_STRIDE(h, nH) hidx[Hs[h]] = (int32_t)h;
+}
+
+// ------------------------------------------------------------ deposit
+
+// one thread per cell of S_L (8 per refined parent); 32 parents per block.
+// patch[f][px][py][pz] (4x4x4) holds what the particles of parent f give to
+// the level-L cells 2P-1 .. 2P+2 per axis.
+__global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* __restrict__ Sstart,
+                                                 const uint32_t* __restrict__ Scount,
+                                                 const int32_t* __restrict__ hidx,
+                                                 const float* __restrict__ hT,
+                                                 const double* __restrict__ hM, Parts P,
+                                                 uint32_t mask, float scale,
+                                                 float* __restrict__ patch,
+                                                 double* __restrict__ Spmass) {
+  __shared__ float Ts[256][28];
+  const int t = threadIdx.x;
+  const uint64_t f = (uint64_t)blockIdx.x * 32 + (t >> 3);
+  const int d = t & 7;
+  float T[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) T[k] = 0.0f;
+  if (f < nFp) {
+    const uint64_t s = f * 8 + d;
+    const uint32_t n = Scount[s];
+    double ms = 0.0;
+    if (n > (uint32_t)kHeavy) {
+      const int32_t h = hidx[s];
+#pragma unroll
+      for (int k = 0; k < 27; ++k) T[k] = hT[(uint64_t)h * 27 + k];
+      ms = hM[h];
+    } else {
+      const uint32_t a = Sstart[s];
+      for (uint32_t i = 0; i < n; ++i) add_particle(P, a + i, mask, scale, T, ms);
+    }
+    Spmass[s] = ms;
+  }
+#pragma unroll
+  for (int k = 0; k < 27; ++k) Ts[t][k] = T[k];
+  __syncthreads();
+  if (f >= nFp) return;
+  const int base = t & ~7;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int q = d * 8 + j;
+    const int px = q >> 4, py = (q >> 2) & 3, pz = q & 3;
+    float sum = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = px - ((c >> 2) & 1), b = py - ((c >> 1) & 1), e = pz - (c & 1);
+      if (a >= 0 && a <= 2 && b >= 0 && b <= 2 && e >= 0 && e <= 2)
+        sum += Ts[base + c][a * 9 + b * 3 + e];
+    }
+    patch[f * 64 + q] = sum;
+  }
+}
+
+// one thread per brick cell: sum of the (at most 8) parent patches covering it,
+// in a fixed order (own parent first)
+__global__ void k_combine(int L, uint64_t nB, const uint64_t* __restrict__ Bkey, int pbits, Tree tree,
+                          const int32_t* __restrict__ pslot_f, const float* __restrict__ patch,
+                          float* __restrict__ mass, uint32_t* __restrict__ err) {
+  GRID_STRIDE(i, nB * 8) {
+    const uint64_t bi = i >> 3;
+    const int d = (int)(i & 7);
+    const int ex = (d >> 2) & 1, ey = (d >> 1) & 1, ez = d & 1;
+    const uint64_t P = Bkey ? Bkey[bi] : bi;
+    float sum = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int sx = (c >> 2) & 1, sy = (c >> 1) & 1, sz = c & 1;
+      const int ox = sx ? (ex ? 1 : -1) : 0, oy = sy ? (ey ? 1 : -1) : 0, oz = sz ? (ez ? 1 : -1) : 0;
+      const int px = sx ? (ex ? 0 : 3) : ex + 1;
+      const int py = sy ? (ey ? 0 : 3) : ey + 1;
+      const int pz = sz ? (ez ? 0 : 3) : ez + 1;
+      const uint64_t Pn = c ? shift_key(P, pbits, ox, oy, oz) : P;
+      int64_t f;
+      if (L == 0) {
+        f = (int64_t)Pn;
+      } else {
+        const int64_t slot = tree_lookup(tree, L - 1, Pn);
+        f = slot < 0 ? -1 : (int64_t)pslot_f[slot];
+      }
+      if (f >= 0) sum += patch[(uint64_t)f * 64 + px * 16 + py * 4 + pz];
+    }
+    mass[i] = sum;
+  }
+}
+
+// ------------------------------------------------------------ next level's bricks
+
+__device__ inline uint64_t slot_of_s(uint64_t s, const int32_t* Pbrick) {
+  return Pbrick ? (uint64_t)Pbrick[s >> 3] * 8 + (s & 7) : s;
+}
+
+__global__ void k_slot_f(uint64_t nF, const uint32_t* __restrict__ Fs,
+                         const int32_t* __restrict__ Pbrick, int32_t* __restrict__ slot_f) {
+  GRID_STRIDE(f, nF) slot_f[slot_of_s(Fs[f], Pbrick)] = (int32_t)f;
+}
+
+// mark every level-L slot within one cell of a refined cell
+__global__ void k_mark(int L, int bits, uint64_t nF, const uint32_t* __restrict__ Fs,
+                       const uint64_t* __restrict__ Skey, Tree tree, uint32_t* __restrict__ mark,
+                       uint32_t* __restrict__ err) {
+  GRID_STRIDE(i, nF * 27) {
+    const uint64_t f = i / 27;
+    const int o = (int)(i % 27);
+    const uint32_t s = Fs[f];
+    const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
+    const uint64_t nk = shift_key(key, bits, o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1);
+    const int64_t slot = tree_lookup(tree, L, nk);
+    if (slot < 0) atomicOr(err, kErrLookup);
+    else mark[slot] = 1u;
+  }
+}
+
+__global__ void k_build_bricks(uint64_t nslot, const uint32_t* __restrict__ mark,
+                               const uint32_t* __restrict__ rank,
+                               const uint64_t* __restrict__ Bkey,
+                               const int32_t* __restrict__ slot_f,
+                               int32_t* __restrict__ slot_child, uint64_t* __restrict__ nBkey,
+                               int32_t* __restrict__ nBcell) {
+  GRID_STRIDE(i, nslot) {
+    if (mark[i]) {
+      const uint32_t r = rank[i];
+      slot_child[i] = (int32_t)r;
+      nBkey[r] = Bkey ? ((Bkey[i >> 3] << 3) | (i & 7)) : i;
+      const int32_t f = slot_f[i];
+      nBcell[r] = f >= 0 ? f * 8 : -1;
+    } else {
+      slot_child[i] = -1;
+    }
+  }
+}
+
+__global__ void k_pbrick(uint64_t nF, const uint32_t* __restrict__ Fs,
+                         const int32_t* __restrict__ Pbrick, const int32_t* __restrict__ slot_child,
+                         int32_t* __restrict__ nPbrick) {
+  GRID_STRIDE(f, nF) nPbrick[f] = slot_child[slot_of_s(Fs[f], Pbrick)];
+}
+
+// ------------------------------------------------------------ labels
+
+__device__ inline int32_t uf_load(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int32_t uf_find(int32_t* par, int32_t x) {
+  while (true) {
+    const int32_t p = uf_load(&par[x]);
+    if (p == x) return x;
+    const int32_t gp = uf_load(&par[p]);
+    if (gp == p) return p;
+    __hip_atomic_store(&par[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // path halving
+    x = gp;
+  }
+}
+
+// link the larger root under the smaller one; retry while the root moved
+__device__ inline void uf_unite(int32_t* par, int32_t a, int32_t b) {
+  while (true) {
+    a = uf_find(par, a);
+    b = uf_find(par, b);
+    if (a == b) return;
+    if (a > b) {
+      const int32_t t = a;
+      a = b;
+      b = t;
+    }
+    if (atomicCAS(&par[b], b, a) == b) return;
+  }
+}
+
+__global__ void k_uf_init(int32_t* par, uint64_t n) {
+  GRID_STRIDE(i, n) par[i] = (int32_t)i;
+}
+
+// half of the neighbour offsets of the connectivity (the other half is symmetric)
+__constant__ int8_t c_half26[13][3] = {{1, -1, -1}, {1, -1, 0}, {1, -1, 1}, {1, 0, -1}, {1, 0, 0},
+                                       {1, 0, 1},   {1, 1, -1}, {1, 1, 0},  {1, 1, 1},  {0, 1, -1},
+                                       {0, 1, 0},   {0, 1, 1},  {0, 0, 1}};
+
+__device__ inline bool conn_ok(int dx, int dy, int dz, int conn) {
+  const int s = abs(dx) + abs(dy) + abs(dz);
+  return conn == 6 ? s == 1 : (conn == 18 ? s <= 2 : true);
+}
+
+// elements are the refined cells F of level Lp; each is united with its
+// refined neighbours
+__global__ void k_uf_hook(int Lp, int bits, uint64_t nF, const uint32_t* __restrict__ Fs,
+                          const uint64_t* __restrict__ Skey, Tree tree,
+                          const int32_t* __restrict__ slot_f, int conn, int32_t* __restrict__ par,
+                          uint32_t* __restrict__ err) {
+  GRID_STRIDE(i, nF * 13) {
+    const int32_t f = (int32_t)(i / 13);
+    const int o = (int)(i % 13);
+    const int dx = c_half26[o][0], dy = c_half26[o][1], dz = c_half26[o][2];
+    if (!conn_ok(dx, dy, dz, conn)) continue;
+    const uint32_t s = Fs[f];
+    const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
+    const uint64_t nk = shift_key(key, bits, dx, dy, dz);
+    const int64_t slot = tree_lookup(tree, Lp, nk);
+    if (slot < 0) {
+      atomicOr(err, kErrLookup);
+      continue;
+    }
+    const int32_t g = slot_f[slot];
+    if (g >= 0 && g != f) uf_unite(par, f, g);
+  }
+}
+
+__global__ void k_uf_compress(int32_t* par, uint64_t n, uint32_t* __restrict__ pred) {
+  GRID_STRIDE(i, n) {
+    const int32_t r = uf_find(par, (int32_t)i);
+    par[i] = r;
+    pred[i] = (r == (int32_t)i) ? 1u : 0u;
+  }
+}
+
+__global__ void k_uf_label(const int32_t* __restrict__ par, const uint32_t* __restrict__ rank,
+                           uint64_t n, int32_t* __restrict__ lab) {
+  GRID_STRIDE(i, n) lab[i] = (int32_t)rank[par[i]];
+}
+
+__global__ void k_cell_patch(const int32_t* __restrict__ lab, uint64_t nS, int32_t* __restrict__ Spatch) {
+  GRID_STRIDE(s, nS) Spatch[s] = lab[s >> 3];
+}
+
+// per patch: cells, particles (exact integer atomics); mass as fixed point
+__global__ void k_patch_stats(const int32_t* __restrict__ lab, uint64_t nF,
+                              const uint32_t* __restrict__ pFs, const uint32_t* __restrict__ pScount,
+                              const double* __restrict__ pSpmass, double fscale,
+                              uint32_t* __restrict__ ncells, unsigned long long* __restrict__ npart,
+                              unsigned long long* __restrict__ mfix) {
+  GRID_STRIDE(f, nF) {
+    const int32_t p = lab[f];
+    const uint32_t s = pFs[f];
+    atomicAdd(&ncells[p], 8u);
+    atomicAdd(&npart[p], (unsigned long long)pScount[s]);
+    if (mfix) atomicAdd(&mfix[p], (unsigned long long)llrint(pSpmass[s] * fscale));
+  }
+}
+
+__global__ void k_patch_parent(const int32_t* __restrict__ par, const int32_t* __restrict__ lab,
+                               uint64_t nF, const uint32_t* __restrict__ pFs,
+                               const int32_t* __restrict__ pSpatch, int32_t* __restrict__ parent) {
+  GRID_STRIDE(f, nF) {
+    if (par[f] == (int32_t)f) parent[lab[f]] = pSpatch ? pSpatch[pFs[f]] : -1;
+  }
+}
+
+__global__ void k_patch_mass(uint64_t np, const unsigned long long* __restrict__ npart,
+                             const unsigned long long* __restrict__ mfix, double mscalar,
+                             double inv_scale, double* __restrict__ pm) {
+  GRID_STRIDE(p, np) pm[p] = mfix ? (double)mfix[p] * inv_scale : (double)npart[p] * mscalar;
+}
+
+// ------------------------------------------------------------ host orchestration
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+static Tree make_tree(const Hier* h) {
+  Tree t;
+  for (int l = 0; l < kMaxLevels; ++l) t.slot_child[l] = nullptr;
+  for (size_t l = 0; l < h->lev.size() && l < (size_t)kMaxLevels; ++l)
+    t.slot_child[l] = h->lev[l].slot_child;
+  return t;
+}
+
+void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm, hipStream_t st,
+                     Hier* h) {
+  const double t0 = now_ms();
+  h->prm = prm;
+  h->n = p.n;
+  const int g = prm.g;
+  const int B = g + prm.Lmax;
+  h->B = B;
+  h->has_mass = p.mass != nullptr;
+  h->mass_scalar = p.mass_scalar;
+  const uint64_t n = p.n;
+
+  uint32_t* dev_u32 = ws.get<uint32_t>(8);   // [0] error flags, [1..] counters
+  double* dev_tot = ws.get<double>(3 * kMaxLevels);
+  HIP_CHECK(hipMemsetAsync(dev_u32, 0, 8 * sizeof(uint32_t), st));
+  HIP_CHECK(hipMemsetAsync(dev_tot, 0, 3 * kMaxLevels * sizeof(double), st));
+  uint32_t* err = dev_u32;
+
+  // ---- keys and their stable sort
+  uint64_t* keys = ws.get<uint64_t>(n);
+  uint32_t* vals = ws.get<uint32_t>(n);
+  uint64_t* ktmp = ws.get<uint64_t>(n);
+  uint32_t* vtmp = ws.get<uint32_t>(n);
+  if (n > 0) {
+    AHF_TIMED(ctx, "keys", st, (k_keys<<<grid_for(n), kT, 0, st>>>(p.x, p.y, p.z, n, B, keys, vals, err)));
+    sort_pairs(ws, keys, vals, ktmp, vtmp, n, 3 * B, st);
+  }
+  h->order = h->mem.get<uint32_t>(n);
+  if (n > 0) HIP_CHECK(hipMemcpyAsync(h->order, vals, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  const uint64_t* skey = keys;
+
+  Parts P;
+  uint32_t* sx = ws.get<uint32_t>(n);
+  uint32_t* sy = ws.get<uint32_t>(n);
+  uint32_t* sz = ws.get<uint32_t>(n);
+  float* sfx = ws.get<float>(n);
+  float* sfy = ws.get<float>(n);
+  float* sfz = ws.get<float>(n);
+  float* sm = p.mass ? ws.get<float>(n) : nullptr;
+  if (n > 0) {
+    AHF_TIMED(ctx, "gather", st,
+              (k_gather<<<grid_for(n), kT, 0, st>>>(h->order, n, p.x, p.y, p.z, p.fx, p.fy, p.fz,
+                                                    p.mass, sx, sy, sz, sfx, sfy, sfz, sm)));
+  }
+  P.x = sx; P.y = sy; P.z = sz; P.fx = sfx; P.fy = sfy; P.fz = sfz; P.m = sm;
+  P.mscalar = (float)p.mass_scalar;
+  HIP_CHECK(hipStreamSynchronize(st));
+  const double t1 = now_ms();
+
+  // ---- levels
+  uint64_t nFp = 1ull << (3 * (g - 1));  // parents of level 0: the virtual level -1
+  uint64_t nB = nFp;
+  uint64_t* Bkey = nullptr;
+  int32_t* Bcell = nullptr;
+  int32_t* Pbrick = nullptr;
+  h->lev.clear();
+  h->lev.reserve(kMaxLevels);
+  for (int L = 0; L <= prm.Lmax; ++L) {
+    h->lev.emplace_back();
+    Level& lv = h->lev.back();
+    const int b = g + L;
+    lv.b = (uint32_t)b;
+    const int sh = 3 * (B - b);
+    Ws::Mark lvl_mark = ws.mark();
+    if (L == 0) {
+      lv.nS = 1ull << (3 * g);
+      lv.Sstart = h->mem.get<uint32_t>(lv.nS + 1);
+      lv.Scount = h->mem.get<uint32_t>(lv.nS);
+      AHF_TIMED(ctx, "level0_start", st,
+                (k_l0_start<<<grid_for(n + 1), kT, 0, st>>>(skey, n, sh, lv.nS, lv.Sstart)));
+      k_l0_count<<<grid_for(lv.nS), kT, 0, st>>>(lv.Sstart, lv.nS, lv.Scount);
+      HIP_LAUNCH_CHECK();
+    } else {
+      const Level& pv = h->lev[L - 1];
+      lv.nS = 8 * pv.nF;
+      lv.Skey = h->mem.get<uint64_t>(lv.nS);
+      lv.Sstart = h->mem.get<uint32_t>(lv.nS);
+      lv.Scount = h->mem.get<uint32_t>(lv.nS);
+      AHF_TIMED(ctx, "child_ranges", st,
+                (k_child_ranges<<<grid_for(lv.nS), kT, 0, st>>>(skey, lv.nS, pv.Fs, pv.Sstart,
+                                                                pv.Scount, pv.Skey, sh, lv.Skey,
+                                                                lv.Sstart, lv.Scount)));
+    }
+    lv.nB = nB;
+    lv.Bkey = Bkey;
+    lv.Bcell = Bcell;
+    lv.Pbrick = Pbrick;
+    lv.Sflag = h->mem.get<uint8_t>(lv.nS);
+    lv.Spmass = h->mem.get<double>(lv.nS);
+
+    // refinement flags and the cells too full for one thread
+    const int can_refine = (L < prm.Lmax && b < kQBits) ? 1 : 0;
+    const double thr = (L == 0) ? prm.dom_ref : prm.ref_ref;
+    uint32_t* predF = ws.get<uint32_t>(lv.nS);
+    uint32_t* predH = ws.get<uint32_t>(lv.nS);
+    uint32_t* ofsF = ws.get<uint32_t>(lv.nS);
+    uint32_t* ofsH = ws.get<uint32_t>(lv.nS);
+    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag, predF, predH);
+    HIP_LAUNCH_CHECK();
+    scan_u32(ws, predF, ofsF, lv.nS, dev_u32 + 1, st);
+    scan_u32(ws, predH, ofsH, lv.nS, dev_u32 + 2, st);
+    uint32_t cnts[2];
+    HIP_CHECK(hipMemcpyAsync(cnts, dev_u32 + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    lv.nF = cnts[0];
+    const uint64_t nH = cnts[1];
+    lv.Fs = h->mem.get<uint32_t>(lv.nF);
+    if (lv.nF) {
+      k_compact<<<grid_for(lv.nS), kT, 0, st>>>(predF, ofsF, lv.nS, lv.Fs);
+      HIP_LAUNCH_CHECK();
+    }
+
+    const uint32_t mask = (1u << (kQBits - b)) - 1u;
+    const float scale = std::ldexp(1.0f, -(kQBits - b));
+
+    // heavy cells: chunked block sums
+    int32_t* hidx = nullptr;
+    float* hT = nullptr;
+    double* hM = nullptr;
+    if (nH > 0) {
+      uint32_t* Hs = ws.get<uint32_t>(nH);
+      k_compact<<<grid_for(lv.nS), kT, 0, st>>>(predH, ofsH, lv.nS, Hs);
+      HIP_LAUNCH_CHECK();
+      uint32_t* nch = ws.get<uint32_t>(nH);
+      uint32_t* chofs = ws.get<uint32_t>(nH);
+      k_heavy_nchunks<<<grid_for(nH), kT, 0, st>>>(Hs, nH, lv.Scount, nch);
+      HIP_LAUNCH_CHECK();
+      scan_u32(ws, nch, chofs, nH, dev_u32 + 3, st);
+      const uint64_t maxch = nH + n / kChunk + 1;
+      uint32_t* ch_h = ws.get<uint32_t>(maxch);
+      uint32_t* ch_j = ws.get<uint32_t>(maxch);
+      k_chunk_list<<<grid_for(nH), kT, 0, st>>>(nch, chofs, nH, ch_h, ch_j);
+      HIP_LAUNCH_CHECK();
+      float* chT = ws.get<float>(maxch * 27);
+      double* chM = ws.get<double>(maxch);
+      AHF_TIMED(ctx, "heavy_chunk", st,
+                (k_heavy_chunk<<<(unsigned)maxch, 256, 0, st>>>(dev_u32 + 3, ch_h, ch_j, Hs,
+                                                                lv.Sstart, lv.Scount, P, mask,
+                                                                scale, chT, chM)));
+      hT = ws.get<float>(nH * 27);
+      hM = ws.get<double>(nH);
+      k_heavy_reduce<<<grid_for(nH * 28), kT, 0, st>>>(nch, chofs, nH, chT, chM, hT, hM);
+      HIP_LAUNCH_CHECK();
+      hidx = ws.get<int32_t>(lv.nS);
+      k_fill_i32<<<grid_for(lv.nS), kT, 0, st>>>(hidx, lv.nS, -1);
+      HIP_LAUNCH_CHECK();
+      k_set_hidx<<<grid_for(nH), kT, 0, st>>>(Hs, nH, hidx);
+      HIP_LAUNCH_CHECK();
+    }
+
+    // TSC deposit: parent patches, then brick cells
+    float* patch = ws.get<float>(nFp * 64);
+    if (nFp) {
+      AHF_TIMED(ctx, "patches", st,
+                (k_patches<<<(unsigned)((nFp + 31) / 32), 256, 0, st>>>(
+                    nFp, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, patch, lv.Spmass)));
+    }
+    lv.mass = h->mem.get<float>(8 * nB);
+    {
+      Tree tree = make_tree(h);
+      const int32_t* pslot_f = (L > 0) ? h->lev[L - 1].slot_f : nullptr;
+      AHF_TIMED(ctx, "combine", st,
+                (k_combine<<<grid_for(8 * nB), kT, 0, st>>>(L, nB, Bkey, b - 1, tree, pslot_f,
+                                                            patch, lv.mass, err)));
+    }
+    sum_to_f64(ws, lv.mass, 8 * nB, dev_tot + 3 * L + 0, st);
+    sum_to_f64(ws, lv.Spmass, lv.nS, dev_tot + 3 * L + 1, st);
+    sum_to_f64(ws, lv.Scount, lv.nS, dev_tot + 3 * L + 2, st);
+
+    if (lv.nF == 0) {
+      ws.release(lvl_mark);
+      break;
+    }
+
+    // bricks of level L+1: children of every level-L cell within one cell of F_L
+    const uint64_t nslot = 8 * nB;
+    lv.slot_f = h->mem.get<int32_t>(nslot);
+    lv.slot_child = h->mem.get<int32_t>(nslot);
+    k_fill_i32<<<grid_for(nslot), kT, 0, st>>>(lv.slot_f, nslot, -1);
+    HIP_LAUNCH_CHECK();
+    k_slot_f<<<grid_for(lv.nF), kT, 0, st>>>(lv.nF, lv.Fs, lv.Pbrick, lv.slot_f);
+    HIP_LAUNCH_CHECK();
+    uint32_t* mark = ws.get<uint32_t>(nslot);
+    uint32_t* rank = ws.get<uint32_t>(nslot);
+    HIP_CHECK(hipMemsetAsync(mark, 0, nslot * sizeof(uint32_t), st));
+    {
+      Tree tree = make_tree(h);
+      AHF_TIMED(ctx, "mark", st,
+                (k_mark<<<grid_for(lv.nF * 27), kT, 0, st>>>(L, b, lv.nF, lv.Fs, lv.Skey, tree,
+                                                             mark, err)));
+    }
+    scan_u32(ws, mark, rank, nslot, dev_u32 + 4, st);
+    uint32_t nD = 0;
+    HIP_CHECK(hipMemcpyAsync(&nD, dev_u32 + 4, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    uint64_t* nBkey = h->mem.get<uint64_t>(nD);
+    int32_t* nBcell = h->mem.get<int32_t>(nD);
+    k_build_bricks<<<grid_for(nslot), kT, 0, st>>>(nslot, mark, rank, lv.Bkey, lv.slot_f,
+                                                   lv.slot_child, nBkey, nBcell);
+    HIP_LAUNCH_CHECK();
+    int32_t* nPbrick = h->mem.get<int32_t>(lv.nF);
+    k_pbrick<<<grid_for(lv.nF), kT, 0, st>>>(lv.nF, lv.Fs, lv.Pbrick, lv.slot_child, nPbrick);
+    HIP_LAUNCH_CHECK();
+    nFp = lv.nF;
+    nB = nD;
+    Bkey = nBkey;
+    Bcell = nBcell;
+    Pbrick = nPbrick;
+    ws.release(lvl_mark);
+  }
+
+  // totals and the device error flags
+  const size_t nl = h->lev.size();
+  std::vector<double> tot(3 * kMaxLevels);
+  uint32_t herr = 0;
+  HIP_CHECK(hipMemcpyAsync(tot.data(), dev_tot, 3 * kMaxLevels * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (size_t L = 0; L < nl; ++L) {
+    h->lev[L].tot_cell = tot[3 * L + 0];
+    h->lev[L].tot_part = tot[3 * L + 1];
+    h->lev[L].nP = (uint64_t)tot[3 * L + 2];
+  }
+  const double t2 = now_ms();
+  h->ms[0] = t1 - t0;
+  h->ms[1] = t2 - t1;
+  h->ms[3] = t2 - t0;
+  if (herr & kErrCoord) throw Error{AHF_EINVAL, "a particle coordinate is >= 2^21"};
+  if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed on the device"};
+}
+
+void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
+  if (h->labelled) return;
+  const double t0 = now_ms();
+  uint32_t* dev = ws.get<uint32_t>(4);
+  HIP_CHECK(hipMemsetAsync(dev, 0, 4 * sizeof(uint32_t), st));
+  const Tree tree = make_tree(h);
+  const double total_mass = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
+  for (size_t L = 1; L < h->lev.size(); ++L) {
+    Level& pv = h->lev[L - 1];
+    Level& lv = h->lev[L];
+    const uint64_t nE = pv.nF;
+    Ws::Mark m = ws.mark();
+    int32_t* par = ws.get<int32_t>(nE);
+    uint32_t* pred = ws.get<uint32_t>(nE);
+    uint32_t* rank = ws.get<uint32_t>(nE);
+    int32_t* lab = ws.get<int32_t>(nE);
+    k_uf_init<<<grid_for(nE), kT, 0, st>>>(par, nE);
+    HIP_LAUNCH_CHECK();
+    AHF_TIMED(ctx, "uf_hook", st,
+              (k_uf_hook<<<grid_for(nE * 13), kT, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs,
+                                                           pv.Skey, tree, pv.slot_f, h->prm.conn,
+                                                           par, dev)));
+    k_uf_compress<<<grid_for(nE), kT, 0, st>>>(par, nE, pred);
+    HIP_LAUNCH_CHECK();
+    scan_u32(ws, pred, rank, nE, dev + 1, st);
+    uint32_t np = 0;
+    HIP_CHECK(hipMemcpyAsync(&np, dev + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    lv.nPatch = np;
+    k_uf_label<<<grid_for(nE), kT, 0, st>>>(par, rank, nE, lab);
+    HIP_LAUNCH_CHECK();
+    lv.Spatch = h->mem.get<int32_t>(lv.nS);
+    k_cell_patch<<<grid_for(lv.nS), kT, 0, st>>>(lab, lv.nS, lv.Spatch);
+    HIP_LAUNCH_CHECK();
+    lv.patch_parent = h->mem.get<int32_t>(np);
+    lv.patch_ncells = h->mem.get<uint32_t>(np);
+    lv.patch_npart = h->mem.get<uint64_t>(np);
+    lv.patch_mass = h->mem.get<double>(np);
+    HIP_CHECK(hipMemsetAsync(lv.patch_ncells, 0, (np ? np : 1) * sizeof(uint32_t), st));
+    HIP_CHECK(hipMemsetAsync(lv.patch_npart, 0, (np ? np : 1) * sizeof(uint64_t), st));
+    unsigned long long* mfix = nullptr;
+    double fscale = 1.0;
+    if (h->has_mass) {
+      mfix = ws.get<unsigned long long>(np);
+      HIP_CHECK(hipMemsetAsync(mfix, 0, (np ? np : 1) * sizeof(unsigned long long), st));
+      int e = 0;
+      std::frexp(total_mass > 0 ? total_mass : 1.0, &e);
+      fscale = std::ldexp(1.0, 61 - e);
+    }
+    k_patch_stats<<<grid_for(nE), kT, 0, st>>>(lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale,
+                                               lv.patch_ncells,
+                                               (unsigned long long*)lv.patch_npart, mfix);
+    HIP_LAUNCH_CHECK();
+    k_patch_parent<<<grid_for(nE), kT, 0, st>>>(par, lab, nE, pv.Fs, (L >= 2) ? pv.Spatch : nullptr,
+                                                lv.patch_parent);
+    HIP_LAUNCH_CHECK();
+    k_patch_mass<<<grid_for(np), kT, 0, st>>>(np, (const unsigned long long*)lv.patch_npart, mfix,
+                                              h->mass_scalar, 1.0 / fscale, lv.patch_mass);
+    HIP_LAUNCH_CHECK();
+    HIP_CHECK(hipStreamSynchronize(st));
+    ws.release(m);
+  }
+  uint32_t herr = 0;
+  HIP_CHECK(hipMemcpyAsync(&herr, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed while labelling"};
+  h->labelled = true;
+  h->ms[2] = now_ms() - t0;
+  h->ms[3] += h->ms[2];
+}
+
+}  // namespace ahf

@@ -1,0 +1,123 @@
+"""Device hierarchy vs the CPU oracle, through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0904_3662_amd import synth
+from tests.gpu_compare import compare_hierarchy
+from tests.helpers import Q, clustered, from_positions, particles, small_mixed_scaled, uniform
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_0904_3662_amd import ahf
+    c = ahf.Context(0)
+    yield c
+    c.close()
+
+
+def run_case(ctx, p, connectivity=26, labels=True):
+    from paper_0904_3662_amd import ahf
+    print(f"case {p.name} n={p.n} g={p.g} Lmax={p.max_levels} conn={connectivity}", flush=True)
+    levels, order = oracle.build(p, connectivity=connectivity, labels=labels)
+    h, dev = ahf.build_snapshot(ctx, p, labels=labels, connectivity=connectivity)
+    m_max = 1.0 if p.mass is None else float(np.max(p.mass))
+    compare_hierarchy(h, p.n, levels, order, m_max=m_max, labels=labels)
+    h.free()
+    return levels
+
+
+def test_small_mixed_32k_full_parity(ctx):
+    # 32^3 particles, 70% uniform + 8 NFW halos, 32^3 domain grid, 4 levels
+    levels = run_case(ctx, synth.small_mixed(0))
+    assert len(levels) >= 3
+
+
+@pytest.mark.parametrize("conn", [26, 18, 6])
+def test_clustered_connectivities(ctx, conn):
+    run_case(ctx, clustered(3, 20000, n_clumps=6, spread=0.01, g=4, thr=5, max_levels=5), conn)
+
+
+@pytest.mark.parametrize("seed,g,Lmax", [(1, 1, 4), (2, 2, 4), (3, 3, 3), (4, 6, 2)])
+def test_uniform_various_grids(ctx, seed, g, Lmax):
+    run_case(ctx, uniform(seed, 5000, g=g, thr=5, max_levels=Lmax))
+
+
+def test_heavy_cells_multichunk(ctx):
+    # 40000 particles in one domain cell (3 chunks of 16384) plus background
+    rng = np.random.Generator(np.random.PCG64(5))
+    core = np.array([0.53, 0.41, 0.77]) + rng.normal(0, 0.004, (40000, 3))
+    bg = rng.random((3000, 3))
+    p = from_positions(np.concatenate([core, bg]), g=3, thr=5, max_levels=6)
+    p.name = "heavy"
+    run_case(ctx, p)
+
+
+def test_full_refinement_and_no_refinement(ctx):
+    run_case(ctx, uniform(7, 3000, g=2, thr=-1.0, max_levels=3))
+    run_case(ctx, uniform(8, 3000, g=4, thr=1e9, max_levels=3))
+
+
+def test_per_particle_mass(ctx):
+    p = clustered(9, 8000, g=3, thr=4, max_levels=4)
+    p.mass = (np.random.Generator(np.random.PCG64(10)).random(p.n) + 0.5).astype(np.float32)
+    run_case(ctx, p)
+
+
+def test_ragged_and_tiny_inputs(ctx):
+    for n in (1, 2, 63, 64, 65, 4095, 4097):
+        run_case(ctx, clustered(100 + n, n, g=2, thr=2, max_levels=3))
+
+
+def test_empty_input(ctx):
+    run_case(ctx, particles([], [], [], g=3, thr=5, max_levels=3))
+
+
+def test_coincident_chain_to_cap(ctx):
+    K = 100
+    x = 123457
+    f = np.float32(0.375)
+    p = particles([x] * K, [x + 999] * K, [x + 77777] * K, [f] * K, [f] * K, [f] * K, g=2,
+                  thr=5, max_levels=19)
+    run_case(ctx, p)
+
+
+def test_bit_identical_reruns(ctx):
+    from paper_0904_3662_amd import ahf
+    p = small_mixed_scaled(4, 30000, g=4, max_levels=5)
+    h1, dev = ahf.build_snapshot(ctx, p)
+    h2, _ = ahf.build_snapshot(ctx, p, dev=dev)
+    assert h1.num_levels() == h2.num_levels()
+    for L in range(h1.num_levels()):
+        a, b = h1.level_numpy(L), h2.level_numpy(L)
+        for k, v in a.items():
+            if isinstance(v, np.ndarray):
+                assert np.array_equal(v, b[k]), (L, k)
+            else:
+                assert v == b[k], (L, k)
+    h1.free()
+    h2.free()
+
+
+def test_invalid_coordinate_is_reported(ctx):
+    from paper_0904_3662_amd import ahf
+    p = uniform(11, 100, g=3, thr=5, max_levels=2)
+    p.X[5] = Q  # one past the 21-bit range
+    with pytest.raises(ahf.AhfError) as e:
+        ahf.build_snapshot(ctx, p)
+    assert e.value.code == ahf.AHF_EINVAL
+
+
+def test_bad_parameters_rejected_before_launch(ctx):
+    from paper_0904_3662_amd import ahf
+    p = uniform(12, 100, g=3, thr=5, max_levels=2)
+    dev = ahf.snapshot_to_device(p)
+    for kw in (dict(g=0), dict(g=11, max_levels=0), dict(g=10, max_levels=12),
+               dict(connectivity=7), dict(dom_ref=float("nan"))):
+        args = dict(g=3, dom_ref=5.0, ref_ref=5.0, max_levels=2, connectivity=26)
+        args.update(kw)
+        with pytest.raises(ahf.AhfError) as e:
+            ahf.build_hierarchy(ctx, *dev[:6], dev[6], **args)
+        assert e.value.code == ahf.AHF_EINVAL
