@@ -75,6 +75,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: the HIP library must be built first")
+    # torch ships its own HIP runtime; loading it first makes libahf.so bind to
+    # that same runtime (matched by soname) instead of a second copy
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     L.ahf_last_error.restype = C.c_char_p
@@ -102,7 +105,8 @@ def _hip_runtime():
     """libamdhip64 for device-to-host copies of the level arrays."""
     global _hip
     if _hip is None:
-        for name in ("libamdhip64.so", "/opt/rocm/lib/libamdhip64.so"):
+        load()  # the runtime already in the process, found by its soname
+        for name in ("libamdhip64.so.7", "libamdhip64.so"):
             try:
                 _hip = C.CDLL(name)
                 break
