@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -160,6 +161,7 @@ class Context:
         _check(L.ahf_ctx_create(C.byref(d), C.byref(h)))
         self._h = h
         self.device = device
+        self._live = weakref.WeakSet()  # hierarchies drawing on this context's memory
 
     @property
     def handle(self):
@@ -167,6 +169,8 @@ class Context:
 
     def close(self):
         if self._h:
+            for h in list(self._live):
+                h.free()
             load().ahf_ctx_destroy(self._h)
             self._h = None
 
@@ -203,9 +207,12 @@ def make_particles(x, y, z, fx=None, fy=None, fz=None, mass=None, mass_scalar=1.
 class Hierarchy:
     """A built hierarchy; level arrays stay on the device until copied."""
 
-    def __init__(self, handle, keep=None):
+    def __init__(self, handle, ctx=None, keep=None):
         self._h = handle
+        self._ctx = ctx
         self._keep = keep  # input tensors stay alive while the build may read them
+        if ctx is not None:
+            ctx._live.add(self)
 
     @property
     def handle(self):
@@ -265,7 +272,8 @@ class Hierarchy:
 
     def free(self):
         if self._h:
-            load().ahf_hierarchy_free(self._h)
+            if self._ctx is None or self._ctx._h:
+                load().ahf_hierarchy_free(self._h)
             self._h = None
             self._keep = None
 
@@ -286,7 +294,7 @@ def build_hierarchy(ctx: Context, x, y, z, fx=None, fy=None, fz=None, mass=None,
     h = C.c_void_p()
     _check(load().ahf_build_hierarchy(ctx.handle, C.byref(parts), C.byref(prm),
                                       _stream_handle(stream), C.byref(h)))
-    return Hierarchy(h, keep=(x, y, z, fx, fy, fz, mass))
+    return Hierarchy(h, ctx=ctx, keep=(x, y, z, fx, fy, fz, mass))
 
 
 def snapshot_to_device(s, device="cuda"):

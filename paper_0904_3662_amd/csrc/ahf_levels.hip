@@ -71,24 +71,16 @@ __global__ void k_keys(const uint32_t* __restrict__ X, const uint32_t* __restric
   }
 }
 
-// payload in sorted order
-__global__ void k_gather(const uint32_t* __restrict__ order, uint64_t n,
-                         const uint32_t* __restrict__ X, const uint32_t* __restrict__ Y,
-                         const uint32_t* __restrict__ Z, const float* __restrict__ fx,
-                         const float* __restrict__ fy, const float* __restrict__ fz,
-                         const float* __restrict__ m, uint32_t* __restrict__ sx,
-                         uint32_t* __restrict__ sy, uint32_t* __restrict__ sz,
-                         float* __restrict__ sfx, float* __restrict__ sfy,
-                         float* __restrict__ sfz, float* __restrict__ sm) {
+// payload in sorted order, two 32-bit arrays at a time: the pair being read
+// (2 x 4 B per particle) stays inside the 256 MB last-level cache, so the
+// random reads are served there instead of from HBM
+__global__ void k_gather2(const uint32_t* __restrict__ order, uint64_t n,
+                          const uint32_t* __restrict__ a, uint32_t* __restrict__ da, uint32_t ma,
+                          const uint32_t* __restrict__ b, uint32_t* __restrict__ db, uint32_t mb) {
   GRID_STRIDE(i, n) {
     const uint32_t j = order[i];
-    sx[i] = X[j] & 0x1fffffu;
-    sy[i] = Y[j] & 0x1fffffu;
-    sz[i] = Z[j] & 0x1fffffu;
-    sfx[i] = fx ? fx[j] : 0.0f;
-    sfy[i] = fy ? fy[j] : 0.0f;
-    sfz[i] = fz ? fz[j] : 0.0f;
-    if (m) sm[i] = m[j];
+    da[i] = a ? (a[j] & ma) : 0u;
+    if (db) db[i] = b ? (b[j] & mb) : 0u;
   }
 }
 
@@ -436,33 +428,39 @@ __global__ void k_pbrick(uint64_t nF, const uint32_t* __restrict__ Fs,
 
 // ------------------------------------------------------------ labels
 
-__device__ inline int32_t uf_load(int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// The forest keeps par[x] <= x, and a value stored in par[x] stays an
+// ancestor of x for ever after.  Plain (cached) loads may return an older
+// value, which is still an ancestor: a find then ends higher up the tree but
+// at a node of the same component.  Only roots are changed by the atomic CAS,
+// and a failed CAS returns the true parent, so every retry starts strictly
+// lower than the last one and the loop ends.  Path-halving stores are
+// device-scope atomics, so no cache line of par is ever dirty in an XCD's L2
+// (a late write-back of such a line could otherwise undo a CAS).
 __device__ inline int32_t uf_find(int32_t* par, int32_t x) {
   while (true) {
-    const int32_t p = uf_load(&par[x]);
+    const int32_t p = par[x];
     if (p == x) return x;
-    const int32_t gp = uf_load(&par[p]);
+    const int32_t gp = par[p];
     if (gp == p) return p;
-    __hip_atomic_store(&par[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // path halving
+    __hip_atomic_store(&par[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     x = gp;
   }
 }
 
-// link the larger root under the smaller one; retry while the root moved
+// link the larger root under the smaller one
 __device__ inline void uf_unite(int32_t* par, int32_t a, int32_t b) {
-  while (true) {
-    a = uf_find(par, a);
-    b = uf_find(par, b);
-    if (a == b) return;
+  a = uf_find(par, a);
+  b = uf_find(par, b);
+  while (a != b) {
     if (a > b) {
       const int32_t t = a;
       a = b;
       b = t;
     }
-    if (atomicCAS(&par[b], b, a) == b) return;
+    const int32_t old = atomicCAS(&par[b], b, a);
+    if (old == b) return;
+    b = uf_find(par, old);
+    a = uf_find(par, a);
   }
 }
 
@@ -481,66 +479,108 @@ __device__ inline bool conn_ok(int dx, int dy, int dz, int conn) {
 }
 
 // elements are the refined cells F of level Lp; each is united with its
-// refined neighbours
+// refined neighbours (one thread per cell, half of the offsets)
 __global__ void k_uf_hook(int Lp, int bits, uint64_t nF, const uint32_t* __restrict__ Fs,
                           const uint64_t* __restrict__ Skey, Tree tree,
                           const int32_t* __restrict__ slot_f, int conn, int32_t* __restrict__ par,
                           uint32_t* __restrict__ err) {
-  GRID_STRIDE(i, nF * 13) {
-    const int32_t f = (int32_t)(i / 13);
-    const int o = (int)(i % 13);
-    const int dx = c_half26[o][0], dy = c_half26[o][1], dz = c_half26[o][2];
-    if (!conn_ok(dx, dy, dz, conn)) continue;
+  GRID_STRIDE(i, nF) {
+    const int32_t f = (int32_t)i;
     const uint32_t s = Fs[f];
     const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
-    const uint64_t nk = shift_key(key, bits, dx, dy, dz);
-    const int64_t slot = tree_lookup(tree, Lp, nk);
-    if (slot < 0) {
-      atomicOr(err, kErrLookup);
-      continue;
+    for (int o = 0; o < 13; ++o) {
+      const int dx = c_half26[o][0], dy = c_half26[o][1], dz = c_half26[o][2];
+      if (!conn_ok(dx, dy, dz, conn)) continue;
+      const uint64_t nk = shift_key(key, bits, dx, dy, dz);
+      const int64_t slot = tree_lookup(tree, Lp, nk);
+      if (slot < 0) {
+        atomicOr(err, kErrLookup);
+        continue;
+      }
+      const int32_t g = slot_f[slot];
+      if (g >= 0 && g != f) uf_unite(par, f, g);
     }
-    const int32_t g = slot_f[slot];
-    if (g >= 0 && g != f) uf_unite(par, f, g);
   }
 }
 
-__global__ void k_uf_compress(int32_t* par, uint64_t n, uint32_t* __restrict__ pred) {
+// roots go to a separate array: par itself may still receive path-halving
+// stores from other threads, so it is never read back as the answer
+__global__ void k_uf_compress(int32_t* par, uint64_t n, int32_t* __restrict__ root,
+                              uint32_t* __restrict__ pred) {
   GRID_STRIDE(i, n) {
     const int32_t r = uf_find(par, (int32_t)i);
-    par[i] = r;
+    root[i] = r;
     pred[i] = (r == (int32_t)i) ? 1u : 0u;
   }
 }
 
-__global__ void k_uf_label(const int32_t* __restrict__ par, const uint32_t* __restrict__ rank,
+__global__ void k_uf_label(const int32_t* __restrict__ root, const uint32_t* __restrict__ rank,
                            uint64_t n, int32_t* __restrict__ lab) {
-  GRID_STRIDE(i, n) lab[i] = (int32_t)rank[par[i]];
+  GRID_STRIDE(i, n) lab[i] = (int32_t)rank[root[i]];
 }
 
 __global__ void k_cell_patch(const int32_t* __restrict__ lab, uint64_t nS, int32_t* __restrict__ Spatch) {
   GRID_STRIDE(s, nS) Spatch[s] = lab[s >> 3];
 }
 
-// per patch: cells, particles (exact integer atomics); mass as fixed point
-__global__ void k_patch_stats(const int32_t* __restrict__ lab, uint64_t nF,
+// per patch: cells, particles (exact integer atomics); mass as fixed point.
+// Refined cells are in key order and patches are compact, so neighbouring
+// lanes mostly share a patch: each wave sums every run of equal patch ids
+// (segmented scan) and adds it with one atomic per run.
+__device__ inline uint64_t shfl_up_u64(uint64_t v, int d) {
+  const uint32_t lo = __shfl_up((uint32_t)v, d, 64);
+  const uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ __launch_bounds__(256) void k_patch_stats(const int32_t* __restrict__ lab, uint64_t nF,
                               const uint32_t* __restrict__ pFs, const uint32_t* __restrict__ pScount,
                               const double* __restrict__ pSpmass, double fscale,
                               uint32_t* __restrict__ ncells, unsigned long long* __restrict__ npart,
                               unsigned long long* __restrict__ mfix) {
-  GRID_STRIDE(f, nF) {
-    const int32_t p = lab[f];
-    const uint32_t s = pFs[f];
-    atomicAdd(&ncells[p], 8u);
-    atomicAdd(&npart[p], (unsigned long long)pScount[s]);
-    if (mfix) atomicAdd(&mfix[p], (unsigned long long)llrint(pSpmass[s] * fscale));
+  const int lane = (int)__lane_id();
+  const uint64_t le = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < nF;
+       base += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t f = base + threadIdx.x;
+    const bool valid = f < nF;
+    const int32_t p = valid ? lab[f] : -1;
+    uint32_t c = valid ? 8u : 0u;
+    uint64_t np = 0, mf = 0;
+    if (valid) {
+      const uint32_t s = pFs[f];
+      np = pScount[s];
+      if (mfix) mf = (uint64_t)llrint(pSpmass[s] * fscale);
+    }
+    const int32_t pp = __shfl_up(p, 1, 64);
+    const bool head = (lane == 0) || (pp != p);
+    const uint64_t heads = __ballot(head);
+    const int rstart = 63 - __clzll(heads & le);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t c2 = __shfl_up(c, d, 64);
+      const uint64_t n2 = shfl_up_u64(np, d);
+      const uint64_t m2 = shfl_up_u64(mf, d);
+      if (lane - d >= rstart) {
+        c += c2;
+        np += n2;
+        mf += m2;
+      }
+    }
+    const bool tail = (lane == 63) || ((heads >> (lane + 1)) & 1ull);
+    if (valid && tail) {
+      atomicAdd(&ncells[p], c);
+      atomicAdd(&npart[p], (unsigned long long)np);
+      if (mfix) atomicAdd(&mfix[p], (unsigned long long)mf);
+    }
   }
 }
 
-__global__ void k_patch_parent(const int32_t* __restrict__ par, const int32_t* __restrict__ lab,
+__global__ void k_patch_parent(const int32_t* __restrict__ root, const int32_t* __restrict__ lab,
                                uint64_t nF, const uint32_t* __restrict__ pFs,
                                const int32_t* __restrict__ pSpatch, int32_t* __restrict__ parent) {
   GRID_STRIDE(f, nF) {
-    if (par[f] == (int32_t)f) parent[lab[f]] = pSpatch ? pSpatch[pFs[f]] : -1;
+    if (root[f] == (int32_t)f) parent[lab[f]] = pSpatch ? pSpatch[pFs[f]] : -1;
   }
 }
 
@@ -606,9 +646,25 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   float* sfz = ws.get<float>(n);
   float* sm = p.mass ? ws.get<float>(n) : nullptr;
   if (n > 0) {
+    const uint32_t* fxu = reinterpret_cast<const uint32_t*>(p.fx);
+    const uint32_t* fyu = reinterpret_cast<const uint32_t*>(p.fy);
+    const uint32_t* fzu = reinterpret_cast<const uint32_t*>(p.fz);
+    const uint32_t* mu = reinterpret_cast<const uint32_t*>(p.mass);
     AHF_TIMED(ctx, "gather", st,
-              (k_gather<<<grid_for(n), kT, 0, st>>>(h->order, n, p.x, p.y, p.z, p.fx, p.fy, p.fz,
-                                                    p.mass, sx, sy, sz, sfx, sfy, sfz, sm)));
+              (k_gather2<<<grid_for(n), kT, 0, st>>>(h->order, n, p.x, sx, 0x1fffffu, p.y, sy,
+                                                     0x1fffffu)));
+    AHF_TIMED(ctx, "gather", st,
+              (k_gather2<<<grid_for(n), kT, 0, st>>>(h->order, n, p.z, sz, 0x1fffffu, fxu,
+                                                     reinterpret_cast<uint32_t*>(sfx), ~0u)));
+    AHF_TIMED(ctx, "gather", st,
+              (k_gather2<<<grid_for(n), kT, 0, st>>>(h->order, n, fyu,
+                                                     reinterpret_cast<uint32_t*>(sfy), ~0u, fzu,
+                                                     reinterpret_cast<uint32_t*>(sfz), ~0u)));
+    if (sm)
+      AHF_TIMED(ctx, "gather", st,
+                (k_gather2<<<grid_for(n), kT, 0, st>>>(h->order, n, mu,
+                                                       reinterpret_cast<uint32_t*>(sm), ~0u,
+                                                       nullptr, nullptr, 0u)));
   }
   P.x = sx; P.y = sy; P.z = sz; P.fx = sfx; P.fy = sfy; P.fz = sfz; P.m = sm;
   P.mscalar = (float)p.mass_scalar;
@@ -811,23 +867,24 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     const uint64_t nE = pv.nF;
     Ws::Mark m = ws.mark();
     int32_t* par = ws.get<int32_t>(nE);
+    int32_t* root = ws.get<int32_t>(nE);
     uint32_t* pred = ws.get<uint32_t>(nE);
     uint32_t* rank = ws.get<uint32_t>(nE);
     int32_t* lab = ws.get<int32_t>(nE);
     k_uf_init<<<grid_for(nE), kT, 0, st>>>(par, nE);
     HIP_LAUNCH_CHECK();
     AHF_TIMED(ctx, "uf_hook", st,
-              (k_uf_hook<<<grid_for(nE * 13), kT, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs,
+              (k_uf_hook<<<grid_for(nE), kT, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs,
                                                            pv.Skey, tree, pv.slot_f, h->prm.conn,
                                                            par, dev)));
-    k_uf_compress<<<grid_for(nE), kT, 0, st>>>(par, nE, pred);
+    k_uf_compress<<<grid_for(nE), kT, 0, st>>>(par, nE, root, pred);
     HIP_LAUNCH_CHECK();
     scan_u32(ws, pred, rank, nE, dev + 1, st);
     uint32_t np = 0;
     HIP_CHECK(hipMemcpyAsync(&np, dev + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     lv.nPatch = np;
-    k_uf_label<<<grid_for(nE), kT, 0, st>>>(par, rank, nE, lab);
+    k_uf_label<<<grid_for(nE), kT, 0, st>>>(root, rank, nE, lab);
     HIP_LAUNCH_CHECK();
     lv.Spatch = h->mem.get<int32_t>(lv.nS);
     k_cell_patch<<<grid_for(lv.nS), kT, 0, st>>>(lab, lv.nS, lv.Spatch);
@@ -847,11 +904,11 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
       std::frexp(total_mass > 0 ? total_mass : 1.0, &e);
       fscale = std::ldexp(1.0, 61 - e);
     }
-    k_patch_stats<<<grid_for(nE), kT, 0, st>>>(lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale,
+    k_patch_stats<<<grid_for(nE), 256, 0, st>>>(lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale,
                                                lv.patch_ncells,
                                                (unsigned long long*)lv.patch_npart, mfix);
     HIP_LAUNCH_CHECK();
-    k_patch_parent<<<grid_for(nE), kT, 0, st>>>(par, lab, nE, pv.Fs, (L >= 2) ? pv.Spatch : nullptr,
+    k_patch_parent<<<grid_for(nE), kT, 0, st>>>(root, lab, nE, pv.Fs, (L >= 2) ? pv.Spatch : nullptr,
                                                 lv.patch_parent);
     HIP_LAUNCH_CHECK();
     k_patch_mass<<<grid_for(np), kT, 0, st>>>(np, (const unsigned long long*)lv.patch_npart, mfix,

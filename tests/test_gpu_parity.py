@@ -121,3 +121,16 @@ def test_bad_parameters_rejected_before_launch(ctx):
         with pytest.raises(ahf.AhfError) as e:
             ahf.build_hierarchy(ctx, *dev[:6], dev[6], **args)
         assert e.value.code == ahf.AHF_EINVAL
+
+
+@pytest.mark.parametrize("conn", [26, 18, 6])
+def test_labels_match_oracle_on_repeated_builds(ctx, conn):
+    # the union-find runs concurrently; every build must give the oracle's labels
+    from paper_0904_3662_amd import ahf
+    p = clustered(13, 30000, n_clumps=10, spread=0.015, g=4, thr=4, max_levels=5)
+    levels, order = oracle.build(p, connectivity=conn)
+    dev = ahf.snapshot_to_device(p)
+    for _ in range(5):
+        h, _ = ahf.build_snapshot(ctx, p, connectivity=conn, dev=dev)
+        compare_hierarchy(h, p.n, levels, order)
+        h.free()
