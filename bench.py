@@ -107,7 +107,7 @@ def main():
     total = time.perf_counter() - t_start
     kstats = {}
     for name in ("rs_scatter", "rs_hist", "keys", "gather", "level0_start", "child_ranges",
-                 "heavy_chunk", "patches", "combine", "mark", "uf_hook"):
+                 "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross"):
         kstats[name] = ctx.kernel_time(name)
     ctx.set_profiling(False)
     print(f"# steps done: {args.steps} in {total:.3f} s", file=sys.stderr, flush=True)

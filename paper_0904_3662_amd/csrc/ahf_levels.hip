@@ -53,34 +53,38 @@ __global__ void k_fill_i32(int32_t* a, uint64_t n, int32_t v) {
   GRID_STRIDE(i, n) a[i] = v;
 }
 
-__global__ void k_fill_u32(uint32_t* a, uint64_t n, uint32_t v) {
-  GRID_STRIDE(i, n) a[i] = v;
-}
 
-// Morton keys at B bits per axis and the identity permutation
+// Morton keys at B bits per axis, the identity permutation, and the particle
+// as one 32-byte record {X, Y, Z, mass | fx, fy, fz, 0} (input order)
 __global__ void k_keys(const uint32_t* __restrict__ X, const uint32_t* __restrict__ Y,
-                       const uint32_t* __restrict__ Z, uint64_t n, int B,
+                       const uint32_t* __restrict__ Z, const float* __restrict__ fx,
+                       const float* __restrict__ fy, const float* __restrict__ fz,
+                       const float* __restrict__ m, float mscalar, uint64_t n, int B,
                        uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                       uint32_t* __restrict__ err) {
+                       uint4* __restrict__ rec, uint32_t* __restrict__ err) {
   const int s = kQBits - B;
   GRID_STRIDE(i, n) {
     const uint32_t x = X[i], y = Y[i], z = Z[i];
     if ((x | y | z) >= (1u << kQBits)) atomicOr(err, kErrCoord);
-    keys[i] = morton3((x & 0x1fffffu) >> s, (y & 0x1fffffu) >> s, (z & 0x1fffffu) >> s);
+    const uint32_t xm = x & 0x1fffffu, ym = y & 0x1fffffu, zm = z & 0x1fffffu;
+    keys[i] = morton3(xm >> s, ym >> s, zm >> s);
     vals[i] = (uint32_t)i;
+    const float w = m ? m[i] : mscalar;
+    rec[2 * i] = make_uint4(xm, ym, zm, __float_as_uint(w));
+    rec[2 * i + 1] = make_uint4(fx ? __float_as_uint(fx[i]) : 0u, fy ? __float_as_uint(fy[i]) : 0u,
+                                fz ? __float_as_uint(fz[i]) : 0u, 0u);
   }
 }
 
-// payload in sorted order, two 32-bit arrays at a time: the pair being read
-// (2 x 4 B per particle) stays inside the 256 MB last-level cache, so the
-// random reads are served there instead of from HBM
-__global__ void k_gather2(const uint32_t* __restrict__ order, uint64_t n,
-                          const uint32_t* __restrict__ a, uint32_t* __restrict__ da, uint32_t ma,
-                          const uint32_t* __restrict__ b, uint32_t* __restrict__ db, uint32_t mb) {
+// records in sorted order: one random 32-byte read per particle
+__global__ void k_gather_rec(const uint32_t* __restrict__ order, uint64_t n,
+                             const uint4* __restrict__ rec, uint4* __restrict__ srec) {
   GRID_STRIDE(i, n) {
     const uint32_t j = order[i];
-    da[i] = a ? (a[j] & ma) : 0u;
-    if (db) db[i] = b ? (b[j] & mb) : 0u;
+    const uint4 a = rec[2 * (uint64_t)j];
+    const uint4 b = rec[2 * (uint64_t)j + 1];
+    srec[2 * i] = a;
+    srec[2 * i + 1] = b;
   }
 }
 
@@ -165,18 +169,18 @@ __device__ inline void tsc_axis(uint32_t X, float f, uint32_t mask, float scale,
 }
 
 struct Parts {
-  const uint32_t *x, *y, *z;
-  const float *fx, *fy, *fz, *m;
-  float mscalar;
+  const uint4* rec;  // 2 per particle, sorted order
 };
 
 __device__ inline void add_particle(const Parts& P, uint32_t p, uint32_t mask, float scale,
                                     float T[27], double& msum) {
+  const uint4 r0 = P.rec[2 * (uint64_t)p];
+  const uint4 r1 = P.rec[2 * (uint64_t)p + 1];
   float wx[3], wy[3], wz[3];
-  tsc_axis(P.x[p], P.fx[p], mask, scale, wx);
-  tsc_axis(P.y[p], P.fy[p], mask, scale, wy);
-  tsc_axis(P.z[p], P.fz[p], mask, scale, wz);
-  const float m = P.m ? P.m[p] : P.mscalar;
+  tsc_axis(r0.x, __uint_as_float(r1.x), mask, scale, wx);
+  tsc_axis(r0.y, __uint_as_float(r1.y), mask, scale, wy);
+  tsc_axis(r0.z, __uint_as_float(r1.z), mask, scale, wz);
+  const float m = __uint_as_float(r0.w);
   msum += (double)m;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -342,35 +346,101 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
   }
 }
 
-// one thread per brick cell: sum of the (at most 8) parent patches covering it,
+// 8 lanes per brick (32 bricks per block): the lanes share the lookups of
+// the refined parents among the 27 neighbours of the brick's parent through
+// LDS; each lane then sums, for its cell, the (at most 8) patches covering it
 // in a fixed order (own parent first)
-__global__ void k_combine(int L, uint64_t nB, const uint64_t* __restrict__ Bkey, int pbits, Tree tree,
-                          const int32_t* __restrict__ pslot_f, const float* __restrict__ patch,
-                          float* __restrict__ mass, uint32_t* __restrict__ err) {
-  GRID_STRIDE(i, nB * 8) {
-    const uint64_t bi = i >> 3;
-    const int d = (int)(i & 7);
-    const int ex = (d >> 2) & 1, ey = (d >> 1) & 1, ez = d & 1;
+__global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint64_t* __restrict__ Bkey,
+                                                 int pbits, Tree tree,
+                                                 const int32_t* __restrict__ pslot_f,
+                                                 const float* __restrict__ patch,
+                                                 float* __restrict__ mass) {
+  __shared__ int32_t fn[32][28];
+  const int lb = threadIdx.x >> 3;
+  const int d = threadIdx.x & 7;
+  const uint64_t bi = (uint64_t)blockIdx.x * 32 + lb;
+  if (bi < nB) {
     const uint64_t P = Bkey ? Bkey[bi] : bi;
-    float sum = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int sx = (c >> 2) & 1, sy = (c >> 1) & 1, sz = c & 1;
-      const int ox = sx ? (ex ? 1 : -1) : 0, oy = sy ? (ey ? 1 : -1) : 0, oz = sz ? (ez ? 1 : -1) : 0;
-      const int px = sx ? (ex ? 0 : 3) : ex + 1;
-      const int py = sy ? (ey ? 0 : 3) : ey + 1;
-      const int pz = sz ? (ez ? 0 : 3) : ez + 1;
-      const uint64_t Pn = c ? shift_key(P, pbits, ox, oy, oz) : P;
-      int64_t f;
+    uint32_t qx, qy, qz;
+    unmorton3(P, qx, qy, qz);
+    const uint32_t msk = (1u << pbits) - 1u;
+    for (int o = d; o < 27; o += 8) {
+      const int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
+      const uint64_t k = morton3((qx + dx) & msk, (qy + dy) & msk, (qz + dz) & msk);
+      int32_t f;
       if (L == 0) {
-        f = (int64_t)Pn;
+        f = (int32_t)k;
       } else {
-        const int64_t slot = tree_lookup(tree, L - 1, Pn);
-        f = slot < 0 ? -1 : (int64_t)pslot_f[slot];
+        const int64_t slot = tree_lookup(tree, L - 1, k);
+        f = slot < 0 ? -1 : pslot_f[slot];
       }
-      if (f >= 0) sum += patch[(uint64_t)f * 64 + px * 16 + py * 4 + pz];
+      fn[lb][o] = f;
     }
-    mass[i] = sum;
+  }
+  __syncthreads();
+  if (bi >= nB) return;
+  const int ex = (d >> 2) & 1, ey = (d >> 1) & 1, ez = d & 1;
+  float sum = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int sx = (c >> 2) & 1, sy = (c >> 1) & 1, sz = c & 1;
+    const int ox = sx ? (ex ? 1 : -1) : 0, oy = sy ? (ey ? 1 : -1) : 0, oz = sz ? (ez ? 1 : -1) : 0;
+    const int px = sx ? (ex ? 0 : 3) : ex + 1;
+    const int py = sy ? (ey ? 0 : 3) : ey + 1;
+    const int pz = sz ? (ez ? 0 : 3) : ez + 1;
+    const int32_t f = fn[lb][(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
+    if (f >= 0) sum += patch[(uint64_t)f * 64 + px * 16 + py * 4 + pz];
+  }
+  mass[bi * 8 + d] = sum;
+}
+
+// FP64 sums of a level: the field, the particle mass per cell, the counts
+__global__ __launch_bounds__(256) void k_level_sums(const float* __restrict__ a, uint64_t na,
+                                                    const double* __restrict__ b, uint64_t nb,
+                                                    const uint32_t* __restrict__ c, uint64_t nc,
+                                                    double* __restrict__ part) {
+  __shared__ double lds[3][4];
+  double s[3] = {0.0, 0.0, 0.0};
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint64_t i = i0; i < na; i += stride) s[0] += (double)a[i];
+  for (uint64_t i = i0; i < nb; i += stride) s[1] += b[i];
+  for (uint64_t i = i0; i < nc; i += stride) s[2] += (double)c[i];
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double v = s[k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) lds[k][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    part[(uint64_t)blockIdx.x * 3 + k] = (lds[k][0] + lds[k][1]) + (lds[k][2] + lds[k][3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_level_sums_final(const double* __restrict__ part, int np,
+                                                          double* __restrict__ out) {
+  __shared__ double lds[3][4];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < np; i += 256) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[k] += part[(uint64_t)i * 3 + k];
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double v = s[k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) lds[k][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    out[k] = (lds[k][0] + lds[k][1]) + (lds[k][2] + lds[k][3]);
   }
 }
 
@@ -464,9 +534,6 @@ __device__ inline void uf_unite(int32_t* par, int32_t a, int32_t b) {
   }
 }
 
-__global__ void k_uf_init(int32_t* par, uint64_t n) {
-  GRID_STRIDE(i, n) par[i] = (int32_t)i;
-}
 
 // half of the neighbour offsets of the connectivity (the other half is symmetric)
 __constant__ int8_t c_half26[13][3] = {{1, -1, -1}, {1, -1, 0}, {1, -1, 1}, {1, 0, -1}, {1, 0, 0},
@@ -478,27 +545,104 @@ __device__ inline bool conn_ok(int dx, int dy, int dz, int conn) {
   return conn == 6 ? s == 1 : (conn == 18 ? s <= 2 : true);
 }
 
-// elements are the refined cells F of level Lp; each is united with its
-// refined neighbours (one thread per cell, half of the offsets)
-__global__ void k_uf_hook(int Lp, int bits, uint64_t nF, const uint32_t* __restrict__ Fs,
-                          const uint64_t* __restrict__ Skey, Tree tree,
-                          const int32_t* __restrict__ slot_f, int conn, int32_t* __restrict__ par,
-                          uint32_t* __restrict__ err) {
-  GRID_STRIDE(i, nF) {
-    const int32_t f = (int32_t)i;
+constexpr int kUfTile = 1024;
+
+__device__ inline int32_t lds_find(volatile int32_t* lp, int32_t x) {
+  while (true) {
+    const int32_t p = lp[x];
+    if (p == x) return x;
+    const int32_t gp = lp[p];
+    if (gp == p) return p;
+    lp[x] = gp;
+    x = gp;
+  }
+}
+
+__device__ inline void lds_unite(int32_t* lp, int32_t a, int32_t b) {
+  volatile int32_t* v = lp;
+  a = lds_find(v, a);
+  b = lds_find(v, b);
+  while (a != b) {
+    if (a > b) {
+      const int32_t t = a;
+      a = b;
+      b = t;
+    }
+    const int32_t old = atomicCAS(&lp[b], b, a);
+    if (old == b) return;
+    b = lds_find(v, old);
+    a = lds_find(v, a);
+  }
+}
+
+__device__ inline int32_t refined_neighbour(int Lp, int bits, const Tree& tree,
+                                            const int32_t* __restrict__ slot_f, uint64_t key,
+                                            int o, uint32_t* err) {
+  const uint64_t nk = shift_key(key, bits, c_half26[o][0], c_half26[o][1], c_half26[o][2]);
+  const int64_t slot = tree_lookup(tree, Lp, nk);
+  if (slot < 0) {
+    atomicOr(err, kErrLookup);
+    return -1;
+  }
+  return slot_f[slot];
+}
+
+// Elements are the refined cells F of level Lp (key order).  Each block
+// unites the cells of kUfTile consecutive elements in LDS; edges that leave
+// the tile are marked in xmask for the global pass.  par[f] leaves as the
+// smallest index of f's component inside the tile.
+__global__ __launch_bounds__(256) void k_uf_local(int Lp, int bits, uint64_t nF,
+                                                  const uint32_t* __restrict__ Fs,
+                                                  const uint64_t* __restrict__ Skey, Tree tree,
+                                                  const int32_t* __restrict__ slot_f, int conn,
+                                                  int32_t* __restrict__ par,
+                                                  uint16_t* __restrict__ xmask,
+                                                  uint32_t* __restrict__ err) {
+  __shared__ int32_t lp[kUfTile];
+  const uint64_t t0 = (uint64_t)blockIdx.x * kUfTile;
+  const uint32_t tn = (uint32_t)((nF - t0) < (uint64_t)kUfTile ? (nF - t0) : (uint64_t)kUfTile);
+  for (int i = threadIdx.x; i < kUfTile; i += 256) lp[i] = i;
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < tn; i += 256) {
+    const uint64_t f = t0 + i;
     const uint32_t s = Fs[f];
     const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
+    uint32_t xm = 0;
+    int32_t gs[13];
+#pragma unroll
+    for (int o = 0; o < 13; ++o)
+      gs[o] = conn_ok(c_half26[o][0], c_half26[o][1], c_half26[o][2], conn)
+                  ? refined_neighbour(Lp, bits, tree, slot_f, key, o, err)
+                  : -1;
+#pragma unroll
     for (int o = 0; o < 13; ++o) {
-      const int dx = c_half26[o][0], dy = c_half26[o][1], dz = c_half26[o][2];
-      if (!conn_ok(dx, dy, dz, conn)) continue;
-      const uint64_t nk = shift_key(key, bits, dx, dy, dz);
-      const int64_t slot = tree_lookup(tree, Lp, nk);
-      if (slot < 0) {
-        atomicOr(err, kErrLookup);
-        continue;
-      }
-      const int32_t g = slot_f[slot];
-      if (g >= 0 && g != f) uf_unite(par, f, g);
+      const int32_t g = gs[o];
+      if (g < 0 || (uint64_t)g == f) continue;
+      if ((uint64_t)g >= t0 && (uint64_t)g < t0 + tn) lds_unite(lp, (int32_t)i, (int32_t)(g - t0));
+      else xm |= 1u << o;
+    }
+    xmask[f] = (uint16_t)xm;
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < tn; i += 256)
+    par[t0 + i] = (int32_t)(t0 + (uint64_t)lds_find(lp, (int32_t)i));
+}
+
+// the edges between tiles, on the global forest
+__global__ void k_uf_cross(int Lp, int bits, uint64_t nF, const uint32_t* __restrict__ Fs,
+                           const uint64_t* __restrict__ Skey, Tree tree,
+                           const int32_t* __restrict__ slot_f, const uint16_t* __restrict__ xmask,
+                           int32_t* __restrict__ par, uint32_t* __restrict__ err) {
+  GRID_STRIDE(f, nF) {
+    uint32_t xm = xmask[f];
+    if (!xm) continue;
+    const uint32_t s = Fs[f];
+    const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
+    while (xm) {
+      const int o = __ffs(xm) - 1;
+      xm &= xm - 1;
+      const int32_t g = refined_neighbour(Lp, bits, tree, slot_f, key, o, err);
+      if (g >= 0) uf_unite(par, (int32_t)f, g);
     }
   }
 }
@@ -629,8 +773,12 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   uint32_t* vals = ws.get<uint32_t>(n);
   uint64_t* ktmp = ws.get<uint64_t>(n);
   uint32_t* vtmp = ws.get<uint32_t>(n);
+  uint4* rec = ws.get<uint4>(2 * n);
   if (n > 0) {
-    AHF_TIMED(ctx, "keys", st, (k_keys<<<grid_for(n), kT, 0, st>>>(p.x, p.y, p.z, n, B, keys, vals, err)));
+    AHF_TIMED(ctx, "keys", st,
+              (k_keys<<<grid_for(n), kT, 0, st>>>(p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass,
+                                                  (float)p.mass_scalar, n, B, keys, vals, rec,
+                                                  err)));
     sort_pairs(ws, keys, vals, ktmp, vtmp, n, 3 * B, st);
   }
   h->order = h->mem.get<uint32_t>(n);
@@ -638,36 +786,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   const uint64_t* skey = keys;
 
   Parts P;
-  uint32_t* sx = ws.get<uint32_t>(n);
-  uint32_t* sy = ws.get<uint32_t>(n);
-  uint32_t* sz = ws.get<uint32_t>(n);
-  float* sfx = ws.get<float>(n);
-  float* sfy = ws.get<float>(n);
-  float* sfz = ws.get<float>(n);
-  float* sm = p.mass ? ws.get<float>(n) : nullptr;
-  if (n > 0) {
-    const uint32_t* fxu = reinterpret_cast<const uint32_t*>(p.fx);
-    const uint32_t* fyu = reinterpret_cast<const uint32_t*>(p.fy);
-    const uint32_t* fzu = reinterpret_cast<const uint32_t*>(p.fz);
-    const uint32_t* mu = reinterpret_cast<const uint32_t*>(p.mass);
+  uint4* srec = ws.get<uint4>(2 * n);
+  if (n > 0)
     AHF_TIMED(ctx, "gather", st,
-              (k_gather2<<<grid_for(n), kT, 0, st>>>(h->order, n, p.x, sx, 0x1fffffu, p.y, sy,
-                                                     0x1fffffu)));
-    AHF_TIMED(ctx, "gather", st,
-              (k_gather2<<<grid_for(n), kT, 0, st>>>(h->order, n, p.z, sz, 0x1fffffu, fxu,
-                                                     reinterpret_cast<uint32_t*>(sfx), ~0u)));
-    AHF_TIMED(ctx, "gather", st,
-              (k_gather2<<<grid_for(n), kT, 0, st>>>(h->order, n, fyu,
-                                                     reinterpret_cast<uint32_t*>(sfy), ~0u, fzu,
-                                                     reinterpret_cast<uint32_t*>(sfz), ~0u)));
-    if (sm)
-      AHF_TIMED(ctx, "gather", st,
-                (k_gather2<<<grid_for(n), kT, 0, st>>>(h->order, n, mu,
-                                                       reinterpret_cast<uint32_t*>(sm), ~0u,
-                                                       nullptr, nullptr, 0u)));
-  }
-  P.x = sx; P.y = sy; P.z = sz; P.fx = sfx; P.fy = sfy; P.fz = sfz; P.m = sm;
-  P.mscalar = (float)p.mass_scalar;
+              (k_gather_rec<<<grid_for(n), kT, 0, st>>>(h->order, n, rec, srec)));
+  P.rec = srec;
   HIP_CHECK(hipStreamSynchronize(st));
   const double t1 = now_ms();
 
@@ -784,12 +907,20 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       Tree tree = make_tree(h);
       const int32_t* pslot_f = (L > 0) ? h->lev[L - 1].slot_f : nullptr;
       AHF_TIMED(ctx, "combine", st,
-                (k_combine<<<grid_for(8 * nB), kT, 0, st>>>(L, nB, Bkey, b - 1, tree, pslot_f,
-                                                            patch, lv.mass, err)));
+                (k_combine<<<(unsigned)((nB + 31) / 32), 256, 0, st>>>(L, nB, Bkey, b - 1, tree,
+                                                                       pslot_f, patch, lv.mass)));
     }
-    sum_to_f64(ws, lv.mass, 8 * nB, dev_tot + 3 * L + 0, st);
-    sum_to_f64(ws, lv.Spmass, lv.nS, dev_tot + 3 * L + 1, st);
-    sum_to_f64(ws, lv.Scount, lv.nS, dev_tot + 3 * L + 2, st);
+    {
+      const uint64_t nmax = (8 * nB > lv.nS) ? 8 * nB : lv.nS;
+      int nblk = (int)((nmax + 255) / 256);
+      if (nblk > 2048) nblk = 2048;
+      if (nblk < 1) nblk = 1;
+      double* part = ws.get<double>(3 * (uint64_t)nblk);
+      k_level_sums<<<nblk, 256, 0, st>>>(lv.mass, 8 * nB, lv.Spmass, lv.nS, lv.Scount, lv.nS, part);
+      HIP_LAUNCH_CHECK();
+      k_level_sums_final<<<1, 256, 0, st>>>(part, nblk, dev_tot + 3 * L);
+      HIP_LAUNCH_CHECK();
+    }
 
     if (lv.nF == 0) {
       ws.release(lvl_mark);
@@ -871,12 +1002,16 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     uint32_t* pred = ws.get<uint32_t>(nE);
     uint32_t* rank = ws.get<uint32_t>(nE);
     int32_t* lab = ws.get<int32_t>(nE);
-    k_uf_init<<<grid_for(nE), kT, 0, st>>>(par, nE);
-    HIP_LAUNCH_CHECK();
-    AHF_TIMED(ctx, "uf_hook", st,
-              (k_uf_hook<<<grid_for(nE), kT, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs,
-                                                           pv.Skey, tree, pv.slot_f, h->prm.conn,
-                                                           par, dev)));
+    uint16_t* xmask = ws.get<uint16_t>(nE);
+    if (nE) {
+      AHF_TIMED(ctx, "uf_hook", st,
+                (k_uf_local<<<(unsigned)((nE + kUfTile - 1) / kUfTile), 256, 0, st>>>(
+                    (int)L - 1, (int)pv.b, nE, pv.Fs, pv.Skey, tree, pv.slot_f, h->prm.conn, par,
+                    xmask, dev)));
+      AHF_TIMED(ctx, "uf_cross", st,
+                (k_uf_cross<<<grid_for(nE), kT, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs, pv.Skey,
+                                                         tree, pv.slot_f, xmask, par, dev)));
+    }
     k_uf_compress<<<grid_for(nE), kT, 0, st>>>(par, nE, root, pred);
     HIP_LAUNCH_CHECK();
     scan_u32(ws, pred, rank, nE, dev + 1, st);
