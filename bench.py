@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="16m", choices=["16m", "32k"])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -106,7 +108,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     kstats = {}
-    for name in ("rs_scatter", "rs_hist", "keys", "gather", "level0_start", "child_ranges",
+    for name in ("rs_scatter", "keys", "gather", "level0_start", "child_ranges",
                  "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross"):
         kstats[name] = ctx.kernel_time(name)
     ctx.set_profiling(False)
@@ -146,6 +148,13 @@ def main():
         "kernels_ms_per_step": {k: v[1] / args.steps for k, v in kstats.items()},
         "levels": lv_info,
     }
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        rec["copy_probe_bytes"] = 2 * a.numel() * 4
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(snap)
     ctx.close()

@@ -175,7 +175,7 @@ void ahf_hierarchy_free(ahf_hierarchy *h);
 /*
  * Kernel timing for profiling.  While enabled, the context records a pair of
  * HIP events on the build stream around every launch of its main kernels
- * ("keys", "rs_hist", "rs_scatter", "gather", "level0_start", "child_ranges",
+ * ("keys", "rs_scatter", "gather", "level0_start", "child_ranges",
  * "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross").  Enabling or
  * disabling clears the accumulated times.  ahf_ctx_kernel_time returns the
  * number of launches and their summed device time (ms) for one name, reading

@@ -14,6 +14,7 @@ constexpr int kChunk = 16384;       // particles per chunk of a heavy cell (256 
 constexpr uint32_t kErrCoord = 1u;     // a coordinate >= 2^21
 constexpr uint32_t kErrLookup = 2u;    // a cell that must exist was not found
 constexpr uint32_t kErrInternal = 4u;
+constexpr uint32_t kErrSpin = 8u;      // a bounded wait gave up (never expected)
 
 // 21-bit value -> every third bit of a 63-bit word (Morton spreading)
 __host__ __device__ inline uint64_t spread3(uint32_t v) {
@@ -78,6 +79,30 @@ __device__ inline int64_t tree_lookup(const Tree& t, int L, uint64_t key) {
 __device__ inline uint64_t lanemask_lt() {
   const uint32_t lane = __lane_id();
   return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// Adds each active lane's key to h[p * 256 + digit_p] for the npass 8-bit
+// digits p, with one LDS atomic per distinct digit of the wave (lanes with the
+// same digit are matched by ballots).
+__device__ inline void wave_digit_hist(uint64_t key, bool valid, int npass, uint32_t* h) {
+  const uint64_t lt = lanemask_lt();
+  const uint64_t act = __ballot(valid);
+  // low digits of Morton keys are spread out: plain atomics rarely collide
+  const int plain = npass > 2 ? npass - 2 : 0;
+  for (int p = 0; p < plain; ++p)
+    if (valid) atomicAdd(&h[p * 256 + ((uint32_t)(key >> (8 * p)) & 255u)], 1u);
+  // the top digits take few values: match equal digits and add once per group
+  for (int p = plain; p < npass; ++p) {
+    const uint32_t d = (uint32_t)(key >> (8 * p)) & 255u;
+    uint64_t peer = act;
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t bm = __ballot(on);
+      peer &= on ? bm : ~bm;
+    }
+    if (valid && (peer & lt) == 0ull) atomicAdd(&h[p * 256 + d], (uint32_t)__popcll(peer));
+  }
 }
 
 }  // namespace ahf

@@ -55,7 +55,22 @@ struct Ctx {
   void* user = nullptr;
   Pool pool;
   Prof prof;
+  // decoupled look-back status words of the radix sort (kept between builds;
+  // every pass tags its words with a fresh epoch, so they never need clearing)
+  unsigned long long* rs_status = nullptr;
+  size_t rs_status_n = 0;
+  uint32_t rs_epoch = 0;
+  // the same for the one-pass scans; tile counters come from a ring of words
+  // that is cleared once every kLbCtrs scans
+  unsigned long long* lb_status = nullptr;
+  size_t lb_status_n = 0;
+  uint32_t lb_epoch = 0;
+  uint32_t* lb_ctr = nullptr;
+  uint32_t lb_ctr_used = 0;
+  uint32_t* dev_err = nullptr;  // device error flags of the running build
 };
+
+constexpr uint32_t kLbCtrs = 4096;
 
 // times one launch when the context profiles
 #define AHF_TIMED(ctxp, name, st, launch)                  \
@@ -128,8 +143,13 @@ struct Owned {
 // ---------------------------------------------------------------- primitives
 void scan_u32(Ws& ws, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
               hipStream_t st);
-void sort_pairs(Ws& ws, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp,
-                uint64_t n, int bits, hipStream_t st);
+// Stable LSD sort of (key, value) pairs by the low `bits` key bits in 8-bit
+// digits.  ghist[p * 256 + d] must hold the count of digit d of pass p over all
+// keys (see wave_digit_hist).  On return keys/vals hold the result.
+void sort_pairs(Ctx* ctx, Ws& ws, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp,
+                uint32_t*& vtmp, uint64_t n, int bits, const uint32_t* ghist, uint32_t* err,
+                hipStream_t st);
+constexpr int kRsMaxPass = 8;
 template <typename T>
 void sum_to_f64(Ws& ws, const T* a, uint64_t n, double* out, hipStream_t st);
 

@@ -27,6 +27,7 @@
 // the 4x4x4 patch they touch, and each brick cell gathers the at most 8 patches
 // that cover it, in a fixed order.  Every float sum therefore has a fixed
 // order and the result is bit-reproducible.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -54,26 +55,46 @@ __global__ void k_fill_i32(int32_t* a, uint64_t n, int32_t v) {
 }
 
 
-// Morton keys at B bits per axis, the identity permutation, and the particle
-// as one 32-byte record {X, Y, Z, mass | fx, fy, fz, 0} (input order)
-__global__ void k_keys(const uint32_t* __restrict__ X, const uint32_t* __restrict__ Y,
-                       const uint32_t* __restrict__ Z, const float* __restrict__ fx,
-                       const float* __restrict__ fy, const float* __restrict__ fz,
-                       const float* __restrict__ m, float mscalar, uint64_t n, int B,
-                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                       uint4* __restrict__ rec, uint32_t* __restrict__ err) {
+// Morton keys at B bits per axis, the identity permutation, the particle as
+// one 32-byte record {X, Y, Z, mass | fx, fy, fz, 0} (input order), and the
+// histograms of every 8-bit digit of the keys for the radix sort
+__global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
+                                              const uint32_t* __restrict__ Y,
+                                              const uint32_t* __restrict__ Z,
+                                              const float* __restrict__ fx,
+                                              const float* __restrict__ fy,
+                                              const float* __restrict__ fz,
+                                              const float* __restrict__ m, float mscalar,
+                                              uint64_t n, int B, int npass,
+                                              uint64_t* __restrict__ keys,
+                                              uint32_t* __restrict__ vals, uint4* __restrict__ rec,
+                                              uint32_t* __restrict__ ghist,
+                                              uint32_t* __restrict__ err) {
+  __shared__ uint32_t h[kRsMaxPass * 256];
+  for (int i = threadIdx.x; i < kRsMaxPass * 256; i += 256) h[i] = 0u;
+  __syncthreads();
   const int s = kQBits - B;
-  GRID_STRIDE(i, n) {
-    const uint32_t x = X[i], y = Y[i], z = Z[i];
-    if ((x | y | z) >= (1u << kQBits)) atomicOr(err, kErrCoord);
-    const uint32_t xm = x & 0x1fffffu, ym = y & 0x1fffffu, zm = z & 0x1fffffu;
-    keys[i] = morton3(xm >> s, ym >> s, zm >> s);
-    vals[i] = (uint32_t)i;
-    const float w = m ? m[i] : mscalar;
-    rec[2 * i] = make_uint4(xm, ym, zm, __float_as_uint(w));
-    rec[2 * i + 1] = make_uint4(fx ? __float_as_uint(fx[i]) : 0u, fy ? __float_as_uint(fy[i]) : 0u,
-                                fz ? __float_as_uint(fz[i]) : 0u, 0u);
+  for (uint64_t base = (uint64_t)blockIdx.x * 256; base < n; base += (uint64_t)gridDim.x * 256) {
+    const uint64_t i = base + threadIdx.x;
+    const bool valid = i < n;
+    uint64_t key = 0;
+    if (valid) {
+      const uint32_t x = X[i], y = Y[i], z = Z[i];
+      if ((x | y | z) >= (1u << kQBits)) atomicOr(err, kErrCoord);
+      const uint32_t xm = x & 0x1fffffu, ym = y & 0x1fffffu, zm = z & 0x1fffffu;
+      key = morton3(xm >> s, ym >> s, zm >> s);
+      keys[i] = key;
+      vals[i] = (uint32_t)i;
+      const float w = m ? m[i] : mscalar;
+      rec[2 * i] = make_uint4(xm, ym, zm, __float_as_uint(w));
+      rec[2 * i + 1] = make_uint4(fx ? __float_as_uint(fx[i]) : 0u, fy ? __float_as_uint(fy[i]) : 0u,
+                                  fz ? __float_as_uint(fz[i]) : 0u, 0u);
+    }
+    wave_digit_hist(key, valid, npass, h);
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < npass * 256; i += 256)
+    if (h[i]) atomicAdd(&ghist[i], h[i]);
 }
 
 // records in sorted order: one random 32-byte read per particle
@@ -455,6 +476,24 @@ __global__ void k_slot_f(uint64_t nF, const uint32_t* __restrict__ Fs,
   GRID_STRIDE(f, nF) slot_f[slot_of_s(Fs[f], Pbrick)] = (int32_t)f;
 }
 
+// level 0 is dense: a cell is in the dilation when one of its 27 neighbours
+// (itself included) is refined
+__global__ void k_mark_dense0(int g, uint64_t ncell, const uint8_t* __restrict__ flag,
+                              uint32_t* __restrict__ mark) {
+  const uint32_t msk = (1u << g) - 1u;
+  GRID_STRIDE(c, ncell) {
+    uint32_t x, y, z;
+    unmorton3(c, x, y, z);
+    uint32_t any = 0;
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+      const int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
+      any |= flag[morton3((x + dx) & msk, (y + dy) & msk, (z + dz) & msk)];
+    }
+    mark[c] = any ? 1u : 0u;
+  }
+}
+
 // mark every level-L slot within one cell of a refined cell
 __global__ void k_mark(int L, int bits, uint64_t nF, const uint32_t* __restrict__ Fs,
                        const uint64_t* __restrict__ Skey, Tree tree, uint32_t* __restrict__ mark,
@@ -545,7 +584,7 @@ __device__ inline bool conn_ok(int dx, int dy, int dz, int conn) {
   return conn == 6 ? s == 1 : (conn == 18 ? s <= 2 : true);
 }
 
-constexpr int kUfTile = 1024;
+constexpr int kUfTile = 256;
 
 __device__ inline int32_t lds_find(volatile int32_t* lp, int32_t x) {
   while (true) {
@@ -677,6 +716,9 @@ __device__ inline uint64_t shfl_up_u64(uint64_t v, int d) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// every wave walks its own contiguous range of cells 64 at a time and keeps
+// the run that reaches the end of a chunk as a carry, so a patch spread over
+// many cells costs about one atomic per wave
 __global__ __launch_bounds__(256) void k_patch_stats(const int32_t* __restrict__ lab, uint64_t nF,
                               const uint32_t* __restrict__ pFs, const uint32_t* __restrict__ pScount,
                               const double* __restrict__ pSpmass, double fscale,
@@ -684,10 +726,18 @@ __global__ __launch_bounds__(256) void k_patch_stats(const int32_t* __restrict__
                               unsigned long long* __restrict__ mfix) {
   const int lane = (int)__lane_id();
   const uint64_t le = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < nF;
-       base += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t f = base + threadIdx.x;
-    const bool valid = f < nF;
+  const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+  const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  uint64_t chunk = (nF + nw - 1) / nw;
+  chunk = (chunk + 63) & ~63ull;
+  const uint64_t r0 = wid * chunk;
+  const uint64_t r1 = (r0 + chunk < nF) ? r0 + chunk : nF;
+  int32_t cp = -1;  // carried run (wave-uniform)
+  uint32_t cc = 0;
+  uint64_t cn = 0, cm = 0;
+  for (uint64_t base = r0; base < r1; base += 64) {
+    const uint64_t f = base + lane;
+    const bool valid = f < r1;
     const int32_t p = valid ? lab[f] : -1;
     uint32_t c = valid ? 8u : 0u;
     uint64_t np = 0, mf = 0;
@@ -711,12 +761,41 @@ __global__ __launch_bounds__(256) void k_patch_stats(const int32_t* __restrict__
         mf += m2;
       }
     }
-    const bool tail = (lane == 63) || ((heads >> (lane + 1)) & 1ull);
-    if (valid && tail) {
+    // the chunk's first run continues the carried run when the ids agree
+    const int32_t p0 = __shfl(p, 0, 64);
+    if (cp >= 0 && cp != p0) {
+      if (lane == 0) {
+        atomicAdd(&ncells[cp], cc);
+        atomicAdd(&npart[cp], (unsigned long long)cn);
+        if (mfix) atomicAdd(&mfix[cp], (unsigned long long)cm);
+      }
+      cp = -1;
+    }
+    if (cp >= 0 && rstart == 0) {
+      c += cc;
+      np += cn;
+      mf += cm;
+    }
+    const uint64_t vmask = __ballot(valid);
+    const int last = 63 - __clzll(vmask);
+    const bool tail = valid && ((lane == last) || ((heads >> (lane + 1)) & 1ull));
+    if (tail && lane != last) {
       atomicAdd(&ncells[p], c);
       atomicAdd(&npart[p], (unsigned long long)np);
       if (mfix) atomicAdd(&mfix[p], (unsigned long long)mf);
     }
+    // the last run becomes the carry
+    cp = __shfl(p, last, 64);
+    cc = __shfl(c, last, 64);
+    cn = ((uint64_t)(uint32_t)__shfl((uint32_t)(np >> 32), last, 64) << 32) |
+         (uint32_t)__shfl((uint32_t)np, last, 64);
+    cm = ((uint64_t)(uint32_t)__shfl((uint32_t)(mf >> 32), last, 64) << 32) |
+         (uint32_t)__shfl((uint32_t)mf, last, 64);
+  }
+  if (cp >= 0 && lane == 0) {
+    atomicAdd(&ncells[cp], cc);
+    atomicAdd(&npart[cp], (unsigned long long)cn);
+    if (mfix) atomicAdd(&mfix[cp], (unsigned long long)cm);
   }
 }
 
@@ -767,6 +846,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   HIP_CHECK(hipMemsetAsync(dev_u32, 0, 8 * sizeof(uint32_t), st));
   HIP_CHECK(hipMemsetAsync(dev_tot, 0, 3 * kMaxLevels * sizeof(double), st));
   uint32_t* err = dev_u32;
+  ctx->dev_err = err;
 
   // ---- keys and their stable sort
   uint64_t* keys = ws.get<uint64_t>(n);
@@ -775,11 +855,16 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   uint32_t* vtmp = ws.get<uint32_t>(n);
   uint4* rec = ws.get<uint4>(2 * n);
   if (n > 0) {
+    const int npass = (3 * B + 7) / 8;
+    uint32_t* ghist = ws.get<uint32_t>(kRsMaxPass * 256);
+    HIP_CHECK(hipMemsetAsync(ghist, 0, kRsMaxPass * 256 * sizeof(uint32_t), st));
+    unsigned kb = grid_for(n);
+    if (kb > 2048) kb = 2048;
     AHF_TIMED(ctx, "keys", st,
-              (k_keys<<<grid_for(n), kT, 0, st>>>(p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass,
-                                                  (float)p.mass_scalar, n, B, keys, vals, rec,
-                                                  err)));
-    sort_pairs(ws, keys, vals, ktmp, vtmp, n, 3 * B, st);
+              (k_keys<<<kb, 256, 0, st>>>(p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass,
+                                          (float)p.mass_scalar, n, B, npass, keys, vals, rec,
+                                          ghist, err)));
+    sort_pairs(ctx, ws, keys, vals, ktmp, vtmp, n, 3 * B, ghist, err, st);
   }
   h->order = h->mem.get<uint32_t>(n);
   if (n > 0) HIP_CHECK(hipMemcpyAsync(h->order, vals, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
@@ -937,8 +1022,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     HIP_LAUNCH_CHECK();
     uint32_t* mark = ws.get<uint32_t>(nslot);
     uint32_t* rank = ws.get<uint32_t>(nslot);
-    HIP_CHECK(hipMemsetAsync(mark, 0, nslot * sizeof(uint32_t), st));
-    {
+    if (L == 0) {
+      AHF_TIMED(ctx, "mark", st,
+                (k_mark_dense0<<<grid_for(nslot), kT, 0, st>>>(g, nslot, lv.Sflag, mark)));
+    } else {
+      HIP_CHECK(hipMemsetAsync(mark, 0, nslot * sizeof(uint32_t), st));
       Tree tree = make_tree(h);
       AHF_TIMED(ctx, "mark", st,
                 (k_mark<<<grid_for(lv.nF * 27), kT, 0, st>>>(L, b, lv.nF, lv.Fs, lv.Skey, tree,
@@ -982,6 +1070,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   h->ms[1] = t2 - t1;
   h->ms[3] = t2 - t0;
   if (herr & kErrCoord) throw Error{AHF_EINVAL, "a particle coordinate is >= 2^21"};
+  if (herr & kErrSpin) throw Error{AHF_EDEVICE, "a look-back wait gave up (sort or scan)"};
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed on the device"};
 }
 
@@ -990,6 +1079,7 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
   const double t0 = now_ms();
   uint32_t* dev = ws.get<uint32_t>(4);
   HIP_CHECK(hipMemsetAsync(dev, 0, 4 * sizeof(uint32_t), st));
+  ctx->dev_err = dev;
   const Tree tree = make_tree(h);
   const double total_mass = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
   for (size_t L = 1; L < h->lev.size(); ++L) {
@@ -1039,7 +1129,7 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
       std::frexp(total_mass > 0 ? total_mass : 1.0, &e);
       fscale = std::ldexp(1.0, 61 - e);
     }
-    k_patch_stats<<<grid_for(nE), 256, 0, st>>>(lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale,
+    k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (nE + 4095) / 4096 + 1), 256, 0, st>>>(lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale,
                                                lv.patch_ncells,
                                                (unsigned long long*)lv.patch_npart, mfix);
     HIP_LAUNCH_CHECK();
@@ -1055,6 +1145,7 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
   uint32_t herr = 0;
   HIP_CHECK(hipMemcpyAsync(&herr, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  if (herr & kErrSpin) throw Error{AHF_EDEVICE, "scan look-back gave up waiting"};
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed while labelling"};
   h->labelled = true;
   h->ms[2] = now_ms() - t0;

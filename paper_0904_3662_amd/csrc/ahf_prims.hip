@@ -44,35 +44,89 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t& total, uint32_t
 }
 
 // ------------------------------------------------------------------ scan
+//
+// Exclusive scan of uint32 in one pass: tiles of 8192 values take their index
+// in start order, publish their sum, and find their offset by decoupled
+// look-back over earlier tiles (same status-word scheme as the radix sort).
 
 constexpr int kScanT = 256;
-constexpr int kScanI = 8;
+constexpr int kScanI = 32;
 constexpr int kScanTile = kScanT * kScanI;
+constexpr uint32_t kScanSpinMax = 1u << 22;
 
-__global__ __launch_bounds__(kScanT) void k_scan_reduce(const uint32_t* __restrict__ in, uint64_t n,
-                                                        uint32_t* __restrict__ bsum) {
-  __shared__ uint32_t lds[kScanT / 64 + 1];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-  uint32_t s = 0;
-#pragma unroll
-  for (int i = 0; i < kScanI; ++i) {
-    const uint64_t j = base + (uint64_t)i * kScanT + threadIdx.x;
-    if (j < n) s += in[j];
-  }
-  uint32_t tot;
-  block_excl_scan<kScanT>(s, tot, lds);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+__device__ inline unsigned long long lb_load(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void lb_store(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// blocked layout: thread t owns items [base + t*kScanI, base + t*kScanI + kScanI)
-__global__ __launch_bounds__(kScanT) void k_scan_apply(const uint32_t* __restrict__ in,
-                                                       uint32_t* __restrict__ out, uint64_t n,
-                                                       const uint32_t* __restrict__ boff,
-                                                       uint32_t* __restrict__ total_out) {
+// Exclusive prefix of tile `tile`, computed by the first wave of the block:
+// the 64 lanes read the status words of the 64 preceding tiles at once, sum
+// them back to the nearest inclusive prefix, and step back 64 tiles when
+// there is none.  status word: [63:40] epoch, [39:32] 1 = tile sum,
+// 2 = inclusive prefix, [31:0] value.  Call from all lanes of wave 0.
+__device__ inline uint32_t wave_lookback(unsigned long long* status, uint32_t tile, uint32_t own,
+                                         unsigned long long epoch, uint32_t spin_max,
+                                         uint32_t* err) {
+  const int lane = (int)__lane_id();
+  const unsigned long long tag = epoch << 40;
+  if (lane == 0) lb_store(status + tile, tag | ((tile == 0 ? 2ull : 1ull) << 32) | own);
+  if (tile == 0) return 0u;
+  uint32_t excl = 0;
+  int64_t j0 = (int64_t)tile - 1;
+  uint32_t spins = 0;
+  while (j0 >= 0) {
+    const int64_t j = j0 - lane;
+    uint32_t val = 0;
+    bool ready = true, incl = true;
+    if (j >= 0) {
+      const unsigned long long v = lb_load(status + j);
+      const uint32_t flag = (uint32_t)(v >> 32) & 0xffu;
+      ready = ((v >> 40) == epoch) && flag != 0u;
+      incl = ready && flag == 2u;
+      val = (uint32_t)v;
+    }
+    const uint64_t rmask = __ballot(ready);
+    const uint64_t imask = __ballot(incl);
+    uint64_t need = ~0ull;
+    if (imask) {
+      const int k = __ffsll((unsigned long long)imask) - 1;
+      need = (k == 63) ? ~0ull : ((1ull << (k + 1)) - 1ull);
+    }
+    if ((rmask & need) != need) {
+      if (++spins > spin_max) {
+        if (lane == 0) atomicOr(err, kErrSpin);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    uint32_t part = ((need >> lane) & 1ull) ? val : 0u;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+    excl += part;
+    if (imask) break;
+    j0 -= 64;
+  }
+  if (lane == 0) lb_store(status + tile, tag | (2ull << 32) | (uint32_t)(excl + own));
+  return excl;
+}
+
+__global__ __launch_bounds__(kScanT) void k_scan(const uint32_t* __restrict__ in,
+                                                 uint32_t* __restrict__ out, uint64_t n,
+                                                 unsigned long long* __restrict__ status,
+                                                 uint32_t* __restrict__ ctr,
+                                                 unsigned long long epoch,
+                                                 uint32_t* __restrict__ total,
+                                                 uint32_t* __restrict__ err) {
   __shared__ uint32_t lds[kScanT / 64 + 1];
   __shared__ uint32_t tile[kScanTile];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-  // coalesced load into LDS
+  __shared__ uint32_t tile_sh, excl_sh;
+  if (threadIdx.x == 0) tile_sh = atomicAdd(ctr, 1u);
+  __syncthreads();
+  const uint32_t t = tile_sh;
+  const uint64_t base = (uint64_t)t * kScanTile;
 #pragma unroll
   for (int i = 0; i < kScanI; ++i) {
     const uint64_t j = base + (uint64_t)i * kScanT + threadIdx.x;
@@ -88,7 +142,15 @@ __global__ __launch_bounds__(kScanT) void k_scan_apply(const uint32_t* __restric
   }
   uint32_t tot;
   uint32_t off = block_excl_scan<kScanT>(s, tot, lds);
-  off += boff ? boff[blockIdx.x] : 0u;
+  if (threadIdx.x < 64) {
+    const uint32_t e = wave_lookback(status, t, tot, epoch, kScanSpinMax, err);
+    if (threadIdx.x == 0) {
+      excl_sh = e;
+      if (total && (uint64_t)(t + 1) * kScanTile >= n) *total = e + tot;
+    }
+  }
+  __syncthreads();
+  off += excl_sh;
 #pragma unroll
   for (int i = 0; i < kScanI; ++i) {
     tile[threadIdx.x * kScanI + i] = off;
@@ -100,79 +162,115 @@ __global__ __launch_bounds__(kScanT) void k_scan_apply(const uint32_t* __restric
     const uint64_t j = base + (uint64_t)i * kScanT + threadIdx.x;
     if (j < n) out[j] = tile[i * kScanT + threadIdx.x];
   }
-  if (total_out && boff == nullptr && threadIdx.x == 0) *total_out = tot;
 }
 
 void scan_u32(Ws& ws, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
               hipStream_t st) {
-  const uint64_t nb = (n + kScanTile - 1) / kScanTile;
-  if (nb <= 1) {
-    k_scan_apply<<<1, kScanT, 0, st>>>(in, out, n, nullptr, total);
-    HIP_LAUNCH_CHECK();
-    return;
+  Ctx* ctx = ws.ctx();
+  uint64_t nt = (n + kScanTile - 1) / kScanTile;
+  if (nt < 1) nt = 1;
+  if (ctx->lb_status_n < nt) {
+    if (ctx->lb_status) ctx_free(ctx, ctx->lb_status, ctx->lb_status_n * 8, st);
+    const size_t want = nt < 4096 ? 4096 : nt;
+    ctx->lb_status = static_cast<unsigned long long*>(ctx_alloc(ctx, want * 8, st));
+    ctx->lb_status_n = want;
+    HIP_CHECK(hipMemsetAsync(ctx->lb_status, 0, want * 8, st));
+    ctx->lb_epoch = 0;
   }
-  uint32_t* bsum = ws.get<uint32_t>(nb);
-  k_scan_reduce<<<(unsigned)nb, kScanT, 0, st>>>(in, n, bsum);
-  HIP_LAUNCH_CHECK();
-  scan_u32(ws, bsum, bsum, nb, total, st);
-  k_scan_apply<<<(unsigned)nb, kScanT, 0, st>>>(in, out, n, bsum, nullptr);
+  if (ctx->lb_epoch + 1 >= (1u << 24) - 1) {
+    HIP_CHECK(hipMemsetAsync(ctx->lb_status, 0, ctx->lb_status_n * 8, st));
+    ctx->lb_epoch = 0;
+  }
+  // one counter word per scan, taken from a ring that is cleared in bulk
+  if (!ctx->lb_ctr) {
+    ctx->lb_ctr = static_cast<uint32_t*>(ctx_alloc(ctx, kLbCtrs * sizeof(uint32_t), st));
+    HIP_CHECK(hipMemsetAsync(ctx->lb_ctr, 0, kLbCtrs * sizeof(uint32_t), st));
+    ctx->lb_ctr_used = 0;
+  }
+  if (ctx->lb_ctr_used >= kLbCtrs) {
+    HIP_CHECK(hipMemsetAsync(ctx->lb_ctr, 0, kLbCtrs * sizeof(uint32_t), st));
+    ctx->lb_ctr_used = 0;
+  }
+  uint32_t* ctr = ctx->lb_ctr + ctx->lb_ctr_used++;
+  const unsigned long long epoch = ++ctx->lb_epoch;
+  k_scan<<<(unsigned)nt, kScanT, 0, st>>>(in, out, n, ctx->lb_status, ctr, epoch, total,
+                                          ctx->dev_err);
   HIP_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------------------------ radix sort
 //
-// LSD, 8-bit digits, reduce-then-scan.  A tile of 4096 pairs is split over
-// 4 waves of 1024 consecutive pairs; each wave ranks its pairs 64 at a time
-// with ballot-based digit matching, so the rank of a pair counts only pairs
-// before it in input order: the sort is stable.
+// LSD, 8-bit digits, one kernel per digit.  The digit histograms of all
+// passes come from the kernel that makes the keys.  A tile of 4096 pairs is
+// split over 4 waves of 1024 consecutive pairs; each wave ranks its pairs 64
+// at a time with ballot-based digit matching, so a pair's rank counts only
+// pairs before it in input order and the sort is stable.  Tiles take their
+// index in the order they start, publish their digit counts, and add up the
+// counts of earlier tiles by decoupled look-back: a tile only waits for tiles
+// that started before it, so every wait ends; the wait is bounded anyway and
+// raises an error flag instead of hanging.
 
 constexpr int kRsT = 256;
 constexpr int kRsW = kRsT / 64;
 constexpr int kRsR = 16;                 // rounds of 64 per wave
 constexpr int kRsTile = kRsT * kRsR;     // 4096
+constexpr uint32_t kRsSpinMax = 1u << 22;
 
-__global__ __launch_bounds__(kRsT) void k_rs_hist(const uint64_t* __restrict__ keys, uint64_t n,
-                                                  int shift, uint32_t* __restrict__ ghist,
-                                                  uint32_t ntiles) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
-#pragma unroll 4
-  for (int i = 0; i < kRsR; ++i) {
-    const uint64_t j = base + (uint64_t)i * kRsT + threadIdx.x;
-    if (j < n) atomicAdd(&h[(uint32_t)(keys[j] >> shift) & 255u], 1u);
+__global__ void k_rs_offsets(const uint32_t* __restrict__ ghist, int npass,
+                             uint32_t* __restrict__ gofs) {
+  __shared__ uint32_t lds[kRsT / 64 + 1];
+  for (int p = 0; p < npass; ++p) {
+    uint32_t tot;
+    const uint32_t v = ghist[p * 256 + threadIdx.x];
+    gofs[p * 256 + threadIdx.x] = block_excl_scan<kRsT>(v, tot, lds);
   }
-  __syncthreads();
-  ghist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kRsT) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                     const uint32_t* __restrict__ vin,
-                                                     uint64_t* __restrict__ kout,
-                                                     uint32_t* __restrict__ vout, uint64_t n,
-                                                     int shift, const uint32_t* __restrict__ goff,
-                                                     uint32_t ntiles) {
+__device__ inline unsigned long long rs_load(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void rs_store(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// status word: [63:40] epoch, [39:32] 1 = tile count, 2 = inclusive prefix, [31:0] value
+__global__ __launch_bounds__(kRsT) void k_rs_onesweep(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
+    const uint32_t* __restrict__ gofs, unsigned long long* __restrict__ status,
+    uint32_t* __restrict__ tile_ctr, unsigned long long epoch, uint32_t* __restrict__ err) {
   __shared__ uint64_t sk[kRsTile];
   __shared__ uint32_t sv[kRsTile];
   __shared__ uint32_t cnt[kRsW][256];
   __shared__ uint32_t doff[256];
+  __shared__ uint32_t gbase[256];
   __shared__ uint32_t lds[kRsT / 64 + 1];
+  __shared__ uint32_t tile_sh;
   const int w = threadIdx.x >> 6;
   const uint32_t lane = __lane_id();
+  if (threadIdx.x == 0) tile_sh = atomicAdd(tile_ctr, 1u);
   for (int i = threadIdx.x; i < kRsW * 256; i += kRsT) (&cnt[0][0])[i] = 0u;
   __syncthreads();
-  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+  const uint32_t tile = tile_sh;
+  const uint64_t tile0 = (uint64_t)tile * kRsTile;
   const uint64_t lt = lanemask_lt();
   uint64_t key[kRsR];
   uint32_t val[kRsR];
   uint32_t rk[kRsR];
+  // issue every load of the tile before the first use (the ranking below is a
+  // chain of ballots and LDS updates that would otherwise wait on each load)
+#pragma unroll
+  for (int r = 0; r < kRsR; ++r) {
+    const uint64_t j = tile0 + (uint64_t)w * (kRsR * 64) + (uint64_t)r * 64 + lane;
+    key[r] = (j < n) ? __builtin_nontemporal_load(kin + j) : 0ull;
+    val[r] = (j < n) ? __builtin_nontemporal_load(vin + j) : 0u;
+  }
 #pragma unroll
   for (int r = 0; r < kRsR; ++r) {
     const uint64_t j = tile0 + (uint64_t)w * (kRsR * 64) + (uint64_t)r * 64 + lane;
     const bool valid = j < n;
-    const uint64_t k = valid ? kin[j] : 0ull;
-    const uint32_t v = valid ? vin[j] : 0u;
+    const uint64_t k = key[r];
+    const uint32_t v = val[r];
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
     uint64_t peer = __ballot(valid);
 #pragma unroll
@@ -200,6 +298,51 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const uint64_t* __restrict_
     }
     uint32_t tot;
     doff[d] = block_excl_scan<kRsT>(s, tot, lds);
+    const unsigned long long tag = epoch << 40;
+    unsigned long long* mine = status + (uint64_t)tile * 256 + d;
+    uint32_t excl = 0;
+    if (tile == 0) {
+      rs_store(mine, tag | (2ull << 32) | s);
+    } else {
+      rs_store(mine, tag | (1ull << 32) | s);
+      // read 8 predecessors at a time; sum back to the nearest inclusive prefix
+      int64_t j0 = (int64_t)tile - 1;
+      uint32_t spins = 0;
+      while (j0 >= 0) {
+        unsigned long long v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          v[q] = (j0 - q >= 0) ? rs_load(status + (uint64_t)(j0 - q) * 256 + d)
+                               : ((epoch << 40) | (2ull << 32));
+        uint32_t acc = 0;
+        int done = 0;  // 1: reached an inclusive prefix, -1: hit a tile not ready yet
+        int used = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (done) continue;
+          const uint32_t flag = (uint32_t)(v[q] >> 32) & 0xffu;
+          if ((v[q] >> 40) != epoch || flag == 0u) {
+            done = -1;
+            continue;
+          }
+          acc += (uint32_t)v[q];
+          ++used;
+          if (flag == 2u) done = 1;
+        }
+        excl += acc;
+        j0 -= used;
+        if (done == 1) break;
+        if (done == -1) {
+          if (++spins > kRsSpinMax) {
+            atomicOr(err, kErrSpin);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      rs_store(mine, tag | (2ull << 32) | (uint32_t)(excl + s));
+    }
+    gbase[d] = gofs[d] + excl;
   }
   __syncthreads();
 #pragma unroll
@@ -216,27 +359,41 @@ __global__ __launch_bounds__(kRsT) void k_rs_scatter(const uint64_t* __restrict_
   for (uint32_t i = threadIdx.x; i < tn; i += kRsT) {
     const uint64_t k = sk[i];
     const uint32_t d = (uint32_t)(k >> shift) & 255u;
-    const uint64_t o = (uint64_t)goff[(uint64_t)d * ntiles + blockIdx.x] + (i - doff[d]);
+    const uint64_t o = (uint64_t)gbase[d] + (i - doff[d]);
     kout[o] = k;
     vout[o] = sv[i];
   }
 }
 
-// sorts by the low `bits` key bits; returns the buffers that hold the result
-void sort_pairs(Ws& ws, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp, uint32_t*& vtmp,
-                uint64_t n, int bits, hipStream_t st) {
+void sort_pairs(Ctx* ctx, Ws& ws, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp,
+                uint32_t*& vtmp, uint64_t n, int bits, const uint32_t* ghist, uint32_t* err,
+                hipStream_t st) {
   if (n <= 1 || bits <= 0) return;
+  const int npass = (bits + 7) / 8;
   const uint32_t ntiles = (uint32_t)((n + kRsTile - 1) / kRsTile);
-  const uint64_t nh = (uint64_t)ntiles * 256;
-  uint32_t* hist = ws.get<uint32_t>(nh);
-  for (int shift = 0; shift < bits; shift += 8) {
-    AHF_TIMED(ws.ctx(), "rs_hist", st,
-              (k_rs_hist<<<ntiles, kRsT, 0, st>>>(keys, n, shift, hist, ntiles)));
-    Ws::Mark m = ws.mark();
-    scan_u32(ws, hist, hist, nh, nullptr, st);
-    ws.release(m);
-    AHF_TIMED(ws.ctx(), "rs_scatter", st,
-              (k_rs_scatter<<<ntiles, kRsT, 0, st>>>(keys, vals, ktmp, vtmp, n, shift, hist, ntiles)));
+  const size_t nstat = (size_t)ntiles * 256;
+  if (ctx->rs_status_n < nstat) {
+    if (ctx->rs_status) ctx_free(ctx, ctx->rs_status, ctx->rs_status_n * 8, st);
+    ctx->rs_status = static_cast<unsigned long long*>(ctx_alloc(ctx, nstat * 8, st));
+    ctx->rs_status_n = nstat;
+    HIP_CHECK(hipMemsetAsync(ctx->rs_status, 0, nstat * 8, st));
+    ctx->rs_epoch = 0;
+  }
+  if (ctx->rs_epoch + npass >= (1u << 24) - 1) {
+    HIP_CHECK(hipMemsetAsync(ctx->rs_status, 0, ctx->rs_status_n * 8, st));
+    ctx->rs_epoch = 0;
+  }
+  uint32_t* gofs = ws.get<uint32_t>((uint64_t)npass * 256);
+  uint32_t* ctrs = ws.get<uint32_t>(kRsMaxPass);
+  HIP_CHECK(hipMemsetAsync(ctrs, 0, kRsMaxPass * sizeof(uint32_t), st));
+  k_rs_offsets<<<1, kRsT, 0, st>>>(ghist, npass, gofs);
+  HIP_LAUNCH_CHECK();
+  for (int p = 0; p < npass; ++p) {
+    const unsigned long long epoch = ++ctx->rs_epoch;
+    AHF_TIMED(ctx, "rs_scatter", st,
+              (k_rs_onesweep<<<ntiles, kRsT, 0, st>>>(keys, vals, ktmp, vtmp, n, 8 * p,
+                                                      gofs + p * 256, ctx->rs_status, ctrs + p,
+                                                      epoch, err)));
     std::swap(keys, ktmp);
     std::swap(vals, vtmp);
   }

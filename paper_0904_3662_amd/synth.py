@@ -22,6 +22,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -100,6 +102,21 @@ def power_law_counts(rng: np.random.Generator, k: int, lo: float, hi: float,
     return base
 
 
+CHUNK = 1 << 21
+
+
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _pmap(fn, items):
+    items = list(items)
+    if len(items) <= 1:
+        return [fn(it) for it in items]
+    with ThreadPoolExecutor(max_workers=_workers()) as ex:
+        return list(ex.map(fn, items))
+
+
 def _isotropic(rng: np.random.Generator, n: int) -> np.ndarray:
     mu = rng.uniform(-1.0, 1.0, n)
     phi = rng.uniform(0.0, 2.0 * math.pi, n)
@@ -111,24 +128,33 @@ def _nfw_m(x):
     return np.log1p(x) - x / (1.0 + x)
 
 
-def nfw_offsets(rng: np.random.Generator, counts: np.ndarray, conc: np.ndarray,
+def _nfw_chunk(rng, c, rs):
+    target = rng.random(len(c)) * _nfw_m(c)
+    lo = np.zeros(len(c))
+    hi = c.copy()
+    for _ in range(40):  # 2^-40 of c r_s: far below the 2^-21 quantum
+        mid = 0.5 * (lo + hi)
+        up = _nfw_m(mid) < target
+        np.copyto(lo, mid, where=up)
+        np.copyto(hi, mid, where=~up)
+    return _isotropic(rng, len(c)) * (0.5 * (lo + hi) * rs)[:, None]
+
+
+def nfw_offsets(seq: np.random.SeedSequence, counts: np.ndarray, conc: np.ndarray,
                 r200: np.ndarray) -> np.ndarray:
     """Offsets for halos with `counts[i]` particles, concentration conc[i] and
-    radius r200[i]: radius x*r_s with m(x)/m(c) uniform, solved by bisection in
-    float64 on [0, c]; directions isotropic."""
+    radius r200[i]: radius x*r_s with m(x)/m(c) uniform (m(x) = ln(1+x) -
+    x/(1+x)), solved by bisection in float64 on [0, c]; directions isotropic.
+    Drawn in fixed chunks, each from its own child stream of `seq`."""
     n = int(counts.sum())
     c = np.repeat(conc.astype(np.float64), counts)
     rs = np.repeat((r200 / conc).astype(np.float64), counts)
-    target = rng.random(n) * _nfw_m(c)
-    lo = np.zeros(n)
-    hi = c.copy()
-    for _ in range(64):
-        mid = 0.5 * (lo + hi)
-        go_up = _nfw_m(mid) < target
-        lo = np.where(go_up, mid, lo)
-        hi = np.where(go_up, hi, mid)
-    r = 0.5 * (lo + hi) * rs
-    return _isotropic(rng, n) * r[:, None]
+    starts = list(range(0, n, CHUNK))
+    seqs = seq.spawn(len(starts))
+    parts = _pmap(lambda k: _nfw_chunk(np.random.Generator(np.random.PCG64(seqs[k])),
+                                       c[starts[k]:starts[k] + CHUNK],
+                                       rs[starts[k]:starts[k] + CHUNK]), range(len(starts)))
+    return np.concatenate(parts) if parts else np.zeros((0, 3))
 
 
 def plummer_offsets(rng: np.random.Generator, counts: np.ndarray, a: np.ndarray,
@@ -152,6 +178,51 @@ def r200_of(count: np.ndarray, n_total: int) -> np.ndarray:
     return (3.0 * count / (4.0 * math.pi * 200.0 * n_total)) ** (1.0 / 3.0)
 
 
+def _lattice_subset(seq, sites: int, k: int) -> np.ndarray:
+    """Exactly k distinct lattice sites, each site equally likely: a
+    Bernoulli(k/sites) draw per site in fixed chunks, then the surplus or
+    shortfall removed or added uniformly at random."""
+    starts = list(range(0, sites, 1 << 24))
+    seqs = seq.spawn(len(starts) + 1)
+    frac = k / float(sites)
+
+    def draw(j):
+        r = np.random.Generator(np.random.PCG64(seqs[j]))
+        m = min(1 << 24, sites - starts[j])
+        return np.nonzero(r.random(m) < frac)[0].astype(np.int64) + starts[j]
+    pick = np.concatenate(_pmap(draw, range(len(starts))))
+    fix = np.random.Generator(np.random.PCG64(seqs[-1]))
+    if len(pick) > k:
+        drop = fix.choice(len(pick), len(pick) - k, replace=False)
+        keep = np.ones(len(pick), bool)
+        keep[drop] = False
+        pick = pick[keep]
+    elif len(pick) < k:
+        chosen = np.zeros(sites, bool)
+        chosen[pick] = True
+        while len(pick) < k:
+            extra = fix.integers(0, sites, 2 * (k - len(pick)) + 16)
+            extra = np.unique(extra[~chosen[extra]])
+            extra = extra[:k - len(pick)]
+            chosen[extra] = True
+            pick = np.sort(np.concatenate([pick, extra]))
+    return pick
+
+
+def _quantize_chunks(pos: np.ndarray):
+    n = pos.shape[0]
+    X = np.empty(n, np.uint32); Y = np.empty(n, np.uint32); Z = np.empty(n, np.uint32)
+    fx = np.empty(n, np.float32); fy = np.empty(n, np.float32); fz = np.empty(n, np.float32)
+
+    def q(a):
+        sl = slice(a, min(n, a + CHUNK))
+        X[sl], fx[sl] = quantize(pos[sl, 0])
+        Y[sl], fy[sl] = quantize(pos[sl, 1])
+        Z[sl], fz[sl] = quantize(pos[sl, 2])
+    _pmap(q, range(0, n, CHUNK))
+    return X, Y, Z, fx, fy, fz
+
+
 def snapshot(seed: int, n: int, *, g: int, thr: float, max_levels: int,
              halo_frac: float, n_halos: int, mass_lo: float, mass_hi: float,
              conc: float | tuple[float, float], lattice_side: int = 0,
@@ -161,29 +232,48 @@ def snapshot(seed: int, n: int, *, g: int, thr: float, max_levels: int,
     """Background (uniform if lattice_side == 0, else a random subset of a
     lattice_side^3 lattice perturbed by a Gaussian of sigma_cells * spacing per
     axis) plus `n_halos` NFW halos holding round(halo_frac*n) particles, with
-    optional Plummer subhalos inside each host."""
-    rng = np.random.Generator(np.random.PCG64(seed))
+    optional Plummer subhalos inside each host.  Every random draw comes from a
+    child stream of SeedSequence(seed) in fixed-size chunks, so the result does
+    not depend on the number of threads."""
+    root = np.random.SeedSequence(seed)
+    s_bg, s_halo, s_nfw, s_sub, s_shuf = root.spawn(5)
+    rng = np.random.Generator(np.random.PCG64(s_halo))
     n_halo_part = int(round(halo_frac * n))
     n_bg = n - n_halo_part
+    meta = dict(seed=seed, n=n, n_background=n_bg, n_halo_particles=n_halo_part,
+                n_halos=n_halos, lattice_side=lattice_side)
+    pos = np.empty((n, 3), np.float64)
     if lattice_side > 0:
         sites = lattice_side ** 3
         if n_bg > sites:
             raise ValueError("background larger than the lattice")
-        pick = rng.choice(sites, size=n_bg, replace=False)
-        iz = pick % lattice_side
-        iy = (pick // lattice_side) % lattice_side
-        ix = pick // (lattice_side * lattice_side)
+        s_pick, s_noise = s_bg.spawn(2)
+        pick = _lattice_subset(s_pick, sites, n_bg)
         sp = 1.0 / lattice_side
-        bg = np.stack([ix, iy, iz], axis=1).astype(np.float64) * sp + 0.5 * sp
-        bg += rng.normal(0.0, sigma_cells * sp, size=bg.shape)
+        starts = list(range(0, n_bg, CHUNK))
+        seqs = s_noise.spawn(len(starts))
+
+        def lat(j):
+            a = starts[j]
+            b = min(n_bg, a + CHUNK)
+            pk = pick[a:b]
+            r = np.random.Generator(np.random.PCG64(seqs[j]))
+            pos[a:b, 0] = (pk // (lattice_side * lattice_side)) * sp + 0.5 * sp
+            pos[a:b, 1] = ((pk // lattice_side) % lattice_side) * sp + 0.5 * sp
+            pos[a:b, 2] = (pk % lattice_side) * sp + 0.5 * sp
+            pos[a:b] += r.normal(0.0, sigma_cells * sp, size=(b - a, 3))
+        _pmap(lat, range(len(starts)))
     else:
-        bg = rng.random((n_bg, 3))
-    parts = [bg]
-    meta = dict(seed=seed, n=n, n_background=n_bg, n_halo_particles=n_halo_part,
-                n_halos=n_halos, lattice_side=lattice_side)
+        starts = list(range(0, n_bg, CHUNK))
+        seqs = s_bg.spawn(len(starts))
+
+        def uni(j):
+            a = starts[j]
+            b = min(n_bg, a + CHUNK)
+            pos[a:b] = np.random.Generator(np.random.PCG64(seqs[j])).random((b - a, 3))
+        _pmap(uni, range(len(starts)))
     if n_halo_part > 0 and n_halos > 0:
         counts = power_law_counts(rng, n_halos, mass_lo, mass_hi, n_halo_part)
-        expect = counts.sum()
         if isinstance(conc, tuple):
             cc = np.exp(rng.uniform(math.log(conc[0]), math.log(conc[1]), n_halos))
         else:
@@ -200,28 +290,30 @@ def snapshot(seed: int, n: int, *, g: int, thr: float, max_levels: int,
         else:
             host_counts = counts
         r200 = r200_of(counts, n)
-        host_off = nfw_offsets(rng, host_counts, cc, r200)
-        parts.append(np.repeat(centres, host_counts, axis=0) + host_off)
+        a = n_bg
+        nh = int(host_counts.sum())
+        pos[a:a + nh] = np.repeat(centres, host_counts, axis=0) + nfw_offsets(s_nfw, host_counts, cc, r200)
+        a += nh
         if n_sub > 0:
+            srng = np.random.Generator(np.random.PCG64(s_sub))
             sc = sub_counts.reshape(-1)
             keep = sc > 0
             owner = np.repeat(np.arange(n_halos), n_sub)[keep]
             sc = sc[keep]
             # subhalo centres follow the host's NFW profile inside r200
             sub_centre = centres[owner] + nfw_offsets(
-                rng, np.ones(len(sc), dtype=np.int64), cc[owner], r200[owner])
+                s_sub.spawn(1)[0], np.ones(len(sc), dtype=np.int64), cc[owner], r200[owner])
             rt = r200_of(sc, n)
-            parts.append(np.repeat(sub_centre, sc, axis=0) +
-                         plummer_offsets(rng, sc, rt / 5.0, rt))
+            ns = int(sc.sum())
+            pos[a:a + ns] = np.repeat(sub_centre, sc, axis=0) + plummer_offsets(srng, sc, rt / 5.0, rt)
+            a += ns
             meta["n_subhalos"] = int(len(sc))
-        meta["halo_count_sum"] = int(expect)
-    pos = np.concatenate(parts, axis=0)
-    assert pos.shape[0] == n, (pos.shape, n)
+        assert a == n, (a, n)
+        meta["halo_count_sum"] = int(counts.sum())
     if shuffle:
-        pos = pos[rng.permutation(n)]
-    X, fx = quantize(pos[:, 0])
-    Y, fy = quantize(pos[:, 1])
-    Z, fz = quantize(pos[:, 2])
+        perm = np.random.Generator(np.random.PCG64(s_shuf)).permutation(n)
+        pos = pos[perm]
+    X, Y, Z, fx, fy, fz = _quantize_chunks(pos)
     return Snapshot(X, Y, Z, fx, fy, fz, None, g, float(thr), float(thr), max_levels,
                     name, meta)
 
