@@ -185,6 +185,81 @@ ahf_status ahf_ctx_set_profiling(ahf_ctx *ctx, int enable);
 ahf_status ahf_ctx_kernel_time(ahf_ctx *ctx, const char *kernel, uint64_t *launches,
                                double *total_ms);
 
+/*
+ * Label query on one hierarchy: patch id of each level-`level` cell given by
+ * its Morton key (host arrays of n entries); -1 for a cell outside S_L and
+ * for every cell of level 0 (the domain grid is the root of the tree).
+ * The hierarchy must be labelled.  Synchronous on `stream`.
+ */
+ahf_status ahf_hierarchy_query_label(ahf_ctx *ctx, const ahf_hierarchy *h, uint32_t level,
+                                     uint64_t n, const uint64_t *keys, int32_t *out,
+                                     void *stream);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * A server builds hierarchies of many snapshot sub-volumes concurrently:
+ * n_streams worker threads, each with its own HIP stream and scratch space,
+ * take admitted requests in submission order, so requests that arrive while
+ * others are on the GPU start as soon as a worker and HBM are free and their
+ * kernels overlap on the device.  A request is admitted when its estimated
+ * footprint (inputs excluded) fits the HBM budget together with everything
+ * in flight and resident; finished hierarchies stay resident for label
+ * queries until released, and the least recently used finished ones are
+ * evicted when an admission needs their memory.  Results do not depend on
+ * what else runs: every build is deterministic.  All server calls are
+ * thread-safe.
+ */
+typedef struct {
+    uint32_t struct_size;   /* sizeof(ahf_server_desc) */
+    uint32_t n_streams;     /* concurrent builds, 1..16 */
+    uint32_t max_queue;     /* queued (not yet admitted) requests; 0 = 1024 */
+    uint32_t flags;         /* reserved, 0 */
+    uint64_t hbm_budget;    /* bytes for builds in flight + resident results;
+                               0 = 80% of the free device memory at creation */
+} ahf_server_desc;
+
+typedef struct {
+    uint64_t submitted, completed, failed, evicted, released;
+    uint64_t queued, running, resident;
+    uint64_t bytes_in_use;     /* estimates of running builds + resident results */
+    uint64_t bytes_peak;
+} ahf_server_stats;
+
+/* ctx supplies the device and the allocation callbacks; it must outlive the
+ * server.  Errors: AHF_EINVAL, AHF_EDEVICE, AHF_ENOMEM. */
+ahf_status ahf_server_create(ahf_ctx *ctx, const ahf_server_desc *desc, ahf_server **out);
+
+/* Non-blocking.  The particle arrays are borrowed until ahf_poll/ahf_wait has
+ * returned something other than AHF_PENDING for the ticket.  Errors:
+ * AHF_EINVAL (parameters, as ahf_build_hierarchy), AHF_ELIMIT (the request
+ * alone exceeds the budget), AHF_EBUSY (queue full). */
+ahf_status ahf_submit(ahf_server *s, const ahf_particles *particles, const ahf_params *params,
+                      uint64_t *ticket);
+
+/* AHF_PENDING while queued or running; AHF_OK with *h borrowed from the
+ * server (valid until ahf_release or eviction); the build's error status if
+ * it failed; AHF_ECANCELED if released before it ran; AHF_ENOTFOUND for an
+ * unknown, released or evicted ticket. */
+ahf_status ahf_poll(ahf_server *s, uint64_t ticket, ahf_hierarchy **h);
+/* as ahf_poll, but waits while the request is pending */
+ahf_status ahf_wait(ahf_server *s, uint64_t ticket, ahf_hierarchy **h);
+
+/* label query on a finished, resident request (see ahf_hierarchy_query_label) */
+ahf_status ahf_query_label(ahf_server *s, uint64_t ticket, uint32_t level, uint64_t n,
+                           const uint64_t *keys, int32_t *out);
+
+/* Drops the result of a finished request, or cancels a queued one (its poll
+ * then returns AHF_ENOTFOUND).  A running request is released when it ends. */
+ahf_status ahf_release(ahf_server *s, uint64_t ticket);
+
+/* submit, admission, start and end times of a request in ms on the host's
+ * steady clock (t[0..3]); start/end are 0 until they happen */
+ahf_status ahf_ticket_times(ahf_server *s, uint64_t ticket, double *t);
+ahf_status ahf_server_get_stats(ahf_server *s, ahf_server_stats *out);
+
+/* Waits for running builds, frees every result. */
+void ahf_server_destroy(ahf_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,9 @@ EXPORTS = [
     "ahf_last_error", "ahf_ctx_create", "ahf_ctx_destroy", "ahf_build_hierarchy",
     "ahf_label_refinements", "ahf_hierarchy_num_levels", "ahf_level_get",
     "ahf_hierarchy_order", "ahf_hierarchy_timings", "ahf_hierarchy_free",
-    "ahf_ctx_set_profiling", "ahf_ctx_kernel_time",
+    "ahf_ctx_set_profiling", "ahf_ctx_kernel_time", "ahf_hierarchy_query_label",
+    "ahf_server_create", "ahf_submit", "ahf_poll", "ahf_wait", "ahf_query_label",
+    "ahf_release", "ahf_ticket_times", "ahf_server_get_stats", "ahf_server_destroy",
 ]
 
 
@@ -65,6 +67,17 @@ class LevelView(C.Structure):
                 ("total_cell_mass", C.c_double), ("total_particle_mass", C.c_double)]
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_streams", C.c_uint32),
+                ("max_queue", C.c_uint32), ("flags", C.c_uint32), ("hbm_budget", C.c_uint64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in ("submitted", "completed", "failed", "evicted",
+                                          "released", "queued", "running", "resident",
+                                          "bytes_in_use", "bytes_peak")]
+
+
 _lib = None
 _hip = None
 
@@ -95,8 +108,20 @@ def load():
     L.ahf_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
     L.ahf_hierarchy_free.argtypes = [vp]
     L.ahf_hierarchy_free.restype = None
+    L.ahf_hierarchy_query_label.argtypes = [vp, vp, C.c_uint32, C.c_uint64, vp, vp, vp]
+    L.ahf_server_create.argtypes = [vp, C.POINTER(ServerDesc), C.POINTER(vp)]
+    L.ahf_submit.argtypes = [vp, C.POINTER(Particles), C.POINTER(Params), C.POINTER(C.c_uint64)]
+    L.ahf_poll.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+    L.ahf_wait.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+    L.ahf_query_label.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint64, vp, vp]
+    L.ahf_release.argtypes = [vp, C.c_uint64]
+    L.ahf_ticket_times.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
+    L.ahf_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    L.ahf_server_destroy.argtypes = [vp]
+    L.ahf_server_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("ahf_ctx_destroy", "ahf_hierarchy_free", "ahf_last_error"):
+        if name not in ("ahf_ctx_destroy", "ahf_hierarchy_free", "ahf_last_error",
+                        "ahf_server_destroy"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -207,11 +232,12 @@ def make_particles(x, y, z, fx=None, fy=None, fz=None, mass=None, mass_scalar=1.
 class Hierarchy:
     """A built hierarchy; level arrays stay on the device until copied."""
 
-    def __init__(self, handle, ctx=None, keep=None):
+    def __init__(self, handle, ctx=None, keep=None, borrowed=False):
         self._h = handle
         self._ctx = ctx
         self._keep = keep  # input tensors stay alive while the build may read them
-        if ctx is not None:
+        self._borrowed = borrowed  # owned by a server: never freed from here
+        if ctx is not None and not borrowed:
             ctx._live.add(self)
 
     @property
@@ -270,9 +296,18 @@ class Hierarchy:
     def label(self, ctx: Context, stream=None):
         _check(load().ahf_label_refinements(ctx.handle, self._h, _stream_handle(stream)))
 
+    def query_label(self, ctx: "Context", level: int, keys: np.ndarray, stream=None) -> np.ndarray:
+        """Patch id of each level cell given by key (-1 outside S_L)."""
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        out = np.empty(len(k), np.int32)
+        _check(load().ahf_hierarchy_query_label(ctx.handle, self._h, int(level), len(k),
+                                                k.ctypes.data, out.ctypes.data,
+                                                _stream_handle(stream)))
+        return out
+
     def free(self):
         if self._h:
-            if self._ctx is None or self._ctx._h:
+            if not self._borrowed and (self._ctx is None or self._ctx._h):
                 load().ahf_hierarchy_free(self._h)
             self._h = None
             self._keep = None
@@ -314,3 +349,80 @@ def build_snapshot(ctx: Context, s, labels=True, connectivity=26, stream=None, d
     return build_hierarchy(ctx, *dev[:6], dev[6], g=s.g, dom_ref=s.dom_ref, ref_ref=s.ref_ref,
                            max_levels=s.max_levels, connectivity=connectivity, labels=labels,
                            stream=stream), dev
+
+
+class Server:
+    """Continuous-batching server (ahf_server_*): requests overlap on the GPU."""
+
+    def __init__(self, ctx: Context, n_streams: int = 4, max_queue: int = 0,
+                 hbm_budget: int = 0):
+        d = ServerDesc(C.sizeof(ServerDesc), int(n_streams), int(max_queue), 0, int(hbm_budget))
+        h = C.c_void_p()
+        _check(load().ahf_server_create(ctx.handle, C.byref(d), C.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._inputs = {}  # ticket -> tensors the build reads
+
+    def submit(self, x, y, z, fx=None, fy=None, fz=None, mass=None, *, g, dom_ref, ref_ref,
+               max_levels, connectivity=26, labels=True, mass_scalar=1.0) -> int:
+        parts = make_particles(x, y, z, fx, fy, fz, mass, mass_scalar)
+        prm = make_params(g, dom_ref, ref_ref, max_levels, connectivity,
+                          0 if labels else AHF_NO_LABELS)
+        t = C.c_uint64()
+        _check(load().ahf_submit(self._h, C.byref(parts), C.byref(prm), C.byref(t)))
+        self._inputs[t.value] = (x, y, z, fx, fy, fz, mass)
+        return int(t.value)
+
+    def submit_snapshot(self, snap, dev=None, connectivity=26, labels=True) -> int:
+        dev = dev if dev is not None else snapshot_to_device(snap)
+        return self.submit(*dev[:6], dev[6], g=snap.g, dom_ref=snap.dom_ref,
+                           ref_ref=snap.ref_ref, max_levels=snap.max_levels,
+                           connectivity=connectivity, labels=labels)
+
+    def _result(self, rc, ticket, h):
+        if rc == AHF_PENDING:
+            return None
+        self._inputs.pop(ticket, None)
+        _check(rc)
+        return Hierarchy(h, borrowed=True)
+
+    def poll(self, ticket: int):
+        """None while pending, else the (borrowed) Hierarchy; raises on failure."""
+        h = C.c_void_p()
+        return self._result(load().ahf_poll(self._h, C.c_uint64(ticket), C.byref(h)), ticket, h)
+
+    def wait(self, ticket: int):
+        h = C.c_void_p()
+        return self._result(load().ahf_wait(self._h, C.c_uint64(ticket), C.byref(h)), ticket, h)
+
+    def query_label(self, ticket: int, level: int, keys: np.ndarray) -> np.ndarray:
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        out = np.empty(len(k), np.int32)
+        _check(load().ahf_query_label(self._h, C.c_uint64(ticket), int(level), len(k),
+                                      k.ctypes.data, out.ctypes.data))
+        return out
+
+    def release(self, ticket: int):
+        _check(load().ahf_release(self._h, C.c_uint64(ticket)))
+
+    def times(self, ticket: int):
+        a = (C.c_double * 4)()
+        _check(load().ahf_ticket_times(self._h, C.c_uint64(ticket), a))
+        return list(a)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().ahf_server_get_stats(self._h, C.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            load().ahf_server_destroy(self._h)
+            self._h = None
+            self._inputs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

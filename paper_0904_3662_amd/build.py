@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libahf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["ahf_prims.hip", "ahf_levels.hip", "ahf_capi.cpp"]
+SOURCES = ["ahf_prims.hip", "ahf_levels.hip", "ahf_capi.cpp", "ahf_server.cpp"]
 ARCH = os.environ.get("AHF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -45,7 +45,8 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = OUT + ".tmp"
-    r = subprocess.run([cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp],
+    r = subprocess.run([cc, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp,
+                        "-lpthread"],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{r.stdout}\n{r.stderr}")

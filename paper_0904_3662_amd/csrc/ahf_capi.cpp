@@ -10,6 +10,8 @@ namespace ahf {
 
 static thread_local std::string g_last_error;
 
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
 static ahf_status fail(ahf_status code, const std::string& msg) {
   g_last_error = msg;
   return code;
@@ -28,6 +30,8 @@ static size_t round_size(size_t b) {
   return (b + q - 1) / q * q;
 }
 
+static void release_free_blocks(Ctx* c);
+
 void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s) {
   if (bytes == 0) bytes = 1;
   if (c->alloc) {
@@ -36,6 +40,7 @@ void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s) {
     return p;
   }
   const size_t r = round_size(bytes);
+  std::lock_guard<std::mutex> lk(c->pool.mu);
   auto& fb = c->pool.free_blocks;
   for (size_t i = 0; i < fb.size(); ++i) {
     if (fb[i].first == r) {
@@ -49,7 +54,7 @@ void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s) {
   if (hipMalloc(&p, r) != hipSuccess) {
     (void)hipGetLastError();
     // give cached blocks back and retry once
-    ctx_release_pool(c);
+    release_free_blocks(c);
     if (hipMalloc(&p, r) != hipSuccess) {
       (void)hipGetLastError();
       throw Error{AHF_ENOMEM, "hipMalloc of " + std::to_string(r) + " bytes failed"};
@@ -66,10 +71,12 @@ void ctx_free(Ctx* c, void* p, size_t bytes, hipStream_t s) {
     c->free(c->user, p, bytes, (void*)s);
     return;
   }
+  std::lock_guard<std::mutex> lk(c->pool.mu);
   c->pool.free_blocks.emplace_back(round_size(bytes), p);
 }
 
-void ctx_release_pool(Ctx* c) {
+// caller holds the pool lock
+static void release_free_blocks(Ctx* c) {
   auto& fb = c->pool.free_blocks;
   for (auto& b : fb) {
     (void)hipFree(b.second);
@@ -81,6 +88,17 @@ void ctx_release_pool(Ctx* c) {
       }
   }
   fb.clear();
+}
+
+void ctx_release_pool(Ctx* c) {
+  std::lock_guard<std::mutex> lk(c->pool.mu);
+  release_free_blocks(c);
+}
+
+size_t hier_bytes(const Hier* h) {
+  size_t s = 0;
+  for (auto& a : h->mem.list) s += a.second;
+  return s;
 }
 
 void* Ws::raw(size_t bytes) {
@@ -192,15 +210,6 @@ void Prof::clear() {
 }
 
 }  // namespace ahf
-
-struct ahf_ctx {
-  ahf::Ctx c;
-  ahf::Ws ws;
-};
-
-struct ahf_hierarchy {
-  ahf::Hier h;
-};
 
 using namespace ahf;
 
@@ -380,6 +389,30 @@ ahf_status ahf_hierarchy_order(const ahf_hierarchy* h, const uint32_t** sorted_i
 ahf_status ahf_hierarchy_timings(const ahf_hierarchy* h, double* ms, uint32_t n) {
   if (!h || !ms || n > 4) return fail(AHF_EINVAL, "bad arguments");
   for (uint32_t i = 0; i < n; ++i) ms[i] = h->h.ms[i];
+  return AHF_OK;
+}
+
+ahf_status ahf_hierarchy_query_label(ahf_ctx* ctx, const ahf_hierarchy* h, uint32_t level,
+                                     uint64_t n, const uint64_t* keys, int32_t* out, void* stream) {
+  if (!ctx || !h || (n && (!keys || !out))) return fail(AHF_EINVAL, "bad arguments");
+  if (level >= h->h.lev.size()) return fail(AHF_EINVAL, "level out of range");
+  if (level >= 1 && !h->h.labelled) return fail(AHF_EINVAL, "the hierarchy is not labelled");
+  const uint32_t b = h->h.lev[level].b;
+  for (uint64_t i = 0; i < n; ++i)
+    if (3 * b < 64 && (keys[i] >> (3 * b)) != 0) return fail(AHF_EINVAL, "key beyond the level's bits");
+  if (n == 0) return AHF_OK;
+  if (level == 0) {
+    for (uint64_t i = 0; i < n; ++i) out[i] = -1;
+    return AHF_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    HIP_CHECK(hipSetDevice(ctx->c.device));
+    ctx->ws.bind(&ctx->c, st);
+    query_labels(ctx->ws, &h->h, (int)level, n, keys, out, st);
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
   return AHF_OK;
 }
 

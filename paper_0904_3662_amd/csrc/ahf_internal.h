@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -27,6 +28,7 @@ struct Error {
 
 // device memory through the context's callbacks or its own caching pool
 struct Pool {
+  std::mutex mu;  // hierarchies may be freed from another thread (server)
   std::vector<std::pair<size_t, void*>> free_blocks;  // (size, ptr)
   std::vector<std::pair<size_t, void*>> all;          // everything hipMalloc'd
 };
@@ -200,5 +202,19 @@ struct Hier {
 void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm, hipStream_t st,
                      Hier* h);
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
+// patch ids of level-L cells given by key (host arrays); level >= 1, labelled
+void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys_host,
+                  int32_t* out_host, hipStream_t st);
+size_t hier_bytes(const Hier* h);
+void set_last_error(const std::string& msg);  // message returned by ahf_last_error
 
 }  // namespace ahf
+
+struct ahf_ctx {
+  ahf::Ctx c;
+  ahf::Ws ws;
+};
+
+struct ahf_hierarchy {
+  ahf::Hier h;
+};

@@ -813,6 +813,23 @@ __global__ void k_patch_mass(uint64_t np, const unsigned long long* __restrict__
   GRID_STRIDE(p, np) pm[p] = mfix ? (double)mfix[p] * inv_scale : (double)npart[p] * mscalar;
 }
 
+// ------------------------------------------------------------ label queries
+
+// patch id of each queried level-L cell (-1 if the cell is not in S_L)
+__global__ void k_query_label(Tree tree, int L, const uint64_t* __restrict__ keys, uint64_t n,
+                              const int32_t* __restrict__ Bcell,
+                              const int32_t* __restrict__ Spatch, int32_t* __restrict__ out) {
+  GRID_STRIDE(i, n) {
+    const int64_t slot = tree_lookup(tree, L, keys[i]);
+    int32_t r = -1;
+    if (slot >= 0) {
+      const int32_t bc = Bcell[slot >> 3];
+      if (bc >= 0) r = Spatch[bc + (int32_t)(slot & 7)];
+    }
+    out[i] = r;
+  }
+}
+
 // ------------------------------------------------------------ host orchestration
 
 static double now_ms() {
@@ -1072,6 +1089,20 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   if (herr & kErrCoord) throw Error{AHF_EINVAL, "a particle coordinate is >= 2^21"};
   if (herr & kErrSpin) throw Error{AHF_EDEVICE, "a look-back wait gave up (sort or scan)"};
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed on the device"};
+}
+
+void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys_host,
+                  int32_t* out_host, hipStream_t st) {
+  const Level& lv = h->lev[L];
+  Ws::Mark m = ws.mark();
+  uint64_t* dk = ws.get<uint64_t>(n);
+  int32_t* dout = ws.get<int32_t>(n);
+  HIP_CHECK(hipMemcpyAsync(dk, keys_host, n * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  k_query_label<<<grid_for(n), kT, 0, st>>>(make_tree(h), L, dk, n, lv.Bcell, lv.Spatch, dout);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemcpyAsync(out_host, dout, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  ws.release(m);
 }
 
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
