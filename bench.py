@@ -48,6 +48,164 @@ def cpu_baseline(snap, seconds_target=20.0):
                       f"same grid parameters, single-threaded FP64 oracle, {dt:.1f} s"}
 
 
+def _pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def run_batched(args):
+    """64 independent periodic sub-volumes with particle counts log-uniform in
+    1e4..1e7 (seed 3; halo fraction 10..40%, domain grid ~N^{1/3}/2 clamped to
+    32^3..128^3, threshold 5, 10 levels): the sequential one-stream path against
+    the server with several streams building them concurrently."""
+    import torch
+    from paper_0904_3662_amd import ahf, synth
+    sizes = synth.subvolume_sizes(3, 64, 4.0, 7.0)
+    t0 = time.perf_counter()
+    subs = [synth.subvolume(1000 + i, int(n)) for i, n in enumerate(sizes)]
+    print(f"# generated 64 sub-volumes, {int(sizes.sum())} particles in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    devs = [ahf.snapshot_to_device(s) for s in subs]
+    torch.cuda.synchronize()
+    ctx = ahf.Context(0)
+    total = int(sizes.sum())
+    order = np.argsort(-sizes, kind="stable")  # largest first
+    out = {"metric": "particles/s through full hierarchy build, batched sub-volumes",
+           "unit": "particles/s", "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "64 sub-volumes, N log-uniform 1e4..1e7", "particles": total,
+                      "sub_volumes": 64}}
+    # sequential: one stream, one build at a time
+    for rep in range(args.warmup + 1):
+        lat = []
+        a = time.perf_counter()
+        for i in order:
+            b = time.perf_counter()
+            h, _ = ahf.build_snapshot(ctx, subs[i], dev=devs[i])
+            h.free()
+            lat.append((time.perf_counter() - b) * 1e3)
+        seq = time.perf_counter() - a
+    out["sequential"] = {"value": total / seq, "seconds": seq, "p50_ms": _pct(lat, 50),
+                         "p99_ms": _pct(lat, 99)}
+    print(f"# sequential {seq:.3f} s", file=sys.stderr, flush=True)
+    for k in (2, 4, 8):
+        with ahf.Server(ctx, n_streams=k) as srv:
+            for rep in range(args.warmup + 1):
+                a = time.perf_counter()
+                tickets = [srv.submit_snapshot(subs[i], dev=devs[i]) for i in order]
+                for t in tickets:
+                    srv.wait(t)
+                el = time.perf_counter() - a
+                lat = []
+                for t in tickets:
+                    tt = srv.times(t)
+                    lat.append(tt[3] - tt[0])
+                    srv.release(t)
+        out[f"streams_{k}"] = {"value": total / el, "seconds": el, "p50_ms": _pct(lat, 50),
+                               "p99_ms": _pct(lat, 99)}
+        print(f"# {k} streams {el:.3f} s", file=sys.stderr, flush=True)
+    best = max((out[f"streams_{k}"]["value"], k) for k in (2, 4, 8))
+    out["value"] = best[0]
+    out["n_streams"] = best[1]
+    out["speedup_vs_sequential"] = best[0] / out["sequential"]["value"]
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_served(args):
+    """Poisson stream of sub-volume builds, sizes log-uniform in 1e5..5e7 (seed 4),
+    admitted by the server against the HBM budget, results kept resident for
+    follow-up label queries; each arrival rate is run with several streams and
+    with one stream (the sequential per-request path)."""
+    import torch
+    from paper_0904_3662_amd import ahf, synth
+    npool = args.pool
+    sizes = synth.subvolume_sizes(4, npool, 5.0, float(np.log10(5e7)))
+    t0 = time.perf_counter()
+    subs = [synth.subvolume(4000 + i, int(n)) for i, n in enumerate(sizes)]
+    print(f"# generated a pool of {npool} sub-volumes, {int(sizes.sum())} particles in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    devs = [ahf.snapshot_to_device(s) for s in subs]
+    torch.cuda.synchronize()
+    ctx = ahf.Context(0)
+    rng = np.random.Generator(np.random.PCG64(44))
+    R = args.requests
+    pick = rng.integers(0, npool, R)
+    # sequential capacity: mean build time over the request mix
+    for i in range(npool):
+        h, _ = ahf.build_snapshot(ctx, subs[i], dev=devs[i])
+        h.free()
+    tb = []
+    for i in range(npool):
+        a = time.perf_counter()
+        h, _ = ahf.build_snapshot(ctx, subs[i], dev=devs[i])
+        h.free()
+        tb.append(time.perf_counter() - a)
+    mean_t = float(np.mean(np.asarray(tb)[pick]))
+    capacity = 1.0 / mean_t
+    out = {"metric": "particles/s through full hierarchy build, served request stream",
+           "unit": "particles/s", "n_gpus": 1, "data": "synthetic", "dtype": "f32",
+           "config": {"workload": f"Poisson stream, {R} requests from a pool of {npool} "
+                                  "sub-volumes, N log-uniform 1e5..5e7",
+                      "requests": R, "sequential_capacity_req_per_s": capacity},
+           "rates": {}}
+    for frac in (0.5, 0.8, 1.2):
+        lam = frac * capacity
+        gaps = rng.exponential(1.0 / lam, R)
+        arrive = np.cumsum(gaps)
+        res = {}
+        for k in (1, args.streams):
+            with ahf.Server(ctx, n_streams=k) as srv:
+                live = []
+                lat = []
+                queries = 0
+                a = time.perf_counter()
+                i = 0
+                while i < R or live:
+                    now = time.perf_counter() - a
+                    if i < R and now >= arrive[i]:
+                        live.append(srv.submit_snapshot(subs[pick[i]], dev=devs[pick[i]]))
+                        i += 1
+                        continue
+                    still = []
+                    for t in live:
+                        h = srv.poll(t)
+                        if h is None:
+                            still.append(t)
+                            continue
+                        if h.num_levels() > 1:
+                            v = h.view(1)
+                            keys = np.arange(min(64, v.n_cells), dtype=np.uint64)
+                            srv.query_label(t, 1, keys)
+                            queries += 1
+                        tt = srv.times(t)
+                        lat.append(tt[3] - tt[0])
+                        srv.release(t)
+                    live = still
+                    if i < R:
+                        wait = arrive[i] - (time.perf_counter() - a)
+                        if wait > 0:
+                            time.sleep(min(wait, 0.0005))
+                    else:
+                        time.sleep(0.0002)
+                el = time.perf_counter() - a
+                parts = int(sizes[pick].sum())
+                res[f"streams_{k}"] = {"value": parts / el, "seconds": el,
+                                       "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+                                       "label_queries": queries,
+                                       "bytes_peak": srv.stats()["bytes_peak"]}
+            print(f"# rate {frac} x capacity, {k} streams: {el:.2f} s, p99 "
+                  f"{res[f'streams_{k}']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        out["rates"][f"{frac}"] = {"req_per_s": lam, **res}
+    r = out["rates"]["0.8"]
+    out["value"] = r[f"streams_{args.streams}"]["value"]
+    out["p50_ms"] = r[f"streams_{args.streams}"]["p50_ms"]
+    out["p99_ms"] = r[f"streams_{args.streams}"]["p99_ms"]
+    out["n_streams"] = args.streams
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +213,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="16m", choices=["16m", "32k"])
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served"])
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--pool", type=int, default=8)
+    ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -62,6 +224,10 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batched":
+        return run_batched(args)
+    if args.mode == "served":
+        return run_served(args)
 
     import torch
     from paper_0904_3662_amd import ahf, synth
