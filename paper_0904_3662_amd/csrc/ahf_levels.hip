@@ -314,6 +314,36 @@ __global__ void k_set_hidx(const uint32_t* __restrict__ Hs, uint64_t nH, int32_t
 
 // ------------------------------------------------------------ deposit
 
+// Layout of the 4x4x4 patch of a parent: the cells are grouped by the brick
+// they belong to (the parent's own brick first, then its 26 neighbours in
+// offset order), so a brick reads each neighbour's share as one contiguous
+// run.  layout[q] is the stored position of patch cell q = 16 px + 4 py + pz;
+// inv is its inverse.
+struct PatchLayout {
+  uint8_t layout[64];
+  uint8_t inv[64];
+};
+
+constexpr int patch_dir(int p) { return p == 0 ? -1 : (p == 3 ? 1 : 0); }
+
+constexpr PatchLayout make_patch_layout() {
+  PatchLayout t{};
+  int n = 0;
+  for (int k = 0; k < 27; ++k) {
+    const int o = (k == 0) ? 13 : (k <= 13 ? k - 1 : k);
+    const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
+    for (int q = 0; q < 64; ++q)
+      if (patch_dir(q >> 4) == ox && patch_dir((q >> 2) & 3) == oy && patch_dir(q & 3) == oz) {
+        t.layout[q] = (uint8_t)n;
+        t.inv[n] = (uint8_t)q;
+        ++n;
+      }
+  }
+  return t;
+}
+
+__constant__ PatchLayout c_patch = make_patch_layout();
+
 // one thread per cell of S_L (8 per refined parent); 32 parents per block.
 // patch[f][px][py][pz] (4x4x4) holds what the particles of parent f give to
 // the level-L cells 2P-1 .. 2P+2 per axis.
@@ -325,8 +355,10 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
                                                  uint32_t mask, float scale,
                                                  float* __restrict__ patch,
                                                  double* __restrict__ Spmass) {
-  __shared__ float Ts[256][28];
+  __shared__ float Ts[256][27];  // odd stride: the 64 lanes hit distinct banks
+  __shared__ uint8_t inv[64];    // lane-dependent lookups: LDS, not the scalar cache
   const int t = threadIdx.x;
+  if (t < 64) inv[t] = c_patch.inv[t];
   const uint64_t f = (uint64_t)blockIdx.x * 32 + (t >> 3);
   const int d = t & 7;
   float T[27];
@@ -345,16 +377,17 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
       const uint32_t a = Sstart[s];
       for (uint32_t i = 0; i < n; ++i) add_particle(P, a + i, mask, scale, T, ms);
     }
-    Spmass[s] = ms;
+    if (Spmass) Spmass[s] = ms;
   }
 #pragma unroll
   for (int k = 0; k < 27; ++k) Ts[t][k] = T[k];
   __syncthreads();
   if (f >= nFp) return;
   const int base = t & ~7;
+  float out[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int q = d * 8 + j;
+    const int q = inv[d * 8 + j];
     const int px = q >> 4, py = (q >> 2) & 3, pz = q & 3;
     float sum = 0.0f;
 #pragma unroll
@@ -363,8 +396,11 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
       if (a >= 0 && a <= 2 && b >= 0 && b <= 2 && e >= 0 && e <= 2)
         sum += Ts[base + c][a * 9 + b * 3 + e];
     }
-    patch[f * 64 + q] = sum;
+    out[j] = sum;
   }
+  float4* dst = reinterpret_cast<float4*>(patch + f * 64 + d * 8);
+  dst[0] = make_float4(out[0], out[1], out[2], out[3]);
+  dst[1] = make_float4(out[4], out[5], out[6], out[7]);
 }
 
 // 8 lanes per brick (32 bricks per block): the lanes share the lookups of
@@ -377,6 +413,8 @@ __global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint6
                                                  const float* __restrict__ patch,
                                                  float* __restrict__ mass) {
   __shared__ int32_t fn[32][28];
+  __shared__ uint8_t lay[64];
+  if (threadIdx.x < 64) lay[threadIdx.x] = c_patch.layout[threadIdx.x];
   const int lb = threadIdx.x >> 3;
   const int d = threadIdx.x & 7;
   const uint64_t bi = (uint64_t)blockIdx.x * 32 + lb;
@@ -410,7 +448,7 @@ __global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint6
     const int py = sy ? (ey ? 0 : 3) : ey + 1;
     const int pz = sz ? (ez ? 0 : 3) : ez + 1;
     const int32_t f = fn[lb][(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
-    if (f >= 0) sum += patch[(uint64_t)f * 64 + px * 16 + py * 4 + pz];
+    if (f >= 0) sum += patch[(uint64_t)f * 64 + lay[px * 16 + py * 4 + pz]];
   }
   mass[bi * 8 + d] = sum;
 }
@@ -425,7 +463,8 @@ __global__ __launch_bounds__(256) void k_level_sums(const float* __restrict__ a,
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (uint64_t i = i0; i < na; i += stride) s[0] += (double)a[i];
-  for (uint64_t i = i0; i < nb; i += stride) s[1] += b[i];
+  if (b)
+    for (uint64_t i = i0; i < nb; i += stride) s[1] += b[i];
   for (uint64_t i = i0; i < nc; i += stride) s[2] += (double)c[i];
   const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -667,22 +706,59 @@ __global__ __launch_bounds__(256) void k_uf_local(int Lp, int bits, uint64_t nF,
     par[t0 + i] = (int32_t)(t0 + (uint64_t)lds_find(lp, (int32_t)i));
 }
 
-// the edges between tiles, on the global forest
-__global__ void k_uf_cross(int Lp, int bits, uint64_t nF, const uint32_t* __restrict__ Fs,
-                           const uint64_t* __restrict__ Skey, Tree tree,
-                           const int32_t* __restrict__ slot_f, const uint16_t* __restrict__ xmask,
-                           int32_t* __restrict__ par, uint32_t* __restrict__ err) {
-  GRID_STRIDE(f, nF) {
-    uint32_t xm = xmask[f];
-    if (!xm) continue;
-    const uint32_t s = Fs[f];
-    const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
-    while (xm) {
-      const int o = __ffs(xm) - 1;
-      xm &= xm - 1;
-      const int32_t g = refined_neighbour(Lp, bits, tree, slot_f, key, o, err);
-      if (g >= 0) uf_unite(par, (int32_t)f, g);
+// The edges between tiles, on the global forest.  Most edges that leave a
+// tile join the same two local roots (par[] holds each cell's tile-local
+// root), so each block first collects the distinct (root, root) pairs of its
+// cells in an LDS hash set and unites each pair once.
+constexpr int kPairSlots = 2048;
+
+__global__ __launch_bounds__(256) void k_uf_cross(int Lp, int bits, uint64_t nF,
+                                                  const uint32_t* __restrict__ Fs,
+                                                  const uint64_t* __restrict__ Skey, Tree tree,
+                                                  const int32_t* __restrict__ slot_f,
+                                                  const uint16_t* __restrict__ xmask,
+                                                  int32_t* __restrict__ par,
+                                                  uint32_t* __restrict__ err) {
+  __shared__ unsigned long long set[kPairSlots];
+  for (uint64_t base = (uint64_t)blockIdx.x * 256; base < nF; base += (uint64_t)gridDim.x * 256) {
+    for (int i = threadIdx.x; i < kPairSlots; i += 256) set[i] = ~0ull;
+    __syncthreads();
+    const uint64_t f = base + threadIdx.x;
+    if (f < nF) {
+      uint32_t xm = xmask[f];
+      if (xm) {
+        const uint32_t s = Fs[f];
+        const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
+        const int32_t ra = par[f];  // tile-local root (written by k_uf_local)
+        while (xm) {
+          const int o = __ffs(xm) - 1;
+          xm &= xm - 1;
+          const int32_t g = refined_neighbour(Lp, bits, tree, slot_f, key, o, err);
+          if (g < 0) continue;
+          const int32_t rb = par[g];
+          const int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+          if (lo == hi) continue;
+          const unsigned long long pk = ((unsigned long long)(uint32_t)lo << 32) | (uint32_t)hi;
+          uint32_t h = (uint32_t)((pk * 0x9E3779B97F4A7C15ull) >> 53) & (kPairSlots - 1);
+          bool mine = false, full = true;
+          for (int probe = 0; probe < kPairSlots; ++probe) {
+            const unsigned long long old = atomicCAS(&set[h], ~0ull, pk);
+            if (old == ~0ull) {
+              mine = true;
+              full = false;
+              break;
+            }
+            if (old == pk) {
+              full = false;
+              break;
+            }
+            h = (h + 1) & (kPairSlots - 1);
+          }
+          if (mine || full) uf_unite(par, lo, hi);
+        }
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -935,7 +1011,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     lv.Bcell = Bcell;
     lv.Pbrick = Pbrick;
     lv.Sflag = h->mem.get<uint8_t>(lv.nS);
-    lv.Spmass = h->mem.get<double>(lv.nS);
+    // particle mass per cell: only needed when masses differ (else count x m)
+    lv.Spmass = p.mass ? h->mem.get<double>(lv.nS) : nullptr;
 
     // refinement flags and the cells too full for one thread
     const int can_refine = (L < prm.Lmax && b < kQBits) ? 1 : 0;
@@ -1079,8 +1156,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   HIP_CHECK(hipStreamSynchronize(st));
   for (size_t L = 0; L < nl; ++L) {
     h->lev[L].tot_cell = tot[3 * L + 0];
-    h->lev[L].tot_part = tot[3 * L + 1];
     h->lev[L].nP = (uint64_t)tot[3 * L + 2];
+    h->lev[L].tot_part = p.mass ? tot[3 * L + 1] : (double)h->lev[L].nP * p.mass_scalar;
   }
   const double t2 = now_ms();
   h->ms[0] = t1 - t0;
@@ -1130,8 +1207,8 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
                     (int)L - 1, (int)pv.b, nE, pv.Fs, pv.Skey, tree, pv.slot_f, h->prm.conn, par,
                     xmask, dev)));
       AHF_TIMED(ctx, "uf_cross", st,
-                (k_uf_cross<<<grid_for(nE), kT, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs, pv.Skey,
-                                                         tree, pv.slot_f, xmask, par, dev)));
+                (k_uf_cross<<<grid_for(nE), 256, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs, pv.Skey,
+                                                          tree, pv.slot_f, xmask, par, dev)));
     }
     k_uf_compress<<<grid_for(nE), kT, 0, st>>>(par, nE, root, pred);
     HIP_LAUNCH_CHECK();
