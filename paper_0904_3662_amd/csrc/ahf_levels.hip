@@ -157,15 +157,22 @@ __global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
   }
 }
 
+// refinement flags; cells too full for one thread are appended to Hs (in no
+// particular order: the list only routes each such cell to its own sums)
 __global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double thr,
                         int can_refine, uint8_t* __restrict__ flag, uint32_t* __restrict__ predF,
-                        uint32_t* __restrict__ predH) {
+                        uint32_t* __restrict__ nheavy, uint32_t* __restrict__ Hs,
+                        int32_t* __restrict__ hidx) {
   GRID_STRIDE(s, nS) {
     const uint32_t c = count[s];
     const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
     flag[s] = (uint8_t)f;
     predF[s] = f;
-    predH[s] = c > (uint32_t)kHeavy ? 1u : 0u;
+    if (c > (uint32_t)kHeavy) {
+      const uint32_t h = atomicAdd(nheavy, 1u);
+      Hs[h] = (uint32_t)s;
+      hidx[s] = (int32_t)h;
+    }
   }
 }
 
@@ -193,10 +200,8 @@ struct Parts {
   const uint4* rec;  // 2 per particle, sorted order
 };
 
-__device__ inline void add_particle(const Parts& P, uint32_t p, uint32_t mask, float scale,
-                                    float T[27], double& msum) {
-  const uint4 r0 = P.rec[2 * (uint64_t)p];
-  const uint4 r1 = P.rec[2 * (uint64_t)p + 1];
+__device__ inline void add_record(const uint4& r0, const uint4& r1, uint32_t mask, float scale,
+                                  float T[27], double& msum) {
   float wx[3], wy[3], wz[3];
   tsc_axis(r0.x, __uint_as_float(r1.x), mask, scale, wx);
   tsc_axis(r0.y, __uint_as_float(r1.y), mask, scale, wy);
@@ -215,18 +220,42 @@ __device__ inline void add_particle(const Parts& P, uint32_t p, uint32_t mask, f
   }
 }
 
-// ------------------------------------------------------------ heavy cells
-
-__global__ void k_heavy_nchunks(const uint32_t* __restrict__ Hs, uint64_t nH,
-                                const uint32_t* __restrict__ Scount, uint32_t* __restrict__ nch) {
-  GRID_STRIDE(h, nH) nch[h] = (Scount[Hs[h]] + kChunk - 1) / kChunk;
+__device__ inline void add_particle(const Parts& P, uint32_t p, uint32_t mask, float scale,
+                                    float T[27], double& msum) {
+  add_record(P.rec[2 * (uint64_t)p], P.rec[2 * (uint64_t)p + 1], mask, scale, T, msum);
 }
 
-__global__ void k_chunk_list(const uint32_t* __restrict__ nch, const uint32_t* __restrict__ chofs,
-                             uint64_t nH, uint32_t* __restrict__ ch_h, uint32_t* __restrict__ ch_j) {
+// the particles [a, a+n) of one cell, four records loaded ahead of their use
+__device__ inline void add_range(const Parts& P, uint32_t a, uint32_t n, uint32_t mask, float scale,
+                                 float T[27], double& msum) {
+  uint32_t i = 0;
+  for (; i + 4 <= n; i += 4) {
+    uint4 r[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      r[2 * k] = P.rec[2 * (uint64_t)(a + i + k)];
+      r[2 * k + 1] = P.rec[2 * (uint64_t)(a + i + k) + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) add_record(r[2 * k], r[2 * k + 1], mask, scale, T, msum);
+  }
+  for (; i < n; ++i) add_particle(P, a + i, mask, scale, T, msum);
+}
+
+// ------------------------------------------------------------ heavy cells
+
+// every heavy cell takes a contiguous run of chunk slots; its chunks are
+// later summed in the order of their index j inside that run
+__global__ void k_chunk_list(const uint32_t* __restrict__ Hs, uint64_t nH,
+                             const uint32_t* __restrict__ Scount, uint32_t* __restrict__ nchunks,
+                             uint32_t* __restrict__ nch, uint32_t* __restrict__ chofs,
+                             uint32_t* __restrict__ ch_h, uint32_t* __restrict__ ch_j) {
   GRID_STRIDE(h, nH) {
-    const uint32_t o = chofs[h];
-    for (uint32_t j = 0; j < nch[h]; ++j) {
+    const uint32_t m = (Scount[Hs[h]] + kChunk - 1) / kChunk;
+    const uint32_t o = atomicAdd(nchunks, m);
+    nch[h] = m;
+    chofs[h] = o;
+    for (uint32_t j = 0; j < m; ++j) {
       ch_h[o + j] = (uint32_t)h;
       ch_j[o + j] = j;
     }
@@ -253,7 +282,18 @@ __global__ __launch_bounds__(256) void k_heavy_chunk(
 #pragma unroll
   for (int k = 0; k < 27; ++k) T[k] = 0.0f;
   double ms = 0.0;
-  for (uint32_t i = threadIdx.x; i < len; i += 256) add_particle(P, a + i, mask, scale, T, ms);
+  uint32_t i = threadIdx.x;
+  for (; i + 3 * 256 < len; i += 4 * 256) {
+    uint4 r[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      r[2 * k] = P.rec[2 * (uint64_t)(a + i + k * 256)];
+      r[2 * k + 1] = P.rec[2 * (uint64_t)(a + i + k * 256) + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) add_record(r[2 * k], r[2 * k + 1], mask, scale, T, ms);
+  }
+  for (; i < len; i += 256) add_particle(P, a + i, mask, scale, T, ms);
   const int w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 27; ++k) {
@@ -308,9 +348,6 @@ __global__ void k_heavy_reduce(const uint32_t* __restrict__ nch, const uint32_t*
   }
 }
 
-__global__ void k_set_hidx(const uint32_t* __restrict__ Hs, uint64_t nH, int32_t* __restrict__ hidx) {
-  GRID_STRIDE(h, nH) hidx[Hs[h]] = (int32_t)h;
-}
 
 // ------------------------------------------------------------ deposit
 
@@ -375,7 +412,7 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
       ms = hM[h];
     } else {
       const uint32_t a = Sstart[s];
-      for (uint32_t i = 0; i < n; ++i) add_particle(P, a + i, mask, scale, T, ms);
+      add_range(P, a, n, mask, scale, T, ms);
     }
     if (Spmass) Spmass[s] = ms;
   }
@@ -883,9 +920,11 @@ __global__ void k_patch_parent(const int32_t* __restrict__ root, const int32_t* 
   }
 }
 
-__global__ void k_patch_mass(uint64_t np, const unsigned long long* __restrict__ npart,
+__global__ void k_patch_mass(const uint32_t* __restrict__ npatch,
+                             const unsigned long long* __restrict__ npart,
                              const unsigned long long* __restrict__ mfix, double mscalar,
                              double inv_scale, double* __restrict__ pm) {
+  const uint64_t np = *npatch;
   GRID_STRIDE(p, np) pm[p] = mfix ? (double)mfix[p] * inv_scale : (double)npart[p] * mscalar;
 }
 
@@ -1018,13 +1057,15 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     const int can_refine = (L < prm.Lmax && b < kQBits) ? 1 : 0;
     const double thr = (L == 0) ? prm.dom_ref : prm.ref_ref;
     uint32_t* predF = ws.get<uint32_t>(lv.nS);
-    uint32_t* predH = ws.get<uint32_t>(lv.nS);
     uint32_t* ofsF = ws.get<uint32_t>(lv.nS);
-    uint32_t* ofsH = ws.get<uint32_t>(lv.nS);
-    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag, predF, predH);
+    const uint64_t maxH = std::min<uint64_t>(lv.nS, n / (kHeavy + 1) + 1);
+    uint32_t* Hs = ws.get<uint32_t>(maxH);
+    int32_t* hidx = ws.get<int32_t>(lv.nS);  // read only for cells above kHeavy
+    HIP_CHECK(hipMemsetAsync(dev_u32 + 2, 0, 2 * sizeof(uint32_t), st));
+    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag, predF,
+                                            dev_u32 + 2, Hs, hidx);
     HIP_LAUNCH_CHECK();
     scan_u32(ws, predF, ofsF, lv.nS, dev_u32 + 1, st);
-    scan_u32(ws, predH, ofsH, lv.nS, dev_u32 + 2, st);
     uint32_t cnts[2];
     HIP_CHECK(hipMemcpyAsync(cnts, dev_u32 + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
@@ -1040,22 +1081,16 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     const float scale = std::ldexp(1.0f, -(kQBits - b));
 
     // heavy cells: chunked block sums
-    int32_t* hidx = nullptr;
     float* hT = nullptr;
     double* hM = nullptr;
     if (nH > 0) {
-      uint32_t* Hs = ws.get<uint32_t>(nH);
-      k_compact<<<grid_for(lv.nS), kT, 0, st>>>(predH, ofsH, lv.nS, Hs);
-      HIP_LAUNCH_CHECK();
       uint32_t* nch = ws.get<uint32_t>(nH);
       uint32_t* chofs = ws.get<uint32_t>(nH);
-      k_heavy_nchunks<<<grid_for(nH), kT, 0, st>>>(Hs, nH, lv.Scount, nch);
-      HIP_LAUNCH_CHECK();
-      scan_u32(ws, nch, chofs, nH, dev_u32 + 3, st);
       const uint64_t maxch = nH + n / kChunk + 1;
       uint32_t* ch_h = ws.get<uint32_t>(maxch);
       uint32_t* ch_j = ws.get<uint32_t>(maxch);
-      k_chunk_list<<<grid_for(nH), kT, 0, st>>>(nch, chofs, nH, ch_h, ch_j);
+      k_chunk_list<<<grid_for(nH), kT, 0, st>>>(Hs, nH, lv.Scount, dev_u32 + 3, nch, chofs, ch_h,
+                                                ch_j);
       HIP_LAUNCH_CHECK();
       float* chT = ws.get<float>(maxch * 27);
       double* chM = ws.get<double>(maxch);
@@ -1066,11 +1101,6 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       hT = ws.get<float>(nH * 27);
       hM = ws.get<double>(nH);
       k_heavy_reduce<<<grid_for(nH * 28), kT, 0, st>>>(nch, chofs, nH, chT, chM, hT, hM);
-      HIP_LAUNCH_CHECK();
-      hidx = ws.get<int32_t>(lv.nS);
-      k_fill_i32<<<grid_for(lv.nS), kT, 0, st>>>(hidx, lv.nS, -1);
-      HIP_LAUNCH_CHECK();
-      k_set_hidx<<<grid_for(nH), kT, 0, st>>>(Hs, nH, hidx);
       HIP_LAUNCH_CHECK();
     }
 
@@ -1185,15 +1215,27 @@ void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
   if (h->labelled) return;
   const double t0 = now_ms();
-  uint32_t* dev = ws.get<uint32_t>(4);
-  HIP_CHECK(hipMemsetAsync(dev, 0, 4 * sizeof(uint32_t), st));
+  // dev[0]: error flags; dev[4 + L]: the number of patches on level L. The
+  // levels are labelled back to back on the stream; the counts are read once
+  // at the end, so the per-level patch arrays are sized by their bound nE.
+  const size_t nlev = h->lev.size();
+  uint32_t* dev = ws.get<uint32_t>(4 + nlev);
+  HIP_CHECK(hipMemsetAsync(dev, 0, (4 + nlev) * sizeof(uint32_t), st));
   ctx->dev_err = dev;
   const Tree tree = make_tree(h);
   const double total_mass = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
-  for (size_t L = 1; L < h->lev.size(); ++L) {
+  double fscale = 1.0;
+  if (h->has_mass) {
+    int e = 0;
+    std::frexp(total_mass > 0 ? total_mass : 1.0, &e);
+    fscale = std::ldexp(1.0, 61 - e);
+  }
+  for (size_t L = 1; L < nlev; ++L) {
     Level& pv = h->lev[L - 1];
     Level& lv = h->lev[L];
     const uint64_t nE = pv.nF;
+    const uint64_t nE1 = nE ? nE : 1;
+    uint32_t* npatch = dev + 4 + L;
     Ws::Mark m = ws.mark();
     int32_t* par = ws.get<int32_t>(nE);
     int32_t* root = ws.get<int32_t>(nE);
@@ -1212,49 +1254,43 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     }
     k_uf_compress<<<grid_for(nE), kT, 0, st>>>(par, nE, root, pred);
     HIP_LAUNCH_CHECK();
-    scan_u32(ws, pred, rank, nE, dev + 1, st);
-    uint32_t np = 0;
-    HIP_CHECK(hipMemcpyAsync(&np, dev + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    lv.nPatch = np;
+    scan_u32(ws, pred, rank, nE, npatch, st);
     k_uf_label<<<grid_for(nE), kT, 0, st>>>(root, rank, nE, lab);
     HIP_LAUNCH_CHECK();
     lv.Spatch = h->mem.get<int32_t>(lv.nS);
     k_cell_patch<<<grid_for(lv.nS), kT, 0, st>>>(lab, lv.nS, lv.Spatch);
     HIP_LAUNCH_CHECK();
-    lv.patch_parent = h->mem.get<int32_t>(np);
-    lv.patch_ncells = h->mem.get<uint32_t>(np);
-    lv.patch_npart = h->mem.get<uint64_t>(np);
-    lv.patch_mass = h->mem.get<double>(np);
-    HIP_CHECK(hipMemsetAsync(lv.patch_ncells, 0, (np ? np : 1) * sizeof(uint32_t), st));
-    HIP_CHECK(hipMemsetAsync(lv.patch_npart, 0, (np ? np : 1) * sizeof(uint64_t), st));
+    lv.patch_parent = h->mem.get<int32_t>(nE1);
+    lv.patch_ncells = h->mem.get<uint32_t>(nE1);
+    lv.patch_npart = h->mem.get<uint64_t>(nE1);
+    lv.patch_mass = h->mem.get<double>(nE1);
+    HIP_CHECK(hipMemsetAsync(lv.patch_ncells, 0, nE1 * sizeof(uint32_t), st));
+    HIP_CHECK(hipMemsetAsync(lv.patch_npart, 0, nE1 * sizeof(uint64_t), st));
     unsigned long long* mfix = nullptr;
-    double fscale = 1.0;
     if (h->has_mass) {
-      mfix = ws.get<unsigned long long>(np);
-      HIP_CHECK(hipMemsetAsync(mfix, 0, (np ? np : 1) * sizeof(unsigned long long), st));
-      int e = 0;
-      std::frexp(total_mass > 0 ? total_mass : 1.0, &e);
-      fscale = std::ldexp(1.0, 61 - e);
+      mfix = ws.get<unsigned long long>(nE1);
+      HIP_CHECK(hipMemsetAsync(mfix, 0, nE1 * sizeof(unsigned long long), st));
     }
-    k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (nE + 4095) / 4096 + 1), 256, 0, st>>>(lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale,
-                                               lv.patch_ncells,
-                                               (unsigned long long*)lv.patch_npart, mfix);
+    k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (nE + 4095) / 4096 + 1), 256, 0, st>>>(
+        lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale, lv.patch_ncells,
+        (unsigned long long*)lv.patch_npart, mfix);
     HIP_LAUNCH_CHECK();
     k_patch_parent<<<grid_for(nE), kT, 0, st>>>(root, lab, nE, pv.Fs, (L >= 2) ? pv.Spatch : nullptr,
                                                 lv.patch_parent);
     HIP_LAUNCH_CHECK();
-    k_patch_mass<<<grid_for(np), kT, 0, st>>>(np, (const unsigned long long*)lv.patch_npart, mfix,
-                                              h->mass_scalar, 1.0 / fscale, lv.patch_mass);
+    k_patch_mass<<<grid_for(nE), kT, 0, st>>>(npatch, (const unsigned long long*)lv.patch_npart,
+                                              mfix, h->mass_scalar, 1.0 / fscale, lv.patch_mass);
     HIP_LAUNCH_CHECK();
-    HIP_CHECK(hipStreamSynchronize(st));
+    // stream order keeps the released workspace from being reused early
     ws.release(m);
   }
-  uint32_t herr = 0;
-  HIP_CHECK(hipMemcpyAsync(&herr, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  std::vector<uint32_t> hv(4 + nlev);
+  HIP_CHECK(hipMemcpyAsync(hv.data(), dev, (4 + nlev) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  const uint32_t herr = hv[0];
   if (herr & kErrSpin) throw Error{AHF_EDEVICE, "scan look-back gave up waiting"};
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed while labelling"};
+  for (size_t L = 1; L < nlev; ++L) h->lev[L].nPatch = hv[4 + L];
   h->labelled = true;
   h->ms[2] = now_ms() - t0;
   h->ms[3] += h->ms[2];
