@@ -23,6 +23,36 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particles/s through full hierarchy build (1 GPU, % HBM peak); p50/p99 latency"
 
 
+def sort_plan(n, key_bits):
+    """Index width ib and number q of (key, index) passes of the radix sort:
+    q is the first pass count after which the unsorted key bits fit beside
+    the index in one 64-bit word."""
+    ib = 1
+    while ib < 32 and (1 << ib) < n:
+        ib += 1
+    q = 0
+    while key_bits - 8 * q > 64 - ib:
+        q += 1
+    return ib, q, (key_bits + 7) // 8
+
+
+def sort_scatter_bytes(n, key_bits):
+    """Bytes the scatter kernels of one sort read and write: a (key, index)
+    pass reads the 8-byte key (and the 4-byte index after the first pass) and
+    writes both, the pass that packs writes one 8-byte word, and every later
+    pass reads and writes one word."""
+    ib, q, npass = sort_plan(n, key_bits)
+    tot = 0
+    for p in range(npass):
+        if p < q:
+            rd = 8 + (4 if p > 0 else 0)
+            wr = 8 if p == q - 1 else 12
+        else:
+            rd, wr = 8, 8
+        tot += (rd + wr) * n
+    return tot
+
+
 def algorithmic_bytes(n, levels, sp=24):
     """Bytes the method itself must move per build (inputs read once, one
     read+write of the key/index pairs, the sorted payload written once, and
@@ -274,7 +304,7 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
     kstats = {}
-    for name in ("rs_scatter", "keys", "gather", "level0_start", "child_ranges",
+    for name in ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "level0_start", "child_ranges",
                  "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross"):
         kstats[name] = ctx.kernel_time(name)
     ctx.set_profiling(False)
@@ -285,7 +315,7 @@ def main():
     value = n * args.steps / total
     launches, tms = kstats["rs_scatter"]
     avg_ms = tms / max(launches, 1)
-    alg_bytes_launch = 24.0 * n          # one read + one write of (uint64 key, uint32 index)
+    alg_bytes_launch = sort_scatter_bytes(n, 3 * (snap.g + snap.max_levels)) / max(launches // args.steps, 1)
     achieved = alg_bytes_launch / (avg_ms * 1e-3) / 1e9 if launches else None
     b_alg = algorithmic_bytes(n, lv_info)
     rec = {

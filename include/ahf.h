@@ -175,8 +175,10 @@ void ahf_hierarchy_free(ahf_hierarchy *h);
 /*
  * Kernel timing for profiling.  While enabled, the context records a pair of
  * HIP events on the build stream around every launch of its main kernels
- * ("keys", "rs_scatter", "gather", "level0_start", "child_ranges",
- * "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross").  Enabling or
+ * ("keys", "rs_up", "rs_tscan", "rs_scatter", "gather", "level0_start",
+ * "child_ranges", "heavy_chunk", "patches", "combine", "mark", "uf_hook",
+ * "uf_cross"; the three "rs_" names are the tile histogram, tile offset and
+ * scatter kernels of each radix-sort pass).  Enabling or
  * disabling clears the accumulated times.  ahf_ctx_kernel_time returns the
  * number of launches and their summed device time (ms) for one name, reading
  * the events of finished builds.

@@ -57,13 +57,10 @@ struct Ctx {
   void* user = nullptr;
   Pool pool;
   Prof prof;
-  // decoupled look-back status words of the radix sort (kept between builds;
-  // every pass tags its words with a fresh epoch, so they never need clearing)
-  unsigned long long* rs_status = nullptr;
-  size_t rs_status_n = 0;
-  uint32_t rs_epoch = 0;
-  // the same for the one-pass scans; tile counters come from a ring of words
-  // that is cleared once every kLbCtrs scans
+  // decoupled look-back status words of the one-pass scans (kept between
+  // builds; every scan tags its words with a fresh epoch, so they never need
+  // clearing); tile counters come from a ring of words that is cleared once
+  // every kLbCtrs scans
   unsigned long long* lb_status = nullptr;
   size_t lb_status_n = 0;
   uint32_t lb_epoch = 0;
@@ -145,12 +142,19 @@ struct Owned {
 // ---------------------------------------------------------------- primitives
 void scan_u32(Ws& ws, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
               hipStream_t st);
-// Stable LSD sort of (key, value) pairs by the low `bits` key bits in 8-bit
-// digits.  ghist[p * 256 + d] must hold the count of digit d of pass p over all
-// keys (see wave_digit_hist).  On return keys/vals hold the result.
-void sort_pairs(Ctx* ctx, Ws& ws, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp,
-                uint32_t*& vtmp, uint64_t n, int bits, const uint32_t* ghist, uint32_t* err,
-                hipStream_t st);
+// Stable LSD sort of particles by Morton key (key_bits bits), ties by index,
+// in 8-bit digits.  The first q passes move (key, index) pairs; from pass q on
+// one packed word per element, ((key >> 8q) << ib) | index, with ib the index
+// width.  sort_keys takes keys[i] = key of particle i (or, when q == 0, the
+// packed word of particle i already) and ghist[p * 256 + d] = the number of
+// keys whose digit p is d; it returns the sorted packed words (keys or a
+// workspace buffer).
+struct SortPlan {
+  int key_bits = 0, npass = 0, ib = 1, q = 0;
+};
+SortPlan sort_plan(uint64_t n, int key_bits);
+uint64_t* sort_keys(Ctx* ctx, Ws& ws, uint64_t* keys, uint64_t n, const SortPlan& sp,
+                    const uint32_t* ghist, hipStream_t st);
 constexpr int kRsMaxPass = 8;
 template <typename T>
 void sum_to_f64(Ws& ws, const T* a, uint64_t n, double* out, hipStream_t st);

@@ -65,9 +65,9 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
                                               const float* __restrict__ fy,
                                               const float* __restrict__ fz,
                                               const float* __restrict__ m, float mscalar,
-                                              uint64_t n, int B, int npass,
+                                              uint64_t n, int B, int npass, int word_ib,
                                               uint64_t* __restrict__ keys,
-                                              uint32_t* __restrict__ vals, uint4* __restrict__ rec,
+                                              uint4* __restrict__ rec,
                                               uint32_t* __restrict__ ghist,
                                               uint32_t* __restrict__ err) {
   __shared__ uint32_t h[kRsMaxPass * 256];
@@ -83,8 +83,8 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
       if ((x | y | z) >= (1u << kQBits)) atomicOr(err, kErrCoord);
       const uint32_t xm = x & 0x1fffffu, ym = y & 0x1fffffu, zm = z & 0x1fffffu;
       key = morton3(xm >> s, ym >> s, zm >> s);
-      keys[i] = key;
-      vals[i] = (uint32_t)i;
+      // word_ib >= 0: the sort starts on packed words (key << ib) | index
+      keys[i] = (word_ib >= 0) ? ((key << word_ib) | i) : key;
       const float w = m ? m[i] : mscalar;
       rec[2 * i] = make_uint4(xm, ym, zm, __float_as_uint(w));
       rec[2 * i + 1] = make_uint4(fx ? __float_as_uint(fx[i]) : 0u, fy ? __float_as_uint(fy[i]) : 0u,
@@ -98,14 +98,19 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
 }
 
 // records in sorted order: one random 32-byte read per particle
-__global__ void k_gather_rec(const uint32_t* __restrict__ order, uint64_t n,
-                             const uint4* __restrict__ rec, uint4* __restrict__ srec) {
+// sorted position i: particle index from the packed word, its record, and its
+// full key rebuilt from the coordinates (written over the word, in place)
+__global__ void k_gather_rec(uint64_t* __restrict__ words, int ib, int s, uint64_t n,
+                             const uint4* __restrict__ rec, uint4* __restrict__ srec,
+                             uint32_t* __restrict__ order) {
   GRID_STRIDE(i, n) {
-    const uint32_t j = order[i];
+    const uint32_t j = (uint32_t)(words[i] & ((1ull << ib) - 1ull));
     const uint4 a = rec[2 * (uint64_t)j];
     const uint4 b = rec[2 * (uint64_t)j + 1];
+    order[i] = j;
     srec[2 * i] = a;
     srec[2 * i + 1] = b;
+    words[i] = morton3(a.x >> s, a.y >> s, a.z >> s);
   }
 }
 
@@ -982,31 +987,27 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
 
   // ---- keys and their stable sort
   uint64_t* keys = ws.get<uint64_t>(n);
-  uint32_t* vals = ws.get<uint32_t>(n);
-  uint64_t* ktmp = ws.get<uint64_t>(n);
-  uint32_t* vtmp = ws.get<uint32_t>(n);
   uint4* rec = ws.get<uint4>(2 * n);
+  const SortPlan sp = sort_plan(n, 3 * B);
+  h->order = h->mem.get<uint32_t>(n);
+  uint4* srec = ws.get<uint4>(2 * n);
+  uint64_t* skey = keys;
   if (n > 0) {
-    const int npass = (3 * B + 7) / 8;
     uint32_t* ghist = ws.get<uint32_t>(kRsMaxPass * 256);
     HIP_CHECK(hipMemsetAsync(ghist, 0, kRsMaxPass * 256 * sizeof(uint32_t), st));
     unsigned kb = grid_for(n);
     if (kb > 2048) kb = 2048;
     AHF_TIMED(ctx, "keys", st,
               (k_keys<<<kb, 256, 0, st>>>(p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass,
-                                          (float)p.mass_scalar, n, B, npass, keys, vals, rec,
-                                          ghist, err)));
-    sort_pairs(ctx, ws, keys, vals, ktmp, vtmp, n, 3 * B, ghist, err, st);
+                                          (float)p.mass_scalar, n, B, sp.npass,
+                                          sp.q == 0 ? sp.ib : -1, keys, rec, ghist, err)));
+    skey = sort_keys(ctx, ws, keys, n, sp, ghist, st);
+    AHF_TIMED(ctx, "gather", st,
+              (k_gather_rec<<<grid_for(n), kT, 0, st>>>(skey, sp.ib, kQBits - B, n, rec, srec,
+                                                        h->order)));
   }
-  h->order = h->mem.get<uint32_t>(n);
-  if (n > 0) HIP_CHECK(hipMemcpyAsync(h->order, vals, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-  const uint64_t* skey = keys;
 
   Parts P;
-  uint4* srec = ws.get<uint4>(2 * n);
-  if (n > 0)
-    AHF_TIMED(ctx, "gather", st,
-              (k_gather_rec<<<grid_for(n), kT, 0, st>>>(h->order, n, rec, srec)));
   P.rec = srec;
   HIP_CHECK(hipStreamSynchronize(st));
   const double t1 = now_ms();

@@ -200,21 +200,39 @@ void scan_u32(Ws& ws, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* t
 
 // ------------------------------------------------------------------ radix sort
 //
-// LSD, 8-bit digits, one kernel per digit.  The digit histograms of all
-// passes come from the kernel that makes the keys.  A tile of 4096 pairs is
-// split over 4 waves of 1024 consecutive pairs; each wave ranks its pairs 64
-// at a time with ballot-based digit matching, so a pair's rank counts only
-// pairs before it in input order and the sort is stable.  Tiles take their
-// index in the order they start, publish their digit counts, and add up the
-// counts of earlier tiles by decoupled look-back: a tile only waits for tiles
-// that started before it, so every wait ends; the wait is bounded anyway and
-// raises an error flag instead of hanging.
+// Stable LSD sort of Morton keys with the particle index as tie-break, 8-bit
+// digits.  Every pass is reduce-then-scan, with no waits between tiles:
+//   k_rs_up    per tile of 4096 elements, the histogram of the pass digit;
+//   k_rs_tscan per digit, the exclusive prefix over tiles plus the digit's
+//              global offset (global digit histograms come from the kernel
+//              that makes the keys);
+//   k_rs_down  ranks the tile (4 waves of 1024 consecutive elements, 64 at a
+//              time with ballot-based digit matching, so a rank counts only
+//              elements before it: stable), stages it in LDS by digit and
+//              writes each digit run to its place.
+// The first passes move (key, index) pairs.  Once the key bits still to be
+// sorted fit beside the index in 64 bits, a pass writes one packed word
+// ((key >> 8q) << ib) | index and the remaining passes move 8 bytes per
+// element instead of 12.  The sorted keys themselves are rebuilt from the
+// particle coordinates by the consumer.
 
 constexpr int kRsT = 256;
 constexpr int kRsW = kRsT / 64;
 constexpr int kRsR = 16;                 // rounds of 64 per wave
 constexpr int kRsTile = kRsT * kRsR;     // 4096
-constexpr uint32_t kRsSpinMax = 1u << 22;
+
+SortPlan sort_plan(uint64_t n, int key_bits) {
+  SortPlan sp;
+  int ib = 1;
+  while (ib < 32 && (1ull << ib) < n) ++ib;
+  sp.ib = ib;
+  sp.key_bits = key_bits;
+  sp.npass = (key_bits + 7) / 8;
+  int q = 0;
+  while (key_bits - 8 * q > 64 - ib) ++q;
+  sp.q = q;
+  return sp;
+}
 
 __global__ void k_rs_offsets(const uint32_t* __restrict__ ghist, int npass,
                              uint32_t* __restrict__ gofs) {
@@ -226,52 +244,101 @@ __global__ void k_rs_offsets(const uint32_t* __restrict__ ghist, int npass,
   }
 }
 
-__device__ inline unsigned long long rs_load(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void rs_store(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// digit histogram of every tile: th[d * ntiles + tile]
+__global__ __launch_bounds__(kRsT) void k_rs_up(const uint64_t* __restrict__ in, uint64_t n,
+                                               int shift, uint32_t ntiles,
+                                               uint32_t* __restrict__ th) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+  uint64_t key[kRsR];
+#pragma unroll
+  for (int r = 0; r < kRsR; ++r) {
+    const uint64_t j = tile0 + (uint64_t)r * kRsT + threadIdx.x;
+    key[r] = (j < n) ? __builtin_nontemporal_load(in + j) : 0ull;
+  }
+#pragma unroll
+  for (int r = 0; r < kRsR; ++r) {
+    const uint64_t j = tile0 + (uint64_t)r * kRsT + threadIdx.x;
+    if (j < n) atomicAdd(&h[(uint32_t)(key[r] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  th[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// status word: [63:40] epoch, [39:32] 1 = tile count, 2 = inclusive prefix, [31:0] value
-__global__ __launch_bounds__(kRsT) void k_rs_onesweep(
+constexpr int kTsT = 1024;
+
+// one block per digit: tofs[d * ntiles + t] = gofs[d] + sum of th[d * ntiles + t'] over t' < t
+__global__ __launch_bounds__(kTsT) void k_rs_tscan(const uint32_t* __restrict__ th,
+                                                   uint32_t ntiles,
+                                                   const uint32_t* __restrict__ gofs,
+                                                   uint32_t* __restrict__ tofs) {
+  __shared__ uint32_t lds[kTsT / 64 + 1];
+  const uint32_t d = blockIdx.x;
+  const uint32_t* row = th + (uint64_t)d * ntiles;
+  uint32_t* orow = tofs + (uint64_t)d * ntiles;
+  uint32_t carry = gofs[d];
+  for (uint32_t c0 = 0; c0 < ntiles; c0 += kTsT * 4) {
+    uint32_t v[4];
+    const uint32_t a = c0 + threadIdx.x * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (a + k < ntiles) ? row[a + k] : 0u;
+    const uint32_t s = (v[0] + v[1]) + (v[2] + v[3]);
+    uint32_t tot;
+    uint32_t e = block_excl_scan<kTsT>(s, tot, lds) + carry;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (a + k < ntiles) orow[a + k] = e;
+      e += v[k];
+    }
+    carry += tot;
+  }
+}
+
+enum RsIn { kInKeyIota = 0, kInKeyVal = 1, kInWord = 2 };
+enum RsOut { kOutKeyVal = 0, kOutWord = 1 };
+
+// One pass over one tile.  IN: (key, index) with the index implied by the
+// position (first pass), (key, index) pairs, or packed words.  OUT: pairs, or
+// packed words ((key >> pk_shift) << ib) | index.
+template <int IN, int OUT>
+__global__ __launch_bounds__(kRsT) void k_rs_down(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
-    const uint32_t* __restrict__ gofs, unsigned long long* __restrict__ status,
-    uint32_t* __restrict__ tile_ctr, unsigned long long epoch, uint32_t* __restrict__ err) {
+    int pk_shift, int ib, uint32_t ntiles, const uint32_t* __restrict__ tofs) {
+  constexpr bool kPack = OUT == kOutWord && IN != kInWord;
   __shared__ uint64_t sk[kRsTile];
-  __shared__ uint32_t sv[kRsTile];
+  __shared__ uint8_t sdig[kPack ? kRsTile : 1];  // a packed word no longer holds this digit
   __shared__ uint32_t cnt[kRsW][256];
   __shared__ uint32_t doff[256];
   __shared__ uint32_t gbase[256];
   __shared__ uint32_t lds[kRsT / 64 + 1];
-  __shared__ uint32_t tile_sh;
   const int w = threadIdx.x >> 6;
   const uint32_t lane = __lane_id();
-  if (threadIdx.x == 0) tile_sh = atomicAdd(tile_ctr, 1u);
+  const uint32_t tile = blockIdx.x;
+  const uint32_t base_off = tofs[(uint64_t)threadIdx.x * ntiles + tile];
   for (int i = threadIdx.x; i < kRsW * 256; i += kRsT) (&cnt[0][0])[i] = 0u;
   __syncthreads();
-  const uint32_t tile = tile_sh;
   const uint64_t tile0 = (uint64_t)tile * kRsTile;
-  const uint64_t lt = lanemask_lt();
+  const uint64_t wbase = tile0 + (uint64_t)w * (kRsR * 64);
   uint64_t key[kRsR];
   uint32_t val[kRsR];
   uint32_t rk[kRsR];
-  // issue every load of the tile before the first use (the ranking below is a
-  // chain of ballots and LDS updates that would otherwise wait on each load)
+  // every load of the tile is issued before the first use
 #pragma unroll
   for (int r = 0; r < kRsR; ++r) {
-    const uint64_t j = tile0 + (uint64_t)w * (kRsR * 64) + (uint64_t)r * 64 + lane;
+    const uint64_t j = wbase + (uint64_t)r * 64 + lane;
     key[r] = (j < n) ? __builtin_nontemporal_load(kin + j) : 0ull;
-    val[r] = (j < n) ? __builtin_nontemporal_load(vin + j) : 0u;
+    if (IN == kInKeyVal) val[r] = (j < n) ? __builtin_nontemporal_load(vin + j) : 0u;
+    if (IN == kInKeyIota) val[r] = (uint32_t)j;
   }
+  const uint64_t lt = lanemask_lt();
 #pragma unroll
   for (int r = 0; r < kRsR; ++r) {
-    const uint64_t j = tile0 + (uint64_t)w * (kRsR * 64) + (uint64_t)r * 64 + lane;
+    const uint64_t j = wbase + (uint64_t)r * 64 + lane;
     const bool valid = j < n;
-    const uint64_t k = key[r];
-    const uint32_t v = val[r];
-    const uint32_t d = (uint32_t)(k >> shift) & 255u;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
     uint64_t peer = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
@@ -282,8 +349,6 @@ __global__ __launch_bounds__(kRsT) void k_rs_onesweep(
     const uint32_t before = cnt[w][d];
     const uint32_t mine = (uint32_t)__popcll(peer & lt);
     if (valid && (peer & lt) == 0ull) cnt[w][d] = before + (uint32_t)__popcll(peer);
-    key[r] = k;
-    val[r] = v;
     rk[r] = valid ? before + mine : 0xffffffffu;
   }
   __syncthreads();
@@ -298,105 +363,101 @@ __global__ __launch_bounds__(kRsT) void k_rs_onesweep(
     }
     uint32_t tot;
     doff[d] = block_excl_scan<kRsT>(s, tot, lds);
-    const unsigned long long tag = epoch << 40;
-    unsigned long long* mine = status + (uint64_t)tile * 256 + d;
-    uint32_t excl = 0;
-    if (tile == 0) {
-      rs_store(mine, tag | (2ull << 32) | s);
-    } else {
-      rs_store(mine, tag | (1ull << 32) | s);
-      // read 8 predecessors at a time; sum back to the nearest inclusive prefix
-      int64_t j0 = (int64_t)tile - 1;
-      uint32_t spins = 0;
-      while (j0 >= 0) {
-        unsigned long long v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          v[q] = (j0 - q >= 0) ? rs_load(status + (uint64_t)(j0 - q) * 256 + d)
-                               : ((epoch << 40) | (2ull << 32));
-        uint32_t acc = 0;
-        int done = 0;  // 1: reached an inclusive prefix, -1: hit a tile not ready yet
-        int used = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          if (done) continue;
-          const uint32_t flag = (uint32_t)(v[q] >> 32) & 0xffu;
-          if ((v[q] >> 40) != epoch || flag == 0u) {
-            done = -1;
-            continue;
-          }
-          acc += (uint32_t)v[q];
-          ++used;
-          if (flag == 2u) done = 1;
-        }
-        excl += acc;
-        j0 -= used;
-        if (done == 1) break;
-        if (done == -1) {
-          if (++spins > kRsSpinMax) {
-            atomicOr(err, kErrSpin);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-      rs_store(mine, tag | (2ull << 32) | (uint32_t)(excl + s));
-    }
-    gbase[d] = gofs[d] + excl;
+    gbase[d] = base_off;
   }
   __syncthreads();
+  const uint32_t tn = (uint32_t)((n - tile0) < (uint64_t)kRsTile ? (n - tile0) : (uint64_t)kRsTile);
+  // keys (or packed words) through LDS in digit order, then out
 #pragma unroll
   for (int r = 0; r < kRsR; ++r) {
     if (rk[r] != 0xffffffffu) {
       const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
       const uint32_t pos = doff[d] + cnt[w][d] + rk[r];
-      sk[pos] = key[r];
-      sv[pos] = val[r];
+      if (kPack) {
+        sk[pos] = ((key[r] >> pk_shift) << ib) | (uint64_t)val[r];
+        sdig[pos] = (uint8_t)d;
+      } else {
+        sk[pos] = key[r];
+      }
+      rk[r] = pos;
     }
   }
   __syncthreads();
-  const uint32_t tn = (uint32_t)((n - tile0) < (uint64_t)kRsTile ? (n - tile0) : (uint64_t)kRsTile);
   for (uint32_t i = threadIdx.x; i < tn; i += kRsT) {
     const uint64_t k = sk[i];
-    const uint32_t d = (uint32_t)(k >> shift) & 255u;
-    const uint64_t o = (uint64_t)gbase[d] + (i - doff[d]);
-    kout[o] = k;
-    vout[o] = sv[i];
+    const uint32_t d = kPack ? (uint32_t)sdig[i] : (uint32_t)(k >> shift) & 255u;
+    kout[(uint64_t)gbase[d] + (i - doff[d])] = k;
+  }
+  if (OUT == kOutKeyVal) {
+    // the indices, through the same LDS with the digit beside each
+    __syncthreads();
+    uint32_t* sv = reinterpret_cast<uint32_t*>(sk);
+    uint8_t* sd = reinterpret_cast<uint8_t*>(sk) + 4 * kRsTile;
+#pragma unroll
+    for (int r = 0; r < kRsR; ++r) {
+      if (rk[r] != 0xffffffffu) {
+        sv[rk[r]] = val[r];
+        sd[rk[r]] = (uint8_t)((uint32_t)(key[r] >> shift) & 255u);
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < tn; i += kRsT) {
+      const uint32_t d = sd[i];
+      vout[(uint64_t)gbase[d] + (i - doff[d])] = sv[i];
+    }
   }
 }
 
-void sort_pairs(Ctx* ctx, Ws& ws, uint64_t*& keys, uint32_t*& vals, uint64_t*& ktmp,
-                uint32_t*& vtmp, uint64_t n, int bits, const uint32_t* ghist, uint32_t* err,
-                hipStream_t st) {
-  if (n <= 1 || bits <= 0) return;
-  const int npass = (bits + 7) / 8;
+uint64_t* sort_keys(Ctx* ctx, Ws& ws, uint64_t* keys, uint64_t n, const SortPlan& sp,
+                    const uint32_t* ghist, hipStream_t st) {
+  if (n == 0) return keys;
   const uint32_t ntiles = (uint32_t)((n + kRsTile - 1) / kRsTile);
-  const size_t nstat = (size_t)ntiles * 256;
-  if (ctx->rs_status_n < nstat) {
-    if (ctx->rs_status) ctx_free(ctx, ctx->rs_status, ctx->rs_status_n * 8, st);
-    ctx->rs_status = static_cast<unsigned long long*>(ctx_alloc(ctx, nstat * 8, st));
-    ctx->rs_status_n = nstat;
-    HIP_CHECK(hipMemsetAsync(ctx->rs_status, 0, nstat * 8, st));
-    ctx->rs_epoch = 0;
-  }
-  if (ctx->rs_epoch + npass >= (1u << 24) - 1) {
-    HIP_CHECK(hipMemsetAsync(ctx->rs_status, 0, ctx->rs_status_n * 8, st));
-    ctx->rs_epoch = 0;
-  }
-  uint32_t* gofs = ws.get<uint32_t>((uint64_t)npass * 256);
-  uint32_t* ctrs = ws.get<uint32_t>(kRsMaxPass);
-  HIP_CHECK(hipMemsetAsync(ctrs, 0, kRsMaxPass * sizeof(uint32_t), st));
-  k_rs_offsets<<<1, kRsT, 0, st>>>(ghist, npass, gofs);
+  uint32_t* gofs = ws.get<uint32_t>((uint64_t)sp.npass * 256);
+  uint32_t* th = ws.get<uint32_t>((uint64_t)ntiles * 256);
+  uint32_t* tofs = ws.get<uint32_t>((uint64_t)ntiles * 256);
+  uint64_t* kt = ws.get<uint64_t>(n);
+  uint32_t* va = (sp.q >= 2) ? ws.get<uint32_t>(n) : nullptr;
+  uint32_t* vb = (sp.q >= 3) ? ws.get<uint32_t>(n) : nullptr;
+  k_rs_offsets<<<1, kRsT, 0, st>>>(ghist, sp.npass, gofs);
   HIP_LAUNCH_CHECK();
-  for (int p = 0; p < npass; ++p) {
-    const unsigned long long epoch = ++ctx->rs_epoch;
-    AHF_TIMED(ctx, "rs_scatter", st,
-              (k_rs_onesweep<<<ntiles, kRsT, 0, st>>>(keys, vals, ktmp, vtmp, n, 8 * p,
-                                                      gofs + p * 256, ctx->rs_status, ctrs + p,
-                                                      epoch, err)));
-    std::swap(keys, ktmp);
-    std::swap(vals, vtmp);
+  uint64_t* a = keys;
+  uint64_t* b = kt;
+  uint32_t* vin = nullptr;
+  for (int p = 0; p < sp.npass; ++p) {
+    // pass p sorts key bits [8p, 8p + 8): in a packed word they sit above the index
+    const bool word_in = p >= sp.q;
+    const int shift = word_in ? sp.ib + 8 * (p - sp.q) : 8 * p;
+    AHF_TIMED(ctx, "rs_up", st, (k_rs_up<<<ntiles, kRsT, 0, st>>>(a, n, shift, ntiles, th)));
+    AHF_TIMED(ctx, "rs_tscan", st,
+              (k_rs_tscan<<<256, kTsT, 0, st>>>(th, ntiles, gofs + p * 256, tofs)));
+    uint32_t* vout = (vin == va) ? vb : va;
+    if (word_in) {
+      AHF_TIMED(ctx, "rs_scatter", st,
+                (k_rs_down<kInWord, kOutWord><<<ntiles, kRsT, 0, st>>>(
+                    a, nullptr, b, nullptr, n, shift, 0, sp.ib, ntiles, tofs)));
+    } else if (p == sp.q - 1) {
+      if (p == 0)
+        AHF_TIMED(ctx, "rs_scatter", st,
+                  (k_rs_down<kInKeyIota, kOutWord><<<ntiles, kRsT, 0, st>>>(
+                      a, nullptr, b, nullptr, n, shift, 8 * sp.q, sp.ib, ntiles, tofs)));
+      else
+        AHF_TIMED(ctx, "rs_scatter", st,
+                  (k_rs_down<kInKeyVal, kOutWord><<<ntiles, kRsT, 0, st>>>(
+                      a, vin, b, nullptr, n, shift, 8 * sp.q, sp.ib, ntiles, tofs)));
+    } else {
+      if (p == 0)
+        AHF_TIMED(ctx, "rs_scatter", st,
+                  (k_rs_down<kInKeyIota, kOutKeyVal><<<ntiles, kRsT, 0, st>>>(
+                      a, nullptr, b, vout, n, shift, 0, sp.ib, ntiles, tofs)));
+      else
+        AHF_TIMED(ctx, "rs_scatter", st,
+                  (k_rs_down<kInKeyVal, kOutKeyVal><<<ntiles, kRsT, 0, st>>>(
+                      a, vin, b, vout, n, shift, 0, sp.ib, ntiles, tofs)));
+      vin = vout;
+    }
+    std::swap(a, b);
   }
+  return a;
 }
 
 // ------------------------------------------------------------------ reductions

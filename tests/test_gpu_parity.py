@@ -5,7 +5,8 @@ import pytest
 import oracle
 from paper_0904_3662_amd import synth
 from tests.gpu_compare import compare_hierarchy
-from tests.helpers import Q, clustered, from_positions, particles, small_mixed_scaled, uniform
+from tests.helpers import (Q, clustered, from_positions, morton_py, particles, small_mixed_scaled,
+                           uniform)
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +83,46 @@ def test_coincident_chain_to_cap(ctx):
     p = particles([x] * K, [x + 999] * K, [x + 77777] * K, [f] * K, [f] * K, [f] * K, g=2,
                   thr=5, max_levels=19)
     run_case(ctx, p)
+
+
+def sort_layout(n, key_bits):
+    """(index width, number of (key, index) passes) of the device radix sort."""
+    ib = 1
+    while ib < 32 and (1 << ib) < n:
+        ib += 1
+    q = 0
+    while key_bits - 8 * q > 64 - ib:
+        q += 1
+    return ib, q
+
+
+# every pass layout of the sort: packed words from the start (q = 0), and
+# one, two or three (key, index) passes before packing
+@pytest.mark.parametrize("n,g,Lmax,q", [(5000, 3, 6, 0), (70000, 7, 10, 1),
+                                        (100000, 7, 14, 2), (300000, 7, 14, 3)])
+def test_particle_order_every_sort_layout(ctx, n, g, Lmax, q):
+    from paper_0904_3662_amd import ahf
+    B = g + Lmax
+    assert sort_layout(n, 3 * B)[1] == q
+    print(f"sort layout case n={n} B={B} q={q}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(n))
+    X = rng.integers(0, Q, n, dtype=np.uint32)
+    Y = rng.integers(0, Q, n, dtype=np.uint32)
+    Z = rng.integers(0, Q, n, dtype=np.uint32)
+    # a fifth of the particles repeat earlier positions: equal keys keep index order
+    dup = rng.random(n) < 0.2
+    src = rng.integers(0, n, n)
+    for a in (X, Y, Z):
+        a[dup] = a[src[dup]]
+    p = particles(X, Y, Z, g=g, thr=1e30, max_levels=Lmax)
+    h, _ = ahf.build_snapshot(ctx, p, labels=False)
+    order = h.order_numpy(n)
+    s = 21 - B
+    keys = morton_py(X >> s, Y >> s, Z >> s, B)
+    want = np.lexsort((np.arange(n), keys)).astype(np.uint32)
+    assert np.array_equal(order, want)
+    assert int(h.level_numpy(0)["cell_count"].sum()) == n
+    h.free()
 
 
 def test_bit_identical_reruns(ctx):
