@@ -57,19 +57,9 @@ struct Ctx {
   void* user = nullptr;
   Pool pool;
   Prof prof;
-  // decoupled look-back status words of the one-pass scans (kept between
-  // builds; every scan tags its words with a fresh epoch, so they never need
-  // clearing); tile counters come from a ring of words that is cleared once
-  // every kLbCtrs scans
-  unsigned long long* lb_status = nullptr;
-  size_t lb_status_n = 0;
-  uint32_t lb_epoch = 0;
-  uint32_t* lb_ctr = nullptr;
-  uint32_t lb_ctr_used = 0;
   uint32_t* dev_err = nullptr;  // device error flags of the running build
 };
 
-constexpr uint32_t kLbCtrs = 4096;
 
 // times one launch when the context profiles
 #define AHF_TIMED(ctxp, name, st, launch)                  \
@@ -137,11 +127,24 @@ struct Owned {
     for (auto& a : list) ctx_free(ctx, a.first, a.second, st);
     list.clear();
   }
+  // frees one allocation made by get (no-op for null)
+  void drop(void* p) {
+    for (size_t i = list.size(); i-- > 0;)
+      if (list[i].first == p) {
+        ctx_free(ctx, p, list[i].second, st);
+        list.erase(list.begin() + (long)i);
+        return;
+      }
+  }
 };
 
 // ---------------------------------------------------------------- primitives
-void scan_u32(Ws& ws, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
-              hipStream_t st);
+// Indices of the nonzero bytes of flags[0, n) in increasing order: list[r]
+// = index of the r-th flagged element and/or rank[i] = r for each flagged i
+// (either may be null; rank is left untouched at unflagged indices); *count
+// (device) = number of flagged elements.
+void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uint32_t* rank,
+                   uint32_t* count, hipStream_t st);
 // Stable LSD sort of particles by Morton key (key_bits bits), ties by index,
 // in 8-bit digits.  The first q passes move (key, index) pairs; from pass q on
 // one packed word per element, ((key >> 8q) << ib) | index, with ib the index

@@ -165,14 +165,13 @@ __global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
 // refinement flags; cells too full for one thread are appended to Hs (in no
 // particular order: the list only routes each such cell to its own sums)
 __global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double thr,
-                        int can_refine, uint8_t* __restrict__ flag, uint32_t* __restrict__ predF,
+                        int can_refine, uint8_t* __restrict__ flag,
                         uint32_t* __restrict__ nheavy, uint32_t* __restrict__ Hs,
                         int32_t* __restrict__ hidx) {
   GRID_STRIDE(s, nS) {
     const uint32_t c = count[s];
     const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
     flag[s] = (uint8_t)f;
-    predF[s] = f;
     if (c > (uint32_t)kHeavy) {
       const uint32_t h = atomicAdd(nheavy, 1u);
       Hs[h] = (uint32_t)s;
@@ -181,10 +180,6 @@ __global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double 
   }
 }
 
-__global__ void k_compact(const uint32_t* __restrict__ pred, const uint32_t* __restrict__ ofs,
-                          uint64_t n, uint32_t* __restrict__ out) {
-  GRID_STRIDE(i, n) if (pred[i]) out[ofs[i]] = (uint32_t)i;
-}
 
 // ------------------------------------------------------------ TSC weights
 
@@ -552,15 +547,17 @@ __device__ inline uint64_t slot_of_s(uint64_t s, const int32_t* Pbrick) {
   return Pbrick ? (uint64_t)Pbrick[s >> 3] * 8 + (s & 7) : s;
 }
 
-__global__ void k_slot_f(uint64_t nF, const uint32_t* __restrict__ Fs,
-                         const int32_t* __restrict__ Pbrick, int32_t* __restrict__ slot_f) {
-  GRID_STRIDE(f, nF) slot_f[slot_of_s(Fs[f], Pbrick)] = (int32_t)f;
+// slot of every refined cell -> its index in F_L
+__global__ void k_slot_f(uint64_t nS, const uint8_t* __restrict__ flag,
+                         const uint32_t* __restrict__ rankF, const int32_t* __restrict__ Pbrick,
+                         int32_t* __restrict__ slot_f) {
+  GRID_STRIDE(s, nS) if (flag[s]) slot_f[slot_of_s(s, Pbrick)] = (int32_t)rankF[s];
 }
 
 // level 0 is dense: a cell is in the dilation when one of its 27 neighbours
 // (itself included) is refined
 __global__ void k_mark_dense0(int g, uint64_t ncell, const uint8_t* __restrict__ flag,
-                              uint32_t* __restrict__ mark) {
+                              uint8_t* __restrict__ mark) {
   const uint32_t msk = (1u << g) - 1u;
   GRID_STRIDE(c, ncell) {
     uint32_t x, y, z;
@@ -571,14 +568,16 @@ __global__ void k_mark_dense0(int g, uint64_t ncell, const uint8_t* __restrict__
       const int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
       any |= flag[morton3((x + dx) & msk, (y + dy) & msk, (z + dz) & msk)];
     }
-    mark[c] = any ? 1u : 0u;
+    mark[c] = any ? 1 : 0;
   }
 }
 
 // mark every level-L slot within one cell of a refined cell
-__global__ void k_mark(int L, int bits, uint64_t nF, const uint32_t* __restrict__ Fs,
-                       const uint64_t* __restrict__ Skey, Tree tree, uint32_t* __restrict__ mark,
-                       uint32_t* __restrict__ err) {
+// (the number of refined cells is read on the device: the grid is a bound)
+__global__ void k_mark(int L, int bits, const uint32_t* __restrict__ nFdev,
+                       const uint32_t* __restrict__ Fs, const uint64_t* __restrict__ Skey,
+                       Tree tree, uint8_t* __restrict__ mark, uint32_t* __restrict__ err) {
+  const uint64_t nF = *nFdev;
   GRID_STRIDE(i, nF * 27) {
     const uint64_t f = i / 27;
     const int o = (int)(i % 27);
@@ -587,11 +586,11 @@ __global__ void k_mark(int L, int bits, uint64_t nF, const uint32_t* __restrict_
     const uint64_t nk = shift_key(key, bits, o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1);
     const int64_t slot = tree_lookup(tree, L, nk);
     if (slot < 0) atomicOr(err, kErrLookup);
-    else mark[slot] = 1u;
+    else mark[slot] = 1;
   }
 }
 
-__global__ void k_build_bricks(uint64_t nslot, const uint32_t* __restrict__ mark,
+__global__ void k_build_bricks(uint64_t nslot, const uint8_t* __restrict__ mark,
                                const uint32_t* __restrict__ rank,
                                const uint64_t* __restrict__ Bkey,
                                const int32_t* __restrict__ slot_f,
@@ -807,11 +806,11 @@ __global__ __launch_bounds__(256) void k_uf_cross(int Lp, int bits, uint64_t nF,
 // roots go to a separate array: par itself may still receive path-halving
 // stores from other threads, so it is never read back as the answer
 __global__ void k_uf_compress(int32_t* par, uint64_t n, int32_t* __restrict__ root,
-                              uint32_t* __restrict__ pred) {
+                              uint8_t* __restrict__ pred) {
   GRID_STRIDE(i, n) {
     const int32_t r = uf_find(par, (int32_t)i);
     root[i] = r;
-    pred[i] = (r == (int32_t)i) ? 1u : 0u;
+    pred[i] = (r == (int32_t)i) ? 1 : 0;
   }
 }
 
@@ -1057,25 +1056,58 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     // refinement flags and the cells too full for one thread
     const int can_refine = (L < prm.Lmax && b < kQBits) ? 1 : 0;
     const double thr = (L == 0) ? prm.dom_ref : prm.ref_ref;
-    uint32_t* predF = ws.get<uint32_t>(lv.nS);
-    uint32_t* ofsF = ws.get<uint32_t>(lv.nS);
     const uint64_t maxH = std::min<uint64_t>(lv.nS, n / (kHeavy + 1) + 1);
     uint32_t* Hs = ws.get<uint32_t>(maxH);
     int32_t* hidx = ws.get<int32_t>(lv.nS);  // read only for cells above kHeavy
     HIP_CHECK(hipMemsetAsync(dev_u32 + 2, 0, 2 * sizeof(uint32_t), st));
-    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag, predF,
+    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag,
                                             dev_u32 + 2, Hs, hidx);
     HIP_LAUNCH_CHECK();
-    scan_u32(ws, predF, ofsF, lv.nS, dev_u32 + 1, st);
-    uint32_t cnts[2];
-    HIP_CHECK(hipMemcpyAsync(cnts, dev_u32 + 1, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    uint32_t* Ftmp = ws.get<uint32_t>(lv.nS);
+    uint32_t* rankF = ws.get<uint32_t>(lv.nS);
+    compact_flags(ws, lv.Sflag, lv.nS, Ftmp, rankF, dev_u32 + 1, st);
+
+    // the dilation of F_L: slots of level L that hold a brick on level L+1
+    // (sized by the bound nF <= nS, so that one sync per level reads nF, the
+    // heavy-cell count and the brick count together)
+    const uint64_t nslot = 8 * nB;
+    uint8_t* mark = nullptr;
+    uint32_t* rank = nullptr;
+    if (can_refine) {
+      lv.slot_f = h->mem.get<int32_t>(nslot);
+      k_fill_i32<<<grid_for(nslot), kT, 0, st>>>(lv.slot_f, nslot, -1);
+      HIP_LAUNCH_CHECK();
+      k_slot_f<<<grid_for(lv.nS), kT, 0, st>>>(lv.nS, lv.Sflag, rankF, lv.Pbrick, lv.slot_f);
+      HIP_LAUNCH_CHECK();
+      mark = ws.get<uint8_t>(nslot);
+      rank = ws.get<uint32_t>(nslot);
+      if (L == 0) {
+        AHF_TIMED(ctx, "mark", st,
+                  (k_mark_dense0<<<grid_for(nslot), kT, 0, st>>>(g, nslot, lv.Sflag, mark)));
+      } else {
+        HIP_CHECK(hipMemsetAsync(mark, 0, nslot, st));
+        Tree tree = make_tree(h);
+        unsigned mb = grid_for(lv.nS * 27);
+        if (mb > 8192) mb = 8192;
+        AHF_TIMED(ctx, "mark", st,
+                  (k_mark<<<mb, kT, 0, st>>>(L, b, dev_u32 + 1, Ftmp, lv.Skey, tree, mark, err)));
+      }
+      compact_flags(ws, mark, nslot, nullptr, rank, dev_u32 + 4, st);
+    } else {
+      HIP_CHECK(hipMemsetAsync(dev_u32 + 4, 0, sizeof(uint32_t), st));
+    }
+    uint32_t cnts[4];
+    HIP_CHECK(hipMemcpyAsync(cnts, dev_u32 + 1, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     lv.nF = cnts[0];
     const uint64_t nH = cnts[1];
+    const uint32_t nD = cnts[3];
     lv.Fs = h->mem.get<uint32_t>(lv.nF);
-    if (lv.nF) {
-      k_compact<<<grid_for(lv.nS), kT, 0, st>>>(predF, ofsF, lv.nS, lv.Fs);
-      HIP_LAUNCH_CHECK();
+    if (lv.nF)
+      HIP_CHECK(hipMemcpyAsync(lv.Fs, Ftmp, lv.nF * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    if (lv.nF == 0 && lv.slot_f) {
+      h->mem.drop(lv.slot_f);
+      lv.slot_f = nullptr;
     }
 
     const uint32_t mask = (1u << (kQBits - b)) - 1u;
@@ -1138,29 +1170,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     }
 
     // bricks of level L+1: children of every level-L cell within one cell of F_L
-    const uint64_t nslot = 8 * nB;
-    lv.slot_f = h->mem.get<int32_t>(nslot);
     lv.slot_child = h->mem.get<int32_t>(nslot);
-    k_fill_i32<<<grid_for(nslot), kT, 0, st>>>(lv.slot_f, nslot, -1);
-    HIP_LAUNCH_CHECK();
-    k_slot_f<<<grid_for(lv.nF), kT, 0, st>>>(lv.nF, lv.Fs, lv.Pbrick, lv.slot_f);
-    HIP_LAUNCH_CHECK();
-    uint32_t* mark = ws.get<uint32_t>(nslot);
-    uint32_t* rank = ws.get<uint32_t>(nslot);
-    if (L == 0) {
-      AHF_TIMED(ctx, "mark", st,
-                (k_mark_dense0<<<grid_for(nslot), kT, 0, st>>>(g, nslot, lv.Sflag, mark)));
-    } else {
-      HIP_CHECK(hipMemsetAsync(mark, 0, nslot * sizeof(uint32_t), st));
-      Tree tree = make_tree(h);
-      AHF_TIMED(ctx, "mark", st,
-                (k_mark<<<grid_for(lv.nF * 27), kT, 0, st>>>(L, b, lv.nF, lv.Fs, lv.Skey, tree,
-                                                             mark, err)));
-    }
-    scan_u32(ws, mark, rank, nslot, dev_u32 + 4, st);
-    uint32_t nD = 0;
-    HIP_CHECK(hipMemcpyAsync(&nD, dev_u32 + 4, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
     uint64_t* nBkey = h->mem.get<uint64_t>(nD);
     int32_t* nBcell = h->mem.get<int32_t>(nD);
     k_build_bricks<<<grid_for(nslot), kT, 0, st>>>(nslot, mark, rank, lv.Bkey, lv.slot_f,
@@ -1240,7 +1250,7 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     Ws::Mark m = ws.mark();
     int32_t* par = ws.get<int32_t>(nE);
     int32_t* root = ws.get<int32_t>(nE);
-    uint32_t* pred = ws.get<uint32_t>(nE);
+    uint8_t* pred = ws.get<uint8_t>(nE);
     uint32_t* rank = ws.get<uint32_t>(nE);
     int32_t* lab = ws.get<int32_t>(nE);
     uint16_t* xmask = ws.get<uint16_t>(nE);
@@ -1255,7 +1265,7 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     }
     k_uf_compress<<<grid_for(nE), kT, 0, st>>>(par, nE, root, pred);
     HIP_LAUNCH_CHECK();
-    scan_u32(ws, pred, rank, nE, npatch, st);
+    compact_flags(ws, pred, nE, nullptr, rank, npatch, st);
     k_uf_label<<<grid_for(nE), kT, 0, st>>>(root, rank, nE, lab);
     HIP_LAUNCH_CHECK();
     lv.Spatch = h->mem.get<int32_t>(lv.nS);

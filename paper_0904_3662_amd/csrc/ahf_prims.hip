@@ -43,158 +43,101 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t& total, uint32_t
   return r;
 }
 
-// ------------------------------------------------------------------ scan
+// ------------------------------------------------------------------ compaction
 //
-// Exclusive scan of uint32 in one pass: tiles of 8192 values take their index
-// in start order, publish their sum, and find their offset by decoupled
-// look-back over earlier tiles (same status-word scheme as the radix sort).
+// Positions of the nonzero bytes of a flag array, in index order, by
+// reduce-then-scan over tiles of 8192 flags: count per tile, exclusive scan
+// of the tile counts in one block, then each tile re-reads its flags and
+// writes the index of every flagged element at its rank (list) and/or its
+// rank at its index (rank).  One tile needs no count pass.
 
-constexpr int kScanT = 256;
-constexpr int kScanI = 32;
-constexpr int kScanTile = kScanT * kScanI;
-constexpr uint32_t kScanSpinMax = 1u << 22;
+constexpr int kCfT = 256;
+constexpr int kCfPer = 32;                 // flags per thread
+constexpr int kCfTile = kCfT * kCfPer;     // 8192
+constexpr int kCfMidT = 1024;
 
-__device__ inline unsigned long long lb_load(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void lb_store(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Exclusive prefix of tile `tile`, computed by the first wave of the block:
-// the 64 lanes read the status words of the 64 preceding tiles at once, sum
-// them back to the nearest inclusive prefix, and step back 64 tiles when
-// there is none.  status word: [63:40] epoch, [39:32] 1 = tile sum,
-// 2 = inclusive prefix, [31:0] value.  Call from all lanes of wave 0.
-__device__ inline uint32_t wave_lookback(unsigned long long* status, uint32_t tile, uint32_t own,
-                                         unsigned long long epoch, uint32_t spin_max,
-                                         uint32_t* err) {
-  const int lane = (int)__lane_id();
-  const unsigned long long tag = epoch << 40;
-  if (lane == 0) lb_store(status + tile, tag | ((tile == 0 ? 2ull : 1ull) << 32) | own);
-  if (tile == 0) return 0u;
-  uint32_t excl = 0;
-  int64_t j0 = (int64_t)tile - 1;
-  uint32_t spins = 0;
-  while (j0 >= 0) {
-    const int64_t j = j0 - lane;
-    uint32_t val = 0;
-    bool ready = true, incl = true;
-    if (j >= 0) {
-      const unsigned long long v = lb_load(status + j);
-      const uint32_t flag = (uint32_t)(v >> 32) & 0xffu;
-      ready = ((v >> 40) == epoch) && flag != 0u;
-      incl = ready && flag == 2u;
-      val = (uint32_t)v;
-    }
-    const uint64_t rmask = __ballot(ready);
-    const uint64_t imask = __ballot(incl);
-    uint64_t need = ~0ull;
-    if (imask) {
-      const int k = __ffsll((unsigned long long)imask) - 1;
-      need = (k == 63) ? ~0ull : ((1ull << (k + 1)) - 1ull);
-    }
-    if ((rmask & need) != need) {
-      if (++spins > spin_max) {
-        if (lane == 0) atomicOr(err, kErrSpin);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    uint32_t part = ((need >> lane) & 1ull) ? val : 0u;
+// the 32 flags of thread t of a tile, one bit each
+__device__ inline uint32_t cf_bits(const uint8_t* __restrict__ flags, uint64_t n, uint64_t i0) {
+  uint32_t m = 0;
+  if (i0 + kCfPer <= n) {
+    const uint4* p = reinterpret_cast<const uint4*>(flags + i0);
+    const uint4 a = p[0], b = p[1];
+    const uint32_t wds[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
-    excl += part;
-    if (imask) break;
-    j0 -= 64;
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if ((wds[k] >> (8 * j)) & 255u) m |= 1u << (4 * k + j);
+  } else {
+    for (int k = 0; k < kCfPer; ++k)
+      if (i0 + k < n && flags[i0 + k]) m |= 1u << k;
   }
-  if (lane == 0) lb_store(status + tile, tag | (2ull << 32) | (uint32_t)(excl + own));
-  return excl;
+  return m;
 }
 
-__global__ __launch_bounds__(kScanT) void k_scan(const uint32_t* __restrict__ in,
-                                                 uint32_t* __restrict__ out, uint64_t n,
-                                                 unsigned long long* __restrict__ status,
-                                                 uint32_t* __restrict__ ctr,
-                                                 unsigned long long epoch,
-                                                 uint32_t* __restrict__ total,
-                                                 uint32_t* __restrict__ err) {
-  __shared__ uint32_t lds[kScanT / 64 + 1];
-  __shared__ uint32_t tile[kScanTile];
-  __shared__ uint32_t tile_sh, excl_sh;
-  if (threadIdx.x == 0) tile_sh = atomicAdd(ctr, 1u);
-  __syncthreads();
-  const uint32_t t = tile_sh;
-  const uint64_t base = (uint64_t)t * kScanTile;
-#pragma unroll
-  for (int i = 0; i < kScanI; ++i) {
-    const uint64_t j = base + (uint64_t)i * kScanT + threadIdx.x;
-    tile[i * kScanT + threadIdx.x] = (j < n) ? in[j] : 0u;
-  }
-  __syncthreads();
-  uint32_t v[kScanI];
-  uint32_t s = 0;
-#pragma unroll
-  for (int i = 0; i < kScanI; ++i) {
-    v[i] = tile[threadIdx.x * kScanI + i];
-    s += v[i];
-  }
+__global__ __launch_bounds__(kCfT) void k_cf_up(const uint8_t* __restrict__ flags, uint64_t n,
+                                               uint32_t* __restrict__ tcnt) {
+  __shared__ uint32_t lds[kCfT / 64 + 1];
+  const uint64_t i0 = (uint64_t)blockIdx.x * kCfTile + (uint64_t)threadIdx.x * kCfPer;
+  const uint32_t c = (uint32_t)__popc(cf_bits(flags, n, i0));
   uint32_t tot;
-  uint32_t off = block_excl_scan<kScanT>(s, tot, lds);
-  if (threadIdx.x < 64) {
-    const uint32_t e = wave_lookback(status, t, tot, epoch, kScanSpinMax, err);
-    if (threadIdx.x == 0) {
-      excl_sh = e;
-      if (total && (uint64_t)(t + 1) * kScanTile >= n) *total = e + tot;
-    }
-  }
-  __syncthreads();
-  off += excl_sh;
-#pragma unroll
-  for (int i = 0; i < kScanI; ++i) {
-    tile[threadIdx.x * kScanI + i] = off;
-    off += v[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kScanI; ++i) {
-    const uint64_t j = base + (uint64_t)i * kScanT + threadIdx.x;
-    if (j < n) out[j] = tile[i * kScanT + threadIdx.x];
+  block_excl_scan<kCfT>(c, tot, lds);
+  if (threadIdx.x == 0) tcnt[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kCfMidT) void k_cf_mid(const uint32_t* __restrict__ tcnt,
+                                                    uint32_t ntiles, uint32_t* __restrict__ tofs) {
+  __shared__ uint32_t lds[kCfMidT / 64 + 1];
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < ntiles; c0 += kCfMidT) {
+    const uint32_t t = c0 + threadIdx.x;
+    const uint32_t v = (t < ntiles) ? tcnt[t] : 0u;
+    uint32_t tot;
+    const uint32_t e = block_excl_scan<kCfMidT>(v, tot, lds);
+    if (t < ntiles) tofs[t] = carry + e;
+    carry += tot;
   }
 }
 
-void scan_u32(Ws& ws, const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* total,
-              hipStream_t st) {
-  Ctx* ctx = ws.ctx();
-  uint64_t nt = (n + kScanTile - 1) / kScanTile;
-  if (nt < 1) nt = 1;
-  if (ctx->lb_status_n < nt) {
-    if (ctx->lb_status) ctx_free(ctx, ctx->lb_status, ctx->lb_status_n * 8, st);
-    const size_t want = nt < 4096 ? 4096 : nt;
-    ctx->lb_status = static_cast<unsigned long long*>(ctx_alloc(ctx, want * 8, st));
-    ctx->lb_status_n = want;
-    HIP_CHECK(hipMemsetAsync(ctx->lb_status, 0, want * 8, st));
-    ctx->lb_epoch = 0;
+__global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ flags, uint64_t n,
+                                                 const uint32_t* __restrict__ tofs,
+                                                 uint32_t* __restrict__ list,
+                                                 uint32_t* __restrict__ rank,
+                                                 uint32_t* __restrict__ count) {
+  __shared__ uint32_t lds[kCfT / 64 + 1];
+  const uint64_t i0 = (uint64_t)blockIdx.x * kCfTile + (uint64_t)threadIdx.x * kCfPer;
+  uint32_t m = cf_bits(flags, n, i0);
+  uint32_t tot;
+  uint32_t pos = block_excl_scan<kCfT>((uint32_t)__popc(m), tot, lds);
+  const uint32_t base = tofs ? tofs[blockIdx.x] : 0u;
+  pos += base;
+  while (m) {
+    const int k = __ffs(m) - 1;
+    m &= m - 1u;
+    if (list) list[pos] = (uint32_t)(i0 + k);
+    if (rank) rank[i0 + k] = pos;
+    ++pos;
   }
-  if (ctx->lb_epoch + 1 >= (1u << 24) - 1) {
-    HIP_CHECK(hipMemsetAsync(ctx->lb_status, 0, ctx->lb_status_n * 8, st));
-    ctx->lb_epoch = 0;
+  if (count && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *count = base + tot;
+}
+
+void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uint32_t* rank,
+                   uint32_t* count, hipStream_t st) {
+  const uint64_t ntiles = (n + kCfTile - 1) / kCfTile;
+  if (ntiles == 0) {
+    HIP_CHECK(hipMemsetAsync(count, 0, sizeof(uint32_t), st));
+    return;
   }
-  // one counter word per scan, taken from a ring that is cleared in bulk
-  if (!ctx->lb_ctr) {
-    ctx->lb_ctr = static_cast<uint32_t*>(ctx_alloc(ctx, kLbCtrs * sizeof(uint32_t), st));
-    HIP_CHECK(hipMemsetAsync(ctx->lb_ctr, 0, kLbCtrs * sizeof(uint32_t), st));
-    ctx->lb_ctr_used = 0;
+  uint32_t* tofs = nullptr;
+  if (ntiles > 1) {
+    uint32_t* tcnt = ws.get<uint32_t>(ntiles);
+    tofs = ws.get<uint32_t>(ntiles);
+    k_cf_up<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, n, tcnt);
+    HIP_LAUNCH_CHECK();
+    k_cf_mid<<<1, kCfMidT, 0, st>>>(tcnt, (uint32_t)ntiles, tofs);
+    HIP_LAUNCH_CHECK();
   }
-  if (ctx->lb_ctr_used >= kLbCtrs) {
-    HIP_CHECK(hipMemsetAsync(ctx->lb_ctr, 0, kLbCtrs * sizeof(uint32_t), st));
-    ctx->lb_ctr_used = 0;
-  }
-  uint32_t* ctr = ctx->lb_ctr + ctx->lb_ctr_used++;
-  const unsigned long long epoch = ++ctx->lb_epoch;
-  k_scan<<<(unsigned)nt, kScanT, 0, st>>>(in, out, n, ctx->lb_status, ctr, epoch, total,
-                                          ctx->dev_err);
+  k_cf_down<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, n, tofs, list, rank, count);
   HIP_LAUNCH_CHECK();
 }
 
