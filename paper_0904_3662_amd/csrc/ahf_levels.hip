@@ -54,6 +54,15 @@ __global__ void k_fill_i32(int32_t* a, uint64_t n, int32_t v) {
   GRID_STRIDE(i, n) a[i] = v;
 }
 
+// slot -> F index starts at -1, dilation marks (when given) at 0
+__global__ void k_clear_slots(int32_t* __restrict__ slot_f, uint8_t* __restrict__ mark,
+                              uint64_t nslot) {
+  GRID_STRIDE(i, nslot) {
+    slot_f[i] = -1;
+    if (mark) mark[i] = 0;
+  }
+}
+
 
 // Morton keys at B bits per axis, the identity permutation, the particle as
 // one 32-byte record {X, Y, Z, mass | fx, fy, fz, 0} (input order), and the
@@ -167,7 +176,8 @@ __global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
 __global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double thr,
                         int can_refine, uint8_t* __restrict__ flag,
                         uint32_t* __restrict__ nheavy, uint32_t* __restrict__ Hs,
-                        int32_t* __restrict__ hidx) {
+                        int32_t* __restrict__ hidx, uint32_t* __restrict__ clear) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *clear = 0u;
   GRID_STRIDE(s, nS) {
     const uint32_t c = count[s];
     const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
@@ -491,6 +501,8 @@ __global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint6
 }
 
 // FP64 sums of a level: the field, the particle mass per cell, the counts
+// FP64 sums of the brick masses, the per-cell particle masses and the cell
+// counts: partial sums per block, then one block adds them in block order
 __global__ __launch_bounds__(256) void k_level_sums(const float* __restrict__ a, uint64_t na,
                                                     const double* __restrict__ b, uint64_t nb,
                                                     const uint32_t* __restrict__ c, uint64_t nc,
@@ -595,7 +607,8 @@ __global__ void k_build_bricks(uint64_t nslot, const uint8_t* __restrict__ mark,
                                const uint64_t* __restrict__ Bkey,
                                const int32_t* __restrict__ slot_f,
                                int32_t* __restrict__ slot_child, uint64_t* __restrict__ nBkey,
-                               int32_t* __restrict__ nBcell) {
+                               int32_t* __restrict__ nBcell, uint32_t* __restrict__ clear) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *clear = 0u;
   GRID_STRIDE(i, nslot) {
     if (mark[i]) {
       const uint32_t r = rank[i];
@@ -609,10 +622,15 @@ __global__ void k_build_bricks(uint64_t nslot, const uint8_t* __restrict__ mark,
   }
 }
 
-__global__ void k_pbrick(uint64_t nF, const uint32_t* __restrict__ Fs,
+// brick of every refined cell's children; also moves F_L to its final buffer
+__global__ void k_pbrick(uint64_t nF, const uint32_t* __restrict__ Ftmp,
                          const int32_t* __restrict__ Pbrick, const int32_t* __restrict__ slot_child,
-                         int32_t* __restrict__ nPbrick) {
-  GRID_STRIDE(f, nF) nPbrick[f] = slot_child[slot_of_s(Fs[f], Pbrick)];
+                         int32_t* __restrict__ nPbrick, uint32_t* __restrict__ Fs) {
+  GRID_STRIDE(f, nF) {
+    const uint32_t s = Ftmp[f];
+    Fs[f] = s;
+    nPbrick[f] = slot_child[slot_of_s(s, Pbrick)];
+  }
 }
 
 // ------------------------------------------------------------ labels
@@ -805,22 +823,33 @@ __global__ __launch_bounds__(256) void k_uf_cross(int Lp, int bits, uint64_t nF,
 
 // roots go to a separate array: par itself may still receive path-halving
 // stores from other threads, so it is never read back as the answer
+// final roots; also clears the per-patch accumulators (nz >= n entries)
 __global__ void k_uf_compress(int32_t* par, uint64_t n, int32_t* __restrict__ root,
-                              uint8_t* __restrict__ pred) {
-  GRID_STRIDE(i, n) {
+                              uint8_t* __restrict__ pred, uint64_t nz, uint32_t* __restrict__ z32,
+                              unsigned long long* __restrict__ z64a,
+                              unsigned long long* __restrict__ z64b) {
+  GRID_STRIDE(i, nz) {
+    z32[i] = 0u;
+    z64a[i] = 0ull;
+    if (z64b) z64b[i] = 0ull;
+    if (i >= n) continue;
     const int32_t r = uf_find(par, (int32_t)i);
     root[i] = r;
     pred[i] = (r == (int32_t)i) ? 1 : 0;
   }
 }
 
+// patch id of every refined parent (the rank of its root among the roots),
+// and of its 8 children, the cells of S_L
 __global__ void k_uf_label(const int32_t* __restrict__ root, const uint32_t* __restrict__ rank,
-                           uint64_t n, int32_t* __restrict__ lab) {
-  GRID_STRIDE(i, n) lab[i] = (int32_t)rank[root[i]];
-}
-
-__global__ void k_cell_patch(const int32_t* __restrict__ lab, uint64_t nS, int32_t* __restrict__ Spatch) {
-  GRID_STRIDE(s, nS) Spatch[s] = lab[s >> 3];
+                           uint64_t n, int32_t* __restrict__ lab, int32_t* __restrict__ Spatch) {
+  GRID_STRIDE(i, n) {
+    const int32_t l = (int32_t)rank[root[i]];
+    lab[i] = l;
+    int4* o = reinterpret_cast<int4*>(Spatch + 8 * i);
+    o[0] = make_int4(l, l, l, l);
+    o[1] = make_int4(l, l, l, l);
+  }
 }
 
 // per patch: cells, particles (exact integer atomics); mass as fixed point.
@@ -916,20 +945,21 @@ __global__ __launch_bounds__(256) void k_patch_stats(const int32_t* __restrict__
   }
 }
 
+// per patch, from its root: the parent patch (the level-(L-1) patch of the
+// root's cell) and the mass (fixed point back to FP64, or count x mass)
 __global__ void k_patch_parent(const int32_t* __restrict__ root, const int32_t* __restrict__ lab,
                                uint64_t nF, const uint32_t* __restrict__ pFs,
-                               const int32_t* __restrict__ pSpatch, int32_t* __restrict__ parent) {
+                               const int32_t* __restrict__ pSpatch, int32_t* __restrict__ parent,
+                               const unsigned long long* __restrict__ npart,
+                               const unsigned long long* __restrict__ mfix, double mscalar,
+                               double inv_scale, double* __restrict__ pm) {
   GRID_STRIDE(f, nF) {
-    if (root[f] == (int32_t)f) parent[lab[f]] = pSpatch ? pSpatch[pFs[f]] : -1;
+    if (root[f] == (int32_t)f) {
+      const int32_t p = lab[f];
+      parent[p] = pSpatch ? pSpatch[pFs[f]] : -1;
+      pm[p] = mfix ? (double)mfix[p] * inv_scale : (double)npart[p] * mscalar;
+    }
   }
-}
-
-__global__ void k_patch_mass(const uint32_t* __restrict__ npatch,
-                             const unsigned long long* __restrict__ npart,
-                             const unsigned long long* __restrict__ mfix, double mscalar,
-                             double inv_scale, double* __restrict__ pm) {
-  const uint64_t np = *npatch;
-  GRID_STRIDE(p, np) pm[p] = mfix ? (double)mfix[p] * inv_scale : (double)npart[p] * mscalar;
 }
 
 // ------------------------------------------------------------ label queries
@@ -1059,9 +1089,10 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     const uint64_t maxH = std::min<uint64_t>(lv.nS, n / (kHeavy + 1) + 1);
     uint32_t* Hs = ws.get<uint32_t>(maxH);
     int32_t* hidx = ws.get<int32_t>(lv.nS);  // read only for cells above kHeavy
-    HIP_CHECK(hipMemsetAsync(dev_u32 + 2, 0, 2 * sizeof(uint32_t), st));
+    // dev_u32[2] (heavy cells) is zero here: cleared at the start and by
+    // k_build_bricks of the previous level; k_flags clears dev_u32[3]
     k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag,
-                                            dev_u32 + 2, Hs, hidx);
+                                            dev_u32 + 2, Hs, hidx, dev_u32 + 3);
     HIP_LAUNCH_CHECK();
     uint32_t* Ftmp = ws.get<uint32_t>(lv.nS);
     uint32_t* rankF = ws.get<uint32_t>(lv.nS);
@@ -1075,17 +1106,16 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     uint32_t* rank = nullptr;
     if (can_refine) {
       lv.slot_f = h->mem.get<int32_t>(nslot);
-      k_fill_i32<<<grid_for(nslot), kT, 0, st>>>(lv.slot_f, nslot, -1);
+      mark = ws.get<uint8_t>(nslot);
+      rank = ws.get<uint32_t>(nslot);
+      k_clear_slots<<<grid_for(nslot), kT, 0, st>>>(lv.slot_f, L == 0 ? nullptr : mark, nslot);
       HIP_LAUNCH_CHECK();
       k_slot_f<<<grid_for(lv.nS), kT, 0, st>>>(lv.nS, lv.Sflag, rankF, lv.Pbrick, lv.slot_f);
       HIP_LAUNCH_CHECK();
-      mark = ws.get<uint8_t>(nslot);
-      rank = ws.get<uint32_t>(nslot);
       if (L == 0) {
         AHF_TIMED(ctx, "mark", st,
                   (k_mark_dense0<<<grid_for(nslot), kT, 0, st>>>(g, nslot, lv.Sflag, mark)));
       } else {
-        HIP_CHECK(hipMemsetAsync(mark, 0, nslot, st));
         Tree tree = make_tree(h);
         unsigned mb = grid_for(lv.nS * 27);
         if (mb > 8192) mb = 8192;
@@ -1102,9 +1132,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     lv.nF = cnts[0];
     const uint64_t nH = cnts[1];
     const uint32_t nD = cnts[3];
-    lv.Fs = h->mem.get<uint32_t>(lv.nF);
-    if (lv.nF)
-      HIP_CHECK(hipMemcpyAsync(lv.Fs, Ftmp, lv.nF * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    lv.Fs = h->mem.get<uint32_t>(lv.nF);  // filled from Ftmp by k_pbrick below
     if (lv.nF == 0 && lv.slot_f) {
       h->mem.drop(lv.slot_f);
       lv.slot_f = nullptr;
@@ -1127,12 +1155,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       HIP_LAUNCH_CHECK();
       float* chT = ws.get<float>(maxch * 27);
       double* chM = ws.get<double>(maxch);
-      AHF_TIMED(ctx, "heavy_chunk", st,
-                (k_heavy_chunk<<<(unsigned)maxch, 256, 0, st>>>(dev_u32 + 3, ch_h, ch_j, Hs,
-                                                                lv.Sstart, lv.Scount, P, mask,
-                                                                scale, chT, chM)));
       hT = ws.get<float>(nH * 27);
       hM = ws.get<double>(nH);
+      AHF_TIMED(ctx, "heavy_chunk", st,
+                (k_heavy_chunk<<<(unsigned)maxch, 256, 0, st>>>(
+                    dev_u32 + 3, ch_h, ch_j, Hs, lv.Sstart, lv.Scount, P, mask, scale, chT, chM)));
       k_heavy_reduce<<<grid_for(nH * 28), kT, 0, st>>>(nch, chofs, nH, chT, chM, hT, hM);
       HIP_LAUNCH_CHECK();
     }
@@ -1174,10 +1201,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     uint64_t* nBkey = h->mem.get<uint64_t>(nD);
     int32_t* nBcell = h->mem.get<int32_t>(nD);
     k_build_bricks<<<grid_for(nslot), kT, 0, st>>>(nslot, mark, rank, lv.Bkey, lv.slot_f,
-                                                   lv.slot_child, nBkey, nBcell);
+                                                   lv.slot_child, nBkey, nBcell, dev_u32 + 2);
     HIP_LAUNCH_CHECK();
     int32_t* nPbrick = h->mem.get<int32_t>(lv.nF);
-    k_pbrick<<<grid_for(lv.nF), kT, 0, st>>>(lv.nF, lv.Fs, lv.Pbrick, lv.slot_child, nPbrick);
+    k_pbrick<<<grid_for(lv.nF), kT, 0, st>>>(lv.nF, Ftmp, lv.Pbrick, lv.slot_child, nPbrick,
+                                             lv.Fs);
     HIP_LAUNCH_CHECK();
     nFp = lv.nF;
     nB = nD;
@@ -1263,34 +1291,26 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
                 (k_uf_cross<<<grid_for(nE), 256, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs, pv.Skey,
                                                           tree, pv.slot_f, xmask, par, dev)));
     }
-    k_uf_compress<<<grid_for(nE), kT, 0, st>>>(par, nE, root, pred);
-    HIP_LAUNCH_CHECK();
-    compact_flags(ws, pred, nE, nullptr, rank, npatch, st);
-    k_uf_label<<<grid_for(nE), kT, 0, st>>>(root, rank, nE, lab);
-    HIP_LAUNCH_CHECK();
     lv.Spatch = h->mem.get<int32_t>(lv.nS);
-    k_cell_patch<<<grid_for(lv.nS), kT, 0, st>>>(lab, lv.nS, lv.Spatch);
-    HIP_LAUNCH_CHECK();
     lv.patch_parent = h->mem.get<int32_t>(nE1);
     lv.patch_ncells = h->mem.get<uint32_t>(nE1);
     lv.patch_npart = h->mem.get<uint64_t>(nE1);
     lv.patch_mass = h->mem.get<double>(nE1);
-    HIP_CHECK(hipMemsetAsync(lv.patch_ncells, 0, nE1 * sizeof(uint32_t), st));
-    HIP_CHECK(hipMemsetAsync(lv.patch_npart, 0, nE1 * sizeof(uint64_t), st));
-    unsigned long long* mfix = nullptr;
-    if (h->has_mass) {
-      mfix = ws.get<unsigned long long>(nE1);
-      HIP_CHECK(hipMemsetAsync(mfix, 0, nE1 * sizeof(unsigned long long), st));
-    }
+    unsigned long long* mfix = h->has_mass ? ws.get<unsigned long long>(nE1) : nullptr;
+    k_uf_compress<<<grid_for(nE1), kT, 0, st>>>(par, nE, root, pred, nE1, lv.patch_ncells,
+                                                (unsigned long long*)lv.patch_npart, mfix);
+    HIP_LAUNCH_CHECK();
+    compact_flags(ws, pred, nE, nullptr, rank, npatch, st);
+    k_uf_label<<<grid_for(nE), kT, 0, st>>>(root, rank, nE, lab, lv.Spatch);
+    HIP_LAUNCH_CHECK();
     k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (nE + 4095) / 4096 + 1), 256, 0, st>>>(
         lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale, lv.patch_ncells,
         (unsigned long long*)lv.patch_npart, mfix);
     HIP_LAUNCH_CHECK();
     k_patch_parent<<<grid_for(nE), kT, 0, st>>>(root, lab, nE, pv.Fs, (L >= 2) ? pv.Spatch : nullptr,
-                                                lv.patch_parent);
-    HIP_LAUNCH_CHECK();
-    k_patch_mass<<<grid_for(nE), kT, 0, st>>>(npatch, (const unsigned long long*)lv.patch_npart,
-                                              mfix, h->mass_scalar, 1.0 / fscale, lv.patch_mass);
+                                                lv.patch_parent,
+                                                (const unsigned long long*)lv.patch_npart, mfix,
+                                                h->mass_scalar, 1.0 / fscale, lv.patch_mass);
     HIP_LAUNCH_CHECK();
     // stream order keeps the released workspace from being reused early
     ws.release(m);

@@ -55,6 +55,7 @@ constexpr int kCfT = 256;
 constexpr int kCfPer = 32;                 // flags per thread
 constexpr int kCfTile = kCfT * kCfPer;     // 8192
 constexpr int kCfMidT = 1024;
+constexpr uint64_t kCfSumTiles = 2048;     // up to here a tile sums the counts before it
 
 // the 32 flags of thread t of a tile, one bit each
 __device__ inline uint32_t cf_bits(const uint8_t* __restrict__ flags, uint64_t n, uint64_t i0) {
@@ -99,17 +100,24 @@ __global__ __launch_bounds__(kCfMidT) void k_cf_mid(const uint32_t* __restrict__
   }
 }
 
+// tile offset: from the scanned tile counts (tofs), or summed here from the
+// tile counts of the tiles before this one (tcnt, few tiles), or 0 (one tile)
 __global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ flags, uint64_t n,
+                                                 const uint32_t* __restrict__ tcnt,
                                                  const uint32_t* __restrict__ tofs,
                                                  uint32_t* __restrict__ list,
                                                  uint32_t* __restrict__ rank,
                                                  uint32_t* __restrict__ count) {
   __shared__ uint32_t lds[kCfT / 64 + 1];
   const uint64_t i0 = (uint64_t)blockIdx.x * kCfTile + (uint64_t)threadIdx.x * kCfPer;
+  uint32_t before = 0;
+  if (!tofs && tcnt)
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kCfT) before += tcnt[t];
   uint32_t m = cf_bits(flags, n, i0);
-  uint32_t tot;
+  uint32_t tot, tb;
+  if (!tofs && tcnt) block_excl_scan<kCfT>(before, tb, lds);
   uint32_t pos = block_excl_scan<kCfT>((uint32_t)__popc(m), tot, lds);
-  const uint32_t base = tofs ? tofs[blockIdx.x] : 0u;
+  const uint32_t base = tofs ? tofs[blockIdx.x] : (tcnt ? tb : 0u);
   pos += base;
   while (m) {
     const int k = __ffs(m) - 1;
@@ -128,16 +136,20 @@ void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uin
     HIP_CHECK(hipMemsetAsync(count, 0, sizeof(uint32_t), st));
     return;
   }
+  uint32_t* tcnt = nullptr;
   uint32_t* tofs = nullptr;
   if (ntiles > 1) {
-    uint32_t* tcnt = ws.get<uint32_t>(ntiles);
-    tofs = ws.get<uint32_t>(ntiles);
+    tcnt = ws.get<uint32_t>(ntiles);
     k_cf_up<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, n, tcnt);
     HIP_LAUNCH_CHECK();
-    k_cf_mid<<<1, kCfMidT, 0, st>>>(tcnt, (uint32_t)ntiles, tofs);
-    HIP_LAUNCH_CHECK();
+    if (ntiles > kCfSumTiles) {
+      // many tiles: scan the counts once instead of summing them per tile
+      tofs = ws.get<uint32_t>(ntiles);
+      k_cf_mid<<<1, kCfMidT, 0, st>>>(tcnt, (uint32_t)ntiles, tofs);
+      HIP_LAUNCH_CHECK();
+    }
   }
-  k_cf_down<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, n, tofs, list, rank, count);
+  k_cf_down<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, n, tcnt, tofs, list, rank, count);
   HIP_LAUNCH_CHECK();
 }
 
