@@ -176,12 +176,15 @@ __global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
 __global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double thr,
                         int can_refine, uint8_t* __restrict__ flag,
                         uint32_t* __restrict__ nheavy, uint32_t* __restrict__ Hs,
-                        int32_t* __restrict__ hidx, uint32_t* __restrict__ clear) {
+                        int32_t* __restrict__ hidx, uint32_t* __restrict__ clear,
+                        uint32_t* __restrict__ rank_unset) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *clear = 0u;
   GRID_STRIDE(s, nS) {
     const uint32_t c = count[s];
     const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
     flag[s] = (uint8_t)f;
+    // the compaction fills in the rank of the refined cells
+    if (rank_unset && !f) rank_unset[s] = 0xffffffffu;
     if (c > (uint32_t)kHeavy) {
       const uint32_t h = atomicAdd(nheavy, 1u);
       Hs[h] = (uint32_t)s;
@@ -387,6 +390,146 @@ constexpr PatchLayout make_patch_layout() {
       }
   }
   return t;
+}
+
+// ------------------------------------------------------------ dense tiles
+//
+// Levels whose parents form a dense grid (level 0, whose parents are the
+// virtual level -1, and level 1 over a well-refined level 0) deposit by
+// tiles of 4x4x4 parents = 8x8x8 cells, one cell per thread: the cells add
+// their 27-tensors into an LDS grid of the tile plus a one-cell halo, the
+// tile's own cells go straight to their bricks and the halo (the tile's
+// deposit into its neighbours' cells) to a buffer that k_tile_halo_add folds
+// in afterwards.
+
+constexpr int kTileT = 512;   // threads = cells per tile
+constexpr int kTileMaxG = 8;  // largest domain grid (bits per axis) tiled: halo <= 1 GB
+constexpr int kTileG = 10;    // cells per axis with the halo
+constexpr int kTileH = kTileG * kTileG * kTileG;
+
+__device__ inline uint32_t tile_local_parent(uint32_t x, uint32_t y, uint32_t z) {
+  // Morton index of a parent inside its 4x4x4 tile
+  return (((x >> 1) & 1u) << 5) | (((y >> 1) & 1u) << 4) | (((z >> 1) & 1u) << 3) |
+         ((x & 1u) << 2) | ((y & 1u) << 1) | (z & 1u);
+}
+
+// DENSE0: the tile's parents are virtual (every level-0 cell exists, cell =
+// 8 * parent + digit, brick = parent); else parents are level-0 cells, a
+// refined one (prank != ~0) holds 8 cells of S_1 at 8 * prank + digit, and
+// bricks come from the level-0 slot -> level-1 brick map.  Level-0 cells
+// hold several particles each: their records are loaded four ahead.
+template <bool DENSE0>
+__global__ __launch_bounds__(kTileT) void k_tile_deposit(
+    const uint32_t* __restrict__ prank,
+    const uint32_t* __restrict__ Sstart, const uint32_t* __restrict__ Scount,
+    const int32_t* __restrict__ hidx, const float* __restrict__ hT,
+    const double* __restrict__ hM, Parts P, uint32_t mask, float scale,
+    const int32_t* __restrict__ pslot_child, float* __restrict__ mass,
+    float* __restrict__ halo, double* __restrict__ Spmass) {
+  __shared__ float G[kTileH];  // the tile's cells and their one-cell halo
+  const int t = threadIdx.x;
+  const uint64_t tile = blockIdx.x;
+  for (int q = t; q < kTileH; q += kTileT) G[q] = 0.0f;
+  const uint32_t pm = (uint32_t)t >> 3, d = (uint32_t)t & 7u;
+  const uint32_t px = (((pm >> 5) & 1u) << 1) | ((pm >> 2) & 1u);
+  const uint32_t py = (((pm >> 4) & 1u) << 1) | ((pm >> 1) & 1u);
+  const uint32_t pz = (((pm >> 3) & 1u) << 1) | (pm & 1u);
+  const uint32_t cx = 2 * px + ((d >> 2) & 1u), cy = 2 * py + ((d >> 1) & 1u), cz = 2 * pz + (d & 1u);
+  const uint64_t pg = tile * 64 + pm;
+  float T[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) T[k] = 0.0f;
+  const uint32_t r = DENSE0 ? 0u : prank[pg];
+  if (DENSE0 || r != 0xffffffffu) {
+    const uint64_t s = DENSE0 ? pg * 8 + d : (uint64_t)r * 8 + d;
+    const uint32_t n = Scount[s];
+    const uint32_t a0 = Sstart[s];
+    double ms = 0.0;
+    if (n > (uint32_t)kHeavy) {
+      const int32_t h = hidx[s];
+#pragma unroll
+      for (int k = 0; k < 27; ++k) T[k] = hT[(uint64_t)h * 27 + k];
+      ms = hM[h];
+    } else if (DENSE0) {
+      add_range(P, a0, n, mask, scale, T, ms);
+    } else {
+      for (uint32_t i = 0; i < n; ++i) add_particle(P, a0 + i, mask, scale, T, ms);
+    }
+    if (Spmass) Spmass[s] = ms;
+  }
+  // 27 phases, one per neighbour offset in a fixed order: within a phase every
+  // cell adds to a different grid cell, so no two writes collide and every
+  // grid cell sums its contributions in the same order on every run
+  const int g0 = ((int)(cx + 1) * kTileG + (int)(cy + 1)) * kTileG + (int)(cz + 1);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int q = g0 + ((a - 1) * kTileG + (b - 1)) * kTileG + (c - 1);
+        G[q] += T[a * 9 + b * 3 + c];
+        __syncthreads();
+      }
+  for (int q = t; q < kTileH; q += kTileT) {
+    const int dx = q / 100 - 1, dy = (q / 10) % 10 - 1, dz = q % 10 - 1;
+    const float sum = G[q];
+    if ((unsigned)dx < 8u && (unsigned)dy < 8u && (unsigned)dz < 8u) {
+      const uint64_t pp = tile * 64 + tile_local_parent((uint32_t)dx >> 1, (uint32_t)dy >> 1,
+                                                        (uint32_t)dz >> 1);
+      const int64_t br = DENSE0 ? (int64_t)pp : (int64_t)pslot_child[pp];
+      const uint32_t dd = (((uint32_t)dx & 1u) << 2) | (((uint32_t)dy & 1u) << 1) | ((uint32_t)dz & 1u);
+      if (br >= 0) mass[(uint64_t)br * 8 + dd] = sum;
+    } else {
+      halo[tile * kTileH + q] = sum;
+    }
+  }
+}
+
+// adds to the cells on a tile's faces what the neighbouring tiles deposited
+// there (own tile first, then the neighbours in a fixed offset order); nb =
+// tile bits per axis
+__global__ __launch_bounds__(256) void k_tile_halo_add(int dense0, int nb,
+                                                      const int32_t* __restrict__ pslot_child,
+                                                      const float* __restrict__ halo,
+                                                      float* __restrict__ mass) {
+  const uint64_t tile = blockIdx.x;
+  uint32_t tx, ty, tz;
+  unmorton3(tile, tx, ty, tz);
+  const uint32_t tm = (1u << nb) - 1u;
+  for (int li = threadIdx.x; li < 512; li += 256) {
+    const int cx = li >> 6, cy = (li >> 3) & 7, cz = li & 7;
+    const bool fx = cx == 0 || cx == 7, fy = cy == 0 || cy == 7, fz = cz == 0 || cz == 7;
+    if (!(fx || fy || fz)) continue;
+    const uint64_t pp = tile * 64 + tile_local_parent((uint32_t)cx >> 1, (uint32_t)cy >> 1,
+                                                      (uint32_t)cz >> 1);
+    const int64_t br = dense0 ? (int64_t)pp : (int64_t)pslot_child[pp];
+    if (br < 0) continue;
+    const uint32_t dd = (((uint32_t)cx & 1u) << 2) | (((uint32_t)cy & 1u) << 1) | ((uint32_t)cz & 1u);
+    const int sx = cx == 0 ? -1 : (cx == 7 ? 1 : 0);
+    const int sy = cy == 0 ? -1 : (cy == 7 ? 1 : 0);
+    const int sz = cz == 0 ? -1 : (cz == 7 ? 1 : 0);
+    // the (up to 7) neighbour tiles whose halo covers this cell: loads first,
+    // then the sum in a fixed order
+    float hv[8];
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+      const int ax = (m & 4) ? sx : 0, ay = (m & 2) ? sy : 0, az = (m & 1) ? sz : 0;
+      const bool ok = (!(m & 4) || sx) && (!(m & 2) || sy) && (!(m & 1) || sz);
+      hv[m] = 0.0f;
+      if (ok) {
+        const uint64_t nt = morton3((tx + (uint32_t)ax) & tm, (ty + (uint32_t)ay) & tm,
+                                    (tz + (uint32_t)az) & tm);
+        const int q = ((cx - 8 * ax + 1) * kTileG + (cy - 8 * ay + 1)) * kTileG + (cz - 8 * az + 1);
+        hv[m] = halo[nt * kTileH + q];
+      }
+    }
+    float v = mass[(uint64_t)br * 8 + dd];
+#pragma unroll
+    for (int m = 1; m < 8; ++m) v += hv[m];
+    mass[(uint64_t)br * 8 + dd] = v;
+  }
 }
 
 __constant__ PatchLayout c_patch = make_patch_layout();
@@ -1049,12 +1192,14 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   int32_t* Pbrick = nullptr;
   h->lev.clear();
   h->lev.reserve(kMaxLevels);
+  uint32_t* rank0 = nullptr;  // rank of each refined level-0 cell in F_0 (dense tiles)
   for (int L = 0; L <= prm.Lmax; ++L) {
     h->lev.emplace_back();
     Level& lv = h->lev.back();
     const int b = g + L;
     lv.b = (uint32_t)b;
     const int sh = 3 * (B - b);
+    if (L == 0 && g >= 2 && g <= kTileMaxG) rank0 = ws.get<uint32_t>(1ull << (3 * g));
     Ws::Mark lvl_mark = ws.mark();
     if (L == 0) {
       lv.nS = 1ull << (3 * g);
@@ -1092,10 +1237,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     // dev_u32[2] (heavy cells) is zero here: cleared at the start and by
     // k_build_bricks of the previous level; k_flags clears dev_u32[3]
     k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag,
-                                            dev_u32 + 2, Hs, hidx, dev_u32 + 3);
+                                            dev_u32 + 2, Hs, hidx, dev_u32 + 3,
+                                            (L == 0) ? rank0 : nullptr);
     HIP_LAUNCH_CHECK();
     uint32_t* Ftmp = ws.get<uint32_t>(lv.nS);
-    uint32_t* rankF = ws.get<uint32_t>(lv.nS);
+    uint32_t* rankF = (L == 0 && rank0) ? rank0 : ws.get<uint32_t>(lv.nS);
     compact_flags(ws, lv.Sflag, lv.nS, Ftmp, rankF, dev_u32 + 1, st);
 
     // the dilation of F_L: slots of level L that hold a brick on level L+1
@@ -1164,15 +1310,37 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       HIP_LAUNCH_CHECK();
     }
 
-    // TSC deposit: parent patches, then brick cells
-    float* patch = ws.get<float>(nFp * 64);
-    if (nFp) {
-      AHF_TIMED(ctx, "patches", st,
-                (k_patches<<<(unsigned)((nFp + 31) / 32), 256, 0, st>>>(
-                    nFp, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, patch, lv.Spmass)));
-    }
+    // TSC deposit: by dense tiles where the parents form a well-filled grid,
+    // else parent patches, then brick cells
     lv.mass = h->mem.get<float>(8 * nB);
-    {
+    const bool tiles0 = L == 0 && g - 1 >= 2 && g <= kTileMaxG;
+    const bool tiles1 = L == 1 && g >= 2 && g <= kTileMaxG && rank0 &&
+                        8 * nFp >= (1ull << (3 * g));
+    if (tiles0 || tiles1) {
+      const int pb = tiles0 ? g - 1 : g;  // bits per axis of the parent grid
+      const uint64_t ntiles = 1ull << (3 * (pb - 2));
+      float* halo = ws.get<float>(ntiles * kTileH);
+      const Level& l0 = h->lev[0];
+      if (tiles0)
+        AHF_TIMED(ctx, "patches", st,
+                  (k_tile_deposit<true><<<(unsigned)ntiles, kTileT, 0, st>>>(
+                      nullptr, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, nullptr,
+                      lv.mass, halo, lv.Spmass)));
+      else
+        AHF_TIMED(ctx, "patches", st,
+                  (k_tile_deposit<false><<<(unsigned)ntiles, kTileT, 0, st>>>(
+                      rank0, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, l0.slot_child,
+                      lv.mass, halo, lv.Spmass)));
+      AHF_TIMED(ctx, "combine", st,
+                (k_tile_halo_add<<<(unsigned)ntiles, 256, 0, st>>>(
+                    tiles0 ? 1 : 0, pb - 2, tiles0 ? nullptr : l0.slot_child, halo, lv.mass)));
+    } else {
+      float* patch = ws.get<float>(nFp * 64);
+      if (nFp) {
+        AHF_TIMED(ctx, "patches", st,
+                  (k_patches<<<(unsigned)((nFp + 31) / 32), 256, 0, st>>>(
+                      nFp, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, patch, lv.Spmass)));
+      }
       Tree tree = make_tree(h);
       const int32_t* pslot_f = (L > 0) ? h->lev[L - 1].slot_f : nullptr;
       AHF_TIMED(ctx, "combine", st,
