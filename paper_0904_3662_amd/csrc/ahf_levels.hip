@@ -163,8 +163,12 @@ __global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
     const uint32_t e = a + pScount[ps];
     const uint64_t pk = pSkey ? pSkey[ps] : (uint64_t)ps;
     const uint64_t ck = (pk << 3) | d;
+    // the 8 children of a parent sit on 8 consecutive lanes (nS is a multiple
+    // of 8 and so is every lane group's first s): each finds where its child
+    // starts, and ends where the next child starts
     const uint32_t lo = (d == 0) ? a : lower_bound_key(skey, a, e, ck << sh);
-    const uint32_t hi = (d == 7) ? e : lower_bound_key(skey, lo, e, (ck + 1) << sh);
+    const uint32_t nxt = (uint32_t)__shfl_down((int)lo, 1, 8);
+    const uint32_t hi = (d == 7) ? e : nxt;
     Skey[s] = ck;
     Sstart[s] = lo;
     Scount[s] = hi - lo;
@@ -275,16 +279,16 @@ __global__ void k_chunk_list(const uint32_t* __restrict__ Hs, uint64_t nH,
   }
 }
 
-// one block per chunk of <= kChunk particles of one heavy cell; every thread
-// sums at most kChunk/256 = 64 particles, then a fixed tree over the block
+// one wave per chunk of <= kChunk particles of one heavy cell (4 chunks per
+// block of 256 threads); every lane sums at most kChunk/64 = 64 particles,
+// then a fixed butterfly over the wave
 __global__ __launch_bounds__(256) void k_heavy_chunk(
     const uint32_t* __restrict__ nchunks, const uint32_t* __restrict__ ch_h,
     const uint32_t* __restrict__ ch_j, const uint32_t* __restrict__ Hs,
     const uint32_t* __restrict__ Sstart, const uint32_t* __restrict__ Scount, Parts P,
     uint32_t mask, float scale, float* __restrict__ chT, double* __restrict__ chM) {
-  __shared__ float red[4][27];
-  __shared__ double redm[4];
-  const uint32_t c = blockIdx.x;
+  const uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63u;
   if (c >= *nchunks) return;
   const uint32_t s = Hs[ch_h[c]];
   const uint32_t j = ch_j[c];
@@ -295,35 +299,28 @@ __global__ __launch_bounds__(256) void k_heavy_chunk(
 #pragma unroll
   for (int k = 0; k < 27; ++k) T[k] = 0.0f;
   double ms = 0.0;
-  uint32_t i = threadIdx.x;
-  for (; i + 3 * 256 < len; i += 4 * 256) {
+  uint32_t i = lane;
+  for (; i + 3 * 64 < len; i += 4 * 64) {
     uint4 r[8];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      r[2 * k] = P.rec[2 * (uint64_t)(a + i + k * 256)];
-      r[2 * k + 1] = P.rec[2 * (uint64_t)(a + i + k * 256) + 1];
+      r[2 * k] = P.rec[2 * (uint64_t)(a + i + k * 64)];
+      r[2 * k + 1] = P.rec[2 * (uint64_t)(a + i + k * 64) + 1];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) add_record(r[2 * k], r[2 * k + 1], mask, scale, T, ms);
   }
-  for (; i < len; i += 256) add_particle(P, a + i, mask, scale, T, ms);
-  const int w = threadIdx.x >> 6;
+  for (; i < len; i += 64) add_particle(P, a + i, mask, scale, T, ms);
 #pragma unroll
   for (int k = 0; k < 27; ++k) {
     float v = T[k];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if ((threadIdx.x & 63) == 0) red[w][k] = v;
+    if (lane == (uint32_t)k) chT[(uint64_t)c * 27 + k] = v;
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) ms += __shfl_xor(ms, d, 64);
-  if ((threadIdx.x & 63) == 0) redm[w] = ms;
-  __syncthreads();
-  if (threadIdx.x < 27) {
-    const int k = threadIdx.x;
-    chT[(uint64_t)c * 27 + k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
-  }
-  if (threadIdx.x == 27) chM[c] = (redm[0] + redm[1]) + (redm[2] + redm[3]);
+  if (lane == 27) chM[c] = ms;
 }
 
 // pairwise (binary-counter) sum over the chunks of each heavy cell
@@ -475,7 +472,9 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
   for (int q = t; q < kTileH; q += kTileT) {
     const int dx = q / 100 - 1, dy = (q / 10) % 10 - 1, dz = q % 10 - 1;
     const float sum = G[q];
-    if ((unsigned)dx < 8u && (unsigned)dy < 8u && (unsigned)dz < 8u) {
+    // cells off the tile's faces are final; face cells and the halo go to
+    // the buffer, where k_tile_halo_add adds the neighbours' share
+    if ((unsigned)(dx - 1) < 6u && (unsigned)(dy - 1) < 6u && (unsigned)(dz - 1) < 6u) {
       const uint64_t pp = tile * 64 + tile_local_parent((uint32_t)dx >> 1, (uint32_t)dy >> 1,
                                                         (uint32_t)dz >> 1);
       const int64_t br = DENSE0 ? (int64_t)pp : (int64_t)pslot_child[pp];
@@ -505,7 +504,6 @@ __global__ __launch_bounds__(256) void k_tile_halo_add(int dense0, int nb,
     const uint64_t pp = tile * 64 + tile_local_parent((uint32_t)cx >> 1, (uint32_t)cy >> 1,
                                                       (uint32_t)cz >> 1);
     const int64_t br = dense0 ? (int64_t)pp : (int64_t)pslot_child[pp];
-    if (br < 0) continue;
     const uint32_t dd = (((uint32_t)cx & 1u) << 2) | (((uint32_t)cy & 1u) << 1) | ((uint32_t)cz & 1u);
     const int sx = cx == 0 ? -1 : (cx == 7 ? 1 : 0);
     const int sy = cy == 0 ? -1 : (cy == 7 ? 1 : 0);
@@ -525,10 +523,10 @@ __global__ __launch_bounds__(256) void k_tile_halo_add(int dense0, int nb,
         hv[m] = halo[nt * kTileH + q];
       }
     }
-    float v = mass[(uint64_t)br * 8 + dd];
+    float v = halo[tile * kTileH + ((cx + 1) * kTileG + (cy + 1)) * kTileG + (cz + 1)];
 #pragma unroll
     for (int m = 1; m < 8; ++m) v += hv[m];
-    mass[(uint64_t)br * 8 + dd] = v;
+    if (br >= 0) mass[(uint64_t)br * 8 + dd] = v;
   }
 }
 
@@ -1304,7 +1302,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       hT = ws.get<float>(nH * 27);
       hM = ws.get<double>(nH);
       AHF_TIMED(ctx, "heavy_chunk", st,
-                (k_heavy_chunk<<<(unsigned)maxch, 256, 0, st>>>(
+                (k_heavy_chunk<<<(unsigned)((maxch + 3) / 4), 256, 0, st>>>(
                     dev_u32 + 3, ch_h, ch_j, Hs, lv.Sstart, lv.Scount, P, mask, scale, chT, chM)));
       k_heavy_reduce<<<grid_for(nH * 28), kT, 0, st>>>(nch, chofs, nH, chT, chM, hT, hM);
       HIP_LAUNCH_CHECK();
