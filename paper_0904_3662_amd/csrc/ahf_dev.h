@@ -76,6 +76,26 @@ __device__ inline int64_t tree_lookup(const Tree& t, int L, uint64_t key) {
   return slot;
 }
 
+// slots of K level-L keys at once (-1 where a key is not in the field, or
+// where its slot is given as -1 on entry, i.e. skipped): all keys descend one
+// level at a time, so their K loads per level are in flight together
+template <int K>
+__device__ inline void tree_lookup_k(const Tree& t, int L, const uint64_t (&key)[K],
+                                     int64_t (&slot)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (slot[k] >= 0) slot[k] = (int64_t)(key[k] >> (3 * L));
+  for (int l = 1; l <= L; ++l) {
+    const int32_t* sc = t.slot_child[l - 1];
+    int32_t dv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) dv[k] = slot[k] >= 0 ? sc[slot[k]] : -1;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      slot[k] = dv[k] < 0 ? -1 : (int64_t)dv[k] * 8 + (int64_t)((key[k] >> (3 * (L - l))) & 7u);
+  }
+}
+
 __device__ inline uint64_t lanemask_lt() {
   const uint32_t lane = __lane_id();
   return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));

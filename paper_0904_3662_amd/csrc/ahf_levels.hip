@@ -611,17 +611,26 @@ __global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint6
     uint32_t qx, qy, qz;
     unmorton3(P, qx, qy, qz);
     const uint32_t msk = (1u << pbits) - 1u;
-    for (int o = d; o < 27; o += 8) {
+    // lane d looks up neighbours d, d+8, d+16 (and 24), together
+    uint64_t k[4];
+    int64_t slot[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = d + 8 * j;
       const int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
-      const uint64_t k = morton3((qx + dx) & msk, (qy + dy) & msk, (qz + dz) & msk);
-      int32_t f;
-      if (L == 0) {
-        f = (int32_t)k;
-      } else {
-        const int64_t slot = tree_lookup(tree, L - 1, k);
-        f = slot < 0 ? -1 : pslot_f[slot];
-      }
-      fn[lb][o] = f;
+      k[j] = morton3((qx + dx) & msk, (qy + dy) & msk, (qz + dz) & msk);
+      slot[j] = (o < 27) ? 0 : -1;
+    }
+    if (L == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) slot[j] = slot[j] < 0 ? -1 : (int64_t)k[j];
+    } else {
+      tree_lookup_k<4>(tree, L - 1, k, slot);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = d + 8 * j;
+      if (o < 27) fn[lb][o] = slot[j] < 0 ? -1 : (L == 0 ? (int32_t)slot[j] : pslot_f[slot[j]]);
     }
   }
   __syncthreads();
@@ -823,6 +832,15 @@ __device__ inline bool conn_ok(int dx, int dy, int dz, int conn) {
   return conn == 6 ? s == 1 : (conn == 18 ? s <= 2 : true);
 }
 
+// the half-neighbourhood offsets that count as adjacent under conn
+__device__ inline uint32_t conn_mask(int conn) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int o = 0; o < 13; ++o)
+    if (conn_ok(c_half26[o][0], c_half26[o][1], c_half26[o][2], conn)) m |= 1u << o;
+  return m;
+}
+
 constexpr int kUfTile = 256;
 
 __device__ inline int32_t lds_find(volatile int32_t* lp, int32_t x) {
@@ -853,17 +871,29 @@ __device__ inline void lds_unite(int32_t* lp, int32_t a, int32_t b) {
   }
 }
 
-__device__ inline int32_t refined_neighbour(int Lp, int bits, const Tree& tree,
-                                            const int32_t* __restrict__ slot_f, uint64_t key,
-                                            int o, uint32_t* err) {
-  const uint64_t nk = shift_key(key, bits, c_half26[o][0], c_half26[o][1], c_half26[o][2]);
-  const int64_t slot = tree_lookup(tree, Lp, nk);
-  if (slot < 0) {
-    atomicOr(err, kErrLookup);
-    return -1;
+// F indices of the 13 half-neighbourhood neighbours selected by `sel` (bit
+// o = offset c_half26[o]); -1 where unselected or not refined
+__device__ inline void refined_neighbours(int Lp, int bits, const Tree& tree,
+                                          const int32_t* __restrict__ slot_f, uint64_t key,
+                                          uint32_t sel, int32_t (&g)[13], uint32_t* err) {
+  uint64_t nk[13];
+  int64_t slot[13];
+#pragma unroll
+  for (int o = 0; o < 13; ++o) {
+    nk[o] = shift_key(key, bits, c_half26[o][0], c_half26[o][1], c_half26[o][2]);
+    slot[o] = ((sel >> o) & 1u) ? 0 : -1;
   }
-  return slot_f[slot];
+  tree_lookup_k<13>(tree, Lp, nk, slot);
+#pragma unroll
+  for (int o = 0; o < 13; ++o) {
+    g[o] = -1;
+    if ((sel >> o) & 1u) {
+      if (slot[o] < 0) atomicOr(err, kErrLookup);
+      else g[o] = slot_f[slot[o]];
+    }
+  }
 }
+
 
 // Elements are the refined cells F of level Lp (key order).  Each block
 // unites the cells of kUfTile consecutive elements in LDS; edges that leave
@@ -887,11 +917,7 @@ __global__ __launch_bounds__(256) void k_uf_local(int Lp, int bits, uint64_t nF,
     const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
     uint32_t xm = 0;
     int32_t gs[13];
-#pragma unroll
-    for (int o = 0; o < 13; ++o)
-      gs[o] = conn_ok(c_half26[o][0], c_half26[o][1], c_half26[o][2], conn)
-                  ? refined_neighbour(Lp, bits, tree, slot_f, key, o, err)
-                  : -1;
+    refined_neighbours(Lp, bits, tree, slot_f, key, conn_mask(conn), gs, err);
 #pragma unroll
     for (int o = 0; o < 13; ++o) {
       const int32_t g = gs[o];
@@ -930,10 +956,11 @@ __global__ __launch_bounds__(256) void k_uf_cross(int Lp, int bits, uint64_t nF,
         const uint32_t s = Fs[f];
         const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
         const int32_t ra = par[f];  // tile-local root (written by k_uf_local)
-        while (xm) {
-          const int o = __ffs(xm) - 1;
-          xm &= xm - 1;
-          const int32_t g = refined_neighbour(Lp, bits, tree, slot_f, key, o, err);
+        int32_t gs[13];
+        refined_neighbours(Lp, bits, tree, slot_f, key, xm, gs, err);
+#pragma unroll
+        for (int o = 0; o < 13; ++o) {
+          const int32_t g = gs[o];
           if (g < 0) continue;
           const int32_t rb = par[g];
           const int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
