@@ -166,8 +166,9 @@ ahf_status ahf_level_get(const ahf_hierarchy *h, uint32_t level, ahf_level_view 
  * particles of every cell of every level are contiguous in this order. */
 ahf_status ahf_hierarchy_order(const ahf_hierarchy *h, const uint32_t **sorted_idx);
 
-/* Per-build stage times in milliseconds (host clock around the stream work),
- * for profiling: [0] keys+sort, [1] levels, [2] labels, [3] total.  n <= 4. */
+/* Per-build stage times in milliseconds, for profiling: [0] keys + sort +
+ * gather and [1] levels (device time between events on the build stream),
+ * [2] labels and [3] total (host clock around the call).  n <= 4. */
 ahf_status ahf_hierarchy_timings(const ahf_hierarchy *h, double *ms, uint32_t n);
 
 void ahf_hierarchy_free(ahf_hierarchy *h);

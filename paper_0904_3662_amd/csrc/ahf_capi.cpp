@@ -245,6 +245,10 @@ void ahf_ctx_destroy(ahf_ctx* ctx) {
   (void)hipSetDevice(ctx->c.device);
   (void)hipDeviceSynchronize();
   ctx->ws.free_all();
+  if (ctx->c.host_cnt) (void)hipHostFree(ctx->c.host_cnt);
+  if (ctx->c.cnt_ev) (void)hipEventDestroy(ctx->c.cnt_ev);
+  for (auto& e : ctx->c.phase_ev)
+    if (e) (void)hipEventDestroy(e);
   ctx->c.prof.collect();
   for (auto e : ctx->c.prof.spare) (void)hipEventDestroy(e);
   ctx_release_pool(&ctx->c);

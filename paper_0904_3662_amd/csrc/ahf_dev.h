@@ -14,7 +14,6 @@ constexpr int kChunk = 4096;        // particles per chunk of a heavy cell (64 l
 constexpr uint32_t kErrCoord = 1u;     // a coordinate >= 2^21
 constexpr uint32_t kErrLookup = 2u;    // a cell that must exist was not found
 constexpr uint32_t kErrInternal = 4u;
-constexpr uint32_t kErrSpin = 8u;      // a bounded wait gave up (never expected)
 
 // 21-bit value -> every third bit of a 63-bit word (Morton spreading)
 __host__ __device__ inline uint64_t spread3(uint32_t v) {

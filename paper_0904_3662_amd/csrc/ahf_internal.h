@@ -58,6 +58,11 @@ struct Ctx {
   Pool pool;
   Prof prof;
   uint32_t* dev_err = nullptr;  // device error flags of the running build
+  // per-level counts read back while the level's deposit runs: pinned host
+  // words, an event behind their copy, and events that time the build phases
+  uint32_t* host_cnt = nullptr;
+  hipEvent_t cnt_ev = nullptr;
+  hipEvent_t phase_ev[3] = {nullptr, nullptr, nullptr};
 };
 
 

@@ -263,10 +263,11 @@ __device__ inline void add_range(const Parts& P, uint32_t a, uint32_t n, uint32_
 
 // every heavy cell takes a contiguous run of chunk slots; its chunks are
 // later summed in the order of their index j inside that run
-__global__ void k_chunk_list(const uint32_t* __restrict__ Hs, uint64_t nH,
+__global__ void k_chunk_list(const uint32_t* __restrict__ Hs, const uint32_t* __restrict__ nHdev,
                              const uint32_t* __restrict__ Scount, uint32_t* __restrict__ nchunks,
                              uint32_t* __restrict__ nch, uint32_t* __restrict__ chofs,
                              uint32_t* __restrict__ ch_h, uint32_t* __restrict__ ch_j) {
+  const uint64_t nH = *nHdev;
   GRID_STRIDE(h, nH) {
     const uint32_t m = (Scount[Hs[h]] + kChunk - 1) / kChunk;
     const uint32_t o = atomicAdd(nchunks, m);
@@ -287,9 +288,9 @@ __global__ __launch_bounds__(256) void k_heavy_chunk(
     const uint32_t* __restrict__ ch_j, const uint32_t* __restrict__ Hs,
     const uint32_t* __restrict__ Sstart, const uint32_t* __restrict__ Scount, Parts P,
     uint32_t mask, float scale, float* __restrict__ chT, double* __restrict__ chM) {
-  const uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint32_t lane = threadIdx.x & 63u;
-  if (c >= *nchunks) return;
+  const uint32_t nc = *nchunks;
+  for (uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < nc; c += gridDim.x * 4) {
   const uint32_t s = Hs[ch_h[c]];
   const uint32_t j = ch_j[c];
   const uint32_t n = Scount[s];
@@ -321,13 +322,15 @@ __global__ __launch_bounds__(256) void k_heavy_chunk(
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) ms += __shfl_xor(ms, d, 64);
   if (lane == 27) chM[c] = ms;
+  }
 }
 
 // pairwise (binary-counter) sum over the chunks of each heavy cell
 __global__ void k_heavy_reduce(const uint32_t* __restrict__ nch, const uint32_t* __restrict__ chofs,
-                               uint64_t nH, const float* __restrict__ chT,
+                               const uint32_t* __restrict__ nHdev, const float* __restrict__ chT,
                                const double* __restrict__ chM, float* __restrict__ hT,
                                double* __restrict__ hM) {
+  const uint64_t nH = *nHdev;
   GRID_STRIDE(i, nH * 28) {
     const uint64_t h = i / 28;
     const int k = (int)(i % 28);
@@ -1175,6 +1178,14 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   h->mass_scalar = p.mass_scalar;
   const uint64_t n = p.n;
 
+  if (!ctx->host_cnt) {
+    void* hp = nullptr;
+    HIP_CHECK(hipHostMalloc(&hp, 64, hipHostMallocDefault));
+    ctx->host_cnt = static_cast<uint32_t*>(hp);
+    HIP_CHECK(hipEventCreateWithFlags(&ctx->cnt_ev, hipEventDisableTiming));
+    for (auto& e : ctx->phase_ev) HIP_CHECK(hipEventCreate(&e));
+  }
+  HIP_CHECK(hipEventRecord(ctx->phase_ev[0], st));
   uint32_t* dev_u32 = ws.get<uint32_t>(8);   // [0] error flags, [1..] counters
   double* dev_tot = ws.get<double>(3 * kMaxLevels);
   HIP_CHECK(hipMemsetAsync(dev_u32, 0, 8 * sizeof(uint32_t), st));
@@ -1206,8 +1217,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
 
   Parts P;
   P.rec = srec;
-  HIP_CHECK(hipStreamSynchronize(st));
-  const double t1 = now_ms();
+  HIP_CHECK(hipEventRecord(ctx->phase_ev[1], st));
 
   // ---- levels
   uint64_t nFp = 1ull << (3 * (g - 1));  // parents of level 0: the virtual level -1
@@ -1294,44 +1304,36 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
                   (k_mark<<<mb, kT, 0, st>>>(L, b, dev_u32 + 1, Ftmp, lv.Skey, tree, mark, err)));
       }
       compact_flags(ws, mark, nslot, nullptr, rank, dev_u32 + 4, st);
-    } else {
-      HIP_CHECK(hipMemsetAsync(dev_u32 + 4, 0, sizeof(uint32_t), st));
     }
-    uint32_t cnts[4];
-    HIP_CHECK(hipMemcpyAsync(cnts, dev_u32 + 1, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    lv.nF = cnts[0];
-    const uint64_t nH = cnts[1];
-    const uint32_t nD = cnts[3];
-    lv.Fs = h->mem.get<uint32_t>(lv.nF);  // filled from Ftmp by k_pbrick below
-    if (lv.nF == 0 && lv.slot_f) {
-      h->mem.drop(lv.slot_f);
-      lv.slot_f = nullptr;
-    }
+    // the counts travel to the host while the level's deposit runs
+    HIP_CHECK(hipMemcpyAsync(ctx->host_cnt, dev_u32 + 1, 4 * sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipEventRecord(ctx->cnt_ev, st));
 
     const uint32_t mask = (1u << (kQBits - b)) - 1u;
     const float scale = std::ldexp(1.0f, -(kQBits - b));
 
-    // heavy cells: chunked block sums
-    float* hT = nullptr;
-    double* hM = nullptr;
-    if (nH > 0) {
-      uint32_t* nch = ws.get<uint32_t>(nH);
-      uint32_t* chofs = ws.get<uint32_t>(nH);
-      const uint64_t maxch = nH + n / kChunk + 1;
+    // heavy cells: chunked wave sums (sizes from the device counts; buffers
+    // and grids from the bound maxH)
+    float* hT = ws.get<float>(maxH * 27);
+    double* hM = ws.get<double>(maxH);
+    {
+      uint32_t* nch = ws.get<uint32_t>(maxH);
+      uint32_t* chofs = ws.get<uint32_t>(maxH);
+      const uint64_t maxch = maxH + n / kChunk + 1;
       uint32_t* ch_h = ws.get<uint32_t>(maxch);
       uint32_t* ch_j = ws.get<uint32_t>(maxch);
-      k_chunk_list<<<grid_for(nH), kT, 0, st>>>(Hs, nH, lv.Scount, dev_u32 + 3, nch, chofs, ch_h,
-                                                ch_j);
-      HIP_LAUNCH_CHECK();
       float* chT = ws.get<float>(maxch * 27);
       double* chM = ws.get<double>(maxch);
-      hT = ws.get<float>(nH * 27);
-      hM = ws.get<double>(nH);
+      k_chunk_list<<<std::min(grid_for(maxH), 1024u), kT, 0, st>>>(Hs, dev_u32 + 2, lv.Scount,
+                                                                   dev_u32 + 3, nch, chofs, ch_h,
+                                                                   ch_j);
+      HIP_LAUNCH_CHECK();
       AHF_TIMED(ctx, "heavy_chunk", st,
-                (k_heavy_chunk<<<(unsigned)((maxch + 3) / 4), 256, 0, st>>>(
+                (k_heavy_chunk<<<(unsigned)std::min<uint64_t>((maxch + 3) / 4, 2048), 256, 0, st>>>(
                     dev_u32 + 3, ch_h, ch_j, Hs, lv.Sstart, lv.Scount, P, mask, scale, chT, chM)));
-      k_heavy_reduce<<<grid_for(nH * 28), kT, 0, st>>>(nch, chofs, nH, chT, chM, hT, hM);
+      k_heavy_reduce<<<std::min(grid_for(maxH * 28), 1024u), kT, 0, st>>>(nch, chofs, dev_u32 + 2,
+                                                                          chT, chM, hT, hM);
       HIP_LAUNCH_CHECK();
     }
 
@@ -1384,6 +1386,14 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       HIP_LAUNCH_CHECK();
     }
 
+    HIP_CHECK(hipEventSynchronize(ctx->cnt_ev));
+    lv.nF = ctx->host_cnt[0];
+    const uint32_t nD = can_refine ? ctx->host_cnt[3] : 0u;
+    lv.Fs = h->mem.get<uint32_t>(lv.nF);  // filled from Ftmp by k_pbrick below
+    if (lv.nF == 0 && lv.slot_f) {
+      h->mem.drop(lv.slot_f);
+      lv.slot_f = nullptr;
+    }
     if (lv.nF == 0) {
       ws.release(lvl_mark);
       break;
@@ -1412,6 +1422,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   const size_t nl = h->lev.size();
   std::vector<double> tot(3 * kMaxLevels);
   uint32_t herr = 0;
+  HIP_CHECK(hipEventRecord(ctx->phase_ev[2], st));
   HIP_CHECK(hipMemcpyAsync(tot.data(), dev_tot, 3 * kMaxLevels * sizeof(double),
                            hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -1421,12 +1432,13 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     h->lev[L].nP = (uint64_t)tot[3 * L + 2];
     h->lev[L].tot_part = p.mass ? tot[3 * L + 1] : (double)h->lev[L].nP * p.mass_scalar;
   }
-  const double t2 = now_ms();
-  h->ms[0] = t1 - t0;
-  h->ms[1] = t2 - t1;
-  h->ms[3] = t2 - t0;
+  float e01 = 0.0f, e12 = 0.0f;
+  HIP_CHECK(hipEventElapsedTime(&e01, ctx->phase_ev[0], ctx->phase_ev[1]));
+  HIP_CHECK(hipEventElapsedTime(&e12, ctx->phase_ev[1], ctx->phase_ev[2]));
+  h->ms[0] = e01;
+  h->ms[1] = e12;
+  h->ms[3] = now_ms() - t0;
   if (herr & kErrCoord) throw Error{AHF_EINVAL, "a particle coordinate is >= 2^21"};
-  if (herr & kErrSpin) throw Error{AHF_EDEVICE, "a look-back wait gave up (sort or scan)"};
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed on the device"};
 }
 
@@ -1512,7 +1524,6 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
   HIP_CHECK(hipMemcpyAsync(hv.data(), dev, (4 + nlev) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   const uint32_t herr = hv[0];
-  if (herr & kErrSpin) throw Error{AHF_EDEVICE, "scan look-back gave up waiting"};
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed while labelling"};
   for (size_t L = 1; L < nlev; ++L) h->lev[L].nPatch = hv[4 + L];
   h->labelled = true;
