@@ -303,8 +303,13 @@ ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, con
     h->h.mem.st = st;
     ctx->ws.bind(&ctx->c, st);
     ctx->ws.reset();
-    build_hierarchy(&ctx->c, ctx->ws, *particles, prm, st, &h->h);
-    if (!(prm.flags & AHF_NO_LABELS)) label_hierarchy(&ctx->c, ctx->ws, &h->h, st);
+    // with equal masses the labels need nothing from the build's totals: they
+    // are enqueued behind it, and one wait at the end covers both
+    const bool labels = !(prm.flags & AHF_NO_LABELS);
+    const bool defer = labels && particles->mass == nullptr;
+    build_hierarchy(&ctx->c, ctx->ws, *particles, prm, st, &h->h, !defer);
+    if (labels) label_hierarchy(&ctx->c, ctx->ws, &h->h, st);
+    if (defer) finish_build(&ctx->c, &h->h);
     ctx->ws.reset();
   } catch (const Error& e) {
     (void)hipStreamSynchronize(st);

@@ -61,6 +61,7 @@ struct Ctx {
   // per-level counts read back while the level's deposit runs: pinned host
   // words, an event behind their copy, and events that time the build phases
   uint32_t* host_cnt = nullptr;
+  double* host_tot = nullptr;  // level totals and the error word (same allocation)
   hipEvent_t cnt_ev = nullptr;
   hipEvent_t phase_ev[3] = {nullptr, nullptr, nullptr};
 };
@@ -209,10 +210,15 @@ struct Hier {
   bool labelled = false;
   std::vector<Level> lev;
   double ms[4] = {0, 0, 0, 0};
+  double t_start = 0.0;  // host clock at the start of the build
 };
 
+// Enqueues the build on st.  With finish, waits for it and completes h
+// (totals, timings, device error flags); without, the caller must call
+// finish_build once the stream has passed the build (labels may run first).
 void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm, hipStream_t st,
-                     Hier* h);
+                     Hier* h, bool finish = true);
+void finish_build(Ctx* ctx, Hier* h);
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
 // patch ids of level-L cells given by key (host arrays); level >= 1, labelled
 void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys_host,

@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 
 #include "ahf_internal.h"
 
@@ -1167,7 +1168,7 @@ static Tree make_tree(const Hier* h) {
 }
 
 void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm, hipStream_t st,
-                     Hier* h) {
+                     Hier* h, bool finish) {
   const double t0 = now_ms();
   h->prm = prm;
   h->n = p.n;
@@ -1180,8 +1181,9 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
 
   if (!ctx->host_cnt) {
     void* hp = nullptr;
-    HIP_CHECK(hipHostMalloc(&hp, 64, hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc(&hp, 4096, hipHostMallocDefault));
     ctx->host_cnt = static_cast<uint32_t*>(hp);
+    ctx->host_tot = reinterpret_cast<double*>(static_cast<char*>(hp) + 256);
     HIP_CHECK(hipEventCreateWithFlags(&ctx->cnt_ev, hipEventDisableTiming));
     for (auto& e : ctx->phase_ev) HIP_CHECK(hipEventCreate(&e));
   }
@@ -1418,26 +1420,35 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     ws.release(lvl_mark);
   }
 
-  // totals and the device error flags
-  const size_t nl = h->lev.size();
-  std::vector<double> tot(3 * kMaxLevels);
-  uint32_t herr = 0;
+  // totals and the device error flags, into pinned memory; read by
+  // finish_build once the stream has passed this point
   HIP_CHECK(hipEventRecord(ctx->phase_ev[2], st));
-  HIP_CHECK(hipMemcpyAsync(tot.data(), dev_tot, 3 * kMaxLevels * sizeof(double),
+  HIP_CHECK(hipMemcpyAsync(ctx->host_tot, dev_tot, 3 * kMaxLevels * sizeof(double),
                            hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipStreamSynchronize(st));
-  for (size_t L = 0; L < nl; ++L) {
+  HIP_CHECK(hipMemcpyAsync(ctx->host_tot + 3 * kMaxLevels, err, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, st));
+  h->t_start = t0;
+  if (finish) {
+    HIP_CHECK(hipStreamSynchronize(st));
+    finish_build(ctx, h);
+  }
+}
+
+void finish_build(Ctx* ctx, Hier* h) {
+  const double* tot = ctx->host_tot;
+  uint32_t herr = 0;
+  std::memcpy(&herr, ctx->host_tot + 3 * kMaxLevels, sizeof(uint32_t));
+  for (size_t L = 0; L < h->lev.size(); ++L) {
     h->lev[L].tot_cell = tot[3 * L + 0];
     h->lev[L].nP = (uint64_t)tot[3 * L + 2];
-    h->lev[L].tot_part = p.mass ? tot[3 * L + 1] : (double)h->lev[L].nP * p.mass_scalar;
+    h->lev[L].tot_part = h->has_mass ? tot[3 * L + 1] : (double)h->lev[L].nP * h->mass_scalar;
   }
   float e01 = 0.0f, e12 = 0.0f;
   HIP_CHECK(hipEventElapsedTime(&e01, ctx->phase_ev[0], ctx->phase_ev[1]));
   HIP_CHECK(hipEventElapsedTime(&e12, ctx->phase_ev[1], ctx->phase_ev[2]));
   h->ms[0] = e01;
   h->ms[1] = e12;
-  h->ms[3] = now_ms() - t0;
+  h->ms[3] = now_ms() - h->t_start;
   if (herr & kErrCoord) throw Error{AHF_EINVAL, "a particle coordinate is >= 2^21"};
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed on the device"};
 }
