@@ -55,11 +55,19 @@ __global__ void k_fill_i32(int32_t* a, uint64_t n, int32_t v) {
   GRID_STRIDE(i, n) a[i] = v;
 }
 
-// slot -> F index starts at -1, dilation marks (when given) at 0
-__global__ void k_clear_slots(int32_t* __restrict__ slot_f, uint8_t* __restrict__ mark,
-                              uint64_t nslot) {
+// slot -> F index of the refined cell in it (-1 for other cells and ghost
+// slots); the cell in slot i of brick i/8 is Bcell[i/8] + i%8 (level 0: i);
+// also clears the dilation marks when given
+__global__ void k_slots(uint64_t nslot, const int32_t* __restrict__ Bcell,
+                        const uint8_t* __restrict__ flag, const uint32_t* __restrict__ rankF,
+                        int32_t* __restrict__ slot_f, uint8_t* __restrict__ mark) {
   GRID_STRIDE(i, nslot) {
-    slot_f[i] = -1;
+    int64_t s = (int64_t)i;
+    if (Bcell) {
+      const int32_t c0 = Bcell[i >> 3];
+      s = c0 >= 0 ? (int64_t)c0 + (int64_t)(i & 7) : -1;
+    }
+    slot_f[i] = (s >= 0 && flag[s]) ? (int32_t)rankF[s] : -1;
     if (mark) mark[i] = 0;
   }
 }
@@ -178,12 +186,24 @@ __global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
 
 // refinement flags; cells too full for one thread are appended to Hs (in no
 // particular order: the list only routes each such cell to its own sums)
+// Heavy cells: every cell above kHeavy particles takes an index h (in no
+// particular order: h only routes the cell to its own sums) and a contiguous
+// run of chunk slots, whose chunks are later summed in the order of their
+// index j inside that run.  The two counters start at zero.
+struct HeavyList {
+  uint32_t* nheavy;   // number of heavy cells
+  uint32_t* nchunks;  // number of chunks
+  uint32_t* Hs;       // cell of heavy index h
+  int32_t* hidx;      // heavy index of a heavy cell
+  uint32_t* nch;      // chunks of heavy cell h
+  uint32_t* chofs;    // first chunk slot of heavy cell h
+  uint32_t* ch_h;     // heavy cell of a chunk slot
+  uint32_t* ch_j;     // chunk index within its cell
+};
+
 __global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double thr,
-                        int can_refine, uint8_t* __restrict__ flag,
-                        uint32_t* __restrict__ nheavy, uint32_t* __restrict__ Hs,
-                        int32_t* __restrict__ hidx, uint32_t* __restrict__ clear,
+                        int can_refine, uint8_t* __restrict__ flag, HeavyList hl,
                         uint32_t* __restrict__ rank_unset) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *clear = 0u;
   GRID_STRIDE(s, nS) {
     const uint32_t c = count[s];
     const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
@@ -191,9 +211,17 @@ __global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double 
     // the compaction fills in the rank of the refined cells
     if (rank_unset && !f) rank_unset[s] = 0xffffffffu;
     if (c > (uint32_t)kHeavy) {
-      const uint32_t h = atomicAdd(nheavy, 1u);
-      Hs[h] = (uint32_t)s;
-      hidx[s] = (int32_t)h;
+      const uint32_t h = atomicAdd(hl.nheavy, 1u);
+      const uint32_t m = (c + kChunk - 1) / kChunk;
+      const uint32_t o = atomicAdd(hl.nchunks, m);
+      hl.Hs[h] = (uint32_t)s;
+      hl.hidx[s] = (int32_t)h;
+      hl.nch[h] = m;
+      hl.chofs[h] = o;
+      for (uint32_t j = 0; j < m; ++j) {
+        hl.ch_h[o + j] = h;
+        hl.ch_j[o + j] = j;
+      }
     }
   }
 }
@@ -262,24 +290,6 @@ __device__ inline void add_range(const Parts& P, uint32_t a, uint32_t n, uint32_
 
 // ------------------------------------------------------------ heavy cells
 
-// every heavy cell takes a contiguous run of chunk slots; its chunks are
-// later summed in the order of their index j inside that run
-__global__ void k_chunk_list(const uint32_t* __restrict__ Hs, const uint32_t* __restrict__ nHdev,
-                             const uint32_t* __restrict__ Scount, uint32_t* __restrict__ nchunks,
-                             uint32_t* __restrict__ nch, uint32_t* __restrict__ chofs,
-                             uint32_t* __restrict__ ch_h, uint32_t* __restrict__ ch_j) {
-  const uint64_t nH = *nHdev;
-  GRID_STRIDE(h, nH) {
-    const uint32_t m = (Scount[Hs[h]] + kChunk - 1) / kChunk;
-    const uint32_t o = atomicAdd(nchunks, m);
-    nch[h] = m;
-    chofs[h] = o;
-    for (uint32_t j = 0; j < m; ++j) {
-      ch_h[o + j] = (uint32_t)h;
-      ch_j[o + j] = j;
-    }
-  }
-}
 
 // one wave per chunk of <= kChunk particles of one heavy cell (4 chunks per
 // block of 256 threads); every lane sums at most kChunk/64 = 64 particles,
@@ -684,9 +694,18 @@ __global__ __launch_bounds__(256) void k_level_sums(const float* __restrict__ a,
   }
 }
 
-__global__ __launch_bounds__(256) void k_level_sums_final(const double* __restrict__ part, int np,
-                                                          double* __restrict__ out) {
+constexpr int kSumBlocks = 2048;
+struct SumBlocks {
+  int n[kMaxLevels];
+};
+
+// block L adds the partial sums of level L in block order
+__global__ __launch_bounds__(256) void k_level_sums_final(const double* __restrict__ part_all,
+                                                          SumBlocks nb, double* __restrict__ out_all) {
   __shared__ double lds[3][4];
+  const int np = nb.n[blockIdx.x];
+  const double* part = part_all + (uint64_t)blockIdx.x * 3 * kSumBlocks;
+  double* out = out_all + 3 * blockIdx.x;
   double s[3] = {0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < np; i += 256) {
 #pragma unroll
@@ -713,12 +732,6 @@ __device__ inline uint64_t slot_of_s(uint64_t s, const int32_t* Pbrick) {
   return Pbrick ? (uint64_t)Pbrick[s >> 3] * 8 + (s & 7) : s;
 }
 
-// slot of every refined cell -> its index in F_L
-__global__ void k_slot_f(uint64_t nS, const uint8_t* __restrict__ flag,
-                         const uint32_t* __restrict__ rankF, const int32_t* __restrict__ Pbrick,
-                         int32_t* __restrict__ slot_f) {
-  GRID_STRIDE(s, nS) if (flag[s]) slot_f[slot_of_s(s, Pbrick)] = (int32_t)rankF[s];
-}
 
 // level 0 is dense: a cell is in the dilation when one of its 27 neighbours
 // (itself included) is refined
@@ -756,13 +769,19 @@ __global__ void k_mark(int L, int bits, const uint32_t* __restrict__ nFdev,
   }
 }
 
+// next level's bricks (one per marked slot, in key order by rank); a refined
+// cell's slot is always marked, so its F entry is finished here too: its
+// children's brick, and F_L moved to its final buffer.  Also clears the
+// heavy-cell counters for the next level.
 __global__ void k_build_bricks(uint64_t nslot, const uint8_t* __restrict__ mark,
                                const uint32_t* __restrict__ rank,
                                const uint64_t* __restrict__ Bkey,
                                const int32_t* __restrict__ slot_f,
                                int32_t* __restrict__ slot_child, uint64_t* __restrict__ nBkey,
-                               int32_t* __restrict__ nBcell, uint32_t* __restrict__ clear) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *clear = 0u;
+                               int32_t* __restrict__ nBcell, const uint32_t* __restrict__ Ftmp,
+                               uint32_t* __restrict__ Fs, int32_t* __restrict__ nPbrick,
+                               uint32_t* __restrict__ clear2) {
+  if (blockIdx.x == 0 && threadIdx.x < 2) clear2[threadIdx.x] = 0u;
   GRID_STRIDE(i, nslot) {
     if (mark[i]) {
       const uint32_t r = rank[i];
@@ -770,22 +789,16 @@ __global__ void k_build_bricks(uint64_t nslot, const uint8_t* __restrict__ mark,
       nBkey[r] = Bkey ? ((Bkey[i >> 3] << 3) | (i & 7)) : i;
       const int32_t f = slot_f[i];
       nBcell[r] = f >= 0 ? f * 8 : -1;
+      if (f >= 0) {
+        Fs[f] = Ftmp[f];
+        nPbrick[f] = (int32_t)r;
+      }
     } else {
       slot_child[i] = -1;
     }
   }
 }
 
-// brick of every refined cell's children; also moves F_L to its final buffer
-__global__ void k_pbrick(uint64_t nF, const uint32_t* __restrict__ Ftmp,
-                         const int32_t* __restrict__ Pbrick, const int32_t* __restrict__ slot_child,
-                         int32_t* __restrict__ nPbrick, uint32_t* __restrict__ Fs) {
-  GRID_STRIDE(f, nF) {
-    const uint32_t s = Ftmp[f];
-    Fs[f] = s;
-    nPbrick[f] = slot_child[slot_of_s(s, Pbrick)];
-  }
-}
 
 // ------------------------------------------------------------ labels
 
@@ -1230,6 +1243,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   h->lev.clear();
   h->lev.reserve(kMaxLevels);
   uint32_t* rank0 = nullptr;  // rank of each refined level-0 cell in F_0 (dense tiles)
+  double* part_all = ws.get<double>((uint64_t)kMaxLevels * 3 * kSumBlocks);
+  SumBlocks sum_blocks;
   for (int L = 0; L <= prm.Lmax; ++L) {
     h->lev.emplace_back();
     Level& lv = h->lev.back();
@@ -1268,13 +1283,21 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     // refinement flags and the cells too full for one thread
     const int can_refine = (L < prm.Lmax && b < kQBits) ? 1 : 0;
     const double thr = (L == 0) ? prm.dom_ref : prm.ref_ref;
+    // heavy-cell lists, sized by bounds: at most n/65 cells above 64
+    // particles, at most that many plus n/4096 chunks
     const uint64_t maxH = std::min<uint64_t>(lv.nS, n / (kHeavy + 1) + 1);
-    uint32_t* Hs = ws.get<uint32_t>(maxH);
-    int32_t* hidx = ws.get<int32_t>(lv.nS);  // read only for cells above kHeavy
-    // dev_u32[2] (heavy cells) is zero here: cleared at the start and by
-    // k_build_bricks of the previous level; k_flags clears dev_u32[3]
-    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag,
-                                            dev_u32 + 2, Hs, hidx, dev_u32 + 3,
+    const uint64_t maxch = maxH + n / kChunk + 1;
+    HeavyList hl;
+    hl.nheavy = dev_u32 + 2;  // both counters are zero here: cleared at the start
+    hl.nchunks = dev_u32 + 3; // and by k_build_bricks of the previous level
+    hl.Hs = ws.get<uint32_t>(maxH);
+    hl.hidx = ws.get<int32_t>(lv.nS);  // read only for cells above kHeavy
+    hl.nch = ws.get<uint32_t>(maxH);
+    hl.chofs = ws.get<uint32_t>(maxH);
+    hl.ch_h = ws.get<uint32_t>(maxch);
+    hl.ch_j = ws.get<uint32_t>(maxch);
+    const int32_t* hidx = hl.hidx;
+    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag, hl,
                                             (L == 0) ? rank0 : nullptr);
     HIP_LAUNCH_CHECK();
     uint32_t* Ftmp = ws.get<uint32_t>(lv.nS);
@@ -1291,9 +1314,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       lv.slot_f = h->mem.get<int32_t>(nslot);
       mark = ws.get<uint8_t>(nslot);
       rank = ws.get<uint32_t>(nslot);
-      k_clear_slots<<<grid_for(nslot), kT, 0, st>>>(lv.slot_f, L == 0 ? nullptr : mark, nslot);
-      HIP_LAUNCH_CHECK();
-      k_slot_f<<<grid_for(lv.nS), kT, 0, st>>>(lv.nS, lv.Sflag, rankF, lv.Pbrick, lv.slot_f);
+      k_slots<<<grid_for(nslot), kT, 0, st>>>(nslot, L == 0 ? nullptr : lv.Bcell, lv.Sflag, rankF,
+                                              lv.slot_f, L == 0 ? nullptr : mark);
       HIP_LAUNCH_CHECK();
       if (L == 0) {
         AHF_TIMED(ctx, "mark", st,
@@ -1320,22 +1342,14 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     float* hT = ws.get<float>(maxH * 27);
     double* hM = ws.get<double>(maxH);
     {
-      uint32_t* nch = ws.get<uint32_t>(maxH);
-      uint32_t* chofs = ws.get<uint32_t>(maxH);
-      const uint64_t maxch = maxH + n / kChunk + 1;
-      uint32_t* ch_h = ws.get<uint32_t>(maxch);
-      uint32_t* ch_j = ws.get<uint32_t>(maxch);
       float* chT = ws.get<float>(maxch * 27);
       double* chM = ws.get<double>(maxch);
-      k_chunk_list<<<std::min(grid_for(maxH), 1024u), kT, 0, st>>>(Hs, dev_u32 + 2, lv.Scount,
-                                                                   dev_u32 + 3, nch, chofs, ch_h,
-                                                                   ch_j);
-      HIP_LAUNCH_CHECK();
       AHF_TIMED(ctx, "heavy_chunk", st,
                 (k_heavy_chunk<<<(unsigned)std::min<uint64_t>((maxch + 3) / 4, 2048), 256, 0, st>>>(
-                    dev_u32 + 3, ch_h, ch_j, Hs, lv.Sstart, lv.Scount, P, mask, scale, chT, chM)));
-      k_heavy_reduce<<<std::min(grid_for(maxH * 28), 1024u), kT, 0, st>>>(nch, chofs, dev_u32 + 2,
-                                                                          chT, chM, hT, hM);
+                    hl.nchunks, hl.ch_h, hl.ch_j, hl.Hs, lv.Sstart, lv.Scount, P, mask, scale, chT,
+                    chM)));
+      k_heavy_reduce<<<std::min(grid_for(maxH * 28), 1024u), kT, 0, st>>>(
+          hl.nch, hl.chofs, hl.nheavy, chT, chM, hT, hM);
       HIP_LAUNCH_CHECK();
     }
 
@@ -1379,19 +1393,18 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     {
       const uint64_t nmax = (8 * nB > lv.nS) ? 8 * nB : lv.nS;
       int nblk = (int)((nmax + 255) / 256);
-      if (nblk > 2048) nblk = 2048;
+      if (nblk > kSumBlocks) nblk = kSumBlocks;
       if (nblk < 1) nblk = 1;
-      double* part = ws.get<double>(3 * (uint64_t)nblk);
-      k_level_sums<<<nblk, 256, 0, st>>>(lv.mass, 8 * nB, lv.Spmass, lv.nS, lv.Scount, lv.nS, part);
+      k_level_sums<<<nblk, 256, 0, st>>>(lv.mass, 8 * nB, lv.Spmass, lv.nS, lv.Scount, lv.nS,
+                                         part_all + (uint64_t)L * 3 * kSumBlocks);
       HIP_LAUNCH_CHECK();
-      k_level_sums_final<<<1, 256, 0, st>>>(part, nblk, dev_tot + 3 * L);
-      HIP_LAUNCH_CHECK();
+      sum_blocks.n[L] = nblk;
     }
 
     HIP_CHECK(hipEventSynchronize(ctx->cnt_ev));
     lv.nF = ctx->host_cnt[0];
     const uint32_t nD = can_refine ? ctx->host_cnt[3] : 0u;
-    lv.Fs = h->mem.get<uint32_t>(lv.nF);  // filled from Ftmp by k_pbrick below
+    lv.Fs = h->mem.get<uint32_t>(lv.nF);  // filled from Ftmp by k_build_bricks below
     if (lv.nF == 0 && lv.slot_f) {
       h->mem.drop(lv.slot_f);
       lv.slot_f = nullptr;
@@ -1405,12 +1418,10 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     lv.slot_child = h->mem.get<int32_t>(nslot);
     uint64_t* nBkey = h->mem.get<uint64_t>(nD);
     int32_t* nBcell = h->mem.get<int32_t>(nD);
-    k_build_bricks<<<grid_for(nslot), kT, 0, st>>>(nslot, mark, rank, lv.Bkey, lv.slot_f,
-                                                   lv.slot_child, nBkey, nBcell, dev_u32 + 2);
-    HIP_LAUNCH_CHECK();
     int32_t* nPbrick = h->mem.get<int32_t>(lv.nF);
-    k_pbrick<<<grid_for(lv.nF), kT, 0, st>>>(lv.nF, Ftmp, lv.Pbrick, lv.slot_child, nPbrick,
-                                             lv.Fs);
+    k_build_bricks<<<grid_for(nslot), kT, 0, st>>>(nslot, mark, rank, lv.Bkey, lv.slot_f,
+                                                   lv.slot_child, nBkey, nBcell, Ftmp, lv.Fs,
+                                                   nPbrick, dev_u32 + 2);
     HIP_LAUNCH_CHECK();
     nFp = lv.nF;
     nB = nD;
@@ -1419,6 +1430,10 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     Pbrick = nPbrick;
     ws.release(lvl_mark);
   }
+
+  // every level's totals from its partial sums, one block per level
+  k_level_sums_final<<<(unsigned)h->lev.size(), 256, 0, st>>>(part_all, sum_blocks, dev_tot);
+  HIP_LAUNCH_CHECK();
 
   // totals and the device error flags, into pinned memory; read by
   // finish_build once the stream has passed this point
