@@ -185,6 +185,10 @@ void ahf_hierarchy_free(ahf_hierarchy *h);
  * the events of finished builds.
  */
 ahf_status ahf_ctx_set_profiling(ahf_ctx *ctx, int enable);
+/* Restricts the timing to the listed kernel names (comma-separated, e.g.
+ * "rs_scatter,gather"), so that the events cost nothing elsewhere; NULL or ""
+ * times every name again.  Takes effect for launches made afterwards. */
+ahf_status ahf_ctx_profile_only(ahf_ctx *ctx, const char *names);
 ahf_status ahf_ctx_kernel_time(ahf_ctx *ctx, const char *kernel, uint64_t *launches,
                                double *total_ms);
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "ahf_last_error", "ahf_ctx_create", "ahf_ctx_destroy", "ahf_build_hierarchy",
     "ahf_label_refinements", "ahf_hierarchy_num_levels", "ahf_level_get",
     "ahf_hierarchy_order", "ahf_hierarchy_timings", "ahf_hierarchy_free",
-    "ahf_ctx_set_profiling", "ahf_ctx_kernel_time", "ahf_hierarchy_query_label",
+    "ahf_ctx_set_profiling", "ahf_ctx_profile_only", "ahf_ctx_kernel_time", "ahf_hierarchy_query_label",
     "ahf_server_create", "ahf_submit", "ahf_poll", "ahf_wait", "ahf_query_label",
     "ahf_release", "ahf_ticket_times", "ahf_server_get_stats", "ahf_server_destroy",
 ]
@@ -106,6 +106,7 @@ def load():
     L.ahf_hierarchy_timings.argtypes = [vp, C.POINTER(C.c_double), C.c_uint32]
     L.ahf_ctx_set_profiling.argtypes = [vp, C.c_int]
     L.ahf_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
+    L.ahf_ctx_profile_only.argtypes = [vp, C.c_char_p]
     L.ahf_hierarchy_free.argtypes = [vp]
     L.ahf_hierarchy_free.restype = None
     L.ahf_hierarchy_query_label.argtypes = [vp, vp, C.c_uint32, C.c_uint64, vp, vp, vp]
@@ -201,6 +202,10 @@ class Context:
 
     def set_profiling(self, on: bool):
         _check(load().ahf_ctx_set_profiling(self._h, 1 if on else 0))
+
+    def profile_only(self, names):
+        """Time only these kernel names (a list; None or [] = all)."""
+        _check(load().ahf_ctx_profile_only(self._h, ",".join(names or []).encode()))
 
     def kernel_time(self, name: str):
         """(launches, total device ms) of one kernel while profiling."""

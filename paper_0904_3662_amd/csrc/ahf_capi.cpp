@@ -431,8 +431,33 @@ ahf_status ahf_ctx_set_profiling(ahf_ctx* ctx, int enable) {
     HIP_CHECK(hipSetDevice(ctx->c.device));
     ctx->c.prof.clear();
     ctx->c.prof.on = enable != 0;
+    // events for a few builds up front: creating them between launches
+    // would slow the builds being timed
+    while (enable && ctx->c.prof.spare.size() < 2048) {
+      hipEvent_t e = nullptr;
+      HIP_CHECK(hipEventCreate(&e));
+      ctx->c.prof.spare.push_back(e);
+    }
   } catch (const Error& e) {
     return fail(e.code, e.msg);
+  }
+  return AHF_OK;
+}
+
+ahf_status ahf_ctx_profile_only(ahf_ctx* ctx, const char* names) {
+  if (!ctx) return fail(AHF_EINVAL, "ctx is NULL");
+  ctx->c.prof.only.clear();
+  if (names) {
+    std::string cur;
+    for (const char* p = names;; ++p) {
+      if (*p == ',' || *p == 0) {
+        if (!cur.empty()) ctx->c.prof.only.push_back(cur);
+        cur.clear();
+        if (*p == 0) break;
+      } else {
+        cur.push_back(*p);
+      }
+    }
   }
   return AHF_OK;
 }

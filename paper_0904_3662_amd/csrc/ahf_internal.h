@@ -36,6 +36,13 @@ struct Pool {
 // HIP-event timing of selected kernels (profiling mode of a context)
 struct Prof {
   bool on = false;
+  std::vector<std::string> only;  // names to time; empty = all
+  bool wants(const char* name) const {
+    if (only.empty()) return true;
+    for (auto& n : only)
+      if (n == name) return true;
+    return false;
+  }
   struct Rec {
     std::string name;
     hipEvent_t a, b;
@@ -71,10 +78,11 @@ struct Ctx {
 #define AHF_TIMED(ctxp, name, st, launch)                  \
   do {                                                     \
     hipEvent_t ev_a_ = nullptr;                            \
-    if ((ctxp)->prof.on) (ctxp)->prof.begin(name, st, &ev_a_); \
+    const bool tm_ = (ctxp)->prof.on && (ctxp)->prof.wants(name); \
+    if (tm_) (ctxp)->prof.begin(name, st, &ev_a_);         \
     launch;                                                \
     HIP_LAUNCH_CHECK();                                    \
-    if ((ctxp)->prof.on) (ctxp)->prof.end(name, st, ev_a_);    \
+    if (tm_) (ctxp)->prof.end(name, st, ev_a_);            \
   } while (0)
 
 void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s);  // throws AHF_ENOMEM
