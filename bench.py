@@ -92,7 +92,7 @@ def cpu_baseline(snap, seconds_target=20.0):
     """The FP64 oracle on a bounded random sample of the same workload."""
     import oracle
     rng = np.random.Generator(np.random.PCG64(12345))
-    n = min(snap.n, 1 << 20)
+    n = min(snap.n, 1 << 22)  # about 20 s of single-thread oracle work
     idx = np.sort(rng.choice(snap.n, n, replace=False))
     sub = snap.subset(idx, "sample")
     t0 = time.perf_counter()
@@ -335,6 +335,18 @@ def main():
     ctx.set_profiling(False)
     print(f"# steps done: {args.steps} in {total:.3f} s", file=sys.stderr, flush=True)
 
+    # host/substructure classification of the grid tree (a step after the
+    # labels): wall time of the classification call on built hierarchies
+    cls = []
+    for i in range(3):
+        h = step()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        h.classify(ctx, stream)
+        cls.append((time.perf_counter() - a) * 1e3)
+        nstruct = h.structures()["n_structures"]
+        h.free()
+
     # per-kernel split from two more builds, untimed, with every kernel timed
     names = ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "level0_start", "child_ranges",
              "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross")
@@ -387,6 +399,7 @@ def main():
             "achieved": 84.0 * n / (kstats["gather"][1] / kstats["gather"][0] * 1e-3) / 1e9,
             "frac": 84.0 * n / (kstats["gather"][1] / kstats["gather"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms_per_step": ksplit,
+        "substructure": {"ms": float(np.median(cls)), "structures": int(nstruct)},
         "levels": lv_info,
     }
     if args.copy_probe:

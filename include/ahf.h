@@ -53,6 +53,8 @@ enum {
 
 /* flags of ahf_params */
 #define AHF_NO_LABELS 1u   /* ahf_build_hierarchy skips the grid tree        */
+#define AHF_SUBSTRUCTURE 2u /* ... and classifies it into host structures and
+                                substructures (needs the grid tree)          */
 
 typedef struct ahf_ctx ahf_ctx;
 typedef struct ahf_hierarchy ahf_hierarchy;
@@ -81,7 +83,7 @@ typedef struct {
                                 g + max_levels <= 21                         */
     uint32_t connectivity;   /* 6, 18 or 26 (0 means 26): adjacency of the
                                 isolated refinements                          */
-    uint32_t flags;          /* AHF_NO_LABELS                                 */
+    uint32_t flags;          /* AHF_NO_LABELS, AHF_SUBSTRUCTURE               */
 } ahf_params;
 
 /* Particle snapshot.  All arrays are device pointers of n elements, borrowed:
@@ -129,7 +131,24 @@ typedef struct {
     const double *patch_mass;      /* [n_patches] particle mass in the patch     */
     double total_cell_mass;        /* sum of brick_mass (FP64 sum)               */
     double total_particle_mass;    /* mass of the particles inside S_L (FP64)    */
+    const int32_t *patch_struct;   /* [n_patches] structure of each patch (see
+                                      ahf_hierarchy_structures); NULL before
+                                      classification                           */
 } ahf_level_view;
+
+/* Host structures and substructures of the grid tree (Sect. 2.1 of the
+ * paper: the tree is walked from coarse to fine; where a patch splits, the
+ * child with the most particles continues the parent's structure and the
+ * others start substructures of it, recursively).  Every level-1 patch starts
+ * a host structure; ties go to the lower patch id; structures are numbered by
+ * (start level, start patch).  Device arrays of n_structures entries. */
+typedef struct {
+    uint64_t n_structures;
+    const int32_t *host;   /* structure it branched off, -1 for a host       */
+    const int32_t *level;  /* level of its first (coarsest) patch            */
+    const int32_t *patch;  /* that patch's id on its level                   */
+    const int32_t *depth;  /* 0 host, 1 substructure, 2 sub-substructure ... */
+} ahf_structures;
 
 const char *ahf_last_error(void);
 
@@ -160,6 +179,14 @@ ahf_status ahf_label_refinements(ahf_ctx *ctx, ahf_hierarchy *h, void *stream);
 
 ahf_status ahf_hierarchy_num_levels(const ahf_hierarchy *h, uint32_t *out);
 ahf_status ahf_level_get(const ahf_hierarchy *h, uint32_t level, ahf_level_view *out);
+
+/* Classifies a labelled hierarchy into host structures and substructures
+ * (done by ahf_build_hierarchy when params.flags has AHF_SUBSTRUCTURE).
+ * Returns when it is complete.  AHF_EINVAL if the hierarchy is unlabelled. */
+ahf_status ahf_classify_substructure(ahf_ctx *ctx, ahf_hierarchy *h, void *stream);
+
+/* The structures of a classified hierarchy (AHF_EINVAL before). */
+ahf_status ahf_hierarchy_structures(const ahf_hierarchy *h, ahf_structures *out);
 
 /* Particle order: sorted_idx[i] is the input index of the i-th particle in
  * ascending B-bit Morton key (B = g + max_levels), ties by input index.  The

@@ -19,6 +19,7 @@ AHF_OK, AHF_PENDING = 0, 1
 AHF_EINVAL, AHF_ENOMEM, AHF_EDEVICE, AHF_ELIMIT = -1, -2, -3, -4
 AHF_EBUSY, AHF_ENOTFOUND, AHF_ECANCELED = -5, -6, -7
 AHF_NO_LABELS = 1
+AHF_SUBSTRUCTURE = 2
 
 # every symbol declared in include/ahf.h
 EXPORTS = [
@@ -28,6 +29,7 @@ EXPORTS = [
     "ahf_ctx_set_profiling", "ahf_ctx_profile_only", "ahf_ctx_kernel_time", "ahf_hierarchy_query_label",
     "ahf_server_create", "ahf_submit", "ahf_poll", "ahf_wait", "ahf_query_label",
     "ahf_release", "ahf_ticket_times", "ahf_server_get_stats", "ahf_server_destroy",
+    "ahf_classify_substructure", "ahf_hierarchy_structures",
 ]
 
 
@@ -64,7 +66,13 @@ class LevelView(C.Structure):
                 ("brick_cell", C.c_void_p), ("brick_mass", C.c_void_p),
                 ("patch_parent", C.c_void_p), ("patch_ncells", C.c_void_p),
                 ("patch_nparticles", C.c_void_p), ("patch_mass", C.c_void_p),
-                ("total_cell_mass", C.c_double), ("total_particle_mass", C.c_double)]
+                ("total_cell_mass", C.c_double), ("total_particle_mass", C.c_double),
+                ("patch_struct", C.c_void_p)]
+
+
+class Structures(C.Structure):
+    _fields_ = [("n_structures", C.c_uint64), ("host", C.c_void_p), ("level", C.c_void_p),
+                ("patch", C.c_void_p), ("depth", C.c_void_p)]
 
 
 class ServerDesc(C.Structure):
@@ -107,6 +115,8 @@ def load():
     L.ahf_ctx_set_profiling.argtypes = [vp, C.c_int]
     L.ahf_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
     L.ahf_ctx_profile_only.argtypes = [vp, C.c_char_p]
+    L.ahf_classify_substructure.argtypes = [vp, vp, vp]
+    L.ahf_hierarchy_structures.argtypes = [vp, C.POINTER(Structures)]
     L.ahf_hierarchy_free.argtypes = [vp]
     L.ahf_hierarchy_free.restype = None
     L.ahf_hierarchy_query_label.argtypes = [vp, vp, C.c_uint32, C.c_uint64, vp, vp, vp]
@@ -296,7 +306,22 @@ class Hierarchy:
         d["patch_ncells"] = to_host(v.patch_ncells, nP, np.uint32)
         d["patch_nparticles"] = to_host(v.patch_nparticles, nP, np.uint64)
         d["patch_mass"] = to_host(v.patch_mass, nP, np.float64)
+        d["patch_struct"] = to_host(v.patch_struct, nP, np.int32)
         return d
+
+    def classify(self, ctx: "Context", stream=None):
+        """Host structures and substructures of the (labelled) grid tree."""
+        _check(load().ahf_classify_substructure(ctx.handle, self._h, _stream_handle(stream)))
+
+    def structures(self) -> dict:
+        s = Structures()
+        _check(load().ahf_hierarchy_structures(self._h, C.byref(s)))
+        n = s.n_structures
+        out = {"n_structures": n}
+        for k in ("host", "level", "patch", "depth"):
+            a = to_host(getattr(s, k), n, np.int32)
+            out[k] = np.zeros(0, np.int32) if a is None else a
+        return out
 
     def label(self, ctx: Context, stream=None):
         _check(load().ahf_label_refinements(ctx.handle, self._h, _stream_handle(stream)))
@@ -327,10 +352,10 @@ class Hierarchy:
 def build_hierarchy(ctx: Context, x, y, z, fx=None, fy=None, fz=None, mass=None, *,
                     g: int, dom_ref: float, ref_ref: float, max_levels: int,
                     connectivity: int = 26, labels: bool = True, mass_scalar: float = 1.0,
-                    stream=None) -> Hierarchy:
+                    substructure: bool = False, stream=None) -> Hierarchy:
     parts = make_particles(x, y, z, fx, fy, fz, mass, mass_scalar)
     prm = make_params(g, dom_ref, ref_ref, max_levels, connectivity,
-                      0 if labels else AHF_NO_LABELS)
+                      _flags(labels, substructure))
     h = C.c_void_p()
     _check(load().ahf_build_hierarchy(ctx.handle, C.byref(parts), C.byref(prm),
                                       _stream_handle(stream), C.byref(h)))
@@ -347,13 +372,18 @@ def snapshot_to_device(s, device="cuda"):
     return X, Y, Z, t(s.fx), t(s.fy), t(s.fz), t(s.mass)
 
 
-def build_snapshot(ctx: Context, s, labels=True, connectivity=26, stream=None, dev=None):
+def build_snapshot(ctx: Context, s, labels=True, connectivity=26, stream=None, dev=None,
+                   substructure=False):
     """Build the hierarchy of a synth.Snapshot (copies it to the device first
     unless `dev` already holds its device tensors)."""
     dev = dev if dev is not None else snapshot_to_device(s)
     return build_hierarchy(ctx, *dev[:6], dev[6], g=s.g, dom_ref=s.dom_ref, ref_ref=s.ref_ref,
                            max_levels=s.max_levels, connectivity=connectivity, labels=labels,
-                           stream=stream), dev
+                           substructure=substructure, stream=stream), dev
+
+
+def _flags(labels, substructure):
+    return (0 if labels else AHF_NO_LABELS) | (AHF_SUBSTRUCTURE if substructure else 0)
 
 
 class Server:
@@ -369,20 +399,22 @@ class Server:
         self._inputs = {}  # ticket -> tensors the build reads
 
     def submit(self, x, y, z, fx=None, fy=None, fz=None, mass=None, *, g, dom_ref, ref_ref,
-               max_levels, connectivity=26, labels=True, mass_scalar=1.0) -> int:
+               max_levels, connectivity=26, labels=True, mass_scalar=1.0,
+               substructure=False) -> int:
         parts = make_particles(x, y, z, fx, fy, fz, mass, mass_scalar)
         prm = make_params(g, dom_ref, ref_ref, max_levels, connectivity,
-                          0 if labels else AHF_NO_LABELS)
+                          _flags(labels, substructure))
         t = C.c_uint64()
         _check(load().ahf_submit(self._h, C.byref(parts), C.byref(prm), C.byref(t)))
         self._inputs[t.value] = (x, y, z, fx, fy, fz, mass)
         return int(t.value)
 
-    def submit_snapshot(self, snap, dev=None, connectivity=26, labels=True) -> int:
+    def submit_snapshot(self, snap, dev=None, connectivity=26, labels=True,
+                        substructure=False) -> int:
         dev = dev if dev is not None else snapshot_to_device(snap)
         return self.submit(*dev[:6], dev[6], g=snap.g, dom_ref=snap.dom_ref,
                            ref_ref=snap.ref_ref, max_levels=snap.max_levels,
-                           connectivity=connectivity, labels=labels)
+                           connectivity=connectivity, labels=labels, substructure=substructure)
 
     def _result(self, rc, ticket, h):
         if rc == AHF_PENDING:

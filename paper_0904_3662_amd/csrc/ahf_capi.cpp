@@ -271,6 +271,8 @@ static ahf_status check_params(const ahf_params* prm, Params* out) {
   out->conn = (int)conn;
   out->dom_ref = prm->dom_ref;
   out->ref_ref = prm->ref_ref;
+  if ((prm->flags & AHF_SUBSTRUCTURE) && (prm->flags & AHF_NO_LABELS))
+    return fail(AHF_EINVAL, "AHF_SUBSTRUCTURE needs the grid tree (not AHF_NO_LABELS)");
   out->flags = prm->flags;
   return AHF_OK;
 }
@@ -384,6 +386,41 @@ ahf_status ahf_level_get(const ahf_hierarchy* h, uint32_t level, ahf_level_view*
   }
   v->total_cell_mass = L.tot_cell;
   v->total_particle_mass = L.tot_part;
+  v->patch_struct = (level >= 1 && h->h.classified) ? L.patch_struct : nullptr;
+  return AHF_OK;
+}
+
+ahf_status ahf_classify_substructure(ahf_ctx* ctx, ahf_hierarchy* h, void* stream) {
+  if (!ctx || !h) return fail(AHF_EINVAL, "ctx and h are required");
+  if (!h->h.labelled) return fail(AHF_EINVAL, "the hierarchy is not labelled");
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    HIP_CHECK(hipSetDevice(ctx->c.device));
+    ctx->ws.bind(&ctx->c, st);
+    ctx->ws.reset();
+    h->h.mem.st = st;
+    classify_hierarchy(&ctx->c, ctx->ws, &h->h, st);
+    ctx->ws.reset();
+  } catch (const Error& e) {
+    (void)hipStreamSynchronize(st);
+    ctx->ws.reset();
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(AHF_ENOMEM, "host allocation failed");
+  }
+  return AHF_OK;
+}
+
+ahf_status ahf_hierarchy_structures(const ahf_hierarchy* h, ahf_structures* out) {
+  if (!out) return fail(AHF_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (!h) return fail(AHF_EINVAL, "h is NULL");
+  if (!h->h.classified) return fail(AHF_EINVAL, "the hierarchy is not classified");
+  out->n_structures = h->h.nStruct;
+  out->host = h->h.s_host;
+  out->level = h->h.s_level;
+  out->patch = h->h.s_patch;
+  out->depth = h->h.s_depth;
   return AHF_OK;
 }
 

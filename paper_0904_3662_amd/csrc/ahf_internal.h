@@ -197,6 +197,7 @@ struct Level {
   uint32_t* patch_ncells = nullptr;
   uint64_t* patch_npart = nullptr;
   double* patch_mass = nullptr;
+  int32_t* patch_struct = nullptr;  // [nPatch] structure of each patch (classified)
   double tot_cell = 0.0, tot_part = 0.0;
 };
 
@@ -216,6 +217,12 @@ struct Hier {
   bool has_mass = false;
   double mass_scalar = 1.0;
   bool labelled = false;
+  uint32_t* npatch_dev = nullptr;  // [kMaxLevels] patch counts on the device (labelled)
+  // host structures and substructures of the grid tree (classified)
+  bool classified = false;
+  uint64_t nStruct = 0;
+  int32_t *s_host = nullptr, *s_level = nullptr, *s_patch = nullptr, *s_depth = nullptr;
+  uint32_t* cls_base = nullptr;  // [kMaxLevels + 1] structures starting up to each level
   std::vector<Level> lev;
   double ms[4] = {0, 0, 0, 0};
   double t_start = 0.0;  // host clock at the start of the build
@@ -228,6 +235,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
                      Hier* h, bool finish = true);
 void finish_build(Ctx* ctx, Hier* h);
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
+// host structures and substructures of a labelled hierarchy (waits for it);
+// classify_levels only enqueues, finish_classify waits and reads the count
+void classify_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
+void classify_levels(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
+void finish_classify(Ctx* ctx, Hier* h, hipStream_t st);
 // patch ids of level-L cells given by key (host arrays); level >= 1, labelled
 void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys_host,
                   int32_t* out_host, hipStream_t st);

@@ -1491,6 +1491,7 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
   const size_t nlev = h->lev.size();
   uint32_t* dev = ws.get<uint32_t>(4 + nlev);
   HIP_CHECK(hipMemsetAsync(dev, 0, (4 + nlev) * sizeof(uint32_t), st));
+  h->npatch_dev = dev + 4;  // copied into the hierarchy below, with the counts
   ctx->dev_err = dev;
   const Tree tree = make_tree(h);
   const double total_mass = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
@@ -1546,15 +1547,160 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     // stream order keeps the released workspace from being reused early
     ws.release(m);
   }
+  uint32_t* keep = h->mem.get<uint32_t>(kMaxLevels);
+  HIP_CHECK(hipMemsetAsync(keep, 0, kMaxLevels * sizeof(uint32_t), st));
+  HIP_CHECK(hipMemcpyAsync(keep, dev + 4, nlev * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  h->npatch_dev = keep;
+  if (h->prm.flags & AHF_SUBSTRUCTURE) classify_levels(ctx, ws, h, st);
   std::vector<uint32_t> hv(4 + nlev);
   HIP_CHECK(hipMemcpyAsync(hv.data(), dev, (4 + nlev) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   const uint32_t herr = hv[0];
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed while labelling"};
   for (size_t L = 1; L < nlev; ++L) h->lev[L].nPatch = hv[4 + L];
+  if (h->prm.flags & AHF_SUBSTRUCTURE) finish_classify(ctx, h, st);
   h->labelled = true;
   h->ms[2] = now_ms() - t0;
   h->ms[3] += h->ms[2];
+}
+
+
+// ------------------------------------------------------------ substructure
+//
+// The grid tree walked from coarse to fine (Sect. 2.1, classification of the
+// grid tree into substructure): every level-1 patch starts a host structure;
+// where a patch has several children, the child with the most particles
+// (ties: the lower patch id) continues the parent's structure and every
+// other child starts a substructure of it.  Structures are numbered by
+// (start level, start patch); base[L] = structures starting on levels <= L.
+
+__global__ void k_struct_roots(const uint32_t* __restrict__ npdev, int32_t* __restrict__ pstruct,
+                               int32_t* __restrict__ s_host, int32_t* __restrict__ s_level,
+                               int32_t* __restrict__ s_patch, int32_t* __restrict__ s_depth,
+                               uint32_t* __restrict__ base) {
+  const uint32_t n = npdev[1];
+  GRID_STRIDE(p, n) {
+    pstruct[p] = (int32_t)p;
+    s_host[p] = -1;
+    s_level[p] = 1;
+    s_patch[p] = (int32_t)p;
+    s_depth[p] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) base[1] = n;
+}
+
+// the main branch of every parent: the largest (count, -id) among its children
+__global__ void k_struct_best(int L, const uint32_t* __restrict__ npdev,
+                              const int32_t* __restrict__ parent,
+                              const uint64_t* __restrict__ npart,
+                              unsigned long long* __restrict__ best) {
+  const uint32_t n = npdev[L];
+  GRID_STRIDE(p, n)
+    atomicMax(&best[parent[p]], (unsigned long long)(npart[p] << 32) | (0xffffffffull - p));
+}
+
+// start flags over the bound nE (0 past the level's patch count)
+__global__ void k_struct_split(int L, uint64_t nE, const uint32_t* __restrict__ npdev,
+                               const int32_t* __restrict__ parent,
+                               const unsigned long long* __restrict__ best,
+                               uint8_t* __restrict__ start) {
+  const uint32_t n = npdev[L];
+  GRID_STRIDE(p, nE)
+    start[p] = (p < n && (best[parent[p]] & 0xffffffffull) != 0xffffffffull - p) ? 1 : 0;
+}
+
+__global__ void k_struct_assign(int L, const uint32_t* __restrict__ npdev,
+                                const int32_t* __restrict__ parent,
+                                const uint8_t* __restrict__ start,
+                                const uint32_t* __restrict__ rank,
+                                const uint32_t* __restrict__ nstart,
+                                const int32_t* __restrict__ ppstruct,
+                                int32_t* __restrict__ pstruct, int32_t* __restrict__ s_host,
+                                int32_t* __restrict__ s_level, int32_t* __restrict__ s_patch,
+                                int32_t* __restrict__ s_depth, uint32_t* __restrict__ base) {
+  const uint32_t n = npdev[L];
+  const uint32_t b = base[L - 1];
+  GRID_STRIDE(p, n) {
+    const int32_t up = ppstruct[parent[p]];
+    if (start[p]) {
+      const uint32_t sid = b + rank[p];
+      pstruct[p] = (int32_t)sid;
+      s_host[sid] = up;
+      s_level[sid] = L;
+      s_patch[sid] = (int32_t)p;
+      s_depth[sid] = s_depth[up] + 1;  // up < b: written on a coarser level
+    } else {
+      pstruct[p] = up;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) base[L] = b + *nstart;
+}
+
+// enqueues the classification of every level (counts stay on the device;
+// arrays are sized by the label pass's bounds)
+void classify_levels(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
+  const size_t nlev = h->lev.size();
+  if (nlev < 2) return;
+  uint64_t bound = 0;
+  for (size_t L = 1; L < nlev; ++L) bound += std::max<uint64_t>(h->lev[L - 1].nF, 1);
+  h->s_host = h->mem.get<int32_t>(bound);
+  h->s_level = h->mem.get<int32_t>(bound);
+  h->s_patch = h->mem.get<int32_t>(bound);
+  h->s_depth = h->mem.get<int32_t>(bound);
+  h->cls_base = h->mem.get<uint32_t>(kMaxLevels + 1);
+  HIP_CHECK(hipMemsetAsync(h->cls_base, 0, (kMaxLevels + 1) * sizeof(uint32_t), st));
+  for (size_t L = 1; L < nlev; ++L) {
+    const uint64_t nE = std::max<uint64_t>(h->lev[L - 1].nF, 1);  // bound on the patches of L
+    h->lev[L].patch_struct = h->mem.get<int32_t>(nE);
+  }
+  k_struct_roots<<<grid_for(h->lev[0].nF), kT, 0, st>>>(
+      h->npatch_dev, h->lev[1].patch_struct, h->s_host, h->s_level, h->s_patch, h->s_depth,
+      h->cls_base);
+  HIP_LAUNCH_CHECK();
+  for (size_t L = 2; L < nlev; ++L) {
+    const uint64_t nE = std::max<uint64_t>(h->lev[L - 1].nF, 1);
+    const uint64_t nEp = std::max<uint64_t>(h->lev[L - 2].nF, 1);  // patches of level L-1
+    Ws::Mark m = ws.mark();
+    unsigned long long* best = ws.get<unsigned long long>(nEp);
+    uint8_t* start = ws.get<uint8_t>(nE);
+    uint32_t* rank = ws.get<uint32_t>(nE);
+    uint32_t* nstart = ws.get<uint32_t>(1);
+    HIP_CHECK(hipMemsetAsync(best, 0, nEp * sizeof(unsigned long long), st));
+    k_struct_best<<<grid_for(nE), kT, 0, st>>>((int)L, h->npatch_dev, h->lev[L].patch_parent,
+                                                h->lev[L].patch_npart, best);
+    HIP_LAUNCH_CHECK();
+    k_struct_split<<<grid_for(nE), kT, 0, st>>>((int)L, nE, h->npatch_dev,
+                                                 h->lev[L].patch_parent, best, start);
+    HIP_LAUNCH_CHECK();
+    compact_flags(ws, start, nE, nullptr, rank, nstart, st);
+    k_struct_assign<<<grid_for(nE), kT, 0, st>>>(
+        (int)L, h->npatch_dev, h->lev[L].patch_parent, start, rank, nstart,
+        h->lev[L - 1].patch_struct, h->lev[L].patch_struct, h->s_host, h->s_level, h->s_patch,
+        h->s_depth, h->cls_base);
+    HIP_LAUNCH_CHECK();
+    ws.release(m);
+  }
+}
+
+// after the stream has passed classify_levels: the number of structures
+void finish_classify(Ctx* ctx, Hier* h, hipStream_t st) {
+  (void)ctx;
+  const size_t nlev = h->lev.size();
+  uint32_t nst = 0;
+  if (nlev >= 2) {
+    HIP_CHECK(hipMemcpyAsync(&nst, h->cls_base + (nlev - 1), sizeof(uint32_t),
+                             hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+  h->nStruct = nst;
+  h->classified = true;
+}
+
+void classify_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
+  if (h->classified) return;
+  if (!h->labelled) throw Error{AHF_EINVAL, "the hierarchy is not labelled"};
+  classify_levels(ctx, ws, h, st);
+  finish_classify(ctx, h, st);
 }
 
 }  // namespace ahf
