@@ -51,7 +51,7 @@ def lib():
         L.orc_build.restype = C.c_int
         L.orc_build.argtypes = [C.c_uint64, _u32p, _u32p, _u32p, _f32p, _f32p, _f32p,
                                 C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_double,
-                                C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
+                                C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_void_p)]
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_num_levels.restype = C.c_int
         L.orc_num_levels.argtypes = [C.c_void_p]
@@ -94,10 +94,11 @@ class Level:
 
 
 def build(p, g=None, dom_ref=None, ref_ref=None, max_levels=None, connectivity=26,
-          labels=True, mass_scalar=1.0):
+          labels=True, mass_scalar=1.0, density=False):
     """Run the oracle on a particle set (anything with X, Y, Z, fx, fy, fz and
     optionally mass attributes; parameters default to the object's own).
-    Returns (levels, order)."""
+    density: refine on the TSC particle number of a cell instead of its
+    particle count.  Returns (levels, order)."""
     L = lib()
     X, Y, Z, fx, fy, fz, m = _arrays(p)
     g = p.g if g is None else g
@@ -108,7 +109,8 @@ def build(p, g=None, dom_ref=None, ref_ref=None, max_levels=None, connectivity=2
     rc = L.orc_build(len(X), X, Y, Z, fx, fy, fz,
                      None if m is None else m.ctypes.data_as(C.c_void_p),
                      float(mass_scalar), int(g), float(dom_ref), float(ref_ref),
-                     int(max_levels), int(connectivity), int(bool(labels)), C.byref(h))
+                     int(max_levels), int(connectivity), int(bool(labels)), int(bool(density)),
+                     C.byref(h))
     if rc != 0:
         raise ValueError(f"oracle build failed with code {rc}")
     try:

@@ -17,6 +17,10 @@
  *    threshold (DomRef on level 0, RefRef above); refinement stops at the
  *    level cap, at b = 21, or when no cell is refined.  A refined cell is
  *    covered by its 8 half-size children (all 8 exist, empty ones included).
+ *    With the density criterion (Sect. 2.1 read literally: the particle
+ *    density, from the TSC assignment, exceeds the threshold), the quantity
+ *    compared is instead the TSC particle number of the cell, N_L(c) = sum
+ *    over P_L of the particle's weight on c, in particles per cell.
  *  - S_L is the set of cells of level L, P_L the particles inside S_L.  The
  *    particles of P_L are assigned to the cells with triangular-shaped-cloud
  *    weights (Hockney & Eastwood): per axis, with u the in-cell offset in
@@ -55,6 +59,7 @@ typedef struct {
     uint64_t nE;
     uint64_t *E_key;
     double *E_mass;
+    double *E_num;   /* TSC particle number per cell of E_L (density criterion) */
     uint8_t *E_ghost;
     uint64_t nP;
     double tot_cell_mass;
@@ -179,7 +184,7 @@ static void free_level(orc_level *v)
 {
     free(v->S_key); free(v->S_count); free(v->S_start); free(v->S_flag);
     free(v->S_patch); free(v->S_pmass);
-    free(v->E_key); free(v->E_mass); free(v->E_ghost);
+    free(v->E_key); free(v->E_mass); free(v->E_num); free(v->E_ghost);
     free(v->patch_parent); free(v->patch_ncells); free(v->patch_npart); free(v->patch_mass);
     memset(v, 0, sizeof(*v));
 }
@@ -264,7 +269,7 @@ static int label_level(orc_hier *h, int L, int conn)
 int orc_build(uint64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t *Z,
               const float *fx, const float *fy, const float *fz, const float *mass,
               double mass_scalar, int g, double dom_ref, double ref_ref, int max_levels,
-              int conn, int labels, orc_hier **out)
+              int conn, int labels, int density, orc_hier **out)
 {
     *out = NULL;
     if (g < 1 || max_levels < 0 || g + max_levels > 21) return -1;
@@ -356,8 +361,9 @@ int orc_build(uint64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t *
             if (!v->E_key) { free(cand); goto oom; }
         }
         v->E_mass = (double *)calloc(v->nE ? v->nE : 1, sizeof(double));
+        v->E_num = (double *)calloc(v->nE ? v->nE : 1, sizeof(double));
         v->E_ghost = (uint8_t *)calloc(v->nE ? v->nE : 1, 1);
-        if (!v->E_mass || !v->E_ghost) goto oom;
+        if (!v->E_mass || !v->E_num || !v->E_ghost) goto oom;
         for (uint64_t e = 0; e < v->nE; e++)
             v->E_ghost[e] = find_key(v->S_key, nS, v->E_key[e]) < 0;
 
@@ -376,6 +382,7 @@ int orc_build(uint64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t *
                         int64_t e = find_key(v->E_key, v->nE, t);
                         if (e < 0) goto fail; /* cannot happen: t is within one cell of S_L */
                         v->E_mass[e] += m * w;
+                        v->E_num[e] += w;
                     }
         }
         v->tot_cell_mass = 0.0;
@@ -387,7 +394,13 @@ int orc_build(uint64_t n, const uint32_t *X, const uint32_t *Y, const uint32_t *
         double thr = (L == 0) ? dom_ref : ref_ref;
         uint64_t nF = 0;
         for (uint64_t i = 0; i < nS; i++) {
-            v->S_flag[i] = (double)v->S_count[i] > thr;
+            if (density) {
+                /* the cell's TSC particle number: its entry in E_L */
+                int64_t e = find_key(v->E_key, v->nE, v->S_key[i]);
+                v->S_flag[i] = v->E_num[e] > thr;
+            } else {
+                v->S_flag[i] = (double)v->S_count[i] > thr;
+            }
             nF += v->S_flag[i];
         }
         if (nF == 0) break;

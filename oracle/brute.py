@@ -33,10 +33,12 @@ def _key(x: int, y: int, z: int, bits: int) -> int:
     return k
 
 
-def brute(p, g, thr_dom, thr_ref, max_levels, conn=26):
+def brute(p, g, thr_dom, thr_ref, max_levels, conn=26, density=False):
     """Returns a list of dicts, one per level, with dense arrays indexed [x,y,z]:
-    inS, count, flag, mass (numpy float64, zero outside E), inE, patch (-1 off S),
-    plus per-patch parents and the smallest key of every patch."""
+    inS, count, flag, mass (numpy float64, zero outside E), number (TSC particle
+    number), inE, patch (-1 off S), plus per-patch parents and the smallest key
+    of every patch.  density: refine where the TSC particle number exceeds the
+    threshold instead of the count."""
     X = np.asarray(p.X, np.int64); Y = np.asarray(p.Y, np.int64); Z = np.asarray(p.Z, np.int64)
     fx = np.asarray(p.fx, np.float64); fy = np.asarray(p.fy, np.float64)
     fz = np.asarray(p.fz, np.float64)
@@ -58,6 +60,7 @@ def brute(p, g, thr_dom, thr_ref, max_levels, conn=26):
         inP = inS[cx, cy, cz]
         np.add.at(count, (cx[inP], cy[inP], cz[inP]), 1)
         field = np.zeros((n, n, n))
+        number = np.zeros((n, n, n))
         for i in np.nonzero(inP)[0]:
             for a in (-1, 0, 1):
                 ix = cx[i] + a
@@ -69,6 +72,7 @@ def brute(p, g, thr_dom, thr_ref, max_levels, conn=26):
                         iz = cz[i] + c
                         wz = tsc_distance_weight(pz[i] - (iz + 0.5))
                         field[ix % n, iy % n, iz % n] += mass[i] * wx * wy * wz
+                        number[ix % n, iy % n, iz % n] += wx * wy * wz
         # E = S dilated by one cell, periodic
         inE = np.zeros_like(inS)
         for a in (-1, 0, 1):
@@ -77,9 +81,10 @@ def brute(p, g, thr_dom, thr_ref, max_levels, conn=26):
                     inE |= np.roll(inS, (a, bb, c), axis=(0, 1, 2))
         last = (L == max_levels) or (b >= 21)
         thr = thr_dom if L == 0 else thr_ref
-        flag = (count > thr) & inS & (not last)
+        crit = number if density else count
+        flag = (crit > thr) & inS & (not last)
         lev = dict(level=L, bits=b, inS=inS.copy(), count=count, flag=flag, mass=field,
-                   inE=inE, n_particles=int(inP.sum()))
+                   number=number, inE=inE, n_particles=int(inP.sum()))
         if L >= 1:
             patch = -np.ones((n, n, n), np.int64)
             cells = np.argwhere(inS)
