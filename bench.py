@@ -347,6 +347,18 @@ def main():
         nstruct = h.structures()["n_structures"]
         h.free()
 
+    # the paper-literal density criterion (refine on the TSC particle number):
+    # same workload and thresholds, whole builds timed
+    dens = []
+    for i in range(4):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        h, _ = ahf.build_snapshot(ctx, snap, dev=dev, stream=stream, density_criterion=True)
+        torch.cuda.synchronize()
+        dens.append((time.perf_counter() - a) * 1e3)
+        dens_levels = h.num_levels()
+        h.free()
+
     # per-kernel split from two more builds, untimed, with every kernel timed
     names = ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "level0_start", "child_ranges",
              "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross")
@@ -400,6 +412,8 @@ def main():
             "frac": 84.0 * n / (kstats["gather"][1] / kstats["gather"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_ms_per_step": ksplit,
         "substructure": {"ms": float(np.median(cls)), "structures": int(nstruct)},
+        "density_criterion": {"ms_per_build": float(np.median(dens[1:])),
+                              "levels_built": int(dens_levels)},
         "levels": lv_info,
     }
     if args.copy_probe:

@@ -55,6 +55,15 @@ enum {
 #define AHF_NO_LABELS 1u   /* ahf_build_hierarchy skips the grid tree        */
 #define AHF_SUBSTRUCTURE 2u /* ... and classifies it into host structures and
                                 substructures (needs the grid tree)          */
+#define AHF_DENSITY_CRITERION 4u /* refine where a cell's TSC particle density
+                                (its deposited mass / mass_scalar, particles
+                                per cell) exceeds the threshold, as the paper
+                                states the criterion (Sect. 2.1), instead of
+                                its particle count; needs equal masses
+                                (mass NULL, mass_scalar > 0).  Flags then
+                                rest on FP32 sums: a cell within ~1e-5 of the
+                                threshold may decide differently from an
+                                exact computation                            */
 
 typedef struct ahf_ctx ahf_ctx;
 typedef struct ahf_hierarchy ahf_hierarchy;
@@ -83,7 +92,8 @@ typedef struct {
                                 g + max_levels <= 21                         */
     uint32_t connectivity;   /* 6, 18 or 26 (0 means 26): adjacency of the
                                 isolated refinements                          */
-    uint32_t flags;          /* AHF_NO_LABELS, AHF_SUBSTRUCTURE               */
+    uint32_t flags;          /* AHF_NO_LABELS, AHF_SUBSTRUCTURE,
+                                AHF_DENSITY_CRITERION                        */
 } ahf_params;
 
 /* Particle snapshot.  All arrays are device pointers of n elements, borrowed:

@@ -20,6 +20,7 @@ AHF_EINVAL, AHF_ENOMEM, AHF_EDEVICE, AHF_ELIMIT = -1, -2, -3, -4
 AHF_EBUSY, AHF_ENOTFOUND, AHF_ECANCELED = -5, -6, -7
 AHF_NO_LABELS = 1
 AHF_SUBSTRUCTURE = 2
+AHF_DENSITY_CRITERION = 4
 
 # every symbol declared in include/ahf.h
 EXPORTS = [
@@ -352,10 +353,11 @@ class Hierarchy:
 def build_hierarchy(ctx: Context, x, y, z, fx=None, fy=None, fz=None, mass=None, *,
                     g: int, dom_ref: float, ref_ref: float, max_levels: int,
                     connectivity: int = 26, labels: bool = True, mass_scalar: float = 1.0,
-                    substructure: bool = False, stream=None) -> Hierarchy:
+                    substructure: bool = False, density_criterion: bool = False,
+                    stream=None) -> Hierarchy:
     parts = make_particles(x, y, z, fx, fy, fz, mass, mass_scalar)
     prm = make_params(g, dom_ref, ref_ref, max_levels, connectivity,
-                      _flags(labels, substructure))
+                      _flags(labels, substructure, density_criterion))
     h = C.c_void_p()
     _check(load().ahf_build_hierarchy(ctx.handle, C.byref(parts), C.byref(prm),
                                       _stream_handle(stream), C.byref(h)))
@@ -373,17 +375,19 @@ def snapshot_to_device(s, device="cuda"):
 
 
 def build_snapshot(ctx: Context, s, labels=True, connectivity=26, stream=None, dev=None,
-                   substructure=False):
+                   substructure=False, density_criterion=False):
     """Build the hierarchy of a synth.Snapshot (copies it to the device first
     unless `dev` already holds its device tensors)."""
     dev = dev if dev is not None else snapshot_to_device(s)
     return build_hierarchy(ctx, *dev[:6], dev[6], g=s.g, dom_ref=s.dom_ref, ref_ref=s.ref_ref,
                            max_levels=s.max_levels, connectivity=connectivity, labels=labels,
-                           substructure=substructure, stream=stream), dev
+                           substructure=substructure, density_criterion=density_criterion,
+                           stream=stream), dev
 
 
-def _flags(labels, substructure):
-    return (0 if labels else AHF_NO_LABELS) | (AHF_SUBSTRUCTURE if substructure else 0)
+def _flags(labels, substructure, density_criterion=False):
+    return ((0 if labels else AHF_NO_LABELS) | (AHF_SUBSTRUCTURE if substructure else 0)
+            | (AHF_DENSITY_CRITERION if density_criterion else 0))
 
 
 class Server:

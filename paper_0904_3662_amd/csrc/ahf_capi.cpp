@@ -209,6 +209,47 @@ void Prof::clear() {
   acc.clear();
 }
 
+// ---------------------------------------------------------------- validation
+
+static ahf_status check_params(const ahf_params* prm, Params* out) {
+  if (!prm || prm->struct_size < sizeof(ahf_params)) return fail(AHF_EINVAL, "bad ahf_params");
+  const int g = (int)prm->dom_grid_log2;
+  if (g < 1 || g > 10) return fail(AHF_EINVAL, "dom_grid_log2 must be in 1..10");
+  if ((uint64_t)prm->dom_grid_log2 + prm->max_levels > 21)
+    return fail(AHF_EINVAL, "dom_grid_log2 + max_levels must be <= 21");
+  if (std::isnan(prm->dom_ref) || std::isnan(prm->ref_ref))
+    return fail(AHF_EINVAL, "thresholds must not be NaN");
+  const uint32_t conn = prm->connectivity ? prm->connectivity : 26;
+  if (conn != 6 && conn != 18 && conn != 26) return fail(AHF_EINVAL, "connectivity must be 6, 18 or 26");
+  out->g = g;
+  out->Lmax = (int)prm->max_levels;
+  out->conn = (int)conn;
+  out->dom_ref = prm->dom_ref;
+  out->ref_ref = prm->ref_ref;
+  if ((prm->flags & AHF_SUBSTRUCTURE) && (prm->flags & AHF_NO_LABELS))
+    return fail(AHF_EINVAL, "AHF_SUBSTRUCTURE needs the grid tree (not AHF_NO_LABELS)");
+  out->flags = prm->flags;
+  return AHF_OK;
+}
+
+static ahf_status check_particles(const ahf_particles* p) {
+  if (!p) return fail(AHF_EINVAL, "particles is NULL");
+  if (p->n >= (1ull << 32)) return fail(AHF_EINVAL, "at most 2^32 - 1 particles");
+  if (p->n > 0 && (!p->x || !p->y || !p->z)) return fail(AHF_EINVAL, "x, y and z are required");
+  if (!p->mass && !(std::isfinite(p->mass_scalar))) return fail(AHF_EINVAL, "mass_scalar must be finite");
+  return AHF_OK;
+}
+
+ahf_status check_request(const ahf_params* prm, const ahf_particles* p, Params* out) {
+  ahf_status s = check_params(prm, out);
+  if (s != AHF_OK) return s;
+  s = check_particles(p);
+  if (s != AHF_OK) return s;
+  if ((out->flags & AHF_DENSITY_CRITERION) && (p->mass || !(p->mass_scalar > 0.0)))
+    return fail(AHF_EINVAL, "AHF_DENSITY_CRITERION needs equal masses (mass NULL, mass_scalar > 0)");
+  return AHF_OK;
+}
+
 }  // namespace ahf
 
 using namespace ahf;
@@ -256,44 +297,13 @@ void ahf_ctx_destroy(ahf_ctx* ctx) {
   delete ctx;
 }
 
-static ahf_status check_params(const ahf_params* prm, Params* out) {
-  if (!prm || prm->struct_size < sizeof(ahf_params)) return fail(AHF_EINVAL, "bad ahf_params");
-  const int g = (int)prm->dom_grid_log2;
-  if (g < 1 || g > 10) return fail(AHF_EINVAL, "dom_grid_log2 must be in 1..10");
-  if ((uint64_t)prm->dom_grid_log2 + prm->max_levels > 21)
-    return fail(AHF_EINVAL, "dom_grid_log2 + max_levels must be <= 21");
-  if (std::isnan(prm->dom_ref) || std::isnan(prm->ref_ref))
-    return fail(AHF_EINVAL, "thresholds must not be NaN");
-  const uint32_t conn = prm->connectivity ? prm->connectivity : 26;
-  if (conn != 6 && conn != 18 && conn != 26) return fail(AHF_EINVAL, "connectivity must be 6, 18 or 26");
-  out->g = g;
-  out->Lmax = (int)prm->max_levels;
-  out->conn = (int)conn;
-  out->dom_ref = prm->dom_ref;
-  out->ref_ref = prm->ref_ref;
-  if ((prm->flags & AHF_SUBSTRUCTURE) && (prm->flags & AHF_NO_LABELS))
-    return fail(AHF_EINVAL, "AHF_SUBSTRUCTURE needs the grid tree (not AHF_NO_LABELS)");
-  out->flags = prm->flags;
-  return AHF_OK;
-}
-
-static ahf_status check_particles(const ahf_particles* p) {
-  if (!p) return fail(AHF_EINVAL, "particles is NULL");
-  if (p->n >= (1ull << 32)) return fail(AHF_EINVAL, "at most 2^32 - 1 particles");
-  if (p->n > 0 && (!p->x || !p->y || !p->z)) return fail(AHF_EINVAL, "x, y and z are required");
-  if (!p->mass && !(std::isfinite(p->mass_scalar))) return fail(AHF_EINVAL, "mass_scalar must be finite");
-  return AHF_OK;
-}
-
 ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, const ahf_params* params,
                                void* stream, ahf_hierarchy** out) {
   if (!out) return fail(AHF_EINVAL, "out is NULL");
   *out = nullptr;
   if (!ctx) return fail(AHF_EINVAL, "ctx is NULL");
   Params prm;
-  ahf_status s = check_params(params, &prm);
-  if (s != AHF_OK) return s;
-  s = check_particles(particles);
+  ahf_status s = check_request(params, particles, &prm);
   if (s != AHF_OK) return s;
   ahf_hierarchy* h = new (std::nothrow) ahf_hierarchy();
   if (!h) return fail(AHF_ENOMEM, "host allocation failed");

@@ -244,6 +244,9 @@ void finish_classify(Ctx* ctx, Hier* h, hipStream_t st);
 void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys_host,
                   int32_t* out_host, hipStream_t st);
 size_t hier_bytes(const Hier* h);
+// validation of a build request before anything is launched (AHF_OK or an
+// error status with the message set)
+ahf_status check_request(const ahf_params* prm, const ahf_particles* p, Params* out);
 void set_last_error(const std::string& msg);  // message returned by ahf_last_error
 
 }  // namespace ahf

@@ -227,6 +227,21 @@ __global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double 
 }
 
 
+// density criterion: a cell of S_L is refined where its TSC particle number
+// (its deposited mass over the common particle mass) exceeds the threshold;
+// the cell's field value sits in its own slot of the level's bricks
+__global__ void k_flags_density(uint64_t nS, const float* __restrict__ mass,
+                                const int32_t* __restrict__ Pbrick, double mscalar, double thr,
+                                int can_refine, uint8_t* __restrict__ flag,
+                                uint32_t* __restrict__ rank_unset) {
+  GRID_STRIDE(s, nS) {
+    const uint64_t slot = Pbrick ? (uint64_t)Pbrick[s >> 3] * 8 + (s & 7) : s;
+    const uint32_t f = (can_refine && (double)mass[slot] / mscalar > thr) ? 1u : 0u;
+    flag[s] = (uint8_t)f;
+    if (rank_unset && !f) rank_unset[s] = 0xffffffffu;
+  }
+}
+
 // ------------------------------------------------------------ TSC weights
 
 // per-axis TSC weights of coordinate (X, f) on a grid with k = 21 - b sub-bits:
@@ -1282,6 +1297,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
 
     // refinement flags and the cells too full for one thread
     const int can_refine = (L < prm.Lmax && b < kQBits) ? 1 : 0;
+    const bool density = (prm.flags & AHF_DENSITY_CRITERION) != 0;
     const double thr = (L == 0) ? prm.dom_ref : prm.ref_ref;
     // heavy-cell lists, sized by bounds: at most n/65 cells above 64
     // particles, at most that many plus n/4096 chunks
@@ -1297,19 +1313,23 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     hl.ch_h = ws.get<uint32_t>(maxch);
     hl.ch_j = ws.get<uint32_t>(maxch);
     const int32_t* hidx = hl.hidx;
-    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, can_refine, lv.Sflag, hl,
-                                            (L == 0) ? rank0 : nullptr);
+    // with the count criterion the flags come here; with the density
+    // criterion they need the level's deposit and come after it
+    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, density ? 0 : can_refine,
+                                            lv.Sflag, hl,
+                                            (L == 0 && !density) ? rank0 : nullptr);
     HIP_LAUNCH_CHECK();
     uint32_t* Ftmp = ws.get<uint32_t>(lv.nS);
     uint32_t* rankF = (L == 0 && rank0) ? rank0 : ws.get<uint32_t>(lv.nS);
+    const uint64_t nslot = 8 * nB;
+    uint8_t* mark = nullptr;
+    uint32_t* rank = nullptr;
+    auto flag_phase = [&]() {
     compact_flags(ws, lv.Sflag, lv.nS, Ftmp, rankF, dev_u32 + 1, st);
 
     // the dilation of F_L: slots of level L that hold a brick on level L+1
     // (sized by the bound nF <= nS, so that one sync per level reads nF, the
     // heavy-cell count and the brick count together)
-    const uint64_t nslot = 8 * nB;
-    uint8_t* mark = nullptr;
-    uint32_t* rank = nullptr;
     if (can_refine) {
       lv.slot_f = h->mem.get<int32_t>(nslot);
       mark = ws.get<uint8_t>(nslot);
@@ -1333,6 +1353,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     HIP_CHECK(hipMemcpyAsync(ctx->host_cnt, dev_u32 + 1, 4 * sizeof(uint32_t),
                              hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipEventRecord(ctx->cnt_ev, st));
+    };
+    if (!density) flag_phase();
 
     const uint32_t mask = (1u << (kQBits - b)) - 1u;
     const float scale = std::ldexp(1.0f, -(kQBits - b));
@@ -1389,6 +1411,13 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       AHF_TIMED(ctx, "combine", st,
                 (k_combine<<<(unsigned)((nB + 31) / 32), 256, 0, st>>>(L, nB, Bkey, b - 1, tree,
                                                                        pslot_f, patch, lv.mass)));
+    }
+    if (density) {
+      k_flags_density<<<grid_for(lv.nS), kT, 0, st>>>(lv.nS, lv.mass, lv.Pbrick, p.mass_scalar,
+                                                      thr, can_refine, lv.Sflag,
+                                                      (L == 0) ? rank0 : nullptr);
+      HIP_LAUNCH_CHECK();
+      flag_phase();
     }
     {
       const uint64_t nmax = (8 * nB > lv.nS) ? 8 * nB : lv.nS;

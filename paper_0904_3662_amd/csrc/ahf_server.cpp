@@ -215,10 +215,11 @@ ahf_status ahf_server_create(ahf_ctx* ctx, const ahf_server_desc* desc, ahf_serv
 ahf_status ahf_submit(ahf_server* s, const ahf_particles* p, const ahf_params* prm, uint64_t* ticket) {
   if (!ticket) return fail(AHF_EINVAL, "ticket is NULL");
   *ticket = 0;
-  if (!s || !p || !prm || prm->struct_size < sizeof(ahf_params)) return fail(AHF_EINVAL, "bad arguments");
+  if (!s) return fail(AHF_EINVAL, "bad arguments");
+  ahf::Params checked;
+  const ahf_status cs = ahf::check_request(prm, p, &checked);
+  if (cs != AHF_OK) return cs;
   const uint32_t g = prm->dom_grid_log2;
-  if (g < 1 || g > 10 || (uint64_t)g + prm->max_levels > 21 || p->n >= (1ull << 32))
-    return fail(AHF_EINVAL, "bad parameters");
   const uint64_t est = estimate_bytes(p->n, g);
   std::lock_guard<std::mutex> lk(s->mu);
   if (est > s->budget) return fail(AHF_ELIMIT, "request footprint exceeds the HBM budget");
