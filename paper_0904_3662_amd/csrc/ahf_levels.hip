@@ -197,32 +197,108 @@ struct HeavyList {
   int32_t* hidx;      // heavy index of a heavy cell
   uint32_t* nch;      // chunks of heavy cell h
   uint32_t* chofs;    // first chunk slot of heavy cell h
-  uint32_t* ch_h;     // heavy cell of a chunk slot
-  uint32_t* ch_j;     // chunk index within its cell
+  uint32_t* ch_a;     // first particle of a chunk
+  uint32_t* ch_n;     // particles in a chunk
 };
 
-__global__ void k_flags(const uint32_t* __restrict__ count, uint64_t nS, double thr,
-                        int can_refine, uint8_t* __restrict__ flag, HeavyList hl,
-                        uint32_t* __restrict__ rank_unset) {
-  GRID_STRIDE(s, nS) {
-    const uint32_t c = count[s];
-    const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
-    flag[s] = (uint8_t)f;
-    // the compaction fills in the rank of the refined cells
-    if (rank_unset && !f) rank_unset[s] = 0xffffffffu;
-    if (c > (uint32_t)kHeavy) {
-      const uint32_t h = atomicAdd(hl.nheavy, 1u);
-      const uint32_t m = (c + kChunk - 1) / kChunk;
-      const uint32_t o = atomicAdd(hl.nchunks, m);
-      hl.Hs[h] = (uint32_t)s;
-      hl.hidx[s] = (int32_t)h;
-      hl.nch[h] = m;
-      hl.chofs[h] = o;
-      for (uint32_t j = 0; j < m; ++j) {
-        hl.ch_h[o + j] = h;
-        hl.ch_j[o + j] = j;
+__device__ inline uint32_t wave_excl_scan_u32(uint32_t v) {
+  const uint32_t lane = __lane_id();
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += t;
+  }
+  return x - v;
+}
+
+// Refinement flags and the heavy-cell list.  Each block takes one contiguous
+// run of cells: a first pass counts its heavy cells and their chunks, one
+// atomic per counter reserves the block's indices, a second pass writes them.
+// (Atomics on one address from different blocks are served one after
+// another far from the CU, so their number sets the cost: the grid is kept
+// small.)
+constexpr int kFlagT = 1024;
+constexpr unsigned kFlagBlocks = 256;
+
+__global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ count,
+                                                  const uint32_t* __restrict__ start, uint64_t nS,
+                                                  double thr, int can_refine,
+                                                  uint8_t* __restrict__ flag, HeavyList hl,
+                                                  uint32_t* __restrict__ rank_unset) {
+  __shared__ uint32_t wh[kFlagT / 64], wc[kFlagT / 64];
+  __shared__ uint32_t base_h, base_c;
+  const uint64_t lt = lanemask_lt();
+  const int w = threadIdx.x >> 6;
+  const int lane = (int)__lane_id();
+  const uint64_t per = ((nS + gridDim.x - 1) / gridDim.x + kFlagT - 1) / kFlagT * kFlagT;
+  const uint64_t lo = (uint64_t)blockIdx.x * per;
+  const uint64_t hi = lo + per < nS ? lo + per : nS;
+  // pass 1: flags, and the block's heavy cells and chunks per thread
+  uint32_t my_h = 0, my_c = 0;
+  for (uint64_t s0 = lo + threadIdx.x; s0 < hi; s0 += 8 * kFlagT) {
+    uint32_t cs[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t s = s0 + (uint64_t)k * kFlagT;
+      cs[k] = s < hi ? count[s] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t s = s0 + (uint64_t)k * kFlagT;
+      if (s >= hi) break;
+      const uint32_t c = cs[k];
+      const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
+      flag[s] = (uint8_t)f;
+      // the compaction fills in the rank of the refined cells
+      if (rank_unset && !f) rank_unset[s] = 0xffffffffu;
+      if (c > (uint32_t)kHeavy) {
+        my_h += 1;
+        my_c += (c + kChunk - 1) / kChunk;
       }
     }
+  }
+  const uint32_t th = __syncthreads_count(my_h != 0);
+  if (th == 0) return;  // uniform: no heavy cell in the block
+  // block totals and one reservation
+  const uint32_t ho = wave_excl_scan_u32(my_h), co = wave_excl_scan_u32(my_c);
+  if (lane == 63) {
+    wh[w] = ho + my_h;
+    wc[w] = co + my_c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t sh = 0, sc = 0;
+    for (int i = 0; i < kFlagT / 64; ++i) {
+      const uint32_t a = wh[i], b = wc[i];
+      wh[i] = sh;
+      wc[i] = sc;
+      sh += a;
+      sc += b;
+    }
+    base_h = atomicAdd(hl.nheavy, sh);
+    base_c = atomicAdd(hl.nchunks, sc);
+  }
+  __syncthreads();
+  // pass 2: each thread's heavy cells in its own index range
+  uint32_t h = base_h + wh[w] + ho;
+  uint32_t o = base_c + wc[w] + co;
+  if (my_h == 0) return;
+  for (uint64_t s = lo + threadIdx.x; s < hi; s += kFlagT) {
+    const uint32_t c = count[s];
+    if (c <= (uint32_t)kHeavy) continue;
+    const uint32_t m = (c + kChunk - 1) / kChunk;
+    const uint32_t a = start[s];
+    hl.Hs[h] = (uint32_t)s;
+    hl.hidx[s] = (int32_t)h;
+    hl.nch[h] = m;
+    hl.chofs[h] = o;
+    for (uint32_t j = 0; j < m; ++j) {
+      hl.ch_a[o + j] = a + j * kChunk;
+      hl.ch_n[o + j] = min((uint32_t)kChunk, c - j * kChunk);
+    }
+    h += 1;
+    o += m;
   }
 }
 
@@ -310,18 +386,14 @@ __device__ inline void add_range(const Parts& P, uint32_t a, uint32_t n, uint32_
 // block of 256 threads); every lane sums at most kChunk/64 = 64 particles,
 // then a fixed butterfly over the wave
 __global__ __launch_bounds__(256) void k_heavy_chunk(
-    const uint32_t* __restrict__ nchunks, const uint32_t* __restrict__ ch_h,
-    const uint32_t* __restrict__ ch_j, const uint32_t* __restrict__ Hs,
-    const uint32_t* __restrict__ Sstart, const uint32_t* __restrict__ Scount, Parts P,
-    uint32_t mask, float scale, float* __restrict__ chT, double* __restrict__ chM) {
+    const uint32_t* __restrict__ nchunks, const uint32_t* __restrict__ ch_a,
+    const uint32_t* __restrict__ ch_n, Parts P, uint32_t mask, float scale,
+    float* __restrict__ chT, double* __restrict__ chM) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t nc = *nchunks;
   for (uint32_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < nc; c += gridDim.x * 4) {
-  const uint32_t s = Hs[ch_h[c]];
-  const uint32_t j = ch_j[c];
-  const uint32_t n = Scount[s];
-  const uint32_t a = Sstart[s] + j * kChunk;
-  const uint32_t len = min((uint32_t)kChunk, n - j * kChunk);
+  const uint32_t a = ch_a[c];
+  const uint32_t len = ch_n[c];
   float T[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) T[k] = 0.0f;
@@ -1310,12 +1382,14 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     hl.hidx = ws.get<int32_t>(lv.nS);  // read only for cells above kHeavy
     hl.nch = ws.get<uint32_t>(maxH);
     hl.chofs = ws.get<uint32_t>(maxH);
-    hl.ch_h = ws.get<uint32_t>(maxch);
-    hl.ch_j = ws.get<uint32_t>(maxch);
+    hl.ch_a = ws.get<uint32_t>(maxch);
+    hl.ch_n = ws.get<uint32_t>(maxch);
     const int32_t* hidx = hl.hidx;
     // with the count criterion the flags come here; with the density
     // criterion they need the level's deposit and come after it
-    k_flags<<<grid_for(lv.nS), kT, 0, st>>>(lv.Scount, lv.nS, thr, density ? 0 : can_refine,
+    k_flags<<<std::min(grid_for(lv.nS, kFlagT), kFlagBlocks), kFlagT, 0, st>>>(
+        lv.Scount, lv.Sstart, lv.nS, thr,
+                                            density ? 0 : can_refine,
                                             lv.Sflag, hl,
                                             (L == 0 && !density) ? rank0 : nullptr);
     HIP_LAUNCH_CHECK();
@@ -1368,8 +1442,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       double* chM = ws.get<double>(maxch);
       AHF_TIMED(ctx, "heavy_chunk", st,
                 (k_heavy_chunk<<<(unsigned)std::min<uint64_t>((maxch + 3) / 4, 2048), 256, 0, st>>>(
-                    hl.nchunks, hl.ch_h, hl.ch_j, hl.Hs, lv.Sstart, lv.Scount, P, mask, scale, chT,
-                    chM)));
+                    hl.nchunks, hl.ch_a, hl.ch_n, P, mask, scale, chT, chM)));
       k_heavy_reduce<<<std::min(grid_for(maxH * 28), 1024u), kT, 0, st>>>(
           hl.nch, hl.chofs, hl.nheavy, chT, chM, hT, hM);
       HIP_LAUNCH_CHECK();
