@@ -222,29 +222,6 @@ __global__ __launch_bounds__(kRsT) void k_rs_up(const uint64_t* __restrict__ in,
   th[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// the same from the byte array of the pass's digits (written by the previous
-// pass in output order): 1 byte per element read instead of 8
-__global__ __launch_bounds__(kRsT) void k_rs_up_b(const uint8_t* __restrict__ dig, uint64_t n,
-                                                 uint32_t ntiles, uint32_t* __restrict__ th) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0u;
-  __syncthreads();
-  const uint64_t i0 = (uint64_t)blockIdx.x * kRsTile + (uint64_t)threadIdx.x * kRsR;
-  if (i0 + kRsR <= n) {
-    const uint4 v = *reinterpret_cast<const uint4*>(dig + i0);
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) atomicAdd(&h[(w[k] >> (8 * j)) & 255u], 1u);
-  } else {
-    for (int k = 0; k < kRsR; ++k)
-      if (i0 + k < n) atomicAdd(&h[dig[i0 + k]], 1u);
-  }
-  __syncthreads();
-  th[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
-}
-
 constexpr int kTsT = 1024;
 
 // one block per digit: tofs[d * ntiles + t] = gofs[d] + sum of th[d * ntiles + t'] over t' < t
@@ -284,8 +261,7 @@ template <int IN, int OUT>
 __global__ __launch_bounds__(kRsT) void k_rs_down(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n, int shift,
-    int pk_shift, int ib, uint32_t ntiles, const uint32_t* __restrict__ tofs,
-    uint8_t* __restrict__ dnext, int nshift) {
+    int pk_shift, int ib, uint32_t ntiles, const uint32_t* __restrict__ tofs) {
   constexpr bool kPack = OUT == kOutWord && IN != kInWord;
   __shared__ uint64_t sk[kRsTile];
   __shared__ uint8_t sdig[kPack ? kRsTile : 1];  // a packed word no longer holds this digit
@@ -365,10 +341,7 @@ __global__ __launch_bounds__(kRsT) void k_rs_down(
   for (uint32_t i = threadIdx.x; i < tn; i += kRsT) {
     const uint64_t k = sk[i];
     const uint32_t d = kPack ? (uint32_t)sdig[i] : (uint32_t)(k >> shift) & 255u;
-    const uint64_t o = (uint64_t)gbase[d] + (i - doff[d]);
-    kout[o] = k;
-    // the next pass's digit, in output order, for its tile histograms
-    if (dnext) dnext[o] = (uint8_t)((k >> nshift) & 255u);
+    kout[(uint64_t)gbase[d] + (i - doff[d])] = k;
   }
   if (OUT == kOutKeyVal) {
     // the indices, through the same LDS with the digit beside each
@@ -405,45 +378,36 @@ uint64_t* sort_keys(Ctx* ctx, Ws& ws, uint64_t* keys, uint64_t n, const SortPlan
   uint64_t* a = keys;
   uint64_t* b = kt;
   uint32_t* vin = nullptr;
-  uint8_t* dig = sp.npass > 1 ? ws.get<uint8_t>(n) : nullptr;
   for (int p = 0; p < sp.npass; ++p) {
     // pass p sorts key bits [8p, 8p + 8): in a packed word they sit above the index
     const bool word_in = p >= sp.q;
     const int shift = word_in ? sp.ib + 8 * (p - sp.q) : 8 * p;
-    // where the next pass's digit sits in what this pass writes
-    const int nshift = (p + 1 >= sp.q) ? sp.ib + 8 * (p + 1 - sp.q) : 8 * (p + 1);
-    uint8_t* dnext = (p + 1 < sp.npass) ? dig : nullptr;
-    if (p == 0)
-      AHF_TIMED(ctx, "rs_up", st, (k_rs_up<<<ntiles, kRsT, 0, st>>>(a, n, shift, ntiles, th)));
-    else
-      AHF_TIMED(ctx, "rs_up", st, (k_rs_up_b<<<ntiles, kRsT, 0, st>>>(dig, n, ntiles, th)));
+    AHF_TIMED(ctx, "rs_up", st, (k_rs_up<<<ntiles, kRsT, 0, st>>>(a, n, shift, ntiles, th)));
     AHF_TIMED(ctx, "rs_tscan", st,
               (k_rs_tscan<<<256, kTsT, 0, st>>>(th, ntiles, gofs + p * 256, tofs)));
     uint32_t* vout = (vin == va) ? vb : va;
     if (word_in) {
       AHF_TIMED(ctx, "rs_scatter", st,
                 (k_rs_down<kInWord, kOutWord><<<ntiles, kRsT, 0, st>>>(
-                    a, nullptr, b, nullptr, n, shift, 0, sp.ib, ntiles, tofs, dnext, nshift)));
+                    a, nullptr, b, nullptr, n, shift, 0, sp.ib, ntiles, tofs)));
     } else if (p == sp.q - 1) {
       if (p == 0)
         AHF_TIMED(ctx, "rs_scatter", st,
                   (k_rs_down<kInKeyIota, kOutWord><<<ntiles, kRsT, 0, st>>>(
-                      a, nullptr, b, nullptr, n, shift, 8 * sp.q, sp.ib, ntiles, tofs, dnext,
-                      nshift)));
+                      a, nullptr, b, nullptr, n, shift, 8 * sp.q, sp.ib, ntiles, tofs)));
       else
         AHF_TIMED(ctx, "rs_scatter", st,
                   (k_rs_down<kInKeyVal, kOutWord><<<ntiles, kRsT, 0, st>>>(
-                      a, vin, b, nullptr, n, shift, 8 * sp.q, sp.ib, ntiles, tofs, dnext,
-                      nshift)));
+                      a, vin, b, nullptr, n, shift, 8 * sp.q, sp.ib, ntiles, tofs)));
     } else {
       if (p == 0)
         AHF_TIMED(ctx, "rs_scatter", st,
                   (k_rs_down<kInKeyIota, kOutKeyVal><<<ntiles, kRsT, 0, st>>>(
-                      a, nullptr, b, vout, n, shift, 0, sp.ib, ntiles, tofs, dnext, nshift)));
+                      a, nullptr, b, vout, n, shift, 0, sp.ib, ntiles, tofs)));
       else
         AHF_TIMED(ctx, "rs_scatter", st,
                   (k_rs_down<kInKeyVal, kOutKeyVal><<<ntiles, kRsT, 0, st>>>(
-                      a, vin, b, vout, n, shift, 0, sp.ib, ntiles, tofs, dnext, nshift)));
+                      a, vin, b, vout, n, shift, 0, sp.ib, ntiles, tofs)));
       vin = vout;
     }
     std::swap(a, b);
