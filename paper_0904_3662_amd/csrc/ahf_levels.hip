@@ -999,37 +999,79 @@ __device__ inline void refined_neighbours(int Lp, int bits, const Tree& tree,
 }
 
 
-// Elements are the refined cells F of level Lp (key order).  Each block
-// unites the cells of kUfTile consecutive elements in LDS; edges that leave
-// the tile are marked in xmask for the global pass.  par[f] leaves as the
-// smallest index of f's component inside the tile.
-__global__ __launch_bounds__(256) void k_uf_local(int Lp, int bits, uint64_t nF,
-                                                  const uint32_t* __restrict__ Fs,
-                                                  const uint64_t* __restrict__ Skey, Tree tree,
-                                                  const int32_t* __restrict__ slot_f, int conn,
+// All levels are labelled in one pass per step.  Entry k of the set is the
+// refined cells F_k of level k (key order), whose children make S_{k+1};
+// element e of the concatenated range is the refined cell e - off[k] of the
+// entry k holding e.  Neighbours are only looked up on the element's own
+// level, so components never cross levels and one forest over all elements
+// holds every level's components.  Indices and roots are global; a patch of
+// level k+1 with id p (its rank among that level's roots) gets the slot
+// off[k] + p in the per-patch arrays, which keeps the levels' slots apart.
+struct LabLev {
+  const uint32_t* Fs;      // S index of each refined cell of level k
+  const uint64_t* Skey;    // keys of S_k (null on level 0, where index = key)
+  const int32_t* slot_f;   // level-k slot -> index in F_k, or -1
+  const uint32_t* Scount;  // particles per cell of S_k
+  const double* Spmass;    // particle mass per cell of S_k, or null
+  uint32_t bits;           // bits per axis of level k
+};
+struct LabSet {
+  uint32_t nlev;              // entries 0 .. nlev-1
+  uint64_t off[kMaxLevels];   // first element of each entry; off[nlev] = total
+  uint64_t toff[kMaxLevels];  // first tile (kUfTile elements) of each entry
+  LabLev lv[kMaxLevels - 1];
+};
+
+__device__ inline int lab_entry(const LabSet& S, uint64_t e) {
+  int k = 0;
+  while (k + 1 < (int)S.nlev && e >= S.off[k + 1]) ++k;
+  return k;
+}
+
+// The tree lookups run on tiles of kUfTile elements that never straddle two
+// entries, so the level of a lookup is uniform over the block; the element
+// kernels without lookups find each element's entry per lane.  The set lives
+// in device memory, so that it can be indexed per lane.
+__device__ inline int lab_tile_entry(const LabSet& S, uint64_t tile) {
+  int k = 0;
+  while (k + 1 < (int)S.nlev && tile >= S.toff[k + 1]) ++k;
+  return k;
+}
+
+// Each block unites the cells of kUfTile consecutive elements in LDS; edges
+// that leave the tile are marked in xmask for the global pass.  par[e] leaves
+// as the smallest index of e's component inside the tile.
+__global__ __launch_bounds__(256) void k_uf_local(const LabSet* __restrict__ pS, Tree tree, int conn,
                                                   int32_t* __restrict__ par,
                                                   uint16_t* __restrict__ xmask,
                                                   uint32_t* __restrict__ err) {
   __shared__ int32_t lp[kUfTile];
-  const uint64_t t0 = (uint64_t)blockIdx.x * kUfTile;
-  const uint32_t tn = (uint32_t)((nF - t0) < (uint64_t)kUfTile ? (nF - t0) : (uint64_t)kUfTile);
+  const LabSet& S = *pS;
+  const int k = lab_tile_entry(S, blockIdx.x);
+  const LabLev& lv = S.lv[k];
+  const uint64_t o = S.off[k];
+  const uint64_t t0 = o + ((uint64_t)blockIdx.x - S.toff[k]) * kUfTile;
+  const uint64_t rest = S.off[k + 1] - t0;
+  const uint32_t tn = (uint32_t)(rest < (uint64_t)kUfTile ? rest : (uint64_t)kUfTile);
   for (int i = threadIdx.x; i < kUfTile; i += 256) lp[i] = i;
   __syncthreads();
+  const uint32_t cm = conn_mask(conn);
   for (uint32_t i = threadIdx.x; i < tn; i += 256) {
-    const uint64_t f = t0 + i;
-    const uint32_t s = Fs[f];
-    const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
+    const uint64_t e = t0 + i;
+    const uint32_t s = lv.Fs[e - o];
+    const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
     uint32_t xm = 0;
     int32_t gs[13];
-    refined_neighbours(Lp, bits, tree, slot_f, key, conn_mask(conn), gs, err);
+    refined_neighbours(k, (int)lv.bits, tree, lv.slot_f, key, cm, gs, err);
 #pragma unroll
-    for (int o = 0; o < 13; ++o) {
-      const int32_t g = gs[o];
-      if (g < 0 || (uint64_t)g == f) continue;
-      if ((uint64_t)g >= t0 && (uint64_t)g < t0 + tn) lds_unite(lp, (int32_t)i, (int32_t)(g - t0));
-      else xm |= 1u << o;
+    for (int q = 0; q < 13; ++q) {
+      if (gs[q] < 0) continue;
+      const uint64_t g = o + (uint64_t)gs[q];
+      if (g == e) continue;
+      if (g >= t0 && g < t0 + tn) lds_unite(lp, (int32_t)i, (int32_t)(g - t0));
+      else xm |= 1u << q;
     }
-    xmask[f] = (uint16_t)xm;
+    xmask[e] = (uint16_t)xm;
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < tn; i += 256)
@@ -1041,32 +1083,35 @@ __global__ __launch_bounds__(256) void k_uf_local(int Lp, int bits, uint64_t nF,
 // root), so each block first collects the distinct (root, root) pairs of its
 // cells in an LDS hash set and unites each pair once.
 constexpr int kPairSlots = 2048;
+static_assert(kUfTile == 256, "k_uf_cross takes one element per thread of a tile");
 
-__global__ __launch_bounds__(256) void k_uf_cross(int Lp, int bits, uint64_t nF,
-                                                  const uint32_t* __restrict__ Fs,
-                                                  const uint64_t* __restrict__ Skey, Tree tree,
-                                                  const int32_t* __restrict__ slot_f,
+__global__ __launch_bounds__(256) void k_uf_cross(const LabSet* __restrict__ pS, Tree tree,
                                                   const uint16_t* __restrict__ xmask,
                                                   int32_t* __restrict__ par,
                                                   uint32_t* __restrict__ err) {
   __shared__ unsigned long long set[kPairSlots];
-  for (uint64_t base = (uint64_t)blockIdx.x * 256; base < nF; base += (uint64_t)gridDim.x * 256) {
+  const LabSet& S = *pS;
+  const uint64_t ntiles = S.toff[S.nlev];
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int k = lab_tile_entry(S, tile);
+    const LabLev& lv = S.lv[k];
+    const uint64_t o = S.off[k];
+    const uint64_t base = o + (tile - S.toff[k]) * kUfTile;
     for (int i = threadIdx.x; i < kPairSlots; i += 256) set[i] = ~0ull;
     __syncthreads();
     const uint64_t f = base + threadIdx.x;
-    if (f < nF) {
+    if (f < S.off[k + 1]) {
       uint32_t xm = xmask[f];
       if (xm) {
-        const uint32_t s = Fs[f];
-        const uint64_t key = Skey ? Skey[s] : (uint64_t)s;
+        const uint32_t s = lv.Fs[f - o];
+        const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
         const int32_t ra = par[f];  // tile-local root (written by k_uf_local)
         int32_t gs[13];
-        refined_neighbours(Lp, bits, tree, slot_f, key, xm, gs, err);
+        refined_neighbours(k, (int)lv.bits, tree, lv.slot_f, key, xm, gs, err);
 #pragma unroll
-        for (int o = 0; o < 13; ++o) {
-          const int32_t g = gs[o];
-          if (g < 0) continue;
-          const int32_t rb = par[g];
+        for (int q = 0; q < 13; ++q) {
+          if (gs[q] < 0) continue;
+          const int32_t rb = par[o + (uint64_t)gs[q]];
           const int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
           if (lo == hi) continue;
           const unsigned long long pk = ((unsigned long long)(uint32_t)lo << 32) | (uint32_t)hi;
@@ -1111,16 +1156,30 @@ __global__ void k_uf_compress(int32_t* par, uint64_t n, int32_t* __restrict__ ro
   }
 }
 
-// patch id of every refined parent (the rank of its root among the roots),
-// and of its 8 children, the cells of S_L
-__global__ void k_uf_label(const int32_t* __restrict__ root, const uint32_t* __restrict__ rank,
-                           uint64_t n, int32_t* __restrict__ lab, int32_t* __restrict__ Spatch) {
+// patch id of every element (the rank of its root among its level's roots;
+// the level's first element is always a root, so rank[off[k]] is the
+// level's base) and of its 8 children, the cells of S_{k+1}; lab[e] is the
+// patch's global slot.  The level's first element also writes the level's
+// patch count.
+__global__ void k_uf_label(const LabSet* __restrict__ pS, const int32_t* __restrict__ root,
+                           const uint32_t* __restrict__ rank, const uint32_t* __restrict__ nroots,
+                           int32_t* __restrict__ lab, int32_t* __restrict__ Spatch,
+                           uint32_t* __restrict__ npatch) {
+  const LabSet& S = *pS;
+  const uint64_t n = S.off[S.nlev];
   GRID_STRIDE(i, n) {
-    const int32_t l = (int32_t)rank[root[i]];
-    lab[i] = l;
-    int4* o = reinterpret_cast<int4*>(Spatch + 8 * i);
-    o[0] = make_int4(l, l, l, l);
-    o[1] = make_int4(l, l, l, l);
+    const int k = lab_entry(S, i);
+    const uint64_t o = S.off[k];
+    const uint32_t r0 = rank[o];
+    const int32_t l = (int32_t)(rank[root[i]] - r0);
+    lab[i] = (int32_t)(o + (uint64_t)l);
+    int4* out = reinterpret_cast<int4*>(Spatch + 8 * i);
+    out[0] = make_int4(l, l, l, l);
+    out[1] = make_int4(l, l, l, l);
+    if (i == o) {
+      const uint64_t o1 = S.off[k + 1];
+      npatch[k + 1] = (o1 < n ? rank[o1] : *nroots) - r0;
+    }
   }
 }
 
@@ -1137,11 +1196,13 @@ __device__ inline uint64_t shfl_up_u64(uint64_t v, int d) {
 // every wave walks its own contiguous range of cells 64 at a time and keeps
 // the run that reaches the end of a chunk as a carry, so a patch spread over
 // many cells costs about one atomic per wave
-__global__ __launch_bounds__(256) void k_patch_stats(const int32_t* __restrict__ lab, uint64_t nF,
-                              const uint32_t* __restrict__ pFs, const uint32_t* __restrict__ pScount,
-                              const double* __restrict__ pSpmass, double fscale,
+__global__ __launch_bounds__(256) void k_patch_stats(const LabSet* __restrict__ pS,
+                              const int32_t* __restrict__ lab,
+                              double fscale,
                               uint32_t* __restrict__ ncells, unsigned long long* __restrict__ npart,
                               unsigned long long* __restrict__ mfix) {
+  const LabSet& S = *pS;
+  const uint64_t nF = S.off[S.nlev];
   const int lane = (int)__lane_id();
   const uint64_t le = (lane == 63) ? ~0ull : ((1ull << (lane + 1)) - 1ull);
   const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -1160,9 +1221,11 @@ __global__ __launch_bounds__(256) void k_patch_stats(const int32_t* __restrict__
     uint32_t c = valid ? 8u : 0u;
     uint64_t np = 0, mf = 0;
     if (valid) {
-      const uint32_t s = pFs[f];
-      np = pScount[s];
-      if (mfix) mf = (uint64_t)llrint(pSpmass[s] * fscale);
+      const int k = lab_entry(S, f);
+      const LabLev& lv = S.lv[k];
+      const uint32_t s = lv.Fs[f - S.off[k]];
+      np = lv.Scount[s];
+      if (mfix) mf = (uint64_t)llrint(lv.Spmass[s] * fscale);
     }
     const int32_t pp = __shfl_up(p, 1, 64);
     const bool head = (lane == 0) || (pp != p);
@@ -1217,18 +1280,22 @@ __global__ __launch_bounds__(256) void k_patch_stats(const int32_t* __restrict__
   }
 }
 
-// per patch, from its root: the parent patch (the level-(L-1) patch of the
-// root's cell) and the mass (fixed point back to FP64, or count x mass)
-__global__ void k_patch_parent(const int32_t* __restrict__ root, const int32_t* __restrict__ lab,
-                               uint64_t nF, const uint32_t* __restrict__ pFs,
-                               const int32_t* __restrict__ pSpatch, int32_t* __restrict__ parent,
+// per patch, from its root: the parent patch (the level-k patch of the
+// root's cell, none on level 1) and the mass (fixed point back to FP64, or
+// count x mass)
+__global__ void k_patch_parent(const LabSet* __restrict__ pS, const int32_t* __restrict__ root,
+                               const int32_t* __restrict__ lab,
+                               const int32_t* __restrict__ Spatch, int32_t* __restrict__ parent,
                                const unsigned long long* __restrict__ npart,
                                const unsigned long long* __restrict__ mfix, double mscalar,
                                double inv_scale, double* __restrict__ pm) {
+  const LabSet& S = *pS;
+  const uint64_t nF = S.off[S.nlev];
   GRID_STRIDE(f, nF) {
     if (root[f] == (int32_t)f) {
       const int32_t p = lab[f];
-      parent[p] = pSpatch ? pSpatch[pFs[f]] : -1;
+      const int k = lab_entry(S, f);
+      parent[p] = k > 0 ? Spatch[8 * S.off[k - 1] + S.lv[k].Fs[f - S.off[k]]] : -1;
       pm[p] = mfix ? (double)mfix[p] * inv_scale : (double)npart[p] * mscalar;
     }
   }
@@ -1587,9 +1654,9 @@ void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
   if (h->labelled) return;
   const double t0 = now_ms();
-  // dev[0]: error flags; dev[4 + L]: the number of patches on level L. The
-  // levels are labelled back to back on the stream; the counts are read once
-  // at the end, so the per-level patch arrays are sized by their bound nE.
+  // dev[0]: error flags; dev[1]: roots over all levels; dev[4 + L]: the
+  // number of patches on level L.  The counts are read once at the end, so
+  // the per-level patch arrays are sized by their bound, the level's parents.
   const size_t nlev = h->lev.size();
   uint32_t* dev = ws.get<uint32_t>(4 + nlev);
   HIP_CHECK(hipMemsetAsync(dev, 0, (4 + nlev) * sizeof(uint32_t), st));
@@ -1603,48 +1670,65 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     std::frexp(total_mass > 0 ? total_mass : 1.0, &e);
     fscale = std::ldexp(1.0, 61 - e);
   }
-  for (size_t L = 1; L < nlev; ++L) {
-    Level& pv = h->lev[L - 1];
-    Level& lv = h->lev[L];
-    const uint64_t nE = pv.nF;
-    const uint64_t nE1 = nE ? nE : 1;
-    uint32_t* npatch = dev + 4 + L;
+  // every level at once: entry k = the refined cells of level k, parents of
+  // the cells of level k + 1
+  LabSet S{};
+  S.nlev = nlev > 1 ? (uint32_t)(nlev - 1) : 0u;
+  uint64_t tot = 0, ntiles = 0;
+  for (uint32_t k = 0; k < S.nlev; ++k) {
+    const Level& pv = h->lev[k];
+    S.off[k] = tot;
+    S.toff[k] = ntiles;
+    S.lv[k] = LabLev{pv.Fs, pv.Skey, pv.slot_f, pv.Scount, pv.Spmass, pv.b};
+    tot += pv.nF;
+    ntiles += (pv.nF + kUfTile - 1) / kUfTile;
+  }
+  S.off[S.nlev] = tot;
+  S.toff[S.nlev] = ntiles;
+  if (tot >= (1ull << 31)) throw Error{AHF_ELIMIT, "too many refined cells to label"};
+  const uint64_t tot1 = tot ? tot : 1;
+  int32_t* Spatch = h->mem.get<int32_t>(8 * tot1);
+  int32_t* pparent = h->mem.get<int32_t>(tot1);
+  uint32_t* pncells = h->mem.get<uint32_t>(tot1);
+  uint64_t* pnpart = h->mem.get<uint64_t>(tot1);
+  double* pmass = h->mem.get<double>(tot1);
+  for (uint32_t k = 0; k < S.nlev; ++k) {
+    Level& lv = h->lev[k + 1];
+    lv.Spatch = Spatch + 8 * S.off[k];
+    lv.patch_parent = pparent + S.off[k];
+    lv.patch_ncells = pncells + S.off[k];
+    lv.patch_npart = pnpart + S.off[k];
+    lv.patch_mass = pmass + S.off[k];
+  }
+  if (tot) {
     Ws::Mark m = ws.mark();
-    int32_t* par = ws.get<int32_t>(nE);
-    int32_t* root = ws.get<int32_t>(nE);
-    uint8_t* pred = ws.get<uint8_t>(nE);
-    uint32_t* rank = ws.get<uint32_t>(nE);
-    int32_t* lab = ws.get<int32_t>(nE);
-    uint16_t* xmask = ws.get<uint16_t>(nE);
-    if (nE) {
-      AHF_TIMED(ctx, "uf_hook", st,
-                (k_uf_local<<<(unsigned)((nE + kUfTile - 1) / kUfTile), 256, 0, st>>>(
-                    (int)L - 1, (int)pv.b, nE, pv.Fs, pv.Skey, tree, pv.slot_f, h->prm.conn, par,
-                    xmask, dev)));
-      AHF_TIMED(ctx, "uf_cross", st,
-                (k_uf_cross<<<grid_for(nE), 256, 0, st>>>((int)L - 1, (int)pv.b, nE, pv.Fs, pv.Skey,
-                                                          tree, pv.slot_f, xmask, par, dev)));
-    }
-    lv.Spatch = h->mem.get<int32_t>(lv.nS);
-    lv.patch_parent = h->mem.get<int32_t>(nE1);
-    lv.patch_ncells = h->mem.get<uint32_t>(nE1);
-    lv.patch_npart = h->mem.get<uint64_t>(nE1);
-    lv.patch_mass = h->mem.get<double>(nE1);
-    unsigned long long* mfix = h->has_mass ? ws.get<unsigned long long>(nE1) : nullptr;
-    k_uf_compress<<<grid_for(nE1), kT, 0, st>>>(par, nE, root, pred, nE1, lv.patch_ncells,
-                                                (unsigned long long*)lv.patch_npart, mfix);
+    int32_t* par = ws.get<int32_t>(tot);
+    int32_t* root = ws.get<int32_t>(tot);
+    uint8_t* pred = ws.get<uint8_t>(tot);
+    uint32_t* rank = ws.get<uint32_t>(tot);
+    int32_t* lab = ws.get<int32_t>(tot);
+    uint16_t* xmask = ws.get<uint16_t>(tot);
+    unsigned long long* mfix = h->has_mass ? ws.get<unsigned long long>(tot) : nullptr;
+    LabSet* dS = ws.get<LabSet>(1);
+    HIP_CHECK(hipMemcpyAsync(dS, &S, sizeof(LabSet), hipMemcpyHostToDevice, st));
+    AHF_TIMED(ctx, "uf_hook", st,
+              (k_uf_local<<<(unsigned)ntiles, 256, 0, st>>>(
+                  dS, tree, h->prm.conn, par, xmask, dev)));
+    AHF_TIMED(ctx, "uf_cross", st,
+              (k_uf_cross<<<(unsigned)std::min<uint64_t>(ntiles, 1u << 20), 256, 0, st>>>(
+                  dS, tree, xmask, par, dev)));
+    k_uf_compress<<<grid_for(tot), kT, 0, st>>>(par, tot, root, pred, tot, pncells,
+                                                (unsigned long long*)pnpart, mfix);
     HIP_LAUNCH_CHECK();
-    compact_flags(ws, pred, nE, nullptr, rank, npatch, st);
-    k_uf_label<<<grid_for(nE), kT, 0, st>>>(root, rank, nE, lab, lv.Spatch);
+    compact_flags(ws, pred, tot, nullptr, rank, dev + 1, st);
+    k_uf_label<<<grid_for(tot), kT, 0, st>>>(dS, root, rank, dev + 1, lab, Spatch, dev + 4);
     HIP_LAUNCH_CHECK();
-    k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (nE + 4095) / 4096 + 1), 256, 0, st>>>(
-        lab, nE, pv.Fs, pv.Scount, pv.Spmass, fscale, lv.patch_ncells,
-        (unsigned long long*)lv.patch_npart, mfix);
+    k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (tot + 4095) / 4096 + 1), 256, 0, st>>>(
+        dS, lab, fscale, pncells, (unsigned long long*)pnpart, mfix);
     HIP_LAUNCH_CHECK();
-    k_patch_parent<<<grid_for(nE), kT, 0, st>>>(root, lab, nE, pv.Fs, (L >= 2) ? pv.Spatch : nullptr,
-                                                lv.patch_parent,
-                                                (const unsigned long long*)lv.patch_npart, mfix,
-                                                h->mass_scalar, 1.0 / fscale, lv.patch_mass);
+    k_patch_parent<<<grid_for(tot), kT, 0, st>>>(dS, root, lab, Spatch, pparent,
+                                                 (const unsigned long long*)pnpart, mfix,
+                                                 h->mass_scalar, 1.0 / fscale, pmass);
     HIP_LAUNCH_CHECK();
     // stream order keeps the released workspace from being reused early
     ws.release(m);
