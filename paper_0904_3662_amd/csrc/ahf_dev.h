@@ -8,7 +8,7 @@ namespace ahf {
 constexpr int kQBits = 21;          // bits per axis of the quantized positions
 constexpr int kMaxLevels = 22;      // levels 0..21
 constexpr int kHeavy = 64;          // cells with more particles take the chunked path
-constexpr int kChunk = 4096;        // particles per chunk of a heavy cell (64 lanes x 64)
+constexpr int kChunk = 1024;        // particles per chunk of a heavy cell (64 lanes x 16)
 
 // device error flags (bit mask in a uint32 the host reads after the build)
 constexpr uint32_t kErrCoord = 1u;     // a coordinate >= 2^21

@@ -383,7 +383,7 @@ __device__ inline void add_range(const Parts& P, uint32_t a, uint32_t n, uint32_
 
 
 // one wave per chunk of <= kChunk particles of one heavy cell (4 chunks per
-// block of 256 threads); every lane sums at most kChunk/64 = 64 particles,
+// block of 256 threads); every lane sums at most kChunk/64 = 16 particles,
 // then a fixed butterfly over the wave
 __global__ __launch_bounds__(256) void k_heavy_chunk(
     const uint32_t* __restrict__ nchunks, const uint32_t* __restrict__ ch_a,
@@ -1193,9 +1193,10 @@ __device__ inline uint64_t shfl_up_u64(uint64_t v, int d) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// every wave walks its own contiguous range of cells 64 at a time and keeps
-// the run that reaches the end of a chunk as a carry, so a patch spread over
-// many cells costs about one atomic per wave
+// every wave walks its own contiguous range of cells 64 at a time (the loads
+// of four rows issued together) and keeps the run that reaches the end of a
+// row as a carry, so a patch spread over many cells costs about one atomic
+// per wave
 __global__ __launch_bounds__(256) void k_patch_stats(const LabSet* __restrict__ pS,
                               const int32_t* __restrict__ lab,
                               double fscale,
@@ -1208,25 +1209,37 @@ __global__ __launch_bounds__(256) void k_patch_stats(const LabSet* __restrict__ 
   const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
   const uint64_t wid = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   uint64_t chunk = (nF + nw - 1) / nw;
-  chunk = (chunk + 63) & ~63ull;
+  chunk = (chunk + 255) & ~255ull;
   const uint64_t r0 = wid * chunk;
   const uint64_t r1 = (r0 + chunk < nF) ? r0 + chunk : nF;
   int32_t cp = -1;  // carried run (wave-uniform)
   uint32_t cc = 0;
   uint64_t cn = 0, cm = 0;
-  for (uint64_t base = r0; base < r1; base += 64) {
-    const uint64_t f = base + lane;
-    const bool valid = f < r1;
-    const int32_t p = valid ? lab[f] : -1;
-    uint32_t c = valid ? 8u : 0u;
-    uint64_t np = 0, mf = 0;
-    if (valid) {
-      const int k = lab_entry(S, f);
+  for (uint64_t base = r0; base < r1; base += 4 * 64) {
+    // the loads of four rows of 64 first (indices clamped into the range),
+    // then the rows in order
+    int32_t pv[4];
+    uint64_t npv[4], mfv[4];
+    const int k0 = lab_entry(S, base);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t fr = base + 64 * j + lane;
+      const uint64_t f = fr < r1 ? fr : r1 - 1;
+      int k = k0;
+      while (k + 1 < (int)S.nlev && f >= S.off[k + 1]) ++k;
       const LabLev& lv = S.lv[k];
       const uint32_t s = lv.Fs[f - S.off[k]];
-      np = lv.Scount[s];
-      if (mfix) mf = (uint64_t)llrint(lv.Spmass[s] * fscale);
+      pv[j] = lab[f];
+      npv[j] = lv.Scount[s];
+      mfv[j] = mfix ? (uint64_t)llrint(lv.Spmass[s] * fscale) : 0ull;
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+    if (base + 64 * j >= r1) break;
+    const bool valid = base + 64 * j + lane < r1;
+    const int32_t p = valid ? pv[j] : -1;
+    uint32_t c = valid ? 8u : 0u;
+    uint64_t np = valid ? npv[j] : 0ull, mf = valid ? mfv[j] : 0ull;
     const int32_t pp = __shfl_up(p, 1, 64);
     const bool head = (lane == 0) || (pp != p);
     const uint64_t heads = __ballot(head);
@@ -1272,6 +1285,7 @@ __global__ __launch_bounds__(256) void k_patch_stats(const LabSet* __restrict__ 
          (uint32_t)__shfl((uint32_t)np, last, 64);
     cm = ((uint64_t)(uint32_t)__shfl((uint32_t)(mf >> 32), last, 64) << 32) |
          (uint32_t)__shfl((uint32_t)mf, last, 64);
+    }
   }
   if (cp >= 0 && lane == 0) {
     atomicAdd(&ncells[cp], cc);

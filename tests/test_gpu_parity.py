@@ -47,7 +47,7 @@ def test_uniform_various_grids(ctx, seed, g, Lmax):
 
 
 def test_heavy_cells_multichunk(ctx):
-    # 40000 particles in one domain cell (10 chunks of 4096) plus background
+    # 40000 particles in one domain cell (40 chunks of 1024) plus background
     rng = np.random.Generator(np.random.PCG64(5))
     core = np.array([0.53, 0.41, 0.77]) + rng.normal(0, 0.004, (40000, 3))
     bg = rng.random((3000, 3))
