@@ -174,8 +174,29 @@ __global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
     const uint64_t ck = (pk << 3) | d;
     // the 8 children of a parent sit on 8 consecutive lanes (nS is a multiple
     // of 8 and so is every lane group's first s): each finds where its child
-    // starts, and ends where the next child starts
-    const uint32_t lo = (d == 0) ? a : lower_bound_key(skey, a, e, ck << sh);
+    // starts, and ends where the next child starts.  A parent of at most 32
+    // particles is read by its 8 lanes together (one load each per 8 keys),
+    // which count the particles of every child digit; a larger one is
+    // searched.
+    uint32_t lo;
+    if (e - a <= 32u) {
+      uint64_t hist = 0;  // one byte per child digit
+#pragma unroll
+      for (uint32_t k = 0; k < 4; ++k) {
+        const uint32_t i = a + d + 8u * k;
+        if (i < e) hist += 1ull << (8u * (uint32_t)((skey[i] >> sh) & 7u));
+      }
+#pragma unroll
+      for (int m = 1; m < 8; m <<= 1) {
+        const uint32_t l32 = __shfl_xor((uint32_t)hist, m, 8);
+        const uint32_t h32 = __shfl_xor((uint32_t)(hist >> 32), m, 8);
+        hist += ((uint64_t)h32 << 32) | l32;
+      }
+      const uint64_t below = d ? (hist & ((1ull << (8u * d)) - 1ull)) : 0ull;
+      lo = a + (uint32_t)((below * 0x0101010101010101ull) >> 56);
+    } else {
+      lo = (d == 0) ? a : lower_bound_key(skey, a, e, ck << sh);
+    }
     const uint32_t nxt = (uint32_t)__shfl_down((int)lo, 1, 8);
     const uint32_t hi = (d == 7) ? e : nxt;
     Skey[s] = ck;
@@ -525,9 +546,11 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
     const int32_t* __restrict__ pslot_child, float* __restrict__ mass,
     float* __restrict__ halo, double* __restrict__ Spmass) {
   __shared__ float G[kTileH];  // the tile's cells and their one-cell halo
+  __shared__ int32_t sbr[64];  // brick of each parent's children (loaded with the first loads)
   const int t = threadIdx.x;
   const uint64_t tile = blockIdx.x;
   for (int q = t; q < kTileH; q += kTileT) G[q] = 0.0f;
+  if (t < 64) sbr[t] = DENSE0 ? (int32_t)(tile * 64 + (uint64_t)t) : pslot_child[tile * 64 + (uint64_t)t];
   const uint32_t pm = (uint32_t)t >> 3, d = (uint32_t)t & 7u;
   const uint32_t px = (((pm >> 5) & 1u) << 1) | ((pm >> 2) & 1u);
   const uint32_t py = (((pm >> 4) & 1u) << 1) | ((pm >> 1) & 1u);
@@ -576,9 +599,7 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
     // cells off the tile's faces are final; face cells and the halo go to
     // the buffer, where k_tile_halo_add adds the neighbours' share
     if ((unsigned)(dx - 1) < 6u && (unsigned)(dy - 1) < 6u && (unsigned)(dz - 1) < 6u) {
-      const uint64_t pp = tile * 64 + tile_local_parent((uint32_t)dx >> 1, (uint32_t)dy >> 1,
-                                                        (uint32_t)dz >> 1);
-      const int64_t br = DENSE0 ? (int64_t)pp : (int64_t)pslot_child[pp];
+      const int64_t br = sbr[tile_local_parent((uint32_t)dx >> 1, (uint32_t)dy >> 1, (uint32_t)dz >> 1)];
       const uint32_t dd = (((uint32_t)dx & 1u) << 2) | (((uint32_t)dy & 1u) << 1) | ((uint32_t)dz & 1u);
       if (br >= 0) mass[(uint64_t)br * 8 + dd] = sum;
     } else {
