@@ -166,7 +166,7 @@ hipEvent_t Prof::take() {
     return e;
   }
   hipEvent_t e = nullptr;
-  HIP_CHECK(hipEventCreate(&e));
+  HIP_CHECK(hipEventCreateWithFlags(&e, kTimingEventFlags));
   return e;
 }
 
@@ -482,7 +482,7 @@ ahf_status ahf_ctx_set_profiling(ahf_ctx* ctx, int enable) {
     // would slow the builds being timed
     while (enable && ctx->c.prof.spare.size() < 2048) {
       hipEvent_t e = nullptr;
-      HIP_CHECK(hipEventCreate(&e));
+      HIP_CHECK(hipEventCreateWithFlags(&e, kTimingEventFlags));
       ctx->c.prof.spare.push_back(e);
     }
   } catch (const Error& e) {

@@ -34,6 +34,11 @@ struct Pool {
 };
 
 // HIP-event timing of selected kernels (profiling mode of a context)
+// Events that only time work: recording one performs no system-scope fence
+// (no L2 write-back between the kernels around it); their elapsed times are
+// read once the stream has passed them.
+constexpr unsigned kTimingEventFlags = hipEventDisableSystemFence;
+
 struct Prof {
   bool on = false;
   std::vector<std::string> only;  // names to time; empty = all

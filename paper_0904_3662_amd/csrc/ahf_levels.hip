@@ -249,7 +249,6 @@ __global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ c
                                                   uint32_t* __restrict__ rank_unset) {
   __shared__ uint32_t wh[kFlagT / 64], wc[kFlagT / 64];
   __shared__ uint32_t base_h, base_c;
-  const uint64_t lt = lanemask_lt();
   const int w = threadIdx.x >> 6;
   const int lane = (int)__lane_id();
   const uint64_t per = ((nS + gridDim.x - 1) / gridDim.x + kFlagT - 1) / kFlagT * kFlagT;
@@ -1387,7 +1386,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     ctx->host_cnt = static_cast<uint32_t*>(hp);
     ctx->host_tot = reinterpret_cast<double*>(static_cast<char*>(hp) + 256);
     HIP_CHECK(hipEventCreateWithFlags(&ctx->cnt_ev, hipEventDisableTiming));
-    for (auto& e : ctx->phase_ev) HIP_CHECK(hipEventCreate(&e));
+    for (auto& e : ctx->phase_ev) HIP_CHECK(hipEventCreateWithFlags(&e, kTimingEventFlags));
   }
   HIP_CHECK(hipEventRecord(ctx->phase_ev[0], st));
   uint32_t* dev_u32 = ws.get<uint32_t>(8);   // [0] error flags, [1..] counters
