@@ -25,7 +25,17 @@ METRIC = "particles/s through full hierarchy build (1 GPU, % HBM peak); p50/p99 
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_rs_scatter_lattice-nfw-16.8M.txt")
-SCATTER_SRC = os.path.join(ROOT, "paper_0904_3662_amd", "csrc", "ahf_prims.hip")
+# the files the scatter kernel is compiled from
+SCATTER_SRC = [os.path.join(ROOT, "paper_0904_3662_amd", "csrc", f)
+               for f in ("ahf_prims.hip", "ahf_dev.h", "ahf_internal.h")]
+
+
+def scatter_source_hash():
+    h = hashlib.sha256()
+    for f in SCATTER_SRC:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def measured_traffic(workload):
@@ -41,9 +51,7 @@ def measured_traffic(workload):
             vals["t"] = float(line.split(":")[1])
         if line.startswith("source_sha256"):
             vals["h"] = line.split(":")[1].strip()
-    with open(SCATTER_SRC, "rb") as f:
-        cur = hashlib.sha256(f.read()).hexdigest()
-    if "t" not in vals or vals.get("h") != cur:
+    if "t" not in vals or vals.get("h") != scatter_source_hash():
         return None
     return vals["t"]
 

@@ -95,6 +95,27 @@ __device__ inline void tree_lookup_k(const Tree& t, int L, const uint64_t (&key)
   }
 }
 
+// Blocks go to the GPU's 8 XCDs in turn (block b runs on XCD b mod 8), and
+// every XCD has its own L2.  xcd_tile maps block b to a tile so that each XCD
+// takes one contiguous run of tiles: neighbouring tiles, which share cache
+// lines at their edges, then meet in one L2.  A bijection on [0, ntiles).
+__device__ inline uint32_t xcd_tile(uint32_t b, uint32_t ntiles) {
+  const uint32_t q = ntiles >> 3, r = ntiles & 7u;
+  const uint32_t x = b & 7u, j = b >> 3;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// The same for work that varies from tile to tile: each XCD takes runs of C
+// consecutive tiles, and the runs go to the XCDs in turn, so that no XCD is
+// left with one dense region.  The tiles past the last whole round of 8 runs
+// keep their block's index.  A bijection on [0, ntiles).
+__device__ inline uint32_t xcd_tile_runs(uint32_t b, uint32_t ntiles, uint32_t C) {
+  const uint32_t full = ntiles / (8u * C) * (8u * C);
+  if (b >= full) return b;
+  const uint32_t x = b & 7u, j = b >> 3;
+  return ((j / C) * 8u + x) * C + j % C;
+}
+
 __device__ inline uint64_t lanemask_lt() {
   const uint32_t lane = __lane_id();
   return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));

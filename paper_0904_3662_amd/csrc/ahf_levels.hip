@@ -37,6 +37,9 @@
 namespace ahf {
 
 constexpr int kT = 256;
+// runs of consecutive tiles per XCD for kernels whose work varies by tile
+// (16: measured against 1, 4 and 64, best by a small margin)
+constexpr uint32_t kXcdRun = 16;
 
 static inline unsigned grid_for(uint64_t n, int t = kT) {
   uint64_t b = (n + t - 1) / t;
@@ -547,7 +550,7 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
   __shared__ float G[kTileH];  // the tile's cells and their one-cell halo
   __shared__ int32_t sbr[64];  // brick of each parent's children (loaded with the first loads)
   const int t = threadIdx.x;
-  const uint64_t tile = blockIdx.x;
+  const uint64_t tile = xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun);
   for (int q = t; q < kTileH; q += kTileT) G[q] = 0.0f;
   if (t < 64) sbr[t] = DENSE0 ? (int32_t)(tile * 64 + (uint64_t)t) : pslot_child[tile * 64 + (uint64_t)t];
   const uint32_t pm = (uint32_t)t >> 3, d = (uint32_t)t & 7u;
@@ -614,7 +617,7 @@ __global__ __launch_bounds__(256) void k_tile_halo_add(int dense0, int nb,
                                                       const int32_t* __restrict__ pslot_child,
                                                       const float* __restrict__ halo,
                                                       float* __restrict__ mass) {
-  const uint64_t tile = blockIdx.x;
+  const uint64_t tile = xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun);
   uint32_t tx, ty, tz;
   unmorton3(tile, tx, ty, tz);
   const uint32_t tm = (1u << nb) - 1u;
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
   __shared__ uint8_t inv[64];    // lane-dependent lookups: LDS, not the scalar cache
   const int t = threadIdx.x;
   if (t < 64) inv[t] = c_patch.inv[t];
-  const uint64_t f = (uint64_t)blockIdx.x * 32 + (t >> 3);
+  const uint64_t f = (uint64_t)xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun) * 32 + (t >> 3);
   const int d = t & 7;
   float T[27];
 #pragma unroll
@@ -726,7 +729,7 @@ __global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint6
   if (threadIdx.x < 64) lay[threadIdx.x] = c_patch.layout[threadIdx.x];
   const int lb = threadIdx.x >> 3;
   const int d = threadIdx.x & 7;
-  const uint64_t bi = (uint64_t)blockIdx.x * 32 + lb;
+  const uint64_t bi = (uint64_t)xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun) * 32 + lb;
   if (bi < nB) {
     const uint64_t P = Bkey ? Bkey[bi] : bi;
     uint32_t qx, qy, qz;
@@ -1067,10 +1070,11 @@ __global__ __launch_bounds__(256) void k_uf_local(const LabSet* __restrict__ pS,
                                                   uint32_t* __restrict__ err) {
   __shared__ int32_t lp[kUfTile];
   const LabSet& S = *pS;
-  const int k = lab_tile_entry(S, blockIdx.x);
+  const uint32_t tile = xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun);
+  const int k = lab_tile_entry(S, tile);
   const LabLev& lv = S.lv[k];
   const uint64_t o = S.off[k];
-  const uint64_t t0 = o + ((uint64_t)blockIdx.x - S.toff[k]) * kUfTile;
+  const uint64_t t0 = o + ((uint64_t)tile - S.toff[k]) * kUfTile;
   const uint64_t rest = S.off[k + 1] - t0;
   const uint32_t tn = (uint32_t)(rest < (uint64_t)kUfTile ? rest : (uint64_t)kUfTile);
   for (int i = threadIdx.x; i < kUfTile; i += 256) lp[i] = i;
@@ -1111,50 +1115,47 @@ __global__ __launch_bounds__(256) void k_uf_cross(const LabSet* __restrict__ pS,
                                                   uint32_t* __restrict__ err) {
   __shared__ unsigned long long set[kPairSlots];
   const LabSet& S = *pS;
-  const uint64_t ntiles = S.toff[S.nlev];
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int k = lab_tile_entry(S, tile);
-    const LabLev& lv = S.lv[k];
-    const uint64_t o = S.off[k];
-    const uint64_t base = o + (tile - S.toff[k]) * kUfTile;
-    for (int i = threadIdx.x; i < kPairSlots; i += 256) set[i] = ~0ull;
-    __syncthreads();
-    const uint64_t f = base + threadIdx.x;
-    if (f < S.off[k + 1]) {
-      uint32_t xm = xmask[f];
-      if (xm) {
-        const uint32_t s = lv.Fs[f - o];
-        const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
-        const int32_t ra = par[f];  // tile-local root (written by k_uf_local)
-        int32_t gs[13];
-        refined_neighbours(k, (int)lv.bits, tree, lv.slot_f, key, xm, gs, err);
+  const uint32_t tile = xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun);
+  const int k = lab_tile_entry(S, tile);
+  const LabLev& lv = S.lv[k];
+  const uint64_t o = S.off[k];
+  const uint64_t base = o + (tile - S.toff[k]) * kUfTile;
+  for (int i = threadIdx.x; i < kPairSlots; i += 256) set[i] = ~0ull;
+  __syncthreads();
+  const uint64_t f = base + threadIdx.x;
+  if (f < S.off[k + 1]) {
+    uint32_t xm = xmask[f];
+    if (xm) {
+      const uint32_t s = lv.Fs[f - o];
+      const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
+      const int32_t ra = par[f];  // tile-local root (written by k_uf_local)
+      int32_t gs[13];
+      refined_neighbours(k, (int)lv.bits, tree, lv.slot_f, key, xm, gs, err);
 #pragma unroll
-        for (int q = 0; q < 13; ++q) {
-          if (gs[q] < 0) continue;
-          const int32_t rb = par[o + (uint64_t)gs[q]];
-          const int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
-          if (lo == hi) continue;
-          const unsigned long long pk = ((unsigned long long)(uint32_t)lo << 32) | (uint32_t)hi;
-          uint32_t h = (uint32_t)((pk * 0x9E3779B97F4A7C15ull) >> 53) & (kPairSlots - 1);
-          bool mine = false, full = true;
-          for (int probe = 0; probe < kPairSlots; ++probe) {
-            const unsigned long long old = atomicCAS(&set[h], ~0ull, pk);
-            if (old == ~0ull) {
-              mine = true;
-              full = false;
-              break;
-            }
-            if (old == pk) {
-              full = false;
-              break;
-            }
-            h = (h + 1) & (kPairSlots - 1);
+      for (int q = 0; q < 13; ++q) {
+        if (gs[q] < 0) continue;
+        const int32_t rb = par[o + (uint64_t)gs[q]];
+        const int32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+        if (lo == hi) continue;
+        const unsigned long long pk = ((unsigned long long)(uint32_t)lo << 32) | (uint32_t)hi;
+        uint32_t h = (uint32_t)((pk * 0x9E3779B97F4A7C15ull) >> 53) & (kPairSlots - 1);
+        bool mine = false, full = true;
+        for (int probe = 0; probe < kPairSlots; ++probe) {
+          const unsigned long long old = atomicCAS(&set[h], ~0ull, pk);
+          if (old == ~0ull) {
+            mine = true;
+            full = false;
+            break;
           }
-          if (mine || full) uf_unite(par, lo, hi);
+          if (old == pk) {
+            full = false;
+            break;
+          }
+          h = (h + 1) & (kPairSlots - 1);
         }
+        if (mine || full) uf_unite(par, lo, hi);
       }
     }
-    __syncthreads();
   }
 }
 
@@ -1749,7 +1750,7 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
               (k_uf_local<<<(unsigned)ntiles, 256, 0, st>>>(
                   dS, tree, h->prm.conn, par, xmask, dev)));
     AHF_TIMED(ctx, "uf_cross", st,
-              (k_uf_cross<<<(unsigned)std::min<uint64_t>(ntiles, 1u << 20), 256, 0, st>>>(
+              (k_uf_cross<<<(unsigned)ntiles, 256, 0, st>>>(
                   dS, tree, xmask, par, dev)));
     k_uf_compress<<<grid_for(tot), kT, 0, st>>>(par, tot, root, pred, tot, pncells,
                                                 (unsigned long long*)pnpart, mfix);

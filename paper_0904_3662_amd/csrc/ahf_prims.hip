@@ -206,7 +206,8 @@ __global__ __launch_bounds__(kRsT) void k_rs_up(const uint64_t* __restrict__ in,
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0u;
   __syncthreads();
-  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
+  const uint64_t tile0 = (uint64_t)tile * kRsTile;
   uint64_t key[kRsR];
 #pragma unroll
   for (int r = 0; r < kRsR; ++r) {
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(kRsT) void k_rs_up(const uint64_t* __restrict__ in,
     if (j < n) atomicAdd(&h[(uint32_t)(key[r] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  th[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  th[(uint64_t)threadIdx.x * ntiles + tile] = h[threadIdx.x];
 }
 
 constexpr int kTsT = 1024;
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(kRsT) void k_rs_down(
   __shared__ uint32_t lds[kRsT / 64 + 1];
   const int w = threadIdx.x >> 6;
   const uint32_t lane = __lane_id();
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = xcd_tile(blockIdx.x, ntiles);
   const uint32_t base_off = tofs[(uint64_t)threadIdx.x * ntiles + tile];
   for (int i = threadIdx.x; i < kRsW * 256; i += kRsT) (&cnt[0][0])[i] = 0u;
   __syncthreads();
