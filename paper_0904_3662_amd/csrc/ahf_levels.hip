@@ -563,10 +563,12 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
 #pragma unroll
   for (int k = 0; k < 27; ++k) T[k] = 0.0f;
   const uint32_t r = DENSE0 ? 0u : prank[pg];
+  bool has = false;  // the cell holds particles (an empty cell adds only zeros)
   if (DENSE0 || r != 0xffffffffu) {
     const uint64_t s = DENSE0 ? pg * 8 + d : (uint64_t)r * 8 + d;
     const uint32_t n = Scount[s];
     const uint32_t a0 = Sstart[s];
+    has = n > 0;
     double ms = 0.0;
     if (n > (uint32_t)kHeavy) {
       const int32_t h = hidx[s];
@@ -576,7 +578,15 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
     } else if (DENSE0) {
       add_range(P, a0, n, mask, scale, T, ms);
     } else {
-      for (uint32_t i = 0; i < n; ++i) add_particle(P, a0 + i, mask, scale, T, ms);
+      // level-1 cells hold about one particle: two records in flight at once
+      uint32_t i = 0;
+      for (; i + 2 <= n; i += 2) {
+        const uint4 q0 = P.rec[2 * (uint64_t)(a0 + i)], q1 = P.rec[2 * (uint64_t)(a0 + i) + 1];
+        const uint4 q2 = P.rec[2 * (uint64_t)(a0 + i + 1)], q3 = P.rec[2 * (uint64_t)(a0 + i + 1) + 1];
+        add_record(q0, q1, mask, scale, T, ms);
+        add_record(q2, q3, mask, scale, T, ms);
+      }
+      if (i < n) add_particle(P, a0 + i, mask, scale, T, ms);
     }
     if (Spmass) Spmass[s] = ms;
   }
@@ -592,7 +602,7 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int q = g0 + ((a - 1) * kTileG + (b - 1)) * kTileG + (c - 1);
-        G[q] += T[a * 9 + b * 3 + c];
+        if (has) G[q] += T[a * 9 + b * 3 + c];
         __syncthreads();
       }
   for (int q = t; q < kTileH; q += kTileT) {
