@@ -446,39 +446,51 @@ __global__ __launch_bounds__(256) void k_heavy_chunk(
   }
 }
 
-// pairwise (binary-counter) sum over the chunks of each heavy cell
-__global__ void k_heavy_reduce(const uint32_t* __restrict__ nch, const uint32_t* __restrict__ chofs,
-                               const uint32_t* __restrict__ nHdev, const float* __restrict__ chT,
-                               const double* __restrict__ chM, float* __restrict__ hT,
-                               double* __restrict__ hM) {
+// the chunks of each heavy cell summed by one wave: each run of 64 chunks
+// (one per lane) as a pairwise tree (a butterfly, which leaves the same sum
+// on every lane), the runs in chunk order; lane k keeps component k (the
+// mass on lane 27).  A cell of one chunk is copied.
+__global__ __launch_bounds__(256) void k_heavy_reduce(const uint32_t* __restrict__ nch,
+                                                      const uint32_t* __restrict__ chofs,
+                                                      const uint32_t* __restrict__ nHdev,
+                                                      const float* __restrict__ chT,
+                                                      const double* __restrict__ chM,
+                                                      float* __restrict__ hT,
+                                                      double* __restrict__ hM) {
   const uint64_t nH = *nHdev;
-  GRID_STRIDE(i, nH * 28) {
-    const uint64_t h = i / 28;
-    const int k = (int)(i % 28);
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint64_t h = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); h < nH;
+       h += (uint64_t)gridDim.x * 4) {
     const uint32_t o = chofs[h], m = nch[h];
-    if (k < 27) {
-      float st[33];
-      int top = 0;
-      for (uint32_t q = 0; q < m; ++q) {
-        float v = chT[(uint64_t)(o + q) * 27 + k];
-        for (uint32_t c = q + 1; (c & 1u) == 0u; c >>= 1) v = st[--top] + v;
-        st[top++] = v;
-      }
-      float s = 0.0f;
-      while (top > 0) s = st[--top] + s;
-      hT[h * 27 + k] = s;
-    } else {
-      double st[33];
-      int top = 0;
-      for (uint32_t q = 0; q < m; ++q) {
-        double v = chM[o + q];
-        for (uint32_t c = q + 1; (c & 1u) == 0u; c >>= 1) v = st[--top] + v;
-        st[top++] = v;
-      }
-      double s = 0.0;
-      while (top > 0) s = st[--top] + s;
-      hM[h] = s;
+    if (m == 1) {  // most heavy cells: one chunk, copied
+      if (lane < 27) hT[h * 27 + lane] = chT[(uint64_t)o * 27 + lane];
+      if (lane == 27) hM[h] = chM[o];
+      continue;
     }
+    float acc = 0.0f;
+    double accm = 0.0;
+    for (uint32_t g = 0; g < m; g += 64) {
+      const bool v = g + lane < m;
+      const uint64_t c = (uint64_t)o + g + lane;
+      float w[27];
+#pragma unroll
+      for (int k = 0; k < 27; ++k) w[k] = v ? chT[c * 27 + k] : 0.0f;
+      double wm = v ? chM[c] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 27; ++k)
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) w[k] += __shfl_xor(w[k], d, 64);
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) wm += __shfl_xor(wm, d, 64);
+      float mine = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 27; ++k)
+        if (lane == (uint32_t)k) mine = w[k];
+      acc += mine;
+      accm += wm;
+    }
+    if (lane < 27) hT[h * 27 + lane] = acc;
+    if (lane == 27) hM[h] = accm;
   }
 }
 
@@ -1555,7 +1567,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       AHF_TIMED(ctx, "heavy_chunk", st,
                 (k_heavy_chunk<<<(unsigned)std::min<uint64_t>((maxch + 3) / 4, 2048), 256, 0, st>>>(
                     hl.nchunks, hl.ch_a, hl.ch_n, P, mask, scale, chT, chM)));
-      k_heavy_reduce<<<std::min(grid_for(maxH * 28), 1024u), kT, 0, st>>>(
+      k_heavy_reduce<<<(unsigned)std::min<uint64_t>((maxH + 3) / 4, 2048), 256, 0, st>>>(
           hl.nch, hl.chofs, hl.nheavy, chT, chM, hT, hM);
       HIP_LAUNCH_CHECK();
     }
