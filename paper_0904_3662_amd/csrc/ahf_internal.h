@@ -160,8 +160,8 @@ struct Owned {
 // ---------------------------------------------------------------- primitives
 // Indices of the nonzero bytes of flags[0, n) in increasing order: list[r]
 // = index of the r-th flagged element and/or rank[i] = r for each flagged i
-// (either may be null; rank is left untouched at unflagged indices); *count
-// (device) = number of flagged elements.
+// (either may be null; an unflagged i keeps its value or becomes all ones);
+// *count (device) = number of flagged elements.
 void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uint32_t* rank,
                    uint32_t* count, hipStream_t st);
 // Stable LSD sort of particles by Morton key (key_bits bits), ties by index,

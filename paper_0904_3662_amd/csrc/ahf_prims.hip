@@ -101,7 +101,10 @@ __global__ __launch_bounds__(kCfMidT) void k_cf_mid(const uint32_t* __restrict__
 }
 
 // tile offset: from the scanned tile counts (tofs), or summed here from the
-// tile counts of the tiles before this one (tcnt, few tiles), or 0 (one tile)
+// tile counts of the tiles before this one (tcnt, few tiles), or 0 (one tile).
+// The list goes out through LDS, one contiguous run per tile; a thread with
+// any flag set writes the ranks of its 32 flags as one 128-byte run (all
+// ones where the flag is clear).
 __global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ flags, uint64_t n,
                                                  const uint32_t* __restrict__ tcnt,
                                                  const uint32_t* __restrict__ tofs,
@@ -109,22 +112,42 @@ __global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ fl
                                                  uint32_t* __restrict__ rank,
                                                  uint32_t* __restrict__ count) {
   __shared__ uint32_t lds[kCfT / 64 + 1];
-  const uint64_t i0 = (uint64_t)blockIdx.x * kCfTile + (uint64_t)threadIdx.x * kCfPer;
+  __shared__ uint32_t stage[kCfTile];
+  const uint64_t t0 = (uint64_t)blockIdx.x * kCfTile;
+  const uint64_t i0 = t0 + (uint64_t)threadIdx.x * kCfPer;
   uint32_t before = 0;
   if (!tofs && tcnt)
     for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kCfT) before += tcnt[t];
-  uint32_t m = cf_bits(flags, n, i0);
+  const uint32_t m = cf_bits(flags, n, i0);
   uint32_t tot, tb;
   if (!tofs && tcnt) block_excl_scan<kCfT>(before, tb, lds);
-  uint32_t pos = block_excl_scan<kCfT>((uint32_t)__popc(m), tot, lds);
+  const uint32_t lpos = block_excl_scan<kCfT>((uint32_t)__popc(m), tot, lds);
   const uint32_t base = tofs ? tofs[blockIdx.x] : (tcnt ? tb : 0u);
-  pos += base;
-  while (m) {
-    const int k = __ffs(m) - 1;
-    m &= m - 1u;
-    if (list) list[pos] = (uint32_t)(i0 + k);
-    if (rank) rank[i0 + k] = pos;
-    ++pos;
+  if (list) {
+    uint32_t mm = m, p = lpos;
+    while (mm) {
+      const int k = __ffs(mm) - 1;
+      mm &= mm - 1u;
+      stage[p++] = (uint32_t)(i0 + k);
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < tot; j += kCfT) list[base + j] = stage[j];
+  }
+  if (rank && m) {
+    uint32_t r[kCfPer];
+    uint32_t p = base + lpos;
+#pragma unroll
+    for (int k = 0; k < kCfPer; ++k) r[k] = ((m >> k) & 1u) ? p++ : 0xffffffffu;
+    if (i0 + kCfPer <= n) {
+      uint4* o = reinterpret_cast<uint4*>(rank + i0);
+#pragma unroll
+      for (int k = 0; k < kCfPer / 4; ++k)
+        o[k] = make_uint4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kCfPer; ++k)
+        if (i0 + k < n) rank[i0 + k] = r[k];
+    }
   }
   if (count && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *count = base + tot;
 }
