@@ -277,6 +277,7 @@ ahf_status ahf_ctx_create(const ahf_ctx_desc* desc, ahf_ctx** out) {
   c->c.free = desc->free;
   c->c.user = desc->user;
   c->ws.bind(&c->c, nullptr);
+  c->ws_dep.bind(&c->c, nullptr);
   *out = c;
   return AHF_OK;
 }
@@ -286,6 +287,10 @@ void ahf_ctx_destroy(ahf_ctx* ctx) {
   (void)hipSetDevice(ctx->c.device);
   (void)hipDeviceSynchronize();
   ctx->ws.free_all();
+  ctx->ws_dep.free_all();
+  if (ctx->c.dep_st) (void)hipStreamDestroy(ctx->c.dep_st);
+  if (ctx->c.dep_ev) (void)hipEventDestroy(ctx->c.dep_ev);
+  if (ctx->c.join_ev) (void)hipEventDestroy(ctx->c.join_ev);
   if (ctx->c.host_cnt) (void)hipHostFree(ctx->c.host_cnt);
   if (ctx->c.cnt_ev) (void)hipEventDestroy(ctx->c.cnt_ev);
   for (auto& e : ctx->c.phase_ev)
@@ -315,21 +320,28 @@ ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, con
     h->h.mem.st = st;
     ctx->ws.bind(&ctx->c, st);
     ctx->ws.reset();
+    ctx->ws_dep.bind(&ctx->c, st);
+    ctx->ws_dep.reset();
     // with equal masses the labels need nothing from the build's totals: they
     // are enqueued behind it, and one wait at the end covers both
     const bool labels = !(prm.flags & AHF_NO_LABELS);
     const bool defer = labels && particles->mass == nullptr;
-    build_hierarchy(&ctx->c, ctx->ws, *particles, prm, st, &h->h, !defer);
+    build_hierarchy(&ctx->c, ctx->ws, ctx->ws_dep, *particles, prm, st, &h->h, !defer);
     if (labels) label_hierarchy(&ctx->c, ctx->ws, &h->h, st);
     if (defer) finish_build(&ctx->c, &h->h);
     ctx->ws.reset();
+    ctx->ws_dep.reset();
   } catch (const Error& e) {
+    // both streams idle before any scratch is reused or freed
+    if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
     (void)hipStreamSynchronize(st);
     h->h.mem.release_all();
     delete h;
     ctx->ws.reset();
+    ctx->ws_dep.reset();
     return fail(e.code, e.msg);
   } catch (const std::bad_alloc&) {
+    if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
     (void)hipStreamSynchronize(st);
     h->h.mem.release_all();
     delete h;

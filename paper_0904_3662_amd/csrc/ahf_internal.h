@@ -76,6 +76,11 @@ struct Ctx {
   double* host_tot = nullptr;  // level totals and the error word (same allocation)
   hipEvent_t cnt_ev = nullptr;
   hipEvent_t phase_ev[3] = {nullptr, nullptr, nullptr};
+  // the second stream of a build: level L's deposit runs there while the
+  // build stream makes the cells of level L+1; dep_ev hands a level to it,
+  // join_ev hands the finished deposits back
+  hipStream_t dep_st = nullptr;
+  hipEvent_t dep_ev = nullptr, join_ev = nullptr;
 };
 
 
@@ -236,8 +241,11 @@ struct Hier {
 // Enqueues the build on st.  With finish, waits for it and completes h
 // (totals, timings, device error flags); without, the caller must call
 // finish_build once the stream has passed the build (labels may run first).
-void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm, hipStream_t st,
-                     Hier* h, bool finish = true);
+// With the count criterion every level's deposit runs on ctx->dep_st, with
+// its scratch from wsd (kept until the build ends; the deposits are joined
+// back into st before the build's last kernels).
+void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Params& prm,
+                     hipStream_t st, Hier* h, bool finish = true);
 void finish_build(Ctx* ctx, Hier* h);
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
 // host structures and substructures of a labelled hierarchy (waits for it);
@@ -259,6 +267,7 @@ void set_last_error(const std::string& msg);  // message returned by ahf_last_er
 struct ahf_ctx {
   ahf::Ctx c;
   ahf::Ws ws;
+  ahf::Ws ws_dep;  // scratch of the deposits running on the second stream
 };
 
 struct ahf_hierarchy {

@@ -903,17 +903,14 @@ __global__ void k_mark(int L, int bits, const uint32_t* __restrict__ nFdev,
 
 // next level's bricks (one per marked slot, in key order by rank); a refined
 // cell's slot is always marked, so its F entry is finished here too: its
-// children's brick, and F_L moved to its final buffer.  Also clears the
-// heavy-cell counters for the next level.
+// children's brick, and F_L moved to its final buffer.
 __global__ void k_build_bricks(uint64_t nslot, const uint8_t* __restrict__ mark,
                                const uint32_t* __restrict__ rank,
                                const uint64_t* __restrict__ Bkey,
                                const int32_t* __restrict__ slot_f,
                                int32_t* __restrict__ slot_child, uint64_t* __restrict__ nBkey,
                                int32_t* __restrict__ nBcell, const uint32_t* __restrict__ Ftmp,
-                               uint32_t* __restrict__ Fs, int32_t* __restrict__ nPbrick,
-                               uint32_t* __restrict__ clear2) {
-  if (blockIdx.x == 0 && threadIdx.x < 2) clear2[threadIdx.x] = 0u;
+                               uint32_t* __restrict__ Fs, int32_t* __restrict__ nPbrick) {
   GRID_STRIDE(i, nslot) {
     if (mark[i]) {
       const uint32_t r = rank[i];
@@ -1391,8 +1388,8 @@ static Tree make_tree(const Hier* h) {
   return t;
 }
 
-void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm, hipStream_t st,
-                     Hier* h, bool finish) {
+void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Params& prm,
+                     hipStream_t st, Hier* h, bool finish) {
   const double t0 = now_ms();
   h->prm = prm;
   h->n = p.n;
@@ -1412,9 +1409,12 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     for (auto& e : ctx->phase_ev) HIP_CHECK(hipEventCreateWithFlags(&e, kTimingEventFlags));
   }
   HIP_CHECK(hipEventRecord(ctx->phase_ev[0], st));
-  uint32_t* dev_u32 = ws.get<uint32_t>(8);   // [0] error flags, [1..] counters
+  // [0] error flags, [1..7] per-level counters, [8 + 2L], [9 + 2L] heavy
+  // cells and chunks of level L
+  constexpr int kDevU32 = 8 + 2 * kMaxLevels;
+  uint32_t* dev_u32 = ws.get<uint32_t>(kDevU32);
   double* dev_tot = ws.get<double>(3 * kMaxLevels);
-  HIP_CHECK(hipMemsetAsync(dev_u32, 0, 8 * sizeof(uint32_t), st));
+  HIP_CHECK(hipMemsetAsync(dev_u32, 0, kDevU32 * sizeof(uint32_t), st));
   HIP_CHECK(hipMemsetAsync(dev_tot, 0, 3 * kMaxLevels * sizeof(double), st));
   uint32_t* err = dev_u32;
   ctx->dev_err = err;
@@ -1446,6 +1446,19 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
   HIP_CHECK(hipEventRecord(ctx->phase_ev[1], st));
 
   // ---- levels
+  // With the count criterion a level's deposit needs only its cells and its
+  // heavy-cell lists: it runs on the second stream while this one goes on
+  // to the next level's cells.  (The density criterion needs the deposit
+  // for the flags: one stream.)
+  const bool density = (prm.flags & AHF_DENSITY_CRITERION) != 0;
+  const bool overlap = !density;
+  if (overlap && !ctx->dep_st) {
+    HIP_CHECK(hipStreamCreateWithFlags(&ctx->dep_st, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&ctx->dep_ev, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+  }
+  hipStream_t ds = overlap ? ctx->dep_st : st;
+  Ws& wd = overlap ? wsd : ws;  // deposit scratch: kept to the end of the build when overlapped
   uint64_t nFp = 1ull << (3 * (g - 1));  // parents of level 0: the virtual level -1
   uint64_t nB = nFp;
   uint64_t* Bkey = nullptr;
@@ -1493,21 +1506,20 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
 
     // refinement flags and the cells too full for one thread
     const int can_refine = (L < prm.Lmax && b < kQBits) ? 1 : 0;
-    const bool density = (prm.flags & AHF_DENSITY_CRITERION) != 0;
     const double thr = (L == 0) ? prm.dom_ref : prm.ref_ref;
     // heavy-cell lists, sized by bounds: at most n/65 cells above 64
     // particles, at most that many plus n/4096 chunks
     const uint64_t maxH = std::min<uint64_t>(lv.nS, n / (kHeavy + 1) + 1);
     const uint64_t maxch = maxH + n / kChunk + 1;
     HeavyList hl;
-    hl.nheavy = dev_u32 + 2;  // both counters are zero here: cleared at the start
-    hl.nchunks = dev_u32 + 3; // and by k_build_bricks of the previous level
-    hl.Hs = ws.get<uint32_t>(maxH);
-    hl.hidx = ws.get<int32_t>(lv.nS);  // read only for cells above kHeavy
-    hl.nch = ws.get<uint32_t>(maxH);
-    hl.chofs = ws.get<uint32_t>(maxH);
-    hl.ch_a = ws.get<uint32_t>(maxch);
-    hl.ch_n = ws.get<uint32_t>(maxch);
+    hl.nheavy = dev_u32 + 8 + 2 * L;   // the level's own counters, zero from the start
+    hl.nchunks = dev_u32 + 9 + 2 * L;
+    hl.Hs = wd.get<uint32_t>(maxH);
+    hl.hidx = wd.get<int32_t>(lv.nS);  // read only for cells above kHeavy
+    hl.nch = wd.get<uint32_t>(maxH);
+    hl.chofs = wd.get<uint32_t>(maxH);
+    hl.ch_a = wd.get<uint32_t>(maxch);
+    hl.ch_n = wd.get<uint32_t>(maxch);
     const int32_t* hidx = hl.hidx;
     // with the count criterion the flags come here; with the density
     // criterion they need the level's deposit and come after it
@@ -1517,6 +1529,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
                                             lv.Sflag, hl,
                                             (L == 0 && !density) ? rank0 : nullptr);
     HIP_LAUNCH_CHECK();
+    if (overlap) {
+      // the level's cells and heavy lists are complete: its deposit may start
+      HIP_CHECK(hipEventRecord(ctx->dep_ev, st));
+      HIP_CHECK(hipStreamWaitEvent(ds, ctx->dep_ev, 0));
+    }
     uint32_t* Ftmp = ws.get<uint32_t>(lv.nS);
     uint32_t* rankF = (L == 0 && rank0) ? rank0 : ws.get<uint32_t>(lv.nS);
     const uint64_t nslot = 8 * nB;
@@ -1559,15 +1576,15 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
 
     // heavy cells: chunked wave sums (sizes from the device counts; buffers
     // and grids from the bound maxH)
-    float* hT = ws.get<float>(maxH * 27);
-    double* hM = ws.get<double>(maxH);
+    float* hT = wd.get<float>(maxH * 27);
+    double* hM = wd.get<double>(maxH);
     {
-      float* chT = ws.get<float>(maxch * 27);
-      double* chM = ws.get<double>(maxch);
-      AHF_TIMED(ctx, "heavy_chunk", st,
-                (k_heavy_chunk<<<(unsigned)std::min<uint64_t>((maxch + 3) / 4, 2048), 256, 0, st>>>(
+      float* chT = wd.get<float>(maxch * 27);
+      double* chM = wd.get<double>(maxch);
+      AHF_TIMED(ctx, "heavy_chunk", ds,
+                (k_heavy_chunk<<<(unsigned)std::min<uint64_t>((maxch + 3) / 4, 2048), 256, 0, ds>>>(
                     hl.nchunks, hl.ch_a, hl.ch_n, P, mask, scale, chT, chM)));
-      k_heavy_reduce<<<(unsigned)std::min<uint64_t>((maxH + 3) / 4, 2048), 256, 0, st>>>(
+      k_heavy_reduce<<<(unsigned)std::min<uint64_t>((maxH + 3) / 4, 2048), 256, 0, ds>>>(
           hl.nch, hl.chofs, hl.nheavy, chT, chM, hT, hM);
       HIP_LAUNCH_CHECK();
     }
@@ -1581,32 +1598,32 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     if (tiles0 || tiles1) {
       const int pb = tiles0 ? g - 1 : g;  // bits per axis of the parent grid
       const uint64_t ntiles = 1ull << (3 * (pb - 2));
-      float* halo = ws.get<float>(ntiles * kTileH);
+      float* halo = wd.get<float>(ntiles * kTileH);
       const Level& l0 = h->lev[0];
       if (tiles0)
-        AHF_TIMED(ctx, "patches", st,
-                  (k_tile_deposit<true><<<(unsigned)ntiles, kTileT, 0, st>>>(
+        AHF_TIMED(ctx, "patches", ds,
+                  (k_tile_deposit<true><<<(unsigned)ntiles, kTileT, 0, ds>>>(
                       nullptr, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, nullptr,
                       lv.mass, halo, lv.Spmass)));
       else
-        AHF_TIMED(ctx, "patches", st,
-                  (k_tile_deposit<false><<<(unsigned)ntiles, kTileT, 0, st>>>(
+        AHF_TIMED(ctx, "patches", ds,
+                  (k_tile_deposit<false><<<(unsigned)ntiles, kTileT, 0, ds>>>(
                       rank0, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, l0.slot_child,
                       lv.mass, halo, lv.Spmass)));
-      AHF_TIMED(ctx, "combine", st,
-                (k_tile_halo_add<<<(unsigned)ntiles, 256, 0, st>>>(
+      AHF_TIMED(ctx, "combine", ds,
+                (k_tile_halo_add<<<(unsigned)ntiles, 256, 0, ds>>>(
                     tiles0 ? 1 : 0, pb - 2, tiles0 ? nullptr : l0.slot_child, halo, lv.mass)));
     } else {
-      float* patch = ws.get<float>(nFp * 64);
+      float* patch = wd.get<float>(nFp * 64);
       if (nFp) {
-        AHF_TIMED(ctx, "patches", st,
-                  (k_patches<<<(unsigned)((nFp + 31) / 32), 256, 0, st>>>(
+        AHF_TIMED(ctx, "patches", ds,
+                  (k_patches<<<(unsigned)((nFp + 31) / 32), 256, 0, ds>>>(
                       nFp, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, patch, lv.Spmass)));
       }
       Tree tree = make_tree(h);
       const int32_t* pslot_f = (L > 0) ? h->lev[L - 1].slot_f : nullptr;
-      AHF_TIMED(ctx, "combine", st,
-                (k_combine<<<(unsigned)((nB + 31) / 32), 256, 0, st>>>(L, nB, Bkey, b - 1, tree,
+      AHF_TIMED(ctx, "combine", ds,
+                (k_combine<<<(unsigned)((nB + 31) / 32), 256, 0, ds>>>(L, nB, Bkey, b - 1, tree,
                                                                        pslot_f, patch, lv.mass)));
     }
     if (density) {
@@ -1621,7 +1638,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
       int nblk = (int)((nmax + 255) / 256);
       if (nblk > kSumBlocks) nblk = kSumBlocks;
       if (nblk < 1) nblk = 1;
-      k_level_sums<<<nblk, 256, 0, st>>>(lv.mass, 8 * nB, lv.Spmass, lv.nS, lv.Scount, lv.nS,
+      k_level_sums<<<nblk, 256, 0, ds>>>(lv.mass, 8 * nB, lv.Spmass, lv.nS, lv.Scount, lv.nS,
                                          part_all + (uint64_t)L * 3 * kSumBlocks);
       HIP_LAUNCH_CHECK();
       sum_blocks.n[L] = nblk;
@@ -1647,7 +1664,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     int32_t* nPbrick = h->mem.get<int32_t>(lv.nF);
     k_build_bricks<<<grid_for(nslot), kT, 0, st>>>(nslot, mark, rank, lv.Bkey, lv.slot_f,
                                                    lv.slot_child, nBkey, nBcell, Ftmp, lv.Fs,
-                                                   nPbrick, dev_u32 + 2);
+                                                   nPbrick);
     HIP_LAUNCH_CHECK();
     nFp = lv.nF;
     nB = nD;
@@ -1657,6 +1674,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, const ahf_particles& p, const Params& prm
     ws.release(lvl_mark);
   }
 
+  if (overlap) {
+    // the deposits back into the build stream
+    HIP_CHECK(hipEventRecord(ctx->join_ev, ds));
+    HIP_CHECK(hipStreamWaitEvent(st, ctx->join_ev, 0));
+  }
   // every level's totals from its partial sums, one block per level
   k_level_sums_final<<<(unsigned)h->lev.size(), 256, 0, st>>>(part_all, sum_blocks, dev_tot);
   HIP_LAUNCH_CHECK();
