@@ -241,9 +241,11 @@ __device__ inline uint32_t wave_excl_scan_u32(uint32_t v) {
 // atomic per counter reserves the block's indices, a second pass writes them.
 // (Atomics on one address from different blocks are served one after
 // another far from the CU, so their number sets the cost: the grid is kept
-// small.)
-constexpr int kFlagT = 1024;
-constexpr unsigned kFlagBlocks = 256;
+// small.  Blocks of 512 threads fit into the wave slots that one block of
+// the previous level's tile deposit, running beside on the other stream,
+// frees; blocks of 1024 waited for that whole kernel.)
+constexpr int kFlagT = 512;
+constexpr unsigned kFlagBlocks = 512;
 
 __global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ count,
                                                   const uint32_t* __restrict__ start, uint64_t nS,
