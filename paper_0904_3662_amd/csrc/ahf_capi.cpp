@@ -289,6 +289,9 @@ void ahf_ctx_destroy(ahf_ctx* ctx) {
   ctx->ws.free_all();
   ctx->ws_dep.free_all();
   if (ctx->c.dep_st) (void)hipStreamDestroy(ctx->c.dep_st);
+  if (ctx->c.lab_st) (void)hipStreamDestroy(ctx->c.lab_st);
+  if (ctx->c.lab_ev) (void)hipEventDestroy(ctx->c.lab_ev);
+  if (ctx->c.lab_pinned) (void)hipHostFree(ctx->c.lab_pinned);
   if (ctx->c.dep_ev) (void)hipEventDestroy(ctx->c.dep_ev);
   if (ctx->c.join_ev) (void)hipEventDestroy(ctx->c.join_ev);
   if (ctx->c.host_cnt) (void)hipHostFree(ctx->c.host_cnt);
@@ -332,8 +335,9 @@ ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, con
     ctx->ws.reset();
     ctx->ws_dep.reset();
   } catch (const Error& e) {
-    // both streams idle before any scratch is reused or freed
+    // every stream idle before any scratch is reused or freed
     if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
+    if (ctx->c.lab_st) (void)hipStreamSynchronize(ctx->c.lab_st);
     (void)hipStreamSynchronize(st);
     h->h.mem.release_all();
     delete h;
@@ -342,6 +346,7 @@ ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, con
     return fail(e.code, e.msg);
   } catch (const std::bad_alloc&) {
     if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
+    if (ctx->c.lab_st) (void)hipStreamSynchronize(ctx->c.lab_st);
     (void)hipStreamSynchronize(st);
     h->h.mem.release_all();
     delete h;

@@ -81,6 +81,12 @@ struct Ctx {
   // join_ev hands the finished deposits back
   hipStream_t dep_st = nullptr;
   hipEvent_t dep_ev = nullptr, join_ev = nullptr;
+  // the third stream: the labels of the first levels, run while the build
+  // stream makes the last, small levels; the level sets of the two label
+  // passes are handed to the device from pinned memory
+  hipStream_t lab_st = nullptr;
+  hipEvent_t lab_ev = nullptr;
+  void* lab_pinned = nullptr;
 };
 
 
@@ -228,6 +234,8 @@ struct Hier {
   double mass_scalar = 1.0;
   bool labelled = false;
   uint32_t* npatch_dev = nullptr;  // [kMaxLevels] patch counts on the device (labelled)
+  uint32_t* lab_dev = nullptr;     // label error flags and counts (npatch_dev = lab_dev + 4)
+  uint32_t lab_done = 0;           // levels whose refined cells were labelled during the build
   // host structures and substructures of the grid tree (classified)
   bool classified = false;
   uint64_t nStruct = 0;
@@ -248,6 +256,10 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
                      hipStream_t st, Hier* h, bool finish = true);
 void finish_build(Ctx* ctx, Hier* h);
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
+// labels the refined cells of levels 0 .. k1-1 on ctx->lab_st once st has
+// passed their cells, with scratch from wsd (kept); label_hierarchy then
+// labels the rest after them
+void label_early(Ctx* ctx, Ws& wsd, Hier* h, uint32_t k1, hipStream_t st);
 // host structures and substructures of a labelled hierarchy (waits for it);
 // classify_levels only enqueues, finish_classify waits and reads the count
 void classify_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);

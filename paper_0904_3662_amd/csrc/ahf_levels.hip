@@ -40,6 +40,9 @@ constexpr int kT = 256;
 // runs of consecutive tiles per XCD for kernels whose work varies by tile
 // (16: measured against 1, 4 and 64, best by a small margin)
 constexpr uint32_t kXcdRun = 16;
+// the labels of the first levels start once a level has fewer cells
+// (2^16: measured against never, 2^18 and 2^20 on the 16.8M workload)
+constexpr uint64_t kLabEarlyCells = 1ull << 16;
 
 static inline unsigned grid_for(uint64_t n, int t = kT) {
   uint64_t b = (n + t - 1) / t;
@@ -1057,6 +1060,9 @@ struct LabLev {
   const int32_t* slot_f;   // level-k slot -> index in F_k, or -1
   const uint32_t* Scount;  // particles per cell of S_k
   const double* Spmass;    // particle mass per cell of S_k, or null
+  int32_t* Spatch;         // out: patch of each cell of S_{k+1}
+  const int32_t* pSpatch;  // patch of each cell of S_k (null on level 0)
+  uint32_t level;          // k
   uint32_t bits;           // bits per axis of level k
 };
 struct LabSet {
@@ -1107,7 +1113,7 @@ __global__ __launch_bounds__(256) void k_uf_local(const LabSet* __restrict__ pS,
     const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
     uint32_t xm = 0;
     int32_t gs[13];
-    refined_neighbours(k, (int)lv.bits, tree, lv.slot_f, key, cm, gs, err);
+    refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, cm, gs, err);
 #pragma unroll
     for (int q = 0; q < 13; ++q) {
       if (gs[q] < 0) continue;
@@ -1151,7 +1157,7 @@ __global__ __launch_bounds__(256) void k_uf_cross(const LabSet* __restrict__ pS,
       const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
       const int32_t ra = par[f];  // tile-local root (written by k_uf_local)
       int32_t gs[13];
-      refined_neighbours(k, (int)lv.bits, tree, lv.slot_f, key, xm, gs, err);
+      refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, xm, gs, err);
 #pragma unroll
       for (int q = 0; q < 13; ++q) {
         if (gs[q] < 0) continue;
@@ -1205,8 +1211,7 @@ __global__ void k_uf_compress(int32_t* par, uint64_t n, int32_t* __restrict__ ro
 // patch count.
 __global__ void k_uf_label(const LabSet* __restrict__ pS, const int32_t* __restrict__ root,
                            const uint32_t* __restrict__ rank, const uint32_t* __restrict__ nroots,
-                           int32_t* __restrict__ lab, int32_t* __restrict__ Spatch,
-                           uint32_t* __restrict__ npatch) {
+                           int32_t* __restrict__ lab, uint32_t* __restrict__ npatch) {
   const LabSet& S = *pS;
   const uint64_t n = S.off[S.nlev];
   GRID_STRIDE(i, n) {
@@ -1215,12 +1220,12 @@ __global__ void k_uf_label(const LabSet* __restrict__ pS, const int32_t* __restr
     const uint32_t r0 = rank[o];
     const int32_t l = (int32_t)(rank[root[i]] - r0);
     lab[i] = (int32_t)(o + (uint64_t)l);
-    int4* out = reinterpret_cast<int4*>(Spatch + 8 * i);
+    int4* out = reinterpret_cast<int4*>(S.lv[k].Spatch + 8 * (i - o));
     out[0] = make_int4(l, l, l, l);
     out[1] = make_int4(l, l, l, l);
     if (i == o) {
       const uint64_t o1 = S.off[k + 1];
-      npatch[k + 1] = (o1 < n ? rank[o1] : *nroots) - r0;
+      npatch[S.lv[k].level + 1] = (o1 < n ? rank[o1] : *nroots) - r0;
     }
   }
 }
@@ -1340,8 +1345,7 @@ __global__ __launch_bounds__(256) void k_patch_stats(const LabSet* __restrict__ 
 // root's cell, none on level 1) and the mass (fixed point back to FP64, or
 // count x mass)
 __global__ void k_patch_parent(const LabSet* __restrict__ pS, const int32_t* __restrict__ root,
-                               const int32_t* __restrict__ lab,
-                               const int32_t* __restrict__ Spatch, int32_t* __restrict__ parent,
+                               const int32_t* __restrict__ lab, int32_t* __restrict__ parent,
                                const unsigned long long* __restrict__ npart,
                                const unsigned long long* __restrict__ mfix, double mscalar,
                                double inv_scale, double* __restrict__ pm) {
@@ -1351,7 +1355,8 @@ __global__ void k_patch_parent(const LabSet* __restrict__ pS, const int32_t* __r
     if (root[f] == (int32_t)f) {
       const int32_t p = lab[f];
       const int k = lab_entry(S, f);
-      parent[p] = k > 0 ? Spatch[8 * S.off[k - 1] + S.lv[k].Fs[f - S.off[k]]] : -1;
+      const int32_t* ps = S.lv[k].pSpatch;
+      parent[p] = ps ? ps[S.lv[k].Fs[f - S.off[k]]] : -1;
       pm[p] = mfix ? (double)mfix[p] * inv_scale : (double)npart[p] * mscalar;
     }
   }
@@ -1471,9 +1476,15 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   uint32_t* rank0 = nullptr;  // rank of each refined level-0 cell in F_0 (dense tiles)
   double* part_all = ws.get<double>((uint64_t)kMaxLevels * 3 * kSumBlocks);
   SumBlocks sum_blocks;
+  // equal masses: the labels need only the cells, so those of the first
+  // levels start, on a third stream, as soon as the levels get small (the
+  // last levels leave most of the GPU idle)
+  const bool early_labels = overlap && !(prm.flags & AHF_NO_LABELS) && !h->has_mass;
   for (int L = 0; L <= prm.Lmax; ++L) {
     h->lev.emplace_back();
     Level& lv = h->lev.back();
+    if (early_labels && L >= 2 && h->lab_done == 0 && 8 * nFp < kLabEarlyCells)
+      label_early(ctx, wsd, h, (uint32_t)L, st);
     const int b = g + L;
     lv.b = (uint32_t)b;
     const int sh = 3 * (B - b);
@@ -1732,17 +1743,29 @@ void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys
   ws.release(m);
 }
 
-void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
-  if (h->labelled) return;
-  const double t0 = now_ms();
-  // dev[0]: error flags; dev[1]: roots over all levels; dev[4 + L]: the
-  // number of patches on level L.  The counts are read once at the end, so
-  // the per-level patch arrays are sized by their bound, the level's parents.
-  const size_t nlev = h->lev.size();
-  uint32_t* dev = ws.get<uint32_t>(4 + nlev);
-  HIP_CHECK(hipMemsetAsync(dev, 0, (4 + nlev) * sizeof(uint32_t), st));
-  h->npatch_dev = dev + 4;  // copied into the hierarchy below, with the counts
-  ctx->dev_err = dev;
+// the two pinned level sets of a context (the early and the final label pass)
+static LabSet* lab_sets(Ctx* ctx) {
+  if (!ctx->lab_pinned) HIP_CHECK(hipHostMalloc(&ctx->lab_pinned, 2 * sizeof(LabSet), hipHostMallocDefault));
+  return static_cast<LabSet*>(ctx->lab_pinned);
+}
+
+// The label counts of a hierarchy: [0] error flags, [1] roots of the running
+// batch, [4 + L] patches on level L.  Kept with the hierarchy.
+static void label_counts(Ctx* ctx, Hier* h, hipStream_t st) {
+  (void)ctx;
+  if (h->lab_dev) return;
+  h->lab_dev = h->mem.get<uint32_t>(4 + kMaxLevels);
+  HIP_CHECK(hipMemsetAsync(h->lab_dev, 0, (4 + kMaxLevels) * sizeof(uint32_t), st));
+}
+
+// Labels the refined cells of levels k0 .. k1-1 (the patches of levels
+// k0+1 .. k1) on st, all of them at once; level k0's patches (k0 > 0) must
+// be labelled already.  The set of levels goes to the device through the
+// pinned slot `slot` of the context.  With keep, the scratch stays allocated
+// (ws may be handed to other work while these kernels run).
+static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, int slot,
+                         bool keep, hipStream_t st) {
+  uint32_t* dev = h->lab_dev;
   const Tree tree = make_tree(h);
   const double total_mass = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
   double fscale = 1.0;
@@ -1751,16 +1774,16 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     std::frexp(total_mass > 0 ? total_mass : 1.0, &e);
     fscale = std::ldexp(1.0, 61 - e);
   }
-  // every level at once: entry k = the refined cells of level k, parents of
-  // the cells of level k + 1
-  LabSet S{};
-  S.nlev = nlev > 1 ? (uint32_t)(nlev - 1) : 0u;
+  // entry j = the refined cells of level k0 + j, parents of the cells of
+  // level k0 + j + 1
+  LabSet& S = lab_sets(ctx)[slot];
+  S = LabSet{};
+  S.nlev = k1 > k0 ? k1 - k0 : 0u;
   uint64_t tot = 0, ntiles = 0;
-  for (uint32_t k = 0; k < S.nlev; ++k) {
-    const Level& pv = h->lev[k];
-    S.off[k] = tot;
-    S.toff[k] = ntiles;
-    S.lv[k] = LabLev{pv.Fs, pv.Skey, pv.slot_f, pv.Scount, pv.Spmass, pv.b};
+  for (uint32_t j = 0; j < S.nlev; ++j) {
+    const Level& pv = h->lev[k0 + j];
+    S.off[j] = tot;
+    S.toff[j] = ntiles;
     tot += pv.nF;
     ntiles += (pv.nF + kUfTile - 1) / kUfTile;
   }
@@ -1773,54 +1796,81 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
   uint32_t* pncells = h->mem.get<uint32_t>(tot1);
   uint64_t* pnpart = h->mem.get<uint64_t>(tot1);
   double* pmass = h->mem.get<double>(tot1);
-  for (uint32_t k = 0; k < S.nlev; ++k) {
+  for (uint32_t j = 0; j < S.nlev; ++j) {
+    const uint32_t k = k0 + j;
+    const Level& pv = h->lev[k];
     Level& lv = h->lev[k + 1];
-    lv.Spatch = Spatch + 8 * S.off[k];
-    lv.patch_parent = pparent + S.off[k];
-    lv.patch_ncells = pncells + S.off[k];
-    lv.patch_npart = pnpart + S.off[k];
-    lv.patch_mass = pmass + S.off[k];
+    lv.Spatch = Spatch + 8 * S.off[j];
+    lv.patch_parent = pparent + S.off[j];
+    lv.patch_ncells = pncells + S.off[j];
+    lv.patch_npart = pnpart + S.off[j];
+    lv.patch_mass = pmass + S.off[j];
+    S.lv[j] = LabLev{pv.Fs, pv.Skey, pv.slot_f, pv.Scount, pv.Spmass, lv.Spatch,
+                     k > 0 ? pv.Spatch : nullptr, k, pv.b};
   }
-  if (tot) {
-    Ws::Mark m = ws.mark();
-    int32_t* par = ws.get<int32_t>(tot);
-    int32_t* root = ws.get<int32_t>(tot);
-    uint8_t* pred = ws.get<uint8_t>(tot);
-    uint32_t* rank = ws.get<uint32_t>(tot);
-    int32_t* lab = ws.get<int32_t>(tot);
-    uint16_t* xmask = ws.get<uint16_t>(tot);
-    unsigned long long* mfix = h->has_mass ? ws.get<unsigned long long>(tot) : nullptr;
-    LabSet* dS = ws.get<LabSet>(1);
-    HIP_CHECK(hipMemcpyAsync(dS, &S, sizeof(LabSet), hipMemcpyHostToDevice, st));
-    AHF_TIMED(ctx, "uf_hook", st,
-              (k_uf_local<<<(unsigned)ntiles, 256, 0, st>>>(
-                  dS, tree, h->prm.conn, par, xmask, dev)));
-    AHF_TIMED(ctx, "uf_cross", st,
-              (k_uf_cross<<<(unsigned)ntiles, 256, 0, st>>>(
-                  dS, tree, xmask, par, dev)));
-    k_uf_compress<<<grid_for(tot), kT, 0, st>>>(par, tot, root, pred, tot, pncells,
-                                                (unsigned long long*)pnpart, mfix);
-    HIP_LAUNCH_CHECK();
-    compact_flags(ws, pred, tot, nullptr, rank, dev + 1, st);
-    k_uf_label<<<grid_for(tot), kT, 0, st>>>(dS, root, rank, dev + 1, lab, Spatch, dev + 4);
-    HIP_LAUNCH_CHECK();
-    k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (tot + 4095) / 4096 + 1), 256, 0, st>>>(
-        dS, lab, fscale, pncells, (unsigned long long*)pnpart, mfix);
-    HIP_LAUNCH_CHECK();
-    k_patch_parent<<<grid_for(tot), kT, 0, st>>>(dS, root, lab, Spatch, pparent,
-                                                 (const unsigned long long*)pnpart, mfix,
-                                                 h->mass_scalar, 1.0 / fscale, pmass);
-    HIP_LAUNCH_CHECK();
-    // stream order keeps the released workspace from being reused early
-    ws.release(m);
+  if (!tot) return;
+  Ws::Mark m = ws.mark();
+  int32_t* par = ws.get<int32_t>(tot);
+  int32_t* root = ws.get<int32_t>(tot);
+  uint8_t* pred = ws.get<uint8_t>(tot);
+  uint32_t* rank = ws.get<uint32_t>(tot);
+  int32_t* lab = ws.get<int32_t>(tot);
+  uint16_t* xmask = ws.get<uint16_t>(tot);
+  unsigned long long* mfix = h->has_mass ? ws.get<unsigned long long>(tot) : nullptr;
+  LabSet* dS = ws.get<LabSet>(1);
+  HIP_CHECK(hipMemcpyAsync(dS, &S, sizeof(LabSet), hipMemcpyHostToDevice, st));
+  AHF_TIMED(ctx, "uf_hook", st,
+            (k_uf_local<<<(unsigned)ntiles, 256, 0, st>>>(dS, tree, h->prm.conn, par, xmask, dev)));
+  AHF_TIMED(ctx, "uf_cross", st,
+            (k_uf_cross<<<(unsigned)ntiles, 256, 0, st>>>(dS, tree, xmask, par, dev)));
+  k_uf_compress<<<grid_for(tot), kT, 0, st>>>(par, tot, root, pred, tot, pncells,
+                                              (unsigned long long*)pnpart, mfix);
+  HIP_LAUNCH_CHECK();
+  compact_flags(ws, pred, tot, nullptr, rank, dev + 1, st);
+  k_uf_label<<<grid_for(tot), kT, 0, st>>>(dS, root, rank, dev + 1, lab, dev + 4);
+  HIP_LAUNCH_CHECK();
+  k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (tot + 4095) / 4096 + 1), 256, 0, st>>>(
+      dS, lab, fscale, pncells, (unsigned long long*)pnpart, mfix);
+  HIP_LAUNCH_CHECK();
+  k_patch_parent<<<grid_for(tot), kT, 0, st>>>(dS, root, lab, pparent,
+                                               (const unsigned long long*)pnpart, mfix,
+                                               h->mass_scalar, 1.0 / fscale, pmass);
+  HIP_LAUNCH_CHECK();
+  // stream order keeps the released workspace from being reused early
+  if (!keep) ws.release(m);
+}
+
+void label_early(Ctx* ctx, Ws& wsd, Hier* h, uint32_t k1, hipStream_t st) {
+  if (!ctx->lab_st) {
+    HIP_CHECK(hipStreamCreateWithFlags(&ctx->lab_st, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&ctx->lab_ev, hipEventDisableTiming));
   }
-  uint32_t* keep = h->mem.get<uint32_t>(kMaxLevels);
-  HIP_CHECK(hipMemsetAsync(keep, 0, kMaxLevels * sizeof(uint32_t), st));
-  HIP_CHECK(hipMemcpyAsync(keep, dev + 4, nlev * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-  h->npatch_dev = keep;
+  label_counts(ctx, h, st);
+  // the cells of levels 0 .. k1 are complete on st
+  HIP_CHECK(hipEventRecord(ctx->lab_ev, st));
+  HIP_CHECK(hipStreamWaitEvent(ctx->lab_st, ctx->lab_ev, 0));
+  label_levels(ctx, wsd, h, 0, k1, 0, true, ctx->lab_st);
+  h->lab_done = k1;
+}
+
+void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
+  if (h->labelled) return;
+  const double t0 = now_ms();
+  const size_t nlev = h->lev.size();
+  label_counts(ctx, h, st);
+  ctx->dev_err = h->lab_dev;
+  if (h->lab_done > 0) {
+    // the levels labelled early, on their stream, come first
+    HIP_CHECK(hipEventRecord(ctx->lab_ev, ctx->lab_st));
+    HIP_CHECK(hipStreamWaitEvent(st, ctx->lab_ev, 0));
+  }
+  const uint32_t kend = nlev > 1 ? (uint32_t)(nlev - 1) : 0u;
+  label_levels(ctx, ws, h, std::min(h->lab_done, kend), kend, 1, false, st);
+  h->npatch_dev = h->lab_dev + 4;
   if (h->prm.flags & AHF_SUBSTRUCTURE) classify_levels(ctx, ws, h, st);
   std::vector<uint32_t> hv(4 + nlev);
-  HIP_CHECK(hipMemcpyAsync(hv.data(), dev, (4 + nlev) * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(hv.data(), h->lab_dev, (4 + nlev) * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   const uint32_t herr = hv[0];
   if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed while labelling"};
