@@ -75,6 +75,24 @@ void ctx_free(Ctx* c, void* p, size_t bytes, hipStream_t s) {
   c->pool.free_blocks.emplace_back(round_size(bytes), p);
 }
 
+// gives one block back for good (not to the pool's cache): the workspace
+// chunks that a reset folds into one would otherwise stay cached beside it
+void ctx_release(Ctx* c, void* p, size_t bytes, hipStream_t s) {
+  if (!p) return;
+  if (c->free) {
+    c->free(c->user, p, bytes ? bytes : 1, (void*)s);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(c->pool.mu);
+  for (size_t i = 0; i < c->pool.all.size(); ++i)
+    if (c->pool.all[i].second == p) {
+      c->pool.all[i] = c->pool.all.back();
+      c->pool.all.pop_back();
+      break;
+    }
+  (void)hipFree(p);
+}
+
 // caller holds the pool lock
 static void release_free_blocks(Ctx* c) {
   auto& fb = c->pool.free_blocks;
@@ -142,10 +160,14 @@ void Ws::release(Mark m) {
 
 void Ws::reset() {
   // fold several chunks into one so that the next build needs a single one
+  // (the old chunks go back for good; the callers have waited for the work
+  // that used them)
   if (chunks_.size() > 1) {
     size_t tot = 0;
     for (auto& c : chunks_) tot += c.size;
-    free_all();
+    for (auto& c : chunks_) ctx_release(ctx_, c.p, c.size, st_);
+    chunks_.clear();
+    cur_ = 0;
     Chunk c{static_cast<char*>(ctx_alloc(ctx_, tot, st_)), tot, 0};
     chunks_.push_back(c);
   }

@@ -103,6 +103,7 @@ struct Ctx {
 
 void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s);  // throws AHF_ENOMEM
 void ctx_free(Ctx* c, void* p, size_t bytes, hipStream_t s);
+void ctx_release(Ctx* c, void* p, size_t bytes, hipStream_t s);  // not kept in the pool
 void ctx_release_pool(Ctx* c);
 
 // Stack-like scratch space for one build: chunks are never moved, so every

@@ -25,10 +25,13 @@ double now_ms() {
 
 // Footprint of one build before it runs: the sort and record buffers
 // (2 x 12 B pairs + 2 x 32 B records per particle), the dense domain grid
-// arrays, and a bound-shaped allowance for the refined levels and labels.
+// arrays, the refined levels and labels, and the deposit scratch that the
+// second stream keeps to the end of the build.  Measured on the device
+// (memory in use after one build on a fresh context, result included):
+// 294 B per particle at 2^24, 263 at 2e6, 151 MB at 2e5 particles.
 uint64_t estimate_bytes(uint64_t n, uint32_t g) {
   const uint64_t dense = 1ull << (3 * g);
-  return 160ull * n + 48ull * dense + (64ull << 20);
+  return 300ull * n + 48ull * dense + (160ull << 20);
 }
 
 struct Request {

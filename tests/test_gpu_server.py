@@ -141,7 +141,7 @@ def test_lru_eviction_under_a_tight_budget(ctx):
         srv.wait(srv.submit_snapshot(subs[0], dev=devs[0]))
         one = srv.stats()["bytes_in_use"]
     g = subs[0].g
-    est = 160 * 200000 + 48 * (1 << (3 * g)) + (64 << 20)
+    est = 300 * 200000 + 48 * (1 << (3 * g)) + (160 << 20)
     # room for the build in flight and one and a half resident results
     budget = est + (3 * one) // 2
     with ahf.Server(ctx, n_streams=1, hbm_budget=budget) as srv:
