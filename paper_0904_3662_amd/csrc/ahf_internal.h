@@ -257,9 +257,9 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
                      hipStream_t st, Hier* h, bool finish = true);
 void finish_build(Ctx* ctx, Hier* h);
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
-// labels the refined cells of levels 0 .. k1-1 on ctx->lab_st once st has
-// passed their cells, with scratch from wsd (kept); label_hierarchy then
-// labels the rest after them
+// labels the refined cells of levels lab_done .. k1-1 on ctx->lab_st once st
+// has passed their cells, with scratch from wsd (kept); at most two calls per
+// build (one pinned level-set slot each); label_hierarchy labels what is left
 void label_early(Ctx* ctx, Ws& wsd, Hier* h, uint32_t k1, hipStream_t st);
 // host structures and substructures of a labelled hierarchy (waits for it);
 // classify_levels only enqueues, finish_classify waits and reads the count

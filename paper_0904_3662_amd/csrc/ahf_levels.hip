@@ -390,21 +390,24 @@ __device__ inline void add_particle(const Parts& P, uint32_t p, uint32_t mask, f
   add_record(P.rec[2 * (uint64_t)p], P.rec[2 * (uint64_t)p + 1], mask, scale, T, msum);
 }
 
-// the particles [a, a+n) of one cell, four records loaded ahead of their use
+// the particles [a, a+n) of one cell, in batches of K whose records are all
+// loaded before the first is used: a cell of up to K particles waits for
+// memory once
+template <int K>
 __device__ inline void add_range(const Parts& P, uint32_t a, uint32_t n, uint32_t mask, float scale,
                                  float T[27], double& msum) {
-  uint32_t i = 0;
-  for (; i + 4 <= n; i += 4) {
-    uint4 r[8];
+  for (uint32_t i = 0; i < n; i += K) {
+    uint4 r[2 * K];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      r[2 * k] = P.rec[2 * (uint64_t)(a + i + k)];
-      r[2 * k + 1] = P.rec[2 * (uint64_t)(a + i + k) + 1];
-    }
+    for (int k = 0; k < K; ++k)
+      if (i + k < n) {
+        r[2 * k] = P.rec[2 * (uint64_t)(a + i + k)];
+        r[2 * k + 1] = P.rec[2 * (uint64_t)(a + i + k) + 1];
+      }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) add_record(r[2 * k], r[2 * k + 1], mask, scale, T, msum);
+    for (int k = 0; k < K; ++k)
+      if (i + k < n) add_record(r[2 * k], r[2 * k + 1], mask, scale, T, msum);
   }
-  for (; i < n; ++i) add_particle(P, a + i, mask, scale, T, msum);
 }
 
 // ------------------------------------------------------------ heavy cells
@@ -534,16 +537,32 @@ constexpr PatchLayout make_patch_layout() {
 //
 // Levels whose parents form a dense grid (level 0, whose parents are the
 // virtual level -1, and level 1 over a well-refined level 0) deposit by
-// tiles of 4x4x4 parents = 8x8x8 cells, one cell per thread: the cells add
-// their 27-tensors into an LDS grid of the tile plus a one-cell halo, the
-// tile's own cells go straight to their bricks and the halo (the tile's
-// deposit into its neighbours' cells) to a buffer that k_tile_halo_add folds
-// in afterwards.
+// tiles of 4x4x4 parents = 8x8x8 cells, one cell per thread.  Every wave
+// holds 2x2x2 parents = 4x4x4 cells and adds their 27-tensors into a grid of
+// its own (its cells plus a one-cell halo, in LDS) with no block barrier;
+// after one barrier the eight wave grids are summed into the tile grid (the
+// tile plus a one-cell halo).  The tile's inner cells go straight to their
+// bricks and the rest (the tile's deposit into its faces and its neighbours'
+// cells) to a buffer that k_tile_halo_add folds in afterwards.
 
 constexpr int kTileT = 512;   // threads = cells per tile
 constexpr int kTileMaxG = 8;  // largest domain grid (bits per axis) tiled: halo <= 1 GB
 constexpr int kTileG = 10;    // cells per axis with the halo
 constexpr int kTileH = kTileG * kTileG * kTileG;
+constexpr int kTileBatch0 = 4;  // records in flight per cell: level 0 (about 6 particles per cell)
+constexpr int kTileBatch1 = 2;  // level 1 (about one; two keep the kernel at 8 waves per SIMD)
+constexpr int kPatchBatch = 4;  // deeper levels
+constexpr int kWaveG = 6;     // a wave's 4x4x4 cells per axis with their halo
+constexpr int kWaveH = kWaveG * kWaveG * kWaveG;
+
+// orders the LDS accesses of one wave: what a lane wrote before is seen by
+// every lane of the wave after (the wave's LDS instructions run in order;
+// this keeps the compiler from moving them across)
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ inline uint32_t tile_local_parent(uint32_t x, uint32_t y, uint32_t z) {
   // Morton index of a parent inside its 4x4x4 tile
@@ -564,11 +583,12 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
     const double* __restrict__ hM, Parts P, uint32_t mask, float scale,
     const int32_t* __restrict__ pslot_child, float* __restrict__ mass,
     float* __restrict__ halo, double* __restrict__ Spmass) {
-  __shared__ float G[kTileH];  // the tile's cells and their one-cell halo
+  __shared__ float Wg[kTileT / 64][kWaveH];  // each wave's cells and their one-cell halo
   __shared__ int32_t sbr[64];  // brick of each parent's children (loaded with the first loads)
   const int t = threadIdx.x;
+  float* wg = Wg[t >> 6];
   const uint64_t tile = xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun);
-  for (int q = t; q < kTileH; q += kTileT) G[q] = 0.0f;
+  for (int q = t & 63; q < kWaveH; q += 64) wg[q] = 0.0f;
   if (t < 64) sbr[t] = DENSE0 ? (int32_t)(tile * 64 + (uint64_t)t) : pslot_child[tile * 64 + (uint64_t)t];
   const uint32_t pm = (uint32_t)t >> 3, d = (uint32_t)t & 7u;
   const uint32_t px = (((pm >> 5) & 1u) << 1) | ((pm >> 2) & 1u);
@@ -593,38 +613,40 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
       for (int k = 0; k < 27; ++k) T[k] = hT[(uint64_t)h * 27 + k];
       ms = hM[h];
     } else if (DENSE0) {
-      add_range(P, a0, n, mask, scale, T, ms);
+      add_range<kTileBatch0>(P, a0, n, mask, scale, T, ms);
     } else {
-      // level-1 cells hold about one particle: two records in flight at once
-      uint32_t i = 0;
-      for (; i + 2 <= n; i += 2) {
-        const uint4 q0 = P.rec[2 * (uint64_t)(a0 + i)], q1 = P.rec[2 * (uint64_t)(a0 + i) + 1];
-        const uint4 q2 = P.rec[2 * (uint64_t)(a0 + i + 1)], q3 = P.rec[2 * (uint64_t)(a0 + i + 1) + 1];
-        add_record(q0, q1, mask, scale, T, ms);
-        add_record(q2, q3, mask, scale, T, ms);
-      }
-      if (i < n) add_particle(P, a0 + i, mask, scale, T, ms);
+      add_range<kTileBatch1>(P, a0, n, mask, scale, T, ms);  // about one particle per cell
     }
     if (Spmass) Spmass[s] = ms;
   }
-  // 27 phases, one per neighbour offset in a fixed order: within a phase every
-  // cell adds to a different grid cell, so no two writes collide and every
-  // grid cell sums its contributions in the same order on every run
-  const int g0 = ((int)(cx + 1) * kTileG + (int)(cy + 1)) * kTileG + (int)(cz + 1);
-  __syncthreads();
+  // 27 phases, one per neighbour offset in a fixed order: within a phase the
+  // wave's cells add to distinct cells of its grid, so no two writes collide
+  // and every grid cell sums its contributions in the same order on every run
+  const int w0 = ((int)(cx & 3u) * kWaveG + (int)(cy & 3u)) * kWaveG + (int)(cz & 3u);
+  wave_lds_sync();
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const int q = g0 + ((a - 1) * kTileG + (b - 1)) * kTileG + (c - 1);
-        if (has) G[q] += T[a * 9 + b * 3 + c];
-        __syncthreads();
+        if (has) wg[w0 + (a * kWaveG + b) * kWaveG + c] += T[a * 9 + b * 3 + c];
+        wave_lds_sync();
       }
+  __syncthreads();
   for (int q = t; q < kTileH; q += kTileT) {
-    const int dx = q / 100 - 1, dy = (q / 10) % 10 - 1, dz = q % 10 - 1;
-    const float sum = G[q];
+    const int gx = q / 100, gy = (q / 10) % 10, gz = q % 10;
+    const int dx = gx - 1, dy = gy - 1, dz = gz - 1;
+    // the wave grids covering this tile grid cell, in wave order (wave w
+    // holds the cells 4 (w>>2 & 1, w>>1 & 1, w & 1) + [0, 4) per axis)
+    float sum = 0.0f;
+#pragma unroll
+    for (int w = 0; w < kTileT / 64; ++w) {
+      const int ex = gx - 4 * ((w >> 2) & 1), ey = gy - 4 * ((w >> 1) & 1), ez = gz - 4 * (w & 1);
+      if ((unsigned)ex < (unsigned)kWaveG && (unsigned)ey < (unsigned)kWaveG &&
+          (unsigned)ez < (unsigned)kWaveG)
+        sum += Wg[w][(ex * kWaveG + ey) * kWaveG + ez];
+    }
     // cells off the tile's faces are final; face cells and the halo go to
     // the buffer, where k_tile_halo_add adds the neighbours' share
     if ((unsigned)(dx - 1) < 6u && (unsigned)(dy - 1) < 6u && (unsigned)(dz - 1) < 6u) {
@@ -714,7 +736,7 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
       ms = hM[h];
     } else {
       const uint32_t a = Sstart[s];
-      add_range(P, a, n, mask, scale, T, ms);
+      add_range<kPatchBatch>(P, a, n, mask, scale, T, ms);
     }
     if (Spmass) Spmass[s] = ms;
   }
@@ -1134,7 +1156,7 @@ __global__ __launch_bounds__(256) void k_uf_local(const LabSet* __restrict__ pS,
 // root), so each block first collects the distinct (root, root) pairs of its
 // cells in an LDS hash set and unites each pair once.
 constexpr int kPairSlots = 2048;
-static_assert(kUfTile == 256, "k_uf_cross takes one element per thread of a tile");
+static_assert(kUfTile % 256 == 0, "the union-find kernels loop over a tile in steps of 256");
 
 __global__ __launch_bounds__(256) void k_uf_cross(const LabSet* __restrict__ pS, Tree tree,
                                                   const uint16_t* __restrict__ xmask,
@@ -1149,8 +1171,9 @@ __global__ __launch_bounds__(256) void k_uf_cross(const LabSet* __restrict__ pS,
   const uint64_t base = o + (tile - S.toff[k]) * kUfTile;
   for (int i = threadIdx.x; i < kPairSlots; i += 256) set[i] = ~0ull;
   __syncthreads();
-  const uint64_t f = base + threadIdx.x;
-  if (f < S.off[k + 1]) {
+  for (uint32_t j = threadIdx.x; j < (uint32_t)kUfTile; j += 256) {
+    const uint64_t f = base + j;
+    if (f >= S.off[k + 1]) break;
     uint32_t xm = xmask[f];
     if (xm) {
       const uint32_t s = lv.Fs[f - o];
@@ -1483,8 +1506,6 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   for (int L = 0; L <= prm.Lmax; ++L) {
     h->lev.emplace_back();
     Level& lv = h->lev.back();
-    if (early_labels && L >= 2 && h->lab_done == 0 && 8 * nFp < kLabEarlyCells)
-      label_early(ctx, wsd, h, (uint32_t)L, st);
     const int b = g + L;
     lv.b = (uint32_t)b;
     const int sh = 3 * (B - b);
@@ -1657,6 +1678,9 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
       sum_blocks.n[L] = nblk;
     }
 
+    // the host enqueues the early labels while it would otherwise wait
+    if (early_labels && L >= 2 && h->lab_done == 0 && 8 * nFp < kLabEarlyCells)
+      label_early(ctx, wsd, h, (uint32_t)L, st);
     HIP_CHECK(hipEventSynchronize(ctx->cnt_ev));
     lv.nF = ctx->host_cnt[0];
     const uint32_t nD = can_refine ? ctx->host_cnt[3] : 0u;
@@ -1687,6 +1711,10 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     ws.release(lvl_mark);
   }
 
+  // once labels have started early, the rest go to the label stream as well:
+  // they need the cells only, not the deposits still running
+  if (early_labels && h->lab_done > 0 && h->lev.size() > 1)
+    label_early(ctx, wsd, h, (uint32_t)(h->lev.size() - 1), st);
   if (overlap) {
     // the deposits back into the build stream
     HIP_CHECK(hipEventRecord(ctx->join_ev, ds));
@@ -1845,11 +1873,13 @@ void label_early(Ctx* ctx, Ws& wsd, Hier* h, uint32_t k1, hipStream_t st) {
     HIP_CHECK(hipStreamCreateWithFlags(&ctx->lab_st, hipStreamNonBlocking));
     HIP_CHECK(hipEventCreateWithFlags(&ctx->lab_ev, hipEventDisableTiming));
   }
+  if (k1 <= h->lab_done) return;
   label_counts(ctx, h, st);
-  // the cells of levels 0 .. k1 are complete on st
+  // the cells of levels lab_done .. k1 are complete on st
   HIP_CHECK(hipEventRecord(ctx->lab_ev, st));
   HIP_CHECK(hipStreamWaitEvent(ctx->lab_st, ctx->lab_ev, 0));
-  label_levels(ctx, wsd, h, 0, k1, 0, true, ctx->lab_st);
+  // the first call reads its level set from pinned slot 0, a second from slot 1
+  label_levels(ctx, wsd, h, h->lab_done, k1, h->lab_done == 0 ? 0 : 1, true, ctx->lab_st);
   h->lab_done = k1;
 }
 
@@ -1865,7 +1895,7 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     HIP_CHECK(hipStreamWaitEvent(st, ctx->lab_ev, 0));
   }
   const uint32_t kend = nlev > 1 ? (uint32_t)(nlev - 1) : 0u;
-  label_levels(ctx, ws, h, std::min(h->lab_done, kend), kend, 1, false, st);
+  if (h->lab_done < kend) label_levels(ctx, ws, h, h->lab_done, kend, 1, false, st);
   h->npatch_dev = h->lab_dev + 4;
   if (h->prm.flags & AHF_SUBSTRUCTURE) classify_levels(ctx, ws, h, st);
   std::vector<uint32_t> hv(4 + nlev);
