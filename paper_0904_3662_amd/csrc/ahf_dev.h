@@ -47,15 +47,24 @@ __host__ __device__ inline void unmorton3(uint64_t k, uint32_t& x, uint32_t& y, 
   z = compact3(k);
 }
 
-// key of the cell displaced by (dx,dy,dz), periodic on a grid of `bits` bits per axis
+// One axis of a Morton key (its bits under mask m) moved by d in {-1, 0, 1},
+// periodic, without leaving the interleaved form: +1 sets the other axes'
+// bits so that the carry runs through them, -1 borrows through their zeros,
+// and the mask drops what leaves the top.
+__host__ __device__ inline uint64_t dilated_step(uint64_t k, uint64_t m, int d) {
+  const uint64_t a = k & m;
+  const uint64_t low = m & (~m + 1ull);
+  const uint64_t b = d > 0 ? (((a | ~m) + low) & m) : (d < 0 ? ((a - low) & m) : a);
+  return (k & ~m) | b;
+}
+
+// key of the cell displaced by (dx,dy,dz), each in {-1, 0, 1}, periodic on a
+// grid of `bits` (<= 21) bits per axis
 __host__ __device__ inline uint64_t shift_key(uint64_t k, int bits, int dx, int dy, int dz) {
-  uint32_t x, y, z;
-  unmorton3(k, x, y, z);
-  const uint32_t m = bits >= 32 ? 0xffffffffu : ((1u << bits) - 1u);
-  x = (uint32_t)((int32_t)x + dx) & m;
-  y = (uint32_t)((int32_t)y + dy) & m;
-  z = (uint32_t)((int32_t)z + dz) & m;
-  return morton3(x, y, z);
+  const uint64_t mz = 0x1249249249249249ull & ((1ull << (3 * bits)) - 1ull);
+  k = dilated_step(k, mz << 2, dx);
+  k = dilated_step(k, mz << 1, dy);
+  return dilated_step(k, mz, dz);
 }
 
 // Per-level descent table: slot_child[l][s] is the brick (of level l+1) made
