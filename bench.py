@@ -369,7 +369,7 @@ def main():
         h.free()
 
     # per-kernel split from two more builds, untimed, with every kernel timed
-    names = ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "level0_start", "child_ranges",
+    names = ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "child_ranges",
              "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross")
     ctx.profile_only(None)
     ctx.set_profiling(True)

@@ -182,13 +182,14 @@ void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uin
 // width.  sort_keys takes keys[i] = key of particle i (or, when q == 0, the
 // packed word of particle i already) and ghist[p * 256 + d] = the number of
 // keys whose digit p is d; it returns the sorted packed words (keys or a
-// workspace buffer).
+// workspace buffer) and, in *spare, the other of the two buffers, free once
+// the sort has run.
 struct SortPlan {
   int key_bits = 0, npass = 0, ib = 1, q = 0;
 };
 SortPlan sort_plan(uint64_t n, int key_bits);
 uint64_t* sort_keys(Ctx* ctx, Ws& ws, uint64_t* keys, uint64_t n, const SortPlan& sp,
-                    const uint32_t* ghist, hipStream_t st);
+                    const uint32_t* ghist, hipStream_t st, uint64_t** spare = nullptr);
 constexpr int kRsMaxPass = 8;
 template <typename T>
 void sum_to_f64(Ws& ws, const T* a, uint64_t n, double* out, hipStream_t st);

@@ -121,30 +121,46 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
     if (h[i]) atomicAdd(&ghist[i], h[i]);
 }
 
-// records in sorted order: one random 32-byte read per particle
-// sorted position i: particle index from the packed word, its record, and its
-// full key rebuilt from the coordinates (written over the word, in place)
-__global__ void k_gather_rec(uint64_t* __restrict__ words, int ib, int s, uint64_t n,
-                             const uint4* __restrict__ rec, uint4* __restrict__ srec,
-                             uint32_t* __restrict__ order) {
-  GRID_STRIDE(i, n) {
-    const uint32_t j = (uint32_t)(words[i] & ((1ull << ib) - 1ull));
-    const uint4 a = rec[2 * (uint64_t)j];
-    const uint4 b = rec[2 * (uint64_t)j + 1];
-    order[i] = j;
-    srec[2 * i] = a;
-    srec[2 * i + 1] = b;
-    words[i] = morton3(a.x >> s, a.y >> s, a.z >> s);
-  }
-}
-
-// level 0: start of every dense cell from the sorted keys (start[ncell] = n)
-__global__ void k_l0_start(const uint64_t* __restrict__ skey, uint64_t n, int sh,
-                           uint64_t ncell, uint32_t* __restrict__ start) {
-  GRID_STRIDE(i, n + 1) {
-    const uint64_t ci = (i < n) ? (skey[i] >> sh) : ncell;
-    const uint64_t c0 = (i > 0) ? (skey[i - 1] >> sh) + 1 : 0;
-    for (uint64_t c = c0; c <= ci; ++c) start[c] = (uint32_t)i;
+// records in sorted order: one random 32-byte read per particle.  Sorted
+// position i: particle index from the packed word, its record, its full key
+// rebuilt from the coordinates, and the level-0 cell starts: element i (and
+// the terminal element n) starts every dense cell after the previous
+// element's cell up to its own.  The previous element's cell comes from the
+// neighbouring lane, or for a wave's first lane from that element's record.
+// Elements 0 .. n (n + 1 of them) in grid-stride rounds that every lane of
+// the grid takes part in.
+__global__ __launch_bounds__(kT) void k_gather_rec(const uint64_t* __restrict__ words, int ib,
+                                                   int s, uint64_t n,
+                                                   const uint4* __restrict__ rec,
+                                                   uint4* __restrict__ srec,
+                                                   uint32_t* __restrict__ order,
+                                                   uint64_t* __restrict__ skey, int sh0,
+                                                   uint64_t ncell0, uint32_t* __restrict__ start0) {
+  const uint64_t im = (1ull << ib) - 1ull;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base <= n; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    uint64_t ci = ncell0;
+    if (i < n) {
+      const uint32_t j = (uint32_t)(words[i] & im);
+      const uint4 a = rec[2 * (uint64_t)j];
+      const uint4 b = rec[2 * (uint64_t)j + 1];
+      order[i] = j;
+      srec[2 * i] = a;
+      srec[2 * i + 1] = b;
+      const uint64_t key = morton3(a.x >> s, a.y >> s, a.z >> s);
+      skey[i] = key;
+      ci = key >> sh0;
+    }
+    const uint32_t lo = __shfl_up((uint32_t)ci, 1, 64);
+    const uint32_t hi = __shfl_up((uint32_t)(ci >> 32), 1, 64);
+    uint64_t cp = ((uint64_t)hi << 32) | lo;
+    if (i > n) continue;
+    if (i > 0 && __lane_id() == 0) {
+      const uint4 a = rec[2 * (words[i - 1] & im)];
+      cp = morton3(a.x >> s, a.y >> s, a.z >> s) >> sh0;
+    }
+    for (uint64_t c = (i > 0) ? cp + 1 : 0; c <= ci; ++c) start0[c] = (uint32_t)i;
   }
 }
 
@@ -1456,6 +1472,9 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   h->order = h->mem.get<uint32_t>(n);
   uint4* srec = ws.get<uint4>(2 * n);
   uint64_t* skey = keys;
+  // level 0 is dense: its cell starts come with the gather
+  const uint64_t ncell0 = 1ull << (3 * g);
+  uint32_t* start0 = h->mem.get<uint32_t>(ncell0 + 1);
   if (n > 0) {
     uint32_t* ghist = ws.get<uint32_t>(kRsMaxPass * 256);
     HIP_CHECK(hipMemsetAsync(ghist, 0, kRsMaxPass * 256 * sizeof(uint32_t), st));
@@ -1465,10 +1484,13 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
               (k_keys<<<kb, 256, 0, st>>>(p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass,
                                           (float)p.mass_scalar, n, B, sp.npass,
                                           sp.q == 0 ? sp.ib : -1, keys, rec, ghist, err)));
-    skey = sort_keys(ctx, ws, keys, n, sp, ghist, st);
+    uint64_t* spare = nullptr;
+    const uint64_t* words = sort_keys(ctx, ws, keys, n, sp, ghist, st, &spare);
+    skey = spare;  // the full sorted keys go to the sort's free buffer
     AHF_TIMED(ctx, "gather", st,
-              (k_gather_rec<<<grid_for(n), kT, 0, st>>>(skey, sp.ib, kQBits - B, n, rec, srec,
-                                                        h->order)));
+              (k_gather_rec<<<grid_for(n + 1), kT, 0, st>>>(words, sp.ib, kQBits - B, n, rec,
+                                                            srec, h->order, skey, 3 * (B - g),
+                                                            ncell0, start0)));
   }
 
   Parts P;
@@ -1512,11 +1534,12 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     if (L == 0 && g >= 2 && g <= kTileMaxG) rank0 = ws.get<uint32_t>(1ull << (3 * g));
     Ws::Mark lvl_mark = ws.mark();
     if (L == 0) {
-      lv.nS = 1ull << (3 * g);
-      lv.Sstart = h->mem.get<uint32_t>(lv.nS + 1);
+      lv.nS = ncell0;
+      lv.Sstart = start0;
       lv.Scount = h->mem.get<uint32_t>(lv.nS);
-      AHF_TIMED(ctx, "level0_start", st,
-                (k_l0_start<<<grid_for(n + 1), kT, 0, st>>>(skey, n, sh, lv.nS, lv.Sstart)));
+      if (n == 0)  // no gather: every cell starts (and ends) at 0
+        k_fill_i32<<<grid_for(lv.nS + 1), kT, 0, st>>>(reinterpret_cast<int32_t*>(lv.Sstart),
+                                                       lv.nS + 1, 0);
       k_l0_count<<<grid_for(lv.nS), kT, 0, st>>>(lv.Sstart, lv.nS, lv.Scount);
       HIP_LAUNCH_CHECK();
     } else {

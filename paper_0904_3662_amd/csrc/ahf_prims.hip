@@ -388,7 +388,8 @@ __global__ __launch_bounds__(kRsT) void k_rs_down(
 }
 
 uint64_t* sort_keys(Ctx* ctx, Ws& ws, uint64_t* keys, uint64_t n, const SortPlan& sp,
-                    const uint32_t* ghist, hipStream_t st) {
+                    const uint32_t* ghist, hipStream_t st, uint64_t** spare) {
+  if (spare) *spare = nullptr;
   if (n == 0) return keys;
   const uint32_t ntiles = (uint32_t)((n + kRsTile - 1) / kRsTile);
   uint32_t* gofs = ws.get<uint32_t>((uint64_t)sp.npass * 256);
@@ -436,6 +437,7 @@ uint64_t* sort_keys(Ctx* ctx, Ws& ws, uint64_t* keys, uint64_t n, const SortPlan
     }
     std::swap(a, b);
   }
+  if (spare) *spare = b;
   return a;
 }
 
