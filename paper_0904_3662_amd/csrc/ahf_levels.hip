@@ -164,11 +164,6 @@ __global__ __launch_bounds__(kT) void k_gather_rec(const uint64_t* __restrict__ 
   }
 }
 
-__global__ void k_l0_count(const uint32_t* __restrict__ start, uint64_t ncell,
-                           uint32_t* __restrict__ count) {
-  GRID_STRIDE(c, ncell) count[c] = start[c + 1] - start[c];
-}
-
 __device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ a, uint32_t lo, uint32_t hi,
                                            uint64_t key) {
   while (lo < hi) {
@@ -258,6 +253,8 @@ __device__ inline uint32_t wave_excl_scan_u32(uint32_t v) {
 // Refinement flags and the heavy-cell list.  Each block takes one contiguous
 // run of cells: a first pass counts its heavy cells and their chunks, one
 // atomic per counter reserves the block's indices, a second pass writes them.
+// On level 0 (count_out set) the counts come from the dense cell starts and
+// are written here.
 // (Atomics on one address from different blocks are served one after
 // another far from the CU, so their number sets the cost: the grid is kept
 // small.  Blocks of 512 threads fit into the wave slots that one block of
@@ -270,7 +267,8 @@ __global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ c
                                                   const uint32_t* __restrict__ start, uint64_t nS,
                                                   double thr, int can_refine,
                                                   uint8_t* __restrict__ flag, HeavyList hl,
-                                                  uint32_t* __restrict__ rank_unset) {
+                                                  uint32_t* __restrict__ rank_unset,
+                                                  uint32_t* __restrict__ count_out) {
   __shared__ uint32_t wh[kFlagT / 64], wc[kFlagT / 64];
   __shared__ uint32_t base_h, base_c;
   const int w = threadIdx.x >> 6;
@@ -285,13 +283,14 @@ __global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ c
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const uint64_t s = s0 + (uint64_t)k * kFlagT;
-      cs[k] = s < hi ? count[s] : 0u;
+      cs[k] = s < hi ? (count_out ? start[s + 1] - start[s] : count[s]) : 0u;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const uint64_t s = s0 + (uint64_t)k * kFlagT;
       if (s >= hi) break;
       const uint32_t c = cs[k];
+      if (count_out) count_out[s] = c;
       const uint32_t f = (can_refine && (double)c > thr) ? 1u : 0u;
       flag[s] = (uint8_t)f;
       // the compaction fills in the rank of the refined cells
@@ -329,7 +328,7 @@ __global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ c
   uint32_t o = base_c + wc[w] + co;
   if (my_h == 0) return;
   for (uint64_t s = lo + threadIdx.x; s < hi; s += kFlagT) {
-    const uint32_t c = count[s];
+    const uint32_t c = count_out ? start[s + 1] - start[s] : count[s];
     if (c <= (uint32_t)kHeavy) continue;
     const uint32_t m = (c + kChunk - 1) / kChunk;
     const uint32_t a = start[s];
@@ -1457,11 +1456,14 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   HIP_CHECK(hipEventRecord(ctx->phase_ev[0], st));
   // [0] error flags, [1..7] per-level counters, [8 + 2L], [9 + 2L] heavy
   // cells and chunks of level L
+  // (one zeroed block: the totals, the counters, the sort's digit histograms)
   constexpr int kDevU32 = 8 + 2 * kMaxLevels;
-  uint32_t* dev_u32 = ws.get<uint32_t>(kDevU32);
-  double* dev_tot = ws.get<double>(3 * kMaxLevels);
-  HIP_CHECK(hipMemsetAsync(dev_u32, 0, kDevU32 * sizeof(uint32_t), st));
-  HIP_CHECK(hipMemsetAsync(dev_tot, 0, 3 * kMaxLevels * sizeof(double), st));
+  constexpr size_t kZeroWords = 3 * kMaxLevels + (kDevU32 + 1) / 2 + (kRsMaxPass * 256) / 2;
+  uint64_t* zero = ws.get<uint64_t>(kZeroWords);
+  HIP_CHECK(hipMemsetAsync(zero, 0, kZeroWords * sizeof(uint64_t), st));
+  double* dev_tot = reinterpret_cast<double*>(zero);
+  uint32_t* dev_u32 = reinterpret_cast<uint32_t*>(zero + 3 * kMaxLevels);
+  uint32_t* ghist0 = reinterpret_cast<uint32_t*>(zero + 3 * kMaxLevels + (kDevU32 + 1) / 2);
   uint32_t* err = dev_u32;
   ctx->dev_err = err;
 
@@ -1476,8 +1478,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   const uint64_t ncell0 = 1ull << (3 * g);
   uint32_t* start0 = h->mem.get<uint32_t>(ncell0 + 1);
   if (n > 0) {
-    uint32_t* ghist = ws.get<uint32_t>(kRsMaxPass * 256);
-    HIP_CHECK(hipMemsetAsync(ghist, 0, kRsMaxPass * 256 * sizeof(uint32_t), st));
+    uint32_t* ghist = ghist0;
     unsigned kb = grid_for(n);
     if (kb > 2048) kb = 2048;
     AHF_TIMED(ctx, "keys", st,
@@ -1540,8 +1541,6 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
       if (n == 0)  // no gather: every cell starts (and ends) at 0
         k_fill_i32<<<grid_for(lv.nS + 1), kT, 0, st>>>(reinterpret_cast<int32_t*>(lv.Sstart),
                                                        lv.nS + 1, 0);
-      k_l0_count<<<grid_for(lv.nS), kT, 0, st>>>(lv.Sstart, lv.nS, lv.Scount);
-      HIP_LAUNCH_CHECK();
     } else {
       const Level& pv = h->lev[L - 1];
       lv.nS = 8 * pv.nF;
@@ -1581,10 +1580,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     // with the count criterion the flags come here; with the density
     // criterion they need the level's deposit and come after it
     k_flags<<<std::min(grid_for(lv.nS, kFlagT), kFlagBlocks), kFlagT, 0, st>>>(
-        lv.Scount, lv.Sstart, lv.nS, thr,
-                                            density ? 0 : can_refine,
-                                            lv.Sflag, hl,
-                                            (L == 0 && !density) ? rank0 : nullptr);
+        L == 0 ? nullptr : lv.Scount, lv.Sstart, lv.nS, thr, density ? 0 : can_refine, lv.Sflag,
+        hl, (L == 0 && !density) ? rank0 : nullptr, L == 0 ? lv.Scount : nullptr);
     HIP_LAUNCH_CHECK();
     if (overlap) {
       // the level's cells and heavy lists are complete: its deposit may start
@@ -1750,9 +1747,10 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   // totals and the device error flags, into pinned memory; read by
   // finish_build once the stream has passed this point
   HIP_CHECK(hipEventRecord(ctx->phase_ev[2], st));
-  HIP_CHECK(hipMemcpyAsync(ctx->host_tot, dev_tot, 3 * kMaxLevels * sizeof(double),
-                           hipMemcpyDeviceToHost, st));
-  HIP_CHECK(hipMemcpyAsync(ctx->host_tot + 3 * kMaxLevels, err, sizeof(uint32_t),
+  // (the error flags follow the totals in the zeroed block: one copy)
+  static_assert(sizeof(double) * 3 * kMaxLevels % 8 == 0, "flags right after the totals");
+  HIP_CHECK(hipMemcpyAsync(ctx->host_tot, dev_tot,
+                           3 * kMaxLevels * sizeof(double) + sizeof(uint32_t),
                            hipMemcpyDeviceToHost, st));
   h->t_start = t0;
   if (finish) {
