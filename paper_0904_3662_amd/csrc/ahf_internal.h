@@ -87,6 +87,10 @@ struct Ctx {
   hipStream_t lab_st = nullptr;
   hipEvent_t lab_ev = nullptr;
   void* lab_pinned = nullptr;
+  // builds keep to their one stream: set for the workers of a server with
+  // several of them, whose concurrent builds already fill the GPU (and whose
+  // streams would otherwise outnumber the hardware queues many times over)
+  bool one_stream = false;
 };
 
 

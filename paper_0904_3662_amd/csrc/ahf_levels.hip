@@ -1502,9 +1502,9 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   // With the count criterion a level's deposit needs only its cells and its
   // heavy-cell lists: it runs on the second stream while this one goes on
   // to the next level's cells.  (The density criterion needs the deposit
-  // for the flags: one stream.)
+  // for the flags: one stream; so do the builds of a server's workers.)
   const bool density = (prm.flags & AHF_DENSITY_CRITERION) != 0;
-  const bool overlap = !density;
+  const bool overlap = !density && !ctx->one_stream;
   if (overlap && !ctx->dep_st) {
     HIP_CHECK(hipStreamCreateWithFlags(&ctx->dep_st, hipStreamNonBlocking));
     HIP_CHECK(hipEventCreateWithFlags(&ctx->dep_ev, hipEventDisableTiming));
