@@ -1400,6 +1400,116 @@ __global__ void k_patch_parent(const LabSet* __restrict__ pS, const int32_t* __r
   }
 }
 
+// The whole label pass in one block, for passes of few elements (the last
+// levels, or a small hierarchy) with equal masses: union-find in LDS over
+// every element (a block holds them all, so there are no tile edges), the
+// roots' ranks by a block scan, then the patch ids of the elements and their
+// children, the per-patch cells and particles (LDS sums), the parents and
+// masses.  The results are those of the general pass, in one launch instead
+// of eight.  Tree lookups go level by level, so their level is uniform over
+// the block.
+constexpr int kLabSmallT = 1024;
+constexpr uint32_t kLabSmallMax = 4096;
+
+__global__ __launch_bounds__(kLabSmallT) void k_label_small(
+    const LabSet* __restrict__ pS, Tree tree, int conn, uint32_t* __restrict__ ncells,
+    unsigned long long* __restrict__ npart, int32_t* __restrict__ parent,
+    double* __restrict__ pm, double mscalar, uint32_t* __restrict__ npatch,
+    uint32_t* __restrict__ err) {
+  __shared__ int32_t lp[kLabSmallMax];
+  __shared__ uint32_t rk[kLabSmallMax];
+  __shared__ uint32_t sc[kLabSmallMax];
+  __shared__ unsigned long long sp[kLabSmallMax];
+  __shared__ uint32_t wsum[kLabSmallT / 64];
+  const LabSet& S = *pS;
+  const uint32_t n = (uint32_t)S.off[S.nlev];
+  const uint32_t cm = conn_mask(conn);
+  const uint32_t t = threadIdx.x;
+  for (uint32_t e = t; e < n; e += kLabSmallT) {
+    lp[e] = (int32_t)e;
+    sc[e] = 0u;
+    sp[e] = 0ull;
+  }
+  __syncthreads();
+  for (int k = 0; k < (int)S.nlev; ++k) {
+    const LabLev& lv = S.lv[k];
+    const uint32_t o = (uint32_t)S.off[k], o1 = (uint32_t)S.off[k + 1];
+    for (uint32_t e = o + t; e < o1; e += kLabSmallT) {
+      const uint32_t s = lv.Fs[e - o];
+      const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
+      int32_t gs[13];
+      refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, cm, gs, err);
+#pragma unroll
+      for (int q = 0; q < 13; ++q) {
+        if (gs[q] < 0) continue;
+        const uint32_t g = o + (uint32_t)gs[q];
+        if (g != e) lds_unite(lp, (int32_t)e, (int32_t)g);
+      }
+    }
+  }
+  __syncthreads();
+  // ranks of the roots (each component's smallest element) in element order
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < n; c0 += kLabSmallT) {
+    const uint32_t e = c0 + t;
+    const uint32_t isr = (e < n && lds_find(lp, (int32_t)e) == (int32_t)e) ? 1u : 0u;
+    uint32_t inc = isr;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(inc, d, 64);
+      if ((t & 63u) >= (uint32_t)d) inc += v;
+    }
+    if ((t & 63u) == 63u) wsum[t >> 6] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kLabSmallT / 64; ++w) {
+      before += (w < (int)(t >> 6)) ? wsum[w] : 0u;
+      tot += wsum[w];
+    }
+    if (isr) rk[e] = carry + before + inc - 1u;
+    carry += tot;
+    __syncthreads();
+  }
+  const uint32_t nroots = carry;
+  for (int k = 0; k < (int)S.nlev; ++k) {
+    const LabLev& lv = S.lv[k];
+    const uint32_t o = (uint32_t)S.off[k], o1 = (uint32_t)S.off[k + 1];
+    const uint32_t r0 = rk[o];  // a level's first element is a root
+    for (uint32_t e = o + t; e < o1; e += kLabSmallT) {
+      const int32_t r = lds_find(lp, (int32_t)e);
+      const int32_t l = (int32_t)(rk[r] - r0);
+      const uint32_t slot = o + (uint32_t)l;
+      int4* out = reinterpret_cast<int4*>(lv.Spatch + 8 * (uint64_t)(e - o));
+      out[0] = make_int4(l, l, l, l);
+      out[1] = make_int4(l, l, l, l);
+      const uint32_t s = lv.Fs[e - o];
+      atomicAdd(&sc[slot], 8u);
+      atomicAdd(&sp[slot], (unsigned long long)lv.Scount[s]);
+      if (r == (int32_t)e) {
+        // the patch of cell s of S_k: from this pass when it is a child of
+        // the set's previous entry, else from an earlier pass (or none)
+        int32_t pp = -1;
+        if (k > 0) {
+          const uint32_t op = (uint32_t)S.off[k - 1];
+          const uint32_t ep = op + (s >> 3);
+          pp = (int32_t)(rk[lds_find(lp, (int32_t)ep)] - rk[op]);
+        } else if (lv.pSpatch) {
+          pp = lv.pSpatch[s];
+        }
+        parent[slot] = pp;
+      }
+      if (e == o) npatch[lv.level + 1] = (o1 < n ? rk[o1] : nroots) - r0;
+    }
+  }
+  __syncthreads();
+  for (uint32_t e = t; e < n; e += kLabSmallT) {
+    ncells[e] = sc[e];
+    npart[e] = sp[e];
+    pm[e] = (double)sp[e] * mscalar;
+  }
+}
+
 // ------------------------------------------------------------ label queries
 
 // patch id of each queried level-L cell (-1 if the cell is not in S_L)
@@ -1859,6 +1969,17 @@ static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, in
   }
   if (!tot) return;
   Ws::Mark m = ws.mark();
+  if (tot <= kLabSmallMax && !h->has_mass) {
+    // few elements: the whole pass in one block
+    LabSet* dS = ws.get<LabSet>(1);
+    HIP_CHECK(hipMemcpyAsync(dS, &S, sizeof(LabSet), hipMemcpyHostToDevice, st));
+    k_label_small<<<1, kLabSmallT, 0, st>>>(dS, tree, h->prm.conn, pncells,
+                                            reinterpret_cast<unsigned long long*>(pnpart),
+                                            pparent, pmass, h->mass_scalar, dev + 4, dev);
+    HIP_LAUNCH_CHECK();
+    if (!keep) ws.release(m);
+    return;
+  }
   int32_t* par = ws.get<int32_t>(tot);
   int32_t* root = ws.get<int32_t>(tot);
   uint8_t* pred = ws.get<uint8_t>(tot);
