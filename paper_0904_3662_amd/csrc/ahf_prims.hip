@@ -49,7 +49,8 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t& total, uint32_t
 // reduce-then-scan over tiles of 8192 flags: count per tile, exclusive scan
 // of the tile counts in one block, then each tile re-reads its flags and
 // writes the index of every flagged element at its rank (list) and/or its
-// rank at its index (rank).  One tile needs no count pass.
+// rank at its index (rank).  One tile needs no count pass, and up to 8 tiles
+// go through one block in one launch.
 
 constexpr int kCfT = 256;
 constexpr int kCfPer = 32;                 // flags per thread
@@ -100,29 +101,17 @@ __global__ __launch_bounds__(kCfMidT) void k_cf_mid(const uint32_t* __restrict__
   }
 }
 
-// tile offset: from the scanned tile counts (tofs), or summed here from the
-// tile counts of the tiles before this one (tcnt, few tiles), or 0 (one tile).
-// The list goes out through LDS, one contiguous run per tile; a thread with
-// any flag set writes the ranks of its 32 flags as one 128-byte run (all
-// ones where the flag is clear).
-__global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ flags, uint64_t n,
-                                                 const uint32_t* __restrict__ tcnt,
-                                                 const uint32_t* __restrict__ tofs,
-                                                 uint32_t* __restrict__ list,
-                                                 uint32_t* __restrict__ rank,
-                                                 uint32_t* __restrict__ count) {
-  __shared__ uint32_t lds[kCfT / 64 + 1];
-  __shared__ uint32_t stage[kCfTile];
-  const uint64_t t0 = (uint64_t)blockIdx.x * kCfTile;
+// Writes one tile's part of the list and/or ranks, given the tile's flag bits
+// per thread (m), its first flag t0 and its offset base; returns the tile's
+// count.  The list goes out through LDS, one contiguous run per tile; a
+// thread with any flag set writes the ranks of its 32 flags as one 128-byte
+// run (all ones where the flag is clear).
+__device__ inline uint32_t cf_tile(uint32_t m, uint64_t n, uint64_t t0, uint32_t base,
+                                   uint32_t* __restrict__ list, uint32_t* __restrict__ rank,
+                                   uint32_t* stage, uint32_t* lds) {
   const uint64_t i0 = t0 + (uint64_t)threadIdx.x * kCfPer;
-  uint32_t before = 0;
-  if (!tofs && tcnt)
-    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kCfT) before += tcnt[t];
-  const uint32_t m = cf_bits(flags, n, i0);
-  uint32_t tot, tb;
-  if (!tofs && tcnt) block_excl_scan<kCfT>(before, tb, lds);
+  uint32_t tot;
   const uint32_t lpos = block_excl_scan<kCfT>((uint32_t)__popc(m), tot, lds);
-  const uint32_t base = tofs ? tofs[blockIdx.x] : (tcnt ? tb : 0u);
   if (list) {
     uint32_t mm = m, p = lpos;
     while (mm) {
@@ -149,7 +138,55 @@ __global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ fl
         if (i0 + k < n) rank[i0 + k] = r[k];
     }
   }
+  return tot;
+}
+
+// tile offset: from the scanned tile counts (tofs), or summed here from the
+// tile counts of the tiles before this one (tcnt, few tiles), or 0 (one tile)
+__global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ flags, uint64_t n,
+                                                 const uint32_t* __restrict__ tcnt,
+                                                 const uint32_t* __restrict__ tofs,
+                                                 uint32_t* __restrict__ list,
+                                                 uint32_t* __restrict__ rank,
+                                                 uint32_t* __restrict__ count) {
+  __shared__ uint32_t lds[kCfT / 64 + 1];
+  __shared__ uint32_t stage[kCfTile];
+  const uint64_t t0 = (uint64_t)blockIdx.x * kCfTile;
+  uint32_t before = 0;
+  if (!tofs && tcnt)
+    for (uint32_t t = threadIdx.x; t < blockIdx.x; t += kCfT) before += tcnt[t];
+  const uint32_t m = cf_bits(flags, n, t0 + (uint64_t)threadIdx.x * kCfPer);
+  uint32_t tb = 0;
+  if (!tofs && tcnt) block_excl_scan<kCfT>(before, tb, lds);
+  const uint32_t base = tofs ? tofs[blockIdx.x] : (tcnt ? tb : 0u);
+  const uint32_t tot = cf_tile(m, n, t0, base, list, rank, stage, lds);
   if (count && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *count = base + tot;
+}
+
+// a few tiles (2 .. kCfSmallTiles) in one block: every tile's flags are
+// loaded first, then the tiles are written in order with a running offset
+constexpr int kCfSmallTiles = 8;
+
+__global__ __launch_bounds__(kCfT) void k_cf_small(const uint8_t* __restrict__ flags, uint64_t n,
+                                                  uint32_t* __restrict__ list,
+                                                  uint32_t* __restrict__ rank,
+                                                  uint32_t* __restrict__ count) {
+  __shared__ uint32_t lds[kCfT / 64 + 1];
+  __shared__ uint32_t stage[kCfTile];
+  uint32_t m[kCfSmallTiles];
+#pragma unroll
+  for (int t = 0; t < kCfSmallTiles; ++t) {
+    const uint64_t t0 = (uint64_t)t * kCfTile;
+    m[t] = t0 < n ? cf_bits(flags, n, t0 + (uint64_t)threadIdx.x * kCfPer) : 0u;
+  }
+  uint32_t carry = 0;
+#pragma unroll
+  for (int t = 0; t < kCfSmallTiles; ++t) {
+    const uint64_t t0 = (uint64_t)t * kCfTile;
+    if (t0 >= n) break;  // uniform
+    carry += cf_tile(m[t], n, t0, carry, list, rank, stage, lds);
+  }
+  if (count && threadIdx.x == 0) *count = carry;
 }
 
 void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uint32_t* rank,
@@ -157,6 +194,11 @@ void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uin
   const uint64_t ntiles = (n + kCfTile - 1) / kCfTile;
   if (ntiles == 0) {
     HIP_CHECK(hipMemsetAsync(count, 0, sizeof(uint32_t), st));
+    return;
+  }
+  if (ntiles > 1 && ntiles <= (uint64_t)kCfSmallTiles) {
+    k_cf_small<<<1, kCfT, 0, st>>>(flags, n, list, rank, count);
+    HIP_LAUNCH_CHECK();
     return;
   }
   uint32_t* tcnt = nullptr;
