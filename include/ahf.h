@@ -212,8 +212,8 @@ void ahf_hierarchy_free(ahf_hierarchy *h);
 
 /*
  * Kernel timing for profiling.  While enabled, the context records a pair of
- * HIP events on the build stream around every launch of its main kernels
- * ("keys", "rs_up", "rs_tscan", "rs_scatter", "gather", "level0_start",
+ * HIP events around every launch of its main kernels, on the stream the
+ * launch goes to ("keys", "rs_up", "rs_tscan", "rs_scatter", "gather",
  * "child_ranges", "heavy_chunk", "patches", "combine", "mark", "uf_hook",
  * "uf_cross"; the three "rs_" names are the tile histogram, tile offset and
  * scatter kernels of each radix-sort pass).  Enabling or

@@ -588,8 +588,10 @@ __device__ inline uint32_t tile_local_parent(uint32_t x, uint32_t y, uint32_t z)
 // DENSE0: the tile's parents are virtual (every level-0 cell exists, cell =
 // 8 * parent + digit, brick = parent); else parents are level-0 cells, a
 // refined one (prank != ~0) holds 8 cells of S_1 at 8 * prank + digit, and
-// bricks come from the level-0 slot -> level-1 brick map.  Level-0 cells
-// hold several particles each: their records are loaded four ahead.
+// bricks come from the level-0 slot -> level-1 brick map.  A cell's records
+// are loaded in batches (kTileBatch0 on level 0, whose cells hold several
+// particles each, kTileBatch1 on level 1), all of a batch before its first
+// record is used.
 template <bool DENSE0>
 __global__ __launch_bounds__(kTileT) void k_tile_deposit(
     const uint32_t* __restrict__ prank,
