@@ -255,7 +255,8 @@ ahf_status ahf_hierarchy_query_label(ahf_ctx *ctx, const ahf_hierarchy *h, uint3
  */
 typedef struct {
     uint32_t struct_size;   /* sizeof(ahf_server_desc) */
-    uint32_t n_streams;     /* concurrent builds, 1..16 */
+    uint32_t n_streams;     /* concurrent builds, 1..16; with more than one,
+                               each build keeps to its worker's one stream */
     uint32_t max_queue;     /* queued (not yet admitted) requests; 0 = 1024 */
     uint32_t flags;         /* reserved, 0 */
     uint64_t hbm_budget;    /* bytes for builds in flight + resident results;
