@@ -159,16 +159,16 @@ void Ws::release(Mark m) {
 }
 
 void Ws::reset() {
-  // fold several chunks into one so that the next build needs a single one
-  // (the old chunks go back for good; the callers have waited for the work
-  // that used them)
+  // fold several chunks into one of the high-water size, so that the next
+  // build of the same size needs a single chunk and nothing more (the old
+  // chunks, which grew geometrically, go back for good; the callers have
+  // waited for the work that used them)
   if (chunks_.size() > 1) {
-    size_t tot = 0;
-    for (auto& c : chunks_) tot += c.size;
     for (auto& c : chunks_) ctx_release(ctx_, c.p, c.size, st_);
     chunks_.clear();
     cur_ = 0;
-    Chunk c{static_cast<char*>(ctx_alloc(ctx_, tot, st_)), tot, 0};
+    const size_t want = (high_ + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
+    Chunk c{static_cast<char*>(ctx_alloc(ctx_, want, st_)), want, 0};
     chunks_.push_back(c);
   }
   for (auto& c : chunks_) c.used = 0;

@@ -27,8 +27,10 @@ double now_ms() {
 // (2 x 12 B pairs + 2 x 32 B records per particle), the dense domain grid
 // arrays, the refined levels and labels, and the deposit scratch that the
 // second stream keeps to the end of the build.  Measured on the device
-// (memory in use after one build on a fresh context, result included):
-// 294 B per particle at 2^24, 263 at 2e6, 151 MB at 2e5 particles.
+// (memory in use after a build, result and the context's folded workspace
+// included): 209 B per particle at 2^24, 230 at 2e6, 151 MB at 2e5
+// particles; the margin covers a first build, whose workspace grows
+// geometrically before it is folded to its high-water size.
 uint64_t estimate_bytes(uint64_t n, uint32_t g) {
   const uint64_t dense = 1ull << (3 * g);
   return 300ull * n + 48ull * dense + (160ull << 20);
