@@ -36,8 +36,8 @@ def _key(x: int, y: int, z: int, bits: int) -> int:
 def brute(p, g, thr_dom, thr_ref, max_levels, conn=26, density=False):
     """Returns a list of dicts, one per level, with dense arrays indexed [x,y,z]:
     inS, count, flag, mass (numpy float64, zero outside E), number (TSC particle
-    number), inE, patch (-1 off S), plus per-patch parents and the smallest key
-    of every patch.  density: refine where the TSC particle number exceeds the
+    number), inE, patch (-1 off S), plus per-patch parents, the smallest key
+    of every patch, and per patch its cells, particles and particle mass.  density: refine where the TSC particle number exceeds the
     threshold instead of the count."""
     X = np.asarray(p.X, np.int64); Y = np.asarray(p.Y, np.int64); Z = np.asarray(p.Z, np.int64)
     fx = np.asarray(p.fx, np.float64); fy = np.asarray(p.fy, np.float64)
@@ -59,6 +59,9 @@ def brute(p, g, thr_dom, thr_ref, max_levels, conn=26, density=False):
         count = np.zeros((n, n, n), np.int64)
         inP = inS[cx, cy, cz]
         np.add.at(count, (cx[inP], cy[inP], cz[inP]), 1)
+        # particle mass held by each cell (the particles whose cell it is)
+        cell_mass = np.zeros((n, n, n))
+        np.add.at(cell_mass, (cx[inP], cy[inP], cz[inP]), mass[inP])
         field = np.zeros((n, n, n))
         number = np.zeros((n, n, n))
         for i in np.nonzero(inP)[0]:
@@ -127,6 +130,19 @@ def brute(p, g, thr_dom, thr_ref, max_levels, conn=26, density=False):
                     z |= ((pk >> (3 * j)) & 1) << j
                 parents.append(int(out[L - 1]["patch"][x >> 1, y >> 1, z >> 1]))
             lev["patch_parent"] = parents
+            # per patch, walking the dense grid cell by cell: cells of S in
+            # it, particles inside those cells, and their mass
+            ncells = [0] * npatch
+            npart = [0] * npatch
+            pmass = [0.0] * npatch
+            for x, y, z in cells:
+                pid = int(patch[x, y, z])
+                ncells[pid] += 1
+                npart[pid] += int(count[x, y, z])
+                pmass[pid] += float(cell_mass[x, y, z])
+            lev["patch_ncells"] = ncells
+            lev["patch_nparticles"] = npart
+            lev["patch_mass"] = pmass
         out.append(lev)
         if not flag.any():
             break

@@ -276,12 +276,18 @@ def test_input_permutation_invariance():
         assert np.array_equal(a.cell_patch, b.cell_patch)
         assert np.array_equal(a.field_key, b.field_key)
         np.testing.assert_allclose(a.field_mass, b.field_mass, rtol=1e-13, atol=1e-300)
-    # the permutation maps the same particles to the same sorted slots
-    assert np.array_equal(perm[order2], order) or True  # ties may reorder; check the multiset
+    # the permutation maps the same particles to the same runs of equal keys:
+    # within a run, the stable sort of q orders them by their index in q, that
+    # of p by their index in p, so the runs hold the same particles and p's
+    # run is ascending
     B = p.g + p.max_levels
     k1 = morton_py(p.X >> (21 - B), p.Y >> (21 - B), p.Z >> (21 - B), B)[order]
     k2 = morton_py(q.X >> (21 - B), q.Y >> (21 - B), q.Z >> (21 - B), B)[order2]
     assert np.array_equal(k1, k2)
+    assert np.any(k1[1:] == k1[:-1]), "the case should have ties"
+    mapped = perm[order2].astype(np.int64)
+    runs_sorted = mapped[np.lexsort((mapped, k1))]
+    assert np.array_equal(runs_sorted, order.astype(np.int64))
 
 
 # ---------------------------------------------------------------- special cases
@@ -391,6 +397,12 @@ def test_oracle_matches_dense_brute_force(name, make, conn):
             assert list(lv.patch_parent) == d["patch_parent"]
             for pid, mk in enumerate(d["patch_minkey"]):
                 assert int(lv.cell_key[lv.cell_patch == pid].min()) == mk
+            # per-patch statistics, summed cell by cell on the dense grid
+            assert list(lv.patch_ncells.astype(int)) == d["patch_ncells"]
+            assert list(lv.patch_nparticles.astype(int)) == d["patch_nparticles"]
+            np.testing.assert_allclose(lv.patch_mass, d["patch_mass"], rtol=1e-12, atol=0)
+            assert sum(d["patch_ncells"]) == len(lv.cell_key)
+            assert sum(d["patch_nparticles"]) == lv.n_particles
 
 
 # ---------------------------------------------------------------- probe
