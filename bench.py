@@ -2,9 +2,11 @@
 
 One step = one complete build of the adaptive density hierarchy (Morton keys,
 stable sort, per-level counts, refinement flags, TSC deposit, FP64 totals,
-grid-tree labels) of the 16.8M-particle lattice + NFW-halo snapshot (256^3
-particles, 128^3 domain grid, threshold 5, up to 10 levels), with the input
-already resident in HBM.  Prints one JSON line.
+grid-tree labels) of the 134M-particle lattice + NFW-halo + subhalo snapshot
+(512^3 particles, 256^3 domain grid, threshold 5, up to 12 levels), with the
+input already resident in HBM; the 16.8M snapshot (256^3 particles, 128^3
+domain grid, up to 10 levels) is measured the same way under its own key.
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,34 +26,35 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particles/s through full hierarchy build (1 GPU, % HBM peak); p50/p99 latency"
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_rs_scatter_lattice-nfw-16.8M.txt")
-# the files the scatter kernel is compiled from
-SCATTER_SRC = [os.path.join(ROOT, "paper_0904_3662_amd", "csrc", f)
-               for f in ("ahf_prims.hip", "ahf_dev.h", "ahf_internal.h")]
+# the files every kernel of the library is compiled from: a PMC summary holds
+# their SHA-256 and is used only while they are unchanged
+KERNEL_SRC = [os.path.join(ROOT, "paper_0904_3662_amd", "csrc", f)
+              for f in ("ahf_prims.hip", "ahf_levels.hip", "ahf_dev.h", "ahf_internal.h")]
 
 
-def scatter_source_hash():
+def kernel_source_hash():
     h = hashlib.sha256()
-    for f in SCATTER_SRC:
+    for f in KERNEL_SRC:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per scatter launch from the committed PMC summary (FETCH_SIZE
-    and WRITE_SIZE runs scaled by a copy kernel of known size), or None when
-    the summary is for another workload or the scatter source has changed
-    since the counters were taken."""
-    if workload != "lattice-nfw-16.8M" or not os.path.exists(PMC_SUMMARY):
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of one kernel from the committed PMC summary
+    profiles/pmc_<kernel>_<workload>.txt (FETCH_SIZE and WRITE_SIZE runs scaled
+    by a copy kernel of known size), or None when there is none or the kernel
+    sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(PMC_SUMMARY):
-        if line.startswith("rs_scatter_traffic_bytes_per_launch:"):
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
             vals["t"] = float(line.split(":")[1])
         if line.startswith("source_sha256"):
             vals["h"] = line.split(":")[1].strip()
-    if "t" not in vals or vals.get("h") != scatter_source_hash():
+    if "t" not in vals or vals.get("h") != kernel_source_hash():
         return None
     return vals["t"]
 
@@ -96,19 +99,76 @@ def algorithmic_bytes(n, levels, sp=24):
     return b
 
 
-def cpu_baseline(snap, seconds_target=20.0):
-    """The FP64 oracle on a bounded random sample of the same workload."""
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "affinity": share}
+
+
+def sub_cubes(snap, k, count, seed=12345):
+    """`count` distinct cubes of k^3 domain cells (drawn at random among the
+    (2^g / k)^3 cubes on a grid of k cells), each as the snapshot's particles
+    inside it: samples of the same workload at the same density, which the
+    oracle refines as deeply as the whole snapshot (only cells at a cube's
+    faces see a different neighbourhood)."""
+    nc = (1 << snap.g) // k
+    sh = 21 - snap.g
+    cid = np.zeros(snap.n, np.int64)
+    inside = np.ones(snap.n, bool)
+    for a in (snap.X, snap.Y, snap.Z):
+        c = (a >> sh) // k
+        inside &= c < nc
+        cid = cid * nc + np.minimum(c, nc - 1)
+    cid[~inside] = -1
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = rng.permutation(nc ** 3)[:count]
+    return [snap.subset(np.nonzero(cid == j)[0], f"{snap.name}-cube{k}") for j in pick], nc
+
+
+def cpu_baseline(snap, k, threads, repeats=1):
+    """The FP64 oracle (its unchanged source built -O3 -march=native for this
+    host) on sub-cubes of the snapshot: once with one thread on one sub-cube
+    (median of `repeats` runs), and once with `threads` threads, each running
+    the oracle on its own sub-cube at the same time (the oracle is one thread;
+    the ctypes call releases the interpreter lock).  Value: the all-thread
+    aggregate in particles/s."""
     import oracle
-    rng = np.random.Generator(np.random.PCG64(12345))
-    n = min(snap.n, 1 << 22)  # about 20 s of single-thread oracle work
-    idx = np.sort(rng.choice(snap.n, n, replace=False))
-    sub = snap.subset(idx, "sample")
+    from concurrent.futures import ThreadPoolExecutor
+    oracle.build_library(force=True, native=True)
+    subs, nc = sub_cubes(snap, k, max(threads, 1))
+    one = []
+    for r in range(repeats):
+        t0 = time.perf_counter()
+        lev, _ = oracle.build(subs[0], native=True)
+        one.append(time.perf_counter() - t0)
+    t1 = float(np.median(one))
+
+    def run(sb):
+        oracle.build(sb, native=True)
     t0 = time.perf_counter()
-    oracle.build(sub)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} particles drawn at random (seed 12345) from the 16.8M snapshot, "
-                      f"same grid parameters, single-threaded FP64 oracle, {dt:.1f} s"}
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(run, subs[:threads]))
+    tall = time.perf_counter() - t0
+    nall = sum(sb.n for sb in subs[:threads])
+    info = host_info()
+    frac = f"1/{nc ** 3}"
+    return {"value": nall / tall, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} sub-cubes of {k}^3 domain cells ({frac} of the box each, "
+                      f"{nall} particles in all) of the {snap.name} snapshot, same grid "
+                      f"parameters, one oracle thread per sub-cube, {tall:.1f} s wall",
+            "single_thread": {"value": subs[0].n / t1, "seconds": t1, "particles": subs[0].n,
+                              "levels": len(lev), "runs": repeats},
+            "build": "gcc -O3 -march=native", **info}
 
 
 def _pct(a, q):
@@ -269,13 +329,163 @@ def run_served(args):
     print(json.dumps(out), flush=True)
 
 
+# per-launch algorithmic bytes of the kernels that can be the roofline kernel
+# (what the step must move, not what the implementation moves):
+#  rs_scatter: one radix pass reads and writes every element (sort_scatter_bytes)
+#  gather: the sorted word (8 B) and the payload X,Y,Z,fx,fy,fz (24 B) read,
+#          the payload (24 B), the particle index (4 B) and the full key (8 B)
+#          written per particle, and the level-0 cell starts (4 B per cell)
+#  tile_deposit0/1: the level's particles (24 B each), the cell ranges (8 B per
+#          cell of S_L) and the field (4 B per brick cell) -- the per-level
+#          deposit terms of the algorithmic byte count
+ROOFLINE_KERNELS = ("rs_scatter", "gather", "tile_deposit0", "tile_deposit1")
+
+
+def kernel_alg_bytes(name, n, key_bits, g, lv_info, launches_per_step):
+    if name == "rs_scatter":
+        return sort_scatter_bytes(n, key_bits) / max(launches_per_step, 1)
+    if name == "gather":
+        return 68.0 * n + 4.0 * ((1 << (3 * g)) + 1)
+    L = 0 if name == "tile_deposit0" else 1
+    if L >= len(lv_info):
+        return None
+    d = lv_info[L]
+    return 24.0 * d["n_particles"] + 8.0 * d["n_cells"] + 32.0 * d["n_bricks"]
+
+
+def measure(ctx, snap, dev, stream, steps, warmup, extras=True):
+    """Warm-up builds (the first also records the level sizes, the second the
+    per-kernel split with every kernel timed), then `steps` timed builds with
+    HIP events only around the roofline kernel, on the stream it runs on."""
+    import torch
+    from paper_0904_3662_amd import ahf
+
+    def step():
+        h, _ = ahf.build_snapshot(ctx, snap, dev=dev, stream=stream)
+        return h
+
+    names = ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "child_ranges",
+             "heavy_chunk", "tile_deposit0", "tile_deposit1", "tile_halo", "patches",
+             "combine", "mark", "uf_hook", "uf_cross")
+    lv_info = None
+    ksplit = {}
+    for i in range(max(warmup, 2)):
+        if i == 1:
+            ctx.profile_only(None)
+            ctx.set_profiling(True)
+        h = step()
+        if i == 0:
+            lv_info = [dict(n_particles=v.n_particles, n_cells=v.n_cells, n_bricks=v.n_bricks,
+                            n_refined=v.n_refined, n_patches=v.n_patches)
+                       for v in (h.view(L) for L in range(h.num_levels()))]
+        h.free()
+        if i == 1:
+            torch.cuda.synchronize()
+            ksplit = {nm: ctx.kernel_time(nm) for nm in names}
+            ctx.set_profiling(False)
+        print(f"# {snap.name}: warmup {i} done", file=sys.stderr, flush=True)
+    n = snap.n
+    key_bits = 3 * (snap.g + snap.max_levels)
+    # the roofline kernel: the one of the candidates with the most time per build
+    rk = max(ROOFLINE_KERNELS, key=lambda nm: ksplit.get(nm, (0, 0.0))[1])
+    per_step = max(ksplit.get(rk, (1, 0.0))[0], 1)
+
+    ctx.profile_only([rk])
+    ctx.set_profiling(True)
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(steps):
+        a = time.perf_counter()
+        h = step()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+        h.free()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    launches, tms = ctx.kernel_time(rk)
+    ctx.set_profiling(False)
+    print(f"# {snap.name}: {steps} steps in {total:.3f} s", file=sys.stderr, flush=True)
+
+    ms_per_step = total * 1e3 / steps
+    avg_ms = tms / max(launches, 1)
+    alg = kernel_alg_bytes(rk, n, key_bits, snap.g, lv_info, per_step)
+    achieved = alg / (avg_ms * 1e-3) / 1e9 if launches and alg else None
+    traffic = measured_traffic(snap.name, rk)
+    out = {
+        "value": n * steps / total,
+        "ms_per_step": ms_per_step,
+        "p50_ms": _pct(lat, 50),
+        "p99_ms": _pct(lat, 99),
+        "end_to_end_hbm_frac": algorithmic_bytes(n, lv_info) / (ms_per_step * 1e-3) /
+                               (HBM_PEAK_GBS * 1e9),
+        "roofline": {"bound": "hbm", "kernel": rk, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "traffic_over_algorithmic": None if traffic is None else traffic / alg,
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_ms": avg_ms,
+                     "launches": launches},
+        "kernels_ms_per_step": {nm: v[1] for nm, v in ksplit.items()},
+        "levels": lv_info,
+    }
+    # the other candidates, from the profiled warm-up build
+    others = {}
+    for nm in ROOFLINE_KERNELS:
+        cnt, t = ksplit.get(nm, (0, 0.0))
+        b = kernel_alg_bytes(nm, n, key_bits, snap.g, lv_info, cnt)
+        if cnt and b:
+            gbs = b / (t / cnt * 1e-3) / 1e9
+            others[nm] = {"achieved": gbs, "frac": gbs / HBM_PEAK_GBS, "avg_launch_ms": t / cnt,
+                          "algorithmic_bytes_per_launch": b, "launches_per_build": cnt}
+    out["kernel_rooflines"] = others
+    if not extras:
+        return out
+
+    # host/substructure classification of the grid tree (a step after the
+    # labels): wall time of the classification call on built hierarchies
+    cls = []
+    for i in range(3):
+        h = step()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        h.classify(ctx, stream)
+        cls.append((time.perf_counter() - a) * 1e3)
+        nstruct = h.structures()["n_structures"]
+        h.free()
+    # the paper-literal density criterion (refine on the TSC particle number):
+    # same workload and thresholds, whole builds timed
+    dens = []
+    for i in range(4):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        h, _ = ahf.build_snapshot(ctx, snap, dev=dev, stream=stream, density_criterion=True)
+        torch.cuda.synchronize()
+        dens.append((time.perf_counter() - a) * 1e3)
+        dens_levels = h.num_levels()
+        h.free()
+    out["substructure"] = {"ms": float(np.median(cls)), "structures": int(nstruct)}
+    out["density_criterion"] = {"ms_per_build": float(np.median(dens[1:])),
+                                "levels_built": int(dens_levels)}
+    return out
+
+
+WORKLOADS = {"134m": ("snapshot_134m", 2), "16m": ("snapshot_16m", 1), "32k": ("small_mixed", 0)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="16m", choices=["16m", "32k"])
+    ap.add_argument("--cpu-cube", type=int, default=48,
+                    help="sub-cube edge in domain cells for the CPU baseline")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads for the CPU baseline (0: the host's share, at most 16)")
+    ap.add_argument("--cpu-repeats", type=int, default=1)
+    ap.add_argument("--workload", default="134m", choices=sorted(WORKLOADS))
+    ap.add_argument("--extra-workload", default="16m", choices=sorted(WORKLOADS) + ["none"],
+                    help="a second workload measured the same way, reported under its name")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "served"])
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--pool", type=int, default=8)
@@ -295,108 +505,41 @@ def main():
     import torch
     from paper_0904_3662_amd import ahf, synth
 
-    t0 = time.perf_counter()
-    snap = synth.snapshot_16m(1) if args.workload == "16m" else synth.small_mixed(0)
-    print(f"# generated {snap.name}: {snap.n} particles in {time.perf_counter() - t0:.1f} s",
-          file=sys.stderr, flush=True)
+    def make(w):
+        fn, seed = WORKLOADS[w]
+        t0 = time.perf_counter()
+        sn = getattr(synth, fn)(seed)
+        print(f"# generated {sn.name}: {sn.n} particles in {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        return sn
+
+    snap = make(args.workload)
     torch.cuda.set_device(0)
-    dev = ahf.snapshot_to_device(snap)
-    torch.cuda.synchronize()
     ctx = ahf.Context(0)
     stream = torch.cuda.current_stream()
-
-    def step():
-        h, _ = ahf.build_snapshot(ctx, snap, dev=dev, stream=stream)
-        return h
-
-    for i in range(args.warmup):
-        h = step()
-        if i == 0:
-            levels = [h.view(L) for L in range(h.num_levels())]
-            lv_info = [dict(n_particles=v.n_particles, n_cells=v.n_cells, n_bricks=v.n_bricks,
-                            n_refined=v.n_refined, n_patches=v.n_patches) for v in levels]
-        h.free()
-        print(f"# warmup {i} done", file=sys.stderr, flush=True)
-    if args.warmup == 0:
-        h = step()
-        lv_info = [dict(n_particles=h.view(L).n_particles, n_cells=h.view(L).n_cells,
-                        n_bricks=h.view(L).n_bricks, n_refined=h.view(L).n_refined,
-                        n_patches=h.view(L).n_patches) for L in range(h.num_levels())]
-        h.free()
-
-    # timed region: HIP events only around the roofline kernel (the sort
-    # scatter), on the build stream; each event recorded between two kernels
-    # holds the stream for a few microseconds, so nothing else is timed here
-    ctx.profile_only(["rs_scatter"])
-    ctx.set_profiling(True)
-    lat = []
+    dev = ahf.snapshot_to_device(snap)
     torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        a = time.perf_counter()
-        h = step()
+    res = measure(ctx, snap, dev, stream, args.steps, args.warmup)
+    del dev
+    extra = None
+    if args.extra_workload not in ("none", args.workload):
+        esnap = make(args.extra_workload)
+        edev = ahf.snapshot_to_device(esnap)
         torch.cuda.synchronize()
-        lat.append((time.perf_counter() - a) * 1e3)
-        h.free()
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    kstats = {"rs_scatter": ctx.kernel_time("rs_scatter")}
-    ctx.set_profiling(False)
-    print(f"# steps done: {args.steps} in {total:.3f} s", file=sys.stderr, flush=True)
-
-    # host/substructure classification of the grid tree (a step after the
-    # labels): wall time of the classification call on built hierarchies
-    cls = []
-    for i in range(3):
-        h = step()
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        h.classify(ctx, stream)
-        cls.append((time.perf_counter() - a) * 1e3)
-        nstruct = h.structures()["n_structures"]
-        h.free()
-
-    # the paper-literal density criterion (refine on the TSC particle number):
-    # same workload and thresholds, whole builds timed
-    dens = []
-    for i in range(4):
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        h, _ = ahf.build_snapshot(ctx, snap, dev=dev, stream=stream, density_criterion=True)
-        torch.cuda.synchronize()
-        dens.append((time.perf_counter() - a) * 1e3)
-        dens_levels = h.num_levels()
-        h.free()
-
-    # per-kernel split from two more builds, untimed, with every kernel timed
-    names = ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "child_ranges",
-             "heavy_chunk", "patches", "combine", "mark", "uf_hook", "uf_cross")
-    ctx.profile_only(None)
-    ctx.set_profiling(True)
-    for i in range(2):
-        step().free()
-    torch.cuda.synchronize()
-    ksplit = {name: ctx.kernel_time(name)[1] / 2 for name in names}
-    kstats["gather"] = ctx.kernel_time("gather")
-    ctx.set_profiling(False)
-
+        extra = measure(ctx, esnap, edev, stream, args.steps, args.warmup, extras=False)
+        extra["config"] = {"workload": esnap.name, "particles": esnap.n,
+                           "domain_grid": 1 << esnap.g, "threshold": esnap.dom_ref,
+                           "max_levels": esnap.max_levels, "levels_built": len(extra["levels"])}
+        del edev, esnap
     n = snap.n
-    ms_per_step = total * 1e3 / args.steps
-    value = n * args.steps / total
-    launches, tms = kstats["rs_scatter"]
-    avg_ms = tms / max(launches, 1)
-    alg_bytes_launch = sort_scatter_bytes(n, 3 * (snap.g + snap.max_levels)) / max(launches // args.steps, 1)
-    achieved = alg_bytes_launch / (avg_ms * 1e-3) / 1e9 if launches else None
-    b_alg = algorithmic_bytes(n, lv_info)
-    traffic = measured_traffic(snap.name)
     rec = {
         "metric": METRIC,
-        "value": value,
+        "value": res["value"],
         "unit": "particles/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -404,29 +547,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": snap.name, "particles": n, "domain_grid": 1 << snap.g,
                    "threshold": snap.dom_ref, "max_levels": snap.max_levels,
-                   "levels_built": len(lv_info)},
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "end_to_end_hbm_frac": b_alg / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
-        "roofline": {"bound": "hbm", "kernel": "rs_scatter", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": None if achieved is None else achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "traffic_over_algorithmic":
-                         None if traffic is None else traffic / alg_bytes_launch,
-                     "avg_launch_ms": avg_ms, "launches": launches},
-        # the particle gather, the largest single launch: 8 B word + 32 B record
-        # read, 32 B record + 4 B index + 8 B key written per particle (timed
-        # in the two builds after the timed region)
-        "gather_roofline": None if not kstats["gather"][0] else {
-            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-            "achieved": 84.0 * n / (kstats["gather"][1] / kstats["gather"][0] * 1e-3) / 1e9,
-            "frac": 84.0 * n / (kstats["gather"][1] / kstats["gather"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "kernels_ms_per_step": ksplit,
-        "substructure": {"ms": float(np.median(cls)), "structures": int(nstruct)},
-        "density_criterion": {"ms_per_build": float(np.median(dens[1:])),
-                              "levels_built": int(dens_levels)},
-        "levels": lv_info,
+                   "levels_built": len(res["levels"])},
     }
+    rec.update({k: v for k, v in res.items() if k not in ("value", "ms_per_step")})
+    if extra is not None:
+        rec["workload_" + extra["config"]["workload"]] = extra
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -434,9 +559,13 @@ def main():
         torch.mul(a, 1.0, out=b)   # a plain streaming kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         rec["copy_probe_bytes"] = 2 * a.numel() * 4
-    if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(snap)
+        del a, b
     ctx.close()
+    if not args.no_cpu_baseline:
+        share = host_info()["affinity"]
+        threads = args.cpu_threads or min(16, share)
+        rec["cpu_baseline"] = cpu_baseline(snap, args.cpu_cube, threads, args.cpu_repeats)
+        print("# cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(rec), flush=True)
 
 

@@ -214,9 +214,12 @@ void ahf_hierarchy_free(ahf_hierarchy *h);
  * Kernel timing for profiling.  While enabled, the context records a pair of
  * HIP events around every launch of its main kernels, on the stream the
  * launch goes to ("keys", "rs_up", "rs_tscan", "rs_scatter", "gather",
- * "child_ranges", "heavy_chunk", "patches", "combine", "mark", "uf_hook",
- * "uf_cross"; the three "rs_" names are the tile histogram, tile offset and
- * scatter kernels of each radix-sort pass).  Enabling or
+ * "child_ranges", "heavy_chunk", "tile_deposit0", "tile_deposit1",
+ * "tile_halo", "patches", "combine", "mark", "uf_hook", "uf_cross"; the three
+ * "rs_" names are the tile histogram, tile offset and scatter kernels of each
+ * radix-sort pass; "tile_deposit0/1" the dense tile deposits of levels 0 and
+ * 1, "tile_halo" their halo adds, "patches" and "combine" the deposit of the
+ * deeper levels).  Enabling or
  * disabling clears the accumulated times.  ahf_ctx_kernel_time returns the
  * number of launches and their summed device time (ms) for one name, reading
  * the events of finished builds.
@@ -246,12 +249,18 @@ ahf_status ahf_hierarchy_query_label(ahf_ctx *ctx, const ahf_hierarchy *h, uint3
  * take admitted requests in submission order, so requests that arrive while
  * others are on the GPU start as soon as a worker and HBM are free and their
  * kernels overlap on the device.  A request is admitted when its estimated
- * footprint (inputs excluded) fits the HBM budget together with everything
- * in flight and resident; finished hierarchies stay resident for label
- * queries until released, and the least recently used finished ones are
- * evicted when an admission needs their memory.  Results do not depend on
- * what else runs: every build is deterministic.  All server calls are
- * thread-safe.
+ * footprint (inputs excluded) fits the HBM budget together with the device
+ * memory the workers' contexts hold (finished results, cached blocks,
+ * workspaces; for contexts with allocation callbacks, what they have
+ * allocated and not freed) and the builds in flight.  To make room, cached
+ * blocks are given back first, then finished results that no client holds
+ * are evicted least recently used first, then idle workers' workspaces are
+ * given back.  A result that ahf_poll or ahf_wait has handed out is held by
+ * the client and never evicted until ahf_release.  If nothing runs and only
+ * held results stand in the way, the waiting request fails with AHF_ELIMIT
+ * rather than wait for ever.  Results do not depend on what else runs: every
+ * build is deterministic.  All server calls are thread-safe; none may be in
+ * progress when ahf_server_destroy is called.
  */
 typedef struct {
     uint32_t struct_size;   /* sizeof(ahf_server_desc) */
@@ -264,10 +273,15 @@ typedef struct {
 } ahf_server_desc;
 
 typedef struct {
-    uint64_t submitted, completed, failed, evicted, released;
+    uint64_t submitted, completed, failed, evicted, released;  /* released
+                                  counts dropped results and canceled requests */
     uint64_t queued, running, resident;
-    uint64_t bytes_in_use;     /* estimates of running builds + resident results */
-    uint64_t bytes_peak;
+    uint64_t bytes_in_use;     /* device memory of the workers' contexts + what
+                                  the estimates of running builds add to it */
+    uint64_t bytes_peak;       /* largest bytes_in_use seen at an admission or
+                                  the end of a build */
+    uint64_t bytes_results;    /* device memory of the resident results (part of
+                                  bytes_in_use) */
 } ahf_server_stats;
 
 /* ctx supplies the device and the allocation callbacks; it must outlive the
@@ -282,9 +296,11 @@ ahf_status ahf_submit(ahf_server *s, const ahf_particles *particles, const ahf_p
                       uint64_t *ticket);
 
 /* AHF_PENDING while queued or running; AHF_OK with *h borrowed from the
- * server (valid until ahf_release or eviction); the build's error status if
- * it failed; AHF_ECANCELED if released before it ran; AHF_ENOTFOUND for an
- * unknown, released or evicted ticket. */
+ * server: from then on the client holds the result, which stays valid (it is
+ * never evicted) until ahf_release; the build's error status if it failed;
+ * AHF_ECANCELED if it was released while still queued (the 4096 most recent
+ * such tickets are remembered); AHF_ENOTFOUND for an unknown, released or
+ * evicted ticket. */
 ahf_status ahf_poll(ahf_server *s, uint64_t ticket, ahf_hierarchy **h);
 /* as ahf_poll, but waits while the request is pending */
 ahf_status ahf_wait(ahf_server *s, uint64_t ticket, ahf_hierarchy **h);
@@ -293,8 +309,10 @@ ahf_status ahf_wait(ahf_server *s, uint64_t ticket, ahf_hierarchy **h);
 ahf_status ahf_query_label(ahf_server *s, uint64_t ticket, uint32_t level, uint64_t n,
                            const uint64_t *keys, int32_t *out);
 
-/* Drops the result of a finished request, or cancels a queued one (its poll
- * then returns AHF_ENOTFOUND).  A running request is released when it ends. */
+/* Drops the result of a finished request (held or not), or cancels a queued
+ * one (its poll then returns AHF_ECANCELED; releasing a canceled ticket again
+ * forgets it).  A running request, or one with a label query in progress, is
+ * released when that ends. */
 ahf_status ahf_release(ahf_server *s, uint64_t ticket);
 
 /* submit, admission, start and end times of a request in ms on the host's

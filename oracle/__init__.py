@@ -19,19 +19,24 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ahf_oracle.c")
 LIB = os.path.join(HERE, "libahf_oracle.so")
+# the same source built for the host it runs on (-O3 -march=native), used only
+# to time the oracle as a CPU baseline
+LIB_NATIVE = os.path.join(HERE, "libahf_oracle_native.so")
 
 
-def build_library(force: bool = True) -> str:
+def build_library(force: bool = True, native: bool = False) -> str:
     """Compile the oracle with the host C compiler (gcc)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", SRC,
+    out = LIB_NATIVE if native else LIB
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
+        tmp = out + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", *opt, "-std=c11", "-Wall", "-shared", "-fPIC", SRC,
                         "-o", tmp, "-lm"], check=True)
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
 
 
-_lib = None
+_libs = {}
 
 _u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
 _f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
@@ -42,12 +47,12 @@ _u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build_library()
-        L = C.CDLL(LIB)
+def lib(native: bool = False):
+    if native not in _libs:
+        path = LIB_NATIVE if native else LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            build_library(force=True, native=native)
+        L = C.CDLL(path)
         L.orc_build.restype = C.c_int
         L.orc_build.argtypes = [C.c_uint64, _u32p, _u32p, _u32p, _f32p, _f32p, _f32p,
                                 C.c_void_p, C.c_double, C.c_int, C.c_double, C.c_double,
@@ -71,8 +76,8 @@ def lib():
         L.orc_probe_cell.argtypes = [C.c_void_p, C.c_int, C.c_uint64, _i64p, C.POINTER(C.c_double)]
         L.orc_morton.restype = C.c_uint64
         L.orc_morton.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
-        _lib = L
-    return _lib
+        _libs[native] = L
+    return _libs[native]
 
 
 def _arrays(p):
@@ -94,12 +99,13 @@ class Level:
 
 
 def build(p, g=None, dom_ref=None, ref_ref=None, max_levels=None, connectivity=26,
-          labels=True, mass_scalar=1.0, density=False):
+          labels=True, mass_scalar=1.0, density=False, native=False):
     """Run the oracle on a particle set (anything with X, Y, Z, fx, fy, fz and
     optionally mass attributes; parameters default to the object's own).
     density: refine on the TSC particle number of a cell instead of its
-    particle count.  Returns (levels, order)."""
-    L = lib()
+    particle count; native: the -O3 -march=native build of the same source.
+    Returns (levels, order)."""
+    L = lib(native)
     X, Y, Z, fx, fy, fz, m = _arrays(p)
     g = p.g if g is None else g
     dom_ref = p.dom_ref if dom_ref is None else dom_ref

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 import weakref
 
 import numpy as np
@@ -84,7 +85,38 @@ class ServerDesc(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in ("submitted", "completed", "failed", "evicted",
                                           "released", "queued", "running", "resident",
-                                          "bytes_in_use", "bytes_peak")]
+                                          "bytes_in_use", "bytes_peak", "bytes_results")]
+
+
+# device memory callbacks of ahf_ctx_desc
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class TorchMemory:
+    """Device memory from PyTorch's caching allocator, for ahf_ctx_desc: the
+    library's hierarchies and scratch space are then PyTorch-owned HBM, taken
+    and given back in the order of the stream the library passes."""
+
+    def __init__(self):
+        import torch
+        raw_alloc = torch._C._cuda_cudaCachingAllocator_raw_alloc
+        raw_delete = torch._C._cuda_cudaCachingAllocator_raw_delete
+
+        def alloc(user, nbytes, stream):
+            try:
+                return raw_alloc(int(nbytes), int(stream or 0))
+            except Exception:  # out of memory: the library reports AHF_ENOMEM
+                return None
+
+        def free(user, ptr, nbytes, stream):
+            try:
+                raw_delete(int(ptr))
+            except Exception:
+                pass
+        # the ctypes thunks must live as long as the context
+        self.alloc = ALLOC_FN(alloc)
+        self.free = FREE_FN(free)
 
 
 _lib = None
@@ -191,9 +223,23 @@ def _stream_handle(stream):
 
 
 class Context:
-    def __init__(self, device: int = 0):
+    """A library context.  memory="torch" (default): device memory comes from
+    PyTorch's caching allocator through ahf_ctx_desc's callbacks; "pool": the
+    library's own caching pool on hipMalloc; or any object with ctypes
+    callbacks `alloc` (ALLOC_FN) and `free` (FREE_FN)."""
+
+    def __init__(self, device: int = 0, memory="torch"):
         L = load()
-        d = CtxDesc(C.sizeof(CtxDesc), int(device), None, None, None)
+        if memory == "torch":
+            memory = TorchMemory()
+        elif memory == "pool":
+            memory = None
+        self._memory = memory  # keeps the callbacks alive
+        if memory is None:
+            d = CtxDesc(C.sizeof(CtxDesc), int(device), None, None, None)
+        else:
+            d = CtxDesc(C.sizeof(CtxDesc), int(device), C.cast(memory.alloc, C.c_void_p),
+                        C.cast(memory.free, C.c_void_p), None)
         h = C.c_void_p()
         _check(L.ahf_ctx_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -344,6 +390,9 @@ class Hierarchy:
             self._keep = None
 
     def __del__(self):
+        # at interpreter exit the allocator behind the context may be gone
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:

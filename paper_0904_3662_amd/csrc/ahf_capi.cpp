@@ -37,18 +37,24 @@ void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s) {
   if (c->alloc) {
     void* p = c->alloc(c->user, bytes, (void*)s);
     if (!p) throw Error{AHF_ENOMEM, "device allocation callback failed"};
+    std::lock_guard<std::mutex> lk(c->pool.mu);
+    c->pool.bytes_outstanding += bytes;
     return p;
   }
   const size_t r = round_size(bytes);
   std::lock_guard<std::mutex> lk(c->pool.mu);
+  // the smallest cached block that fits and wastes at most a quarter of it
   auto& fb = c->pool.free_blocks;
-  for (size_t i = 0; i < fb.size(); ++i) {
-    if (fb[i].first == r) {
-      void* p = fb[i].second;
-      fb[i] = fb.back();
-      fb.pop_back();
-      return p;
-    }
+  size_t best = fb.size();
+  for (size_t i = 0; i < fb.size(); ++i)
+    if (fb[i].first >= r && fb[i].first - r <= fb[i].first / 4 &&
+        (best == fb.size() || fb[i].first < fb[best].first))
+      best = i;
+  if (best < fb.size()) {
+    void* p = fb[best].second;
+    fb[best] = fb.back();
+    fb.pop_back();
+    return p;
   }
   void* p = nullptr;
   if (hipMalloc(&p, r) != hipSuccess) {
@@ -61,7 +67,15 @@ void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s) {
     }
   }
   c->pool.all.emplace_back(r, p);
+  c->pool.bytes_all += r;
   return p;
+}
+
+// size the pool allocated for block p (caller holds the pool lock)
+static size_t block_size(Ctx* c, void* p, size_t bytes) {
+  for (auto& a : c->pool.all)
+    if (a.second == p) return a.first;
+  return round_size(bytes);
 }
 
 void ctx_free(Ctx* c, void* p, size_t bytes, hipStream_t s) {
@@ -69,10 +83,12 @@ void ctx_free(Ctx* c, void* p, size_t bytes, hipStream_t s) {
   if (bytes == 0) bytes = 1;
   if (c->free) {
     c->free(c->user, p, bytes, (void*)s);
+    std::lock_guard<std::mutex> lk(c->pool.mu);
+    c->pool.bytes_outstanding -= std::min(c->pool.bytes_outstanding, bytes);
     return;
   }
   std::lock_guard<std::mutex> lk(c->pool.mu);
-  c->pool.free_blocks.emplace_back(round_size(bytes), p);
+  c->pool.free_blocks.emplace_back(block_size(c, p, bytes), p);
 }
 
 // gives one block back for good (not to the pool's cache): the workspace
@@ -81,11 +97,14 @@ void ctx_release(Ctx* c, void* p, size_t bytes, hipStream_t s) {
   if (!p) return;
   if (c->free) {
     c->free(c->user, p, bytes ? bytes : 1, (void*)s);
+    std::lock_guard<std::mutex> lk(c->pool.mu);
+    c->pool.bytes_outstanding -= std::min(c->pool.bytes_outstanding, bytes ? bytes : 1);
     return;
   }
   std::lock_guard<std::mutex> lk(c->pool.mu);
   for (size_t i = 0; i < c->pool.all.size(); ++i)
     if (c->pool.all[i].second == p) {
+      c->pool.bytes_all -= c->pool.all[i].first;
       c->pool.all[i] = c->pool.all.back();
       c->pool.all.pop_back();
       break;
@@ -100,6 +119,7 @@ static void release_free_blocks(Ctx* c) {
     (void)hipFree(b.second);
     for (size_t i = 0; i < c->pool.all.size(); ++i)
       if (c->pool.all[i].second == b.second) {
+        c->pool.bytes_all -= c->pool.all[i].first;
         c->pool.all[i] = c->pool.all.back();
         c->pool.all.pop_back();
         break;
@@ -113,11 +133,12 @@ void ctx_release_pool(Ctx* c) {
   release_free_blocks(c);
 }
 
-size_t hier_bytes(const Hier* h) {
-  size_t s = 0;
-  for (auto& a : h->mem.list) s += a.second;
-  return s;
+size_t ctx_device_bytes(Ctx* c) {
+  std::lock_guard<std::mutex> lk(c->pool.mu);
+  return c->alloc ? c->pool.bytes_outstanding : c->pool.bytes_all;
 }
+
+size_t hier_bytes(const Hier* h) { return h->mem.bytes(); }
 
 void* Ws::raw(size_t bytes) {
   bytes = (bytes + 255) & ~size_t(255);
@@ -162,14 +183,21 @@ void Ws::reset() {
   // fold several chunks into one of the high-water size, so that the next
   // build of the same size needs a single chunk and nothing more (the old
   // chunks, which grew geometrically, go back for good; the callers have
-  // waited for the work that used them)
+  // waited for the work that used them).  Never throws: when the new chunk
+  // cannot be had, the old ones stay.
   if (chunks_.size() > 1) {
-    for (auto& c : chunks_) ctx_release(ctx_, c.p, c.size, st_);
-    chunks_.clear();
-    cur_ = 0;
     const size_t want = (high_ + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
-    Chunk c{static_cast<char*>(ctx_alloc(ctx_, want, st_)), want, 0};
-    chunks_.push_back(c);
+    char* p = nullptr;
+    try {
+      p = static_cast<char*>(ctx_alloc(ctx_, want, st_));
+    } catch (const Error&) {
+      p = nullptr;
+    }
+    if (p) {
+      for (auto& c : chunks_) ctx_release(ctx_, c.p, c.size, st_);
+      chunks_.clear();
+      chunks_.push_back(Chunk{p, want, 0});
+    }
   }
   for (auto& c : chunks_) c.used = 0;
   cur_ = 0;
@@ -343,6 +371,10 @@ ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, con
     h->h.ctx = &ctx->c;
     h->h.mem.ctx = &ctx->c;
     h->h.mem.st = st;
+    // the arena's first block from the last hierarchy of this context, in
+    // steps of 2 MB so that builds of similar sizes reuse cached blocks
+    h->h.mem.first_hint = (size_t)(ctx->c.hier_bpp * 1.05 * (double)particles->n);
+    h->h.mem.first_hint = (h->h.mem.first_hint + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
     ctx->ws.bind(&ctx->c, st);
     ctx->ws.reset();
     ctx->ws_dep.bind(&ctx->c, st);
@@ -356,6 +388,7 @@ ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, con
     if (defer) finish_build(&ctx->c, &h->h);
     ctx->ws.reset();
     ctx->ws_dep.reset();
+    if (particles->n > 0) ctx->c.hier_bpp = (double)h->h.mem.bytes() / (double)particles->n;
   } catch (const Error& e) {
     // every stream idle before any scratch is reused or freed
     if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -31,6 +32,8 @@ struct Pool {
   std::mutex mu;  // hierarchies may be freed from another thread (server)
   std::vector<std::pair<size_t, void*>> free_blocks;  // (size, ptr)
   std::vector<std::pair<size_t, void*>> all;          // everything hipMalloc'd
+  size_t bytes_all = 0;       // sum of `all`: device memory the pool holds
+  size_t bytes_outstanding = 0;  // through the callbacks: allocated, not yet freed
 };
 
 // HIP-event timing of selected kernels (profiling mode of a context)
@@ -91,6 +94,9 @@ struct Ctx {
   // several of them, whose concurrent builds already fill the GPU (and whose
   // streams would otherwise outnumber the hardware queues many times over)
   bool one_stream = false;
+  // device bytes per particle of the last hierarchy built on this context:
+  // sizes the first block of the next hierarchy's arena
+  double hier_bpp = 0.0;
 };
 
 
@@ -109,6 +115,9 @@ void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s);  // throws AHF_ENOMEM
 void ctx_free(Ctx* c, void* p, size_t bytes, hipStream_t s);
 void ctx_release(Ctx* c, void* p, size_t bytes, hipStream_t s);  // not kept in the pool
 void ctx_release_pool(Ctx* c);
+// device memory the context holds: its pool (free blocks included), or what
+// it has allocated through the callbacks and not yet freed
+size_t ctx_device_bytes(Ctx* c);
 
 // Stack-like scratch space for one build: chunks are never moved, so every
 // pointer handed out stays valid until released.
@@ -132,6 +141,11 @@ class Ws {
   void reset();        // drop every allocation (memory kept for the next build)
   void free_all();     // give the memory back to the context
   size_t high_water() const { return high_; }
+  size_t capacity() const {
+    size_t t = 0;
+    for (auto& c : chunks_) t += c.size;
+    return t;
+  }
   Ctx* ctx() const { return ctx_; }
 
  private:
@@ -146,30 +160,50 @@ class Ws {
   size_t high_ = 0;
 };
 
-// Owned device allocations of one hierarchy.
+// Device memory of one hierarchy: an arena of a few large blocks from the
+// context's allocator, each array a 256-byte aligned piece of one of them
+// (so a build makes a handful of allocator calls, not one per array).  The
+// first block is sized from the previous hierarchy of the context (bytes per
+// particle); a block that is full is followed by one of at least a quarter of
+// everything so far.  Everything goes back at once.
 struct Owned {
   Ctx* ctx = nullptr;
   hipStream_t st = nullptr;
-  std::vector<std::pair<void*, size_t>> list;
+  std::vector<std::pair<void*, size_t>> list;  // blocks
+  size_t used = 0, room = 0;                   // of the last block
+  size_t first_hint = 0;                       // bytes for the first block
   template <class T>
   T* get(uint64_t n) {
-    const size_t b = (n ? n : 1) * sizeof(T);
-    void* p = ctx_alloc(ctx, b, st);
-    list.emplace_back(p, b);
-    return static_cast<T*>(p);
+    return static_cast<T*>(raw((n ? n : 1) * sizeof(T)));
+  }
+  void* raw(size_t b) {
+    b = (b + 255) & ~size_t(255);
+    if (list.empty() || used + b > room) {
+      size_t tot = 0;
+      for (auto& a : list) tot += a.second;
+      size_t want = b;
+      if (list.empty()) want = std::max(want, first_hint);
+      want = std::max(want, tot / 4);
+      want = std::max(want, size_t(1) << 20);
+      want = (want + (size_t(1) << 16) - 1) & ~((size_t(1) << 16) - 1);
+      void* p = ctx_alloc(ctx, want, st);
+      list.emplace_back(p, want);
+      used = 0;
+      room = want;
+    }
+    char* p = static_cast<char*>(list.back().first) + used;
+    used += b;
+    return p;
   }
   void release_all() {
     for (auto& a : list) ctx_free(ctx, a.first, a.second, st);
     list.clear();
+    used = room = 0;
   }
-  // frees one allocation made by get (no-op for null)
-  void drop(void* p) {
-    for (size_t i = list.size(); i-- > 0;)
-      if (list[i].first == p) {
-        ctx_free(ctx, p, list[i].second, st);
-        list.erase(list.begin() + (long)i);
-        return;
-      }
+  size_t bytes() const {
+    size_t t = 0;
+    for (auto& a : list) t += a.second;
+    return t;
   }
 };
 

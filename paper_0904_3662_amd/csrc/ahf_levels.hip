@@ -1767,16 +1767,16 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
       float* halo = wd.get<float>(ntiles * kTileH);
       const Level& l0 = h->lev[0];
       if (tiles0)
-        AHF_TIMED(ctx, "patches", ds,
+        AHF_TIMED(ctx, "tile_deposit0", ds,
                   (k_tile_deposit<true><<<(unsigned)ntiles, kTileT, 0, ds>>>(
                       nullptr, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, nullptr,
                       lv.mass, halo, lv.Spmass)));
       else
-        AHF_TIMED(ctx, "patches", ds,
+        AHF_TIMED(ctx, "tile_deposit1", ds,
                   (k_tile_deposit<false><<<(unsigned)ntiles, kTileT, 0, ds>>>(
                       rank0, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, l0.slot_child,
                       lv.mass, halo, lv.Spmass)));
-      AHF_TIMED(ctx, "combine", ds,
+      AHF_TIMED(ctx, "tile_halo", ds,
                 (k_tile_halo_add<<<(unsigned)ntiles, 256, 0, ds>>>(
                     tiles0 ? 1 : 0, pb - 2, tiles0 ? nullptr : l0.slot_child, halo, lv.mass)));
     } else {
@@ -1817,10 +1817,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     lv.nF = ctx->host_cnt[0];
     const uint32_t nD = can_refine ? ctx->host_cnt[3] : 0u;
     lv.Fs = h->mem.get<uint32_t>(lv.nF);  // filled from Ftmp by k_build_bricks below
-    if (lv.nF == 0 && lv.slot_f) {
-      h->mem.drop(lv.slot_f);
-      lv.slot_f = nullptr;
-    }
+    if (lv.nF == 0) lv.slot_f = nullptr;  // no refined cell: nothing to look up
     if (lv.nF == 0) {
       ws.release(lvl_mark);
       break;

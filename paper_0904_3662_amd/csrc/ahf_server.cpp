@@ -3,9 +3,11 @@
 // n_streams worker threads each own a context (scratch space, memory pool)
 // and a HIP stream of default priority.  Requests are admitted in submission
 // order when a worker is idle and their footprint fits the HBM budget next to
-// the builds in flight and the resident results; the least recently used
-// finished results are evicted to make room.  Builds on different workers run
-// concurrently, so their kernels overlap on the device.
+// the device memory the workers already hold (their results, cached blocks
+// and workspaces) and the builds in flight; finished results nobody holds are
+// evicted least recently used first, and cached blocks and idle workspaces are
+// given back, to make room.  Builds on different workers run concurrently, so
+// their kernels overlap on the device.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -37,7 +39,7 @@ uint64_t estimate_bytes(uint64_t n, uint32_t g) {
 }
 
 struct Request {
-  enum State { QUEUED, RUNNING, DONE, FAILED };
+  enum State { QUEUED, RUNNING, DONE, FAILED, CANCELED };
   ahf_particles p{};
   ahf_params prm{};
   State state = QUEUED;
@@ -48,14 +50,20 @@ struct Request {
   double t[4] = {0, 0, 0, 0};  // submit, admit, start, end
   uint64_t last_use = 0;
   int pins = 0;           // label queries in progress
+  bool held = false;      // polled by the client: never evicted until released
   bool release_when_done = false;
+  int worker = -1;        // the worker building or holding it
 };
 
 struct Worker {
   ahf_ctx* ctx = nullptr;
   hipStream_t st = nullptr;
   std::thread th;
+  bool busy = false;      // a build is running (guarded by the server lock)
 };
+
+// canceled tickets remembered for ahf_poll (the most recent ones)
+constexpr size_t kCanceledKept = 4096;
 
 ahf_status fail(ahf_status c, const std::string& m) {
   ahf::set_last_error(m);
@@ -71,8 +79,9 @@ struct ahf_server {
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
   std::map<uint64_t, Request> reqs;
+  std::deque<uint64_t> canceled;
   uint64_t next_ticket = 1;
-  uint64_t budget = 0, in_use = 0, peak = 0, lru = 0;
+  uint64_t budget = 0, peak = 0, lru = 0;
   uint32_t max_queue = 1024;
   bool stop = false;
   ahf_server_stats st{};
@@ -83,36 +92,88 @@ struct ahf_server {
 
 namespace {
 
-// frees a finished result; caller holds the lock
+// frees a finished result (its blocks go back to its worker's pool); caller
+// holds the lock
 void drop_result(ahf_server* s, Request& r) {
+  (void)s;
   if (r.h) ahf_hierarchy_free(r.h);
   r.h = nullptr;
-  s->in_use -= std::min<uint64_t>(s->in_use, r.bytes);
   r.bytes = 0;
 }
 
-// evict least recently used finished results until `need` more bytes fit;
-// caller holds the lock
+// Device memory the server accounts for: what every worker's context holds
+// (results, cached blocks, workspaces) plus, for each build in flight, what
+// its estimate exceeds the workspace its worker already holds (the build
+// reuses that first).  Caller holds the lock.
+uint64_t in_use(ahf_server* s) {
+  uint64_t t = 0;
+  for (auto& w : s->workers) t += ahf::ctx_device_bytes(&w.ctx->c);
+  for (auto& kv : s->reqs) {
+    const Request& r = kv.second;
+    if (r.state != Request::RUNNING) continue;
+    ahf_ctx* c = s->workers[(size_t)r.worker].ctx;
+    const uint64_t have = c->ws.capacity() + c->ws_dep.capacity();
+    t += r.est > have ? r.est - have : 0;
+  }
+  return t;
+}
+
+void note_peak(ahf_server* s) { s->peak = std::max(s->peak, in_use(s)); }
+
+// gives back memory that nothing uses: every worker's cached free blocks,
+// and the workspaces of idle workers; caller holds the lock
+void trim(ahf_server* s, bool workspaces) {
+  for (auto& w : s->workers) {
+    if (workspaces && !w.busy) {
+      w.ctx->ws.free_all();
+      w.ctx->ws_dep.free_all();
+    }
+    ahf::ctx_release_pool(&w.ctx->c);
+  }
+}
+
+// Makes room for `need` more bytes: cached blocks go first, then the least
+// recently used finished results that no client holds, then the idle
+// workers' workspaces.  Caller holds the lock.
 bool make_room(ahf_server* s, uint64_t need) {
-  while (s->in_use + need > s->budget) {
+  if (in_use(s) + need <= s->budget) return true;
+  trim(s, false);
+  while (in_use(s) + need > s->budget) {
     uint64_t best = 0, best_use = ~0ull;
     for (auto& kv : s->reqs) {
       const Request& r = kv.second;
-      if (r.state == Request::DONE && r.pins == 0 && r.last_use < best_use) {
+      if (r.state == Request::DONE && r.pins == 0 && !r.held && r.last_use < best_use) {
         best = kv.first;
         best_use = r.last_use;
       }
     }
-    if (!best) return false;
+    if (!best) break;
     Request& r = s->reqs[best];
     drop_result(s, r);
     s->reqs.erase(best);
     s->st.evicted++;
+    trim(s, false);
   }
-  return true;
+  if (in_use(s) + need <= s->budget) return true;
+  trim(s, true);
+  return in_use(s) + need <= s->budget;
+}
+
+// a label query in progress holds a result that becomes evictable after it
+bool any_pinned(ahf_server* s) {
+  for (auto& kv : s->reqs)
+    if (kv.second.pins > 0) return true;
+  return false;
+}
+
+size_t running_builds(ahf_server* s) {
+  size_t n = 0;
+  for (auto& w : s->workers) n += w.busy ? 1 : 0;
+  return n;
 }
 
 void worker_loop(ahf_server* s, Worker* w) {
+  const int wi = (int)(w - s->workers.data());
   for (;;) {
     uint64_t ticket = 0;
     Request* r = nullptr;
@@ -123,6 +184,17 @@ void worker_loop(ahf_server* s, Worker* w) {
         if (!s->queue.empty()) {
           Request& head = s->reqs[s->queue.front()];
           if (make_room(s, head.est)) break;
+          if (running_builds(s) == 0 && !any_pinned(s)) {
+            // nothing running and nothing left to evict: only results that
+            // clients hold are in the way, and waiting would never end
+            head.state = Request::FAILED;
+            head.status = AHF_ELIMIT;
+            head.t[3] = now_ms();
+            s->queue.pop_front();
+            s->st.failed++;
+            s->cv_done.notify_all();
+            continue;
+          }
         }
         s->cv_work.wait(lk);
       }
@@ -130,9 +202,10 @@ void worker_loop(ahf_server* s, Worker* w) {
       s->queue.pop_front();
       r = &s->reqs[ticket];
       r->state = Request::RUNNING;
+      r->worker = wi;
       r->t[1] = now_ms();
-      s->in_use += r->est;
-      s->peak = std::max(s->peak, s->in_use);
+      w->busy = true;
+      note_peak(s);
     }
     ahf_hierarchy* h = nullptr;
     const double t0 = now_ms();
@@ -140,21 +213,20 @@ void worker_loop(ahf_server* s, Worker* w) {
     const double t1 = now_ms();
     {
       std::lock_guard<std::mutex> lk(s->mu);
+      w->busy = false;
       r->t[2] = t0;
       r->t[3] = t1;
-      s->in_use -= std::min<uint64_t>(s->in_use, r->est);
       if (rc == AHF_OK) {
         r->state = Request::DONE;
         r->h = h;
         r->bytes = ahf::hier_bytes(&h->h);
-        s->in_use += r->bytes;
-        s->peak = std::max(s->peak, s->in_use);
         s->st.completed++;
       } else {
         r->state = Request::FAILED;
         r->status = rc;
         s->st.failed++;
       }
+      note_peak(s);
       r->last_use = ++s->lru;
       if (r->release_when_done) {
         drop_result(s, *r);
@@ -251,6 +323,10 @@ static ahf_status poll_locked(ahf_server* s, uint64_t ticket, ahf_hierarchy** h)
   Request& r = it->second;
   if (r.state == Request::QUEUED || r.state == Request::RUNNING) return AHF_PENDING;
   if (r.state == Request::FAILED) return fail(r.status, "the build failed");
+  if (r.state == Request::CANCELED) return fail(AHF_ECANCELED, "the request was canceled");
+  // the client holds the result from here on: it is not evicted until
+  // ahf_release, so the handle stays valid
+  r.held = true;
   r.last_use = ++s->lru;
   *h = r.h;
   return AHF_OK;
@@ -321,12 +397,28 @@ ahf_status ahf_release(ahf_server* s, uint64_t ticket) {
     return AHF_OK;
   }
   if (r.state == Request::QUEUED) {
+    // canceled before it ran: its poll answers AHF_ECANCELED (the most
+    // recent kCanceledKept canceled tickets are remembered)
     s->queue.erase(std::find(s->queue.begin(), s->queue.end(), ticket));
+    r.state = Request::CANCELED;
+    r.t[3] = now_ms();
+    s->canceled.push_back(ticket);
+    if (s->canceled.size() > kCanceledKept) {
+      s->reqs.erase(s->canceled.front());
+      s->canceled.pop_front();
+    }
+    s->st.released++;
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+    return AHF_OK;
+  }
+  if (r.state == Request::CANCELED) {
+    s->canceled.erase(std::find(s->canceled.begin(), s->canceled.end(), ticket));
   } else {
     drop_result(s, r);
+    s->st.released++;
   }
   s->reqs.erase(it);
-  s->st.released++;
   s->cv_work.notify_all();
   return AHF_OK;
 }
@@ -347,11 +439,15 @@ ahf_status ahf_server_get_stats(ahf_server* s, ahf_server_stats* out) {
   out->queued = s->queue.size();
   out->running = 0;
   out->resident = 0;
+  out->bytes_results = 0;
   for (auto& kv : s->reqs) {
     if (kv.second.state == Request::RUNNING) out->running++;
-    if (kv.second.state == Request::DONE) out->resident++;
+    if (kv.second.state == Request::DONE) {
+      out->resident++;
+      out->bytes_results += kv.second.bytes;
+    }
   }
-  out->bytes_in_use = s->in_use;
+  out->bytes_in_use = in_use(s);
   out->bytes_peak = s->peak;
   return AHF_OK;
 }

@@ -167,28 +167,45 @@ def test_fullsize_16m(ctx):
     check_fullsize(ctx, synth.snapshot_16m(1), seed=21)
 
 
-RUN_134M = os.environ.get("AHF_RUN_134M") == "1"
-SKIP_134M = "the 134M snapshot takes minutes of host generation; run with AHF_RUN_134M=1"
+@pytest.mark.timeout(900)
+def test_largest_tiled_grid_g8(ctx):
+    # 3M uniform particles on a 256^3 domain grid refined wherever a cell holds
+    # a particle: about 2.7M refined level-0 cells, more than 1/8 of the grid,
+    # so levels 0 and 1 both take the dense tile deposit at its largest grid
+    # (level-1 tiles of 8^3 cells over the whole 512^3 grid)
+    rng = np.random.Generator(np.random.PCG64(808))
+    X, fx = synth.quantize(rng.random(3_000_000))
+    Y, fy = synth.quantize(rng.random(3_000_000))
+    Z, fz = synth.quantize(rng.random(3_000_000))
+    snap = synth.Snapshot(X, Y, Z, fx, fy, fz, None, 8, 0.0, 0.0, 2, "uniform-3M-g8")
+    levels = check_fullsize(ctx, snap, seed=23)
+    assert 8 * levels[0]["n_refined"] >= 1 << 24
 
 
-@pytest.mark.skipif(not RUN_134M, reason=SKIP_134M)
+@pytest.fixture(scope="module")
+def snap134():
+    # 512^3 particles: 70% lattice, 30% in 20000 NFW hosts with 5 Plummer
+    # subhalos each; generated once for the tests below (about a minute)
+    print("generating the 134M snapshot", flush=True)
+    return synth.snapshot_134m(2)
+
+
 @pytest.mark.timeout(1500)
-def test_fullsize_134m_subsample_parity(ctx):
+def test_fullsize_134m_subsample_parity(ctx, snap134):
     # the 134M workload's seeded 64^3 subsample, full oracle parity
     from tests.gpu_compare import compare_hierarchy
     from paper_0904_3662_amd import ahf
-    s = synth.snapshot_134m(2)
+    s = snap134
     idx = np.sort(np.random.Generator(np.random.PCG64(64)).choice(s.n, 64 ** 3, replace=False))
     sub = s.subset(idx, "134M-subsample-64^3")
-    del s
+    print(f"case {sub.name}: n={sub.n}", flush=True)
     levels, order = oracle.build(sub)
     h, _ = ahf.build_snapshot(ctx, sub)
     compare_hierarchy(h, sub.n, levels, order)
     h.free()
 
 
-@pytest.mark.skipif(not RUN_134M, reason=SKIP_134M)
 @pytest.mark.timeout(1500)
-def test_fullsize_134m(ctx):
+def test_fullsize_134m(ctx, snap134):
     # 512^3 particles, 256^3 domain grid, threshold 5, up to 12 levels
-    check_fullsize(ctx, synth.snapshot_134m(2), seed=22)
+    check_fullsize(ctx, snap134, seed=22)
