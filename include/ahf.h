@@ -242,6 +242,20 @@ ahf_status ahf_hierarchy_query_label(ahf_ctx *ctx, const ahf_hierarchy *h, uint3
                                      uint64_t n, const uint64_t *keys, int32_t *out,
                                      void *stream);
 
+/*
+ * The same label query for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the keys and results are staged in a static device array of
+ * the library (3 MB, each GPU holding its own copy until the process ends)
+ * instead of the context's workspace, and no device memory is allocated or
+ * freed.  At most 262144 keys per call (AHF_ELIMIT beyond).  Every call on
+ * one GPU shares that array: calls that overlap on one GPU race and must be
+ * serialised by the caller.  Synchronous on `stream`; the hierarchy's device
+ * must be the one it was built on.  Other errors as ahf_hierarchy_query_label.
+ */
+ahf_status ahf_hierarchy_query_label_static(const ahf_hierarchy *h, uint32_t level, uint64_t n,
+                                            const uint64_t *keys, int32_t *out, void *stream);
+
 /* ------------------------------------------------------------------ serving
  *
  * A server builds hierarchies of many snapshot sub-volumes concurrently:

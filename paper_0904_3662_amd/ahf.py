@@ -32,6 +32,7 @@ EXPORTS = [
     "ahf_server_create", "ahf_submit", "ahf_poll", "ahf_wait", "ahf_query_label",
     "ahf_release", "ahf_ticket_times", "ahf_server_get_stats", "ahf_server_destroy",
     "ahf_classify_substructure", "ahf_hierarchy_structures",
+    "ahf_hierarchy_query_label_static",
 ]
 
 
@@ -153,6 +154,7 @@ def load():
     L.ahf_hierarchy_free.argtypes = [vp]
     L.ahf_hierarchy_free.restype = None
     L.ahf_hierarchy_query_label.argtypes = [vp, vp, C.c_uint32, C.c_uint64, vp, vp, vp]
+    L.ahf_hierarchy_query_label_static.argtypes = [vp, C.c_uint32, C.c_uint64, vp, vp, vp]
     L.ahf_server_create.argtypes = [vp, C.POINTER(ServerDesc), C.POINTER(vp)]
     L.ahf_submit.argtypes = [vp, C.POINTER(Particles), C.POINTER(Params), C.POINTER(C.c_uint64)]
     L.ahf_poll.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
@@ -380,6 +382,16 @@ class Hierarchy:
         _check(load().ahf_hierarchy_query_label(ctx.handle, self._h, int(level), len(k),
                                                 k.ctypes.data, out.ctypes.data,
                                                 _stream_handle(stream)))
+        return out
+
+    def query_label_static(self, level: int, keys: np.ndarray, stream=None) -> np.ndarray:
+        """query_label through the library's static staging area (allocates
+        no device memory; at most 262144 keys per call)."""
+        k = np.ascontiguousarray(keys, dtype=np.uint64)
+        out = np.empty(len(k), np.int32)
+        _check(load().ahf_hierarchy_query_label_static(self._h, int(level), len(k),
+                                                       k.ctypes.data, out.ctypes.data,
+                                                       _stream_handle(stream)))
         return out
 
     def free(self):

@@ -320,6 +320,16 @@ ahf_status ahf_ctx_create(const ahf_ctx_desc* desc, ahf_ctx** out) {
     return fail(AHF_EDEVICE, "no HIP device available");
   }
   if (desc->device < 0 || desc->device >= ndev) return fail(AHF_EINVAL, "device ordinal out of range");
+  // the static staging array's address on this device, once per device
+  try {
+    if (hipSetDevice(desc->device) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(AHF_EDEVICE, "hipSetDevice failed");
+    }
+    (void)static_scratch(desc->device);
+  } catch (const Error& e) {
+    return fail(e.code, e.msg);
+  }
   ahf_ctx* c = new (std::nothrow) ahf_ctx();
   if (!c) return fail(AHF_ENOMEM, "host allocation failed");
   c->c.device = desc->device;

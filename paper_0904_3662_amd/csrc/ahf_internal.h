@@ -305,6 +305,9 @@ void label_early(Ctx* ctx, Ws& wsd, Hier* h, uint32_t k1, hipStream_t st);
 void classify_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
 void classify_levels(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
 void finish_classify(Ctx* ctx, Hier* h, hipStream_t st);
+// the device address of the library's static staging array on `device`
+// (looked up once per device, with that device current)
+void* static_scratch(int device);
 // patch ids of level-L cells given by key (host arrays); level >= 1, labelled
 void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys_host,
                   int32_t* out_host, hipStream_t st);

@@ -31,6 +31,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "ahf_internal.h"
 
@@ -1901,6 +1902,47 @@ void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys
   ws.release(m);
 }
 
+// ------------------------------------------------------------ label queries without allocation
+//
+// For callers that cannot allocate device memory: the query keys and the
+// results are staged in one file-scope device array instead of the context's
+// workspace.  Each GPU holds its own copy of the array; its address on a
+// device comes from hipGetSymbolAddress, taken once per device with that
+// device current (the name itself is only a host-side stand-in).
+constexpr uint64_t kStaticQueryMax = 1ull << 18;  // keys per call (3 MB of staging)
+static __device__ __align__(256) uint64_t scratch[kStaticQueryMax + kStaticQueryMax / 2];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// the array's address on `device`, looked up on the first call for that
+// device (the caller has made it current)
+void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error{AHF_EINVAL, "device ordinal out of range"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+// patch ids of n level-L keys (host arrays) through the static staging area;
+// level >= 1, labelled, n <= kStaticQueryMax
+static void query_labels_static(const Hier* h, int L, uint64_t n, const uint64_t* keys_host,
+                                int32_t* out_host, hipStream_t st) {
+  const Level& lv = h->lev[L];
+  uint64_t* dk = static_cast<uint64_t*>(static_scratch(h->ctx->device));
+  int32_t* dout = reinterpret_cast<int32_t*>(dk + kStaticQueryMax);
+  HIP_CHECK(hipMemcpyAsync(dk, keys_host, n * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  k_query_label<<<grid_for(n), kT, 0, st>>>(make_tree(h), L, dk, n, lv.Bcell, lv.Spatch, dout);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemcpyAsync(out_host, dout, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
 // the two pinned level sets of a context (the early and the final label pass)
 static LabSet* lab_sets(Ctx* ctx) {
   if (!ctx->lab_pinned) HIP_CHECK(hipHostMalloc(&ctx->lab_pinned, 2 * sizeof(LabSet), hipHostMallocDefault));
@@ -2192,3 +2234,34 @@ void classify_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
 }
 
 }  // namespace ahf
+
+extern "C" ahf_status ahf_hierarchy_query_label_static(const ahf_hierarchy* h, uint32_t level,
+                                                       uint64_t n, const uint64_t* keys,
+                                                       int32_t* out, void* stream) {
+  using namespace ahf;
+  auto fail = [](ahf_status c, const char* m) {
+    set_last_error(m);
+    return c;
+  };
+  if (!h || (n && (!keys || !out))) return fail(AHF_EINVAL, "bad arguments");
+  if (level >= h->h.lev.size()) return fail(AHF_EINVAL, "level out of range");
+  if (level >= 1 && !h->h.labelled) return fail(AHF_EINVAL, "the hierarchy is not labelled");
+  if (n > kStaticQueryMax)
+    return fail(AHF_ELIMIT, "more keys than the static staging area holds (262144 per call)");
+  const uint32_t b = h->h.lev[level].b;
+  for (uint64_t i = 0; i < n; ++i)
+    if (3 * b < 64 && (keys[i] >> (3 * b)) != 0) return fail(AHF_EINVAL, "key beyond the level's bits");
+  if (n == 0) return AHF_OK;
+  if (level == 0) {
+    for (uint64_t i = 0; i < n; ++i) out[i] = -1;
+    return AHF_OK;
+  }
+  try {
+    HIP_CHECK(hipSetDevice(h->h.ctx->device));
+    query_labels_static(&h->h, (int)level, n, keys, out, (hipStream_t)stream);
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.code;
+  }
+  return AHF_OK;
+}
