@@ -395,11 +395,13 @@ def measure(ctx, snap, dev, stream, steps, warmup, extras=True):
     lat = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    infos = []
     for i in range(steps):
         a = time.perf_counter()
         h = step()
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - a) * 1e3)
+        infos.append(h.build_info())
         h.free()
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
@@ -427,6 +429,10 @@ def measure(ctx, snap, dev, stream, steps, warmup, extras=True):
                      "launches": launches},
         "kernels_ms_per_step": {nm: v[1] for nm, v in ksplit.items()},
         "levels": lv_info,
+        # timed builds sized ahead from the context's plan (no host wait per
+        # level), and the host waits for level counts per build
+        "planned_builds": sum(i["planned"] for i in infos),
+        "host_waits_per_build": float(np.mean([i["host_waits"] for i in infos])),
     }
     # the other candidates, from the profiled warm-up build
     others = {}

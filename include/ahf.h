@@ -203,12 +203,61 @@ ahf_status ahf_hierarchy_structures(const ahf_hierarchy *h, ahf_structures *out)
  * particles of every cell of every level are contiguous in this order. */
 ahf_status ahf_hierarchy_order(const ahf_hierarchy *h, const uint32_t **sorted_idx);
 
+/*
+ * Builds sized ahead.  After a build, the context remembers, per parameter
+ * set and size class (half octaves of n), how many cells each level refined
+ * and how many bricks the next level got, per particle.  A later build of
+ * that class is then enqueued level after level without the host waiting
+ * for any level's counts: every level is sized from the remembered counts
+ * (plus 15% and 64), the kernels read the true counts on the device, and a
+ * level that outgrows its room is detected on the device; that build is then
+ * redone with one host wait per level, which also updates the plan.  The
+ * results are the same either way.  Planning is on by default; disabling it
+ * also forgets the plans.  (Not used with AHF_DENSITY_CRITERION.)
+ */
+ahf_status ahf_ctx_set_planning(ahf_ctx *ctx, int enable);
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(ahf_build_info) */
+    uint32_t planned;       /* 1: the levels were sized ahead                */
+    uint32_t replanned;     /* 1: a planned attempt outgrew its room first    */
+    uint32_t host_waits;    /* host waits for level counts during the build   */
+    uint64_t device_bytes;  /* device memory the hierarchy holds              */
+} ahf_build_info;
+ahf_status ahf_hierarchy_build_info(const ahf_hierarchy *h, ahf_build_info *out);
+
 /* Per-build stage times in milliseconds, for profiling: [0] keys + sort +
  * gather and [1] levels (device time between events on the build stream),
  * [2] labels and [3] total (host clock around the call).  n <= 4. */
 ahf_status ahf_hierarchy_timings(const ahf_hierarchy *h, double *ms, uint32_t n);
 
 void ahf_hierarchy_free(ahf_hierarchy *h);
+
+/*
+ * Tuning of the TSC deposit by build size.  A cell holding more than `heavy`
+ * particles is summed by whole wavefronts in chunks instead of by one thread
+ * (one threshold for level 0, one for level 1, one for the deeper levels);
+ * batch_level1 records (2 or 4) are in flight per thread on level 1.  The
+ * results do not depend on the tuning beyond FP32 summation order (every
+ * choice is deterministic).  Defaults: heavy 64, 64, 64; batch 2.
+ */
+typedef struct {
+    uint32_t struct_size;       /* sizeof(ahf_tuning) */
+    uint32_t heavy_level0;      /* 1..64 */
+    uint32_t heavy_level1;      /* 1..64 */
+    uint32_t heavy_deeper;      /* 1..64 */
+    uint32_t batch_level1;      /* 2 or 4 */
+} ahf_tuning;
+
+/* Sets the context's tuning table: a build of n particles uses entries[i]
+ * for the largest min_n[i] <= n (the defaults when there is none).  Host
+ * arrays of n_entries (0 clears the table); copied.  AHF_EINVAL for values
+ * out of range.  A server's workers take the table of the context the
+ * server is created with. */
+ahf_status ahf_ctx_set_tuning(ahf_ctx *ctx, uint32_t n_entries, const uint64_t *min_n,
+                              const ahf_tuning *entries);
+/* The tuning a build of n particles would use. */
+ahf_status ahf_ctx_get_tuning(const ahf_ctx *ctx, uint64_t n, ahf_tuning *out);
 
 /*
  * Kernel timing for profiling.  While enabled, the context records a pair of

@@ -32,7 +32,8 @@ EXPORTS = [
     "ahf_server_create", "ahf_submit", "ahf_poll", "ahf_wait", "ahf_query_label",
     "ahf_release", "ahf_ticket_times", "ahf_server_get_stats", "ahf_server_destroy",
     "ahf_classify_substructure", "ahf_hierarchy_structures",
-    "ahf_hierarchy_query_label_static",
+    "ahf_hierarchy_query_label_static", "ahf_ctx_set_tuning", "ahf_ctx_get_tuning",
+    "ahf_ctx_set_planning", "ahf_hierarchy_build_info",
 ]
 
 
@@ -76,6 +77,17 @@ class LevelView(C.Structure):
 class Structures(C.Structure):
     _fields_ = [("n_structures", C.c_uint64), ("host", C.c_void_p), ("level", C.c_void_p),
                 ("patch", C.c_void_p), ("depth", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("heavy_level0", C.c_uint32),
+                ("heavy_level1", C.c_uint32), ("heavy_deeper", C.c_uint32),
+                ("batch_level1", C.c_uint32)]
+
+
+class BuildInfo(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("planned", C.c_uint32), ("replanned", C.c_uint32),
+                ("host_waits", C.c_uint32), ("device_bytes", C.c_uint64)]
 
 
 class ServerDesc(C.Structure):
@@ -149,6 +161,10 @@ def load():
     L.ahf_ctx_set_profiling.argtypes = [vp, C.c_int]
     L.ahf_ctx_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]
     L.ahf_ctx_profile_only.argtypes = [vp, C.c_char_p]
+    L.ahf_ctx_set_tuning.argtypes = [vp, C.c_uint32, vp, C.POINTER(Tuning)]
+    L.ahf_ctx_get_tuning.argtypes = [vp, C.c_uint64, C.POINTER(Tuning)]
+    L.ahf_ctx_set_planning.argtypes = [vp, C.c_int]
+    L.ahf_hierarchy_build_info.argtypes = [vp, C.POINTER(BuildInfo)]
     L.ahf_classify_substructure.argtypes = [vp, vp, vp]
     L.ahf_hierarchy_structures.argtypes = [vp, C.POINTER(Structures)]
     L.ahf_hierarchy_free.argtypes = [vp]
@@ -230,7 +246,7 @@ class Context:
     library's own caching pool on hipMalloc; or any object with ctypes
     callbacks `alloc` (ALLOC_FN) and `free` (FREE_FN)."""
 
-    def __init__(self, device: int = 0, memory="torch"):
+    def __init__(self, device: int = 0, memory="torch", tuning="auto"):
         L = load()
         if memory == "torch":
             memory = TorchMemory()
@@ -247,6 +263,14 @@ class Context:
         self._h = h
         self.device = device
         self._live = weakref.WeakSet()  # hierarchies drawing on this context's memory
+        # tuning="auto": the autotuner's table for this GPU, if it has been
+        # made (paper_0904_3662_amd/autotune.py); None: the library defaults;
+        # or a table [(min_n, dict)]
+        if tuning == "auto":
+            from paper_0904_3662_amd import autotune
+            tuning = autotune.load_table()
+        if tuning:
+            self.set_tuning(tuning)
 
     @property
     def handle(self):
@@ -265,6 +289,28 @@ class Context:
     def profile_only(self, names):
         """Time only these kernel names (a list; None or [] = all)."""
         _check(load().ahf_ctx_profile_only(self._h, ",".join(names or []).encode()))
+
+    def set_tuning(self, table):
+        """table: list of (min_n, dict(heavy_level0=, heavy_level1=,
+        heavy_deeper=, batch_level1=)); a build of n particles uses the entry
+        with the largest min_n <= n.  [] restores the defaults."""
+        n = len(table)
+        mins = np.array([int(t[0]) for t in table], np.uint64)
+        arr = (Tuning * max(n, 1))()
+        for i, (_, d) in enumerate(table):
+            arr[i] = Tuning(C.sizeof(Tuning), int(d["heavy_level0"]), int(d["heavy_level1"]),
+                            int(d["heavy_deeper"]), int(d["batch_level1"]))
+        _check(load().ahf_ctx_set_tuning(self._h, n, mins.ctypes.data if n else None, arr))
+
+    def set_planning(self, on: bool):
+        """Builds sized ahead from what earlier builds of the same class
+        needed (on by default); off also forgets the plans."""
+        _check(load().ahf_ctx_set_planning(self._h, 1 if on else 0))
+
+    def tuning(self, n: int) -> dict:
+        t = Tuning()
+        _check(load().ahf_ctx_get_tuning(self._h, int(n), C.byref(t)))
+        return {k: int(getattr(t, k)) for k, _ in Tuning._fields_ if k != "struct_size"}
 
     def kernel_time(self, name: str):
         """(launches, total device ms) of one kernel while profiling."""
@@ -322,6 +368,11 @@ class Hierarchy:
         p = C.c_void_p()
         _check(load().ahf_hierarchy_order(self._h, C.byref(p)))
         return p.value or 0
+
+    def build_info(self) -> dict:
+        b = BuildInfo()
+        _check(load().ahf_hierarchy_build_info(self._h, C.byref(b)))
+        return {k: int(getattr(b, k)) for k, _ in BuildInfo._fields_ if k != "struct_size"}
 
     def timings(self):
         a = (C.c_double * 4)()

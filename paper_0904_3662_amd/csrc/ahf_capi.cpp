@@ -1,4 +1,5 @@
 // ahf_capi.cpp -- the extern "C" boundary: contexts, memory, validation, views.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -365,6 +366,107 @@ void ahf_ctx_destroy(ahf_ctx* ctx) {
   delete ctx;
 }
 
+}  // extern "C"
+
+namespace ahf {
+
+static int size_class(uint64_t n) { return (int)std::floor(2.0 * std::log2((double)n)); }
+
+static bool same_params(const Ctx::PlanRec& r, const Params& prm, bool has_mass, int bucket) {
+  return r.g == prm.g && r.Lmax == prm.Lmax && r.conn == prm.conn && r.bucket == bucket &&
+         r.dom_ref == prm.dom_ref && r.ref_ref == prm.ref_ref && r.flags == prm.flags &&
+         r.has_mass == has_mass;
+}
+
+// capacities for a build of n particles from a learned plan: the per-particle
+// counts seen, with a margin (15% and 64)
+static bool plan_for(Ctx* c, const Params& prm, bool has_mass, uint64_t n, Plan* out) {
+  const int bucket = size_class(n);
+  for (auto& r : c->plans)
+    if (same_params(r, prm, has_mass, bucket)) {
+      r.last_use = ++c->plan_clock;
+      out->depth = r.depth;
+      for (int L = 0; L < kMaxLevels; ++L) {
+        out->capF[L] = L <= r.depth ? (uint64_t)std::ceil(r.rF[L] * (double)n * 1.15) + 64 : 0;
+        out->capD[L] = L <= r.depth ? (uint64_t)std::ceil(r.rD[L] * (double)n * 1.15) + 64 : 0;
+      }
+      return true;
+    }
+  return false;
+}
+
+// learns from a finished build (the largest counts per particle win)
+static void plan_record(Ctx* c, const Params& prm, bool has_mass, uint64_t n, const Hier* h) {
+  if (n == 0 || h->lev.empty()) return;
+  const int bucket = size_class(n);
+  Ctx::PlanRec* r = nullptr;
+  for (auto& x : c->plans)
+    if (same_params(x, prm, has_mass, bucket)) r = &x;
+  if (!r) {
+    if (c->plans.size() >= 32) {  // forget the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < c->plans.size(); ++i)
+        if (c->plans[i].last_use < c->plans[lru].last_use) lru = i;
+      c->plans.erase(c->plans.begin() + (long)lru);
+    }
+    c->plans.push_back(Ctx::PlanRec{prm.g, prm.Lmax, prm.conn, bucket, prm.dom_ref, prm.ref_ref,
+                                    prm.flags, has_mass, 0, {}, {}, 0});
+    r = &c->plans.back();
+  }
+  r->last_use = ++c->plan_clock;
+  const int depth = (int)h->lev.size() - 1;
+  r->depth = std::max(r->depth, depth);
+  for (int L = 0; L <= depth; ++L) {
+    const double f = (double)h->lev[L].nF / (double)n;
+    const double d = L + 1 <= depth ? (double)h->lev[L + 1].nB / (double)n : 0.0;
+    r->rF[L] = std::max(r->rF[L], f);
+    r->rD[L] = std::max(r->rD[L], d);
+  }
+}
+
+// one attempt at a build (planned when plan is given): the hierarchy is
+// complete, labels included, when this returns
+static void build_once(ahf_ctx* ctx, const ahf_particles* particles, const Params& prm,
+                       hipStream_t st, ahf_hierarchy* h, const Plan* plan) {
+  HIP_CHECK(hipSetDevice(ctx->c.device));
+  h->h.ctx = &ctx->c;
+  h->h.mem.ctx = &ctx->c;
+  h->h.mem.st = st;
+  // the arena's first block from the last hierarchy of this context, in
+  // steps of 2 MB so that builds of similar sizes reuse cached blocks
+  h->h.mem.first_hint = (size_t)(ctx->c.hier_bpp * 1.05 * (double)particles->n);
+  h->h.mem.first_hint = (h->h.mem.first_hint + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
+  ctx->ws.bind(&ctx->c, st);
+  ctx->ws.reset();
+  ctx->ws_dep.bind(&ctx->c, st);
+  ctx->ws_dep.reset();
+  // with equal masses the labels need nothing from the build's totals: they
+  // are enqueued behind it, and one wait at the end covers both (a planned
+  // build first reads its level sizes back, then labels)
+  const bool labels = !(prm.flags & AHF_NO_LABELS);
+  const bool defer = labels && particles->mass == nullptr && !plan;
+  build_hierarchy(&ctx->c, ctx->ws, ctx->ws_dep, *particles, prm, st, &h->h, !defer, plan);
+  if (labels) label_hierarchy(&ctx->c, ctx->ws, &h->h, st);
+  if (defer) finish_build(&ctx->c, &h->h);
+  ctx->ws.reset();
+  ctx->ws_dep.reset();
+}
+
+// every stream of the context idle, the hierarchy's memory returned, the
+// workspaces reset (after a failed attempt)
+static void abandon(ahf_ctx* ctx, ahf_hierarchy* h, hipStream_t st) {
+  if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
+  if (ctx->c.lab_st) (void)hipStreamSynchronize(ctx->c.lab_st);
+  (void)hipStreamSynchronize(st);
+  h->h.mem.release_all();
+  ctx->ws.reset();
+  ctx->ws_dep.reset();
+}
+
+}  // namespace ahf
+
+extern "C" {
+
 ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, const ahf_params* params,
                                void* stream, ahf_hierarchy** out) {
   if (!out) return fail(AHF_EINVAL, "out is NULL");
@@ -373,51 +475,55 @@ ahf_status ahf_build_hierarchy(ahf_ctx* ctx, const ahf_particles* particles, con
   Params prm;
   ahf_status s = check_request(params, particles, &prm);
   if (s != AHF_OK) return s;
-  ahf_hierarchy* h = new (std::nothrow) ahf_hierarchy();
-  if (!h) return fail(AHF_ENOMEM, "host allocation failed");
   hipStream_t st = (hipStream_t)stream;
-  try {
-    HIP_CHECK(hipSetDevice(ctx->c.device));
-    h->h.ctx = &ctx->c;
-    h->h.mem.ctx = &ctx->c;
-    h->h.mem.st = st;
-    // the arena's first block from the last hierarchy of this context, in
-    // steps of 2 MB so that builds of similar sizes reuse cached blocks
-    h->h.mem.first_hint = (size_t)(ctx->c.hier_bpp * 1.05 * (double)particles->n);
-    h->h.mem.first_hint = (h->h.mem.first_hint + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
-    ctx->ws.bind(&ctx->c, st);
-    ctx->ws.reset();
-    ctx->ws_dep.bind(&ctx->c, st);
-    ctx->ws_dep.reset();
-    // with equal masses the labels need nothing from the build's totals: they
-    // are enqueued behind it, and one wait at the end covers both
-    const bool labels = !(prm.flags & AHF_NO_LABELS);
-    const bool defer = labels && particles->mass == nullptr;
-    build_hierarchy(&ctx->c, ctx->ws, ctx->ws_dep, *particles, prm, st, &h->h, !defer);
-    if (labels) label_hierarchy(&ctx->c, ctx->ws, &h->h, st);
-    if (defer) finish_build(&ctx->c, &h->h);
-    ctx->ws.reset();
-    ctx->ws_dep.reset();
-    if (particles->n > 0) ctx->c.hier_bpp = (double)h->h.mem.bytes() / (double)particles->n;
-  } catch (const Error& e) {
-    // every stream idle before any scratch is reused or freed
-    if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
-    if (ctx->c.lab_st) (void)hipStreamSynchronize(ctx->c.lab_st);
-    (void)hipStreamSynchronize(st);
-    h->h.mem.release_all();
-    delete h;
-    ctx->ws.reset();
-    ctx->ws_dep.reset();
-    return fail(e.code, e.msg);
-  } catch (const std::bad_alloc&) {
-    if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
-    if (ctx->c.lab_st) (void)hipStreamSynchronize(ctx->c.lab_st);
-    (void)hipStreamSynchronize(st);
-    h->h.mem.release_all();
-    delete h;
-    return fail(AHF_ENOMEM, "host allocation failed");
+  const bool has_mass = particles->mass != nullptr;
+  Plan plan;
+  bool use_plan = ctx->c.planning && particles->n > 0 && !(prm.flags & AHF_DENSITY_CRITERION) &&
+                  plan_for(&ctx->c, prm, has_mass, particles->n, &plan);
+  bool replanned = false;
+  for (;;) {
+    ahf_hierarchy* h = new (std::nothrow) ahf_hierarchy();
+    if (!h) return fail(AHF_ENOMEM, "host allocation failed");
+    try {
+      build_once(ctx, particles, prm, st, h, use_plan ? &plan : nullptr);
+    } catch (const Error& e) {
+      abandon(ctx, h, st);
+      delete h;
+      if (e.code == kStatusReplan && use_plan) {
+        // the plan was too small for this snapshot: the synced build sizes
+        // every level exactly and teaches the plan
+        use_plan = false;
+        replanned = true;
+        continue;
+      }
+      return fail(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+      abandon(ctx, h, st);
+      delete h;
+      return fail(AHF_ENOMEM, "host allocation failed");
+    }
+    h->h.replanned = replanned;
+    if (particles->n > 0) ctx->c.hier_bpp = (double)h->h.mem.handed / (double)particles->n;
+    if (!(prm.flags & AHF_DENSITY_CRITERION)) plan_record(&ctx->c, prm, has_mass, particles->n, &h->h);
+    *out = h;
+    return AHF_OK;
   }
-  *out = h;
+}
+
+ahf_status ahf_ctx_set_planning(ahf_ctx* ctx, int enable) {
+  if (!ctx) return fail(AHF_EINVAL, "ctx is NULL");
+  ctx->c.planning = enable != 0;
+  if (!enable) ctx->c.plans.clear();
+  return AHF_OK;
+}
+
+ahf_status ahf_hierarchy_build_info(const ahf_hierarchy* h, ahf_build_info* out) {
+  if (!h || !out) return fail(AHF_EINVAL, "bad arguments");
+  out->struct_size = sizeof(ahf_build_info);
+  out->planned = h->h.planned ? 1u : 0u;
+  out->replanned = h->h.replanned ? 1u : 0u;
+  out->host_waits = h->h.host_waits;
+  out->device_bytes = h->h.mem.bytes();
   return AHF_OK;
 }
 
@@ -570,6 +676,39 @@ ahf_status ahf_ctx_set_profiling(ahf_ctx* ctx, int enable) {
   } catch (const Error& e) {
     return fail(e.code, e.msg);
   }
+  return AHF_OK;
+}
+
+ahf_status ahf_ctx_set_tuning(ahf_ctx* ctx, uint32_t n_entries, const uint64_t* min_n,
+                              const ahf_tuning* entries) {
+  if (!ctx || (n_entries && (!min_n || !entries))) return fail(AHF_EINVAL, "bad arguments");
+  std::vector<std::pair<uint64_t, Tuning>> tab;
+  for (uint32_t i = 0; i < n_entries; ++i) {
+    const ahf_tuning& e = entries[i];
+    if (e.struct_size < sizeof(ahf_tuning)) return fail(AHF_EINVAL, "bad ahf_tuning");
+    const uint32_t hv[3] = {e.heavy_level0, e.heavy_level1, e.heavy_deeper};
+    Tuning t;
+    for (int k = 0; k < 3; ++k) {
+      if (hv[k] < 1 || hv[k] > (uint32_t)kHeavyMax)
+        return fail(AHF_EINVAL, "heavy thresholds must be in 1..64");
+      t.heavy[k] = hv[k];
+    }
+    if (e.batch_level1 != 2 && e.batch_level1 != 4) return fail(AHF_EINVAL, "batch_level1 must be 2 or 4");
+    t.batch1 = e.batch_level1;
+    tab.emplace_back(min_n[i], t);
+  }
+  ctx->c.tuning = tab;
+  return AHF_OK;
+}
+
+ahf_status ahf_ctx_get_tuning(const ahf_ctx* ctx, uint64_t n, ahf_tuning* out) {
+  if (!ctx || !out) return fail(AHF_EINVAL, "bad arguments");
+  const Tuning t = ctx->c.tuning_for(n);
+  out->struct_size = sizeof(ahf_tuning);
+  out->heavy_level0 = t.heavy[0];
+  out->heavy_level1 = t.heavy[1];
+  out->heavy_deeper = t.heavy[2];
+  out->batch_level1 = t.batch1;
   return AHF_OK;
 }
 

@@ -7,13 +7,31 @@ namespace ahf {
 
 constexpr int kQBits = 21;          // bits per axis of the quantized positions
 constexpr int kMaxLevels = 22;      // levels 0..21
-constexpr int kHeavy = 64;          // cells with more particles take the chunked path
+constexpr int kHeavy = 64;          // default: cells with more particles take the chunked path
+constexpr int kHeavyMax = 64;       // largest light cell a thread may sum on its own
 constexpr int kChunk = 1024;        // particles per chunk of a heavy cell (64 lanes x 16)
 
 // device error flags (bit mask in a uint32 the host reads after the build)
 constexpr uint32_t kErrCoord = 1u;     // a coordinate >= 2^21
 constexpr uint32_t kErrLookup = 2u;    // a cell that must exist was not found
 constexpr uint32_t kErrInternal = 4u;
+constexpr uint32_t kErrCapacity = 8u;  // a planned level outgrew its capacity
+
+// The number of elements a kernel works on: the host's bound `cap`, and,
+// when the true count is only known on the device (a build whose levels are
+// sized without waiting for the host), the count at p times mult, clamped
+// to cap.  Without p the count is cap itself.
+struct Cnt {
+  const uint32_t* p;
+  uint32_t mult;
+  uint64_t cap;
+};
+__host__ __device__ inline Cnt host_cnt(uint64_t n) { return Cnt{nullptr, 1u, n}; }
+__device__ inline uint64_t cnt_of(const Cnt& c) {
+  if (!c.p) return c.cap;
+  const uint64_t v = (uint64_t)(*c.p) * c.mult;
+  return v < c.cap ? v : c.cap;
+}
 
 // 21-bit value -> every third bit of a 63-bit word (Morton spreading)
 __host__ __device__ inline uint64_t spread3(uint32_t v) {

@@ -65,6 +65,14 @@ struct Prof {
   void clear();
 };
 
+// Per-build tuning: the particle count above which a cell of level 0, of
+// level 1 and of the deeper levels is summed by whole waves (chunks) instead
+// of by one thread, and the records one thread has in flight on level 1.
+struct Tuning {
+  uint32_t heavy[3] = {64, 64, 64};
+  uint32_t batch1 = 2;
+};
+
 struct Ctx {
   int device = 0;
   ahf_alloc_fn alloc = nullptr;
@@ -97,6 +105,36 @@ struct Ctx {
   // device bytes per particle of the last hierarchy built on this context:
   // sizes the first block of the next hierarchy's arena
   double hier_bpp = 0.0;
+  // plans of builds sized ahead, learned from finished builds: per parameter
+  // set and size class (half octaves of n), the depth and, per level, the
+  // refined cells and next-level bricks per particle (largest seen)
+  struct PlanRec {
+    int g, Lmax, conn, bucket;
+    double dom_ref, ref_ref;
+    uint32_t flags;
+    bool has_mass;
+    int depth;
+    double rF[kMaxLevels], rD[kMaxLevels];
+    uint64_t last_use;
+  };
+  std::vector<PlanRec> plans;
+  uint64_t plan_clock = 0;
+  bool planning = true;
+  // tuning by size: the entry with the largest min_n <= n applies to a build
+  // of n particles (defaults when none does)
+  std::vector<std::pair<uint64_t, Tuning>> tuning;
+  Tuning tuning_for(uint64_t n) const {
+    Tuning t;
+    uint64_t best = 0;
+    bool found = false;
+    for (auto& e : tuning)
+      if (e.first <= n && (!found || e.first >= best)) {
+        best = e.first;
+        t = e.second;
+        found = true;
+      }
+    return t;
+  }
 };
 
 
@@ -163,14 +201,16 @@ class Ws {
 // Device memory of one hierarchy: an arena of a few large blocks from the
 // context's allocator, each array a 256-byte aligned piece of one of them
 // (so a build makes a handful of allocator calls, not one per array).  The
-// first block is sized from the previous hierarchy of the context (bytes per
-// particle); a block that is full is followed by one of at least a quarter of
+// first block is sized from the bytes the previous hierarchy of the context
+// used per particle (not its blocks, so the size does not creep from build to
+// build); a block that is full is followed by one of at least a quarter of
 // everything so far.  Everything goes back at once.
 struct Owned {
   Ctx* ctx = nullptr;
   hipStream_t st = nullptr;
   std::vector<std::pair<void*, size_t>> list;  // blocks
   size_t used = 0, room = 0;                   // of the last block
+  size_t handed = 0;                           // bytes handed out in all
   size_t first_hint = 0;                       // bytes for the first block
   template <class T>
   T* get(uint64_t n) {
@@ -193,12 +233,13 @@ struct Owned {
     }
     char* p = static_cast<char*>(list.back().first) + used;
     used += b;
+    handed += b;
     return p;
   }
   void release_all() {
     for (auto& a : list) ctx_free(ctx, a.first, a.second, st);
     list.clear();
-    used = room = 0;
+    used = room = handed = 0;
   }
   size_t bytes() const {
     size_t t = 0;
@@ -213,6 +254,9 @@ struct Owned {
 // (either may be null; an unflagged i keeps its value or becomes all ones);
 // *count (device) = number of flagged elements.
 void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uint32_t* rank,
+                   uint32_t* count, hipStream_t st);
+// the same with a count known on the device only (laid out for nc.cap)
+void compact_flags(Ws& ws, const uint8_t* flags, Cnt nc, uint32_t* list, uint32_t* rank,
                    uint32_t* count, hipStream_t st);
 // Stable LSD sort of particles by Morton key (key_bits bits), ties by index,
 // in 8-bit digits.  The first q passes move (key, index) pairs; from pass q on
@@ -236,6 +280,7 @@ void sum_to_f64(Ws& ws, const T* a, uint64_t n, double* out, hipStream_t st);
 struct Level {
   uint32_t b = 0;
   uint64_t nS = 0, nF = 0, nB = 0, nP = 0, nPatch = 0;
+  uint64_t capF = 0;            // room for the refined cells (= nF once known)
   uint64_t* Skey = nullptr;     // [nS], null on level 0 (identity)
   uint32_t* Sstart = nullptr;   // [nS] (+1 sentinel on level 0)
   uint32_t* Scount = nullptr;   // [nS]
@@ -282,9 +327,26 @@ struct Hier {
   int32_t *s_host = nullptr, *s_level = nullptr, *s_patch = nullptr, *s_depth = nullptr;
   uint32_t* cls_base = nullptr;  // [kMaxLevels + 1] structures starting up to each level
   std::vector<Level> lev;
+  bool planned = false;  // levels sized ahead (no host wait per level)
+  bool sizes_known = true;  // the host knows every level's counts (after finish_build)
+  const uint32_t* dev_lvcnt = nullptr;  // a planned build's level counts on the device
+                                        // (2 per level: refined cells, next-level bricks)
+  bool replanned = false;  // a planned attempt outgrew its capacities and was redone
+  uint32_t host_waits = 0;  // times the host waited for the device during the build
   double ms[4] = {0, 0, 0, 0};
   double t_start = 0.0;  // host clock at the start of the build
 };
+
+// Capacities of a build whose levels are all enqueued without waiting for the
+// host: levels 0..depth, and per level the room for its refined cells (capF)
+// and for the bricks of the next level (capD).
+struct Plan {
+  int depth = 0;
+  uint64_t capF[kMaxLevels] = {};
+  uint64_t capD[kMaxLevels] = {};
+};
+// internal status: a planned build outgrew its capacities and is redone
+constexpr ahf_status kStatusReplan = -100;
 
 // Enqueues the build on st.  With finish, waits for it and completes h
 // (totals, timings, device error flags); without, the caller must call
@@ -293,7 +355,7 @@ struct Hier {
 // its scratch from wsd (kept until the build ends; the deposits are joined
 // back into st before the build's last kernels).
 void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Params& prm,
-                     hipStream_t st, Hier* h, bool finish = true);
+                     hipStream_t st, Hier* h, bool finish = true, const Plan* plan = nullptr);
 void finish_build(Ctx* ctx, Hier* h);
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
 // labels the refined cells of levels lab_done .. k1-1 on ctx->lab_st once st

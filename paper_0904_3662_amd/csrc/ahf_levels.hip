@@ -65,9 +65,10 @@ __global__ void k_fill_i32(int32_t* a, uint64_t n, int32_t v) {
 // slot -> F index of the refined cell in it (-1 for other cells and ghost
 // slots); the cell in slot i of brick i/8 is Bcell[i/8] + i%8 (level 0: i);
 // also clears the dilation marks when given
-__global__ void k_slots(uint64_t nslot, const int32_t* __restrict__ Bcell,
+__global__ void k_slots(Cnt nslot_c, const int32_t* __restrict__ Bcell,
                         const uint8_t* __restrict__ flag, const uint32_t* __restrict__ rankF,
                         int32_t* __restrict__ slot_f, uint8_t* __restrict__ mark) {
+  const uint64_t nslot = cnt_of(nslot_c);
   GRID_STRIDE(i, nslot) {
     int64_t s = (int64_t)i;
     if (Bcell) {
@@ -176,13 +177,14 @@ __device__ inline uint32_t lower_bound_key(const uint64_t* __restrict__ a, uint3
 
 // level L >= 1: the 8 children of every refined cell of level L-1 and their
 // particle ranges (binary searches inside the parent's range)
-__global__ void k_child_ranges(const uint64_t* __restrict__ skey, uint64_t nS,
+__global__ void k_child_ranges(const uint64_t* __restrict__ skey, Cnt nS_c,
                                const uint32_t* __restrict__ pFs,
                                const uint32_t* __restrict__ pSstart,
                                const uint32_t* __restrict__ pScount,
                                const uint64_t* __restrict__ pSkey, int sh,
                                uint64_t* __restrict__ Skey, uint32_t* __restrict__ Sstart,
                                uint32_t* __restrict__ Scount) {
+  const uint64_t nS = cnt_of(nS_c);
   GRID_STRIDE(s, nS) {
     const uint32_t ps = pFs[s >> 3];
     const uint32_t d = (uint32_t)(s & 7);
@@ -251,7 +253,8 @@ __device__ inline uint32_t wave_excl_scan_u32(uint32_t v) {
   return x - v;
 }
 
-// Refinement flags and the heavy-cell list.  Each block takes one contiguous
+// Refinement flags and the heavy-cell list (cells of more than `heavy`
+// particles, summed by whole waves instead of one thread).  Each block takes one contiguous
 // run of cells: a first pass counts its heavy cells and their chunks, one
 // atomic per counter reserves the block's indices, a second pass writes them.
 // On level 0 (count_out set) the counts come from the dense cell starts and
@@ -265,13 +268,14 @@ constexpr int kFlagT = 512;
 constexpr unsigned kFlagBlocks = 512;
 
 __global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ count,
-                                                  const uint32_t* __restrict__ start, uint64_t nS,
-                                                  double thr, int can_refine,
+                                                  const uint32_t* __restrict__ start, Cnt nS_c,
+                                                  double thr, int can_refine, uint32_t heavy,
                                                   uint8_t* __restrict__ flag, HeavyList hl,
                                                   uint32_t* __restrict__ rank_unset,
                                                   uint32_t* __restrict__ count_out) {
   __shared__ uint32_t wh[kFlagT / 64], wc[kFlagT / 64];
   __shared__ uint32_t base_h, base_c;
+  const uint64_t nS = cnt_of(nS_c);
   const int w = threadIdx.x >> 6;
   const int lane = (int)__lane_id();
   const uint64_t per = ((nS + gridDim.x - 1) / gridDim.x + kFlagT - 1) / kFlagT * kFlagT;
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ c
       flag[s] = (uint8_t)f;
       // the compaction fills in the rank of the refined cells
       if (rank_unset && !f) rank_unset[s] = 0xffffffffu;
-      if (c > (uint32_t)kHeavy) {
+      if (c > heavy) {
         my_h += 1;
         my_c += (c + kChunk - 1) / kChunk;
       }
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(kFlagT) void k_flags(const uint32_t* __restrict__ c
   if (my_h == 0) return;
   for (uint64_t s = lo + threadIdx.x; s < hi; s += kFlagT) {
     const uint32_t c = count_out ? start[s + 1] - start[s] : count[s];
-    if (c <= (uint32_t)kHeavy) continue;
+    if (c <= heavy) continue;
     const uint32_t m = (c + kChunk - 1) / kChunk;
     const uint32_t a = start[s];
     hl.Hs[h] = (uint32_t)s;
@@ -566,8 +570,8 @@ constexpr int kTileMaxG = 8;  // largest domain grid (bits per axis) tiled: halo
 constexpr int kTileG = 10;    // cells per axis with the halo
 constexpr int kTileH = kTileG * kTileG * kTileG;
 constexpr int kTileBatch0 = 4;  // records in flight per cell: level 0 (about 6 particles per cell)
-constexpr int kTileBatch1 = 2;  // level 1 (about one; two keep the kernel at 8 waves per SIMD)
 constexpr int kPatchBatch = 4;  // deeper levels
+// level 1 (about one particle per cell): 2 or 4 records in flight, a tuning choice
 constexpr int kWaveG = 6;     // a wave's 4x4x4 cells per axis with their halo
 constexpr int kWaveH = kWaveG * kWaveG * kWaveG;
 
@@ -593,14 +597,14 @@ __device__ inline uint32_t tile_local_parent(uint32_t x, uint32_t y, uint32_t z)
 // are loaded in batches (kTileBatch0 on level 0, whose cells hold several
 // particles each, kTileBatch1 on level 1), all of a batch before its first
 // record is used.
-template <bool DENSE0>
+template <bool DENSE0, int K1>
 __global__ __launch_bounds__(kTileT) void k_tile_deposit(
     const uint32_t* __restrict__ prank,
     const uint32_t* __restrict__ Sstart, const uint32_t* __restrict__ Scount,
     const int32_t* __restrict__ hidx, const float* __restrict__ hT,
-    const double* __restrict__ hM, Parts P, uint32_t mask, float scale,
+    const double* __restrict__ hM, Parts P, uint32_t mask, float scale, uint32_t heavy,
     const int32_t* __restrict__ pslot_child, float* __restrict__ mass,
-    float* __restrict__ halo, double* __restrict__ Spmass) {
+    float* __restrict__ halo, double* __restrict__ Spmass, uint64_t nfp) {
   __shared__ float Wg[kTileT / 64][kWaveH];  // each wave's cells and their one-cell halo
   __shared__ int32_t sbr[64];  // brick of each parent's children (loaded with the first loads)
   const int t = threadIdx.x;
@@ -617,15 +621,17 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
   float T[27];
 #pragma unroll
   for (int k = 0; k < 27; ++k) T[k] = 0.0f;
+  // (a rank at or past nfp, which only a build that overflowed its plan can
+  // hold, counts as unrefined)
   const uint32_t r = DENSE0 ? 0u : prank[pg];
   bool has = false;  // the cell holds particles (an empty cell adds only zeros)
-  if (DENSE0 || r != 0xffffffffu) {
+  if (DENSE0 || (uint64_t)r < nfp) {
     const uint64_t s = DENSE0 ? pg * 8 + d : (uint64_t)r * 8 + d;
     const uint32_t n = Scount[s];
     const uint32_t a0 = Sstart[s];
     has = n > 0;
     double ms = 0.0;
-    if (n > (uint32_t)kHeavy) {
+    if (n > heavy) {
       const int32_t h = hidx[s];
 #pragma unroll
       for (int k = 0; k < 27; ++k) T[k] = hT[(uint64_t)h * 27 + k];
@@ -633,37 +639,54 @@ __global__ __launch_bounds__(kTileT) void k_tile_deposit(
     } else if (DENSE0) {
       add_range<kTileBatch0>(P, a0, n, mask, scale, T, ms);
     } else {
-      add_range<kTileBatch1>(P, a0, n, mask, scale, T, ms);  // about one particle per cell
+      add_range<K1>(P, a0, n, mask, scale, T, ms);  // about one particle per cell
     }
     if (Spmass) Spmass[s] = ms;
   }
   // 27 phases, one per neighbour offset in a fixed order: within a phase the
   // wave's cells add to distinct cells of its grid, so no two writes collide
   // and every grid cell sums its contributions in the same order on every run
+  // (LDS float atomics instead of the read-add-write took twice as long).  A
+  // wave without particles adds nothing.
   const int w0 = ((int)(cx & 3u) * kWaveG + (int)(cy & 3u)) * kWaveG + (int)(cz & 3u);
-  wave_lds_sync();
+  if (__ballot(has) != 0ull) {
+    wave_lds_sync();
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
+      for (int b = 0; b < 3; ++b)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (has) wg[w0 + (a * kWaveG + b) * kWaveG + c] += T[a * 9 + b * 3 + c];
-        wave_lds_sync();
-      }
+        for (int c = 0; c < 3; ++c) {
+          if (has) wg[w0 + (a * kWaveG + b) * kWaveG + c] += T[a * 9 + b * 3 + c];
+          wave_lds_sync();
+        }
+  }
   __syncthreads();
   for (int q = t; q < kTileH; q += kTileT) {
     const int gx = q / 100, gy = (q / 10) % 10, gz = q % 10;
     const int dx = gx - 1, dy = gy - 1, dz = gz - 1;
     // the wave grids covering this tile grid cell, in wave order (wave w
-    // holds the cells 4 (w>>2 & 1, w>>1 & 1, w & 1) + [0, 4) per axis)
+    // holds the cells 4 (w>>2 & 1, w>>1 & 1, w & 1) + [0, 4) per axis, so
+    // per axis the low wave covers g < 6 and the high one g >= 4); the 8
+    // reads are issued together from addresses clamped into the grid, and
+    // only the covering ones are added
+    const bool cov[2][3] = {{gx < kWaveG, gy < kWaveG, gz < kWaveG},
+                            {gx >= 4, gy >= 4, gz >= 4}};
+    const int ox[2] = {gx * kWaveG * kWaveG, (gx - 4) * kWaveG * kWaveG};
+    const int oy[2] = {gy * kWaveG, (gy - 4) * kWaveG};
+    const int oz[2] = {gz, gz - 4};
+    float v[8];
+#pragma unroll
+    for (int w = 0; w < kTileT / 64; ++w) {
+      const int i = (w >> 2) & 1, j = (w >> 1) & 1, k = w & 1;
+      const bool c = cov[i][0] && cov[j][1] && cov[k][2];
+      v[w] = Wg[w][c ? ox[i] + oy[j] + oz[k] : 0];
+    }
     float sum = 0.0f;
 #pragma unroll
     for (int w = 0; w < kTileT / 64; ++w) {
-      const int ex = gx - 4 * ((w >> 2) & 1), ey = gy - 4 * ((w >> 1) & 1), ez = gz - 4 * (w & 1);
-      if ((unsigned)ex < (unsigned)kWaveG && (unsigned)ey < (unsigned)kWaveG &&
-          (unsigned)ez < (unsigned)kWaveG)
-        sum += Wg[w][(ex * kWaveG + ey) * kWaveG + ez];
+      const int i = (w >> 2) & 1, j = (w >> 1) & 1, k = w & 1;
+      if (cov[i][0] && cov[j][1] && cov[k][2]) sum += v[w];
     }
     // cells off the tile's faces are final; face cells and the halo go to
     // the buffer, where k_tile_halo_add adds the neighbours' share
@@ -726,17 +749,18 @@ __constant__ PatchLayout c_patch = make_patch_layout();
 // one thread per cell of S_L (8 per refined parent); 32 parents per block.
 // patch[f][px][py][pz] (4x4x4) holds what the particles of parent f give to
 // the level-L cells 2P-1 .. 2P+2 per axis.
-__global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* __restrict__ Sstart,
+__global__ __launch_bounds__(256) void k_patches(Cnt nFp_c, const uint32_t* __restrict__ Sstart,
                                                  const uint32_t* __restrict__ Scount,
                                                  const int32_t* __restrict__ hidx,
                                                  const float* __restrict__ hT,
                                                  const double* __restrict__ hM, Parts P,
-                                                 uint32_t mask, float scale,
+                                                 uint32_t mask, float scale, uint32_t heavy,
                                                  float* __restrict__ patch,
                                                  double* __restrict__ Spmass) {
   __shared__ float Ts[256][27];  // odd stride: the 64 lanes hit distinct banks
   __shared__ uint8_t inv[64];    // lane-dependent lookups: LDS, not the scalar cache
   const int t = threadIdx.x;
+  const uint64_t nFp = cnt_of(nFp_c);
   if (t < 64) inv[t] = c_patch.inv[t];
   const uint64_t f = (uint64_t)xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun) * 32 + (t >> 3);
   const int d = t & 7;
@@ -747,7 +771,7 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
     const uint64_t s = f * 8 + d;
     const uint32_t n = Scount[s];
     double ms = 0.0;
-    if (n > (uint32_t)kHeavy) {
+    if (n > heavy) {
       const int32_t h = hidx[s];
 #pragma unroll
       for (int k = 0; k < 27; ++k) T[k] = hT[(uint64_t)h * 27 + k];
@@ -786,13 +810,16 @@ __global__ __launch_bounds__(256) void k_patches(uint64_t nFp, const uint32_t* _
 // the refined parents among the 27 neighbours of the brick's parent through
 // LDS; each lane then sums, for its cell, the (at most 8) patches covering it
 // in a fixed order (own parent first)
-__global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint64_t* __restrict__ Bkey,
+// (nfp: the parents that have a patch; an F index at or past it, which only
+// a build that overflowed its plan can hold, counts as no patch)
+__global__ __launch_bounds__(256) void k_combine(int L, Cnt nB_c, const uint64_t* __restrict__ Bkey,
                                                  int pbits, Tree tree,
                                                  const int32_t* __restrict__ pslot_f,
                                                  const float* __restrict__ patch,
-                                                 float* __restrict__ mass) {
+                                                 float* __restrict__ mass, uint64_t nfp) {
   __shared__ int32_t fn[32][28];
   __shared__ uint8_t lay[64];
+  const uint64_t nB = cnt_of(nB_c);
   if (threadIdx.x < 64) lay[threadIdx.x] = c_patch.layout[threadIdx.x];
   const int lb = threadIdx.x >> 3;
   const int d = threadIdx.x & 7;
@@ -821,7 +848,11 @@ __global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint6
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int o = d + 8 * j;
-      if (o < 27) fn[lb][o] = slot[j] < 0 ? -1 : (L == 0 ? (int32_t)slot[j] : pslot_f[slot[j]]);
+      if (o < 27) {
+        int32_t f = slot[j] < 0 ? -1 : (L == 0 ? (int32_t)slot[j] : pslot_f[slot[j]]);
+        if (f >= 0 && (uint64_t)f >= nfp) f = -1;
+        fn[lb][o] = f;
+      }
     }
   }
   __syncthreads();
@@ -844,11 +875,12 @@ __global__ __launch_bounds__(256) void k_combine(int L, uint64_t nB, const uint6
 // FP64 sums of a level: the field, the particle mass per cell, the counts
 // FP64 sums of the brick masses, the per-cell particle masses and the cell
 // counts: partial sums per block, then one block adds them in block order
-__global__ __launch_bounds__(256) void k_level_sums(const float* __restrict__ a, uint64_t na,
-                                                    const double* __restrict__ b, uint64_t nb,
-                                                    const uint32_t* __restrict__ c, uint64_t nc,
+__global__ __launch_bounds__(256) void k_level_sums(const float* __restrict__ a, Cnt na_c,
+                                                    const double* __restrict__ b, Cnt nb_c,
+                                                    const uint32_t* __restrict__ c, Cnt nc_c,
                                                     double* __restrict__ part) {
   __shared__ double lds[3][4];
+  const uint64_t na = cnt_of(na_c), nb = cnt_of(nb_c), nc = cnt_of(nc_c);
   double s[3] = {0.0, 0.0, 0.0};
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -949,28 +981,47 @@ __global__ void k_mark(int L, int bits, const uint32_t* __restrict__ nFdev,
 // next level's bricks (one per marked slot, in key order by rank); a refined
 // cell's slot is always marked, so its F entry is finished here too: its
 // children's brick, and F_L moved to its final buffer.
-__global__ void k_build_bricks(uint64_t nslot, const uint8_t* __restrict__ mark,
+// (capD, capF: the room of the next level's bricks and of F_L; a build
+// whose levels are sized ahead writes nothing beyond them and is redone)
+__global__ void k_build_bricks(Cnt nslot_c, const uint8_t* __restrict__ mark,
                                const uint32_t* __restrict__ rank,
                                const uint64_t* __restrict__ Bkey,
                                const int32_t* __restrict__ slot_f,
                                int32_t* __restrict__ slot_child, uint64_t* __restrict__ nBkey,
                                int32_t* __restrict__ nBcell, const uint32_t* __restrict__ Ftmp,
-                               uint32_t* __restrict__ Fs, int32_t* __restrict__ nPbrick) {
+                               uint32_t* __restrict__ Fs, int32_t* __restrict__ nPbrick,
+                               uint64_t capD, uint64_t capF, const uint32_t* __restrict__ nFraw) {
+  const uint64_t nslot = cnt_of(nslot_c);
   GRID_STRIDE(i, nslot) {
-    if (mark[i]) {
-      const uint32_t r = rank[i];
-      slot_child[i] = (int32_t)r;
+    const uint32_t r = mark[i] ? rank[i] : 0xffffffffu;
+    const bool has_brick = r < capD;
+    const int32_t f = slot_f[i];
+    const bool in_F = f >= 0 && (uint64_t)f < capF;
+    if (in_F) nPbrick[f] = has_brick ? (int32_t)r : -1;
+    slot_child[i] = has_brick ? (int32_t)r : -1;
+    if (has_brick) {
       nBkey[r] = Bkey ? ((Bkey[i >> 3] << 3) | (i & 7)) : i;
-      const int32_t f = slot_f[i];
-      nBcell[r] = f >= 0 ? f * 8 : -1;
-      if (f >= 0) {
-        Fs[f] = Ftmp[f];
-        nPbrick[f] = (int32_t)r;
-      }
-    } else {
-      slot_child[i] = -1;
+      nBcell[r] = in_F ? f * 8 : -1;
     }
   }
+  // F_L to its final buffer, every entry below the (clamped) count: a build
+  // that overflowed its plan may hold refined cells without a slot, and its
+  // later kernels still read every entry below that count
+  const uint64_t nF = *nFraw < capF ? *nFraw : capF;
+  GRID_STRIDE(f, nF) Fs[f] = Ftmp[f];
+}
+
+// the end of a level sized ahead: its refined cells and next-level bricks
+// (raw[0], raw[1]) against their room; the counts the next levels read
+// (cnt[0], cnt[1]) clamped to it, and an error flag when they did not fit,
+// or when the last planned level still refines cells
+__global__ void k_level_check(const uint32_t* __restrict__ raw, uint64_t capF, uint64_t capD,
+                              int last, uint32_t* __restrict__ cnt, uint32_t* __restrict__ err) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const uint32_t nF = raw[0], nD = raw[1];
+  if ((uint64_t)nF > capF || (uint64_t)nD > capD || (last && nF > 0)) atomicOr(err, kErrCapacity);
+  cnt[0] = (uint64_t)nF < capF ? nF : (uint32_t)capF;
+  cnt[1] = (uint64_t)nD < capD ? nD : (uint32_t)capD;
 }
 
 
@@ -1063,10 +1114,13 @@ __device__ inline void lds_unite(int32_t* lp, int32_t a, int32_t b) {
 }
 
 // F indices of the 13 half-neighbourhood neighbours selected by `sel` (bit
-// o = offset c_half26[o]); -1 where unselected or not refined
+// o = offset c_half26[o]); -1 where unselected or not refined.  nF: the
+// level's refined cells in the pass; an index at or past it (which only a
+// build that overflowed its plan can hold) counts as not refined.
 __device__ inline void refined_neighbours(int Lp, int bits, const Tree& tree,
                                           const int32_t* __restrict__ slot_f, uint64_t key,
-                                          uint32_t sel, int32_t (&g)[13], uint32_t* err) {
+                                          uint32_t sel, int32_t (&g)[13], uint32_t* err,
+                                          uint64_t nF) {
   uint64_t nk[13];
   int64_t slot[13];
 #pragma unroll
@@ -1079,8 +1133,12 @@ __device__ inline void refined_neighbours(int Lp, int bits, const Tree& tree,
   for (int o = 0; o < 13; ++o) {
     g[o] = -1;
     if ((sel >> o) & 1u) {
-      if (slot[o] < 0) atomicOr(err, kErrLookup);
-      else g[o] = slot_f[slot[o]];
+      if (slot[o] < 0) {
+        atomicOr(err, kErrLookup);
+      } else {
+        const int32_t f = slot_f[slot[o]];
+        g[o] = (f >= 0 && (uint64_t)f < nF) ? f : -1;
+      }
     }
   }
 }
@@ -1107,10 +1165,32 @@ struct LabLev {
 };
 struct LabSet {
   uint32_t nlev;              // entries 0 .. nlev-1
+  uint32_t total;             // off[nlev], for kernels that take a 32-bit count
   uint64_t off[kMaxLevels];   // first element of each entry; off[nlev] = total
   uint64_t toff[kMaxLevels];  // first tile (kUfTile elements) of each entry
+  // first slot of each entry's patches in the per-patch arrays; pbase[nlev]
+  // = slots in all (equal to off when the level sizes are known on the host;
+  // laid out by the levels' capacities when they are known on the device only)
+  uint64_t pbase[kMaxLevels];
   LabLev lv[kMaxLevels - 1];
 };
+
+// the element offsets of a set whose level sizes are on the device: entry j
+// holds the refined cells of level k0 + j, counted at nF[2 (k0 + j)]
+__global__ void k_labset_counts(LabSet* __restrict__ S, const uint32_t* __restrict__ nF, int k0) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t tot = 0, nt = 0;
+  for (uint32_t j = 0; j < S->nlev; ++j) {
+    const uint64_t c = nF[2 * (k0 + (int)j)];
+    S->off[j] = tot;
+    S->toff[j] = nt;
+    tot += c;
+    nt += (c + kUfTile - 1) / kUfTile;
+  }
+  S->off[S->nlev] = tot;
+  S->toff[S->nlev] = nt;
+  S->total = (uint32_t)tot;
+}
 
 __device__ inline int lab_entry(const LabSet& S, uint64_t e) {
   int k = 0;
@@ -1138,6 +1218,7 @@ __global__ __launch_bounds__(256) void k_uf_local(const LabSet* __restrict__ pS,
   __shared__ int32_t lp[kUfTile];
   const LabSet& S = *pS;
   const uint32_t tile = xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun);
+  if (tile >= S.toff[S.nlev]) return;  // past the true count (grid laid out for a bound)
   const int k = lab_tile_entry(S, tile);
   const LabLev& lv = S.lv[k];
   const uint64_t o = S.off[k];
@@ -1153,7 +1234,8 @@ __global__ __launch_bounds__(256) void k_uf_local(const LabSet* __restrict__ pS,
     const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
     uint32_t xm = 0;
     int32_t gs[13];
-    refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, cm, gs, err);
+    refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, cm, gs, err,
+                       S.off[k + 1] - o);
 #pragma unroll
     for (int q = 0; q < 13; ++q) {
       if (gs[q] < 0) continue;
@@ -1183,6 +1265,7 @@ __global__ __launch_bounds__(256) void k_uf_cross(const LabSet* __restrict__ pS,
   __shared__ unsigned long long set[kPairSlots];
   const LabSet& S = *pS;
   const uint32_t tile = xcd_tile_runs(blockIdx.x, gridDim.x, kXcdRun);
+  if (tile >= S.toff[S.nlev]) return;  // past the true count (grid laid out for a bound)
   const int k = lab_tile_entry(S, tile);
   const LabLev& lv = S.lv[k];
   const uint64_t o = S.off[k];
@@ -1198,7 +1281,8 @@ __global__ __launch_bounds__(256) void k_uf_cross(const LabSet* __restrict__ pS,
       const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
       const int32_t ra = par[f];  // tile-local root (written by k_uf_local)
       int32_t gs[13];
-      refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, xm, gs, err);
+      refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, xm, gs, err,
+                         S.off[k + 1] - o);
 #pragma unroll
       for (int q = 0; q < 13; ++q) {
         if (gs[q] < 0) continue;
@@ -1230,10 +1314,11 @@ __global__ __launch_bounds__(256) void k_uf_cross(const LabSet* __restrict__ pS,
 // roots go to a separate array: par itself may still receive path-halving
 // stores from other threads, so it is never read back as the answer
 // final roots; also clears the per-patch accumulators (nz >= n entries)
-__global__ void k_uf_compress(int32_t* par, uint64_t n, int32_t* __restrict__ root,
+__global__ void k_uf_compress(int32_t* par, Cnt n_c, int32_t* __restrict__ root,
                               uint8_t* __restrict__ pred, uint64_t nz, uint32_t* __restrict__ z32,
                               unsigned long long* __restrict__ z64a,
                               unsigned long long* __restrict__ z64b) {
+  const uint64_t n = cnt_of(n_c);
   GRID_STRIDE(i, nz) {
     z32[i] = 0u;
     z64a[i] = 0ull;
@@ -1260,7 +1345,7 @@ __global__ void k_uf_label(const LabSet* __restrict__ pS, const int32_t* __restr
     const uint64_t o = S.off[k];
     const uint32_t r0 = rank[o];
     const int32_t l = (int32_t)(rank[root[i]] - r0);
-    lab[i] = (int32_t)(o + (uint64_t)l);
+    lab[i] = (int32_t)(S.pbase[k] + (uint64_t)l);
     int4* out = reinterpret_cast<int4*>(S.lv[k].Spatch + 8 * (i - o));
     out[0] = make_int4(l, l, l, l);
     out[1] = make_int4(l, l, l, l);
@@ -1426,9 +1511,10 @@ __global__ __launch_bounds__(kLabSmallT) void k_label_small(
   __shared__ uint32_t wsum[kLabSmallT / 64];
   const LabSet& S = *pS;
   const uint32_t n = (uint32_t)S.off[S.nlev];
+  const uint32_t nslot = (uint32_t)S.pbase[S.nlev];  // >= n
   const uint32_t cm = conn_mask(conn);
   const uint32_t t = threadIdx.x;
-  for (uint32_t e = t; e < n; e += kLabSmallT) {
+  for (uint32_t e = t; e < nslot; e += kLabSmallT) {
     lp[e] = (int32_t)e;
     sc[e] = 0u;
     sp[e] = 0ull;
@@ -1441,7 +1527,8 @@ __global__ __launch_bounds__(kLabSmallT) void k_label_small(
       const uint32_t s = lv.Fs[e - o];
       const uint64_t key = lv.Skey ? lv.Skey[s] : (uint64_t)s;
       int32_t gs[13];
-      refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, cm, gs, err);
+      refined_neighbours((int)lv.level, (int)lv.bits, tree, lv.slot_f, key, cm, gs, err,
+                         o1 - o);
 #pragma unroll
       for (int q = 0; q < 13; ++q) {
         if (gs[q] < 0) continue;
@@ -1482,7 +1569,7 @@ __global__ __launch_bounds__(kLabSmallT) void k_label_small(
     for (uint32_t e = o + t; e < o1; e += kLabSmallT) {
       const int32_t r = lds_find(lp, (int32_t)e);
       const int32_t l = (int32_t)(rk[r] - r0);
-      const uint32_t slot = o + (uint32_t)l;
+      const uint32_t slot = (uint32_t)S.pbase[k] + (uint32_t)l;
       int4* out = reinterpret_cast<int4*>(lv.Spatch + 8 * (uint64_t)(e - o));
       out[0] = make_int4(l, l, l, l);
       out[1] = make_int4(l, l, l, l);
@@ -1506,7 +1593,7 @@ __global__ __launch_bounds__(kLabSmallT) void k_label_small(
     }
   }
   __syncthreads();
-  for (uint32_t e = t; e < n; e += kLabSmallT) {
+  for (uint32_t e = t; e < nslot; e += kLabSmallT) {
     ncells[e] = sc[e];
     npart[e] = sp[e];
     pm[e] = (double)sp[e] * mscalar;
@@ -1547,7 +1634,7 @@ static Tree make_tree(const Hier* h) {
 }
 
 void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Params& prm,
-                     hipStream_t st, Hier* h, bool finish) {
+                     hipStream_t st, Hier* h, bool finish, const Plan* plan) {
   const double t0 = now_ms();
   h->prm = prm;
   h->n = p.n;
@@ -1568,15 +1655,26 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   }
   HIP_CHECK(hipEventRecord(ctx->phase_ev[0], st));
   // [0] error flags, [1..7] per-level counters, [8 + 2L], [9 + 2L] heavy
-  // cells and chunks of level L
-  // (one zeroed block: the totals, the counters, the sort's digit histograms)
-  constexpr int kDevU32 = 8 + 2 * kMaxLevels;
+  // cells and chunks of level L; then, for a planned build, per level the
+  // raw and the clamped counts of refined cells and next-level bricks
+  // (one zeroed block: the totals, the counters, the sort's digit histograms;
+  // cleared by a kernel, not a memset, so that a build can be recorded into
+  // a graph)
+  constexpr int kDevU32 = 8 + 2 * kMaxLevels + 4 * kMaxLevels;
   constexpr size_t kZeroWords = 3 * kMaxLevels + (kDevU32 + 1) / 2 + (kRsMaxPass * 256) / 2;
   uint64_t* zero = ws.get<uint64_t>(kZeroWords);
-  HIP_CHECK(hipMemsetAsync(zero, 0, kZeroWords * sizeof(uint64_t), st));
+  k_fill_i32<<<grid_for(2 * kZeroWords), kT, 0, st>>>(reinterpret_cast<int32_t*>(zero),
+                                                       2 * kZeroWords, 0);
+  HIP_LAUNCH_CHECK();
   double* dev_tot = reinterpret_cast<double*>(zero);
   uint32_t* dev_u32 = reinterpret_cast<uint32_t*>(zero + 3 * kMaxLevels);
+  uint32_t* lvraw = dev_u32 + 8 + 2 * kMaxLevels;
+  uint32_t* lvcnt = lvraw + 2 * kMaxLevels;
   uint32_t* ghist0 = reinterpret_cast<uint32_t*>(zero + 3 * kMaxLevels + (kDevU32 + 1) / 2);
+  h->planned = plan != nullptr;
+  h->sizes_known = plan == nullptr;
+  h->dev_lvcnt = plan ? lvcnt : nullptr;
+  h->host_waits = 0;
   uint32_t* err = dev_u32;
   ctx->dev_err = err;
 
@@ -1625,8 +1723,17 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   }
   hipStream_t ds = overlap ? ctx->dep_st : st;
   Ws& wd = overlap ? wsd : ws;  // deposit scratch: kept to the end of the build when overlapped
-  uint64_t nFp = 1ull << (3 * (g - 1));  // parents of level 0: the virtual level -1
-  uint64_t nB = nFp;
+  // Sizes of the level being built.  Synced (no plan): the host reads each
+  // level's refined cells and next-level bricks once their kernels are done
+  // (one wait per level) and sizes the next level exactly.  Planned: every
+  // level is enqueued at once, sized by the plan's capacities; the kernels
+  // read the true counts on the device (Cnt), clamped to the capacities, and
+  // k_level_check flags a level that did not fit (the build is then redone
+  // synced).
+  const bool planned = plan != nullptr;
+  const uint64_t nFp0 = 1ull << (3 * (g - 1));  // parents of level 0: the virtual level -1
+  Cnt cFp = host_cnt(nFp0);                     // parents of the level (F_{L-1})
+  Cnt cB = host_cnt(nFp0);                      // bricks of the level
   uint64_t* Bkey = nullptr;
   int32_t* Bcell = nullptr;
   int32_t* Pbrick = nullptr;
@@ -1637,9 +1744,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   SumBlocks sum_blocks;
   // equal masses: the labels need only the cells, so those of the first
   // levels start, on a third stream, as soon as the levels get small (the
-  // last levels leave most of the GPU idle)
+  // last levels leave most of the GPU idle); a planned build labels after it
   const bool early_labels = overlap && !(prm.flags & AHF_NO_LABELS) && !h->has_mass;
-  for (int L = 0; L <= prm.Lmax; ++L) {
+  const Tuning tune = ctx->tuning_for(n);
+  const int last_level = planned ? plan->depth : prm.Lmax;
+  for (int L = 0; L <= last_level; ++L) {
     h->lev.emplace_back();
     Level& lv = h->lev.back();
     const int b = g + L;
@@ -1647,8 +1756,13 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     const int sh = 3 * (B - b);
     if (L == 0 && g >= 2 && g <= kTileMaxG) rank0 = ws.get<uint32_t>(1ull << (3 * g));
     Ws::Mark lvl_mark = ws.mark();
+    // the level's cells: all 8 children of every parent (level 0: dense)
+    const Cnt cS = L == 0 ? host_cnt(ncell0) : Cnt{cFp.p, 8u, 8 * cFp.cap};
+    const Cnt cSlot{cB.p, 8u, 8 * cB.cap};  // brick cells (slots) of the level
+    uint32_t* rawF = planned ? lvraw + 2 * L : dev_u32 + 1;   // refined cells (raw count)
+    uint32_t* rawD = planned ? lvraw + 2 * L + 1 : dev_u32 + 4;  // next-level bricks
+    lv.nS = cS.cap;
     if (L == 0) {
-      lv.nS = ncell0;
       lv.Sstart = start0;
       lv.Scount = h->mem.get<uint32_t>(lv.nS);
       if (n == 0)  // no gather: every cell starts (and ends) at 0
@@ -1656,16 +1770,15 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
                                                        lv.nS + 1, 0);
     } else {
       const Level& pv = h->lev[L - 1];
-      lv.nS = 8 * pv.nF;
       lv.Skey = h->mem.get<uint64_t>(lv.nS);
       lv.Sstart = h->mem.get<uint32_t>(lv.nS);
       lv.Scount = h->mem.get<uint32_t>(lv.nS);
       AHF_TIMED(ctx, "child_ranges", st,
-                (k_child_ranges<<<grid_for(lv.nS), kT, 0, st>>>(skey, lv.nS, pv.Fs, pv.Sstart,
+                (k_child_ranges<<<grid_for(lv.nS), kT, 0, st>>>(skey, cS, pv.Fs, pv.Sstart,
                                                                 pv.Scount, pv.Skey, sh, lv.Skey,
                                                                 lv.Sstart, lv.Scount)));
     }
-    lv.nB = nB;
+    lv.nB = cB.cap;
     lv.Bkey = Bkey;
     lv.Bcell = Bcell;
     lv.Pbrick = Pbrick;
@@ -1676,15 +1789,18 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     // refinement flags and the cells too full for one thread
     const int can_refine = (L < prm.Lmax && b < kQBits) ? 1 : 0;
     const double thr = (L == 0) ? prm.dom_ref : prm.ref_ref;
-    // heavy-cell lists, sized by bounds: at most n/65 cells above 64
-    // particles, at most that many plus n/4096 chunks
-    const uint64_t maxH = std::min<uint64_t>(lv.nS, n / (kHeavy + 1) + 1);
+    // heavy-cell lists, sized by bounds: cells above `heavy` particles (the
+    // same threshold for the flag kernel's lists and the level's deposit) are
+    // summed by waves; at most n/(heavy+1) of them, at most that many plus
+    // n/kChunk chunks
+    const uint32_t heavy = tune.heavy[L < 2 ? L : 2];
+    const uint64_t maxH = std::min<uint64_t>(lv.nS, n / (heavy + 1) + 1);
     const uint64_t maxch = maxH + n / kChunk + 1;
     HeavyList hl;
     hl.nheavy = dev_u32 + 8 + 2 * L;   // the level's own counters, zero from the start
     hl.nchunks = dev_u32 + 9 + 2 * L;
     hl.Hs = wd.get<uint32_t>(maxH);
-    hl.hidx = wd.get<int32_t>(lv.nS);  // read only for cells above kHeavy
+    hl.hidx = wd.get<int32_t>(lv.nS);  // read only for heavy cells
     hl.nch = wd.get<uint32_t>(maxH);
     hl.chofs = wd.get<uint32_t>(maxH);
     hl.ch_a = wd.get<uint32_t>(maxch);
@@ -1693,7 +1809,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     // with the count criterion the flags come here; with the density
     // criterion they need the level's deposit and come after it
     k_flags<<<std::min(grid_for(lv.nS, kFlagT), kFlagBlocks), kFlagT, 0, st>>>(
-        L == 0 ? nullptr : lv.Scount, lv.Sstart, lv.nS, thr, density ? 0 : can_refine, lv.Sflag,
+        L == 0 ? nullptr : lv.Scount, lv.Sstart, cS, thr, density ? 0 : can_refine, heavy,
+        lv.Sflag,
         hl, (L == 0 && !density) ? rank0 : nullptr, L == 0 ? lv.Scount : nullptr);
     HIP_LAUNCH_CHECK();
     if (overlap) {
@@ -1703,11 +1820,11 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     }
     uint32_t* Ftmp = ws.get<uint32_t>(lv.nS);
     uint32_t* rankF = (L == 0 && rank0) ? rank0 : ws.get<uint32_t>(lv.nS);
-    const uint64_t nslot = 8 * nB;
+    const uint64_t nslot = cSlot.cap;
     uint8_t* mark = nullptr;
     uint32_t* rank = nullptr;
     auto flag_phase = [&]() {
-    compact_flags(ws, lv.Sflag, lv.nS, Ftmp, rankF, dev_u32 + 1, st);
+    compact_flags(ws, lv.Sflag, cS, Ftmp, rankF, rawF, st);
 
     // the dilation of F_L: slots of level L that hold a brick on level L+1
     // (sized by the bound nF <= nS, so that one sync per level reads nF, the
@@ -1716,7 +1833,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
       lv.slot_f = h->mem.get<int32_t>(nslot);
       mark = ws.get<uint8_t>(nslot);
       rank = ws.get<uint32_t>(nslot);
-      k_slots<<<grid_for(nslot), kT, 0, st>>>(nslot, L == 0 ? nullptr : lv.Bcell, lv.Sflag, rankF,
+      k_slots<<<grid_for(nslot), kT, 0, st>>>(cSlot, L == 0 ? nullptr : lv.Bcell, lv.Sflag, rankF,
                                               lv.slot_f, L == 0 ? nullptr : mark);
       HIP_LAUNCH_CHECK();
       if (L == 0) {
@@ -1727,14 +1844,21 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
         unsigned mb = grid_for(lv.nS * 27);
         if (mb > 8192) mb = 8192;
         AHF_TIMED(ctx, "mark", st,
-                  (k_mark<<<mb, kT, 0, st>>>(L, b, dev_u32 + 1, Ftmp, lv.Skey, tree, mark, err)));
+                  (k_mark<<<mb, kT, 0, st>>>(L, b, rawF, Ftmp, lv.Skey, tree, mark, err)));
       }
-      compact_flags(ws, mark, nslot, nullptr, rank, dev_u32 + 4, st);
+      compact_flags(ws, mark, cSlot, nullptr, rank, rawD, st);
     }
-    // the counts travel to the host while the level's deposit runs
-    HIP_CHECK(hipMemcpyAsync(ctx->host_cnt, dev_u32 + 1, 4 * sizeof(uint32_t),
-                             hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipEventRecord(ctx->cnt_ev, st));
+    if (planned) {
+      // the counts stay on the device: clamped to the plan, checked
+      k_level_check<<<1, 64, 0, st>>>(rawF, plan->capF[L], plan->capD[L], L == last_level ? 1 : 0,
+                                      lvcnt + 2 * L, err);
+      HIP_LAUNCH_CHECK();
+    } else {
+      // the counts travel to the host while the level's deposit runs
+      HIP_CHECK(hipMemcpyAsync(ctx->host_cnt, dev_u32 + 1, 4 * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipEventRecord(ctx->cnt_ev, st));
+    }
     };
     if (!density) flag_phase();
 
@@ -1758,10 +1882,10 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
 
     // TSC deposit: by dense tiles where the parents form a well-filled grid,
     // else parent patches, then brick cells
-    lv.mass = h->mem.get<float>(8 * nB);
+    lv.mass = h->mem.get<float>(8 * cB.cap);
     const bool tiles0 = L == 0 && g - 1 >= 2 && g <= kTileMaxG;
     const bool tiles1 = L == 1 && g >= 2 && g <= kTileMaxG && rank0 &&
-                        8 * nFp >= (1ull << (3 * g));
+                        8 * cFp.cap >= (1ull << (3 * g));
     if (tiles0 || tiles1) {
       const int pb = tiles0 ? g - 1 : g;  // bits per axis of the parent grid
       const uint64_t ntiles = 1ull << (3 * (pb - 2));
@@ -1769,29 +1893,35 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
       const Level& l0 = h->lev[0];
       if (tiles0)
         AHF_TIMED(ctx, "tile_deposit0", ds,
-                  (k_tile_deposit<true><<<(unsigned)ntiles, kTileT, 0, ds>>>(
-                      nullptr, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, nullptr,
-                      lv.mass, halo, lv.Spmass)));
+                  (k_tile_deposit<true, 2><<<(unsigned)ntiles, kTileT, 0, ds>>>(
+                      nullptr, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, heavy, nullptr,
+                      lv.mass, halo, lv.Spmass, 0)));
+      else if (tune.batch1 >= 4)
+        AHF_TIMED(ctx, "tile_deposit1", ds,
+                  (k_tile_deposit<false, 4><<<(unsigned)ntiles, kTileT, 0, ds>>>(
+                      rank0, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, heavy,
+                      l0.slot_child, lv.mass, halo, lv.Spmass, cFp.cap)));
       else
         AHF_TIMED(ctx, "tile_deposit1", ds,
-                  (k_tile_deposit<false><<<(unsigned)ntiles, kTileT, 0, ds>>>(
-                      rank0, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, l0.slot_child,
-                      lv.mass, halo, lv.Spmass)));
+                  (k_tile_deposit<false, 2><<<(unsigned)ntiles, kTileT, 0, ds>>>(
+                      rank0, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, heavy,
+                      l0.slot_child, lv.mass, halo, lv.Spmass, cFp.cap)));
       AHF_TIMED(ctx, "tile_halo", ds,
                 (k_tile_halo_add<<<(unsigned)ntiles, 256, 0, ds>>>(
                     tiles0 ? 1 : 0, pb - 2, tiles0 ? nullptr : l0.slot_child, halo, lv.mass)));
     } else {
-      float* patch = wd.get<float>(nFp * 64);
-      if (nFp) {
+      float* patch = wd.get<float>(cFp.cap * 64);
+      if (cFp.cap) {
         AHF_TIMED(ctx, "patches", ds,
-                  (k_patches<<<(unsigned)((nFp + 31) / 32), 256, 0, ds>>>(
-                      nFp, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, patch, lv.Spmass)));
+                  (k_patches<<<(unsigned)((cFp.cap + 31) / 32), 256, 0, ds>>>(
+                      cFp, lv.Sstart, lv.Scount, hidx, hT, hM, P, mask, scale, heavy, patch,
+                      lv.Spmass)));
       }
       Tree tree = make_tree(h);
       const int32_t* pslot_f = (L > 0) ? h->lev[L - 1].slot_f : nullptr;
       AHF_TIMED(ctx, "combine", ds,
-                (k_combine<<<(unsigned)((nB + 31) / 32), 256, 0, ds>>>(L, nB, Bkey, b - 1, tree,
-                                                                       pslot_f, patch, lv.mass)));
+                (k_combine<<<(unsigned)((cB.cap + 31) / 32), 256, 0, ds>>>(
+                    L, cB, Bkey, b - 1, tree, pslot_f, patch, lv.mass, cFp.cap)));
     }
     if (density) {
       k_flags_density<<<grid_for(lv.nS), kT, 0, st>>>(lv.nS, lv.mass, lv.Pbrick, p.mass_scalar,
@@ -1801,40 +1931,64 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
       flag_phase();
     }
     {
-      const uint64_t nmax = (8 * nB > lv.nS) ? 8 * nB : lv.nS;
+      const uint64_t nmax = (8 * cB.cap > lv.nS) ? 8 * cB.cap : lv.nS;
       int nblk = (int)((nmax + 255) / 256);
       if (nblk > kSumBlocks) nblk = kSumBlocks;
       if (nblk < 1) nblk = 1;
-      k_level_sums<<<nblk, 256, 0, ds>>>(lv.mass, 8 * nB, lv.Spmass, lv.nS, lv.Scount, lv.nS,
+      k_level_sums<<<nblk, 256, 0, ds>>>(lv.mass, cSlot, lv.Spmass, cS, lv.Scount, cS,
                                          part_all + (uint64_t)L * 3 * kSumBlocks);
       HIP_LAUNCH_CHECK();
       sum_blocks.n[L] = nblk;
     }
 
-    // the host enqueues the early labels while it would otherwise wait
-    if (early_labels && L >= 2 && h->lab_done == 0 && 8 * nFp < kLabEarlyCells)
-      label_early(ctx, wsd, h, (uint32_t)L, st);
-    HIP_CHECK(hipEventSynchronize(ctx->cnt_ev));
-    lv.nF = ctx->host_cnt[0];
-    const uint32_t nD = can_refine ? ctx->host_cnt[3] : 0u;
-    lv.Fs = h->mem.get<uint32_t>(lv.nF);  // filled from Ftmp by k_build_bricks below
-    if (lv.nF == 0) lv.slot_f = nullptr;  // no refined cell: nothing to look up
-    if (lv.nF == 0) {
+    uint64_t capF, capD;
+    if (planned) {
+      capF = plan->capF[L];
+      capD = can_refine ? plan->capD[L] : 0;
+      lv.capF = capF;
+      // the early labels, once the levels get small (by their capacities)
+      if (early_labels && L >= 2 && h->lab_done == 0 && 8 * cFp.cap < kLabEarlyCells)
+        label_early(ctx, wsd, h, (uint32_t)L, st);
+      if (L == last_level) {
+        ws.release(lvl_mark);
+        break;
+      }
+    } else {
+      // the host enqueues the early labels while it would otherwise wait
+      if (early_labels && L >= 2 && h->lab_done == 0 && 8 * cFp.cap < kLabEarlyCells)
+        label_early(ctx, wsd, h, (uint32_t)L, st);
+      HIP_CHECK(hipEventSynchronize(ctx->cnt_ev));
+      h->host_waits += 1;
+      capF = ctx->host_cnt[0];
+      capD = can_refine ? ctx->host_cnt[3] : 0u;
+      lv.nF = capF;
+    }
+    lv.capF = capF;
+    lv.Fs = h->mem.get<uint32_t>(capF);  // filled from Ftmp by k_build_bricks below
+    if (!planned && lv.nF == 0) {
+      lv.slot_f = nullptr;  // no refined cell: nothing to look up
       ws.release(lvl_mark);
       break;
     }
 
     // bricks of level L+1: children of every level-L cell within one cell of F_L
     lv.slot_child = h->mem.get<int32_t>(nslot);
-    uint64_t* nBkey = h->mem.get<uint64_t>(nD);
-    int32_t* nBcell = h->mem.get<int32_t>(nD);
-    int32_t* nPbrick = h->mem.get<int32_t>(lv.nF);
-    k_build_bricks<<<grid_for(nslot), kT, 0, st>>>(nslot, mark, rank, lv.Bkey, lv.slot_f,
-                                                   lv.slot_child, nBkey, nBcell, Ftmp, lv.Fs,
-                                                   nPbrick);
-    HIP_LAUNCH_CHECK();
-    nFp = lv.nF;
-    nB = nD;
+    uint64_t* nBkey = h->mem.get<uint64_t>(capD);
+    int32_t* nBcell = h->mem.get<int32_t>(capD);
+    int32_t* nPbrick = h->mem.get<int32_t>(capF);
+    if (can_refine) {
+      k_build_bricks<<<grid_for(std::max<uint64_t>(nslot, capF)), kT, 0, st>>>(
+          cSlot, mark, rank, lv.Bkey, lv.slot_f, lv.slot_child, nBkey, nBcell, Ftmp, lv.Fs,
+          nPbrick, capD, capF, rawF);
+      HIP_LAUNCH_CHECK();
+    } else {
+      // the level cap: no brick of a next level (a planned build only gets
+      // here with no refined cell, which the check kernel has verified)
+      k_fill_i32<<<grid_for(nslot), kT, 0, st>>>(lv.slot_child, nslot, -1);
+      HIP_LAUNCH_CHECK();
+    }
+    cFp = planned ? Cnt{lvcnt + 2 * L, 1u, capF} : host_cnt(capF);
+    cB = planned ? Cnt{lvcnt + 2 * L + 1, 1u, capD} : host_cnt(capD);
     Bkey = nBkey;
     Bcell = nBcell;
     Pbrick = nPbrick;
@@ -1857,10 +2011,13 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   // totals and the device error flags, into pinned memory; read by
   // finish_build once the stream has passed this point
   HIP_CHECK(hipEventRecord(ctx->phase_ev[2], st));
-  // (the error flags follow the totals in the zeroed block: one copy)
+  // (the error flags and the counters follow the totals in the zeroed
+  // block: one copy)
   static_assert(sizeof(double) * 3 * kMaxLevels % 8 == 0, "flags right after the totals");
+  static_assert(256 + sizeof(double) * 3 * kMaxLevels + sizeof(uint32_t) * kDevU32 <= 4096,
+                "the pinned count area holds the copy");
   HIP_CHECK(hipMemcpyAsync(ctx->host_tot, dev_tot,
-                           3 * kMaxLevels * sizeof(double) + sizeof(uint32_t),
+                           3 * kMaxLevels * sizeof(double) + kDevU32 * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, st));
   h->t_start = t0;
   if (finish) {
@@ -1873,6 +2030,29 @@ void finish_build(Ctx* ctx, Hier* h) {
   const double* tot = ctx->host_tot;
   uint32_t herr = 0;
   std::memcpy(&herr, ctx->host_tot + 3 * kMaxLevels, sizeof(uint32_t));
+  if (h->planned) {
+    // a level that outgrew its room: everything after it is clamped, so the
+    // build is redone with a wait per level
+    if (herr & kErrCapacity) throw Error{kStatusReplan, "a planned level outgrew its capacity"};
+    // the true sizes from the device counts; levels past the last one that
+    // has cells are dropped
+    const uint32_t* u = reinterpret_cast<const uint32_t*>(ctx->host_tot + 3 * kMaxLevels);
+    const uint32_t* cnt = u + 8 + 4 * kMaxLevels;
+    size_t keep = h->lev.size();
+    for (size_t L = 0; L < h->lev.size(); ++L) {
+      Level& lv = h->lev[L];
+      if (L > 0) {
+        lv.nS = 8ull * cnt[2 * (L - 1)];
+        lv.nB = cnt[2 * (L - 1) + 1];
+        if (lv.nS == 0 && keep == h->lev.size()) keep = L;
+      }
+      lv.nF = cnt[2 * L];
+    }
+    h->lev.resize(keep);
+    if (!h->lev.empty() && h->lev.back().nF == 0) h->lev.back().slot_f = nullptr;
+    h->sizes_known = true;
+    h->dev_lvcnt = nullptr;
+  }
   for (size_t L = 0; L < h->lev.size(); ++L) {
     h->lev[L].tot_cell = tot[3 * L + 0];
     h->lev[L].nP = (uint64_t)tot[3 * L + 2];
@@ -1976,19 +2156,27 @@ static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, in
   }
   // entry j = the refined cells of level k0 + j, parents of the cells of
   // level k0 + j + 1
+  // With the level sizes on the device only (a planned build labelling
+  // during the build), the arrays and grids are laid out by the levels'
+  // capacities and the element offsets come from the device counts.
+  const bool dev_sizes = !h->sizes_known;
   LabSet& S = lab_sets(ctx)[slot];
   S = LabSet{};
   S.nlev = k1 > k0 ? k1 - k0 : 0u;
   uint64_t tot = 0, ntiles = 0;
   for (uint32_t j = 0; j < S.nlev; ++j) {
     const Level& pv = h->lev[k0 + j];
+    const uint64_t c = dev_sizes ? pv.capF : pv.nF;
     S.off[j] = tot;
     S.toff[j] = ntiles;
-    tot += pv.nF;
-    ntiles += (pv.nF + kUfTile - 1) / kUfTile;
+    S.pbase[j] = tot;
+    tot += c;
+    ntiles += (c + kUfTile - 1) / kUfTile;
   }
   S.off[S.nlev] = tot;
   S.toff[S.nlev] = ntiles;
+  S.pbase[S.nlev] = tot;
+  S.total = (uint32_t)tot;
   if (tot >= (1ull << 31)) throw Error{AHF_ELIMIT, "too many refined cells to label"};
   const uint64_t tot1 = tot ? tot : 1;
   int32_t* Spatch = h->mem.get<int32_t>(8 * tot1);
@@ -2000,11 +2188,11 @@ static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, in
     const uint32_t k = k0 + j;
     const Level& pv = h->lev[k];
     Level& lv = h->lev[k + 1];
-    lv.Spatch = Spatch + 8 * S.off[j];
-    lv.patch_parent = pparent + S.off[j];
-    lv.patch_ncells = pncells + S.off[j];
-    lv.patch_npart = pnpart + S.off[j];
-    lv.patch_mass = pmass + S.off[j];
+    lv.Spatch = Spatch + 8 * S.pbase[j];
+    lv.patch_parent = pparent + S.pbase[j];
+    lv.patch_ncells = pncells + S.pbase[j];
+    lv.patch_npart = pnpart + S.pbase[j];
+    lv.patch_mass = pmass + S.pbase[j];
     S.lv[j] = LabLev{pv.Fs, pv.Skey, pv.slot_f, pv.Scount, pv.Spmass, lv.Spatch,
                      k > 0 ? pv.Spatch : nullptr, k, pv.b};
   }
@@ -2014,6 +2202,10 @@ static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, in
     // few elements: the whole pass in one block
     LabSet* dS = ws.get<LabSet>(1);
     HIP_CHECK(hipMemcpyAsync(dS, &S, sizeof(LabSet), hipMemcpyHostToDevice, st));
+    if (dev_sizes) {
+      k_labset_counts<<<1, 64, 0, st>>>(dS, h->dev_lvcnt, (int)k0);
+      HIP_LAUNCH_CHECK();
+    }
     k_label_small<<<1, kLabSmallT, 0, st>>>(dS, tree, h->prm.conn, pncells,
                                             reinterpret_cast<unsigned long long*>(pnpart),
                                             pparent, pmass, h->mass_scalar, dev + 4, dev);
@@ -2030,14 +2222,19 @@ static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, in
   unsigned long long* mfix = h->has_mass ? ws.get<unsigned long long>(tot) : nullptr;
   LabSet* dS = ws.get<LabSet>(1);
   HIP_CHECK(hipMemcpyAsync(dS, &S, sizeof(LabSet), hipMemcpyHostToDevice, st));
+  if (dev_sizes) {
+    k_labset_counts<<<1, 64, 0, st>>>(dS, h->dev_lvcnt, (int)k0);
+    HIP_LAUNCH_CHECK();
+  }
+  const Cnt ctot{dev_sizes ? &dS->total : nullptr, 1u, tot};
   AHF_TIMED(ctx, "uf_hook", st,
             (k_uf_local<<<(unsigned)ntiles, 256, 0, st>>>(dS, tree, h->prm.conn, par, xmask, dev)));
   AHF_TIMED(ctx, "uf_cross", st,
             (k_uf_cross<<<(unsigned)ntiles, 256, 0, st>>>(dS, tree, xmask, par, dev)));
-  k_uf_compress<<<grid_for(tot), kT, 0, st>>>(par, tot, root, pred, tot, pncells,
+  k_uf_compress<<<grid_for(tot), kT, 0, st>>>(par, ctot, root, pred, tot, pncells,
                                               (unsigned long long*)pnpart, mfix);
   HIP_LAUNCH_CHECK();
-  compact_flags(ws, pred, tot, nullptr, rank, dev + 1, st);
+  compact_flags(ws, pred, ctot, nullptr, rank, dev + 1, st);
   k_uf_label<<<grid_for(tot), kT, 0, st>>>(dS, root, rank, dev + 1, lab, dev + 4);
   HIP_LAUNCH_CHECK();
   k_patch_stats<<<(unsigned)std::min<uint64_t>(256, (tot + 4095) / 4096 + 1), 256, 0, st>>>(

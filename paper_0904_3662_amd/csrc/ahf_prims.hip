@@ -77,9 +77,10 @@ __device__ inline uint32_t cf_bits(const uint8_t* __restrict__ flags, uint64_t n
   return m;
 }
 
-__global__ __launch_bounds__(kCfT) void k_cf_up(const uint8_t* __restrict__ flags, uint64_t n,
+__global__ __launch_bounds__(kCfT) void k_cf_up(const uint8_t* __restrict__ flags, Cnt nc,
                                                uint32_t* __restrict__ tcnt) {
   __shared__ uint32_t lds[kCfT / 64 + 1];
+  const uint64_t n = cnt_of(nc);
   const uint64_t i0 = (uint64_t)blockIdx.x * kCfTile + (uint64_t)threadIdx.x * kCfPer;
   const uint32_t c = (uint32_t)__popc(cf_bits(flags, n, i0));
   uint32_t tot;
@@ -143,7 +144,7 @@ __device__ inline uint32_t cf_tile(uint32_t m, uint64_t n, uint64_t t0, uint32_t
 
 // tile offset: from the scanned tile counts (tofs), or summed here from the
 // tile counts of the tiles before this one (tcnt, few tiles), or 0 (one tile)
-__global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ flags, uint64_t n,
+__global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ flags, Cnt nc,
                                                  const uint32_t* __restrict__ tcnt,
                                                  const uint32_t* __restrict__ tofs,
                                                  uint32_t* __restrict__ list,
@@ -151,6 +152,7 @@ __global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ fl
                                                  uint32_t* __restrict__ count) {
   __shared__ uint32_t lds[kCfT / 64 + 1];
   __shared__ uint32_t stage[kCfTile];
+  const uint64_t n = cnt_of(nc);
   const uint64_t t0 = (uint64_t)blockIdx.x * kCfTile;
   uint32_t before = 0;
   if (!tofs && tcnt)
@@ -167,12 +169,13 @@ __global__ __launch_bounds__(kCfT) void k_cf_down(const uint8_t* __restrict__ fl
 // loaded first, then the tiles are written in order with a running offset
 constexpr int kCfSmallTiles = 8;
 
-__global__ __launch_bounds__(kCfT) void k_cf_small(const uint8_t* __restrict__ flags, uint64_t n,
+__global__ __launch_bounds__(kCfT) void k_cf_small(const uint8_t* __restrict__ flags, Cnt nc,
                                                   uint32_t* __restrict__ list,
                                                   uint32_t* __restrict__ rank,
                                                   uint32_t* __restrict__ count) {
   __shared__ uint32_t lds[kCfT / 64 + 1];
   __shared__ uint32_t stage[kCfTile];
+  const uint64_t n = cnt_of(nc);
   uint32_t m[kCfSmallTiles];
 #pragma unroll
   for (int t = 0; t < kCfSmallTiles; ++t) {
@@ -189,15 +192,29 @@ __global__ __launch_bounds__(kCfT) void k_cf_small(const uint8_t* __restrict__ f
   if (count && threadIdx.x == 0) *count = carry;
 }
 
+__global__ void k_set_u32(uint32_t* p, uint32_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uint32_t* rank,
                    uint32_t* count, hipStream_t st) {
+  compact_flags(ws, flags, host_cnt(n), list, rank, count, st);
+}
+
+// the number of flags may be known on the device only (nc.p): the tiles are
+// laid out for the bound nc.cap, and tiles past the true count hold no flag
+void compact_flags(Ws& ws, const uint8_t* flags, Cnt nc, uint32_t* list, uint32_t* rank,
+                   uint32_t* count, hipStream_t st) {
+  const uint64_t n = nc.cap;
   const uint64_t ntiles = (n + kCfTile - 1) / kCfTile;
   if (ntiles == 0) {
-    HIP_CHECK(hipMemsetAsync(count, 0, sizeof(uint32_t), st));
+    // a kernel, not a memset: it may be recorded into a graph
+    k_set_u32<<<1, 64, 0, st>>>(count, 0u);
+    HIP_LAUNCH_CHECK();
     return;
   }
   if (ntiles > 1 && ntiles <= (uint64_t)kCfSmallTiles) {
-    k_cf_small<<<1, kCfT, 0, st>>>(flags, n, list, rank, count);
+    k_cf_small<<<1, kCfT, 0, st>>>(flags, nc, list, rank, count);
     HIP_LAUNCH_CHECK();
     return;
   }
@@ -205,7 +222,7 @@ void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uin
   uint32_t* tofs = nullptr;
   if (ntiles > 1) {
     tcnt = ws.get<uint32_t>(ntiles);
-    k_cf_up<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, n, tcnt);
+    k_cf_up<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, nc, tcnt);
     HIP_LAUNCH_CHECK();
     if (ntiles > kCfSumTiles) {
       // many tiles: scan the counts once instead of summing them per tile
@@ -214,7 +231,7 @@ void compact_flags(Ws& ws, const uint8_t* flags, uint64_t n, uint32_t* list, uin
       HIP_LAUNCH_CHECK();
     }
   }
-  k_cf_down<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, n, tcnt, tofs, list, rank, count);
+  k_cf_down<<<(unsigned)ntiles, kCfT, 0, st>>>(flags, nc, tcnt, tofs, list, rank, count);
   HIP_LAUNCH_CHECK();
 }
 

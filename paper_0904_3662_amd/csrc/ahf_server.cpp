@@ -286,7 +286,10 @@ ahf_status ahf_server_create(ahf_ctx* ctx, const ahf_server_desc* desc, ahf_serv
   }
   // several workers: each build on its worker's one stream (measured on 64
   // sub-volumes: 2.8 against 2.0 G particles/s at 4 workers)
-  for (auto& w : s->workers) w.ctx->c.one_stream = s->workers.size() > 1;
+  for (auto& w : s->workers) {
+    w.ctx->c.one_stream = s->workers.size() > 1;
+    w.ctx->c.tuning = ctx->c.tuning;
+  }
   for (auto& w : s->workers) w.th = std::thread(worker_loop, s, &w);
   *out = s;
   return AHF_OK;

@@ -175,3 +175,93 @@ def test_labels_match_oracle_on_repeated_builds(ctx, conn):
         h, _ = ahf.build_snapshot(ctx, p, connectivity=conn, dev=dev)
         compare_hierarchy(h, p.n, levels, order)
         h.free()
+
+
+# every tuning gives the oracle's hierarchy (integers exactly, the field within
+# tolerance): light/heavy thresholds down to a few particles per cell, and both
+# level-1 batch sizes
+TUNINGS = [dict(heavy_level0=4, heavy_level1=2, heavy_deeper=3, batch_level1=4),
+           dict(heavy_level0=16, heavy_level1=8, heavy_deeper=16, batch_level1=2),
+           dict(heavy_level0=64, heavy_level1=64, heavy_deeper=64, batch_level1=4)]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=["t4-2-3-b4", "t16-8-16-b2", "t64-b4"])
+def test_tunings_match_oracle(tuning):
+    from paper_0904_3662_amd import ahf
+    with ahf.Context(0) as c:
+        c.set_tuning([(0, tuning)])
+        assert c.tuning(12345) == tuning
+        run_case(c, synth.small_mixed(0))
+        rng = np.random.Generator(np.random.PCG64(15))
+        core = np.array([0.31, 0.62, 0.18]) + rng.normal(0, 0.01, (20000, 3))
+        p = from_positions(np.concatenate([core, rng.random((20000, 3))]), g=5, thr=5,
+                           max_levels=6)
+        p.name = "clump-on-uniform"
+        run_case(c, p)
+        c.set_tuning([])
+        assert c.tuning(12345)["heavy_level1"] == 64
+
+
+# Builds sized ahead: the second build of a snapshot class is enqueued with no
+# host wait per level and gives the oracle's hierarchy; a plan too small for
+# the next snapshot is detected on the device and that build is redone.
+def test_planned_build_matches_oracle_without_host_waits():
+    from paper_0904_3662_amd import ahf
+    cases = [synth.small_mixed(0),
+             clustered(21, 40000, n_clumps=8, spread=0.01, g=4, thr=5, max_levels=6)]
+    with ahf.Context(0) as c:
+        for p in cases:
+            levels, order = oracle.build(p)
+            dev = ahf.snapshot_to_device(p)
+            h1, _ = ahf.build_snapshot(c, p, dev=dev)
+            i1 = h1.build_info()
+            assert i1["planned"] == 0 and i1["host_waits"] >= 1
+            compare_hierarchy(h1, p.n, levels, order)
+            h1.free()
+            for rep in range(2):
+                h2, _ = ahf.build_snapshot(c, p, dev=dev)
+                i2 = h2.build_info()
+                assert i2["planned"] == 1 and i2["host_waits"] == 0 and i2["replanned"] == 0, i2
+                compare_hierarchy(h2, p.n, levels, order)
+                h2.free()
+
+
+def test_plan_too_small_is_redone():
+    from paper_0904_3662_amd import ahf
+    # same size class and parameters, but the second snapshot refines far more
+    sparse = uniform(31, 30000, g=4, thr=5, max_levels=5)
+    dense = clustered(32, 30000, n_clumps=4, spread=0.004, frac=0.9, g=4, thr=5, max_levels=5)
+    levels, order = oracle.build(dense)
+    with ahf.Context(0) as c:
+        ahf.build_snapshot(c, sparse)[0].free()
+        h, _ = ahf.build_snapshot(c, dense)
+        info = h.build_info()
+        assert info["replanned"] == 1 and info["planned"] == 0, info
+        compare_hierarchy(h, dense.n, levels, order)
+        h.free()
+        # the plan has learned: the next build of the dense snapshot is planned
+        h, _ = ahf.build_snapshot(c, dense)
+        assert h.build_info()["planned"] == 1
+        compare_hierarchy(h, dense.n, levels, order)
+        h.free()
+        # a plan deeper than the snapshot: the extra levels stay empty
+        h, _ = ahf.build_snapshot(c, sparse)
+        info = h.build_info()
+        assert info["planned"] == 1, info
+        sl, so = oracle.build(sparse)
+        compare_hierarchy(h, sparse.n, sl, so)
+        h.free()
+
+
+def test_planned_build_with_masses_and_substructure():
+    from paper_0904_3662_amd import ahf
+    p = clustered(33, 20000, n_clumps=6, spread=0.01, g=4, thr=4, max_levels=5)
+    p.mass = (np.random.Generator(np.random.PCG64(34)).random(p.n) + 0.5).astype(np.float32)
+    levels, order = oracle.build(p)
+    with ahf.Context(0) as c:
+        dev = ahf.snapshot_to_device(p)
+        for rep in range(3):
+            h, _ = ahf.build_snapshot(c, p, dev=dev, substructure=True)
+            assert h.build_info()["planned"] == (1 if rep else 0)
+            compare_hierarchy(h, p.n, levels, order, m_max=float(np.max(p.mass)))
+            h.free()
