@@ -212,8 +212,13 @@ ahf_status ahf_hierarchy_order(const ahf_hierarchy *h, const uint32_t **sorted_i
  * (plus 15% and 64), the kernels read the true counts on the device, and a
  * level that outgrows its room is detected on the device; that build is then
  * redone with one host wait per level, which also updates the plan.  The
- * results are the same either way.  Planning is on by default; disabling it
- * also forgets the plans.  (Not used with AHF_DENSITY_CRITERION.)
+ * results are the same either way.  Planning is off by default: a single
+ * build runs slightly faster with its per-level waits (they are hidden behind
+ * the running deposits, and without them the next levels' cell kernels share
+ * the GPU with the deposits, which are the longer chain).  It is what lets a
+ * build run with no host involvement at all (ahf_batch_create records planned
+ * builds into a graph).  Disabling it also forgets the plans.  (Not used with
+ * AHF_DENSITY_CRITERION.)
  */
 ahf_status ahf_ctx_set_planning(ahf_ctx *ctx, int enable);
 

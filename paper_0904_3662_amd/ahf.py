@@ -304,7 +304,8 @@ class Context:
 
     def set_planning(self, on: bool):
         """Builds sized ahead from what earlier builds of the same class
-        needed (on by default); off also forgets the plans."""
+        needed, with no host wait per level (off by default); off also
+        forgets the plans."""
         _check(load().ahf_ctx_set_planning(self._h, 1 if on else 0))
 
     def tuning(self, n: int) -> dict:
@@ -454,7 +455,8 @@ class Hierarchy:
 
     def __del__(self):
         # at interpreter exit the allocator behind the context may be gone
-        if sys.is_finalizing():
+        # (and this module's globals may already be cleared)
+        if sys is None or sys.is_finalizing():
             return
         try:
             self.free()

@@ -119,7 +119,7 @@ struct Ctx {
   };
   std::vector<PlanRec> plans;
   uint64_t plan_clock = 0;
-  bool planning = true;
+  bool planning = false;
   // tuning by size: the entry with the largest min_n <= n applies to a build
   // of n particles (defaults when none does)
   std::vector<std::pair<uint64_t, Tuning>> tuning;

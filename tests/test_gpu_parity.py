@@ -202,14 +202,16 @@ def test_tunings_match_oracle(tuning):
         assert c.tuning(12345)["heavy_level1"] == 64
 
 
-# Builds sized ahead: the second build of a snapshot class is enqueued with no
-# host wait per level and gives the oracle's hierarchy; a plan too small for
-# the next snapshot is detected on the device and that build is redone.
+# Builds sized ahead (planning switched on): the second build of a snapshot
+# class is enqueued with no host wait per level and gives the oracle's
+# hierarchy; a plan too small for the next snapshot is detected on the device
+# and that build is redone.
 def test_planned_build_matches_oracle_without_host_waits():
     from paper_0904_3662_amd import ahf
     cases = [synth.small_mixed(0),
              clustered(21, 40000, n_clumps=8, spread=0.01, g=4, thr=5, max_levels=6)]
     with ahf.Context(0) as c:
+        c.set_planning(True)
         for p in cases:
             levels, order = oracle.build(p)
             dev = ahf.snapshot_to_device(p)
@@ -233,6 +235,7 @@ def test_plan_too_small_is_redone():
     dense = clustered(32, 30000, n_clumps=4, spread=0.004, frac=0.9, g=4, thr=5, max_levels=5)
     levels, order = oracle.build(dense)
     with ahf.Context(0) as c:
+        c.set_planning(True)
         ahf.build_snapshot(c, sparse)[0].free()
         h, _ = ahf.build_snapshot(c, dense)
         info = h.build_info()
@@ -259,6 +262,7 @@ def test_planned_build_with_masses_and_substructure():
     p.mass = (np.random.Generator(np.random.PCG64(34)).random(p.n) + 0.5).astype(np.float32)
     levels, order = oracle.build(p)
     with ahf.Context(0) as c:
+        c.set_planning(True)
         dev = ahf.snapshot_to_device(p)
         for rep in range(3):
             h, _ = ahf.build_snapshot(c, p, dev=dev, substructure=True)
