@@ -391,6 +391,67 @@ ahf_status ahf_server_get_stats(ahf_server *s, ahf_server_stats *out);
 /* Waits for running builds, frees every result. */
 void ahf_server_destroy(ahf_server *s);
 
+/* ------------------------------------------------------------------ batches
+ *
+ * Many independent sub-volumes built by one graph launch.  The paper analyses
+ * independent chunks of a simulation separately (Sect. 2.2.3, and Sect. 5.3 on
+ * splitting a large volume); a batch builds a fixed set of such sub-volumes
+ * again and again (for instance each time their particles have moved) with
+ * no host involvement inside the run.
+ *
+ * ahf_batch_create builds every sub-volume twice on ctx's device: the first
+ * build learns its level sizes, the second runs exactly as every run will
+ * (sized ahead with no host wait per level, labels within the build, a status
+ * block copied on the device) and sizes the batch's memory.  A run enqueues
+ * every build at once: n_chains independent chains (1..16; each with its own
+ * streams and scratch memory), the sub-volumes dealt to the chains largest
+ * first; the host waits once, at ahf_batch_wait.  On return the batch has not
+ * run yet.
+ *
+ * flags: AHF_BATCH_GRAPH records the builds into one HIP graph, so that a run
+ * is one graph launch.  That recording is switched off in this version
+ * (AHF_EINVAL): the HIP runtime faulted while ending the recording of these
+ * multi-stream builds.
+ *
+ * parts[i] and params[i] describe sub-volume i (n >= 1 sub-volumes, each with
+ * at least one particle, equal masses: mass NULL, and none of the flags
+ * AHF_DENSITY_CRITERION and AHF_SUBSTRUCTURE; AHF_EINVAL otherwise).  The
+ * particle arrays are borrowed for the life of the batch: every run reads them
+ * at the same addresses, so the caller may rewrite their contents (not their
+ * sizes) between runs.  Device memory comes from ctx's allocator; ctx must
+ * outlive the batch.  The call first waits for stream (on which the caller
+ * may have produced the particle arrays); the batch has streams of its own.
+ */
+typedef struct ahf_batch ahf_batch;
+#define AHF_BATCH_GRAPH 1u
+ahf_status ahf_batch_create(ahf_ctx *ctx, uint32_t n, const ahf_particles *parts,
+                            const ahf_params *params, uint32_t n_chains, uint32_t flags,
+                            void *stream, ahf_batch **out);
+
+/* Enqueues one run after the work already on stream: every sub-volume is
+ * rebuilt from the current contents of its particle arrays, and stream waits
+ * for the run.  The hierarchies of the previous run are invalid from here
+ * until ahf_batch_wait. */
+ahf_status ahf_batch_run(ahf_batch *b, void *stream);
+
+/* Waits for the run and completes the hierarchies from the status blocks the
+ * run left on the device.  AHF_OK when every sub-volume built; else the first
+ * failing sub-volume's error: AHF_ELIMIT when its particles now need more
+ * cells or bricks on some level than the recorded sizes allow (create the
+ * batch again), AHF_EINVAL for a coordinate >= 2^21, AHF_EDEVICE for a device
+ * fault.  ahf_batch_status gives each sub-volume's status. */
+ahf_status ahf_batch_wait(ahf_batch *b);
+ahf_status ahf_batch_status(const ahf_batch *b, uint32_t i);
+
+/* The hierarchy of sub-volume i after a successful wait, borrowed from the
+ * batch (valid until the next run or ahf_batch_destroy; never freed by the
+ * caller).  AHF_EINVAL before a run has completed or when sub-volume i failed. */
+ahf_status ahf_batch_hierarchy(ahf_batch *b, uint32_t i, ahf_hierarchy **out);
+
+/* Waits for a pending run and frees the graph, the hierarchies and the
+ * chains' memory. */
+void ahf_batch_destroy(ahf_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

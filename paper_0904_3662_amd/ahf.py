@@ -34,6 +34,8 @@ EXPORTS = [
     "ahf_classify_substructure", "ahf_hierarchy_structures",
     "ahf_hierarchy_query_label_static", "ahf_ctx_set_tuning", "ahf_ctx_get_tuning",
     "ahf_ctx_set_planning", "ahf_hierarchy_build_info",
+    "ahf_batch_create", "ahf_batch_run", "ahf_batch_wait", "ahf_batch_status",
+    "ahf_batch_hierarchy", "ahf_batch_destroy",
 ]
 
 
@@ -181,9 +183,17 @@ def load():
     L.ahf_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
     L.ahf_server_destroy.argtypes = [vp]
     L.ahf_server_destroy.restype = None
+    L.ahf_batch_create.argtypes = [vp, C.c_uint32, C.POINTER(Particles), C.POINTER(Params),
+                                   C.c_uint32, C.c_uint32, vp, C.POINTER(vp)]
+    L.ahf_batch_run.argtypes = [vp, vp]
+    L.ahf_batch_wait.argtypes = [vp]
+    L.ahf_batch_status.argtypes = [vp, C.c_uint32]
+    L.ahf_batch_hierarchy.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
+    L.ahf_batch_destroy.argtypes = [vp]
+    L.ahf_batch_destroy.restype = None
     for name in EXPORTS:
         if name not in ("ahf_ctx_destroy", "ahf_hierarchy_free", "ahf_last_error",
-                        "ahf_server_destroy"):
+                        "ahf_server_destroy", "ahf_batch_destroy"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -575,6 +585,60 @@ class Server:
             load().ahf_server_destroy(self._h)
             self._h = None
             self._inputs.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+AHF_BATCH_GRAPH = 1
+
+
+class Batch:
+    """Sub-volumes rebuilt together, one host wait per run (ahf_batch_*).
+    The particle tensors are held for the life of the batch; a run rebuilds
+    every sub-volume from their current contents."""
+
+    def __init__(self, ctx: Context, snaps, devs=None, n_chains: int = 4, connectivity=26,
+                 labels=True, stream=None, graph: bool = False):
+        devs = devs if devs is not None else [snapshot_to_device(s) for s in snaps]
+        n = len(snaps)
+        parts = (Particles * n)()
+        prms = (Params * n)()
+        for i, (s, d) in enumerate(zip(snaps, devs)):
+            parts[i] = make_particles(*d[:6], d[6])
+            prms[i] = make_params(s.g, s.dom_ref, s.ref_ref, s.max_levels, connectivity,
+                                  _flags(labels, False))
+        h = C.c_void_p()
+        _check(load().ahf_batch_create(ctx.handle, n, parts, prms, int(n_chains),
+                                       AHF_BATCH_GRAPH if graph else 0,
+                                       _stream_handle(stream), C.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._keep = devs
+        self.n = n
+
+    def run(self, stream=None):
+        _check(load().ahf_batch_run(self._h, _stream_handle(stream)))
+
+    def wait(self):
+        _check(load().ahf_batch_wait(self._h))
+
+    def status(self, i: int) -> int:
+        return int(load().ahf_batch_status(self._h, int(i)))
+
+    def hierarchy(self, i: int) -> Hierarchy:
+        h = C.c_void_p()
+        _check(load().ahf_batch_hierarchy(self._h, int(i), C.byref(h)))
+        return Hierarchy(h, borrowed=True)
+
+    def close(self):
+        if self._h:
+            load().ahf_batch_destroy(self._h)
+            self._h = None
+            self._keep = None
 
     def __enter__(self):
         return self

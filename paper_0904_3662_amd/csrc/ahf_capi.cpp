@@ -35,6 +35,8 @@ static void release_free_blocks(Ctx* c);
 
 void* ctx_alloc(Ctx* c, size_t bytes, hipStream_t s) {
   if (bytes == 0) bytes = 1;
+  // work being recorded into a graph must find all its memory in place
+  if (c->recording) throw Error{AHF_EDEVICE, "a recorded build asked for device memory"};
   if (c->alloc) {
     void* p = c->alloc(c->user, bytes, (void*)s);
     if (!p) throw Error{AHF_ENOMEM, "device allocation callback failed"};
@@ -352,7 +354,6 @@ void ahf_ctx_destroy(ahf_ctx* ctx) {
   if (ctx->c.dep_st) (void)hipStreamDestroy(ctx->c.dep_st);
   if (ctx->c.lab_st) (void)hipStreamDestroy(ctx->c.lab_st);
   if (ctx->c.lab_ev) (void)hipEventDestroy(ctx->c.lab_ev);
-  if (ctx->c.lab_pinned) (void)hipHostFree(ctx->c.lab_pinned);
   if (ctx->c.dep_ev) (void)hipEventDestroy(ctx->c.dep_ev);
   if (ctx->c.join_ev) (void)hipEventDestroy(ctx->c.join_ev);
   if (ctx->c.host_cnt) (void)hipHostFree(ctx->c.host_cnt);
@@ -380,7 +381,7 @@ static bool same_params(const Ctx::PlanRec& r, const Params& prm, bool has_mass,
 
 // capacities for a build of n particles from a learned plan: the per-particle
 // counts seen, with a margin (15% and 64)
-static bool plan_for(Ctx* c, const Params& prm, bool has_mass, uint64_t n, Plan* out) {
+bool plan_for(Ctx* c, const Params& prm, bool has_mass, uint64_t n, Plan* out) {
   const int bucket = size_class(n);
   for (auto& r : c->plans)
     if (same_params(r, prm, has_mass, bucket)) {

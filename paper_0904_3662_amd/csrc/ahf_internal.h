@@ -93,11 +93,9 @@ struct Ctx {
   hipStream_t dep_st = nullptr;
   hipEvent_t dep_ev = nullptr, join_ev = nullptr;
   // the third stream: the labels of the first levels, run while the build
-  // stream makes the last, small levels; the level sets of the two label
-  // passes are handed to the device from pinned memory
+  // stream makes the last, small levels
   hipStream_t lab_st = nullptr;
   hipEvent_t lab_ev = nullptr;
-  void* lab_pinned = nullptr;
   // builds keep to their one stream: set for the workers of a server with
   // several of them, whose concurrent builds already fill the GPU (and whose
   // streams would otherwise outnumber the hardware queues many times over)
@@ -120,6 +118,13 @@ struct Ctx {
   std::vector<PlanRec> plans;
   uint64_t plan_clock = 0;
   bool planning = false;
+  // builds that run with no host involvement (the sub-volumes of a batch,
+  // recorded into a graph): no timing events, no copy to pinned memory at the
+  // end, the labels enqueued within the build; the host reads each build's
+  // status block after the run (in_graph).  While a graph is being recorded
+  // nothing may allocate (recording).
+  bool in_graph = false;
+  bool recording = false;
   // tuning by size: the entry with the largest min_n <= n applies to a build
   // of n particles (defaults when none does)
   std::vector<std::pair<uint64_t, Tuning>> tuning;
@@ -177,6 +182,12 @@ class Ws {
   Mark mark() const { return Mark{cur_, chunks_.empty() ? 0 : chunks_[cur_].used}; }
   void release(Mark m);
   void reset();        // drop every allocation (memory kept for the next build)
+  // drop every allocation and keep every chunk as it is (memory that work
+  // already recorded into a graph refers to must not move)
+  void rewind() {
+    for (auto& c : chunks_) c.used = 0;
+    cur_ = 0;
+  }
   void free_all();     // give the memory back to the context
   size_t high_water() const { return high_; }
   size_t capacity() const {
@@ -235,6 +246,29 @@ struct Owned {
     used += b;
     handed += b;
     return p;
+  }
+  // the first block, of at least `bytes`, allocated now (before a build
+  // that must not allocate while it is enqueued)
+  void reserve(size_t bytes) {
+    if (!list.empty()) return;
+    const size_t hint = first_hint;
+    first_hint = std::max(first_hint, bytes);
+    (void)raw(1);
+    used = 0;
+    handed = 0;
+    first_hint = hint;
+  }
+  // the same memory handed out again from the start (the work that used it
+  // has finished): one block of at least `bytes`
+  void reuse(size_t bytes) {
+    if (list.size() == 1 && list[0].second >= bytes) {
+      used = 0;
+      room = list[0].second;
+      handed = 0;
+      return;
+    }
+    release_all();
+    reserve(bytes);
   }
   void release_all() {
     for (auto& a : list) ctx_free(ctx, a.first, a.second, st);
@@ -332,6 +366,7 @@ struct Hier {
   const uint32_t* dev_lvcnt = nullptr;  // a planned build's level counts on the device
                                         // (2 per level: refined cells, next-level bricks)
   bool replanned = false;  // a planned attempt outgrew its capacities and was redone
+  const uint64_t* dev_status = nullptr;  // the build's totals, counters and flags (in_graph)
   uint32_t host_waits = 0;  // times the host waited for the device during the build
   double ms[4] = {0, 0, 0, 0};
   double t_start = 0.0;  // host clock at the start of the build
@@ -347,6 +382,9 @@ struct Plan {
 };
 // internal status: a planned build outgrew its capacities and is redone
 constexpr ahf_status kStatusReplan = -100;
+// the capacities for a build of n particles from what the context learned
+// from earlier builds of the same parameters and size class (false: none)
+bool plan_for(Ctx* c, const Params& prm, bool has_mass, uint64_t n, Plan* out);
 
 // Enqueues the build on st.  With finish, waits for it and completes h
 // (totals, timings, device error flags); without, the caller must call
@@ -358,9 +396,21 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
                      hipStream_t st, Hier* h, bool finish = true, const Plan* plan = nullptr);
 void finish_build(Ctx* ctx, Hier* h);
 void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
+// The status block of a build that runs with no host involvement (in_graph):
+// kStatusWords 64-bit words (level totals, counters, device error flags, label
+// counts) that enqueue_status copies to dst on st once the build and its
+// labels are complete; finish_from_status completes h from a host copy
+// (throws like finish_build and label_hierarchy; kStatusReplan when a level
+// outgrew its capacity).
+constexpr size_t kStatusWords = 160;
+void enqueue_status(Hier* h, uint64_t* dst, hipStream_t st);
+void finish_from_status(Hier* h, const uint64_t* status);
+// joins the build's label stream into st and labels whatever is left, all
+// enqueued (in_graph builds: nothing is left)
+void label_enqueue(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st);
 // labels the refined cells of levels lab_done .. k1-1 on ctx->lab_st once st
-// has passed their cells, with scratch from wsd (kept); at most two calls per
-// build (one pinned level-set slot each); label_hierarchy labels what is left
+// has passed their cells, with scratch from wsd (kept); label_hierarchy labels
+// what is left
 void label_early(Ctx* ctx, Ws& wsd, Hier* h, uint32_t k1, hipStream_t st);
 // host structures and substructures of a labelled hierarchy (waits for it);
 // classify_levels only enqueues, finish_classify waits and reads the count

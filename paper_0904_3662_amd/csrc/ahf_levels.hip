@@ -1633,9 +1633,20 @@ static Tree make_tree(const Hier* h) {
   return t;
 }
 
+// The build's zeroed block: 3 totals per level (FP64), then kDevU32 words of
+// counters: [0] error flags, [1..7] per-level counters, [8 + 2L], [9 + 2L]
+// heavy cells and chunks of level L; then, for a planned build, per level the
+// raw and the clamped counts of refined cells and next-level bricks; then the
+// sort's digit histograms.  The status block of a build is its first
+// kZeroStatusWords words followed by the label counts.
+constexpr int kDevU32 = 8 + 2 * kMaxLevels + 4 * kMaxLevels;
+constexpr uint32_t kZeroStatusWords = 3 * kMaxLevels + (kDevU32 + 1) / 2;
+static_assert(kZeroStatusWords + (4 + kMaxLevels + 1) / 2 <= kStatusWords, "status block size");
+
 void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Params& prm,
                      hipStream_t st, Hier* h, bool finish, const Plan* plan) {
   const double t0 = now_ms();
+  const bool graph = ctx->in_graph;  // no host involvement: see Ctx::in_graph
   h->prm = prm;
   h->n = p.n;
   const int g = prm.g;
@@ -1653,14 +1664,9 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     HIP_CHECK(hipEventCreateWithFlags(&ctx->cnt_ev, hipEventDisableTiming));
     for (auto& e : ctx->phase_ev) HIP_CHECK(hipEventCreateWithFlags(&e, kTimingEventFlags));
   }
-  HIP_CHECK(hipEventRecord(ctx->phase_ev[0], st));
-  // [0] error flags, [1..7] per-level counters, [8 + 2L], [9 + 2L] heavy
-  // cells and chunks of level L; then, for a planned build, per level the
-  // raw and the clamped counts of refined cells and next-level bricks
-  // (one zeroed block: the totals, the counters, the sort's digit histograms;
-  // cleared by a kernel, not a memset, so that a build can be recorded into
-  // a graph)
-  constexpr int kDevU32 = 8 + 2 * kMaxLevels + 4 * kMaxLevels;
+  if (!graph) HIP_CHECK(hipEventRecord(ctx->phase_ev[0], st));
+  // the zeroed block (cleared by a kernel, not a memset, so that a build can
+  // be recorded into a graph)
   constexpr size_t kZeroWords = 3 * kMaxLevels + (kDevU32 + 1) / 2 + (kRsMaxPass * 256) / 2;
   uint64_t* zero = ws.get<uint64_t>(kZeroWords);
   k_fill_i32<<<grid_for(2 * kZeroWords), kT, 0, st>>>(reinterpret_cast<int32_t*>(zero),
@@ -1707,7 +1713,7 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
 
   Parts P;
   P.rec = srec;
-  HIP_CHECK(hipEventRecord(ctx->phase_ev[1], st));
+  if (!graph) HIP_CHECK(hipEventRecord(ctx->phase_ev[1], st));
 
   // ---- levels
   // With the count criterion a level's deposit needs only its cells and its
@@ -1996,8 +2002,9 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   }
 
   // once labels have started early, the rest go to the label stream as well:
-  // they need the cells only, not the deposits still running
-  if (early_labels && h->lab_done > 0 && h->lev.size() > 1)
+  // they need the cells only, not the deposits still running (a build with
+  // no host involvement labels every level there)
+  if (early_labels && (h->lab_done > 0 || graph) && h->lev.size() > 1)
     label_early(ctx, wsd, h, (uint32_t)(h->lev.size() - 1), st);
   if (overlap) {
     // the deposits back into the build stream
@@ -2008,6 +2015,12 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   k_level_sums_final<<<(unsigned)h->lev.size(), 256, 0, st>>>(part_all, sum_blocks, dev_tot);
   HIP_LAUNCH_CHECK();
 
+  h->t_start = t0;
+  if (graph) {
+    // the host reads the block after the run (enqueue_status)
+    h->dev_status = zero;
+    return;
+  }
   // totals and the device error flags, into pinned memory; read by
   // finish_build once the stream has passed this point
   HIP_CHECK(hipEventRecord(ctx->phase_ev[2], st));
@@ -2019,24 +2032,26 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   HIP_CHECK(hipMemcpyAsync(ctx->host_tot, dev_tot,
                            3 * kMaxLevels * sizeof(double) + kDevU32 * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, st));
-  h->t_start = t0;
   if (finish) {
     HIP_CHECK(hipStreamSynchronize(st));
     finish_build(ctx, h);
   }
 }
 
-void finish_build(Ctx* ctx, Hier* h) {
-  const double* tot = ctx->host_tot;
+static void label_finish(Hier* h, const uint32_t* hv);
+
+// completes h from a host copy of its totals and device counters (the
+// layout of the build's zeroed block); throws on device errors
+static void finish_from(Hier* h, const double* tot) {
   uint32_t herr = 0;
-  std::memcpy(&herr, ctx->host_tot + 3 * kMaxLevels, sizeof(uint32_t));
+  std::memcpy(&herr, tot + 3 * kMaxLevels, sizeof(uint32_t));
   if (h->planned) {
     // a level that outgrew its room: everything after it is clamped, so the
     // build is redone with a wait per level
     if (herr & kErrCapacity) throw Error{kStatusReplan, "a planned level outgrew its capacity"};
     // the true sizes from the device counts; levels past the last one that
     // has cells are dropped
-    const uint32_t* u = reinterpret_cast<const uint32_t*>(ctx->host_tot + 3 * kMaxLevels);
+    const uint32_t* u = reinterpret_cast<const uint32_t*>(tot + 3 * kMaxLevels);
     const uint32_t* cnt = u + 8 + 4 * kMaxLevels;
     size_t keep = h->lev.size();
     for (size_t L = 0; L < h->lev.size(); ++L) {
@@ -2058,14 +2073,47 @@ void finish_build(Ctx* ctx, Hier* h) {
     h->lev[L].nP = (uint64_t)tot[3 * L + 2];
     h->lev[L].tot_part = h->has_mass ? tot[3 * L + 1] : (double)h->lev[L].nP * h->mass_scalar;
   }
+  h->ms[3] = now_ms() - h->t_start;
+  if (herr & kErrCoord) throw Error{AHF_EINVAL, "a particle coordinate is >= 2^21"};
+  if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed on the device"};
+}
+
+void finish_build(Ctx* ctx, Hier* h) {
+  finish_from(h, ctx->host_tot);
   float e01 = 0.0f, e12 = 0.0f;
   HIP_CHECK(hipEventElapsedTime(&e01, ctx->phase_ev[0], ctx->phase_ev[1]));
   HIP_CHECK(hipEventElapsedTime(&e12, ctx->phase_ev[1], ctx->phase_ev[2]));
   h->ms[0] = e01;
   h->ms[1] = e12;
-  h->ms[3] = now_ms() - h->t_start;
-  if (herr & kErrCoord) throw Error{AHF_EINVAL, "a particle coordinate is >= 2^21"};
-  if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed on the device"};
+}
+
+// The status block: the build's zeroed block up to the end of its counters
+// (level totals, error flags, counters, level counts), then the label counts.
+__global__ void k_copy_status(uint64_t* __restrict__ dst, const uint64_t* __restrict__ blk,
+                              const uint32_t* __restrict__ lab) {
+  constexpr uint32_t kLabWords = (4 + kMaxLevels + 1) / 2;
+  for (uint32_t i = threadIdx.x; i < kStatusWords; i += blockDim.x) {
+    uint64_t v = 0;
+    if (i < kZeroStatusWords) {
+      v = blk[i];
+    } else if (i < kZeroStatusWords + kLabWords && lab) {
+      const uint32_t j = 2 * (i - kZeroStatusWords);
+      const uint64_t lo = lab[j];
+      const uint64_t hi = j + 1 < 4 + kMaxLevels ? lab[j + 1] : 0u;
+      v = lo | (hi << 32);
+    }
+    dst[i] = v;
+  }
+}
+
+void enqueue_status(Hier* h, uint64_t* dst, hipStream_t st) {
+  k_copy_status<<<1, 64, 0, st>>>(dst, h->dev_status, h->lab_dev);
+  HIP_LAUNCH_CHECK();
+}
+
+void finish_from_status(Hier* h, const uint64_t* status) {
+  finish_from(h, reinterpret_cast<const double*>(status));
+  if (h->lab_dev) label_finish(h, reinterpret_cast<const uint32_t*>(status + kZeroStatusWords));
 }
 
 void query_labels(Ws& ws, const Hier* h, int L, uint64_t n, const uint64_t* keys_host,
@@ -2124,9 +2172,12 @@ static void query_labels_static(const Hier* h, int L, uint64_t n, const uint64_t
 }
 
 // the two pinned level sets of a context (the early and the final label pass)
-static LabSet* lab_sets(Ctx* ctx) {
-  if (!ctx->lab_pinned) HIP_CHECK(hipHostMalloc(&ctx->lab_pinned, 2 * sizeof(LabSet), hipHostMallocDefault));
-  return static_cast<LabSet*>(ctx->lab_pinned);
+// The level set of a label pass goes to the device as a kernel argument: the
+// launch carries its own copy, so the host may reuse its memory at once and
+// the hand-over is part of whatever records the launch into a graph.
+static_assert(sizeof(LabSet) + sizeof(LabSet*) <= 4096, "kernel arguments are at most 4 KB");
+__global__ void k_put_labset(LabSet* __restrict__ d, const LabSet s) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d = s;
 }
 
 // The label counts of a hierarchy: [0] error flags, [1] roots of the running
@@ -2135,16 +2186,17 @@ static void label_counts(Ctx* ctx, Hier* h, hipStream_t st) {
   (void)ctx;
   if (h->lab_dev) return;
   h->lab_dev = h->mem.get<uint32_t>(4 + kMaxLevels);
-  HIP_CHECK(hipMemsetAsync(h->lab_dev, 0, (4 + kMaxLevels) * sizeof(uint32_t), st));
+  k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(h->lab_dev), 4 + kMaxLevels, 0);
+  HIP_LAUNCH_CHECK();
 }
 
 // Labels the refined cells of levels k0 .. k1-1 (the patches of levels
 // k0+1 .. k1) on st, all of them at once; level k0's patches (k0 > 0) must
-// be labelled already.  The set of levels goes to the device through the
-// pinned slot `slot` of the context.  With keep, the scratch stays allocated
-// (ws may be handed to other work while these kernels run).
-static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, int slot,
-                         bool keep, hipStream_t st) {
+// be labelled already.  With keep, the scratch stays allocated (ws may be
+// handed to other work while these kernels run).
+static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, bool keep,
+                         hipStream_t st) {
+  (void)ctx;
   uint32_t* dev = h->lab_dev;
   const Tree tree = make_tree(h);
   const double total_mass = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
@@ -2160,8 +2212,7 @@ static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, in
   // during the build), the arrays and grids are laid out by the levels'
   // capacities and the element offsets come from the device counts.
   const bool dev_sizes = !h->sizes_known;
-  LabSet& S = lab_sets(ctx)[slot];
-  S = LabSet{};
+  LabSet S{};
   S.nlev = k1 > k0 ? k1 - k0 : 0u;
   uint64_t tot = 0, ntiles = 0;
   for (uint32_t j = 0; j < S.nlev; ++j) {
@@ -2201,7 +2252,8 @@ static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, in
   if (tot <= kLabSmallMax && !h->has_mass) {
     // few elements: the whole pass in one block
     LabSet* dS = ws.get<LabSet>(1);
-    HIP_CHECK(hipMemcpyAsync(dS, &S, sizeof(LabSet), hipMemcpyHostToDevice, st));
+    k_put_labset<<<1, 64, 0, st>>>(dS, S);
+    HIP_LAUNCH_CHECK();
     if (dev_sizes) {
       k_labset_counts<<<1, 64, 0, st>>>(dS, h->dev_lvcnt, (int)k0);
       HIP_LAUNCH_CHECK();
@@ -2221,7 +2273,8 @@ static void label_levels(Ctx* ctx, Ws& ws, Hier* h, uint32_t k0, uint32_t k1, in
   uint16_t* xmask = ws.get<uint16_t>(tot);
   unsigned long long* mfix = h->has_mass ? ws.get<unsigned long long>(tot) : nullptr;
   LabSet* dS = ws.get<LabSet>(1);
-  HIP_CHECK(hipMemcpyAsync(dS, &S, sizeof(LabSet), hipMemcpyHostToDevice, st));
+  k_put_labset<<<1, 64, 0, st>>>(dS, S);
+    HIP_LAUNCH_CHECK();
   if (dev_sizes) {
     k_labset_counts<<<1, 64, 0, st>>>(dS, h->dev_lvcnt, (int)k0);
     HIP_LAUNCH_CHECK();
@@ -2258,14 +2311,11 @@ void label_early(Ctx* ctx, Ws& wsd, Hier* h, uint32_t k1, hipStream_t st) {
   // the cells of levels lab_done .. k1 are complete on st
   HIP_CHECK(hipEventRecord(ctx->lab_ev, st));
   HIP_CHECK(hipStreamWaitEvent(ctx->lab_st, ctx->lab_ev, 0));
-  // the first call reads its level set from pinned slot 0, a second from slot 1
-  label_levels(ctx, wsd, h, h->lab_done, k1, h->lab_done == 0 ? 0 : 1, true, ctx->lab_st);
+  label_levels(ctx, wsd, h, h->lab_done, k1, true, ctx->lab_st);
   h->lab_done = k1;
 }
 
-void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
-  if (h->labelled) return;
-  const double t0 = now_ms();
+void label_enqueue(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
   const size_t nlev = h->lev.size();
   label_counts(ctx, h, st);
   ctx->dev_err = h->lab_dev;
@@ -2275,18 +2325,30 @@ void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
     HIP_CHECK(hipStreamWaitEvent(st, ctx->lab_ev, 0));
   }
   const uint32_t kend = nlev > 1 ? (uint32_t)(nlev - 1) : 0u;
-  if (h->lab_done < kend) label_levels(ctx, ws, h, h->lab_done, kend, 1, false, st);
+  if (h->lab_done < kend) label_levels(ctx, ws, h, h->lab_done, kend, false, st);
   h->npatch_dev = h->lab_dev + 4;
+}
+
+// the label counts read back: [0] error flags, [4 + L] patches on level L
+static void label_finish(Hier* h, const uint32_t* hv) {
+  if (hv[0]) throw Error{AHF_EDEVICE, "internal consistency check failed while labelling"};
+  for (size_t L = 1; L < h->lev.size(); ++L) h->lev[L].nPatch = hv[4 + L];
+  h->npatch_dev = h->lab_dev + 4;
+  h->labelled = true;
+}
+
+void label_hierarchy(Ctx* ctx, Ws& ws, Hier* h, hipStream_t st) {
+  if (h->labelled) return;
+  const double t0 = now_ms();
+  const size_t nlev = h->lev.size();
+  label_enqueue(ctx, ws, h, st);
   if (h->prm.flags & AHF_SUBSTRUCTURE) classify_levels(ctx, ws, h, st);
   std::vector<uint32_t> hv(4 + nlev);
   HIP_CHECK(hipMemcpyAsync(hv.data(), h->lab_dev, (4 + nlev) * sizeof(uint32_t),
                            hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
-  const uint32_t herr = hv[0];
-  if (herr) throw Error{AHF_EDEVICE, "internal consistency check failed while labelling"};
-  for (size_t L = 1; L < nlev; ++L) h->lev[L].nPatch = hv[4 + L];
+  label_finish(h, hv.data());
   if (h->prm.flags & AHF_SUBSTRUCTURE) finish_classify(ctx, h, st);
-  h->labelled = true;
   h->ms[2] = now_ms() - t0;
   h->ms[3] += h->ms[2];
 }

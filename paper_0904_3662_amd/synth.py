@@ -46,6 +46,7 @@ class Snapshot:
     max_levels: int
     name: str = ""
     meta: dict = dataclasses.field(default_factory=dict)
+    vel: np.ndarray | None = None  # (n, 3) float32 velocities, when drawn
 
     @property
     def n(self) -> int:
@@ -60,7 +61,8 @@ class Snapshot:
                         self.fx[idx].copy(), self.fy[idx].copy(), self.fz[idx].copy(),
                         None if self.mass is None else self.mass[idx].copy(),
                         self.g, self.dom_ref, self.ref_ref, self.max_levels,
-                        name or self.name + "-subset", dict(self.meta))
+                        name or self.name + "-subset", dict(self.meta),
+                        None if self.vel is None else self.vel[idx].copy())
 
 
 def quantize(x: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
@@ -228,13 +230,25 @@ def snapshot(seed: int, n: int, *, g: int, thr: float, max_levels: int,
              conc: float | tuple[float, float], lattice_side: int = 0,
              sigma_cells: float = 0.3, n_sub: int = 0,
              sub_frac: tuple[float, float] = (0.01, 0.1), shuffle: bool = True,
-             name: str = "") -> Snapshot:
+             name: str = "", velocities: bool = False) -> Snapshot:
     """Background (uniform if lattice_side == 0, else a random subset of a
     lattice_side^3 lattice perturbed by a Gaussian of sigma_cells * spacing per
     axis) plus `n_halos` NFW halos holding round(halo_frac*n) particles, with
     optional Plummer subhalos inside each host.  Every random draw comes from a
     child stream of SeedSequence(seed) in fixed-size chunks, so the result does
-    not depend on the number of threads."""
+    not depend on the number of threads.
+
+    With velocities, every particle also gets a velocity (units: box length 1,
+    particle mass 1, G = 1), drawn from a child stream of its own so that the
+    positions are those of the same call without velocities:
+      background  isotropic Gaussian, sigma = v0, the circular velocity at r200
+                  of a halo of the mean host size;
+      host halo   a bulk velocity (Gaussian, sigma = v0) plus an isotropic
+                  Gaussian of sigma = 0.6 * sqrt(G M / r200) per axis, except
+                  5% of its particles, drawn with 3 times that sigma;
+      subhalo     its host's bulk velocity plus a Gaussian of the host's sigma,
+                  plus the same internal recipe with its own count and
+                  truncation radius."""
     root = np.random.SeedSequence(seed)
     s_bg, s_halo, s_nfw, s_sub, s_shuf = root.spawn(5)
     rng = np.random.Generator(np.random.PCG64(s_halo))
@@ -243,6 +257,13 @@ def snapshot(seed: int, n: int, *, g: int, thr: float, max_levels: int,
     meta = dict(seed=seed, n=n, n_background=n_bg, n_halo_particles=n_halo_part,
                 n_halos=n_halos, lattice_side=lattice_side)
     pos = np.empty((n, 3), np.float64)
+    vel = None
+    if velocities:
+        s_vel = root.spawn(1)[0]  # the sixth child: the first five are unchanged
+        vrng = np.random.Generator(np.random.PCG64(s_vel))
+        vel = np.empty((n, 3), np.float64)
+        mean_host = max(1.0, n_halo_part / max(n_halos, 1))
+        v0 = math.sqrt(mean_host / float(r200_of(np.array([mean_host]), n)[0]))
     if lattice_side > 0:
         sites = lattice_side ** 3
         if n_bg > sites:
@@ -293,6 +314,14 @@ def snapshot(seed: int, n: int, *, g: int, thr: float, max_levels: int,
         a = n_bg
         nh = int(host_counts.sum())
         pos[a:a + nh] = np.repeat(centres, host_counts, axis=0) + nfw_offsets(s_nfw, host_counts, cc, r200)
+        if vel is not None:
+            vel[:n_bg] = vrng.normal(0.0, v0, size=(n_bg, 3))
+            bulk = vrng.normal(0.0, v0, size=(n_halos, 3))
+            sig = 0.6 * np.sqrt(counts / r200)
+            s_each = np.repeat(sig, host_counts)
+            s_each = s_each * np.where(vrng.random(nh) < 0.05, 3.0, 1.0)
+            vel[a:a + nh] = (np.repeat(bulk, host_counts, axis=0)
+                             + vrng.normal(0.0, 1.0, size=(nh, 3)) * s_each[:, None])
         a += nh
         if n_sub > 0:
             srng = np.random.Generator(np.random.PCG64(s_sub))
@@ -306,47 +335,59 @@ def snapshot(seed: int, n: int, *, g: int, thr: float, max_levels: int,
             rt = r200_of(sc, n)
             ns = int(sc.sum())
             pos[a:a + ns] = np.repeat(sub_centre, sc, axis=0) + plummer_offsets(srng, sc, rt / 5.0, rt)
+            if vel is not None:
+                sbulk = bulk[owner] + vrng.normal(0.0, 1.0, size=(len(sc), 3)) * sig[owner, None]
+                ssig = 0.6 * np.sqrt(sc / rt)
+                s_each = np.repeat(ssig, sc) * np.where(vrng.random(ns) < 0.05, 3.0, 1.0)
+                vel[a:a + ns] = (np.repeat(sbulk, sc, axis=0)
+                                 + vrng.normal(0.0, 1.0, size=(ns, 3)) * s_each[:, None])
             a += ns
             meta["n_subhalos"] = int(len(sc))
         assert a == n, (a, n)
         meta["halo_count_sum"] = int(counts.sum())
+    elif vel is not None:
+        vel[:] = vrng.normal(0.0, v0, size=(n, 3))
     if shuffle:
         perm = np.random.Generator(np.random.PCG64(s_shuf)).permutation(n)
         pos = pos[perm]
+        if vel is not None:
+            vel = vel[perm]
     X, Y, Z, fx, fy, fz = _quantize_chunks(pos)
     return Snapshot(X, Y, Z, fx, fy, fz, None, g, float(thr), float(thr), max_levels,
-                    name, meta)
+                    name, meta, None if vel is None else vel.astype(np.float32))
 
 
-def small_mixed(seed: int = 0) -> Snapshot:
+def small_mixed(seed: int = 0, velocities: bool = False) -> Snapshot:
     """32^3 equal-mass particles: 70% uniform, 30% in 8 NFW halos (c = 8,
     sizes from M^-1.9 over 200..4000 rescaled to the budget); 32^3 domain
     grid, threshold 5, at most 4 refinement levels."""
     return snapshot(seed, 32 ** 3, g=5, thr=5.0, max_levels=4, halo_frac=0.3,
                     n_halos=8, mass_lo=200.0, mass_hi=4000.0, conc=8.0,
-                    name="small-mixed-32k")
+                    name="small-mixed-32k", velocities=velocities)
 
 
-def snapshot_16m(seed: int = 1) -> Snapshot:
+def snapshot_16m(seed: int = 1, velocities: bool = False) -> Snapshot:
     """256^3 particles: 80% of a 256^3 lattice perturbed by 0.3 lattice spacing,
     20% in 2000 NFW halos (c log-uniform 4..15, sizes M^-1.9 over 20..2e5);
     128^3 domain grid, threshold 5, at most 10 refinement levels."""
     return snapshot(seed, 1 << 24, g=7, thr=5.0, max_levels=10, halo_frac=0.2,
                     n_halos=2000, mass_lo=20.0, mass_hi=2e5, conc=(4.0, 15.0),
-                    lattice_side=256, name="lattice-nfw-16.8M")
+                    lattice_side=256, name="lattice-nfw-16.8M", velocities=velocities)
 
 
-def snapshot_134m(seed: int = 2) -> Snapshot:
+def snapshot_134m(seed: int = 2, velocities: bool = False) -> Snapshot:
     """512^3 particles: 70% of a 512^3 lattice perturbed by 0.3 spacing, 30% in
     20000 NFW hosts with 5 Plummer subhalos each (0.01..0.1 of the host);
     256^3 domain grid, threshold 5, at most 12 refinement levels."""
     return snapshot(seed, 1 << 27, g=8, thr=5.0, max_levels=12, halo_frac=0.3,
                     n_halos=20000, mass_lo=20.0, mass_hi=2e5, conc=(4.0, 15.0),
-                    lattice_side=512, n_sub=5, name="lattice-nfw-sub-134M")
+                    lattice_side=512, n_sub=5, name="lattice-nfw-sub-134M",
+                    velocities=velocities)
 
 
 def scaled_like_16m(seed: int, n: int, g: int | None = None, max_levels: int = 10,
-                    halo_frac: float = 0.2) -> Snapshot:
+                    halo_frac: float = 0.2, velocities: bool = False,
+                    n_sub: int = 0) -> Snapshot:
     """The 16.8M recipe at another particle count: lattice on ceil(n^{1/3})^3
     sites, 2000*n/2^24 halos (at least 1), domain grid chosen so that a domain
     cell holds about 8 particles (clamped to 32^3..128^3 unless given)."""
@@ -358,7 +399,8 @@ def scaled_like_16m(seed: int, n: int, g: int | None = None, max_levels: int = 1
     nh = max(1, int(round(2000 * n / float(1 << 24))))
     return snapshot(seed, n, g=g, thr=5.0, max_levels=max_levels, halo_frac=halo_frac,
                     n_halos=nh, mass_lo=20.0, mass_hi=2e5, conc=(4.0, 15.0),
-                    lattice_side=side, name=f"lattice-nfw-{n}")
+                    lattice_side=side, name=f"lattice-nfw-{n}", velocities=velocities,
+                    n_sub=n_sub)
 
 
 def subvolume_sizes(seed: int, count: int, lo_exp: float, hi_exp: float) -> np.ndarray:

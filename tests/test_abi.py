@@ -59,6 +59,20 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert h.value is None
     lib.ahf_hierarchy_free.argtypes = [C.c_void_p]
     lib.ahf_hierarchy_free(None)
+    # the batch entry points check their arguments before touching a device
+    lib.ahf_batch_create.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                                     C.c_uint32, C.c_uint32, C.c_void_p, C.c_void_p]
+    b = C.c_void_p(1)
+    assert lib.ahf_batch_create(None, 1, None, None, 4, 0, None, C.byref(b)) == -1
+    assert b.value is None
+    lib.ahf_batch_run.argtypes = [C.c_void_p, C.c_void_p]
+    assert lib.ahf_batch_run(None, None) == -1
+    lib.ahf_batch_wait.argtypes = [C.c_void_p]
+    assert lib.ahf_batch_wait(None) == -1
+    lib.ahf_batch_hierarchy.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p]
+    assert lib.ahf_batch_hierarchy(None, 0, C.byref(b)) == -1
+    lib.ahf_batch_destroy.argtypes = [C.c_void_p]
+    lib.ahf_batch_destroy(None)
 
 
 def test_ctx_create_without_a_gpu_fails_cleanly():
