@@ -391,6 +391,77 @@ ahf_status ahf_server_get_stats(ahf_server *s, ahf_server_stats *out);
 /* Waits for running builds, frees every result. */
 void ahf_server_destroy(ahf_server *s);
 
+/* ------------------------------------------------------------------ halos
+ *
+ * Particle collection and iterative unbinding (Sect. 2.1, the paragraphs after
+ * the classification of the grid tree; App. A).  Every structure of a
+ * classified hierarchy is a prospective halo:
+ * - its leaf is its patch on the deepest level its main branch reaches; its
+ *   centre is the centre of mass of the leaf patch's particles (periodic
+ *   minimum image relative to the lower corner of the leaf's smallest-key
+ *   cell; a leaf without mass takes that cell's centre);
+ * - a host collects the particles of its main-branch patch on the deepest
+ *   level whose boundary contour, thr_{L-1} particles per level-(L-1) cell,
+ *   lies below delta_vir times the background density (its start patch when
+ *   none does); a substructure collects every particle within half the
+ *   distance from its centre to its host's centre;
+ * - the halo is then unbound in isolation: per round, the velocity of the halo
+ *   is the mass-weighted mean of its particles' velocities; with the particles
+ *   ordered by radius from the fixed centre (clamped below at half a position
+ *   quantum; ties by index), r_vir is the radius of the last particle whose
+ *   enclosed mean density (itself included) is at least delta_vir times the
+ *   background; the potential is phi(r) = -G (int_r^r_vir M(<r')/r'^2 dr' +
+ *   M_vir / r_vir) within r_vir, -G M_vir / r beyond (App. A, the halo
+ *   truncated at r_vir; the enclosed mass is constant between particles); a
+ *   particle whose kinetic energy per mass relative to the halo exceeds |phi|
+ *   is removed; rounds repeat until none is (at most max_iter);
+ * - the halo's particles are those left within r_vir.  A halo that never
+ *   reaches the overdensity, or does not converge, keeps none (r_vir = M_vir
+ *   = 0).
+ * Units are the caller's: positions in box lengths, the particle masses of
+ * the build, velocities as given, G as given; the background density is the
+ * total particle mass per box volume.
+ */
+typedef struct {
+    uint32_t struct_size;   /* sizeof(ahf_halo_params) */
+    double delta_vir;       /* virial overdensity (the paper's mass functions use 340) */
+    double G;               /* gravitational constant in the caller's units */
+    uint32_t max_iter;      /* at most this many unbinding rounds (>= 1) */
+} ahf_halo_params;
+
+typedef struct ahf_halos ahf_halos;
+
+/* Finds the halos of h, which must be labelled and classified.  p holds the
+ * particles the hierarchy was built from (same device arrays or copies; n as
+ * built); vx, vy, vz are device arrays of n velocities.  Waits for the work
+ * on stream.  The result owns its device memory (ctx's allocator) until
+ * ahf_halos_free. */
+ahf_status ahf_find_halos(ahf_ctx *ctx, const ahf_hierarchy *h, const ahf_particles *p,
+                          const float *vx, const float *vy, const float *vz,
+                          const ahf_halo_params *prm, void *stream, ahf_halos **out);
+
+/* Device views of the halos, one per structure (structure order).  Halo s's
+ * candidates and its particles are stored from cand_offset[s] on: cand[...]
+ * ascending particle indices (cand_count[s] of them), member[...] ascending
+ * (member_count[s]). */
+typedef struct {
+    uint64_t n_halos;
+    const uint64_t *leaf;           /* leaf level << 32 | leaf patch id */
+    const double *centre;           /* [3 n] x, y, z in [0, 1) */
+    const double *radius;           /* collection radius of a substructure, 0 for a host */
+    const uint64_t *cand_offset;    /* [n + 1] */
+    const uint32_t *cand_count;
+    const uint32_t *cand;
+    const uint32_t *member_count;
+    const uint32_t *member;
+    const double *r_vir;
+    const double *m_vir;
+    const double *vel;              /* [3 n] the halo's velocity (last round) */
+    const uint32_t *iterations;     /* unbinding rounds taken */
+} ahf_halos_view;
+ahf_status ahf_halos_get(const ahf_halos *hs, ahf_halos_view *out);
+void ahf_halos_free(ahf_halos *hs);
+
 /* ------------------------------------------------------------------ batches
  *
  * Many independent sub-volumes built by one graph launch.  The paper analyses

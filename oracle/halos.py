@@ -47,6 +47,10 @@ Readings taken here (the paper leaves them open):
   exceeds |phi| (strictly); all unbound particles of an iteration go at once;
   the iteration stops when none goes (at most max_iter iterations);
 - H7 the halo's particles are those left within r_vir; M_vir is their mass;
+  a halo that dissolves (H5) or has not converged after max_iter iterations
+  keeps no particles and has r_vir = M_vir = 0; a leaf patch without mass
+  (possible only with a negative threshold) has the centre of its
+  smallest-key cell;
 - H8 units: box length 1, particle mass 1 (or the given masses), G = 1;
   rho_b = total mass / box volume; Delta_vir = 340 (the value the paper uses
   for its mass functions).
@@ -114,7 +118,10 @@ def centre_of(levels, order, pos, mass, L: int, q: int) -> np.ndarray:
     idx = patch_particles(levels, order, L, q)
     d = min_image(pos[idx] - ref)
     w = mass[idx]
-    c = ref + (w[:, None] * d).sum(axis=0) / w.sum()
+    if w.sum() == 0:
+        c = ref + 0.5 / float(1 << lv.bits)
+    else:
+        c = ref + (w[:, None] * d).sum(axis=0) / w.sum()
     return c - np.floor(c)
 
 
@@ -174,20 +181,19 @@ def unbind(idx, pos, vel, mass, centre, rho_b, delta_vir=340.0, G=1.0, max_iter=
         a, r, m = alive[o], r[o], m[o]
         v, r_vir, m_vir, phi = profile(r, m, rho_b, delta_vir, G)
         if v < 0:  # never dense enough: the halo dissolves
-            out["members"] = np.zeros(0, np.int64)
-            out["vel"] = vh
+            out.update(members=np.zeros(0, np.int64), vel=vh, r_vir=0.0, m_vir=0.0)
             return out
         dv = vel[a] - vh
         ke = 0.5 * (dv * dv).sum(axis=1)
         gone = ke > np.abs(phi)
-        out.update(r_vir=r_vir, vel=vh)
+        out["vel"] = vh
         if not gone.any():
             keep = np.sort(a[:v + 1])
-            out["members"] = keep
-            out["m_vir"] = float(mass[keep].sum())
+            out.update(members=keep, r_vir=r_vir, m_vir=float(mass[keep].sum()))
             return out
         alive = np.sort(a[~gone])
-    # no convergence within max_iter: what is left within r_vir
+    # no convergence within max_iter: no particles
+    out.update(members=np.zeros(0, np.int64), r_vir=0.0, m_vir=0.0)
     return out
 
 

@@ -36,6 +36,7 @@ EXPORTS = [
     "ahf_ctx_set_planning", "ahf_hierarchy_build_info",
     "ahf_batch_create", "ahf_batch_run", "ahf_batch_wait", "ahf_batch_status",
     "ahf_batch_hierarchy", "ahf_batch_destroy",
+    "ahf_find_halos", "ahf_halos_get", "ahf_halos_free",
 ]
 
 
@@ -90,6 +91,19 @@ class Tuning(C.Structure):
 class BuildInfo(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("planned", C.c_uint32), ("replanned", C.c_uint32),
                 ("host_waits", C.c_uint32), ("device_bytes", C.c_uint64)]
+
+
+class HaloParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("delta_vir", C.c_double), ("G", C.c_double),
+                ("max_iter", C.c_uint32)]
+
+
+class HalosView(C.Structure):
+    _fields_ = [("n_halos", C.c_uint64), ("leaf", C.c_void_p), ("centre", C.c_void_p),
+                ("radius", C.c_void_p), ("cand_offset", C.c_void_p), ("cand_count", C.c_void_p),
+                ("cand", C.c_void_p), ("member_count", C.c_void_p), ("member", C.c_void_p),
+                ("r_vir", C.c_void_p), ("m_vir", C.c_void_p), ("vel", C.c_void_p),
+                ("iterations", C.c_void_p)]
 
 
 class ServerDesc(C.Structure):
@@ -191,9 +205,14 @@ def load():
     L.ahf_batch_hierarchy.argtypes = [vp, C.c_uint32, C.POINTER(vp)]
     L.ahf_batch_destroy.argtypes = [vp]
     L.ahf_batch_destroy.restype = None
+    L.ahf_find_halos.argtypes = [vp, vp, C.POINTER(Particles), vp, vp, vp,
+                                 C.POINTER(HaloParams), vp, C.POINTER(vp)]
+    L.ahf_halos_get.argtypes = [vp, C.POINTER(HalosView)]
+    L.ahf_halos_free.argtypes = [vp]
+    L.ahf_halos_free.restype = None
     for name in EXPORTS:
         if name not in ("ahf_ctx_destroy", "ahf_hierarchy_free", "ahf_last_error",
-                        "ahf_server_destroy", "ahf_batch_destroy"):
+                        "ahf_server_destroy", "ahf_batch_destroy", "ahf_halos_free"):
             getattr(L, name).restype = C.c_int32
     _lib = L
     return L
@@ -645,3 +664,44 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+def find_halos(ctx: Context, h: Hierarchy, dev, vel, delta_vir: float = 340.0, G: float = 1.0,
+               max_iter: int = 1000, stream=None) -> dict:
+    """Particle collection and unbinding of every structure of a classified
+    hierarchy (ahf_find_halos); dev holds the particle tensors the hierarchy
+    was built from, vel the (n, 3) velocities on the device.  Returns the
+    halos as numpy arrays (the device result is freed)."""
+    vel = vel.contiguous()
+    vx, vy, vz = (vel[:, k].contiguous() for k in range(3))
+    parts = make_particles(*dev[:6], dev[6])
+    prm = HaloParams(C.sizeof(HaloParams), float(delta_vir), float(G), int(max_iter))
+    out = C.c_void_p()
+    _check(load().ahf_find_halos(ctx.handle, h.handle, C.byref(parts), _ptr(vx), _ptr(vy),
+                                 _ptr(vz), C.byref(prm), _stream_handle(stream), C.byref(out)))
+    try:
+        v = HalosView()
+        _check(load().ahf_halos_get(out, C.byref(v)))
+        n = int(v.n_halos)
+        res = {"n_halos": n}
+        res["leaf"] = to_host(v.leaf, n, np.uint64)
+        res["centre"] = to_host(v.centre, 3 * n, np.float64).reshape(n, 3)
+        res["radius"] = to_host(v.radius, n, np.float64)
+        off = to_host(v.cand_offset, n + 1, np.uint64)
+        res["cand_offset"] = off
+        total = int(off[-1]) if n else 0
+        res["cand_count"] = to_host(v.cand_count, n, np.uint32)
+        res["member_count"] = to_host(v.member_count, n, np.uint32)
+        cand = to_host(v.cand, max(total, 1), np.uint32)
+        mem = to_host(v.member, max(total, 1), np.uint32)
+        res["candidates"] = [cand[int(off[s]):int(off[s]) + int(res["cand_count"][s])]
+                             for s in range(n)]
+        res["members"] = [mem[int(off[s]):int(off[s]) + int(res["member_count"][s])]
+                          for s in range(n)]
+        res["r_vir"] = to_host(v.r_vir, n, np.float64)
+        res["m_vir"] = to_host(v.m_vir, n, np.float64)
+        res["vel"] = to_host(v.vel, 3 * n, np.float64).reshape(n, 3)
+        res["iterations"] = to_host(v.iterations, n, np.uint32)
+        return res
+    finally:
+        load().ahf_halos_free(out)

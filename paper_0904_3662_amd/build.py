@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libahf.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["ahf_prims.hip", "ahf_levels.hip", "ahf_capi.cpp", "ahf_server.cpp", "ahf_batch.cpp"]
+SOURCES = ["ahf_prims.hip", "ahf_levels.hip", "ahf_capi.cpp", "ahf_server.cpp", "ahf_batch.cpp",
+           "ahf_halos.hip"]
 ARCH = os.environ.get("AHF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -1,0 +1,939 @@
+// ahf_halos.hip -- particle collection and iterative unbinding of the halos of
+// a classified grid tree (Sect. 2.1, the paragraphs after the classification;
+// App. A).
+//
+// Every structure of the classification is a prospective halo:
+//   - its leaf is its patch on the deepest level its main branch reaches, and
+//     its centre is the centre of mass of the leaf patch's particles (periodic
+//     minimum image relative to the lower corner of the leaf's smallest-key
+//     cell);
+//   - a host collects the particles of its main-branch patch on the deepest
+//     level whose boundary contour (thr_{L-1} particles per level-(L-1) cell)
+//     lies below Delta_vir times the background density; a substructure
+//     collects every particle within half the distance to its host's centre;
+//   - unbound particles are removed iteratively: with the particles ordered by
+//     radius from the (fixed) centre, the potential is the integral of
+//     M(<r')/r'^2 from r to r_vir plus G M_vir / r_vir (the halo truncated at
+//     r_vir, App. A), -G M_vir / r beyond r_vir, and a particle whose kinetic
+//     energy relative to the halo's mean velocity exceeds |phi| leaves; r_vir
+//     is the radius of the last particle whose enclosed mean density is at
+//     least Delta_vir times the background.
+//
+// Layout: one workgroup per structure for everything that follows one halo
+// (its centre, its sphere query, its unbinding), so that every sum, sort and
+// compaction has a fixed order and reruns are bit-identical; the particle
+// lists of the leaf and isodensity patches are made per cell with atomics
+// (order-free counts and cursors) and sorted by particle index afterwards.
+// The centre does not move while a halo is unbound, so the candidates are
+// sorted by (radius, index) once; each round then keeps that order while it
+// drops the unbound particles.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "ahf_internal.h"
+
+// the FP64 arithmetic of the distance and energy tests is done as written
+// (no fused multiply-adds), as it is in the plain definition
+#pragma clang fp contract(off)
+
+namespace ahf {
+namespace {
+
+constexpr int kHT = 256;             // threads per workgroup of the per-halo kernels
+constexpr int kHW = kHT / 64;        // waves per workgroup
+constexpr int kHB = 256;             // threads per block of the per-cell kernels
+constexpr double kQuantum = 1.0 / (double)(1u << kQBits);
+constexpr double kHalfQuantum = 0.5 / (double)(1u << kQBits);
+
+__global__ void k_fill_u64(uint64_t* a, uint64_t n, uint64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* a, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+unsigned blocks_for(uint64_t n, int t = kHB) {
+  uint64_t b = (n + t - 1) / t;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (unsigned)b;
+}
+
+// ---------------------------------------------------------------- block primitives
+// (kHT threads; every thread of the workgroup calls them)
+
+__device__ inline uint64_t lanes_below() {
+  const uint32_t lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// sum over the workgroup in a fixed order (wave butterflies, then waves in order)
+__device__ double block_sum(double x, double* red) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (__lane_id() == 0) red[w] = x;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < kHW; ++i) t += red[i];
+  return t;
+}
+
+__device__ uint64_t block_or(uint64_t x, uint64_t* red) {
+  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (__lane_id() == 0) red[w] = x;
+  __syncthreads();
+  uint64_t t = 0;
+  for (int i = 0; i < kHW; ++i) t |= red[i];
+  return t;
+}
+
+__device__ uint64_t block_and(uint64_t x, uint64_t* red) {
+  for (int o = 32; o > 0; o >>= 1) x &= __shfl_xor(x, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (__lane_id() == 0) red[w] = x;
+  __syncthreads();
+  uint64_t t = ~0ull;
+  for (int i = 0; i < kHW; ++i) t &= red[i];
+  return t;
+}
+
+__device__ int64_t block_max_i64(int64_t x, int64_t* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(x, o);
+    x = y > x ? y : x;
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if (__lane_id() == 0) red[w] = x;
+  __syncthreads();
+  int64_t t = red[0];
+  for (int i = 1; i < kHW; ++i) t = red[i] > t ? red[i] : t;
+  return t;
+}
+
+// inclusive scan of one value per thread over the workgroup, in thread
+// order; returns the thread's prefix and sets *total
+__device__ double block_scan(double x, double* red, double* total) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) red[w] = x;
+  __syncthreads();
+  double before = 0.0, all = 0.0;
+  for (int i = 0; i < kHW; ++i) {
+    if (i < w) before += red[i];
+    all += red[i];
+  }
+  *total = all;
+  return before + x;
+}
+
+// Stable LSD radix sort of n (key, val) pairs of a segment: the pairs are in
+// (ka, va); kb, vb are as large.  Digits of 8 bits; a digit that every key
+// shares is skipped.  Returns true when the result is in (kb, vb).
+template <class K>
+__device__ bool block_sort(K* ka, uint32_t* va, K* kb, uint32_t* vb, uint32_t n) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kHW][256];
+  __shared__ uint64_t red[kHW];
+  uint64_t o = 0, a = ~0ull;
+  for (uint32_t i = threadIdx.x; i < n; i += kHT) {
+    o |= (uint64_t)ka[i];
+    a &= (uint64_t)ka[i];
+  }
+  const uint64_t any = block_or(o, red);
+  const uint64_t all = block_and(a, red);
+  const uint64_t vary = any ^ all;
+  bool flipped = false;
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  for (int p = 0; p < (int)sizeof(K); ++p) {
+    if (((vary >> (8 * p)) & 255u) == 0) continue;  // same digit everywhere
+    K* src = flipped ? kb : ka;
+    uint32_t* sv = flipped ? vb : va;
+    K* dst = flipped ? ka : kb;
+    uint32_t* dv = flipped ? va : vb;
+    // digit counts, then each digit's first slot
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kHT)
+      atomicAdd(&hist[((uint64_t)src[i] >> (8 * p)) & 255u], 1u);
+    __syncthreads();
+    {
+      const uint32_t c = hist[threadIdx.x];
+      uint32_t x = c;
+      for (int s = 1; s < 64; s <<= 1) {
+        const uint32_t y = __shfl_up(x, s);
+        if (lane >= s) x += y;
+      }
+      __shared__ uint32_t wt[kHW];
+      if (lane == 63) wt[w] = x;
+      __syncthreads();
+      uint32_t before = 0;
+      for (int i = 0; i < w; ++i) before += wt[i];
+      run[threadIdx.x] = before + x - c;  // exclusive: the digit's first slot
+    }
+    __syncthreads();
+    // chunks of kHT in order; within a chunk, ranks by thread order
+    for (uint32_t c0 = 0; c0 < n; c0 += kHT) {
+      const uint32_t i = c0 + threadIdx.x;
+      const bool valid = i < n;
+      K key = valid ? src[i] : K(0);
+      const uint32_t val = valid ? sv[i] : 0u;
+      const uint32_t d = (uint32_t)(((uint64_t)key >> (8 * p)) & 255u);
+      // lanes of this wave with the same digit
+      uint64_t peer = __ballot(valid);
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const uint64_t bm = __ballot(on);
+        peer &= on ? bm : ~bm;
+      }
+      for (int j = threadIdx.x; j < kHW * 256; j += kHT) (&wcnt[0][0])[j] = 0;
+      __syncthreads();
+      const uint32_t rank = (uint32_t)__popcll(peer & lanes_below());
+      if (valid && (peer & lanes_below()) == 0ull) wcnt[w][d] = (uint32_t)__popcll(peer);
+      __syncthreads();
+      if (valid) {
+        uint32_t before = 0;
+        for (int k = 0; k < w; ++k) before += wcnt[k][d];
+        const uint32_t dest = run[d] + before + rank;
+        dst[dest] = key;
+        dv[dest] = val;
+      }
+      __syncthreads();
+      {
+        uint32_t t = 0;
+        for (int k = 0; k < kHW; ++k) t += wcnt[k][threadIdx.x];
+        run[threadIdx.x] += t;
+      }
+      __syncthreads();
+    }
+    flipped = !flipped;
+  }
+  return flipped;
+}
+
+// ---------------------------------------------------------------- leaves and patch lists
+
+// leafkey[s] = max over the patches of structure s of (level << 32 | patch)
+__global__ void k_leaf(int L, const int32_t* __restrict__ pstruct, uint64_t npatch,
+                       unsigned long long* __restrict__ leafkey) {
+  const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (q >= npatch) return;
+  const int32_t s = pstruct[q];
+  if (s < 0) return;
+  atomicMax(&leafkey[s], ((unsigned long long)L << 32) | (unsigned long long)q);
+}
+
+// the isodensity patch of every host: its main-branch patch on the deepest
+// level in [start, leaf] whose contour lies below Delta_vir (bit L of
+// isomask), else its start level
+__global__ void k_iso(int L, const int32_t* __restrict__ pstruct, uint64_t npatch,
+                      const int32_t* __restrict__ s_depth, const int32_t* __restrict__ s_level,
+                      const unsigned long long* __restrict__ leafkey, uint32_t isomask,
+                      int32_t* __restrict__ iso_patch, int32_t* __restrict__ iso_level) {
+  const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (q >= npatch) return;
+  const int32_t s = pstruct[q];
+  if (s < 0 || s_depth[s] != 0) return;
+  const int start = s_level[s];
+  const int leafL = (int)(leafkey[s] >> 32);
+  int li = start;
+  for (int l = start; l <= leafL; ++l)
+    if ((isomask >> l) & 1u) li = l;
+  if (li == L) {
+    iso_patch[s] = (int32_t)q;
+    iso_level[s] = L;
+  }
+}
+
+// Per cell of level L: the cells of a structure's leaf patch count their
+// particles into leaf_cnt (and the smallest key into leaf_min); the cells of a
+// host's isodensity patch count into iso_cnt.  With fill, the particle indices
+// are written into the lists at the structures' offsets instead (cursor order).
+__global__ void k_patch_lists(int L, uint64_t nS, uint64_t npatch, const uint64_t* __restrict__ Skey,
+                              const uint32_t* __restrict__ Sstart,
+                              const uint32_t* __restrict__ Scount,
+                              const int32_t* __restrict__ Spatch,
+                              const int32_t* __restrict__ pstruct,
+                              const unsigned long long* __restrict__ leafkey,
+                              const int32_t* __restrict__ iso_patch,
+                              const int32_t* __restrict__ iso_level, const uint32_t* __restrict__ order,
+                              uint32_t* __restrict__ leaf_cnt,
+                              unsigned long long* __restrict__ leaf_min,
+                              uint32_t* __restrict__ iso_cnt, int fill,
+                              const uint64_t* __restrict__ leaf_off,
+                              uint32_t* __restrict__ leaf_list,
+                              const uint64_t* __restrict__ iso_off, uint32_t* __restrict__ iso_list) {
+  const uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (c >= nS) return;
+  const int32_t q = Spatch[c];
+  if (q < 0 || (uint64_t)q >= npatch) return;
+  const int32_t s = pstruct[q];
+  if (s < 0) return;
+  const uint32_t cnt = Scount[c];
+  const bool is_leaf = leafkey[s] == (((unsigned long long)L << 32) | (unsigned long long)q);
+  const bool is_iso = iso_level[s] == L && iso_patch[s] == q;
+  if (!is_leaf && !is_iso) return;
+  if (!fill) {
+    if (is_leaf) {
+      atomicAdd(&leaf_cnt[s], cnt);
+      atomicMin(&leaf_min[s], (unsigned long long)Skey[c]);
+    }
+    if (is_iso) atomicAdd(&iso_cnt[s], cnt);
+    return;
+  }
+  const uint32_t a = Sstart[c];
+  if (is_leaf && cnt) {
+    const uint32_t at = atomicAdd(&leaf_cnt[s], cnt);
+    for (uint32_t j = 0; j < cnt; ++j) leaf_list[leaf_off[s] + at + j] = order[a + j];
+  }
+  if (is_iso && cnt) {
+    const uint32_t at = atomicAdd(&iso_cnt[s], cnt);
+    for (uint32_t j = 0; j < cnt; ++j) iso_list[iso_off[s] + at + j] = order[a + j];
+  }
+}
+
+// exclusive scan of n counts into n+1 offsets, one workgroup, in order
+__global__ __launch_bounds__(kHT) void k_offsets(const uint32_t* __restrict__ cnt, uint64_t n,
+                                                 uint64_t* __restrict__ off) {
+  __shared__ double red[kHW];
+  uint64_t carry = 0;
+  for (uint64_t c0 = 0; c0 < n; c0 += kHT) {
+    const uint64_t i = c0 + threadIdx.x;
+    const uint32_t v = i < n ? cnt[i] : 0u;
+    // counts fit a double exactly (sums below 2^53)
+    double total = 0.0;
+    const double incl = block_scan((double)v, red, &total);
+    if (i < n) off[i] = carry + (uint64_t)incl - v;
+    carry += (uint64_t)total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) off[n] = carry;
+}
+
+
+// ---------------------------------------------------------------- per-halo kernels
+
+struct PartIn {
+  const uint32_t *X, *Y, *Z;
+  const float *fx, *fy, *fz;  // may be null
+  const float* mass;          // null: every particle has mass_scalar
+  double mass_scalar;
+  const float *vx, *vy, *vz;
+};
+
+__device__ inline double coord(const uint32_t* X, const float* f, uint32_t i) {
+  return ((double)X[i] + (f ? (double)f[i] : 0.0)) * kQuantum;
+}
+__device__ inline double mimg(double d) { return d - rint(d); }  // periodic minimum image
+__device__ inline double pmass(const PartIn& P, uint32_t i) {
+  return P.mass ? (double)P.mass[i] : P.mass_scalar;
+}
+
+// centre of every structure: the leaf list sorted by particle index, then the
+// mass-weighted mean of the minimum-image offsets from the lower corner of the
+// leaf's smallest-key cell
+__global__ __launch_bounds__(kHT) void k_centre(const uint64_t* __restrict__ leaf_off,
+                                                const uint32_t* __restrict__ leaf_cnt,
+                                                uint32_t* leaf_list, uint32_t* leaf_tmp,
+                                                const unsigned long long* __restrict__ leafkey,
+                                                const unsigned long long* __restrict__ leaf_min,
+                                                int g, PartIn P, double* __restrict__ centre) {
+  __shared__ double red[kHW];
+  const uint32_t s = blockIdx.x;
+  const uint32_t n = leaf_cnt[s];
+  uint32_t* a = leaf_list + leaf_off[s];
+  uint32_t* b = leaf_tmp + leaf_off[s];
+  const bool fl = block_sort<uint32_t>(a, a, b, b, n);
+  const uint32_t* idx = fl ? b : a;
+  const int bits = g + (int)(leafkey[s] >> 32);
+  const uint64_t key = leaf_min[s];
+  double ref[3];
+  ref[0] = (double)compact3(key >> 2) / (double)(1ull << bits);
+  ref[1] = (double)compact3(key >> 1) / (double)(1ull << bits);
+  ref[2] = (double)compact3(key) / (double)(1ull << bits);
+  double sx = 0.0, sy = 0.0, sz = 0.0, sw = 0.0;
+  for (uint32_t k = threadIdx.x; k < n; k += kHT) {
+    const uint32_t i = idx[k];
+    const double w = pmass(P, i);
+    sx += w * mimg(coord(P.X, P.fx, i) - ref[0]);
+    sy += w * mimg(coord(P.Y, P.fy, i) - ref[1]);
+    sz += w * mimg(coord(P.Z, P.fz, i) - ref[2]);
+    sw += w;
+  }
+  sx = block_sum(sx, red);
+  sy = block_sum(sy, red);
+  sz = block_sum(sz, red);
+  sw = block_sum(sw, red);
+  if (threadIdx.x == 0) {
+    double c[3];
+    if (sw == 0.0) {
+      for (int d = 0; d < 3; ++d) c[d] = ref[d] + 0.5 / (double)(1ull << bits);
+    } else {
+      c[0] = ref[0] + sx / sw;
+      c[1] = ref[1] + sy / sw;
+      c[2] = ref[2] + sz / sw;
+    }
+    for (int d = 0; d < 3; ++d) centre[3 * s + d] = c[d] - floor(c[d]);
+  }
+}
+
+// the level-0 cells a sphere may touch: per axis the cell range [lo, lo+n)
+// (wrapped), the whole axis when the sphere is at least as wide as the box
+__device__ inline void cube_of(const double* c, double R, int g, int64_t* lo, int64_t* nc) {
+  const int64_t side = 1ll << g;
+  for (int d = 0; d < 3; ++d) {
+    int64_t a = (int64_t)floor((c[d] - R) * (double)side);
+    int64_t b = (int64_t)floor((c[d] + R) * (double)side);
+    if (b - a + 1 >= side) {
+      a = 0;
+      b = side - 1;
+    }
+    lo[d] = a;
+    nc[d] = b - a + 1;
+  }
+}
+
+__device__ inline uint64_t cube_cell(const int64_t* lo, const int64_t* nc, uint64_t k, int g) {
+  const int64_t side = 1ll << g;
+  const int64_t iz = (int64_t)(k % (uint64_t)nc[2]);
+  const int64_t iy = (int64_t)((k / (uint64_t)nc[2]) % (uint64_t)nc[1]);
+  const int64_t ix = (int64_t)(k / ((uint64_t)nc[2] * (uint64_t)nc[1]));
+  const uint32_t x = (uint32_t)(((lo[0] + ix) % side + side) % side);
+  const uint32_t y = (uint32_t)(((lo[1] + iy) % side + side) % side);
+  const uint32_t z = (uint32_t)(((lo[2] + iz) % side + side) % side);
+  return morton3(x, y, z);
+}
+
+// collection radius and an upper bound of the candidates: a host's
+// isodensity patch count; a substructure's sphere (half the distance to its
+// host's centre): the particles of the level-0 cells it may touch
+__global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_depth,
+                                               const int32_t* __restrict__ s_host,
+                                               const double* __restrict__ centre,
+                                               const uint32_t* __restrict__ iso_cnt, int g,
+                                               const uint32_t* __restrict__ count0,
+                                               double* __restrict__ radius,
+                                               uint32_t* __restrict__ bound) {
+  __shared__ double red[kHW];
+  const uint32_t s = blockIdx.x;
+  if (s_depth[s] == 0) {
+    if (threadIdx.x == 0) {
+      radius[s] = 0.0;
+      bound[s] = iso_cnt[s];
+    }
+    return;
+  }
+  const int32_t hh = s_host[s];
+  if (hh < 0) {  // a substructure always has a host; nothing to collect otherwise
+    if (threadIdx.x == 0) {
+      radius[s] = 0.0;
+      bound[s] = 0;
+    }
+    return;
+  }
+  const double* c = centre + 3 * (uint64_t)s;
+  const double* ch = centre + 3 * (uint64_t)hh;
+  const double sx = mimg(c[0] - ch[0]), sy = mimg(c[1] - ch[1]), sz = mimg(c[2] - ch[2]);
+  const double R = 0.5 * sqrt(sx * sx + sy * sy + sz * sz);
+  int64_t lo[3], nc[3];
+  cube_of(c, R, g, lo, nc);
+  const uint64_t ncell = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
+  double t = 0.0;
+  for (uint64_t k = threadIdx.x; k < ncell; k += kHT) t += (double)count0[cube_cell(lo, nc, k, g)];
+  t = block_sum(t, red);
+  if (threadIdx.x == 0) {
+    radius[s] = R;
+    bound[s] = (uint32_t)t;
+  }
+}
+
+// the candidates of every structure, unordered: a host's isodensity list, a
+// substructure's particles within its radius
+__global__ __launch_bounds__(kHT) void k_candidates(
+    const int32_t* __restrict__ s_depth, const double* __restrict__ centre,
+    const double* __restrict__ radius, const uint64_t* __restrict__ iso_off,
+    const uint32_t* __restrict__ iso_cnt, const uint32_t* __restrict__ iso_list, int g,
+    const uint32_t* __restrict__ start0, const uint32_t* __restrict__ count0,
+    const uint32_t* __restrict__ order, PartIn P, const uint64_t* __restrict__ cand_off,
+    uint32_t* __restrict__ cand, uint32_t* __restrict__ cand_cnt) {
+  __shared__ uint32_t cursor;
+  const uint32_t s = blockIdx.x;
+  uint32_t* out = cand + cand_off[s];
+  if (s_depth[s] == 0) {
+    const uint32_t n = iso_cnt[s];
+    const uint32_t* in = iso_list + iso_off[s];
+    for (uint32_t k = threadIdx.x; k < n; k += kHT) out[k] = in[k];
+    if (threadIdx.x == 0) cand_cnt[s] = n;
+    return;
+  }
+  if (threadIdx.x == 0) cursor = 0;
+  __syncthreads();
+  const double* c = centre + 3 * (uint64_t)s;
+  const double R = radius[s];
+  const double R2 = R * R;
+  int64_t lo[3], nc[3];
+  cube_of(c, R, g, lo, nc);
+  const uint64_t ncell = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
+  for (uint64_t k = threadIdx.x; k < ncell; k += kHT) {
+    const uint64_t cell = cube_cell(lo, nc, k, g);
+    const uint32_t a = start0[cell], cnt = count0[cell];
+    for (uint32_t j = 0; j < cnt; ++j) {
+      const uint32_t i = order[a + j];
+      const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
+      const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
+      const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
+      if (dx * dx + dy * dy + dz * dz <= R2) out[atomicAdd(&cursor, 1u)] = i;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) cand_cnt[s] = cursor;
+}
+
+// Unbinding of every structure's candidates.  Scratch per candidate (at the
+// structure's offset): idx_a, idx_b (u32), key_a, key_b (u64), msum, tail
+// (f64).  On exit cand holds the candidates by ascending index, member the
+// halo's particles by ascending index.
+__global__ __launch_bounds__(kHT) void k_unbind(
+    const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ cand_cnt, uint32_t* cand,
+    uint32_t* idx_a, uint32_t* idx_b, uint64_t* key_a, uint64_t* key_b, double* msum,
+    double* tail, const double* __restrict__ centre, PartIn P, double rho_thr, double G,
+    uint32_t max_iter, uint32_t* __restrict__ member, uint32_t* __restrict__ member_cnt,
+    double* __restrict__ r_vir_out, double* __restrict__ m_vir_out, double* __restrict__ vel_out,
+    uint32_t* __restrict__ iters_out) {
+  __shared__ double red[kHW];
+  __shared__ int64_t redi[kHW];
+  __shared__ uint32_t wtot[kHW];
+  const uint32_t s = blockIdx.x;
+  const uint64_t off = cand_off[s];
+  const uint32_t n = cand_cnt[s];
+  uint32_t* cs = cand + off;
+  uint32_t* ia = idx_a + off;
+  uint32_t* ib = idx_b + off;
+  uint64_t* ka = key_a + off;
+  uint64_t* kb = key_b + off;
+  double* M = msum + off;
+  double* T = tail + off;
+  const double* c = centre + 3 * (uint64_t)s;
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+
+  // the candidates by index (the view's order; ties of radius go by index)
+  if (block_sort<uint32_t>(cs, cs, ib, ib, n))
+    for (uint32_t k = threadIdx.x; k < n; k += kHT) cs[k] = ib[k];
+  __syncthreads();
+  // radii (bit patterns of non-negative doubles order like the doubles) and
+  // a stable sort by radius
+  for (uint32_t k = threadIdx.x; k < n; k += kHT) {
+    const uint32_t i = cs[k];
+    const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
+    const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
+    const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r < kHalfQuantum) r = kHalfQuantum;
+    ka[k] = (uint64_t)__double_as_longlong(r);
+    ia[k] = i;
+  }
+  __syncthreads();
+  const bool fl = block_sort<uint64_t>(ka, ia, kb, ib, n);
+  uint64_t* K = fl ? kb : ka;
+  uint32_t* I = fl ? ib : ia;
+
+  uint32_t na = n, iters = 0, nmem = 0;
+  double r_vir = 0.0, m_vir = 0.0;
+  double vh[3] = {0.0, 0.0, 0.0};
+  bool done = false;
+  for (uint32_t it = 1; it <= max_iter && na > 0; ++it) {
+    iters = it;
+    // the halo's velocity: mass-weighted mean
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, sm = 0.0;
+    for (uint32_t k = threadIdx.x; k < na; k += kHT) {
+      const uint32_t i = I[k];
+      const double m = pmass(P, i);
+      s0 += m * (double)P.vx[i];
+      s1 += m * (double)P.vy[i];
+      s2 += m * (double)P.vz[i];
+      sm += m;
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
+    sm = block_sum(sm, red);
+    vh[0] = s0 / sm;
+    vh[1] = s1 / sm;
+    vh[2] = s2 / sm;
+    // enclosed masses along the radii, and the last particle dense enough
+    double carry = 0.0;
+    int64_t v = -1;
+    for (uint32_t c0 = 0; c0 < na; c0 += kHT) {
+      const uint32_t k = c0 + threadIdx.x;
+      const double m = k < na ? pmass(P, I[k]) : 0.0;
+      double tot = 0.0;
+      const double inc = carry + block_scan(m, red, &tot);
+      if (k < na) {
+        M[k] = inc;
+        const double r = __longlong_as_double((long long)K[k]);
+        const double dens = inc / (4.0 / 3.0 * M_PI * (r * r * r));
+        if (dens >= rho_thr) v = (int64_t)k;
+      }
+      carry += tot;
+    }
+    v = block_max_i64(v, redi);
+    if (v < 0) {  // never dense enough: the halo dissolves
+      na = 0;
+      r_vir = 0.0;
+      m_vir = 0.0;
+      done = true;
+      break;
+    }
+    __syncthreads();
+    const double rv = __longlong_as_double((long long)K[v]);
+    const double mv = M[v];
+    // tail[k] = sum over j in [k, v) of M_j (1/r_j - 1/r_{j+1}), chunks from the end
+    double tcarry = 0.0;
+    const uint32_t nv = (uint32_t)v;  // terms 0 .. v-1
+    for (int64_t c1 = (int64_t)nv; c1 > 0; c1 -= kHT) {
+      // this chunk covers [c1 - kHT, c1), thread t takes k = c1 - 1 - t
+      const int64_t k = c1 - 1 - (int64_t)threadIdx.x;
+      double term = 0.0;
+      if (k >= 0) {
+        const double r0 = __longlong_as_double((long long)K[k]);
+        const double r1 = __longlong_as_double((long long)K[k + 1]);
+        term = M[k] * (1.0 / r0 - 1.0 / r1);
+      }
+      double tot = 0.0;
+      const double inc = tcarry + block_scan(term, red, &tot);
+      if (k >= 0) T[k] = inc;
+      tcarry += tot;
+    }
+    __syncthreads();
+    // the unbound particles, then the others kept in radius order
+    uint32_t kept = 0;
+    uint32_t ngone = 0;
+    for (uint32_t c0 = 0; c0 < na; c0 += kHT) {
+      const uint32_t k = c0 + threadIdx.x;
+      bool gone = false;
+      uint64_t key = 0;
+      uint32_t i = 0;
+      if (k < na) {
+        key = K[k];
+        i = I[k];
+        const double r = __longlong_as_double((long long)key);
+        const double phi = (int64_t)k <= v ? -G * ((k < nv ? T[k] : 0.0) + mv / rv) : -G * mv / r;
+        const double dx = (double)P.vx[i] - vh[0];
+        const double dy = (double)P.vy[i] - vh[1];
+        const double dz = (double)P.vz[i] - vh[2];
+        const double ke = 0.5 * (dx * dx + dy * dy + dz * dz);
+        gone = ke > fabs(phi);
+      }
+      const bool keep = k < na && !gone;
+      const uint64_t kb_ = __ballot(keep);
+      const uint64_t gb_ = __ballot(gone);
+      __syncthreads();
+      if (lane == 0) wtot[w] = (uint32_t)__popcll(kb_);
+      __syncthreads();
+      uint32_t before = 0, all = 0;
+      for (int j = 0; j < kHW; ++j) {
+        if (j < w) before += wtot[j];
+        all += wtot[j];
+      }
+      // writes land at or before the reads of this chunk, which are done
+      if (keep) {
+        const uint32_t at = kept + before + (uint32_t)__popcll(kb_ & lanes_below());
+        K[at] = key;
+        I[at] = i;
+      }
+      kept += all;
+      // count the unbound ones (every wave adds its own, in wave order)
+      __syncthreads();
+      if (lane == 0) wtot[w] = (uint32_t)__popcll(gb_);
+      __syncthreads();
+      for (int j = 0; j < kHW; ++j) ngone += wtot[j];
+      __syncthreads();
+    }
+    if (ngone == 0) {
+      // converged: the particles within r_vir (the first v+1 in radius order)
+      nmem = (uint32_t)v + 1;
+      r_vir = rv;
+      done = true;
+      break;
+    }
+    na = kept;
+    __syncthreads();
+  }
+  if (!done) {  // not converged within max_iter (or nothing collected)
+    nmem = 0;
+    r_vir = 0.0;
+  }
+  // the members by index: the first nmem of I, sorted by particle index
+  uint32_t* out = member + off;
+  for (uint32_t k = threadIdx.x; k < nmem; k += kHT) out[k] = I[k];
+  __syncthreads();
+  uint32_t* spare = (I == ia) ? ib : ia;
+  if (block_sort<uint32_t>(out, out, spare, spare, nmem))
+    for (uint32_t k = threadIdx.x; k < nmem; k += kHT) out[k] = spare[k];
+  __syncthreads();
+  double mm = 0.0;
+  for (uint32_t k = threadIdx.x; k < nmem; k += kHT) mm += pmass(P, out[k]);
+  mm = block_sum(mm, red);
+  m_vir = nmem ? mm : 0.0;
+  if (threadIdx.x == 0) {
+    member_cnt[s] = nmem;
+    r_vir_out[s] = r_vir;
+    m_vir_out[s] = m_vir;
+    vel_out[3 * s + 0] = vh[0];
+    vel_out[3 * s + 1] = vh[1];
+    vel_out[3 * s + 2] = vh[2];
+    iters_out[s] = iters;
+  }
+}
+
+}  // namespace
+
+// the halo set of one hierarchy: device arrays in an arena of the context
+struct Halos {
+  Owned mem;
+  uint64_t n = 0;
+  unsigned long long* leafkey = nullptr;
+  double *centre = nullptr, *radius = nullptr, *r_vir = nullptr, *m_vir = nullptr,
+         *vel = nullptr;
+  uint64_t* cand_off = nullptr;
+  uint32_t *cand_cnt = nullptr, *cand = nullptr, *member_cnt = nullptr, *member = nullptr,
+           *iters = nullptr;
+};
+
+static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, const float* vx,
+                       const float* vy, const float* vz, double delta_vir, double G,
+                       uint32_t max_iter, hipStream_t st, Halos* out) {
+  const uint64_t ns = h->nStruct;
+  const size_t nlev = h->lev.size();
+  out->n = ns;
+  Owned& mem = out->mem;
+  out->leafkey = mem.get<unsigned long long>(ns);
+  out->centre = mem.get<double>(3 * ns);
+  out->radius = mem.get<double>(ns);
+  out->r_vir = mem.get<double>(ns);
+  out->m_vir = mem.get<double>(ns);
+  out->vel = mem.get<double>(3 * ns);
+  out->cand_off = mem.get<uint64_t>(ns + 1);
+  out->cand_cnt = mem.get<uint32_t>(ns);
+  out->member_cnt = mem.get<uint32_t>(ns);
+  out->iters = mem.get<uint32_t>(ns);
+  if (ns == 0) {
+    k_fill_u64<<<1, kHB, 0, st>>>(out->cand_off, 1, 0);
+    HIP_LAUNCH_CHECK();
+    out->cand = mem.get<uint32_t>(1);
+    out->member = mem.get<uint32_t>(1);
+    return;
+  }
+  const uint64_t n = h->n;
+  PartIn P{p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass, p.mass_scalar, vx, vy, vz};
+  unsigned long long* leaf_min = ws.get<unsigned long long>(ns);
+  uint32_t* leaf_cnt = ws.get<uint32_t>(ns);
+  uint32_t* iso_cnt = ws.get<uint32_t>(ns);
+  int32_t* iso_patch = ws.get<int32_t>(ns);
+  int32_t* iso_level = ws.get<int32_t>(ns);
+  uint64_t* leaf_off = ws.get<uint64_t>(ns + 1);
+  uint64_t* iso_off = ws.get<uint64_t>(ns + 1);
+  uint32_t* bound = ws.get<uint32_t>(ns);
+  uint32_t* leaf_list = ws.get<uint32_t>(n ? n : 1);
+  uint32_t* leaf_tmp = ws.get<uint32_t>(n ? n : 1);
+  uint32_t* iso_list = ws.get<uint32_t>(n ? n : 1);
+  k_fill_u64<<<blocks_for(ns), kHB, 0, st>>>(reinterpret_cast<uint64_t*>(out->leafkey), ns, 0);
+  k_fill_u64<<<blocks_for(ns), kHB, 0, st>>>(reinterpret_cast<uint64_t*>(leaf_min), ns, ~0ull);
+  k_fill_u32<<<blocks_for(ns), kHB, 0, st>>>(leaf_cnt, ns, 0);
+  k_fill_u32<<<blocks_for(ns), kHB, 0, st>>>(iso_cnt, ns, 0);
+  k_fill_u32<<<blocks_for(ns), kHB, 0, st>>>(reinterpret_cast<uint32_t*>(iso_patch), ns, ~0u);
+  k_fill_u32<<<blocks_for(ns), kHB, 0, st>>>(reinterpret_cast<uint32_t*>(iso_level), ns, ~0u);
+  HIP_LAUNCH_CHECK();
+  // leaves, then the hosts' isodensity patches: bit L of isomask when the
+  // boundary contour of level-L patches lies below delta_vir * rho_b
+  for (size_t L = 1; L < nlev; ++L) {
+    const Level& lv = h->lev[L];
+    if (!lv.nPatch) continue;
+    k_leaf<<<blocks_for(lv.nPatch), kHB, 0, st>>>((int)L, lv.patch_struct, lv.nPatch,
+                                                  out->leafkey);
+    HIP_LAUNCH_CHECK();
+  }
+  uint32_t isomask = 0;
+  for (size_t L = 1; L < nlev && L < 32; ++L) {
+    const double thr = (L - 1 == 0) ? h->prm.dom_ref : h->prm.ref_ref;
+    const double rho = thr * std::pow(8.0, (double)(L - 1)) * std::pow(2.0, 3.0 * h->prm.g) /
+                       (double)n;
+    if (rho < delta_vir) isomask |= 1u << L;
+  }
+  for (size_t L = 1; L < nlev; ++L) {
+    const Level& lv = h->lev[L];
+    if (!lv.nPatch) continue;
+    k_iso<<<blocks_for(lv.nPatch), kHB, 0, st>>>((int)L, lv.patch_struct, lv.nPatch, h->s_depth,
+                                                 h->s_level, out->leafkey, isomask, iso_patch,
+                                                 iso_level);
+    HIP_LAUNCH_CHECK();
+  }
+  // the particle lists of the leaf and isodensity patches: counts, offsets,
+  // then the lists (cursor order)
+  for (int fill = 0; fill < 2; ++fill) {
+    if (fill) {
+      k_offsets<<<1, kHT, 0, st>>>(leaf_cnt, ns, leaf_off);
+      k_offsets<<<1, kHT, 0, st>>>(iso_cnt, ns, iso_off);
+      k_fill_u32<<<blocks_for(ns), kHB, 0, st>>>(leaf_cnt, ns, 0);
+      k_fill_u32<<<blocks_for(ns), kHB, 0, st>>>(iso_cnt, ns, 0);
+      HIP_LAUNCH_CHECK();
+    }
+    for (size_t L = 1; L < nlev; ++L) {
+      const Level& lv = h->lev[L];
+      if (!lv.nS || !lv.nPatch) continue;
+      k_patch_lists<<<blocks_for(lv.nS), kHB, 0, st>>>(
+          (int)L, lv.nS, lv.nPatch, lv.Skey, lv.Sstart, lv.Scount, lv.Spatch, lv.patch_struct,
+          out->leafkey,
+          iso_patch, iso_level, h->order, leaf_cnt, leaf_min, iso_cnt, fill, leaf_off, leaf_list,
+          iso_off, iso_list);
+      HIP_LAUNCH_CHECK();
+    }
+  }
+  const Level& l0 = h->lev[0];
+  k_centre<<<(unsigned)ns, kHT, 0, st>>>(leaf_off, leaf_cnt, leaf_list, leaf_tmp, out->leafkey,
+                                         leaf_min, h->prm.g, P, out->centre);
+  HIP_LAUNCH_CHECK();
+  k_bound<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, h->s_host, out->centre, iso_cnt, h->prm.g,
+                                        l0.Scount, out->radius, bound);
+  HIP_LAUNCH_CHECK();
+  k_offsets<<<1, kHT, 0, st>>>(bound, ns, out->cand_off);
+  HIP_LAUNCH_CHECK();
+  uint64_t total = 0;
+  HIP_CHECK(hipMemcpyAsync(&total, out->cand_off + ns, sizeof(uint64_t), hipMemcpyDeviceToHost,
+                           st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  const uint64_t t1 = total ? total : 1;
+  out->cand = mem.get<uint32_t>(t1);
+  out->member = mem.get<uint32_t>(t1);
+  uint32_t* idx_a = ws.get<uint32_t>(t1);
+  uint32_t* idx_b = ws.get<uint32_t>(t1);
+  uint64_t* key_a = ws.get<uint64_t>(t1);
+  uint64_t* key_b = ws.get<uint64_t>(t1);
+  double* msum = ws.get<double>(t1);
+  double* tail = ws.get<double>(t1);
+  k_candidates<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
+                                             iso_cnt, iso_list, h->prm.g, l0.Sstart, l0.Scount,
+                                             h->order, P, out->cand_off, out->cand,
+                                             out->cand_cnt);
+  HIP_LAUNCH_CHECK();
+  const double rho_b = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
+  k_unbind<<<(unsigned)ns, kHT, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, idx_a, idx_b,
+                                         key_a, key_b, msum, tail, out->centre, P,
+                                         delta_vir * rho_b, G, max_iter, out->member,
+                                         out->member_cnt, out->r_vir, out->m_vir, out->vel,
+                                         out->iters);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+}  // namespace ahf
+
+struct ahf_halos {
+  ahf::Halos h;
+};
+
+extern "C" {
+
+ahf_status ahf_find_halos(ahf_ctx* ctx, const ahf_hierarchy* h, const ahf_particles* p,
+                          const float* vx, const float* vy, const float* vz,
+                          const ahf_halo_params* prm, void* stream, ahf_halos** out) {
+  using namespace ahf;
+  if (!out) {
+    set_last_error("out is NULL");
+    return AHF_EINVAL;
+  }
+  *out = nullptr;
+  if (!ctx || !h || !p || !vx || !vy || !vz || !prm || prm->struct_size < sizeof(ahf_halo_params)) {
+    set_last_error("ctx, h, particles, velocities and params are required");
+    return AHF_EINVAL;
+  }
+  if (!h->h.classified) {
+    set_last_error("the hierarchy is not classified (AHF_SUBSTRUCTURE or ahf_classify_substructure)");
+    return AHF_EINVAL;
+  }
+  if (p->n != h->h.n || !p->x || !p->y || !p->z) {
+    set_last_error("the particles are not those of the hierarchy");
+    return AHF_EINVAL;
+  }
+  if (!(prm->delta_vir > 0.0) || !(prm->G > 0.0) || prm->max_iter == 0) {
+    set_last_error("delta_vir and G must be positive, max_iter at least 1");
+    return AHF_EINVAL;
+  }
+  ahf_halos* r = new (std::nothrow) ahf_halos();
+  if (!r) {
+    set_last_error("host allocation failed");
+    return AHF_ENOMEM;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  r->h.mem.ctx = &ctx->c;
+  r->h.mem.st = st;
+  try {
+    HIP_CHECK(hipSetDevice(ctx->c.device));
+    ctx->ws.bind(&ctx->c, st);
+    ctx->ws.reset();
+    find_halos(&ctx->c, ctx->ws, &h->h, *p, vx, vy, vz, prm->delta_vir, prm->G, prm->max_iter, st,
+               &r->h);
+    ctx->ws.reset();
+  } catch (const Error& e) {
+    (void)hipStreamSynchronize(st);
+    ctx->ws.reset();
+    r->h.mem.release_all();
+    delete r;
+    set_last_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(st);
+    ctx->ws.reset();
+    r->h.mem.release_all();
+    delete r;
+    set_last_error("host allocation failed");
+    return AHF_ENOMEM;
+  }
+  *out = r;
+  return AHF_OK;
+}
+
+ahf_status ahf_halos_get(const ahf_halos* hs, ahf_halos_view* v) {
+  if (!hs || !v) {
+    ahf::set_last_error("bad arguments");
+    return AHF_EINVAL;
+  }
+  const ahf::Halos& h = hs->h;
+  v->n_halos = h.n;
+  v->leaf = reinterpret_cast<const uint64_t*>(h.leafkey);
+  v->centre = h.centre;
+  v->radius = h.radius;
+  v->cand_offset = h.cand_off;
+  v->cand_count = h.cand_cnt;
+  v->cand = h.cand;
+  v->member_count = h.member_cnt;
+  v->member = h.member;
+  v->r_vir = h.r_vir;
+  v->m_vir = h.m_vir;
+  v->vel = h.vel;
+  v->iterations = h.iters;
+  return AHF_OK;
+}
+
+void ahf_halos_free(ahf_halos* hs) {
+  if (!hs) return;
+  hs->h.mem.release_all();
+  delete hs;
+}
+
+}  // extern "C"

@@ -113,7 +113,16 @@ def test_unbinding_edge_cases():
     rng = np.random.Generator(np.random.PCG64(3))
     pos = rng.random((50, 3))
     out = H.unbind(np.arange(50), pos, np.zeros((50, 3)), np.ones(50), c, 50.0)
-    assert out["members"].size == 0
+    assert out["members"].size == 0 and out["r_vir"] == 0.0 and out["m_vir"] == 0.0
+    # not converged within max_iter: no particles either (the cascade needs 3)
+    M0, M1, r1, r2, mt = 1.0e4, 1.0e4, 0.005, 0.01, 1e-12
+    u = 10 * math.sqrt(2.0 * (M0 + M1) / r1)
+    vt = math.sqrt(2.0 * (M0 + 0.5 * M1) / r2)
+    pos = np.array([c, c + [r1, 0, 0], c - [r1, 0, 0], c + [0, r2, 0]])
+    vel = np.array([[0, 0, 0], [0, u, 0], [0, -u, 0], [0, 0, vt]], np.float64)
+    out = H.unbind([0, 1, 2, 3], pos, vel, np.array([M0, M1 / 2, M1 / 2, mt]), c, 1.0,
+                   max_iter=2)
+    assert out["members"].size == 0 and out["iterations"] == 2 and out["r_vir"] == 0.0
 
 
 def test_isodensity_levels_of_the_workloads():
