@@ -504,6 +504,28 @@ def measure(ctx, snap, dev, stream, steps, warmup, extras=True):
         dens_levels = h.num_levels()
         h.free()
     out["substructure"] = {"ms": float(np.median(cls)), "structures": int(nstruct)}
+    # particle collection and unbinding of every structure (needs velocities)
+    if snap.vel is not None:
+        vel = torch.from_numpy(snap.vel).to("cuda")
+        h = step()
+        h.classify(ctx, stream)
+        hal = []
+        for i in range(3):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            res = ahf.find_halos(ctx, h, dev, vel, stream=stream, fetch=False)
+            torch.cuda.synchronize()
+            hal.append((time.perf_counter() - a) * 1e3)
+        h.free()
+        del vel
+        cand = int(res["cand_count"].astype(np.int64).sum())
+        out["halos"] = {"ms": float(np.median(hal)), "halos": int(res["n_halos"]),
+                        "with_particles": int((res["member_count"] > 0).sum()),
+                        "candidates": cand,
+                        "members": int(res["member_count"].astype(np.int64).sum()),
+                        "max_rounds": int(res["iterations"].max()) if res["n_halos"] else 0,
+                        "candidates_per_s": cand / (float(np.median(hal)) * 1e-3)}
+        print(f"# {snap.name}: halos {np.median(hal):.2f} ms", file=sys.stderr, flush=True)
     out["density_criterion"] = {"ms_per_build": float(np.median(dens[1:])),
                                 "levels_built": int(dens_levels)}
     return out
@@ -547,15 +569,15 @@ def main():
     import torch
     from paper_0904_3662_amd import ahf, synth
 
-    def make(w):
+    def make(w, velocities=False):
         fn, seed = WORKLOADS[w]
         t0 = time.perf_counter()
-        sn = getattr(synth, fn)(seed)
+        sn = getattr(synth, fn)(seed, velocities=velocities)
         print(f"# generated {sn.name}: {sn.n} particles in {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
         return sn
 
-    snap = make(args.workload)
+    snap = make(args.workload, velocities=True)  # velocities for the halo step
     torch.cuda.set_device(0)
     ctx = ahf.Context(0)
     stream = torch.cuda.current_stream()

@@ -34,7 +34,13 @@ Readings taken here (the paper leaves them open):
   start patch when none is;
 - H4 a substructure collects every particle within half the distance to its
   host's centre (host = the structure it is a substructure of), periodic
-  minimum image, distance <= radius;
+  minimum image, distance <= radius, the radius capped by the extent of the
+  isolated grid that started the substructure (its start patch): the largest
+  distance from the centre to a corner of one of that patch's cells.  (Where
+  the background itself refines, the host of a first-level substructure is the
+  box-spanning background grid, whose centre can lie anywhere; the paper's
+  first collection step takes the particles on a halo's own isolated grids,
+  and the cap keeps the sphere on them);
 - H5 per iteration: the halo velocity is the mass-weighted mean velocity of
   its current particles; radii are measured from the fixed centre (clamped
   below at half a position quantum); the particles are ordered by radius,
@@ -123,6 +129,22 @@ def centre_of(levels, order, pos, mass, L: int, q: int) -> np.ndarray:
     else:
         c = ref + (w[:, None] * d).sum(axis=0) / w.sum()
     return c - np.floor(c)
+
+
+def patch_extent(levels, L: int, q: int, centre) -> float:
+    """H4: the largest distance from the centre to a corner of a cell of
+    patch q of level L (per axis the farther of the cell's two faces, periodic
+    minimum image)."""
+    lv = levels[L]
+    h = 1.0 / float(1 << lv.bits)
+    ext = 0.0
+    for c in np.nonzero(lv.cell_patch == q)[0]:
+        lo = cell_corner(int(lv.cell_key[c]), lv.bits)
+        a = np.abs(min_image(lo - centre))
+        b = np.abs(min_image(lo + h - centre))
+        d = np.maximum(a, b)
+        ext = max(ext, float(np.sqrt((d * d).sum())))
+    return ext
 
 
 def iso_level(start: int, leaf_level: int, thr_dom: float, thr_ref: float, g: int,
@@ -224,6 +246,8 @@ def halos(p, levels, order, patch_struct, structs, delta_vir=340.0, G=1.0, max_i
             h = int(structs["host"][s])
             sep = min_image(centres[s] - centres[h])
             radius = 0.5 * float(np.sqrt((sep * sep).sum()))
+            ext = patch_extent(levels, start, int(structs["patch"][s]), centres[s])
+            radius = min(radius, ext)
             d = min_image(pos - centres[s])
             cand = np.nonzero((d * d).sum(axis=1) <= radius * radius)[0].astype(np.int64)
         u = unbind(cand, pos, vel, mass, centres[s], rho_b, delta_vir, G, max_iter)

@@ -667,11 +667,12 @@ class Batch:
 
 
 def find_halos(ctx: Context, h: Hierarchy, dev, vel, delta_vir: float = 340.0, G: float = 1.0,
-               max_iter: int = 1000, stream=None) -> dict:
+               max_iter: int = 1000, stream=None, fetch: bool = True) -> dict:
     """Particle collection and unbinding of every structure of a classified
     hierarchy (ahf_find_halos); dev holds the particle tensors the hierarchy
     was built from, vel the (n, 3) velocities on the device.  Returns the
-    halos as numpy arrays (the device result is freed)."""
+    halos as numpy arrays (the device result is freed); without fetch only
+    the per-halo counts and rounds."""
     vel = vel.contiguous()
     vx, vy, vz = (vel[:, k].contiguous() for k in range(3))
     parts = make_particles(*dev[:6], dev[6])
@@ -684,6 +685,11 @@ def find_halos(ctx: Context, h: Hierarchy, dev, vel, delta_vir: float = 340.0, G
         _check(load().ahf_halos_get(out, C.byref(v)))
         n = int(v.n_halos)
         res = {"n_halos": n}
+        if not fetch:
+            res["cand_count"] = to_host(v.cand_count, n, np.uint32)
+            res["member_count"] = to_host(v.member_count, n, np.uint32)
+            res["iterations"] = to_host(v.iterations, n, np.uint32)
+            return res
         res["leaf"] = to_host(v.leaf, n, np.uint64)
         res["centre"] = to_host(v.centre, 3 * n, np.float64).reshape(n, 3)
         res["radius"] = to_host(v.radius, n, np.float64)

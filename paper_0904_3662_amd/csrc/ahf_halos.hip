@@ -32,6 +32,7 @@
 #include <cmath>
 #include <vector>
 
+#include "ahf_block.h"
 #include "ahf_internal.h"
 
 // the FP64 arithmetic of the distance and energy tests is done as written
@@ -41,8 +42,8 @@
 namespace ahf {
 namespace {
 
-constexpr int kHT = 256;             // threads per workgroup of the per-halo kernels
-constexpr int kHW = kHT / 64;        // waves per workgroup
+constexpr int kHT = kBT;             // threads per workgroup of the per-halo kernels
+constexpr int kHW = kBW;             // waves per workgroup
 constexpr int kHB = 256;             // threads per block of the per-cell kernels
 constexpr double kQuantum = 1.0 / (double)(1u << kQBits);
 constexpr double kHalfQuantum = 0.5 / (double)(1u << kQBits);
@@ -65,177 +66,20 @@ unsigned blocks_for(uint64_t n, int t = kHB) {
   return (unsigned)b;
 }
 
-// ---------------------------------------------------------------- block primitives
-// (kHT threads; every thread of the workgroup calls them)
-
-__device__ inline uint64_t lanes_below() {
-  const uint32_t lane = __lane_id();
-  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// sum over the workgroup in a fixed order (wave butterflies, then waves in order)
-__device__ double block_sum(double x, double* red) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if (__lane_id() == 0) red[w] = x;
-  __syncthreads();
-  double t = 0.0;
-  for (int i = 0; i < kHW; ++i) t += red[i];
-  return t;
-}
-
-__device__ uint64_t block_or(uint64_t x, uint64_t* red) {
-  for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if (__lane_id() == 0) red[w] = x;
-  __syncthreads();
-  uint64_t t = 0;
-  for (int i = 0; i < kHW; ++i) t |= red[i];
-  return t;
-}
-
-__device__ uint64_t block_and(uint64_t x, uint64_t* red) {
-  for (int o = 32; o > 0; o >>= 1) x &= __shfl_xor(x, o);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if (__lane_id() == 0) red[w] = x;
-  __syncthreads();
-  uint64_t t = ~0ull;
-  for (int i = 0; i < kHW; ++i) t &= red[i];
-  return t;
-}
-
-__device__ int64_t block_max_i64(int64_t x, int64_t* red) {
-  for (int o = 32; o > 0; o >>= 1) {
-    const int64_t y = __shfl_xor(x, o);
-    x = y > x ? y : x;
-  }
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if (__lane_id() == 0) red[w] = x;
-  __syncthreads();
-  int64_t t = red[0];
-  for (int i = 1; i < kHW; ++i) t = red[i] > t ? red[i] : t;
-  return t;
-}
-
-// inclusive scan of one value per thread over the workgroup, in thread
-// order; returns the thread's prefix and sets *total
-__device__ double block_scan(double x, double* red, double* total) {
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  for (int o = 1; o < 64; o <<= 1) {
-    const double y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  __syncthreads();
-  if (lane == 63) red[w] = x;
-  __syncthreads();
-  double before = 0.0, all = 0.0;
-  for (int i = 0; i < kHW; ++i) {
-    if (i < w) before += red[i];
-    all += red[i];
-  }
-  *total = all;
-  return before + x;
-}
-
-// Stable LSD radix sort of n (key, val) pairs of a segment: the pairs are in
-// (ka, va); kb, vb are as large.  Digits of 8 bits; a digit that every key
-// shares is skipped.  Returns true when the result is in (kb, vb).
-template <class K>
-__device__ bool block_sort(K* ka, uint32_t* va, K* kb, uint32_t* vb, uint32_t n) {
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t wcnt[kHW][256];
-  __shared__ uint64_t red[kHW];
-  uint64_t o = 0, a = ~0ull;
-  for (uint32_t i = threadIdx.x; i < n; i += kHT) {
-    o |= (uint64_t)ka[i];
-    a &= (uint64_t)ka[i];
-  }
-  const uint64_t any = block_or(o, red);
-  const uint64_t all = block_and(a, red);
-  const uint64_t vary = any ^ all;
-  bool flipped = false;
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  for (int p = 0; p < (int)sizeof(K); ++p) {
-    if (((vary >> (8 * p)) & 255u) == 0) continue;  // same digit everywhere
-    K* src = flipped ? kb : ka;
-    uint32_t* sv = flipped ? vb : va;
-    K* dst = flipped ? ka : kb;
-    uint32_t* dv = flipped ? va : vb;
-    // digit counts, then each digit's first slot
-    hist[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += kHT)
-      atomicAdd(&hist[((uint64_t)src[i] >> (8 * p)) & 255u], 1u);
-    __syncthreads();
-    {
-      const uint32_t c = hist[threadIdx.x];
-      uint32_t x = c;
-      for (int s = 1; s < 64; s <<= 1) {
-        const uint32_t y = __shfl_up(x, s);
-        if (lane >= s) x += y;
-      }
-      __shared__ uint32_t wt[kHW];
-      if (lane == 63) wt[w] = x;
-      __syncthreads();
-      uint32_t before = 0;
-      for (int i = 0; i < w; ++i) before += wt[i];
-      run[threadIdx.x] = before + x - c;  // exclusive: the digit's first slot
-    }
-    __syncthreads();
-    // chunks of kHT in order; within a chunk, ranks by thread order
-    for (uint32_t c0 = 0; c0 < n; c0 += kHT) {
-      const uint32_t i = c0 + threadIdx.x;
-      const bool valid = i < n;
-      K key = valid ? src[i] : K(0);
-      const uint32_t val = valid ? sv[i] : 0u;
-      const uint32_t d = (uint32_t)(((uint64_t)key >> (8 * p)) & 255u);
-      // lanes of this wave with the same digit
-      uint64_t peer = __ballot(valid);
-      for (int bit = 0; bit < 8; ++bit) {
-        const bool on = (d >> bit) & 1u;
-        const uint64_t bm = __ballot(on);
-        peer &= on ? bm : ~bm;
-      }
-      for (int j = threadIdx.x; j < kHW * 256; j += kHT) (&wcnt[0][0])[j] = 0;
-      __syncthreads();
-      const uint32_t rank = (uint32_t)__popcll(peer & lanes_below());
-      if (valid && (peer & lanes_below()) == 0ull) wcnt[w][d] = (uint32_t)__popcll(peer);
-      __syncthreads();
-      if (valid) {
-        uint32_t before = 0;
-        for (int k = 0; k < w; ++k) before += wcnt[k][d];
-        const uint32_t dest = run[d] + before + rank;
-        dst[dest] = key;
-        dv[dest] = val;
-      }
-      __syncthreads();
-      {
-        uint32_t t = 0;
-        for (int k = 0; k < kHW; ++k) t += wcnt[k][threadIdx.x];
-        run[threadIdx.x] += t;
-      }
-      __syncthreads();
-    }
-    flipped = !flipped;
-  }
-  return flipped;
-}
+// periodic minimum image of a displacement in the unit box
+__device__ inline double mimg(double d) { return d - rint(d); }
 
 // ---------------------------------------------------------------- leaves and patch lists
 
 // leafkey[s] = max over the patches of structure s of (level << 32 | patch)
 __global__ void k_leaf(int L, const int32_t* __restrict__ pstruct, uint64_t npatch,
                        unsigned long long* __restrict__ leafkey) {
-  const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (q >= npatch) return;
-  const int32_t s = pstruct[q];
-  if (s < 0) return;
-  atomicMax(&leafkey[s], ((unsigned long long)L << 32) | (unsigned long long)q);
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < npatch;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    const int32_t s = pstruct[q];
+    if (s < 0) continue;
+    atomicMax(&leafkey[s], ((unsigned long long)L << 32) | (unsigned long long)q);
+  }
 }
 
 // the isodensity patch of every host: its main-branch patch on the deepest
@@ -245,18 +89,19 @@ __global__ void k_iso(int L, const int32_t* __restrict__ pstruct, uint64_t npatc
                       const int32_t* __restrict__ s_depth, const int32_t* __restrict__ s_level,
                       const unsigned long long* __restrict__ leafkey, uint32_t isomask,
                       int32_t* __restrict__ iso_patch, int32_t* __restrict__ iso_level) {
-  const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (q >= npatch) return;
-  const int32_t s = pstruct[q];
-  if (s < 0 || s_depth[s] != 0) return;
-  const int start = s_level[s];
-  const int leafL = (int)(leafkey[s] >> 32);
-  int li = start;
-  for (int l = start; l <= leafL; ++l)
-    if ((isomask >> l) & 1u) li = l;
-  if (li == L) {
-    iso_patch[s] = (int32_t)q;
-    iso_level[s] = L;
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < npatch;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    const int32_t s = pstruct[q];
+    if (s < 0 || s_depth[s] != 0) continue;
+    const int start = s_level[s];
+    const int leafL = (int)(leafkey[s] >> 32);
+    int li = start;
+    for (int l = start; l <= leafL; ++l)
+      if ((isomask >> l) & 1u) li = l;
+    if (li == L) {
+      iso_patch[s] = (int32_t)q;
+      iso_level[s] = L;
+    }
   }
 }
 
@@ -278,32 +123,65 @@ __global__ void k_patch_lists(int L, uint64_t nS, uint64_t npatch, const uint64_
                               const uint64_t* __restrict__ leaf_off,
                               uint32_t* __restrict__ leaf_list,
                               const uint64_t* __restrict__ iso_off, uint32_t* __restrict__ iso_list) {
-  const uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-  if (c >= nS) return;
-  const int32_t q = Spatch[c];
-  if (q < 0 || (uint64_t)q >= npatch) return;
-  const int32_t s = pstruct[q];
-  if (s < 0) return;
-  const uint32_t cnt = Scount[c];
-  const bool is_leaf = leafkey[s] == (((unsigned long long)L << 32) | (unsigned long long)q);
-  const bool is_iso = iso_level[s] == L && iso_patch[s] == q;
-  if (!is_leaf && !is_iso) return;
-  if (!fill) {
-    if (is_leaf) {
-      atomicAdd(&leaf_cnt[s], cnt);
-      atomicMin(&leaf_min[s], (unsigned long long)Skey[c]);
+  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nS;
+       c += (uint64_t)gridDim.x * blockDim.x) {
+    const int32_t q = Spatch[c];
+    if (q < 0 || (uint64_t)q >= npatch) continue;
+    const int32_t s = pstruct[q];
+    if (s < 0) continue;
+    const uint32_t cnt = Scount[c];
+    const bool is_leaf = leafkey[s] == (((unsigned long long)L << 32) | (unsigned long long)q);
+    const bool is_iso = iso_level[s] == L && iso_patch[s] == q;
+    if (!is_leaf && !is_iso) continue;
+    if (!fill) {
+      if (is_leaf) {
+        atomicAdd(&leaf_cnt[s], cnt);
+        atomicMin(&leaf_min[s], (unsigned long long)Skey[c]);
+      }
+      if (is_iso) atomicAdd(&iso_cnt[s], cnt);
+      continue;
     }
-    if (is_iso) atomicAdd(&iso_cnt[s], cnt);
-    return;
+    const uint32_t a = Sstart[c];
+    if (is_leaf && cnt) {
+      const uint32_t at = atomicAdd(&leaf_cnt[s], cnt);
+      for (uint32_t j = 0; j < cnt; ++j) leaf_list[leaf_off[s] + at + j] = order[a + j];
+    }
+    if (is_iso && cnt) {
+      const uint32_t at = atomicAdd(&iso_cnt[s], cnt);
+      for (uint32_t j = 0; j < cnt; ++j) iso_list[iso_off[s] + at + j] = order[a + j];
+    }
   }
-  const uint32_t a = Sstart[c];
-  if (is_leaf && cnt) {
-    const uint32_t at = atomicAdd(&leaf_cnt[s], cnt);
-    for (uint32_t j = 0; j < cnt; ++j) leaf_list[leaf_off[s] + at + j] = order[a + j];
-  }
-  if (is_iso && cnt) {
-    const uint32_t at = atomicAdd(&iso_cnt[s], cnt);
-    for (uint32_t j = 0; j < cnt; ++j) iso_list[iso_off[s] + at + j] = order[a + j];
+}
+
+// the extent of every substructure's start patch: the largest distance from
+// its centre to a corner of one of the patch's cells (per axis the farther
+// face, periodic minimum image); non-negative doubles order like their bit
+// patterns, so an integer maximum keeps the largest exactly, in any order
+__global__ void k_extent(int L, int bits, uint64_t nS, uint64_t npatch,
+                         const uint64_t* __restrict__ Skey, const int32_t* __restrict__ Spatch,
+                         const int32_t* __restrict__ pstruct, const int32_t* __restrict__ s_depth,
+                         const int32_t* __restrict__ s_level, const int32_t* __restrict__ s_patch,
+                         const double* __restrict__ centre, unsigned long long* __restrict__ ext) {
+  const double h = 1.0 / (double)(1ull << bits);
+  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nS;
+       c += (uint64_t)gridDim.x * blockDim.x) {
+    const int32_t q = Spatch[c];
+    if (q < 0 || (uint64_t)q >= npatch) continue;
+    const int32_t s = pstruct[q];
+    if (s < 0 || s_depth[s] == 0 || s_level[s] != L || s_patch[s] != q) continue;
+    const uint64_t key = Skey[c];
+    const uint32_t ix[3] = {compact3(key >> 2), compact3(key >> 1), compact3(key)};
+    double dd[3];
+    for (int k = 0; k < 3; ++k) {
+      const double ck = centre[3 * (uint64_t)s + k];
+      const double lo = (double)ix[k] / (double)(1ull << bits);
+      const double a = fabs(mimg(lo - ck));
+      const double hi = lo + h;
+      const double b = fabs(mimg(hi - ck));
+      dd[k] = a > b ? a : b;
+    }
+    const double e = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+    atomicMax(&ext[s], (unsigned long long)__double_as_longlong(e));
   }
 }
 
@@ -339,7 +217,6 @@ struct PartIn {
 __device__ inline double coord(const uint32_t* X, const float* f, uint32_t i) {
   return ((double)X[i] + (f ? (double)f[i] : 0.0)) * kQuantum;
 }
-__device__ inline double mimg(double d) { return d - rint(d); }  // periodic minimum image
 __device__ inline double pmass(const PartIn& P, uint32_t i) {
   return P.mass ? (double)P.mass[i] : P.mass_scalar;
 }
@@ -424,6 +301,7 @@ __device__ inline uint64_t cube_cell(const int64_t* lo, const int64_t* nc, uint6
 // host's centre): the particles of the level-0 cells it may touch
 __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_depth,
                                                const int32_t* __restrict__ s_host,
+                                               const unsigned long long* __restrict__ ext,
                                                const double* __restrict__ centre,
                                                const uint32_t* __restrict__ iso_cnt, int g,
                                                const uint32_t* __restrict__ count0,
@@ -449,7 +327,9 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
   const double* c = centre + 3 * (uint64_t)s;
   const double* ch = centre + 3 * (uint64_t)hh;
   const double sx = mimg(c[0] - ch[0]), sy = mimg(c[1] - ch[1]), sz = mimg(c[2] - ch[2]);
-  const double R = 0.5 * sqrt(sx * sx + sy * sy + sz * sz);
+  const double half = 0.5 * sqrt(sx * sx + sy * sy + sz * sz);
+  const double e = __longlong_as_double((long long)ext[s]);
+  const double R = e < half ? e : half;  // capped by the start patch's extent
   int64_t lo[3], nc[3];
   cube_of(c, R, g, lo, nc);
   const uint64_t ncell = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
@@ -808,8 +688,19 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   k_centre<<<(unsigned)ns, kHT, 0, st>>>(leaf_off, leaf_cnt, leaf_list, leaf_tmp, out->leafkey,
                                          leaf_min, h->prm.g, P, out->centre);
   HIP_LAUNCH_CHECK();
-  k_bound<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, h->s_host, out->centre, iso_cnt, h->prm.g,
-                                        l0.Scount, out->radius, bound);
+  unsigned long long* ext = ws.get<unsigned long long>(ns);
+  k_fill_u64<<<blocks_for(ns), kHB, 0, st>>>(reinterpret_cast<uint64_t*>(ext), ns, 0);
+  HIP_LAUNCH_CHECK();
+  for (size_t L = 1; L < nlev; ++L) {
+    const Level& lv = h->lev[L];
+    if (!lv.nS || !lv.nPatch) continue;
+    k_extent<<<blocks_for(lv.nS), kHB, 0, st>>>((int)L, (int)lv.b, lv.nS, lv.nPatch, lv.Skey,
+                                                lv.Spatch, lv.patch_struct, h->s_depth,
+                                                h->s_level, h->s_patch, out->centre, ext);
+    HIP_LAUNCH_CHECK();
+  }
+  k_bound<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, h->s_host, ext, out->centre, iso_cnt,
+                                        h->prm.g, l0.Scount, out->radius, bound);
   HIP_LAUNCH_CHECK();
   k_offsets<<<1, kHT, 0, st>>>(bound, ns, out->cand_off);
   HIP_LAUNCH_CHECK();

@@ -80,6 +80,14 @@ __global__ void k_slots(Cnt nslot_c, const int32_t* __restrict__ Bcell,
   }
 }
 
+// orders the LDS accesses of one wave: what a lane wrote before is seen by
+// every lane of the wave after (the wave's LDS instructions run in order;
+// this keeps the compiler from moving them across)
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Morton keys at B bits per axis, the identity permutation, the particle as
 // one 32-byte record {X, Y, Z, mass | fx, fy, fz, 0} (input order), and the
@@ -97,9 +105,15 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
                                               uint32_t* __restrict__ ghist,
                                               uint32_t* __restrict__ err) {
   __shared__ uint32_t h[kRsMaxPass * 256];
+  // each wave's 64 records (2 KB) pass through LDS, so that each of the two
+  // 16-byte stores per lane writes one contiguous kilobyte (a lane storing
+  // its own record's two halves at a 32-byte stride left half-written lines,
+  // and 29% more bytes reached HBM than the records hold)
+  __shared__ uint4 stage[256 / 64][128];
   for (int i = threadIdx.x; i < kRsMaxPass * 256; i += 256) h[i] = 0u;
   __syncthreads();
   const int s = kQBits - B;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint64_t base = (uint64_t)blockIdx.x * 256; base < n; base += (uint64_t)gridDim.x * 256) {
     const uint64_t i = base + threadIdx.x;
     const bool valid = i < n;
@@ -112,10 +126,21 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
       // word_ib >= 0: the sort starts on packed words (key << ib) | index
       keys[i] = (word_ib >= 0) ? ((key << word_ib) | i) : key;
       const float w = m ? m[i] : mscalar;
-      rec[2 * i] = make_uint4(xm, ym, zm, __float_as_uint(w));
-      rec[2 * i + 1] = make_uint4(fx ? __float_as_uint(fx[i]) : 0u, fy ? __float_as_uint(fy[i]) : 0u,
-                                  fz ? __float_as_uint(fz[i]) : 0u, 0u);
+      stage[wv][2 * lane] = make_uint4(xm, ym, zm, __float_as_uint(w));
+      stage[wv][2 * lane + 1] =
+          make_uint4(fx ? __float_as_uint(fx[i]) : 0u, fy ? __float_as_uint(fy[i]) : 0u,
+                     fz ? __float_as_uint(fz[i]) : 0u, 0u);
     }
+    wave_lds_sync();
+    // the wave's records start at uint4 2 * (wave base); lane l stores
+    // uint4 l, then 64 + l of them (only those of valid elements)
+    const uint64_t w0 = base + (uint64_t)(wv * 64);
+    if (w0 < n) {
+      const uint64_t nrec = 2 * ((n - w0) < 64 ? (n - w0) : 64);
+      if ((uint64_t)lane < nrec) rec[2 * w0 + lane] = stage[wv][lane];
+      if ((uint64_t)(64 + lane) < nrec) rec[2 * w0 + 64 + lane] = stage[wv][64 + lane];
+    }
+    wave_lds_sync();
     wave_digit_hist(key, valid, npass, h);
   }
   __syncthreads();
@@ -574,15 +599,6 @@ constexpr int kPatchBatch = 4;  // deeper levels
 // level 1 (about one particle per cell): 2 or 4 records in flight, a tuning choice
 constexpr int kWaveG = 6;     // a wave's 4x4x4 cells per axis with their halo
 constexpr int kWaveH = kWaveG * kWaveG * kWaveG;
-
-// orders the LDS accesses of one wave: what a lane wrote before is seen by
-// every lane of the wave after (the wave's LDS instructions run in order;
-// this keeps the compiler from moving them across)
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ inline uint32_t tile_local_parent(uint32_t x, uint32_t y, uint32_t z) {
   // Morton index of a parent inside its 4x4x4 tile

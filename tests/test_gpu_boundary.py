@@ -3,6 +3,7 @@ allocation callbacks (PyTorch-owned memory, an injected allocation failure),
 cancellation of a queued request, results held by the client surviving
 eviction, and measured device memory staying inside a server's budget."""
 import ctypes as C
+import gc
 import threading
 import time
 
@@ -65,6 +66,9 @@ def test_torch_owned_memory_and_release():
     p = small_case()
     levels, order = oracle.build(p)
     dev = ahf.snapshot_to_device(p)
+    # objects of earlier tests that only the cycle collector frees would
+    # otherwise be freed in the middle of this test
+    gc.collect()
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
     ctx = ahf.Context(0)  # PyTorch's caching allocator by default

@@ -1,0 +1,80 @@
+"""Particle collection and unbinding at full size (the 16.8M workload with
+velocities, every structure of its classified hierarchy), checked per sampled
+halo against the oracle's own steps fed with the device's inputs: the leaf
+centre recomputed from the device's level arrays, a substructure's sphere by
+brute force over all particles, and the unbinding of the device's candidates
+around the device's centre, whose members must match exactly."""
+import numpy as np
+import pytest
+
+from oracle import halos as H
+from paper_0904_3662_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+class Lv:
+    def __init__(self, d):
+        self.__dict__.update(d)
+
+
+@pytest.mark.timeout(900)
+def test_halos_16m_sampled():
+    import torch
+    from paper_0904_3662_amd import ahf
+    p = synth.snapshot_16m(1, velocities=True)
+    print(f"halos at full size: {p.n} particles", flush=True)
+    dev = ahf.snapshot_to_device(p)
+    vel = torch.from_numpy(p.vel).cuda()
+    with ahf.Context(0) as ctx:
+        h, _ = ahf.build_snapshot(ctx, p, dev=dev, substructure=True)
+        st = h.structures()
+        res = ahf.find_halos(ctx, h, dev, vel)
+        levels = {}
+        order = h.order_numpy(p.n).astype(np.int64)
+
+        def level(L):
+            if L not in levels:
+                d = h.level_numpy(L)
+                levels[L] = Lv(dict(cell_key=d["cell_key"], cell_start=d["cell_start"],
+                                    cell_count=d["cell_count"], cell_patch=d["cell_patch"],
+                                    bits=d["bits"]))
+            return levels[L]
+        n = res["n_halos"]
+        assert n == st["n_structures"] > 1000
+        pos = H.positions(p)
+        velf = p.vel.astype(np.float64)
+        mass = np.ones(p.n)
+        rho_b = float(p.n)
+        rng = np.random.Generator(np.random.PCG64(77))
+        depth = st["depth"]
+        subs = np.nonzero(depth > 0)[0]
+        hosts = np.nonzero(depth == 0)[0]
+        # (where the lattice background refines, it is one host: few hosts)
+        print(f"{len(hosts)} hosts, {len(subs)} substructures", flush=True)
+        sample = np.concatenate([rng.choice(subs, min(20, len(subs)), replace=False),
+                                 rng.choice(hosts, min(20, len(hosts)), replace=False)])
+        # the few largest halos too (the longest unbinding)
+        sample = np.unique(np.concatenate([sample, np.argsort(-res["cand_count"].astype(np.int64))[:5]]))
+        for s in sample:
+            s = int(s)
+            key = int(res["leaf"][s])
+            L, q = key >> 32, key & 0xffffffff
+            lv = level(L)
+            fake = {L: lv}
+            c = H.centre_of(fake, order, pos, mass, L, q)
+            assert np.all(np.abs(H.min_image(res["centre"][s] - c)) <= 1e-12), s
+            cand = res["candidates"][s].astype(np.int64)
+            if depth[s] > 0:
+                d = H.min_image(pos - res["centre"][s])
+                want = np.nonzero((d * d).sum(axis=1) <= res["radius"][s] ** 2)[0]
+                assert np.array_equal(cand, want), s
+            u = H.unbind(cand, pos, velf, mass, res["centre"][s], rho_b)
+            assert np.array_equal(res["members"][s].astype(np.int64), u["members"]), s
+            assert int(res["iterations"][s]) == u["iterations"], s
+            for k in ("r_vir", "m_vir"):
+                assert abs(res[k][s] - u[k]) <= 1e-12 * max(abs(u[k]), 1e-300), (s, k)
+        total = int(res["cand_count"].astype(np.int64).sum())
+        kept = int((res["member_count"] > 0).sum())
+        print(f"{n} halos, {kept} keep particles, {total} candidates", flush=True)
+        h.free()

@@ -205,3 +205,24 @@ def test_full_run_invariants():
             d = H.min_image(pos[cand] - h["centre"])
             assert np.all((d * d).sum(axis=1) <= h["radius"] ** 2)
     assert kept >= 5  # the eight NFW halos mostly survive their unbinding
+
+
+def test_patch_extent_is_the_farthest_cell_corner():
+    # a one-cell patch around its own centre: half the cell's diagonal
+    p = clump_snapshot((0.3, 0.3, 0.3))
+    levels, order = oracle.build(p)
+    lv = levels[2]
+    q = int(lv.cell_patch[0])
+    cells = np.nonzero(lv.cell_patch == q)[0]
+    h = 1.0 / (1 << lv.bits)
+    corners = []
+    for c in cells:
+        lo = H.cell_corner(int(lv.cell_key[c]), lv.bits)
+        for dx in (0, h):
+            for dy in (0, h):
+                for dz in (0, h):
+                    corners.append(lo + [dx, dy, dz])
+    centre = np.array([0.301, 0.299, 0.3005])
+    d = H.min_image(np.array(corners) - centre)
+    want = float(np.sqrt((d * d).sum(axis=1)).max())
+    assert H.patch_extent(levels, 2, q, centre) == pytest.approx(want, rel=1e-15)
