@@ -398,7 +398,8 @@ def measure(ctx, snap, dev, stream, steps, warmup, extras=True):
         h, _ = ahf.build_snapshot(ctx, snap, dev=dev, stream=stream)
         return h
 
-    names = ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "child_ranges",
+    names = ("rs_scatter", "rs_up", "rs_tscan", "keys", "gather", "fix_runs", "fix_long_runs",
+             "child_ranges",
              "heavy_chunk", "tile_deposit0", "tile_deposit1", "tile_halo", "patches",
              "combine", "mark", "uf_hook", "uf_cross")
     lv_info = None

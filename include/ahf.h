@@ -252,6 +252,10 @@ typedef struct {
     uint32_t heavy_level1;      /* 1..64 */
     uint32_t heavy_deeper;      /* 1..64 */
     uint32_t batch_level1;      /* 2 or 4 */
+    int32_t sort_skip_digits;   /* -1: chosen by size; else 0..2 low 8-bit key digits the
+                                 * radix sort leaves out, put in order afterwards only for
+                                 * the particles of the refined cells of the deepest level
+                                 * whose cells do not depend on them */
 } ahf_tuning;
 
 /* Sets the context's tuning table: a build of n particles uses entries[i]

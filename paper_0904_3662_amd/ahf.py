@@ -85,7 +85,7 @@ class Structures(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("heavy_level0", C.c_uint32),
                 ("heavy_level1", C.c_uint32), ("heavy_deeper", C.c_uint32),
-                ("batch_level1", C.c_uint32)]
+                ("batch_level1", C.c_uint32), ("sort_skip_digits", C.c_int32)]
 
 
 class BuildInfo(C.Structure):
@@ -321,14 +321,16 @@ class Context:
 
     def set_tuning(self, table):
         """table: list of (min_n, dict(heavy_level0=, heavy_level1=,
-        heavy_deeper=, batch_level1=)); a build of n particles uses the entry
-        with the largest min_n <= n.  [] restores the defaults."""
+        heavy_deeper=, batch_level1=[, sort_skip_digits=])); a build of n
+        particles uses the entry with the largest min_n <= n.  [] restores the
+        defaults."""
         n = len(table)
         mins = np.array([int(t[0]) for t in table], np.uint64)
         arr = (Tuning * max(n, 1))()
         for i, (_, d) in enumerate(table):
             arr[i] = Tuning(C.sizeof(Tuning), int(d["heavy_level0"]), int(d["heavy_level1"]),
-                            int(d["heavy_deeper"]), int(d["batch_level1"]))
+                            int(d["heavy_deeper"]), int(d["batch_level1"]),
+                            int(d.get("sort_skip_digits", -1)))
         _check(load().ahf_ctx_set_tuning(self._h, n, mins.ctypes.data if n else None, arr))
 
     def set_planning(self, on: bool):

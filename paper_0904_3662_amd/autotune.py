@@ -1,10 +1,11 @@
-"""Autotuner of the deposit's bin sizes: per size class, the light/heavy cell
-thresholds of level 0, level 1 and the deeper levels, and the records in
-flight per thread on level 1 (ahf_ctx_set_tuning).
+"""Autotuner of the build's bin sizes: per size class, the light/heavy cell
+thresholds of level 0, level 1 and the deeper levels, the records in flight
+per thread on level 1, and the low key digits the sort leaves out
+(ahf_ctx_set_tuning).
 
 For each size class a seeded snapshot of the lattice + NFW recipe is built on
 the GPU with every candidate tuning (coordinate descent from the library's
-defaults: level 1 first, then level 0, then the deeper levels), the median
+defaults: level 1 first, then level 0, the deeper levels, the sort), the median
 build time of a few builds decides, and the winners are written as a JSON
 table that ahf.Context loads (tuning_gfx950.json beside this file).
 
@@ -26,11 +27,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_TABLE = os.path.join(HERE, "tuning_gfx950.json")
 
-DEFAULTS = dict(heavy_level0=64, heavy_level1=64, heavy_deeper=64, batch_level1=2)
+DEFAULTS = dict(heavy_level0=64, heavy_level1=64, heavy_deeper=64, batch_level1=2,
+                sort_skip_digits=-1)
 CANDIDATES = {
     "level1": [dict(heavy_level1=h, batch_level1=b) for h in (8, 16, 32, 64) for b in (2, 4)],
     "level0": [dict(heavy_level0=h) for h in (16, 32, 48, 64)],
     "deeper": [dict(heavy_deeper=h) for h in (16, 32, 48, 64)],
+    "sort": [dict(sort_skip_digits=k) for k in (-1, 0, 1, 2)],
 }
 # size classes: the tuning of the largest min_n <= n applies
 SIZES = [1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22, 1 << 24, 1 << 27]
@@ -70,7 +73,7 @@ def tune_size(ctx, n, reps, log):
     best = dict(DEFAULTS)
     best_ms = time_builds(ctx, snap, dev, best, reps)
     log(f"n={snap.n}: defaults {best_ms:.3f} ms")
-    for stage in ("level1", "level0", "deeper"):
+    for stage in ("level1", "level0", "deeper", "sort"):
         for cand in CANDIDATES[stage]:
             t = dict(best, **cand)
             if t == best:
@@ -90,7 +93,9 @@ def load_table(path: str = DEFAULT_TABLE):
     with open(path) as f:
         doc = json.load(f)
     keys = ("heavy_level0", "heavy_level1", "heavy_deeper", "batch_level1")
-    return [(int(e["min_n"]), {k: int(e[k]) for k in keys}) for e in doc["entries"]]
+    return [(int(e["min_n"]), dict({k: int(e[k]) for k in keys},
+                                   sort_skip_digits=int(e.get("sort_skip_digits", -1))))
+            for e in doc["entries"]]
 
 
 def main(argv=None):

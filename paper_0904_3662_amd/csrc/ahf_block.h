@@ -9,6 +9,7 @@ namespace ahf {
 
 constexpr int kBT = 256;        // threads of the workgroups that use these
 constexpr int kBW = kBT / 64;   // their waves
+static_assert(kBT == 256, "the radix sort ranks one 8-bit digit per thread");
 
 __device__ inline uint64_t lanes_below() {
   const uint32_t lane = __lane_id();

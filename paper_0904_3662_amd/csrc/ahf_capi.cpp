@@ -696,6 +696,9 @@ ahf_status ahf_ctx_set_tuning(ahf_ctx* ctx, uint32_t n_entries, const uint64_t* 
     }
     if (e.batch_level1 != 2 && e.batch_level1 != 4) return fail(AHF_EINVAL, "batch_level1 must be 2 or 4");
     t.batch1 = e.batch_level1;
+    if (e.sort_skip_digits < -1 || e.sort_skip_digits > 2)
+      return fail(AHF_EINVAL, "sort_skip_digits must be -1..2");
+    t.sort_skip = e.sort_skip_digits;
     tab.emplace_back(min_n[i], t);
   }
   ctx->c.tuning = tab;
@@ -710,6 +713,7 @@ ahf_status ahf_ctx_get_tuning(const ahf_ctx* ctx, uint64_t n, ahf_tuning* out) {
   out->heavy_level1 = t.heavy[1];
   out->heavy_deeper = t.heavy[2];
   out->batch_level1 = t.batch1;
+  out->sort_skip_digits = t.sort_skip;
   return AHF_OK;
 }
 

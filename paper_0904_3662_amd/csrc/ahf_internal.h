@@ -71,6 +71,7 @@ struct Prof {
 struct Tuning {
   uint32_t heavy[3] = {64, 64, 64};
   uint32_t batch1 = 2;
+  int32_t sort_skip = -1;  // low key digits left out of the sort (-1: by size)
 };
 
 struct Ctx {

@@ -33,6 +33,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "ahf_block.h"
 #include "ahf_internal.h"
 
 namespace ahf {
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
                                               const float* __restrict__ fz,
                                               const float* __restrict__ m, float mscalar,
                                               uint64_t n, int B, int npass, int word_ib,
-                                              uint64_t* __restrict__ keys,
+                                              int kshift, uint64_t* __restrict__ keys,
                                               uint4* __restrict__ rec,
                                               uint32_t* __restrict__ ghist,
                                               uint32_t* __restrict__ err) {
@@ -122,7 +123,8 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
       const uint32_t x = X[i], y = Y[i], z = Z[i];
       if ((x | y | z) >= (1u << kQBits)) atomicOr(err, kErrCoord);
       const uint32_t xm = x & 0x1fffffu, ym = y & 0x1fffffu, zm = z & 0x1fffffu;
-      key = morton3(xm >> s, ym >> s, zm >> s);
+      // the sort orders by the key without its lowest kshift bits
+      key = morton3(xm >> s, ym >> s, zm >> s) >> kshift;
       // word_ib >= 0: the sort starts on packed words (key << ib) | index
       keys[i] = (word_ib >= 0) ? ((key << word_ib) | i) : key;
       const float w = m ? m[i] : mscalar;
@@ -188,6 +190,92 @@ __global__ __launch_bounds__(kT) void k_gather_rec(const uint64_t* __restrict__ 
       cp = morton3(a.x >> s, a.y >> s, a.z >> s) >> sh0;
     }
     for (uint64_t c = (i > 0) ? cp + 1 : 0; c <= ci; ++c) start0[c] = (uint32_t)i;
+  }
+}
+
+// The sort may leave out the lowest `skip` key bits: it then orders by
+// key >> skip, ties by input index, and a run of particles with equal key >>
+// skip still has to be put in full-key order (stable: equal keys keep the
+// input order).  Runs of up to kShortRun particles are sorted in place by the
+// thread at their start (insertion sort moving keys, records and indices);
+// longer ones (dense cores) go to a list for k_fix_long_runs.  Right after the
+// gather, before any level reads the particles.
+constexpr uint32_t kShortRun = 16;
+__global__ void k_fix_runs(uint64_t* __restrict__ skey, uint4* __restrict__ srec,
+                           uint32_t* __restrict__ order, uint64_t n, int skip,
+                           uint32_t* __restrict__ nlong, uint32_t* __restrict__ long_a,
+                           uint32_t* __restrict__ long_m) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = skey[i];
+    if (i > 0 && ((skey[i - 1] ^ k) >> skip) == 0) continue;  // not a run start
+    if (i + 1 >= n || ((skey[i + 1] ^ k) >> skip) != 0) continue;  // one particle
+    uint64_t j = i + 2;
+    while (j < n && ((skey[j] ^ k) >> skip) == 0) ++j;
+    const uint32_t m = (uint32_t)(j - i);
+    if (m > kShortRun) {
+      const uint32_t at = atomicAdd(nlong, 1u);
+      long_a[at] = (uint32_t)i;
+      long_m[at] = m;
+      continue;
+    }
+    // stable insertion sort of the run by the full key
+    for (uint32_t q = 1; q < m; ++q) {
+      const uint64_t kq = skey[i + q];
+      uint32_t r = q;
+      while (r > 0 && skey[i + r - 1] > kq) --r;
+      if (r == q) continue;
+      const uint32_t oq = order[i + q];
+      const uint4 a0 = srec[2 * (i + q)], a1 = srec[2 * (i + q) + 1];
+      for (uint32_t t = q; t > r; --t) {
+        skey[i + t] = skey[i + t - 1];
+        order[i + t] = order[i + t - 1];
+        srec[2 * (i + t)] = srec[2 * (i + t - 1)];
+        srec[2 * (i + t) + 1] = srec[2 * (i + t - 1) + 1];
+      }
+      skey[i + r] = kq;
+      order[i + r] = oq;
+      srec[2 * (i + r)] = a0;
+      srec[2 * (i + r) + 1] = a1;
+    }
+  }
+}
+
+// The long runs: one workgroup per run, a stable sort of (key, position in
+// the run), then keys, indices and records written back permuted.  ka, kb,
+// va, vb, rtmp are scratch at the particles' positions.
+__global__ __launch_bounds__(kBT) void k_fix_long_runs(
+    const uint32_t* __restrict__ nlong, const uint32_t* __restrict__ long_a,
+    const uint32_t* __restrict__ long_m, uint64_t* __restrict__ skey, uint4* __restrict__ srec,
+    uint32_t* __restrict__ order, uint64_t* __restrict__ ka, uint64_t* __restrict__ kb,
+    uint32_t* __restrict__ va, uint32_t* __restrict__ vb, uint4* __restrict__ rtmp) {
+  const uint32_t nr = *nlong;
+  for (uint32_t r = blockIdx.x; r < nr; r += gridDim.x) {
+    const uint64_t a = long_a[r];
+    const uint32_t m = long_m[r];
+    for (uint32_t k = threadIdx.x; k < m; k += kBT) {
+      ka[a + k] = skey[a + k];
+      va[a + k] = k;
+    }
+    __syncthreads();
+    const bool fl = block_sort<uint64_t>(ka + a, va + a, kb + a, vb + a, m);
+    const uint64_t* K = fl ? kb + a : ka + a;
+    const uint32_t* V = fl ? vb + a : va + a;
+    uint32_t* T = fl ? va + a : vb + a;  // the other index buffer
+    for (uint32_t k = threadIdx.x; k < m; k += kBT) {
+      const uint64_t j = a + V[k];
+      T[k] = order[j];
+      rtmp[2 * (a + k)] = srec[2 * j];
+      rtmp[2 * (a + k) + 1] = srec[2 * j + 1];
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < m; k += kBT) {
+      order[a + k] = T[k];
+      skey[a + k] = K[k];
+      srec[2 * (a + k)] = rtmp[2 * (a + k)];
+      srec[2 * (a + k) + 1] = rtmp[2 * (a + k) + 1];
+    }
+    __syncthreads();
   }
 }
 
@@ -1649,6 +1737,18 @@ static Tree make_tree(const Hier* h) {
   return t;
 }
 
+// Low 8-bit key digits the sort leaves out, as tuned or by depth: two when
+// the keys have bits for 12 levels below the domain grid, one for 9, else
+// none, so that the left-out bits lie 6 or more levels below the domain grid,
+// where few particles share the remaining bits; never bits of the domain
+// grid itself
+static int sort_skip_bits(int B, int g, int want) {
+  int k = want;
+  if (k < 0) k = (B - g) >= 12 ? 2 : ((B - g) >= 9 ? 1 : 0);
+  while (k > 0 && (8 * k + 2) / 3 > B - g) --k;
+  return 8 * k;
+}
+
 // The build's zeroed block: 3 totals per level (FP64), then kDevU32 words of
 // counters: [0] error flags, [1..7] per-level counters, [8 + 2L], [9 + 2L]
 // heavy cells and chunks of level L; then, for a planned build, per level the
@@ -1701,9 +1801,15 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   ctx->dev_err = err;
 
   // ---- keys and their stable sort
+  // The radix sort may leave out the lowest `skip` key bits (fewer passes);
+  // runs of particles that those bits alone would order are then sorted
+  // right after the gather (k_fix_runs), so that everything after it sees
+  // the full stable sort.
+  const Tuning tune = ctx->tuning_for(n);
+  const int skip = sort_skip_bits(B, g, tune.sort_skip);
   uint64_t* keys = ws.get<uint64_t>(n);
   uint4* rec = ws.get<uint4>(2 * n);
-  const SortPlan sp = sort_plan(n, 3 * B);
+  const SortPlan sp = sort_plan(n, 3 * B - skip);
   h->order = h->mem.get<uint32_t>(n);
   uint4* srec = ws.get<uint4>(2 * n);
   uint64_t* skey = keys;
@@ -1717,7 +1823,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     AHF_TIMED(ctx, "keys", st,
               (k_keys<<<kb, 256, 0, st>>>(p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass,
                                           (float)p.mass_scalar, n, B, sp.npass,
-                                          sp.q == 0 ? sp.ib : -1, keys, rec, ghist, err)));
+                                          sp.q == 0 ? sp.ib : -1, skip, keys, rec, ghist,
+                                          err)));
     uint64_t* spare = nullptr;
     const uint64_t* words = sort_keys(ctx, ws, keys, n, sp, ghist, st, &spare);
     skey = spare;  // the full sorted keys go to the sort's free buffer
@@ -1725,6 +1832,28 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
               (k_gather_rec<<<grid_for(n + 1), kT, 0, st>>>(words, sp.ib, kQBits - B, n, rec,
                                                             srec, h->order, skey, 3 * (B - g),
                                                             ncell0, start0)));
+    if (skip) {
+      // the runs the left-out bits order: short ones in place, long ones by
+      // workgroups (scratch: what the gather leaves behind, and the lists)
+      Ws::Mark fm = ws.mark();
+      uint32_t* nlong = ws.get<uint32_t>(1);
+      const uint64_t lcap = n / (kShortRun + 1) + 1;
+      uint32_t* long_a = ws.get<uint32_t>(lcap);
+      uint32_t* long_m = ws.get<uint32_t>(lcap);
+      uint64_t* kb2 = ws.get<uint64_t>(n);
+      uint32_t* va2 = ws.get<uint32_t>(n);
+      uint32_t* vb2 = ws.get<uint32_t>(n);
+      k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(nlong), 1, 0);
+      HIP_LAUNCH_CHECK();
+      AHF_TIMED(ctx, "fix_runs", st,
+                (k_fix_runs<<<grid_for(n), kT, 0, st>>>(skey, srec, h->order, n, skip, nlong,
+                                                        long_a, long_m)));
+      AHF_TIMED(ctx, "fix_long_runs", st,
+                (k_fix_long_runs<<<2048, kBT, 0, st>>>(nlong, long_a, long_m, skey, srec,
+                                                       h->order, const_cast<uint64_t*>(words),
+                                                       kb2, va2, vb2, rec)));
+      ws.release(fm);
+    }
   }
 
   Parts P;
@@ -1768,7 +1897,6 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   // levels start, on a third stream, as soon as the levels get small (the
   // last levels leave most of the GPU idle); a planned build labels after it
   const bool early_labels = overlap && !(prm.flags & AHF_NO_LABELS) && !h->has_mass;
-  const Tuning tune = ctx->tuning_for(n);
   const int last_level = planned ? plan->depth : prm.Lmax;
   for (int L = 0; L <= last_level; ++L) {
     h->lev.emplace_back();

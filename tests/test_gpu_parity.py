@@ -180,9 +180,12 @@ def test_labels_match_oracle_on_repeated_builds(ctx, conn):
 # every tuning gives the oracle's hierarchy (integers exactly, the field within
 # tolerance): light/heavy thresholds down to a few particles per cell, and both
 # level-1 batch sizes
-TUNINGS = [dict(heavy_level0=4, heavy_level1=2, heavy_deeper=3, batch_level1=4),
-           dict(heavy_level0=16, heavy_level1=8, heavy_deeper=16, batch_level1=2),
-           dict(heavy_level0=64, heavy_level1=64, heavy_deeper=64, batch_level1=4)]
+TUNINGS = [dict(heavy_level0=4, heavy_level1=2, heavy_deeper=3, batch_level1=4,
+                sort_skip_digits=1),
+           dict(heavy_level0=16, heavy_level1=8, heavy_deeper=16, batch_level1=2,
+                sort_skip_digits=0),
+           dict(heavy_level0=64, heavy_level1=64, heavy_deeper=64, batch_level1=4,
+                sort_skip_digits=-1)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=["t4-2-3-b4", "t16-8-16-b2", "t64-b4"])
@@ -200,6 +203,45 @@ def test_tunings_match_oracle(tuning):
         run_case(c, p)
         c.set_tuning([])
         assert c.tuning(12345)["heavy_level1"] == 64
+
+
+# The sort may leave the lowest key digits out and then sort every run of
+# particles that only those digits order: with one and two digits left out,
+# on a deep clustered input (short runs), one with 300 coincident particles
+# and a tight clump (long runs, ties) and a shallow one, the oracle's
+# hierarchy and particle order, ties included, synced and sized ahead.
+SKIP_CASES = [
+    ("clumps-8lev", lambda: clustered(51, 60000, n_clumps=6, spread=0.006, frac=0.8, g=4, thr=4,
+                                      max_levels=8)),
+    ("chain-ties", lambda: coincident_chain(52)),
+    ("shallow", lambda: uniform(53, 20000, g=4, thr=5, max_levels=8)),
+]
+
+
+def coincident_chain(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = np.concatenate([np.repeat([[0.2, 0.7, 0.4]], 300, axis=0),
+                          np.array([0.6, 0.3, 0.9]) + rng.normal(0, 0.002, (5000, 3)),
+                          rng.random((8000, 3))]) % 1.0
+    return from_positions(pts, g=3, thr=3, max_levels=9)
+
+
+@pytest.mark.parametrize("skip", [1, 2])
+@pytest.mark.parametrize("name,make", SKIP_CASES, ids=[c[0] for c in SKIP_CASES])
+def test_sort_with_skipped_digits_matches_oracle(name, make, skip):
+    from paper_0904_3662_amd import ahf
+    p = make()
+    levels, order = oracle.build(p)
+    dev = ahf.snapshot_to_device(p)
+    t = dict(heavy_level0=64, heavy_level1=64, heavy_deeper=64, batch_level1=2,
+             sort_skip_digits=skip)
+    with ahf.Context(0) as c:
+        c.set_tuning([(0, t)])
+        c.set_planning(True)
+        for rep in range(2):  # synced, then sized ahead
+            h, _ = ahf.build_snapshot(c, p, dev=dev)
+            compare_hierarchy(h, p.n, levels, order)
+            h.free()
 
 
 # Builds sized ahead (planning switched on): the second build of a snapshot
