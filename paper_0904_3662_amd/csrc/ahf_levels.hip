@@ -154,63 +154,109 @@ __global__ __launch_bounds__(256) void k_keys(const uint32_t* __restrict__ X,
 // position i: particle index from the packed word, its record, its full key
 // rebuilt from the coordinates, and the level-0 cell starts: element i (and
 // the terminal element n) starts every dense cell after the previous
-// element's cell up to its own.  The previous element's cell comes from the
+// element's cell up to its own.  The previous element's key comes from the
 // neighbouring lane, or for a wave's first lane from that element's record.
 // Elements 0 .. n (n + 1 of them) in grid-stride rounds that every lane of
 // the grid takes part in.
+//
+// When the sort left out the lowest `skip` key bits it ordered by key >>
+// skip, ties by input index; a run of elements with equal key >> skip then
+// still has to be put in full-key order (stable: equal keys keep the input
+// order).  A run that lies within one wave is ranked there (its keys differ
+// only in the low bits) and written in that order; a run that crosses into
+// the next wave is written as it is and its start listed for k_fix_runs.
+__device__ inline uint64_t key_of(const uint4& a, int s) {
+  return morton3(a.x >> s, a.y >> s, a.z >> s);
+}
+
 __global__ __launch_bounds__(kT) void k_gather_rec(const uint64_t* __restrict__ words, int ib,
                                                    int s, uint64_t n,
                                                    const uint4* __restrict__ rec,
                                                    uint4* __restrict__ srec,
                                                    uint32_t* __restrict__ order,
                                                    uint64_t* __restrict__ skey, int sh0,
-                                                   uint64_t ncell0, uint32_t* __restrict__ start0) {
+                                                   uint64_t ncell0, uint32_t* __restrict__ start0,
+                                                   int skip, uint32_t* __restrict__ ncross,
+                                                   uint32_t* __restrict__ cross) {
   const uint64_t im = (1ull << ib) - 1ull;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const int lane = (int)__lane_id();
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base <= n; base += stride) {
     const uint64_t i = base + threadIdx.x;
-    uint64_t ci = ncell0;
-    if (i < n) {
-      const uint32_t j = (uint32_t)(words[i] & im);
-      const uint4 a = rec[2 * (uint64_t)j];
-      const uint4 b = rec[2 * (uint64_t)j + 1];
-      order[i] = j;
-      srec[2 * i] = a;
-      srec[2 * i + 1] = b;
-      const uint64_t key = morton3(a.x >> s, a.y >> s, a.z >> s);
-      skey[i] = key;
-      ci = key >> sh0;
+    const bool valid = i < n;
+    uint32_t j = 0;
+    uint4 a = make_uint4(0u, 0u, 0u, 0u), b = a;
+    uint64_t key = 0;
+    if (valid) {
+      j = (uint32_t)(words[i] & im);
+      a = rec[2 * (uint64_t)j];
+      b = rec[2 * (uint64_t)j + 1];
+      key = key_of(a, s);
     }
-    const uint32_t lo = __shfl_up((uint32_t)ci, 1, 64);
-    const uint32_t hi = __shfl_up((uint32_t)(ci >> 32), 1, 64);
-    uint64_t cp = ((uint64_t)hi << 32) | lo;
+    uint64_t kprev = ((uint64_t)__shfl_up((uint32_t)(key >> 32), 1, 64) << 32) |
+                     __shfl_up((uint32_t)key, 1, 64);
+    if (lane == 0 && i > 0 && i <= n) kprev = key_of(rec[2 * (words[i - 1] & im)], s);
+    uint64_t dst = i;
+    if (skip) {
+      uint64_t knext = ((uint64_t)__shfl_down((uint32_t)(key >> 32), 1, 64) << 32) |
+                       __shfl_down((uint32_t)key, 1, 64);
+      if (lane == 63 && i + 1 < n) knext = key_of(rec[2 * (words[i + 1] & im)], s);
+      const bool sp = valid && i > 0 && ((kprev ^ key) >> skip) == 0;  // continues a run
+      const bool sn = valid && i + 1 < n && ((knext ^ key) >> skip) == 0;
+      if (__ballot(sp || sn) != 0ull) {
+        const uint64_t heads = __ballot(!sp);  // lanes that do not continue the lane before
+        const uint64_t conts = __ballot(sn);
+        const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+        const uint64_t h_le = heads & le, h_gt = heads & ~le;
+        const int st = h_le ? 63 - __builtin_clzll(h_le) : -1;  // the run's first lane
+        const int en = h_gt ? __builtin_ctzll(h_gt) : 64;       // one past its last lane
+        const bool longer = (sp || sn);
+        // a run that began in an earlier wave, or goes on into the next one
+        const bool crossing = st < 0 || (en == 64 && ((conts >> 63) & 1ull));
+        const bool inside = longer && !crossing;
+        if (longer && crossing && st == lane) cross[atomicAdd(ncross, 1u)] = (uint32_t)i;
+        const uint64_t in_mask = __ballot(inside);
+        if (in_mask) {
+          const int r0 = __builtin_ctzll(in_mask), r1 = 63 - __builtin_clzll(in_mask);
+          const uint32_t lmask = (skip >= 32) ? ~0u : ((1u << skip) - 1u);
+          const uint32_t lo = (uint32_t)key & lmask;
+          uint32_t rank = 0;
+          for (int r = r0; r <= r1; ++r) {
+            const uint32_t lr = (uint32_t)__builtin_amdgcn_readlane((int)lo, r);
+            if (r >= st && r < en && (lr < lo || (lr == lo && r < lane))) ++rank;
+          }
+          if (inside) dst = i - (uint64_t)(lane - st) + rank;
+        }
+      }
+    }
+    if (valid) {
+      order[dst] = j;
+      srec[2 * dst] = a;
+      srec[2 * dst + 1] = b;
+      skey[dst] = key;
+    }
     if (i > n) continue;
-    if (i > 0 && __lane_id() == 0) {
-      const uint4 a = rec[2 * (words[i - 1] & im)];
-      cp = morton3(a.x >> s, a.y >> s, a.z >> s) >> sh0;
-    }
+    const uint64_t ci = valid ? key >> sh0 : ncell0;
+    const uint64_t cp = kprev >> sh0;
     for (uint64_t c = (i > 0) ? cp + 1 : 0; c <= ci; ++c) start0[c] = (uint32_t)i;
   }
 }
 
-// The sort may leave out the lowest `skip` key bits: it then orders by
-// key >> skip, ties by input index, and a run of particles with equal key >>
-// skip still has to be put in full-key order (stable: equal keys keep the
-// input order).  Runs of up to kShortRun particles are sorted in place by the
-// thread at their start (insertion sort moving keys, records and indices);
-// longer ones (dense cores) go to a list for k_fix_long_runs.  Right after the
-// gather, before any level reads the particles.
+// The runs the gather listed (those that cross from one wave into the next):
+// the thread of each finds its end; up to kShortRun particles are sorted in
+// place by that thread (insertion sort moving keys, records and indices),
+// longer ones (dense cores) go to a list for k_fix_long_runs.
 constexpr uint32_t kShortRun = 16;
-__global__ void k_fix_runs(uint64_t* __restrict__ skey, uint4* __restrict__ srec,
-                           uint32_t* __restrict__ order, uint64_t n, int skip,
-                           uint32_t* __restrict__ nlong, uint32_t* __restrict__ long_a,
+__global__ void k_fix_runs(const uint32_t* __restrict__ ncross,
+                           const uint32_t* __restrict__ cross, uint64_t* __restrict__ skey,
+                           uint4* __restrict__ srec, uint32_t* __restrict__ order, uint64_t n,
+                           int skip, uint32_t* __restrict__ nlong, uint32_t* __restrict__ long_a,
                            uint32_t* __restrict__ long_m) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
+  const uint32_t nc = *ncross;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += gridDim.x * blockDim.x) {
+    const uint64_t i = cross[t];
     const uint64_t k = skey[i];
-    if (i > 0 && ((skey[i - 1] ^ k) >> skip) == 0) continue;  // not a run start
-    if (i + 1 >= n || ((skey[i + 1] ^ k) >> skip) != 0) continue;  // one particle
-    uint64_t j = i + 2;
+    uint64_t j = i + 1;
     while (j < n && ((skey[j] ^ k) >> skip) == 0) ++j;
     const uint32_t m = (uint32_t)(j - i);
     if (m > kShortRun) {
@@ -227,11 +273,11 @@ __global__ void k_fix_runs(uint64_t* __restrict__ skey, uint4* __restrict__ srec
       if (r == q) continue;
       const uint32_t oq = order[i + q];
       const uint4 a0 = srec[2 * (i + q)], a1 = srec[2 * (i + q) + 1];
-      for (uint32_t t = q; t > r; --t) {
-        skey[i + t] = skey[i + t - 1];
-        order[i + t] = order[i + t - 1];
-        srec[2 * (i + t)] = srec[2 * (i + t - 1)];
-        srec[2 * (i + t) + 1] = srec[2 * (i + t - 1) + 1];
+      for (uint32_t u = q; u > r; --u) {
+        skey[i + u] = skey[i + u - 1];
+        order[i + u] = order[i + u - 1];
+        srec[2 * (i + u)] = srec[2 * (i + u - 1)];
+        srec[2 * (i + u) + 1] = srec[2 * (i + u - 1) + 1];
       }
       skey[i + r] = kq;
       order[i + r] = oq;
@@ -1802,9 +1848,9 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
 
   // ---- keys and their stable sort
   // The radix sort may leave out the lowest `skip` key bits (fewer passes);
-  // runs of particles that those bits alone would order are then sorted
-  // right after the gather (k_fix_runs), so that everything after it sees
-  // the full stable sort.
+  // runs of particles that those bits alone would order are then sorted by
+  // the gather (and k_fix_runs), so that everything after it sees the full
+  // stable sort.
   const Tuning tune = ctx->tuning_for(n);
   const int skip = sort_skip_bits(B, g, tune.sort_skip);
   uint64_t* keys = ws.get<uint64_t>(n);
@@ -1828,32 +1874,38 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
     uint64_t* spare = nullptr;
     const uint64_t* words = sort_keys(ctx, ws, keys, n, sp, ghist, st, &spare);
     skey = spare;  // the full sorted keys go to the sort's free buffer
+    // with left-out key bits: the runs crossing wave boundaries, listed by
+    // the gather (at most one per wave), then the long ones among them
+    uint32_t* nfix = nullptr;
+    uint32_t* cross = nullptr;
+    Ws::Mark fm = ws.mark();
+    if (skip) {
+      nfix = ws.get<uint32_t>(2);
+      cross = ws.get<uint32_t>((n + 1) / 64 + 2);
+      k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(nfix), 2, 0);
+      HIP_LAUNCH_CHECK();
+    }
     AHF_TIMED(ctx, "gather", st,
               (k_gather_rec<<<grid_for(n + 1), kT, 0, st>>>(words, sp.ib, kQBits - B, n, rec,
                                                             srec, h->order, skey, 3 * (B - g),
-                                                            ncell0, start0)));
+                                                            ncell0, start0, skip, nfix, cross)));
     if (skip) {
-      // the runs the left-out bits order: short ones in place, long ones by
-      // workgroups (scratch: what the gather leaves behind, and the lists)
-      Ws::Mark fm = ws.mark();
-      uint32_t* nlong = ws.get<uint32_t>(1);
+      // scratch: the lists, and what the gather leaves behind
       const uint64_t lcap = n / (kShortRun + 1) + 1;
       uint32_t* long_a = ws.get<uint32_t>(lcap);
       uint32_t* long_m = ws.get<uint32_t>(lcap);
       uint64_t* kb2 = ws.get<uint64_t>(n);
       uint32_t* va2 = ws.get<uint32_t>(n);
       uint32_t* vb2 = ws.get<uint32_t>(n);
-      k_fill_i32<<<1, 64, 0, st>>>(reinterpret_cast<int32_t*>(nlong), 1, 0);
-      HIP_LAUNCH_CHECK();
       AHF_TIMED(ctx, "fix_runs", st,
-                (k_fix_runs<<<grid_for(n), kT, 0, st>>>(skey, srec, h->order, n, skip, nlong,
-                                                        long_a, long_m)));
+                (k_fix_runs<<<1024, 256, 0, st>>>(nfix, cross, skey, srec, h->order, n, skip,
+                                                  nfix + 1, long_a, long_m)));
       AHF_TIMED(ctx, "fix_long_runs", st,
-                (k_fix_long_runs<<<2048, kBT, 0, st>>>(nlong, long_a, long_m, skey, srec,
+                (k_fix_long_runs<<<2048, kBT, 0, st>>>(nfix + 1, long_a, long_m, skey, srec,
                                                        h->order, const_cast<uint64_t*>(words),
                                                        kb2, va2, vb2, rec)));
-      ws.release(fm);
     }
+    ws.release(fm);
   }
 
   Parts P;
