@@ -343,7 +343,10 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
 }
 
 // the candidates of every structure, unordered: a host's isodensity list, a
-// substructure's particles within its radius
+// substructure's particles within its radius.  The cells of a substructure's
+// cube go in chunks of one cell per thread; the chunk's particles are then
+// spread over all threads (a dense cell holds many), each finding its cell by
+// a binary search of the chunk's particle offsets.
 __global__ __launch_bounds__(kHT) void k_candidates(
     const int32_t* __restrict__ s_depth, const double* __restrict__ centre,
     const double* __restrict__ radius, const uint64_t* __restrict__ iso_off,
@@ -352,6 +355,9 @@ __global__ __launch_bounds__(kHT) void k_candidates(
     const uint32_t* __restrict__ order, PartIn P, const uint64_t* __restrict__ cand_off,
     uint32_t* __restrict__ cand, uint32_t* __restrict__ cand_cnt) {
   __shared__ uint32_t cursor;
+  __shared__ uint32_t cofs[kHT + 1];  // the chunk's particle offsets per cell
+  __shared__ uint32_t cst[kHT];       // and each cell's first sorted position
+  __shared__ double red[kHW];
   const uint32_t s = blockIdx.x;
   uint32_t* out = cand + cand_off[s];
   if (s_depth[s] == 0) {
@@ -362,25 +368,44 @@ __global__ __launch_bounds__(kHT) void k_candidates(
     return;
   }
   if (threadIdx.x == 0) cursor = 0;
-  __syncthreads();
   const double* c = centre + 3 * (uint64_t)s;
   const double R = radius[s];
   const double R2 = R * R;
   int64_t lo[3], nc[3];
   cube_of(c, R, g, lo, nc);
   const uint64_t ncell = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
-  for (uint64_t k = threadIdx.x; k < ncell; k += kHT) {
-    const uint64_t cell = cube_cell(lo, nc, k, g);
-    const uint32_t a = start0[cell], cnt = count0[cell];
-    for (uint32_t j = 0; j < cnt; ++j) {
-      const uint32_t i = order[a + j];
+  for (uint64_t k0 = 0; k0 < ncell; k0 += kHT) {
+    const uint64_t k = k0 + threadIdx.x;
+    uint32_t a = 0, cnt = 0;
+    if (k < ncell) {
+      const uint64_t cell = cube_cell(lo, nc, k, g);
+      a = start0[cell];
+      cnt = count0[cell];
+    }
+    // exclusive offsets (counts below 2^32 are exact in FP64)
+    double tot = 0.0;
+    const double inc = block_scan((double)cnt, red, &tot);
+    cofs[threadIdx.x] = (uint32_t)inc - cnt;
+    cst[threadIdx.x] = a;
+    if (threadIdx.x == 0) cofs[kHT] = (uint32_t)tot;
+    __syncthreads();
+    const uint32_t total = (uint32_t)tot;
+    for (uint32_t f = threadIdx.x; f < total; f += kHT) {
+      // the last cell whose offset is at most f (it holds particle f)
+      uint32_t lo_c = 0, hi_c = kHT - 1;
+      while (lo_c < hi_c) {
+        const uint32_t mid = (lo_c + hi_c + 1) >> 1;
+        if (cofs[mid] <= f) lo_c = mid;
+        else hi_c = mid - 1;
+      }
+      const uint32_t i = order[cst[lo_c] + (f - cofs[lo_c])];
       const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
       const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
       const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
       if (dx * dx + dy * dy + dz * dz <= R2) out[atomicAdd(&cursor, 1u)] = i;
     }
+    __syncthreads();
   }
-  __syncthreads();
   if (threadIdx.x == 0) cand_cnt[s] = cursor;
 }
 
