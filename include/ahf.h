@@ -446,8 +446,9 @@ ahf_status ahf_find_halos(ahf_ctx *ctx, const ahf_hierarchy *h, const ahf_partic
 
 /* Device views of the halos, one per structure (structure order).  Halo s's
  * candidates and its particles are stored from cand_offset[s] on: cand[...]
- * ascending particle indices (cand_count[s] of them), member[...] ascending
- * (member_count[s]). */
+ * the candidates' particle indices in radius order from the centre, ties by
+ * index (cand_count[s] of them); member[...] the halo's particles in the same
+ * order (member_count[s]), the innermost of the last round. */
 typedef struct {
     uint64_t n_halos;
     const uint64_t *leaf;           /* leaf level << 32 | leaf patch id */

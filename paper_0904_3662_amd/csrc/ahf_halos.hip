@@ -45,6 +45,12 @@ namespace {
 constexpr int kHT = kBT;             // threads per workgroup of the per-halo kernels
 constexpr int kHW = kBW;             // waves per workgroup
 constexpr int kHB = 256;             // threads per block of the per-cell kernels
+constexpr int kHTBig = 1024;         // threads per workgroup of the largest structures
+constexpr int kRows = 4;             // rows of a workgroup's width whose loads go out together
+constexpr int kSeq = 4;              // consecutive particles per thread in the unbinding scans
+constexpr int kRadiusBits = 40;      // top bits of a radius' bit pattern the sort orders by
+constexpr uint32_t kShortTie = 64;   // longest run of tied truncated radii put in order in place
+constexpr uint64_t kBigCand = 32768; // possible candidates from which a structure counts as large
 constexpr double kQuantum = 1.0 / (double)(1u << kQBits);
 constexpr double kHalfQuantum = 0.5 / (double)(1u << kQBits);
 
@@ -347,23 +353,27 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
 // cube go in chunks of one cell per thread; the chunk's particles are then
 // spread over all threads (a dense cell holds many), each finding its cell by
 // a binary search of the chunk's particle offsets.
-__global__ __launch_bounds__(kHT) void k_candidates(
+template <int BT>
+__global__ __launch_bounds__(BT) void k_candidates(
     const int32_t* __restrict__ s_depth, const double* __restrict__ centre,
     const double* __restrict__ radius, const uint64_t* __restrict__ iso_off,
     const uint32_t* __restrict__ iso_cnt, const uint32_t* __restrict__ iso_list, int g,
     const uint32_t* __restrict__ start0, const uint32_t* __restrict__ count0,
     const uint32_t* __restrict__ order, PartIn P, const uint64_t* __restrict__ cand_off,
-    uint32_t* __restrict__ cand, uint32_t* __restrict__ cand_cnt) {
+    uint32_t* __restrict__ cand, uint32_t* __restrict__ cand_cnt, uint64_t big) {
+  constexpr int BW = BT / 64;
+  // structures with at least `big` possible candidates go to the wide workgroups
+  if ((cand_off[blockIdx.x + 1] - cand_off[blockIdx.x] >= big) != (BT > kHT)) return;
   __shared__ uint32_t cursor;
-  __shared__ uint32_t cofs[kHT + 1];  // the chunk's particle offsets per cell
-  __shared__ uint32_t cst[kHT];       // and each cell's first sorted position
-  __shared__ double red[kHW];
+  __shared__ uint32_t cofs[BT + 1];  // the chunk's particle offsets per cell
+  __shared__ uint32_t cst[BT];       // and each cell's first sorted position
+  __shared__ double red[BW];
   const uint32_t s = blockIdx.x;
   uint32_t* out = cand + cand_off[s];
   if (s_depth[s] == 0) {
     const uint32_t n = iso_cnt[s];
     const uint32_t* in = iso_list + iso_off[s];
-    for (uint32_t k = threadIdx.x; k < n; k += kHT) out[k] = in[k];
+    for (uint32_t k = threadIdx.x; k < n; k += BT) out[k] = in[k];
     if (threadIdx.x == 0) cand_cnt[s] = n;
     return;
   }
@@ -374,7 +384,7 @@ __global__ __launch_bounds__(kHT) void k_candidates(
   int64_t lo[3], nc[3];
   cube_of(c, R, g, lo, nc);
   const uint64_t ncell = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
-  for (uint64_t k0 = 0; k0 < ncell; k0 += kHT) {
+  for (uint64_t k0 = 0; k0 < ncell; k0 += BT) {
     const uint64_t k = k0 + threadIdx.x;
     uint32_t a = 0, cnt = 0;
     if (k < ncell) {
@@ -384,45 +394,125 @@ __global__ __launch_bounds__(kHT) void k_candidates(
     }
     // exclusive offsets (counts below 2^32 are exact in FP64)
     double tot = 0.0;
-    const double inc = block_scan((double)cnt, red, &tot);
+    const double inc = block_scan<BT>((double)cnt, red, &tot);
     cofs[threadIdx.x] = (uint32_t)inc - cnt;
     cst[threadIdx.x] = a;
-    if (threadIdx.x == 0) cofs[kHT] = (uint32_t)tot;
+    if (threadIdx.x == 0) cofs[BT] = (uint32_t)tot;
     __syncthreads();
     const uint32_t total = (uint32_t)tot;
-    for (uint32_t f = threadIdx.x; f < total; f += kHT) {
-      // the last cell whose offset is at most f (it holds particle f)
-      uint32_t lo_c = 0, hi_c = kHT - 1;
-      while (lo_c < hi_c) {
-        const uint32_t mid = (lo_c + hi_c + 1) >> 1;
-        if (cofs[mid] <= f) lo_c = mid;
-        else hi_c = mid - 1;
+    for (uint32_t f0 = threadIdx.x; f0 < total; f0 += kRows * BT) {
+      // the particles of kRows rows, their loads out together
+      uint32_t pi[kRows];
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const uint32_t f = f0 + j * BT;
+        pi[j] = 0;
+        if (f < total) {
+          // the last cell whose offset is at most f (it holds particle f)
+          uint32_t lo_c = 0, hi_c = BT - 1;
+          while (lo_c < hi_c) {
+            const uint32_t mid = (lo_c + hi_c + 1) >> 1;
+            if (cofs[mid] <= f) lo_c = mid;
+            else hi_c = mid - 1;
+          }
+          pi[j] = order[cst[lo_c] + (f - cofs[lo_c])];
+        }
       }
-      const uint32_t i = order[cst[lo_c] + (f - cofs[lo_c])];
-      const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
-      const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
-      const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
-      if (dx * dx + dy * dy + dz * dz <= R2) out[atomicAdd(&cursor, 1u)] = i;
+      double px[kRows], py[kRows], pz[kRows];
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        if (f0 + j * BT < total) {
+          px[j] = coord(P.X, P.fx, pi[j]);
+          py[j] = coord(P.Y, P.fy, pi[j]);
+          pz[j] = coord(P.Z, P.fz, pi[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        if (f0 + j * BT >= total) break;
+        const double dx = mimg(px[j] - c[0]);
+        const double dy = mimg(py[j] - c[1]);
+        const double dz = mimg(pz[j] - c[2]);
+        if (dx * dx + dy * dy + dz * dz <= R2) out[atomicAdd(&cursor, 1u)] = pi[j];
+      }
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) cand_cnt[s] = cursor;
 }
 
+// inclusive scan of one value per thread over the workgroup, in thread
+// order, with one barrier: consecutive calls alternate between the two
+// halves of red (par), so a call never overwrites what the one before it
+// is still reading
+template <int BT>
+__device__ inline double block_scan1(double x, double (*red)[BT / 64], int par, double* total) {
+  constexpr int BW = BT / 64;
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) red[par][w] = x;
+  __syncthreads();
+  double before = 0.0, all = 0.0;
+  for (int i = 0; i < BW; ++i) {
+    if (i < w) before += red[par][i];
+    all += red[par][i];
+  }
+  *total = all;
+  return before + x;
+}
+
+// exclusive scan of one value per thread over the workgroup, in thread
+// order, with one barrier (alternating halves of red as block_scan1)
+template <int BT>
+__device__ inline double block_escan1(double x, double (*red)[BT / 64], int par, double* total) {
+  constexpr int BW = BT / 64;
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  double inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  double exc = __shfl_up(inc, 1);
+  if (lane == 0) exc = 0.0;
+  if (lane == 63) red[par][w] = inc;
+  __syncthreads();
+  double before = 0.0, all = 0.0;
+  for (int i = 0; i < BW; ++i) {
+    if (i < w) before += red[par][i];
+    all += red[par][i];
+  }
+  *total = all;
+  return before + exc;
+}
+
+__device__ inline double vmass(const PartIn& P, const float4& v) {
+  return P.mass ? (double)v.w : P.mass_scalar;
+}
+
 // Unbinding of every structure's candidates.  Scratch per candidate (at the
 // structure's offset): idx_a, idx_b (u32), key_a, key_b (u64), msum, tail
-// (f64).  On exit cand holds the candidates by ascending index, member the
-// halo's particles by ascending index.
-__global__ __launch_bounds__(kHT) void k_unbind(
+// (f64), and the velocity and mass (vbuf) in radius order, kept beside the
+// radii while the rounds drop particles, so that the rounds read them in
+// order instead of by particle index.  On exit cand holds the candidates in
+// radius order, member the halo's particles in radius order.
+template <int BT>
+__global__ __launch_bounds__(BT) void k_unbind(
     const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ cand_cnt, uint32_t* cand,
     uint32_t* idx_a, uint32_t* idx_b, uint64_t* key_a, uint64_t* key_b, double* msum,
-    double* tail, const double* __restrict__ centre, PartIn P, double rho_thr, double G,
+    double* tail, float4* vbuf, const double* __restrict__ centre, PartIn P, double rho_thr,
+    double G,
     uint32_t max_iter, uint32_t* __restrict__ member, uint32_t* __restrict__ member_cnt,
     double* __restrict__ r_vir_out, double* __restrict__ m_vir_out, double* __restrict__ vel_out,
-    uint32_t* __restrict__ iters_out) {
-  __shared__ double red[kHW];
-  __shared__ int64_t redi[kHW];
-  __shared__ uint32_t wtot[kHW];
+    uint32_t* __restrict__ iters_out, uint64_t big) {
+  constexpr int BW = BT / 64;
+  if ((cand_off[blockIdx.x + 1] - cand_off[blockIdx.x] >= big) != (BT > kHT)) return;
+  __shared__ double red[BW];
+  __shared__ double rsc[2][BW];  // the scans, alternating halves
+  __shared__ int64_t redi[BW];
+  __shared__ uint32_t wkeep[2][BW], wgone[2][BW];  // the compaction, alternating halves
   const uint32_t s = blockIdx.x;
   const uint64_t off = cand_off[s];
   const uint32_t n = cand_cnt[s];
@@ -433,29 +523,150 @@ __global__ __launch_bounds__(kHT) void k_unbind(
   uint64_t* kb = key_b + off;
   double* M = msum + off;
   double* T = tail + off;
+  float4* V = vbuf + off;
   const double* c = centre + 3 * (uint64_t)s;
   const int lane = __lane_id(), w = threadIdx.x >> 6;
 
-  // the candidates by index (the view's order; ties of radius go by index)
-  if (block_sort<uint32_t>(cs, cs, ib, ib, n))
-    for (uint32_t k = threadIdx.x; k < n; k += kHT) cs[k] = ib[k];
-  __syncthreads();
-  // radii (bit patterns of non-negative doubles order like the doubles) and
-  // a stable sort by radius
-  for (uint32_t k = threadIdx.x; k < n; k += kHT) {
-    const uint32_t i = cs[k];
-    const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
-    const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
-    const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
-    double r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (r < kHalfQuantum) r = kHalfQuantum;
-    ka[k] = (uint64_t)__double_as_longlong(r);
-    ia[k] = i;
+  // The candidates ordered by radius (bit patterns of non-negative doubles
+  // order like the doubles), ties by particle index.  The sort takes the top
+  // kRadiusBits bits of the radius (few passes) with the candidate's slot as
+  // payload; particles whose truncated radii tie are then put in order by
+  // (radius, index) by the first thread of their run.  A run longer than
+  // kShortTie (near-coincident particles) sends the structure down the full
+  // sort instead: by index, then stably by the whole radius.
+  __shared__ uint32_t long_tie;
+  if (threadIdx.x == 0) long_tie = 0;
+  for (uint32_t k0 = threadIdx.x; k0 < n; k0 += kRows * BT) {
+    // kRows particles per thread, their (random) coordinate loads together
+    uint32_t pi[kRows];
+    double px[kRows], py[kRows], pz[kRows];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) pi[j] = (k0 + j * BT < n) ? cs[k0 + j * BT] : 0u;
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      if (k0 + j * BT < n) {
+        px[j] = coord(P.X, P.fx, pi[j]);
+        py[j] = coord(P.Y, P.fy, pi[j]);
+        pz[j] = coord(P.Z, P.fz, pi[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      const uint32_t k = k0 + j * BT;
+      if (k >= n) break;
+      const double dx = mimg(px[j] - c[0]);
+      const double dy = mimg(py[j] - c[1]);
+      const double dz = mimg(pz[j] - c[2]);
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      if (r < kHalfQuantum) r = kHalfQuantum;
+      M[k] = r;  // the whole radius, by slot (M is free until the rounds)
+      ka[k] = (uint64_t)__double_as_longlong(r) >> (64 - kRadiusBits);
+      ia[k] = k;
+    }
   }
   __syncthreads();
-  const bool fl = block_sort<uint64_t>(ka, ia, kb, ib, n);
-  uint64_t* K = fl ? kb : ka;
-  uint32_t* I = fl ? ib : ia;
+  const bool ft = block_sort<uint64_t, BT>(ka, ia, kb, ib, n);
+  const uint64_t* Kt = ft ? kb : ka;  // truncated radii, sorted
+  const uint32_t* St = ft ? ib : ia;  // their slots
+  uint64_t* K = ft ? ka : kb;         // whole radii in that order
+  uint32_t* I = ft ? ia : ib;         // particle indices in that order
+  // (each thread reads the slots it then overwrites in the other buffers)
+  for (uint32_t k0 = threadIdx.x; k0 < n; k0 += kRows * BT) {
+    uint32_t sl[kRows];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) sl[j] = (k0 + j * BT < n) ? St[k0 + j * BT] : 0u;
+    double rv_[kRows];
+    uint32_t iv[kRows];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      if (k0 + j * BT < n) {
+        rv_[j] = M[sl[j]];
+        iv[j] = cs[sl[j]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      const uint32_t k = k0 + j * BT;
+      if (k >= n) break;
+      K[k] = (uint64_t)__double_as_longlong(rv_[j]);
+      I[k] = iv[j];
+    }
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < n; k += BT) {
+    if (k > 0 && Kt[k - 1] == Kt[k]) continue;  // not a run start
+    uint32_t e = k + 1;
+    while (e < n && Kt[e] == Kt[k] && e - k <= kShortTie) ++e;
+    if (e - k > kShortTie) long_tie = 1u;
+  }
+  __syncthreads();
+  if (long_tie == 0u) {
+    // short ties: insertion sort by (radius, index); the truncated keys of
+    // the other runs are not touched
+    for (uint32_t k = threadIdx.x; k < n; k += BT) {
+      if (k > 0 && Kt[k - 1] == Kt[k]) continue;
+      uint32_t e = k + 1;
+      while (e < n && Kt[e] == Kt[k]) ++e;
+      for (uint32_t q = k + 1; q < e; ++q) {
+        const uint64_t kq = K[q];
+        const uint32_t iq = I[q];
+        uint32_t r = q;
+        while (r > k && (K[r - 1] > kq || (K[r - 1] == kq && I[r - 1] > iq))) {
+          K[r] = K[r - 1];
+          I[r] = I[r - 1];
+          --r;
+        }
+        K[r] = kq;
+        I[r] = iq;
+      }
+    }
+    __syncthreads();
+  } else {
+    // the full sort: the candidates by index, then a stable sort by radius
+    uint32_t* sp1 = ft ? ib : ia;  // the free index buffer (the truncated sort's slots)
+    if (block_sort<uint32_t, BT>(cs, cs, sp1, sp1, n))
+      for (uint32_t k = threadIdx.x; k < n; k += BT) cs[k] = sp1[k];
+    __syncthreads();
+    uint64_t* kx = ft ? kb : ka;  // the truncated keys' buffer, now free
+    for (uint32_t k = threadIdx.x; k < n; k += BT) {
+      const uint32_t i = cs[k];
+      const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
+      const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
+      const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      if (r < kHalfQuantum) r = kHalfQuantum;
+      kx[k] = (uint64_t)__double_as_longlong(r);
+      sp1[k] = i;
+    }
+    __syncthreads();
+    if (block_sort<uint64_t, BT>(kx, sp1, K, I, n)) {
+      // the result is in (K, I) already
+    } else {
+      for (uint32_t k = threadIdx.x; k < n; k += BT) {
+        K[k] = kx[k];
+        I[k] = sp1[k];
+      }
+    }
+    __syncthreads();
+  }
+  // the view's candidates: in radius order
+  for (uint32_t k = threadIdx.x; k < n; k += BT) cs[k] = I[k];
+  __syncthreads();
+  for (uint32_t k0 = threadIdx.x; k0 < n; k0 += kRows * BT) {
+    uint32_t pi[kRows];
+    float4 q[kRows];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) pi[j] = (k0 + j * BT < n) ? I[k0 + j * BT] : 0u;
+#pragma unroll
+    for (int j = 0; j < kRows; ++j)
+      if (k0 + j * BT < n)
+        q[j] = make_float4(P.vx[pi[j]], P.vy[pi[j]], P.vz[pi[j]], P.mass ? P.mass[pi[j]] : 0.0f);
+#pragma unroll
+    for (int j = 0; j < kRows; ++j)
+      if (k0 + j * BT < n) V[k0 + j * BT] = q[j];
+  }
+  __syncthreads();
+  int sc = 0;  // scans so far (their half of rsc)
 
   uint32_t na = n, iters = 0, nmem = 0;
   double r_vir = 0.0, m_vir = 0.0;
@@ -465,38 +676,63 @@ __global__ __launch_bounds__(kHT) void k_unbind(
     iters = it;
     // the halo's velocity: mass-weighted mean
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, sm = 0.0;
-    for (uint32_t k = threadIdx.x; k < na; k += kHT) {
-      const uint32_t i = I[k];
-      const double m = pmass(P, i);
-      s0 += m * (double)P.vx[i];
-      s1 += m * (double)P.vy[i];
-      s2 += m * (double)P.vz[i];
-      sm += m;
+    for (uint32_t k0 = threadIdx.x; k0 < na; k0 += kRows * BT) {
+      float4 q[kRows];
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const uint32_t k = k0 + j * BT;
+        q[j] = k < na ? V[k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        if (k0 + j * BT >= na) break;
+        const double m = vmass(P, q[j]);
+        s0 += m * (double)q[j].x;
+        s1 += m * (double)q[j].y;
+        s2 += m * (double)q[j].z;
+        sm += m;
+      }
     }
-    s0 = block_sum(s0, red);
-    s1 = block_sum(s1, red);
-    s2 = block_sum(s2, red);
-    sm = block_sum(sm, red);
+    s0 = block_sum<BT>(s0, red);
+    s1 = block_sum<BT>(s1, red);
+    s2 = block_sum<BT>(s2, red);
+    sm = block_sum<BT>(sm, red);
     vh[0] = s0 / sm;
     vh[1] = s1 / sm;
     vh[2] = s2 / sm;
-    // enclosed masses along the radii, and the last particle dense enough
+    // enclosed masses along the radii, and the last particle dense enough:
+    // each thread sums kSeq consecutive particles, the threads' sums are
+    // scanned across the workgroup
     double carry = 0.0;
     int64_t v = -1;
-    for (uint32_t c0 = 0; c0 < na; c0 += kHT) {
-      const uint32_t k = c0 + threadIdx.x;
-      const double m = k < na ? pmass(P, I[k]) : 0.0;
+    for (uint32_t c0 = 0; c0 < na; c0 += kSeq * BT) {
+      const uint32_t b0 = c0 + threadIdx.x * kSeq;
+      double pre[kSeq], rr[kSeq];
+      double run = 0.0;
+#pragma unroll
+      for (int e = 0; e < kSeq; ++e) {
+        const uint32_t k = b0 + e;
+        const double m = k < na ? vmass(P, V[k]) : 0.0;
+        rr[e] = k < na ? __longlong_as_double((long long)K[k]) : 1.0;
+        run += m;
+        pre[e] = run;
+      }
       double tot = 0.0;
-      const double inc = carry + block_scan(m, red, &tot);
-      if (k < na) {
-        M[k] = inc;
-        const double r = __longlong_as_double((long long)K[k]);
-        const double dens = inc / (4.0 / 3.0 * M_PI * (r * r * r));
-        if (dens >= rho_thr) v = (int64_t)k;
+      const double before = carry + block_escan1<BT>(run, rsc, (sc++) & 1, &tot);
+#pragma unroll
+      for (int e = 0; e < kSeq; ++e) {
+        const uint32_t k = b0 + e;
+        if (k < na) {
+          const double inc = before + pre[e];
+          M[k] = inc;
+          const double r = rr[e];
+          const double dens = inc / (4.0 / 3.0 * M_PI * (r * r * r));
+          if (dens >= rho_thr) v = (int64_t)k;
+        }
       }
       carry += tot;
     }
-    v = block_max_i64(v, redi);
+    v = block_max_i64<BT>(v, redi);
     if (v < 0) {  // never dense enough: the halo dissolves
       na = 0;
       r_vir = 0.0;
@@ -510,64 +746,95 @@ __global__ __launch_bounds__(kHT) void k_unbind(
     // tail[k] = sum over j in [k, v) of M_j (1/r_j - 1/r_{j+1}), chunks from the end
     double tcarry = 0.0;
     const uint32_t nv = (uint32_t)v;  // terms 0 .. v-1
-    for (int64_t c1 = (int64_t)nv; c1 > 0; c1 -= kHT) {
-      // this chunk covers [c1 - kHT, c1), thread t takes k = c1 - 1 - t
-      const int64_t k = c1 - 1 - (int64_t)threadIdx.x;
-      double term = 0.0;
-      if (k >= 0) {
-        const double r0 = __longlong_as_double((long long)K[k]);
-        const double r1 = __longlong_as_double((long long)K[k + 1]);
-        term = M[k] * (1.0 / r0 - 1.0 / r1);
+    for (int64_t c1 = (int64_t)nv; c1 > 0; c1 -= (int64_t)kSeq * BT) {
+      // thread t takes the kSeq terms k = c1 - 1 - (t kSeq + e), from the top
+      double pre[kSeq];
+      double run = 0.0;
+#pragma unroll
+      for (int e = 0; e < kSeq; ++e) {
+        const int64_t k = c1 - 1 - ((int64_t)threadIdx.x * kSeq + e);
+        double term = 0.0;
+        if (k >= 0) {
+          const double r0 = __longlong_as_double((long long)K[k]);
+          const double r1 = __longlong_as_double((long long)K[k + 1]);
+          term = M[k] * (1.0 / r0 - 1.0 / r1);
+        }
+        run += term;
+        pre[e] = run;
       }
       double tot = 0.0;
-      const double inc = tcarry + block_scan(term, red, &tot);
-      if (k >= 0) T[k] = inc;
+      const double before = tcarry + block_escan1<BT>(run, rsc, (sc++) & 1, &tot);
+#pragma unroll
+      for (int e = 0; e < kSeq; ++e) {
+        const int64_t k = c1 - 1 - ((int64_t)threadIdx.x * kSeq + e);
+        if (k >= 0) T[k] = before + pre[e];
+      }
       tcarry += tot;
     }
     __syncthreads();
-    // the unbound particles, then the others kept in radius order
+    // the unbound particles, then the others kept in radius order, in
+    // place: one particle per thread and row, kRows rows whose loads go out
+    // together; a row's writes land at or before its own reads, which all
+    // come before its barrier, and before the later rows' reads
     uint32_t kept = 0;
     uint32_t ngone = 0;
-    for (uint32_t c0 = 0; c0 < na; c0 += kHT) {
-      const uint32_t k = c0 + threadIdx.x;
-      bool gone = false;
-      uint64_t key = 0;
-      uint32_t i = 0;
-      if (k < na) {
-        key = K[k];
-        i = I[k];
-        const double r = __longlong_as_double((long long)key);
-        const double phi = (int64_t)k <= v ? -G * ((k < nv ? T[k] : 0.0) + mv / rv) : -G * mv / r;
-        const double dx = (double)P.vx[i] - vh[0];
-        const double dy = (double)P.vy[i] - vh[1];
-        const double dz = (double)P.vz[i] - vh[2];
-        const double ke = 0.5 * (dx * dx + dy * dy + dz * dz);
-        gone = ke > fabs(phi);
+    for (uint32_t s0r = 0; s0r < na; s0r += kRows * BT) {
+      uint64_t keyr[kRows];
+      uint32_t ir[kRows];
+      float4 qr[kRows];
+      double tr[kRows];
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const uint32_t k = s0r + j * BT + threadIdx.x;
+        keyr[j] = 0;
+        ir[j] = 0;
+        qr[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        tr[j] = 0.0;
+        if (k < na) {
+          keyr[j] = K[k];
+          ir[j] = I[k];
+          qr[j] = V[k];
+          tr[j] = k < nv ? T[k] : 0.0;
+        }
       }
-      const bool keep = k < na && !gone;
-      const uint64_t kb_ = __ballot(keep);
-      const uint64_t gb_ = __ballot(gone);
-      __syncthreads();
-      if (lane == 0) wtot[w] = (uint32_t)__popcll(kb_);
-      __syncthreads();
-      uint32_t before = 0, all = 0;
-      for (int j = 0; j < kHW; ++j) {
-        if (j < w) before += wtot[j];
-        all += wtot[j];
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const uint32_t c0 = s0r + j * BT;
+        if (c0 >= na) break;
+        const uint32_t k = c0 + threadIdx.x;
+        const int par = (int)((c0 / BT) & 1u);
+        bool gone = false;
+        if (k < na) {
+          const double r = __longlong_as_double((long long)keyr[j]);
+          const double phi = (int64_t)k <= v ? -G * (tr[j] + mv / rv) : -G * mv / r;
+          const double dx = (double)qr[j].x - vh[0];
+          const double dy = (double)qr[j].y - vh[1];
+          const double dz = (double)qr[j].z - vh[2];
+          const double ke = 0.5 * (dx * dx + dy * dy + dz * dz);
+          gone = ke > fabs(phi);
+        }
+        const bool keep = k < na && !gone;
+        const uint64_t kb_ = __ballot(keep);
+        const uint64_t gb_ = __ballot(gone);
+        if (lane == 0) {
+          wkeep[par][w] = (uint32_t)__popcll(kb_);
+          wgone[par][w] = (uint32_t)__popcll(gb_);
+        }
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (int q = 0; q < BW; ++q) {
+          if (q < w) before += wkeep[par][q];
+          all += wkeep[par][q];
+          ngone += wgone[par][q];
+        }
+        if (keep) {
+          const uint32_t at = kept + before + (uint32_t)__popcll(kb_ & lanes_below());
+          K[at] = keyr[j];
+          I[at] = ir[j];
+          V[at] = qr[j];
+        }
+        kept += all;
       }
-      // writes land at or before the reads of this chunk, which are done
-      if (keep) {
-        const uint32_t at = kept + before + (uint32_t)__popcll(kb_ & lanes_below());
-        K[at] = key;
-        I[at] = i;
-      }
-      kept += all;
-      // count the unbound ones (every wave adds its own, in wave order)
-      __syncthreads();
-      if (lane == 0) wtot[w] = (uint32_t)__popcll(gb_);
-      __syncthreads();
-      for (int j = 0; j < kHW; ++j) ngone += wtot[j];
-      __syncthreads();
     }
     if (ngone == 0) {
       // converged: the particles within r_vir (the first v+1 in radius order)
@@ -583,17 +850,14 @@ __global__ __launch_bounds__(kHT) void k_unbind(
     nmem = 0;
     r_vir = 0.0;
   }
-  // the members by index: the first nmem of I, sorted by particle index
+  // the members: the first nmem in radius order
   uint32_t* out = member + off;
-  for (uint32_t k = threadIdx.x; k < nmem; k += kHT) out[k] = I[k];
-  __syncthreads();
-  uint32_t* spare = (I == ia) ? ib : ia;
-  if (block_sort<uint32_t>(out, out, spare, spare, nmem))
-    for (uint32_t k = threadIdx.x; k < nmem; k += kHT) out[k] = spare[k];
-  __syncthreads();
   double mm = 0.0;
-  for (uint32_t k = threadIdx.x; k < nmem; k += kHT) mm += pmass(P, out[k]);
-  mm = block_sum(mm, red);
+  for (uint32_t k = threadIdx.x; k < nmem; k += BT) {
+    out[k] = I[k];
+    mm += vmass(P, V[k]);
+  }
+  mm = block_sum<BT>(mm, red);
   m_vir = nmem ? mm : 0.0;
   if (threadIdx.x == 0) {
     member_cnt[s] = nmem;
@@ -742,17 +1006,33 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   uint64_t* key_b = ws.get<uint64_t>(t1);
   double* msum = ws.get<double>(t1);
   double* tail = ws.get<double>(t1);
-  k_candidates<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
-                                             iso_cnt, iso_list, h->prm.g, l0.Sstart, l0.Scount,
-                                             h->order, P, out->cand_off, out->cand,
-                                             out->cand_cnt);
+  float4* vbuf = ws.get<float4>(t1);
+  // one workgroup per structure: of kHT threads, or of kHTBig for those with
+  // at least kBigCand possible candidates (the few that hold most of them)
+  k_candidates<kHT><<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
+                                                  iso_cnt, iso_list, h->prm.g, l0.Sstart,
+                                                  l0.Scount, h->order, P, out->cand_off,
+                                                  out->cand, out->cand_cnt, kBigCand);
+  HIP_LAUNCH_CHECK();
+  k_candidates<kHTBig><<<(unsigned)ns, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius,
+                                                        iso_off, iso_cnt, iso_list, h->prm.g,
+                                                        l0.Sstart, l0.Scount, h->order, P,
+                                                        out->cand_off, out->cand,
+                                                        out->cand_cnt, kBigCand);
   HIP_LAUNCH_CHECK();
   const double rho_b = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
-  k_unbind<<<(unsigned)ns, kHT, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, idx_a, idx_b,
-                                         key_a, key_b, msum, tail, out->centre, P,
-                                         delta_vir * rho_b, G, max_iter, out->member,
-                                         out->member_cnt, out->r_vir, out->m_vir, out->vel,
-                                         out->iters);
+  k_unbind<kHT><<<(unsigned)ns, kHT, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, idx_a,
+                                              idx_b, key_a, key_b, msum, tail, vbuf, out->centre,
+                                              P, delta_vir * rho_b, G, max_iter, out->member,
+                                              out->member_cnt, out->r_vir, out->m_vir, out->vel,
+                                              out->iters, kBigCand);
+  HIP_LAUNCH_CHECK();
+  k_unbind<kHTBig><<<(unsigned)ns, kHTBig, 0, st>>>(out->cand_off, out->cand_cnt, out->cand,
+                                                    idx_a, idx_b, key_a, key_b, msum, tail, vbuf,
+                                                    out->centre, P, delta_vir * rho_b, G,
+                                                    max_iter, out->member, out->member_cnt,
+                                                    out->r_vir, out->m_vir, out->vel, out->iters,
+                                                    kBigCand);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipStreamSynchronize(st));
 }

@@ -68,9 +68,9 @@ def test_halos_16m_sampled():
             if depth[s] > 0:
                 d = H.min_image(pos - res["centre"][s])
                 want = np.nonzero((d * d).sum(axis=1) <= res["radius"][s] ** 2)[0]
-                assert np.array_equal(cand, want), s
+                assert np.array_equal(np.sort(cand), want), s
             u = H.unbind(cand, pos, velf, mass, res["centre"][s], rho_b)
-            assert np.array_equal(res["members"][s].astype(np.int64), u["members"]), s
+            assert np.array_equal(np.sort(res["members"][s].astype(np.int64)), u["members"]), s
             assert int(res["iterations"][s]) == u["iterations"], s
             for k in ("r_vir", "m_vir"):
                 assert abs(res[k][s] - u[k]) <= 1e-12 * max(abs(u[k]), 1e-300), (s, k)
