@@ -302,6 +302,86 @@ __device__ inline uint64_t cube_cell(const int64_t* lo, const int64_t* nc, uint6
   return morton3(x, y, z);
 }
 
+// The cells of every built level (the hierarchy's device arrays), for the
+// sphere queries; level 0 is dense (its S index is the key)
+struct LevCells {
+  const uint64_t* key[kMaxLevels];
+  const uint32_t* start[kMaxLevels];
+  const uint32_t* count[kMaxLevels];
+  uint64_t n[kMaxLevels];
+  int nlev;
+  int g;
+};
+
+constexpr int kQCells = 125;  // cube cells of a query on a level whose cells are >= R/2 wide
+
+// The level a sphere of radius R is queried on: the deepest built level whose
+// cells are at least R/2 wide, so that at most 5 per axis cover the sphere
+// (level 0 when even its cells are narrower)
+__device__ inline int query_level(const LevCells& LC, double R) {
+  int L = LC.nlev - 1;
+  while (L > 0 && ldexp(1.0, -(LC.g + L)) < 0.5 * R) --L;
+  return L;
+}
+
+// The deepest cell of the hierarchy containing the level-L cell `key`: the
+// cell itself when its parent was refined, else the nearest ancestor that
+// exists (every level-0 cell does); its level and S index
+__device__ inline void resolve_cell(const LevCells& LC, int L, uint64_t key, int* lout,
+                                    uint64_t* iout) {
+  for (;;) {
+    if (L == 0) {
+      *lout = 0;
+      *iout = key;
+      return;
+    }
+    const uint64_t* K = LC.key[L];
+    uint64_t lo = 0, hi = LC.n[L];
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (K[mid] < key) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < LC.n[L] && K[lo] == key) {
+      *lout = L;
+      *iout = lo;
+      return;
+    }
+    key >>= 3;
+    --L;
+  }
+}
+
+// The particle ranges a sphere query scans when its cube on level L has at
+// most kQCells cells: each cube cell resolved to the deepest cell containing
+// it; the resolved cells are the leaves of the hierarchy cut at level L, so
+// two are equal or disjoint, and the distinct ones cover the cube.  Their
+// starts and counts go to qa, qc (LDS, in no particular order); returns their
+// number (every thread).
+template <int BT>
+__device__ inline uint32_t fine_cells(const LevCells& LC, int L, const int64_t* lo,
+                                      const int64_t* nc, uint64_t ncell, uint32_t* qa,
+                                      uint32_t* qc) {
+  __shared__ int ql[kQCells];
+  __shared__ uint64_t qi[kQCells];
+  __shared__ uint32_t nq;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) nq = 0;
+  if (t < ncell) resolve_cell(LC, L, cube_cell(lo, nc, t, LC.g + L), &ql[t], &qi[t]);
+  __syncthreads();
+  if (t < ncell) {
+    bool dup = false;
+    for (uint32_t u = 0; u < t; ++u) dup = dup || (ql[u] == ql[t] && qi[u] == qi[t]);
+    if (!dup) {
+      const uint32_t at = atomicAdd(&nq, 1u);
+      qa[at] = LC.start[ql[t]][qi[t]];
+      qc[at] = LC.count[ql[t]][qi[t]];
+    }
+  }
+  __syncthreads();
+  return nq;
+}
+
 // collection radius and an upper bound of the candidates: a host's
 // isodensity patch count; a substructure's sphere (half the distance to its
 // host's centre): the particles of the level-0 cells it may touch
@@ -309,11 +389,12 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
                                                const int32_t* __restrict__ s_host,
                                                const unsigned long long* __restrict__ ext,
                                                const double* __restrict__ centre,
-                                               const uint32_t* __restrict__ iso_cnt, int g,
-                                               const uint32_t* __restrict__ count0,
+                                               const uint32_t* __restrict__ iso_cnt,
+                                               const LevCells LC,
                                                double* __restrict__ radius,
                                                uint32_t* __restrict__ bound) {
   __shared__ double red[kHW];
+  __shared__ uint32_t qa[kQCells], qc[kQCells];
   const uint32_t s = blockIdx.x;
   if (s_depth[s] == 0) {
     if (threadIdx.x == 0) {
@@ -336,11 +417,19 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
   const double half = 0.5 * sqrt(sx * sx + sy * sy + sz * sz);
   const double e = __longlong_as_double((long long)ext[s]);
   const double R = e < half ? e : half;  // capped by the start patch's extent
+  // the particles of the cells the query scans (integers, exact in FP64)
+  const int L = query_level(LC, R);
   int64_t lo[3], nc[3];
-  cube_of(c, R, g, lo, nc);
+  cube_of(c, R, LC.g + L, lo, nc);
   const uint64_t ncell = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
   double t = 0.0;
-  for (uint64_t k = threadIdx.x; k < ncell; k += kHT) t += (double)count0[cube_cell(lo, nc, k, g)];
+  if (ncell <= kQCells) {
+    const uint32_t nq = fine_cells<kHT>(LC, L, lo, nc, ncell, qa, qc);
+    for (uint32_t k = threadIdx.x; k < nq; k += kHT) t += (double)qc[k];
+  } else {  // level 0, a sphere wider than several of its cells
+    for (uint64_t k = threadIdx.x; k < ncell; k += kHT)
+      t += (double)LC.count[0][cube_cell(lo, nc, k, LC.g)];
+  }
   t = block_sum(t, red);
   if (threadIdx.x == 0) {
     radius[s] = R;
@@ -349,17 +438,18 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
 }
 
 // the candidates of every structure, unordered: a host's isodensity list, a
-// substructure's particles within its radius.  The cells of a substructure's
-// cube go in chunks of one cell per thread; the chunk's particles are then
-// spread over all threads (a dense cell holds many), each finding its cell by
-// a binary search of the chunk's particle offsets.
+// substructure's particles within its radius.  A substructure scans the cells
+// its query level gives (at most kQCells, else level-0 cells in chunks of one
+// per thread); the particles of a chunk of cells are spread over all threads
+// (a dense cell holds many), each finding its cell by a binary search of the
+// chunk's particle offsets.
 template <int BT>
 __global__ __launch_bounds__(BT) void k_candidates(
     const int32_t* __restrict__ s_depth, const double* __restrict__ centre,
     const double* __restrict__ radius, const uint64_t* __restrict__ iso_off,
-    const uint32_t* __restrict__ iso_cnt, const uint32_t* __restrict__ iso_list, int g,
-    const uint32_t* __restrict__ start0, const uint32_t* __restrict__ count0,
-    const uint32_t* __restrict__ order, PartIn P, const uint64_t* __restrict__ cand_off,
+    const uint32_t* __restrict__ iso_cnt, const uint32_t* __restrict__ iso_list,
+    const LevCells LC, const uint32_t* __restrict__ order, PartIn P,
+    const uint64_t* __restrict__ cand_off,
     uint32_t* __restrict__ cand, uint32_t* __restrict__ cand_cnt, uint64_t big) {
   constexpr int BW = BT / 64;
   // structures with at least `big` possible candidates go to the wide workgroups
@@ -381,16 +471,25 @@ __global__ __launch_bounds__(BT) void k_candidates(
   const double* c = centre + 3 * (uint64_t)s;
   const double R = radius[s];
   const double R2 = R * R;
+  const int L = query_level(LC, R);
   int64_t lo[3], nc[3];
-  cube_of(c, R, g, lo, nc);
-  const uint64_t ncell = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
+  cube_of(c, R, LC.g + L, lo, nc);
+  const uint64_t ncube = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
+  const bool fine = ncube <= kQCells;
+  __shared__ uint32_t qa[kQCells], qc[kQCells];
+  const uint64_t ncell = fine ? fine_cells<BT>(LC, L, lo, nc, ncube, qa, qc) : ncube;
   for (uint64_t k0 = 0; k0 < ncell; k0 += BT) {
     const uint64_t k = k0 + threadIdx.x;
     uint32_t a = 0, cnt = 0;
     if (k < ncell) {
-      const uint64_t cell = cube_cell(lo, nc, k, g);
-      a = start0[cell];
-      cnt = count0[cell];
+      if (fine) {
+        a = qa[k];
+        cnt = qc[k];
+      } else {  // level 0
+        const uint64_t cell = cube_cell(lo, nc, k, LC.g);
+        a = LC.start[0][cell];
+        cnt = LC.count[0][cell];
+      }
     }
     // exclusive offsets (counts below 2^32 are exact in FP64)
     double tot = 0.0;
@@ -973,7 +1072,6 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
       HIP_LAUNCH_CHECK();
     }
   }
-  const Level& l0 = h->lev[0];
   k_centre<<<(unsigned)ns, kHT, 0, st>>>(leaf_off, leaf_cnt, leaf_list, leaf_tmp, out->leafkey,
                                          leaf_min, h->prm.g, P, out->centre);
   HIP_LAUNCH_CHECK();
@@ -988,8 +1086,18 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
                                                 h->s_level, h->s_patch, out->centre, ext);
     HIP_LAUNCH_CHECK();
   }
-  k_bound<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, h->s_host, ext, out->centre, iso_cnt,
-                                        h->prm.g, l0.Scount, out->radius, bound);
+  LevCells LC{};
+  LC.nlev = (int)nlev;
+  LC.g = h->prm.g;
+  for (size_t L = 0; L < nlev; ++L) {
+    const Level& lv = h->lev[L];
+    LC.key[L] = lv.Skey;
+    LC.start[L] = lv.Sstart;
+    LC.count[L] = lv.Scount;
+    LC.n[L] = lv.nS;
+  }
+  k_bound<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, h->s_host, ext, out->centre, iso_cnt, LC,
+                                        out->radius, bound);
   HIP_LAUNCH_CHECK();
   k_offsets<<<1, kHT, 0, st>>>(bound, ns, out->cand_off);
   HIP_LAUNCH_CHECK();
@@ -1010,14 +1118,13 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   // one workgroup per structure: of kHT threads, or of kHTBig for those with
   // at least kBigCand possible candidates (the few that hold most of them)
   k_candidates<kHT><<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
-                                                  iso_cnt, iso_list, h->prm.g, l0.Sstart,
-                                                  l0.Scount, h->order, P, out->cand_off,
-                                                  out->cand, out->cand_cnt, kBigCand);
+                                                  iso_cnt, iso_list, LC, h->order, P,
+                                                  out->cand_off, out->cand, out->cand_cnt,
+                                                  kBigCand);
   HIP_LAUNCH_CHECK();
   k_candidates<kHTBig><<<(unsigned)ns, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius,
-                                                        iso_off, iso_cnt, iso_list, h->prm.g,
-                                                        l0.Sstart, l0.Scount, h->order, P,
-                                                        out->cand_off, out->cand,
+                                                        iso_off, iso_cnt, iso_list, LC,
+                                                        h->order, P, out->cand_off, out->cand,
                                                         out->cand_cnt, kBigCand);
   HIP_LAUNCH_CHECK();
   const double rho_b = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
