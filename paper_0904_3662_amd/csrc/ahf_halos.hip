@@ -540,6 +540,40 @@ __global__ __launch_bounds__(BT) void k_candidates(
   if (threadIdx.x == 0) cand_cnt[s] = cursor;
 }
 
+// The radius and the velocity and mass of every candidate of the structures
+// unbound by the wide workgroups, by candidate slot, computed by the whole
+// grid (their loads by particle index are scattered; one workgroup on one
+// compute unit would take them one after another): rad at the slot (the
+// unbinding's msum scratch), vq at the slot.  Slots past a structure's count
+// are left alone.
+__global__ void k_big_data(const uint64_t* __restrict__ cand_off,
+                           const uint32_t* __restrict__ cand_cnt,
+                           const uint32_t* __restrict__ cand, uint64_t ns, uint64_t total,
+                           const double* __restrict__ centre, PartIn P, uint64_t big,
+                           double* __restrict__ rad, float4* __restrict__ vq) {
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < total;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    // the structure of slot j: the last s with cand_off[s] <= j
+    uint64_t lo = 0, hi = ns - 1;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi + 1) >> 1;
+      if (cand_off[mid] <= j) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint64_t s = lo, o = cand_off[s];
+    if (cand_off[s + 1] - o < big || j - o >= cand_cnt[s]) continue;
+    const uint32_t i = cand[j];
+    const double* c = centre + 3 * s;
+    const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
+    const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
+    const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r < kHalfQuantum) r = kHalfQuantum;
+    rad[j] = r;
+    vq[j] = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+  }
+}
+
 // inclusive scan of one value per thread over the workgroup, in thread
 // order, with one barrier: consecutive calls alternate between the two
 // halves of red (par), so a call never overwrites what the one before it
@@ -601,8 +635,8 @@ template <int BT>
 __global__ __launch_bounds__(BT) void k_unbind(
     const uint64_t* __restrict__ cand_off, const uint32_t* __restrict__ cand_cnt, uint32_t* cand,
     uint32_t* idx_a, uint32_t* idx_b, uint64_t* key_a, uint64_t* key_b, double* msum,
-    double* tail, float4* vbuf, const double* __restrict__ centre, PartIn P, double rho_thr,
-    double G,
+    double* tail, float4* vbuf, const float4* __restrict__ vslot,
+    const double* __restrict__ centre, PartIn P, double rho_thr, double G,
     uint32_t max_iter, uint32_t* __restrict__ member, uint32_t* __restrict__ member_cnt,
     double* __restrict__ r_vir_out, double* __restrict__ m_vir_out, double* __restrict__ vel_out,
     uint32_t* __restrict__ iters_out, uint64_t big) {
@@ -623,6 +657,9 @@ __global__ __launch_bounds__(BT) void k_unbind(
   double* M = msum + off;
   double* T = tail + off;
   float4* V = vbuf + off;
+  const float4* VS = vslot + off;
+  // the wide workgroups find radii and velocities by slot (k_big_data)
+  constexpr bool kPre = BT > kHT;
   const double* c = centre + 3 * (uint64_t)s;
   const int lane = __lane_id(), w = threadIdx.x >> 6;
 
@@ -635,6 +672,12 @@ __global__ __launch_bounds__(BT) void k_unbind(
   // sort instead: by index, then stably by the whole radius.
   __shared__ uint32_t long_tie;
   if (threadIdx.x == 0) long_tie = 0;
+  if (kPre) {
+    for (uint32_t k = threadIdx.x; k < n; k += BT) {
+      ka[k] = (uint64_t)__double_as_longlong(M[k]) >> (64 - kRadiusBits);
+      ia[k] = k;
+    }
+  } else {
   for (uint32_t k0 = threadIdx.x; k0 < n; k0 += kRows * BT) {
     // kRows particles per thread, their (random) coordinate loads together
     uint32_t pi[kRows];
@@ -663,6 +706,7 @@ __global__ __launch_bounds__(BT) void k_unbind(
       ia[k] = k;
     }
   }
+  }
   __syncthreads();
   const bool ft = block_sort<uint64_t, BT>(ka, ia, kb, ib, n);
   const uint64_t* Kt = ft ? kb : ka;  // truncated radii, sorted
@@ -676,6 +720,7 @@ __global__ __launch_bounds__(BT) void k_unbind(
     for (int j = 0; j < kRows; ++j) sl[j] = (k0 + j * BT < n) ? St[k0 + j * BT] : 0u;
     double rv_[kRows];
     uint32_t iv[kRows];
+    float4 qv[kRows];
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
       if (k0 + j * BT < n) {
@@ -685,10 +730,19 @@ __global__ __launch_bounds__(BT) void k_unbind(
     }
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
+      if (k0 + j * BT < n) {
+        const uint32_t i = iv[j];
+        qv[j] = kPre ? VS[sl[j]]
+                     : make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
       const uint32_t k = k0 + j * BT;
       if (k >= n) break;
       K[k] = (uint64_t)__double_as_longlong(rv_[j]);
       I[k] = iv[j];
+      V[k] = qv[j];
     }
   }
   __syncthreads();
@@ -709,14 +763,17 @@ __global__ __launch_bounds__(BT) void k_unbind(
       for (uint32_t q = k + 1; q < e; ++q) {
         const uint64_t kq = K[q];
         const uint32_t iq = I[q];
+        const float4 vq = V[q];
         uint32_t r = q;
         while (r > k && (K[r - 1] > kq || (K[r - 1] == kq && I[r - 1] > iq))) {
           K[r] = K[r - 1];
           I[r] = I[r - 1];
+          V[r] = V[r - 1];
           --r;
         }
         K[r] = kq;
         I[r] = iq;
+        V[r] = vq;
       }
     }
     __syncthreads();
@@ -747,23 +804,14 @@ __global__ __launch_bounds__(BT) void k_unbind(
       }
     }
     __syncthreads();
+    for (uint32_t k = threadIdx.x; k < n; k += BT) {
+      const uint32_t i = I[k];
+      V[k] = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+    }
+    __syncthreads();
   }
   // the view's candidates: in radius order
   for (uint32_t k = threadIdx.x; k < n; k += BT) cs[k] = I[k];
-  __syncthreads();
-  for (uint32_t k0 = threadIdx.x; k0 < n; k0 += kRows * BT) {
-    uint32_t pi[kRows];
-    float4 q[kRows];
-#pragma unroll
-    for (int j = 0; j < kRows; ++j) pi[j] = (k0 + j * BT < n) ? I[k0 + j * BT] : 0u;
-#pragma unroll
-    for (int j = 0; j < kRows; ++j)
-      if (k0 + j * BT < n)
-        q[j] = make_float4(P.vx[pi[j]], P.vy[pi[j]], P.vz[pi[j]], P.mass ? P.mass[pi[j]] : 0.0f);
-#pragma unroll
-    for (int j = 0; j < kRows; ++j)
-      if (k0 + j * BT < n) V[k0 + j * BT] = q[j];
-  }
   __syncthreads();
   int sc = 0;  // scans so far (their half of rsc)
 
@@ -1115,33 +1163,50 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   double* msum = ws.get<double>(t1);
   double* tail = ws.get<double>(t1);
   float4* vbuf = ws.get<float4>(t1);
-  // one workgroup per structure: of kHT threads, or of kHTBig for those with
-  // at least kBigCand possible candidates (the few that hold most of them)
-  k_candidates<kHT><<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
-                                                  iso_cnt, iso_list, LC, h->order, P,
-                                                  out->cand_off, out->cand, out->cand_cnt,
-                                                  kBigCand);
-  HIP_LAUNCH_CHECK();
+  float4* vslot = ws.get<float4>(t1);
+  const double rho_b = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
+  // One workgroup per structure: of kHTBig threads for those with at least
+  // kBigCand possible candidates (the few that hold most of them), on st, with
+  // their radii and velocities found by the whole grid first; of kHT threads
+  // for the others, on a second stream beside them.
+  if (!ctx->dep_st) HIP_CHECK(hipStreamCreateWithFlags(&ctx->dep_st, hipStreamNonBlocking));
+  hipStream_t s2 = ctx->dep_st;
+  hipEvent_t fork = nullptr, join = nullptr;
+  HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  HIP_CHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  HIP_CHECK(hipEventRecord(fork, st));
+  HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
   k_candidates<kHTBig><<<(unsigned)ns, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius,
                                                         iso_off, iso_cnt, iso_list, LC,
                                                         h->order, P, out->cand_off, out->cand,
                                                         out->cand_cnt, kBigCand);
   HIP_LAUNCH_CHECK();
-  const double rho_b = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
-  k_unbind<kHT><<<(unsigned)ns, kHT, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, idx_a,
-                                              idx_b, key_a, key_b, msum, tail, vbuf, out->centre,
-                                              P, delta_vir * rho_b, G, max_iter, out->member,
-                                              out->member_cnt, out->r_vir, out->m_vir, out->vel,
-                                              out->iters, kBigCand);
+  k_big_data<<<blocks_for(total), kHB, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, ns,
+                                                total, out->centre, P, kBigCand, msum, vslot);
   HIP_LAUNCH_CHECK();
   k_unbind<kHTBig><<<(unsigned)ns, kHTBig, 0, st>>>(out->cand_off, out->cand_cnt, out->cand,
                                                     idx_a, idx_b, key_a, key_b, msum, tail, vbuf,
-                                                    out->centre, P, delta_vir * rho_b, G,
+                                                    vslot, out->centre, P, delta_vir * rho_b, G,
                                                     max_iter, out->member, out->member_cnt,
                                                     out->r_vir, out->m_vir, out->vel, out->iters,
                                                     kBigCand);
   HIP_LAUNCH_CHECK();
+  k_candidates<kHT><<<(unsigned)ns, kHT, 0, s2>>>(h->s_depth, out->centre, out->radius, iso_off,
+                                                  iso_cnt, iso_list, LC, h->order, P,
+                                                  out->cand_off, out->cand, out->cand_cnt,
+                                                  kBigCand);
+  HIP_LAUNCH_CHECK();
+  k_unbind<kHT><<<(unsigned)ns, kHT, 0, s2>>>(out->cand_off, out->cand_cnt, out->cand, idx_a,
+                                              idx_b, key_a, key_b, msum, tail, vbuf, vslot,
+                                              out->centre, P, delta_vir * rho_b, G, max_iter,
+                                              out->member, out->member_cnt, out->r_vir,
+                                              out->m_vir, out->vel, out->iters, kBigCand);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipEventRecord(join, s2));
+  HIP_CHECK(hipStreamWaitEvent(st, join, 0));
   HIP_CHECK(hipStreamSynchronize(st));
+  HIP_CHECK(hipEventDestroy(fork));
+  HIP_CHECK(hipEventDestroy(join));
 }
 
 }  // namespace ahf
