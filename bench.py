@@ -29,7 +29,8 @@ METRIC = "particles/s through full hierarchy build (1 GPU, % HBM peak); p50/p99 
 # the files every kernel of the library is compiled from: a PMC summary holds
 # their SHA-256 and is used only while they are unchanged
 KERNEL_SRC = [os.path.join(ROOT, "paper_0904_3662_amd", "csrc", f)
-              for f in ("ahf_prims.hip", "ahf_levels.hip", "ahf_dev.h", "ahf_internal.h")]
+              for f in ("ahf_prims.hip", "ahf_levels.hip", "ahf_dev.h", "ahf_internal.h",
+                        "ahf_block.h")]
 
 
 def kernel_source_hash():
