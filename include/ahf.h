@@ -228,6 +228,9 @@ typedef struct {
     uint32_t replanned;     /* 1: a planned attempt outgrew its room first    */
     uint32_t host_waits;    /* host waits for level counts during the build   */
     uint64_t device_bytes;  /* device memory the hierarchy holds              */
+    uint32_t sort_key_bits; /* key bits the radix sort ordered by (3 B less the
+                             * low bits it left out)                         */
+    uint32_t sort_passes;   /* its 8-bit passes                               */
 } ahf_build_info;
 ahf_status ahf_hierarchy_build_info(const ahf_hierarchy *h, ahf_build_info *out);
 
@@ -252,10 +255,12 @@ typedef struct {
     uint32_t heavy_level1;      /* 1..64 */
     uint32_t heavy_deeper;      /* 1..64 */
     uint32_t batch_level1;      /* 2 or 4 */
-    int32_t sort_skip_digits;   /* -1: chosen by size; else 0..2 low 8-bit key digits the
-                                 * radix sort leaves out, put in order afterwards only for
-                                 * the particles of the refined cells of the deepest level
-                                 * whose cells do not depend on them */
+    int32_t sort_skip_digits;   /* -1: chosen by depth (2 when the keys hold 12 or more
+                                 * levels below the domain grid, 1 for 9 or more, else 0);
+                                 * else 0..2 low 8-bit key digits the radix sort leaves
+                                 * out (never a bit of the domain grid); the particles
+                                 * that only those digits order are then put in full-key
+                                 * order, so the result is the same full stable sort */
 } ahf_tuning;
 
 /* Sets the context's tuning table: a build of n particles uses entries[i]

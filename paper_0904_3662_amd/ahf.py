@@ -90,7 +90,8 @@ class Tuning(C.Structure):
 
 class BuildInfo(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("planned", C.c_uint32), ("replanned", C.c_uint32),
-                ("host_waits", C.c_uint32), ("device_bytes", C.c_uint64)]
+                ("host_waits", C.c_uint32), ("device_bytes", C.c_uint64),
+                ("sort_key_bits", C.c_uint32), ("sort_passes", C.c_uint32)]
 
 
 class HaloParams(C.Structure):

@@ -525,6 +525,8 @@ ahf_status ahf_hierarchy_build_info(const ahf_hierarchy* h, ahf_build_info* out)
   out->replanned = h->h.replanned ? 1u : 0u;
   out->host_waits = h->h.host_waits;
   out->device_bytes = h->h.mem.bytes();
+  out->sort_key_bits = h->h.sort_key_bits;
+  out->sort_passes = h->h.sort_passes;
   return AHF_OK;
 }
 

@@ -369,6 +369,7 @@ struct Hier {
   bool replanned = false;  // a planned attempt outgrew its capacities and was redone
   const uint64_t* dev_status = nullptr;  // the build's totals, counters and flags (in_graph)
   uint32_t host_waits = 0;  // times the host waited for the device during the build
+  uint32_t sort_key_bits = 0, sort_passes = 0;  // what the radix sort ordered by
   double ms[4] = {0, 0, 0, 0};
   double t_start = 0.0;  // host clock at the start of the build
 };

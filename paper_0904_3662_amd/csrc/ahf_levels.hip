@@ -1856,6 +1856,8 @@ void build_hierarchy(Ctx* ctx, Ws& ws, Ws& wsd, const ahf_particles& p, const Pa
   uint64_t* keys = ws.get<uint64_t>(n);
   uint4* rec = ws.get<uint4>(2 * n);
   const SortPlan sp = sort_plan(n, 3 * B - skip);
+  h->sort_key_bits = (uint32_t)(3 * B - skip);
+  h->sort_passes = n ? (uint32_t)sp.npass : 0u;
   h->order = h->mem.get<uint32_t>(n);
   uint4* srec = ws.get<uint4>(2 * n);
   uint64_t* skey = keys;

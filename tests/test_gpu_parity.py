@@ -241,6 +241,9 @@ def test_sort_with_skipped_digits_matches_oracle(name, make, skip):
         for rep in range(2):  # synced, then sized ahead
             h, _ = ahf.build_snapshot(c, p, dev=dev)
             compare_hierarchy(h, p.n, levels, order)
+            info = h.build_info()
+            bits = 3 * min(p.g + p.max_levels, 21) - 8 * skip
+            assert info["sort_key_bits"] == bits and info["sort_passes"] == (bits + 7) // 8
             h.free()
 
 
