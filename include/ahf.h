@@ -436,6 +436,10 @@ typedef struct {
     double delta_vir;       /* virial overdensity (the paper's mass functions use 340) */
     double G;               /* gravitational constant in the caller's units */
     uint32_t max_iter;      /* at most this many unbinding rounds (>= 1) */
+    uint32_t large_from;    /* structures with at least this many possible candidates are
+                             * unbound by the whole GPU together, the others by one
+                             * workgroup each (0: 32768); the results do not depend on it
+                             * beyond FP64 summation order */
 } ahf_halo_params;
 
 typedef struct ahf_halos ahf_halos;

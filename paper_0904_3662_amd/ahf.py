@@ -96,7 +96,7 @@ class BuildInfo(C.Structure):
 
 class HaloParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("delta_vir", C.c_double), ("G", C.c_double),
-                ("max_iter", C.c_uint32)]
+                ("max_iter", C.c_uint32), ("large_from", C.c_uint32)]
 
 
 class HalosView(C.Structure):
@@ -670,7 +670,8 @@ class Batch:
 
 
 def find_halos(ctx: Context, h: Hierarchy, dev, vel, delta_vir: float = 340.0, G: float = 1.0,
-               max_iter: int = 1000, stream=None, fetch: bool = True) -> dict:
+               max_iter: int = 1000, stream=None, fetch: bool = True,
+               large_from: int = 0) -> dict:
     """Particle collection and unbinding of every structure of a classified
     hierarchy (ahf_find_halos); dev holds the particle tensors the hierarchy
     was built from, vel the (n, 3) velocities on the device.  Returns the
@@ -679,7 +680,8 @@ def find_halos(ctx: Context, h: Hierarchy, dev, vel, delta_vir: float = 340.0, G
     vel = vel.contiguous()
     vx, vy, vz = (vel[:, k].contiguous() for k in range(3))
     parts = make_particles(*dev[:6], dev[6])
-    prm = HaloParams(C.sizeof(HaloParams), float(delta_vir), float(G), int(max_iter))
+    prm = HaloParams(C.sizeof(HaloParams), float(delta_vir), float(G), int(max_iter),
+                     int(large_from))
     out = C.c_void_p()
     _check(load().ahf_find_halos(ctx.handle, h.handle, C.byref(parts), _ptr(vx), _ptr(vy),
                                  _ptr(vz), C.byref(prm), _stream_handle(stream), C.byref(out)))

@@ -50,7 +50,7 @@ constexpr int kRows = 4;             // rows of a workgroup's width whose loads 
 constexpr int kSeq = 4;              // consecutive particles per thread in the unbinding scans
 constexpr int kRadiusBits = 40;      // top bits of a radius' bit pattern the sort orders by
 constexpr uint32_t kShortTie = 64;   // longest run of tied truncated radii put in order in place
-constexpr uint64_t kBigCand = 32768; // possible candidates from which a structure counts as large
+constexpr uint64_t kBigCand = 32768; // possible candidates from which a structure is wide (default)
 constexpr double kQuantum = 1.0 / (double)(1u << kQBits);
 constexpr double kHalfQuantum = 0.5 / (double)(1u << kQBits);
 
@@ -450,15 +450,17 @@ __global__ __launch_bounds__(BT) void k_candidates(
     const uint32_t* __restrict__ iso_cnt, const uint32_t* __restrict__ iso_list,
     const LevCells LC, const uint32_t* __restrict__ order, PartIn P,
     const uint64_t* __restrict__ cand_off,
-    uint32_t* __restrict__ cand, uint32_t* __restrict__ cand_cnt, uint64_t big) {
+    uint32_t* __restrict__ cand, uint32_t* __restrict__ cand_cnt, uint64_t big,
+    const uint32_t* __restrict__ sel) {
   constexpr int BW = BT / 64;
-  // structures with at least `big` possible candidates go to the wide workgroups
-  if ((cand_off[blockIdx.x + 1] - cand_off[blockIdx.x] >= big) != (BT > kHT)) return;
+  // block b takes structure sel[b] (the wide list) or b; structures with at
+  // least `big` possible candidates go to the wide workgroups
+  const uint32_t s = sel ? sel[blockIdx.x] : blockIdx.x;
+  if ((cand_off[s + 1] - cand_off[s] >= big) != (BT > kHT)) return;
   __shared__ uint32_t cursor;
   __shared__ uint32_t cofs[BT + 1];  // the chunk's particle offsets per cell
   __shared__ uint32_t cst[BT];       // and each cell's first sorted position
   __shared__ double red[BW];
-  const uint32_t s = blockIdx.x;
   uint32_t* out = cand + cand_off[s];
   if (s_depth[s] == 0) {
     const uint32_t n = iso_cnt[s];
@@ -639,14 +641,18 @@ __global__ __launch_bounds__(BT) void k_unbind(
     const double* __restrict__ centre, PartIn P, double rho_thr, double G,
     uint32_t max_iter, uint32_t* __restrict__ member, uint32_t* __restrict__ member_cnt,
     double* __restrict__ r_vir_out, double* __restrict__ m_vir_out, double* __restrict__ vel_out,
-    uint32_t* __restrict__ iters_out, uint64_t big) {
+    uint32_t* __restrict__ iters_out, const uint32_t* __restrict__ mode,
+    const uint32_t* __restrict__ sel) {
   constexpr int BW = BT / 64;
-  if ((cand_off[blockIdx.x + 1] - cand_off[blockIdx.x] >= big) != (BT > kHT)) return;
+  // block b takes structure sel[b] (the wide list) or b; mode 0: the small
+  // structures (kHT threads); mode 2: wide structures with long runs of tied
+  // radii (kHTBig threads); mode 1 goes through the grid
+  const uint32_t s = sel ? sel[blockIdx.x] : blockIdx.x;
+  if (mode[s] != (BT > kHT ? 2u : 0u)) return;
   __shared__ double red[BW];
   __shared__ double rsc[2][BW];  // the scans, alternating halves
   __shared__ int64_t redi[BW];
   __shared__ uint32_t wkeep[2][BW], wgone[2][BW];  // the compaction, alternating halves
-  const uint32_t s = blockIdx.x;
   const uint64_t off = cand_off[s];
   const uint32_t n = cand_cnt[s];
   uint32_t* cs = cand + off;
@@ -1017,6 +1023,764 @@ __global__ __launch_bounds__(BT) void k_unbind(
   }
 }
 
+// ---------------------------------------------------------------- wide unbinding
+//
+// The structures with many possible candidates (the "wide" set: a few hundred
+// that hold most of the candidates) are unbound by the whole grid together
+// instead of by one workgroup each: one global radix sort puts every wide
+// structure's candidates in (structure, radius) order in one array, each
+// structure at its own offset; then every round runs as chunk kernels over
+// all still-active structures (a chunk is kWC consecutive particles of one
+// structure) and segment kernels that combine a structure's chunks in chunk
+// order, one wave per structure.  Every sum has a fixed order, so reruns are
+// bit-identical; the host reads one count per round (the structures still
+// active).
+
+constexpr int kWT = 256;                 // threads of the chunk kernels
+constexpr int kWE = 16;                  // particles per thread and chunk
+constexpr uint32_t kWC = kWT * kWE;      // particles per chunk
+constexpr int kTruncShift = 64 - kRadiusBits;  // radius bits the sort leaves out
+
+// segment (wide structure) and chunk of block b in this round's chunk table
+// (cofs: nG + 1 exclusive chunk offsets); false past the table's end
+__device__ inline bool chunk_of(const uint32_t* __restrict__ cofs, uint32_t nG, uint32_t b,
+                                uint32_t* g, uint32_t* c) {
+  if (b >= cofs[nG]) return false;
+  uint32_t lo = 0, hi = nG - 1;
+  while (lo < hi) {  // the last segment whose first chunk is at most b
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (cofs[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  *g = lo;
+  *c = b - cofs[lo];
+  return true;
+}
+
+// the wide set: structures with at least `big` possible candidates, in
+// structure order (one workgroup scans the flags), their offsets in the wide
+// arrays (by their bounds) and the chunks they need at most
+__global__ __launch_bounds__(kHT) void k_w_list(const uint64_t* __restrict__ cand_off, uint64_t ns,
+                                                uint64_t big, uint32_t* __restrict__ gs,
+                                                uint64_t* __restrict__ boff,
+                                                uint64_t* __restrict__ sizes) {
+  __shared__ double red[kHW];
+  uint64_t ng = 0, tb = 0, ch = 0;
+  for (uint64_t c0 = 0; c0 < ns; c0 += kHT) {
+    const uint64_t s = c0 + threadIdx.x;
+    const uint64_t b = s < ns ? cand_off[s + 1] - cand_off[s] : 0;
+    const bool w = s < ns && b >= big;
+    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    const double i1 = block_scan(w ? 1.0 : 0.0, red, &t1);
+    const double i2 = block_scan(w ? (double)b : 0.0, red, &t2);
+    const double i3 = block_scan(w ? (double)((b + kWC - 1) / kWC) : 0.0, red, &t3);
+    (void)i3;
+    if (w) {
+      const uint64_t g = ng + (uint64_t)i1 - 1;
+      gs[g] = (uint32_t)s;
+      boff[g] = tb + (uint64_t)i2 - b;
+    }
+    ng += (uint64_t)t1;
+    tb += (uint64_t)t2;
+    ch += (uint64_t)t3;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    boff[ng] = tb;
+    sizes[0] = ng;
+    sizes[1] = tb;
+    sizes[2] = ch;
+  }
+}
+
+// sort keys of the wide arrays: (segment << kRadiusBits) | top radius bits
+// for a candidate, all ones below the segment for the slack past its count
+// (it sorts to the segment's end), and the digit histograms of the sort;
+// word_ib >= 0: the sort starts on packed words (key << word_ib) | position
+__global__ __launch_bounds__(256) void k_w_keys(const uint32_t* __restrict__ gs,
+                                                const uint64_t* __restrict__ boff, uint32_t nG,
+                                                const uint64_t* __restrict__ cand_off,
+                                                const uint32_t* __restrict__ cand_cnt,
+                                                const double* __restrict__ rad, int npass,
+                                                int word_ib, uint64_t* __restrict__ keys,
+                                                uint32_t* __restrict__ ghist) {
+  __shared__ uint32_t h[kRsMaxPass * 256];
+  for (int i = threadIdx.x; i < kRsMaxPass * 256; i += 256) h[i] = 0u;
+  __syncthreads();
+  const uint64_t tb = boff[nG];
+  for (uint64_t base = (uint64_t)blockIdx.x * 256; base < tb; base += (uint64_t)gridDim.x * 256) {
+    const uint64_t p = base + threadIdx.x;
+    const bool valid = p < tb;
+    uint64_t key = 0;
+    if (valid) {
+      uint32_t lo = 0, hi = nG - 1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (boff[mid] <= p) lo = mid;
+        else hi = mid - 1;
+      }
+      const uint64_t k = p - boff[lo];
+      const uint32_t s = gs[lo];
+      const uint64_t t = k < cand_cnt[s]
+                             ? (uint64_t)__double_as_longlong(rad[cand_off[s] + k]) >> kTruncShift
+                             : (1ull << kRadiusBits) - 1ull;
+      key = ((uint64_t)lo << kRadiusBits) | t;
+      keys[p] = word_ib >= 0 ? ((key << word_ib) | p) : key;
+    }
+    wave_digit_hist(key, valid, npass, h);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < npass * 256; i += 256)
+    if (h[i]) atomicAdd(&ghist[i], h[i]);
+}
+
+// sorted position p: its candidate (the sort's payload is the input position,
+// whose segment is p's own): whole radius, particle, velocity and mass, and
+// the sort key for the tie runs
+__global__ void k_w_gather(const uint64_t* __restrict__ words, int ib,
+                           const uint32_t* __restrict__ gs, const uint64_t* __restrict__ boff,
+                           uint32_t nG, const uint64_t* __restrict__ cand_off,
+                           const uint32_t* __restrict__ cand_cnt,
+                           const uint32_t* __restrict__ cand, const double* __restrict__ rad,
+                           const float4* __restrict__ vq, uint64_t* __restrict__ K,
+                           uint32_t* __restrict__ I, float4* __restrict__ V,
+                           uint64_t* __restrict__ Kt) {
+  const uint64_t tb = boff[nG];
+  const uint64_t im = (1ull << ib) - 1ull;
+  for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < tb;
+       p += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = nG - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= p) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t s = gs[lo];
+    const uint64_t k = (words[p] & im) - boff[lo];  // the input position's place in the segment
+    if (p - boff[lo] >= cand_cnt[s]) continue;      // slack at the segment's end
+    const uint64_t slot = cand_off[s] + k;
+    const uint64_t rb = (uint64_t)__double_as_longlong(rad[slot]);
+    K[p] = rb;
+    I[p] = cand[slot];
+    V[p] = vq[slot];
+    Kt[p] = ((uint64_t)lo << kRadiusBits) | (rb >> kTruncShift);
+  }
+}
+
+// runs of equal sort keys (within a segment): by (radius, index), insertion
+// by the run's first thread; a run longer than kShortTie marks its structure
+// for the one-workgroup path (mode 2)
+__global__ void k_w_ties(const uint32_t* __restrict__ gs, const uint64_t* __restrict__ boff,
+                         uint32_t nG, const uint32_t* __restrict__ cand_cnt,
+                         const uint64_t* __restrict__ Kt, uint64_t* __restrict__ K,
+                         uint32_t* __restrict__ I, float4* __restrict__ V,
+                         uint32_t* __restrict__ mode) {
+  const uint64_t tb = boff[nG];
+  for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < tb;
+       p += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = nG - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= p) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint64_t b0 = boff[lo], end = b0 + cand_cnt[gs[lo]];
+    if (p >= end) continue;
+    if (p > b0 && Kt[p - 1] == Kt[p]) continue;  // not a run start
+    uint64_t e = p + 1;
+    while (e < end && Kt[e] == Kt[p]) ++e;
+    if (e - p == 1) continue;
+    if (e - p > kShortTie) {
+      mode[gs[lo]] = 2u;
+      continue;
+    }
+    for (uint64_t q = p + 1; q < e; ++q) {
+      const uint64_t kq = K[q];
+      const uint32_t iq = I[q];
+      const float4 vv = V[q];
+      uint64_t r = q;
+      while (r > p && (K[r - 1] > kq || (K[r - 1] == kq && I[r - 1] > iq))) {
+        K[r] = K[r - 1];
+        I[r] = I[r - 1];
+        V[r] = V[r - 1];
+        --r;
+      }
+      K[r] = kq;
+      I[r] = iq;
+      V[r] = vv;
+    }
+  }
+}
+
+// state of the wide set after the sort: the view's candidates in radius
+// order, every structure active with all its candidates (or handed to the
+// one-workgroup path)
+__global__ void k_w_start(const uint32_t* __restrict__ gs, const uint64_t* __restrict__ boff,
+                          uint32_t nG, const uint64_t* __restrict__ cand_off,
+                          const uint32_t* __restrict__ cand_cnt, const uint32_t* __restrict__ I,
+                          const uint32_t* __restrict__ mode, uint32_t* __restrict__ cand,
+                          uint32_t* __restrict__ na, uint32_t* __restrict__ act) {
+  const uint64_t tb = boff[nG];
+  for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < tb;
+       p += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = nG - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= p) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t s = gs[lo];
+    const uint64_t k = p - boff[lo];
+    if (k == 0) {
+      const bool on = mode[s] == 1u && cand_cnt[s] > 0;
+      na[lo] = on ? cand_cnt[s] : 0u;
+      act[lo] = on ? 1u : 0u;
+    }
+    if (k < cand_cnt[s] && mode[s] == 1u) cand[cand_off[s] + k] = I[p];
+  }
+}
+
+// this round's chunk table over the active segments (one workgroup)
+__global__ __launch_bounds__(kHT) void k_w_chunks(const uint32_t* __restrict__ na,
+                                                  const uint32_t* __restrict__ act, uint32_t nG,
+                                                  uint32_t* __restrict__ cofs) {
+  __shared__ double red[kHW];
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < nG; c0 += kHT) {
+    const uint32_t g = c0 + threadIdx.x;
+    const uint32_t v = (g < nG && act[g]) ? (na[g] + kWC - 1) / kWC : 0u;
+    double tot = 0.0;
+    const double inc = block_scan((double)v, red, &tot);
+    if (g < nG) cofs[g] = carry + (uint32_t)inc - v;
+    carry += (uint32_t)tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cofs[nG] = carry;
+}
+
+// per chunk: the sums of m vx, m vy, m vz and m (each thread its kWE
+// particles in row order, then the workgroup's fixed tree)
+__global__ __launch_bounds__(kWT) void k_w_vel(const uint32_t* __restrict__ cofs, uint32_t nG,
+                                               const uint64_t* __restrict__ boff,
+                                               const uint32_t* __restrict__ na,
+                                               const float4* __restrict__ V, PartIn P,
+                                               double* __restrict__ part) {
+  __shared__ double red[kWT / 64];
+  uint32_t g, c;
+  if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
+  const uint64_t k0 = (uint64_t)c * kWC, n = na[g], b0 = boff[g];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, sm = 0.0;
+#pragma unroll 4
+  for (int e = 0; e < kWE; ++e) {
+    const uint64_t k = k0 + (uint64_t)e * kWT + threadIdx.x;
+    if (k < n) {
+      const float4 q = V[b0 + k];
+      const double m = vmass(P, q);
+      s0 += m * (double)q.x;
+      s1 += m * (double)q.y;
+      s2 += m * (double)q.z;
+      sm += m;
+    }
+  }
+  s0 = block_sum<kWT>(s0, red);
+  s1 = block_sum<kWT>(s1, red);
+  s2 = block_sum<kWT>(s2, red);
+  sm = block_sum<kWT>(sm, red);
+  if (threadIdx.x == 0) {
+    double* o = part + 4 * (uint64_t)blockIdx.x;
+    o[0] = s0;
+    o[1] = s1;
+    o[2] = s2;
+    o[3] = sm;
+  }
+}
+
+// per active segment (one wave): the halo velocity from its chunks' sums, and
+// the exclusive offsets of its chunks' masses, in chunk order
+__global__ void k_w_seg_vel(const uint32_t* __restrict__ cofs, uint32_t nG,
+                            const uint32_t* __restrict__ act, const double* __restrict__ part,
+                            double* __restrict__ vh, double* __restrict__ moff) {
+  const uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = __lane_id();
+  if (g >= nG || !act[g]) return;
+  const uint32_t a = cofs[g], e = cofs[g + 1];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, carry = 0.0;
+  for (uint32_t c0 = a; c0 < e; c0 += 64) {
+    const uint32_t c = c0 + lane;
+    double m = 0.0;
+    if (c < e) {
+      s0 += part[4 * (uint64_t)c];
+      s1 += part[4 * (uint64_t)c + 1];
+      s2 += part[4 * (uint64_t)c + 2];
+      m = part[4 * (uint64_t)c + 3];
+    }
+    double inc = m;
+    for (int o = 1; o < 64; o <<= 1) {
+      const double y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    double exc = __shfl_up(inc, 1);
+    if (lane == 0) exc = 0.0;
+    if (c < e) moff[c] = carry + exc;
+    carry += __shfl(inc, 63);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o);
+    s1 += __shfl_xor(s1, o);
+    s2 += __shfl_xor(s2, o);
+  }
+  if (lane == 0) {
+    vh[3 * (uint64_t)g] = s0 / carry;
+    vh[3 * (uint64_t)g + 1] = s1 / carry;
+    vh[3 * (uint64_t)g + 2] = s2 / carry;
+  }
+}
+
+// LDS slot of chunk element i: one double of padding per 16, so that a
+// thread reading its kWE consecutive elements and the lanes of a wave hit
+// different banks
+__device__ inline int wpad(int i) { return i + (i >> 4); }
+constexpr int kWPad = kWC + kWC / 16;
+
+// the exclusive suffix over the workgroup's threads (threads after this one)
+// of one value per thread, with one barrier
+template <int BT>
+__device__ inline double block_esuffix(double x, double* red) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  double inc = x;  // inclusive suffix within the wave
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_down(inc, o);
+    if (lane + o < 64) inc += y;
+  }
+  double exc = __shfl_down(inc, 1);
+  if (lane == 63) exc = 0.0;
+  if (lane == 0) red[w] = inc;
+  __syncthreads();
+  double after = 0.0;
+  for (int i = BT / 64 - 1; i > w; --i) after += red[i];
+  return after + exc;
+}
+
+// per chunk: the enclosed masses (each thread scans its kWE consecutive
+// particles, the threads' sums are scanned over the workgroup, the chunk's
+// offset from the segment's chunks before it), M, and the last particle of
+// the chunk dense enough
+__global__ __launch_bounds__(kWT) void k_w_enc(const uint32_t* __restrict__ cofs, uint32_t nG,
+                                               const uint64_t* __restrict__ boff,
+                                               const uint32_t* __restrict__ na,
+                                               const uint64_t* __restrict__ K,
+                                               const float4* __restrict__ V, PartIn P,
+                                               const double* __restrict__ moff, double rho_thr,
+                                               double* __restrict__ M,
+                                               int64_t* __restrict__ vpart) {
+  __shared__ double sv[kWPad];
+  __shared__ double red[2][kWT / 64];
+  __shared__ int64_t redi[kWT / 64];
+  uint32_t g, c;
+  if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
+  const uint64_t k0 = (uint64_t)c * kWC, n = na[g], b0 = boff[g];
+  for (int e = 0; e < kWE; ++e) {
+    const int i = e * kWT + threadIdx.x;
+    const uint64_t k = k0 + i;
+    sv[wpad(i)] = k < n ? vmass(P, V[b0 + k]) : 0.0;
+  }
+  __syncthreads();
+  double pre[kWE];
+  double run = 0.0;
+#pragma unroll
+  for (int e = 0; e < kWE; ++e) {
+    run += sv[wpad(threadIdx.x * kWE + e)];
+    pre[e] = run;
+  }
+  double tot = 0.0;
+  const double base = moff[blockIdx.x] + block_escan1<kWT>(run, red, 0, &tot);
+  __syncthreads();  // every thread's reads of sv are done
+#pragma unroll
+  for (int e = 0; e < kWE; ++e) sv[wpad(threadIdx.x * kWE + e)] = base + pre[e];
+  __syncthreads();
+  int64_t vl = -1;
+  for (int e = 0; e < kWE; ++e) {
+    const int i = e * kWT + threadIdx.x;
+    const uint64_t k = k0 + i;
+    if (k < n) {
+      const double inc = sv[wpad(i)];
+      M[b0 + k] = inc;
+      const double r = __longlong_as_double((long long)K[b0 + k]);
+      const double dens = inc / (4.0 / 3.0 * M_PI * (r * r * r));
+      if (dens >= rho_thr) vl = (int64_t)k;
+    }
+  }
+  vl = block_max_i64<kWT>(vl, redi);
+  if (threadIdx.x == 0) vpart[blockIdx.x] = vl;
+}
+
+// per active segment (one wave): the last particle dense enough over its
+// chunks; none: the halo dissolves (its results written); else r_vir and
+// M(<r_vir) of the round
+__global__ void k_w_seg_v(const uint32_t* __restrict__ cofs, uint32_t nG,
+                          const uint32_t* __restrict__ gs, const uint64_t* __restrict__ boff,
+                          uint32_t* __restrict__ act, const int64_t* __restrict__ vpart,
+                          const uint64_t* __restrict__ K, const double* __restrict__ M,
+                          const double* __restrict__ vh, uint32_t it,
+                          int64_t* __restrict__ vseg, double* __restrict__ rvseg,
+                          double* __restrict__ mvseg, uint32_t* __restrict__ member_cnt,
+                          double* __restrict__ r_vir_out, double* __restrict__ m_vir_out,
+                          double* __restrict__ vel_out, uint32_t* __restrict__ iters_out) {
+  const uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = __lane_id();
+  if (g >= nG || !act[g]) return;
+  int64_t v = -1;
+  for (uint32_t c = cofs[g] + lane; c < cofs[g + 1]; c += 64) v = vpart[c] > v ? vpart[c] : v;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t y = __shfl_xor(v, o);
+    v = y > v ? y : v;
+  }
+  if (lane != 0) return;
+  vseg[g] = v;
+  if (v < 0) {  // never dense enough: the halo dissolves
+    const uint32_t s = gs[g];
+    act[g] = 0;
+    member_cnt[s] = 0;
+    r_vir_out[s] = 0.0;
+    m_vir_out[s] = 0.0;
+    for (int d = 0; d < 3; ++d) vel_out[3 * (uint64_t)s + d] = vh[3 * (uint64_t)g + d];
+    iters_out[s] = it;
+    return;
+  }
+  rvseg[g] = __longlong_as_double((long long)K[boff[g] + v]);
+  mvseg[g] = M[boff[g] + v];
+}
+
+// the App. A term of particle k < v: M_k (1/r_k - 1/r_{k+1})
+__device__ inline double tail_term(const uint64_t* K, const double* M, uint64_t k) {
+  const double r0 = __longlong_as_double((long long)K[k]);
+  const double r1 = __longlong_as_double((long long)K[k + 1]);
+  return M[k] * (1.0 / r0 - 1.0 / r1);
+}
+
+// per chunk: the sum of its terms below v (each thread its kWE consecutive
+// ones from the top, then the workgroup's fixed tree)
+__global__ __launch_bounds__(kWT) void k_w_tail1(const uint32_t* __restrict__ cofs, uint32_t nG,
+                                                 const uint64_t* __restrict__ boff,
+                                                 const uint32_t* __restrict__ act,
+                                                 const int64_t* __restrict__ vseg,
+                                                 const uint64_t* __restrict__ K,
+                                                 const double* __restrict__ M,
+                                                 double* __restrict__ ttot) {
+  __shared__ double red[kWT / 64];
+  uint32_t g, c;
+  if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
+  if (!act[g]) return;
+  const uint64_t k0 = (uint64_t)c * kWC, b0 = boff[g];
+  const int64_t v = vseg[g];
+  double run = 0.0;
+  for (int e = kWE - 1; e >= 0; --e) {
+    const uint64_t k = k0 + (uint64_t)threadIdx.x * kWE + e;
+    if ((int64_t)k < v) run += tail_term(K + b0, M + b0, k);
+  }
+  run = block_sum<kWT>(run, red);
+  if (threadIdx.x == 0) ttot[blockIdx.x] = run;
+}
+
+// per active segment (one wave): each chunk's offset, the sum of the terms
+// of the chunks after it
+__global__ void k_w_seg_tail(const uint32_t* __restrict__ cofs, uint32_t nG,
+                             const uint32_t* __restrict__ act, const double* __restrict__ ttot,
+                             double* __restrict__ toff) {
+  const uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = __lane_id();
+  if (g >= nG || !act[g]) return;
+  const int64_t a = cofs[g], e = cofs[g + 1];
+  double carry = 0.0;
+  for (int64_t c0 = 0; c0 < e - a; c0 += 64) {
+    const int64_t c = e - 1 - (c0 + lane);  // from the last chunk down
+    const double x = c >= a ? ttot[c] : 0.0;
+    double inc = x;
+    for (int o = 1; o < 64; o <<= 1) {
+      const double y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    double exc = __shfl_up(inc, 1);
+    if (lane == 0) exc = 0.0;
+    if (c >= a) toff[c] = carry + exc;
+    carry += __shfl(inc, 63);
+  }
+}
+
+// per chunk: T_k = the sum of the terms j in [k, v) (each thread sums its
+// kWE consecutive terms from the top, the threads after it in the workgroup
+// and the chunks after this one come first)
+__global__ __launch_bounds__(kWT) void k_w_tail2(const uint32_t* __restrict__ cofs, uint32_t nG,
+                                                 const uint64_t* __restrict__ boff,
+                                                 const uint32_t* __restrict__ act,
+                                                 const int64_t* __restrict__ vseg,
+                                                 const uint64_t* __restrict__ K,
+                                                 const double* __restrict__ M,
+                                                 const double* __restrict__ toff,
+                                                 double* __restrict__ T) {
+  __shared__ double sv[kWPad];
+  __shared__ double red[kWT / 64];
+  uint32_t g, c;
+  if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
+  if (!act[g]) return;
+  const uint64_t k0 = (uint64_t)c * kWC, b0 = boff[g];
+  const int64_t v = vseg[g];
+  if ((int64_t)k0 >= v) return;  // the whole chunk at or past v (uniform)
+  for (int e = 0; e < kWE; ++e) {
+    const int i = e * kWT + threadIdx.x;
+    const uint64_t k = k0 + i;
+    sv[wpad(i)] = (int64_t)k < v ? tail_term(K + b0, M + b0, k) : 0.0;
+  }
+  __syncthreads();
+  double pre[kWE];
+  double run = 0.0;
+#pragma unroll
+  for (int e = kWE - 1; e >= 0; --e) {
+    run += sv[wpad(threadIdx.x * kWE + e)];
+    pre[e] = run;
+  }
+  const double base = toff[blockIdx.x] + block_esuffix<kWT>(run, red);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kWE; ++e) sv[wpad(threadIdx.x * kWE + e)] = base + pre[e];
+  __syncthreads();
+  for (int e = 0; e < kWE; ++e) {
+    const int i = e * kWT + threadIdx.x;
+    const uint64_t k = k0 + i;
+    if ((int64_t)k < v) T[b0 + k] = sv[wpad(i)];
+  }
+}
+
+// per chunk: the escape test of every particle (as the one-workgroup path
+// writes it), the kept ones as ballot words per row and wave, and the
+// chunk's kept and unbound counts
+__global__ __launch_bounds__(kWT) void k_w_esc1(const uint32_t* __restrict__ cofs, uint32_t nG,
+                                                const uint64_t* __restrict__ boff,
+                                                const uint32_t* __restrict__ na,
+                                                const uint32_t* __restrict__ act,
+                                                const int64_t* __restrict__ vseg,
+                                                const double* __restrict__ rvseg,
+                                                const double* __restrict__ mvseg,
+                                                const double* __restrict__ vh, double G,
+                                                const uint64_t* __restrict__ K,
+                                                const float4* __restrict__ V,
+                                                const double* __restrict__ T,
+                                                uint64_t* __restrict__ kbits,
+                                                uint32_t* __restrict__ ckeep,
+                                                uint32_t* __restrict__ cgone) {
+  __shared__ uint32_t wk[kWT / 64], wg[kWT / 64];
+  uint32_t g, c;
+  if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
+  if (!act[g]) return;
+  const uint64_t k0 = (uint64_t)c * kWC, n = na[g], b0 = boff[g];
+  const int64_t v = vseg[g];
+  const uint64_t nv = (uint64_t)v;
+  const double rv = rvseg[g], mv = mvseg[g];
+  const double vx = vh[3 * (uint64_t)g], vy = vh[3 * (uint64_t)g + 1], vz = vh[3 * (uint64_t)g + 2];
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  uint32_t nk = 0, ng = 0;
+  for (int e = 0; e < kWE; ++e) {
+    const uint64_t k = k0 + (uint64_t)e * kWT + threadIdx.x;
+    bool gone = false;
+    if (k < n) {
+      const double r = __longlong_as_double((long long)K[b0 + k]);
+      const float4 q = V[b0 + k];
+      const double phi = (int64_t)k <= v ? -G * ((k < nv ? T[b0 + k] : 0.0) + mv / rv) : -G * mv / r;
+      const double dx = (double)q.x - vx;
+      const double dy = (double)q.y - vy;
+      const double dz = (double)q.z - vz;
+      const double ke = 0.5 * (dx * dx + dy * dy + dz * dz);
+      gone = ke > fabs(phi);
+    }
+    const uint64_t kb = __ballot(k < n && !gone);
+    const uint64_t gb = __ballot(gone);
+    if (lane == 0) kbits[((uint64_t)blockIdx.x * kWE + e) * (kWT / 64) + w] = kb;
+    nk += (uint32_t)__popcll(kb);
+    ng += (uint32_t)__popcll(gb);
+  }
+  if (lane == 0) {
+    wk[w] = nk;
+    wg[w] = ng;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0, b = 0;
+    for (int i = 0; i < kWT / 64; ++i) {
+      a += wk[i];
+      b += wg[i];
+    }
+    ckeep[blockIdx.x] = a;
+    cgone[blockIdx.x] = b;
+  }
+}
+
+// per active segment (one wave): the kept particles' chunk offsets; nothing
+// unbound: the halo converged (the first v + 1 particles; their list and mass
+// are written at the end from this round's arrays, parity `par`); the last
+// round, or nothing kept: it ends without members; else its particles are the
+// kept ones.  Counts the segments still active.
+__global__ void k_w_seg_esc(const uint32_t* __restrict__ cofs, uint32_t nG,
+                            const uint32_t* __restrict__ gs, uint32_t* __restrict__ act,
+                            const uint32_t* __restrict__ ckeep, const uint32_t* __restrict__ cgone,
+                            const int64_t* __restrict__ vseg, const double* __restrict__ rvseg,
+                            const double* __restrict__ vh, uint32_t it, uint32_t max_iter,
+                            uint32_t par, uint32_t* __restrict__ koff, uint32_t* __restrict__ na,
+                            uint32_t* __restrict__ nmem, uint32_t* __restrict__ mpar,
+                            uint32_t* __restrict__ nact, uint32_t* __restrict__ member_cnt,
+                            double* __restrict__ r_vir_out, double* __restrict__ m_vir_out,
+                            double* __restrict__ vel_out, uint32_t* __restrict__ iters_out) {
+  const uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = __lane_id();
+  if (g >= nG || !act[g]) return;
+  const uint32_t a = cofs[g], e = cofs[g + 1];
+  uint32_t carry = 0, gone = 0;
+  for (uint32_t c0 = a; c0 < e; c0 += 64) {
+    const uint32_t c = c0 + lane;
+    const uint32_t x = c < e ? ckeep[c] : 0u;
+    gone += c < e ? cgone[c] : 0u;
+    uint32_t inc = x;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (c < e) koff[c] = carry + inc - x;
+    carry += __shfl(inc, 63);
+  }
+  for (int o = 32; o > 0; o >>= 1) gone += __shfl_xor(gone, o);
+  if (lane != 0) return;
+  const uint32_t s = gs[g];
+  const bool conv = gone == 0;
+  // ends: converged, the last round, or every particle unbound (no members)
+  if (conv || it == max_iter || carry == 0) {
+    act[g] = 0;
+    member_cnt[s] = conv ? (uint32_t)(vseg[g] + 1) : 0u;
+    r_vir_out[s] = conv ? rvseg[g] : 0.0;
+    if (!conv) m_vir_out[s] = 0.0;
+    for (int d = 0; d < 3; ++d) vel_out[3 * (uint64_t)s + d] = vh[3 * (uint64_t)g + d];
+    iters_out[s] = it;
+    nmem[g] = conv ? (uint32_t)(vseg[g] + 1) : 0u;
+    mpar[g] = par;
+  } else {
+    na[g] = carry;
+    atomicAdd(nact, 1u);
+  }
+}
+
+// per chunk of a segment still active: its kept particles to the other
+// arrays, in order, at the chunk's offset
+__global__ __launch_bounds__(kWT) void k_w_esc2(const uint32_t* __restrict__ cofs, uint32_t nG,
+                                                const uint64_t* __restrict__ boff,
+                                                const uint32_t* __restrict__ act,
+                                                const uint64_t* __restrict__ kbits,
+                                                const uint32_t* __restrict__ koff,
+                                                const uint64_t* __restrict__ K,
+                                                const uint32_t* __restrict__ I,
+                                                const float4* __restrict__ V,
+                                                uint64_t* __restrict__ Kn, uint32_t* __restrict__ In,
+                                                float4* __restrict__ Vn) {
+  __shared__ uint64_t kb[kWE * (kWT / 64)];
+  uint32_t g, c;
+  if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
+  if (!act[g]) return;
+  if (threadIdx.x < kWE * (kWT / 64))
+    kb[threadIdx.x] = kbits[(uint64_t)blockIdx.x * kWE * (kWT / 64) + threadIdx.x];
+  __syncthreads();
+  const uint64_t k0 = (uint64_t)c * kWC, b0 = boff[g];
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  uint32_t before = 0;  // kept particles of the rows before this one
+  for (int e = 0; e < kWE; ++e) {
+    const uint64_t mine = kb[e * (kWT / 64) + w];
+    uint32_t wb = 0, rowall = 0;
+    for (int i = 0; i < kWT / 64; ++i) {
+      const uint32_t cnt = (uint32_t)__popcll(kb[e * (kWT / 64) + i]);
+      if (i < w) wb += cnt;
+      rowall += cnt;
+    }
+    if ((mine >> lane) & 1ull) {
+      const uint64_t k = k0 + (uint64_t)e * kWT + threadIdx.x;
+      const uint64_t at = b0 + koff[blockIdx.x] + before + wb +
+                          (uint32_t)__popcll(mine & lanes_below());
+      Kn[at] = K[b0 + k];
+      In[at] = I[b0 + k];
+      Vn[at] = V[b0 + k];
+    }
+    before += rowall;
+  }
+}
+
+// the members of the converged segments: per chunk of their first nmem
+// particles (in the arrays of their last round), the list and the sum of
+// their masses
+__global__ __launch_bounds__(kWT) void k_w_members(const uint32_t* __restrict__ cofs, uint32_t nG,
+                                                   const uint32_t* __restrict__ gs,
+                                                   const uint64_t* __restrict__ boff,
+                                                   const uint32_t* __restrict__ nmem,
+                                                   const uint32_t* __restrict__ mpar,
+                                                   const uint64_t* __restrict__ cand_off,
+                                                   const uint32_t* __restrict__ I0,
+                                                   const uint32_t* __restrict__ I1,
+                                                   const float4* __restrict__ V0,
+                                                   const float4* __restrict__ V1, PartIn P,
+                                                   uint32_t* __restrict__ member,
+                                                   double* __restrict__ part) {
+  __shared__ double red[kWT / 64];
+  uint32_t g, c;
+  if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
+  const uint64_t k0 = (uint64_t)c * kWC, n = nmem[g], b0 = boff[g];
+  const uint32_t* I = mpar[g] ? I1 : I0;
+  const float4* V = mpar[g] ? V1 : V0;
+  uint32_t* out = member + cand_off[gs[g]];
+  double sm = 0.0;
+  for (int e = 0; e < kWE; ++e) {
+    const uint64_t k = k0 + (uint64_t)e * kWT + threadIdx.x;
+    if (k < n) {
+      out[k] = I[b0 + k];
+      sm += vmass(P, V[b0 + k]);
+    }
+  }
+  sm = block_sum<kWT>(sm, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = sm;
+}
+
+__global__ void k_w_seg_mvir(const uint32_t* __restrict__ cofs, uint32_t nG,
+                             const uint32_t* __restrict__ gs, const uint32_t* __restrict__ nmem,
+                             const double* __restrict__ part, double* __restrict__ m_vir_out) {
+  const uint32_t g = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = __lane_id();
+  if (g >= nG || nmem[g] == 0) return;
+  double sm = 0.0;
+  for (uint32_t c = cofs[g] + lane; c < cofs[g + 1]; c += 64) sm += part[c];
+  for (int o = 32; o > 0; o >>= 1) sm += __shfl_xor(sm, o);
+  if (lane == 0) m_vir_out[gs[g]] = sm;
+}
+
+// mode of every structure: 1 for the wide set (at least `big` possible
+// candidates), else 0 (its own workgroup); a wide one with a long run of tied
+// radii is set to 2 later (one wide workgroup)
+__global__ void k_w_mode(const uint64_t* __restrict__ cand_off, uint64_t ns, uint64_t big,
+                         uint32_t* __restrict__ mode) {
+  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < ns;
+       s += (uint64_t)gridDim.x * blockDim.x)
+    mode[s] = (cand_off[s + 1] - cand_off[s] >= big) ? 1u : 0u;
+}
+
+// the results of the wide structures without candidates
+__global__ void k_w_empty(const uint32_t* __restrict__ gs, uint32_t nG,
+                          const uint32_t* __restrict__ cand_cnt, const uint32_t* __restrict__ mode,
+                          uint32_t* __restrict__ member_cnt, double* __restrict__ r_vir_out,
+                          double* __restrict__ m_vir_out, double* __restrict__ vel_out,
+                          uint32_t* __restrict__ iters_out) {
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nG; g += gridDim.x * blockDim.x) {
+    const uint32_t s = gs[g];
+    if (mode[s] != 1u || cand_cnt[s] != 0) continue;
+    member_cnt[s] = 0;
+    r_vir_out[s] = 0.0;
+    m_vir_out[s] = 0.0;
+    for (int d = 0; d < 3; ++d) vel_out[3 * (uint64_t)s + d] = 0.0;
+    iters_out[s] = 0;
+  }
+}
+
 }  // namespace
 
 // the halo set of one hierarchy: device arrays in an arena of the context
@@ -1031,9 +1795,107 @@ struct Halos {
            *iters = nullptr;
 };
 
+// Unbinding of the wide set by the whole grid (the kernels above): sort,
+// then rounds until no structure is active, reading the number still active
+// after each round; the members' lists and masses at the end.
+static void wide_unbind(Ctx* ctx, Ws& ws, uint32_t nG, uint64_t tb, uint64_t maxch,
+                        const uint32_t* gs, const uint64_t* boff, uint32_t* mode,
+                        const double* rad, const float4* vslot, const PartIn& P, double rho_thr,
+                        double G, uint32_t max_iter, hipStream_t st, Halos* out) {
+  int gbits = 1;
+  while ((1ull << gbits) < nG) ++gbits;
+  const SortPlan sp = sort_plan(tb, kRadiusBits + gbits);
+  uint64_t* keys = ws.get<uint64_t>(tb);
+  uint32_t* ghist = ws.get<uint32_t>(kRsMaxPass * 256);
+  k_fill_u32<<<blocks_for(kRsMaxPass * 256), kHB, 0, st>>>(ghist, kRsMaxPass * 256, 0);
+  HIP_LAUNCH_CHECK();
+  const unsigned kb = std::min<unsigned>(blocks_for(tb), 2048u);
+  k_w_keys<<<kb, 256, 0, st>>>(gs, boff, nG, out->cand_off, out->cand_cnt, rad, sp.npass,
+                               sp.q == 0 ? sp.ib : -1, keys, ghist);
+  HIP_LAUNCH_CHECK();
+  const uint64_t* words = sort_keys(ctx, ws, keys, tb, sp, ghist, st, nullptr);
+  uint64_t* Kb[2] = {ws.get<uint64_t>(tb), ws.get<uint64_t>(tb)};
+  uint32_t* Ib[2] = {ws.get<uint32_t>(tb), ws.get<uint32_t>(tb)};
+  float4* Vb[2] = {ws.get<float4>(tb), ws.get<float4>(tb)};
+  uint64_t* Kt = ws.get<uint64_t>(tb);
+  double* M = ws.get<double>(tb);
+  double* T = ws.get<double>(tb);
+  k_w_gather<<<blocks_for(tb), kHB, 0, st>>>(words, sp.ib, gs, boff, nG, out->cand_off,
+                                             out->cand_cnt, out->cand, rad, vslot, Kb[0], Ib[0],
+                                             Vb[0], Kt);
+  HIP_LAUNCH_CHECK();
+  k_w_ties<<<blocks_for(tb), kHB, 0, st>>>(gs, boff, nG, out->cand_cnt, Kt, Kb[0], Ib[0], Vb[0],
+                                           mode);
+  HIP_LAUNCH_CHECK();
+  uint32_t* na = ws.get<uint32_t>(nG);
+  uint32_t* act = ws.get<uint32_t>(nG);
+  uint32_t* nmem = ws.get<uint32_t>(nG);
+  uint32_t* mpar = ws.get<uint32_t>(nG);
+  uint32_t* cofs = ws.get<uint32_t>(nG + 1);
+  uint32_t* nact = ws.get<uint32_t>(1);
+  double* vh = ws.get<double>(3 * (uint64_t)nG);
+  int64_t* vseg = ws.get<int64_t>(nG);
+  double* rvseg = ws.get<double>(nG);
+  double* mvseg = ws.get<double>(nG);
+  double* part = ws.get<double>(4 * maxch);
+  double* moff = ws.get<double>(maxch);
+  int64_t* vpart = ws.get<int64_t>(maxch);
+  double* ttot = ws.get<double>(maxch);
+  double* toff = ws.get<double>(maxch);
+  uint64_t* kbits = ws.get<uint64_t>(maxch * kWE * (kWT / 64));
+  uint32_t* ckeep = ws.get<uint32_t>(maxch);
+  uint32_t* cgone = ws.get<uint32_t>(maxch);
+  uint32_t* koff = ws.get<uint32_t>(maxch);
+  k_fill_u32<<<blocks_for(nG), kHB, 0, st>>>(nmem, nG, 0);
+  HIP_LAUNCH_CHECK();
+  k_w_start<<<blocks_for(tb), kHB, 0, st>>>(gs, boff, nG, out->cand_off, out->cand_cnt, Ib[0],
+                                            mode, out->cand, na, act);
+  HIP_LAUNCH_CHECK();
+  k_w_empty<<<blocks_for(nG), kHB, 0, st>>>(gs, nG, out->cand_cnt, mode, out->member_cnt,
+                                            out->r_vir, out->m_vir, out->vel, out->iters);
+  HIP_LAUNCH_CHECK();
+  const unsigned ch = (unsigned)maxch;
+  const unsigned sg = (nG + 3) / 4;  // one wave per segment
+  for (uint32_t it = 1; it <= max_iter; ++it) {
+    const uint32_t par = (it - 1) & 1u;
+    const uint64_t* K = Kb[par];
+    const uint32_t* I = Ib[par];
+    const float4* V = Vb[par];
+    k_fill_u32<<<1, 64, 0, st>>>(nact, 1, 0);
+    k_w_chunks<<<1, kHT, 0, st>>>(na, act, nG, cofs);
+    k_w_vel<<<ch, kWT, 0, st>>>(cofs, nG, boff, na, V, P, part);
+    k_w_seg_vel<<<sg, 256, 0, st>>>(cofs, nG, act, part, vh, moff);
+    k_w_enc<<<ch, kWT, 0, st>>>(cofs, nG, boff, na, K, V, P, moff, rho_thr, M, vpart);
+    k_w_seg_v<<<sg, 256, 0, st>>>(cofs, nG, gs, boff, act, vpart, K, M, vh, it, vseg, rvseg,
+                                  mvseg, out->member_cnt, out->r_vir, out->m_vir, out->vel,
+                                  out->iters);
+    k_w_tail1<<<ch, kWT, 0, st>>>(cofs, nG, boff, act, vseg, K, M, ttot);
+    k_w_seg_tail<<<sg, 256, 0, st>>>(cofs, nG, act, ttot, toff);
+    k_w_tail2<<<ch, kWT, 0, st>>>(cofs, nG, boff, act, vseg, K, M, toff, T);
+    k_w_esc1<<<ch, kWT, 0, st>>>(cofs, nG, boff, na, act, vseg, rvseg, mvseg, vh, G, K, V, T,
+                                 kbits, ckeep, cgone);
+    k_w_seg_esc<<<sg, 256, 0, st>>>(cofs, nG, gs, act, ckeep, cgone, vseg, rvseg, vh, it,
+                                    max_iter, par, koff, na, nmem, mpar, nact, out->member_cnt,
+                                    out->r_vir, out->m_vir, out->vel, out->iters);
+    k_w_esc2<<<ch, kWT, 0, st>>>(cofs, nG, boff, act, kbits, koff, K, I, V, Kb[par ^ 1u],
+                                 Ib[par ^ 1u], Vb[par ^ 1u]);
+    HIP_LAUNCH_CHECK();
+    uint32_t still = 0;
+    HIP_CHECK(hipMemcpyAsync(&still, nact, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (still == 0) break;
+  }
+  // the members of the converged ones and their mass
+  k_w_chunks<<<1, kHT, 0, st>>>(nmem, nmem, nG, cofs);
+  k_w_members<<<ch, kWT, 0, st>>>(cofs, nG, gs, boff, nmem, mpar, out->cand_off, Ib[0], Ib[1],
+                                  Vb[0], Vb[1], P, out->member, part);
+  k_w_seg_mvir<<<sg, 256, 0, st>>>(cofs, nG, gs, nmem, part, out->m_vir);
+  HIP_LAUNCH_CHECK();
+}
+
 static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, const float* vx,
                        const float* vy, const float* vz, double delta_vir, double G,
-                       uint32_t max_iter, hipStream_t st, Halos* out) {
+                       uint32_t max_iter, uint64_t large, hipStream_t st, Halos* out) {
   const uint64_t ns = h->nStruct;
   const size_t nlev = h->lev.size();
   out->n = ns;
@@ -1149,10 +2011,23 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   HIP_LAUNCH_CHECK();
   k_offsets<<<1, kHT, 0, st>>>(bound, ns, out->cand_off);
   HIP_LAUNCH_CHECK();
-  uint64_t total = 0;
+  // the wide set (structures with at least `large` possible candidates) and
+  // every structure's mode
+  uint32_t* gs = ws.get<uint32_t>(ns);
+  uint64_t* boff = ws.get<uint64_t>(ns + 1);
+  uint64_t* wsz = ws.get<uint64_t>(3);
+  uint32_t* mode = ws.get<uint32_t>(ns);
+  k_w_list<<<1, kHT, 0, st>>>(out->cand_off, ns, large, gs, boff, wsz);
+  HIP_LAUNCH_CHECK();
+  k_w_mode<<<blocks_for(ns), kHB, 0, st>>>(out->cand_off, ns, large, mode);
+  HIP_LAUNCH_CHECK();
+  uint64_t total = 0, wide[3] = {0, 0, 0};
   HIP_CHECK(hipMemcpyAsync(&total, out->cand_off + ns, sizeof(uint64_t), hipMemcpyDeviceToHost,
                            st));
+  HIP_CHECK(hipMemcpyAsync(wide, wsz, sizeof(wide), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
+  const uint32_t nG = (uint32_t)wide[0];
+  const uint64_t tb = wide[1], maxch = wide[2];
   const uint64_t t1 = total ? total : 1;
   out->cand = mem.get<uint32_t>(t1);
   out->member = mem.get<uint32_t>(t1);
@@ -1165,10 +2040,10 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   float4* vbuf = ws.get<float4>(t1);
   float4* vslot = ws.get<float4>(t1);
   const double rho_b = h->lev.empty() ? 0.0 : h->lev[0].tot_part;
-  // One workgroup per structure: of kHTBig threads for those with at least
-  // kBigCand possible candidates (the few that hold most of them), on st, with
-  // their radii and velocities found by the whole grid first; of kHT threads
-  // for the others, on a second stream beside them.
+  // The small structures on a second stream, one workgroup of kHT threads
+  // each; beside them, on st, the wide set's candidates (a workgroup of
+  // kHTBig threads each), their radii and velocities found by the whole grid,
+  // and their unbinding by the grid (wide_unbind).
   if (!ctx->dep_st) HIP_CHECK(hipStreamCreateWithFlags(&ctx->dep_st, hipStreamNonBlocking));
   hipStream_t s2 = ctx->dep_st;
   hipEvent_t fork = nullptr, join = nullptr;
@@ -1176,31 +2051,38 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   HIP_CHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
   HIP_CHECK(hipEventRecord(fork, st));
   HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
-  k_candidates<kHTBig><<<(unsigned)ns, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius,
-                                                        iso_off, iso_cnt, iso_list, LC,
-                                                        h->order, P, out->cand_off, out->cand,
-                                                        out->cand_cnt, kBigCand);
-  HIP_LAUNCH_CHECK();
+  if (nG) {
+    k_candidates<kHTBig><<<nG, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
+                                                iso_cnt, iso_list, LC, h->order, P,
+                                                out->cand_off, out->cand, out->cand_cnt, large,
+                                                gs);
+    HIP_LAUNCH_CHECK();
+  }
   k_big_data<<<blocks_for(total), kHB, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, ns,
-                                                total, out->centre, P, kBigCand, msum, vslot);
+                                                total, out->centre, P, large, msum, vslot);
   HIP_LAUNCH_CHECK();
-  k_unbind<kHTBig><<<(unsigned)ns, kHTBig, 0, st>>>(out->cand_off, out->cand_cnt, out->cand,
-                                                    idx_a, idx_b, key_a, key_b, msum, tail, vbuf,
-                                                    vslot, out->centre, P, delta_vir * rho_b, G,
-                                                    max_iter, out->member, out->member_cnt,
-                                                    out->r_vir, out->m_vir, out->vel, out->iters,
-                                                    kBigCand);
-  HIP_LAUNCH_CHECK();
+  if (nG)
+    wide_unbind(ctx, ws, nG, tb, maxch, gs, boff, mode, msum, vslot, P, delta_vir * rho_b, G,
+                max_iter, st, out);
+  // wide structures whose tied radii were too many for the grid's sort
+  if (nG) {
+    k_unbind<kHTBig><<<nG, kHTBig, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, idx_a, idx_b,
+                                            key_a, key_b, msum, tail, vbuf, vslot, out->centre, P,
+                                            delta_vir * rho_b, G, max_iter, out->member,
+                                            out->member_cnt, out->r_vir, out->m_vir, out->vel,
+                                            out->iters, mode, gs);
+    HIP_LAUNCH_CHECK();
+  }
   k_candidates<kHT><<<(unsigned)ns, kHT, 0, s2>>>(h->s_depth, out->centre, out->radius, iso_off,
                                                   iso_cnt, iso_list, LC, h->order, P,
                                                   out->cand_off, out->cand, out->cand_cnt,
-                                                  kBigCand);
+                                                  large, nullptr);
   HIP_LAUNCH_CHECK();
   k_unbind<kHT><<<(unsigned)ns, kHT, 0, s2>>>(out->cand_off, out->cand_cnt, out->cand, idx_a,
                                               idx_b, key_a, key_b, msum, tail, vbuf, vslot,
                                               out->centre, P, delta_vir * rho_b, G, max_iter,
                                               out->member, out->member_cnt, out->r_vir,
-                                              out->m_vir, out->vel, out->iters, kBigCand);
+                                              out->m_vir, out->vel, out->iters, mode, nullptr);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipEventRecord(join, s2));
   HIP_CHECK(hipStreamWaitEvent(st, join, 0));
@@ -1254,11 +2136,12 @@ ahf_status ahf_find_halos(ahf_ctx* ctx, const ahf_hierarchy* h, const ahf_partic
     HIP_CHECK(hipSetDevice(ctx->c.device));
     ctx->ws.bind(&ctx->c, st);
     ctx->ws.reset();
-    find_halos(&ctx->c, ctx->ws, &h->h, *p, vx, vy, vz, prm->delta_vir, prm->G, prm->max_iter, st,
-               &r->h);
+    find_halos(&ctx->c, ctx->ws, &h->h, *p, vx, vy, vz, prm->delta_vir, prm->G, prm->max_iter,
+               prm->large_from ? prm->large_from : kBigCand, st, &r->h);
     ctx->ws.reset();
   } catch (const Error& e) {
     (void)hipStreamSynchronize(st);
+    if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
     ctx->ws.reset();
     r->h.mem.release_all();
     delete r;
@@ -1266,6 +2149,7 @@ ahf_status ahf_find_halos(ahf_ctx* ctx, const ahf_hierarchy* h, const ahf_partic
     return e.code;
   } catch (const std::bad_alloc&) {
     (void)hipStreamSynchronize(st);
+    if (ctx->c.dep_st) (void)hipStreamSynchronize(ctx->c.dep_st);
     ctx->ws.reset();
     r->h.mem.release_all();
     delete r;

@@ -84,11 +84,15 @@ CASES = [
 ]
 
 
+# large_from: 0 leaves the default (only structures with 32768 or more
+# possible candidates are unbound by the whole GPU, none here); 1 and 200 send
+# every structure, or the larger ones, through the grid-wide unbinding
+@pytest.mark.parametrize("large", [0, 1, 200], ids=["default", "all-wide", "wide-200"])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
-def test_halos_match_the_oracle(name, make):
+def test_halos_match_the_oracle(name, make, large):
     p = make()
-    print(f"halos: {name}, {p.n} particles", flush=True)
-    res, again = device_halos(p)
+    print(f"halos: {name}, {p.n} particles, large_from {large}", flush=True)
+    res, again = device_halos(p, large_from=large)
     ores, st = oracle_halos(p)
     assert len(ores) > 3
     compare(res, ores, name, p)
@@ -142,9 +146,10 @@ def test_halos_with_coincident_particles():
     for dst, src in ((pick[1:301], pick[0]), (pick[301:], other)):
         for a in (p.X, p.Y, p.Z, p.fx, p.fy, p.fz):
             a[dst] = a[src]
-    res, again = device_halos(p)
     ores, _ = oracle_halos(p)
-    compare(res, ores, "coincident", p)
+    for large in (0, 100):  # one workgroup, or the grid with its fall-back for long ties
+        res, again = device_halos(p, large_from=large)
+        compare(res, ores, "coincident", p)
     pos = H.positions(p)
     tied = 0
     for s in range(res["n_halos"]):
