@@ -115,6 +115,58 @@ __global__ void k_iso(int L, const int32_t* __restrict__ pstruct, uint64_t npatc
 // particles into leaf_cnt (and the smallest key into leaf_min); the cells of a
 // host's isodensity patch count into iso_cnt.  With fill, the particle indices
 // are written into the lists at the structures' offsets instead (cursor order).
+// Wave-aggregated atomics on per-structure counters: the lanes where `on` is
+// set add v to ctr[key] (several lanes mostly share a key: neighbouring cells
+// belong to one patch), one atomic per distinct key in the wave; each lane
+// gets the counter's value before its own share (the lanes of a key in lane
+// order).  Every lane of the wave calls it.
+__device__ inline uint32_t wave_add(uint32_t* ctr, int32_t key, uint32_t v, bool on) {
+  const int lane = __lane_id();
+  uint64_t todo = __ballot(on);
+  uint32_t mine = 0;
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int32_t kl = __shfl(key, leader);
+    const bool peer = on && key == kl;
+    const uint64_t peers = __ballot(peer);
+    uint32_t inc = peer ? v : 0u;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    const uint32_t total = __shfl(inc, 63);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[kl], total);
+    base = __shfl(base, leader);
+    if (peer) mine = base + inc - v;
+    todo &= ~peers;
+  }
+  return mine;
+}
+
+// the same for an integer maximum (or minimum, with `is_min`) of 64-bit values
+__device__ inline void wave_extreme(unsigned long long* ctr, int32_t key, unsigned long long v,
+                                    bool on, bool is_min) {
+  const int lane = __lane_id();
+  uint64_t todo = __ballot(on);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const int32_t kl = __shfl(key, leader);
+    const bool peer = on && key == kl;
+    const uint64_t peers = __ballot(peer);
+    unsigned long long x = peer ? v : (is_min ? ~0ull : 0ull);
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long y = __shfl_xor(x, o);
+      x = is_min ? (y < x ? y : x) : (y > x ? y : x);
+    }
+    if (lane == leader) {
+      if (is_min) atomicMin(&ctr[kl], x);
+      else atomicMax(&ctr[kl], x);
+    }
+    todo &= ~peers;
+  }
+}
+
 __global__ void k_patch_lists(int L, uint64_t nS, uint64_t npatch, const uint64_t* __restrict__ Skey,
                               const uint32_t* __restrict__ Sstart,
                               const uint32_t* __restrict__ Scount,
@@ -129,65 +181,78 @@ __global__ void k_patch_lists(int L, uint64_t nS, uint64_t npatch, const uint64_
                               const uint64_t* __restrict__ leaf_off,
                               uint32_t* __restrict__ leaf_list,
                               const uint64_t* __restrict__ iso_off, uint32_t* __restrict__ iso_list) {
-  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nS;
-       c += (uint64_t)gridDim.x * blockDim.x) {
-    const int32_t q = Spatch[c];
-    if (q < 0 || (uint64_t)q >= npatch) continue;
-    const int32_t s = pstruct[q];
-    if (s < 0) continue;
-    const uint32_t cnt = Scount[c];
-    const bool is_leaf = leafkey[s] == (((unsigned long long)L << 32) | (unsigned long long)q);
-    const bool is_iso = iso_level[s] == L && iso_patch[s] == q;
-    if (!is_leaf && !is_iso) continue;
-    if (!fill) {
-      if (is_leaf) {
-        atomicAdd(&leaf_cnt[s], cnt);
-        atomicMin(&leaf_min[s], (unsigned long long)Skey[c]);
+  // rounds of the whole grid, so that every lane of a wave takes part in the
+  // wave-aggregated atomics
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < nS; base += stride) {
+    const uint64_t c = base + threadIdx.x;
+    int32_t s = -1;
+    uint32_t cnt = 0;
+    bool is_leaf = false, is_iso = false;
+    if (c < nS) {
+      const int32_t q = Spatch[c];
+      if (q >= 0 && (uint64_t)q < npatch) {
+        s = pstruct[q];
+        if (s >= 0) {
+          cnt = Scount[c];
+          is_leaf = leafkey[s] == (((unsigned long long)L << 32) | (unsigned long long)q);
+          is_iso = iso_level[s] == L && iso_patch[s] == q;
+        }
       }
-      if (is_iso) atomicAdd(&iso_cnt[s], cnt);
+    }
+    if (!fill) {
+      (void)wave_add(leaf_cnt, s, cnt, is_leaf);
+      wave_extreme(leaf_min, s, is_leaf ? (unsigned long long)Skey[c] : 0ull, is_leaf, true);
+      (void)wave_add(iso_cnt, s, cnt, is_iso);
       continue;
     }
-    const uint32_t a = Sstart[c];
-    if (is_leaf && cnt) {
-      const uint32_t at = atomicAdd(&leaf_cnt[s], cnt);
-      for (uint32_t j = 0; j < cnt; ++j) leaf_list[leaf_off[s] + at + j] = order[a + j];
-    }
-    if (is_iso && cnt) {
-      const uint32_t at = atomicAdd(&iso_cnt[s], cnt);
-      for (uint32_t j = 0; j < cnt; ++j) iso_list[iso_off[s] + at + j] = order[a + j];
+    const uint32_t la = wave_add(leaf_cnt, s, cnt, is_leaf && cnt);
+    const uint32_t ia = wave_add(iso_cnt, s, cnt, is_iso && cnt);
+    if ((is_leaf || is_iso) && cnt) {
+      const uint32_t a = Sstart[c];
+      for (uint32_t j = 0; j < cnt; ++j) {
+        const uint32_t i = order[a + j];
+        if (is_leaf) leaf_list[leaf_off[s] + la + j] = i;
+        if (is_iso) iso_list[iso_off[s] + ia + j] = i;
+      }
     }
   }
 }
-
-// the extent of every substructure's start patch: the largest distance from
-// its centre to a corner of one of the patch's cells (per axis the farther
-// face, periodic minimum image); non-negative doubles order like their bit
-// patterns, so an integer maximum keeps the largest exactly, in any order
 __global__ void k_extent(int L, int bits, uint64_t nS, uint64_t npatch,
                          const uint64_t* __restrict__ Skey, const int32_t* __restrict__ Spatch,
                          const int32_t* __restrict__ pstruct, const int32_t* __restrict__ s_depth,
                          const int32_t* __restrict__ s_level, const int32_t* __restrict__ s_patch,
                          const double* __restrict__ centre, unsigned long long* __restrict__ ext) {
   const double h = 1.0 / (double)(1ull << bits);
-  for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < nS;
-       c += (uint64_t)gridDim.x * blockDim.x) {
-    const int32_t q = Spatch[c];
-    if (q < 0 || (uint64_t)q >= npatch) continue;
-    const int32_t s = pstruct[q];
-    if (s < 0 || s_depth[s] == 0 || s_level[s] != L || s_patch[s] != q) continue;
-    const uint64_t key = Skey[c];
-    const uint32_t ix[3] = {compact3(key >> 2), compact3(key >> 1), compact3(key)};
-    double dd[3];
-    for (int k = 0; k < 3; ++k) {
-      const double ck = centre[3 * (uint64_t)s + k];
-      const double lo = (double)ix[k] / (double)(1ull << bits);
-      const double a = fabs(mimg(lo - ck));
-      const double hi = lo + h;
-      const double b = fabs(mimg(hi - ck));
-      dd[k] = a > b ? a : b;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < nS; base += stride) {
+    const uint64_t c = base + threadIdx.x;
+    int32_t s = -1;
+    bool on = false;
+    unsigned long long ev = 0;
+    if (c < nS) {
+      const int32_t q = Spatch[c];
+      if (q >= 0 && (uint64_t)q < npatch) {
+        s = pstruct[q];
+        on = s >= 0 && s_depth[s] != 0 && s_level[s] == L && s_patch[s] == q;
+      }
     }
-    const double e = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
-    atomicMax(&ext[s], (unsigned long long)__double_as_longlong(e));
+    if (on) {
+      const uint64_t key = Skey[c];
+      const uint32_t ix[3] = {compact3(key >> 2), compact3(key >> 1), compact3(key)};
+      double dd[3];
+      for (int k = 0; k < 3; ++k) {
+        const double ck = centre[3 * (uint64_t)s + k];
+        const double lo = (double)ix[k] / (double)(1ull << bits);
+        const double a = fabs(mimg(lo - ck));
+        const double hi = lo + h;
+        const double b = fabs(mimg(hi - ck));
+        dd[k] = a > b ? a : b;
+      }
+      const double e = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+      ev = (unsigned long long)__double_as_longlong(e);
+    }
+    wave_extreme(ext, s, ev, on, false);
   }
 }
 
@@ -314,6 +379,7 @@ struct LevCells {
 };
 
 constexpr int kQCells = 125;  // cube cells of a query on a level whose cells are >= R/2 wide
+constexpr int kCoarseMax = 4096;  // level-0 cube cells the grid's collection takes for a wide sphere
 
 // The level a sphere of radius R is queried on: the deepest built level whose
 // cells are at least R/2 wide, so that at most 5 per axis cover the sphere
@@ -356,30 +422,32 @@ __device__ inline void resolve_cell(const LevCells& LC, int L, uint64_t key, int
 // most kQCells cells: each cube cell resolved to the deepest cell containing
 // it; the resolved cells are the leaves of the hierarchy cut at level L, so
 // two are equal or disjoint, and the distinct ones cover the cube.  Their
-// starts and counts go to qa, qc (LDS, in no particular order); returns their
-// number (every thread).
+// starts and counts go to qa, qc (LDS) in the order of their first cube cell
+// (the same on every call); returns their number (every thread).
 template <int BT>
 __device__ inline uint32_t fine_cells(const LevCells& LC, int L, const int64_t* lo,
                                       const int64_t* nc, uint64_t ncell, uint32_t* qa,
                                       uint32_t* qc) {
   __shared__ int ql[kQCells];
   __shared__ uint64_t qi[kQCells];
-  __shared__ uint32_t nq;
+  __shared__ double red[BT / 64];
   const uint32_t t = threadIdx.x;
-  if (t == 0) nq = 0;
   if (t < ncell) resolve_cell(LC, L, cube_cell(lo, nc, t, LC.g + L), &ql[t], &qi[t]);
   __syncthreads();
+  bool keep = false;
   if (t < ncell) {
-    bool dup = false;
-    for (uint32_t u = 0; u < t; ++u) dup = dup || (ql[u] == ql[t] && qi[u] == qi[t]);
-    if (!dup) {
-      const uint32_t at = atomicAdd(&nq, 1u);
-      qa[at] = LC.start[ql[t]][qi[t]];
-      qc[at] = LC.count[ql[t]][qi[t]];
-    }
+    keep = true;
+    for (uint32_t u = 0; u < t; ++u) keep = keep && !(ql[u] == ql[t] && qi[u] == qi[t]);
+  }
+  double tot = 0.0;
+  const double inc = block_scan<BT>(keep ? 1.0 : 0.0, red, &tot);
+  if (keep) {
+    const uint32_t at = (uint32_t)inc - 1u;
+    qa[at] = LC.start[ql[t]][qi[t]];
+    qc[at] = LC.count[ql[t]][qi[t]];
   }
   __syncthreads();
-  return nq;
+  return (uint32_t)tot;
 }
 
 // collection radius and an upper bound of the candidates: a host's
@@ -392,7 +460,8 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
                                                const uint32_t* __restrict__ iso_cnt,
                                                const LevCells LC,
                                                double* __restrict__ radius,
-                                               uint32_t* __restrict__ bound) {
+                                               uint32_t* __restrict__ bound,
+                                               uint8_t* __restrict__ coarse) {
   __shared__ double red[kHW];
   __shared__ uint32_t qa[kQCells], qc[kQCells];
   const uint32_t s = blockIdx.x;
@@ -400,6 +469,7 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
     if (threadIdx.x == 0) {
       radius[s] = 0.0;
       bound[s] = iso_cnt[s];
+      coarse[s] = 0;
     }
     return;
   }
@@ -408,6 +478,7 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
     if (threadIdx.x == 0) {
       radius[s] = 0.0;
       bound[s] = 0;
+      coarse[s] = 0;
     }
     return;
   }
@@ -434,6 +505,7 @@ __global__ __launch_bounds__(kHT) void k_bound(const int32_t* __restrict__ s_dep
   if (threadIdx.x == 0) {
     radius[s] = R;
     bound[s] = (uint32_t)t;
+    coarse[s] = ncell > kCoarseMax ? 1 : 0;
   }
 }
 
@@ -451,12 +523,14 @@ __global__ __launch_bounds__(BT) void k_candidates(
     const LevCells LC, const uint32_t* __restrict__ order, PartIn P,
     const uint64_t* __restrict__ cand_off,
     uint32_t* __restrict__ cand, uint32_t* __restrict__ cand_cnt, uint64_t big,
-    const uint32_t* __restrict__ sel) {
+    const uint32_t* __restrict__ sel, const uint8_t* __restrict__ only) {
   constexpr int BW = BT / 64;
   // block b takes structure sel[b] (the wide list) or b; structures with at
-  // least `big` possible candidates go to the wide workgroups
+  // least `big` possible candidates go to the wide workgroups (those with
+  // `only` set: the rest of the wide set is collected by the grid)
   const uint32_t s = sel ? sel[blockIdx.x] : blockIdx.x;
   if ((cand_off[s + 1] - cand_off[s] >= big) != (BT > kHT)) return;
+  if (only && !only[s]) return;
   __shared__ uint32_t cursor;
   __shared__ uint32_t cofs[BT + 1];  // the chunk's particle offsets per cell
   __shared__ uint32_t cst[BT];       // and each cell's first sorted position
@@ -550,20 +624,24 @@ __global__ __launch_bounds__(BT) void k_candidates(
 // are left alone.
 __global__ void k_big_data(const uint64_t* __restrict__ cand_off,
                            const uint32_t* __restrict__ cand_cnt,
-                           const uint32_t* __restrict__ cand, uint64_t ns, uint64_t total,
-                           const double* __restrict__ centre, PartIn P, uint64_t big,
-                           double* __restrict__ rad, float4* __restrict__ vq) {
-  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < total;
-       j += (uint64_t)gridDim.x * blockDim.x) {
-    // the structure of slot j: the last s with cand_off[s] <= j
-    uint64_t lo = 0, hi = ns - 1;
+                           const uint32_t* __restrict__ cand, const uint32_t* __restrict__ gs,
+                           const uint64_t* __restrict__ boff, uint32_t nG,
+                           const double* __restrict__ centre, PartIn P,
+                           const uint8_t* __restrict__ only, double* __restrict__ rad,
+                           float4* __restrict__ vq) {
+  const uint64_t tb = boff[nG];
+  for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < tb;
+       p += (uint64_t)gridDim.x * blockDim.x) {
+    // the wide structure of position p: the last g with boff[g] <= p
+    uint32_t lo = 0, hi = nG - 1;
     while (lo < hi) {
-      const uint64_t mid = (lo + hi + 1) >> 1;
-      if (cand_off[mid] <= j) lo = mid;
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (boff[mid] <= p) lo = mid;
       else hi = mid - 1;
     }
-    const uint64_t s = lo, o = cand_off[s];
-    if (cand_off[s + 1] - o < big || j - o >= cand_cnt[s]) continue;
+    const uint64_t s = gs[lo];
+    if (!only[s] || p - boff[lo] >= cand_cnt[s]) continue;
+    const uint64_t j = cand_off[s] + (p - boff[lo]);
     const uint32_t i = cand[j];
     const double* c = centre + 3 * s;
     const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
@@ -1754,6 +1832,150 @@ __global__ void k_w_seg_mvir(const uint32_t* __restrict__ cofs, uint32_t nG,
   if (lane == 0) m_vir_out[gs[g]] = sm;
 }
 
+// a candidate's distance from the centre c, clamped below at half a position
+// quantum (as everywhere else in this file)
+__device__ inline double cand_radius(const PartIn& P, uint32_t i, const double* c) {
+  const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
+  const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
+  const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  if (r < kHalfQuantum) r = kHalfQuantum;
+  return r;
+}
+
+// bounds of the wide set, per segment
+__global__ void k_w_bounds(const uint64_t* __restrict__ boff, uint32_t nG,
+                           uint32_t* __restrict__ nb) {
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nG; g += gridDim.x * blockDim.x)
+    nb[g] = (uint32_t)(boff[g + 1] - boff[g]);
+}
+
+// The candidates of the wide set (but the coarse substructures) collected by
+// the whole grid: a chunk is kWC of a structure's possible candidates, a
+// host's isodensity list (all of them candidates, at their own slots) or the
+// particles of a substructure's query cells (every block resolves the same
+// cells in the same order); a substructure's candidates get their slots from
+// one atomic per block (in no particular order: the unbinding orders them).
+// Each candidate's radius, velocity and mass are written beside it.
+__global__ __launch_bounds__(kWT) void k_w_collect(
+    const uint32_t* __restrict__ cofs, uint32_t nG, const uint32_t* __restrict__ gs,
+    const int32_t* __restrict__ s_depth, const uint8_t* __restrict__ coarse,
+    const double* __restrict__ centre, const double* __restrict__ radius,
+    const uint64_t* __restrict__ iso_off, const uint32_t* __restrict__ iso_cnt,
+    const uint32_t* __restrict__ iso_list, const LevCells LC, const uint32_t* __restrict__ order,
+    PartIn P, const uint64_t* __restrict__ cand_off, uint32_t* __restrict__ wcnt,
+    uint32_t* __restrict__ cand, double* __restrict__ rad, float4* __restrict__ vq) {
+  __shared__ uint32_t qa[kCoarseMax], qc[kCoarseMax], qo[kCoarseMax + 1];
+  __shared__ double red[kWT / 64];
+  __shared__ uint32_t base;
+  uint32_t g, c;
+  if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
+  const uint32_t s = gs[g];
+  if (coarse[s]) return;
+  const double* ce = centre + 3 * (uint64_t)s;
+  const uint64_t k0 = (uint64_t)c * kWC;
+  uint32_t* out = cand + cand_off[s];
+  double* ro = rad + cand_off[s];
+  float4* vo = vq + cand_off[s];
+  if (s_depth[s] == 0) {  // a host: its isodensity list
+    const uint32_t n = iso_cnt[s];
+    const uint32_t* in = iso_list + iso_off[s];
+    for (int e = 0; e < kWE; ++e) {
+      const uint64_t k = k0 + (uint64_t)e * kWT + threadIdx.x;
+      if (k < n) {
+        const uint32_t i = in[k];
+        out[k] = i;
+        ro[k] = cand_radius(P, i, ce);
+        vo[k] = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+      }
+    }
+    return;
+  }
+  const double R = radius[s];
+  const double R2 = R * R;
+  const int L = query_level(LC, R);
+  int64_t lo[3], nc[3];
+  cube_of(ce, R, LC.g + L, lo, nc);
+  const uint64_t ncube = (uint64_t)nc[0] * (uint64_t)nc[1] * (uint64_t)nc[2];
+  uint32_t nq;
+  if (ncube <= kQCells) {
+    nq = fine_cells<kWT>(LC, L, lo, nc, ncube, qa, qc);
+  } else {  // level 0, at most kCoarseMax cube cells (else the structure is coarse)
+    nq = (uint32_t)ncube;
+    for (uint32_t k = threadIdx.x; k < nq; k += kWT) {
+      const uint64_t cell = cube_cell(lo, nc, k, LC.g);
+      qa[k] = LC.start[0][cell];
+      qc[k] = LC.count[0][cell];
+    }
+    __syncthreads();
+  }
+  {  // the cells' particle offsets, in cell order
+    uint32_t carry = 0;
+    for (uint32_t k0c = 0; k0c < nq; k0c += kWT) {
+      const uint32_t k = k0c + threadIdx.x;
+      const uint32_t q = k < nq ? qc[k] : 0u;
+      double tot = 0.0;
+      const double inc = block_scan<kWT>((double)q, red, &tot);
+      if (k < nq) qo[k] = carry + (uint32_t)inc - q;
+      carry += (uint32_t)tot;
+    }
+    if (threadIdx.x == 0) qo[nq] = carry;
+  }
+  __syncthreads();
+  const uint32_t total = qo[nq];
+  uint32_t pi[kWE];
+  uint32_t mask = 0, cnt = 0;
+#pragma unroll
+  for (int e = 0; e < kWE; ++e) {
+    const uint64_t k = k0 + (uint64_t)e * kWT + threadIdx.x;
+    pi[e] = 0;
+    if (k < total) {
+      uint32_t a = 0, b = nq - 1;  // the last cell whose offset is at most k
+      while (a < b) {
+        const uint32_t mid = (a + b + 1) >> 1;
+        if (qo[mid] <= k) a = mid;
+        else b = mid - 1;
+      }
+      const uint32_t i = order[qa[a] + (uint32_t)(k - qo[a])];
+      pi[e] = i;
+      const double dx = mimg(coord(P.X, P.fx, i) - ce[0]);
+      const double dy = mimg(coord(P.Y, P.fy, i) - ce[1]);
+      const double dz = mimg(coord(P.Z, P.fz, i) - ce[2]);
+      if (dx * dx + dy * dy + dz * dz <= R2) {
+        mask |= 1u << e;
+        ++cnt;
+      }
+    }
+  }
+  double tot = 0.0;
+  const double inc = block_scan<kWT>((double)cnt, red, &tot);
+  if (threadIdx.x == 0) base = atomicAdd(&wcnt[g], (uint32_t)tot);
+  __syncthreads();
+  uint32_t at = base + (uint32_t)inc - cnt;
+#pragma unroll
+  for (int e = 0; e < kWE; ++e) {
+    if ((mask >> e) & 1u) {
+      const uint32_t i = pi[e];
+      out[at] = i;
+      ro[at] = cand_radius(P, i, ce);
+      vo[at] = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+      ++at;
+    }
+  }
+}
+
+// the candidate counts of the wide set collected by the grid
+__global__ void k_w_setcnt(const uint32_t* __restrict__ gs, uint32_t nG,
+                           const int32_t* __restrict__ s_depth, const uint8_t* __restrict__ coarse,
+                           const uint32_t* __restrict__ iso_cnt, const uint32_t* __restrict__ wcnt,
+                           uint32_t* __restrict__ cand_cnt) {
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nG; g += gridDim.x * blockDim.x) {
+    const uint32_t s = gs[g];
+    if (coarse[s]) continue;
+    cand_cnt[s] = s_depth[s] == 0 ? iso_cnt[s] : wcnt[g];
+  }
+}
+
 // mode of every structure: 1 for the wide set (at least `big` possible
 // candidates), else 0 (its own workgroup); a wide one with a long run of tied
 // radii is set to 2 later (one wide workgroup)
@@ -1798,10 +2020,12 @@ struct Halos {
 // Unbinding of the wide set by the whole grid (the kernels above): sort,
 // then rounds until no structure is active, reading the number still active
 // after each round; the members' lists and masses at the end.
+template <class AfterTies>
 static void wide_unbind(Ctx* ctx, Ws& ws, uint32_t nG, uint64_t tb, uint64_t maxch,
                         const uint32_t* gs, const uint64_t* boff, uint32_t* mode,
                         const double* rad, const float4* vslot, const PartIn& P, double rho_thr,
-                        double G, uint32_t max_iter, hipStream_t st, Halos* out) {
+                        double G, uint32_t max_iter, hipStream_t st, Halos* out,
+                        AfterTies after_ties) {
   int gbits = 1;
   while ((1ull << gbits) < nG) ++gbits;
   const SortPlan sp = sort_plan(tb, kRadiusBits + gbits);
@@ -1827,6 +2051,7 @@ static void wide_unbind(Ctx* ctx, Ws& ws, uint32_t nG, uint64_t tb, uint64_t max
   k_w_ties<<<blocks_for(tb), kHB, 0, st>>>(gs, boff, nG, out->cand_cnt, Kt, Kb[0], Ib[0], Vb[0],
                                            mode);
   HIP_LAUNCH_CHECK();
+  after_ties();  // the modes are final from here on
   uint32_t* na = ws.get<uint32_t>(nG);
   uint32_t* act = ws.get<uint32_t>(nG);
   uint32_t* nmem = ws.get<uint32_t>(nG);
@@ -2006,8 +2231,9 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
     LC.count[L] = lv.Scount;
     LC.n[L] = lv.nS;
   }
+  uint8_t* coarse = ws.get<uint8_t>(ns);
   k_bound<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, h->s_host, ext, out->centre, iso_cnt, LC,
-                                        out->radius, bound);
+                                        out->radius, bound, coarse);
   HIP_LAUNCH_CHECK();
   k_offsets<<<1, kHT, 0, st>>>(bound, ns, out->cand_off);
   HIP_LAUNCH_CHECK();
@@ -2051,32 +2277,11 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   HIP_CHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
   HIP_CHECK(hipEventRecord(fork, st));
   HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
-  if (nG) {
-    k_candidates<kHTBig><<<nG, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
-                                                iso_cnt, iso_list, LC, h->order, P,
-                                                out->cand_off, out->cand, out->cand_cnt, large,
-                                                gs);
-    HIP_LAUNCH_CHECK();
-  }
-  k_big_data<<<blocks_for(total), kHB, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, ns,
-                                                total, out->centre, P, large, msum, vslot);
-  HIP_LAUNCH_CHECK();
-  if (nG)
-    wide_unbind(ctx, ws, nG, tb, maxch, gs, boff, mode, msum, vslot, P, delta_vir * rho_b, G,
-                max_iter, st, out);
-  // wide structures whose tied radii were too many for the grid's sort
-  if (nG) {
-    k_unbind<kHTBig><<<nG, kHTBig, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, idx_a, idx_b,
-                                            key_a, key_b, msum, tail, vbuf, vslot, out->centre, P,
-                                            delta_vir * rho_b, G, max_iter, out->member,
-                                            out->member_cnt, out->r_vir, out->m_vir, out->vel,
-                                            out->iters, mode, gs);
-    HIP_LAUNCH_CHECK();
-  }
+  // the small structures first (the wide rounds below wait on the host)
   k_candidates<kHT><<<(unsigned)ns, kHT, 0, s2>>>(h->s_depth, out->centre, out->radius, iso_off,
                                                   iso_cnt, iso_list, LC, h->order, P,
                                                   out->cand_off, out->cand, out->cand_cnt,
-                                                  large, nullptr);
+                                                  large, nullptr, nullptr);
   HIP_LAUNCH_CHECK();
   k_unbind<kHT><<<(unsigned)ns, kHT, 0, s2>>>(out->cand_off, out->cand_cnt, out->cand, idx_a,
                                               idx_b, key_a, key_b, msum, tail, vbuf, vslot,
@@ -2084,6 +2289,47 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
                                               out->member, out->member_cnt, out->r_vir,
                                               out->m_vir, out->vel, out->iters, mode, nullptr);
   HIP_LAUNCH_CHECK();
+  if (nG) {
+    // the wide set's candidates with their radii and velocities: by the grid,
+    // but the coarse substructures' (one wide workgroup each, then the grid)
+    uint32_t* wnb = ws.get<uint32_t>(nG);
+    uint32_t* wcnt = ws.get<uint32_t>(nG);
+    uint32_t* ccofs = ws.get<uint32_t>(nG + 1);
+    k_w_bounds<<<blocks_for(nG), kHB, 0, st>>>(boff, nG, wnb);
+    k_fill_u32<<<blocks_for(nG), kHB, 0, st>>>(wcnt, nG, 0);
+    k_w_chunks<<<1, kHT, 0, st>>>(wnb, wnb, nG, ccofs);
+    HIP_LAUNCH_CHECK();
+    k_w_collect<<<(unsigned)maxch, kWT, 0, st>>>(ccofs, nG, gs, h->s_depth, coarse, out->centre,
+                                                 out->radius, iso_off, iso_cnt, iso_list, LC,
+                                                 h->order, P, out->cand_off, wcnt, out->cand,
+                                                 msum, vslot);
+    HIP_LAUNCH_CHECK();
+    k_w_setcnt<<<blocks_for(nG), kHB, 0, st>>>(gs, nG, h->s_depth, coarse, iso_cnt, wcnt,
+                                               out->cand_cnt);
+    HIP_LAUNCH_CHECK();
+    k_candidates<kHTBig><<<nG, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
+                                                iso_cnt, iso_list, LC, h->order, P,
+                                                out->cand_off, out->cand, out->cand_cnt, large,
+                                                gs, coarse);
+    HIP_LAUNCH_CHECK();
+    k_big_data<<<blocks_for(tb), kHB, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, gs,
+                                               boff, nG, out->centre, P, coarse, msum, vslot);
+    HIP_LAUNCH_CHECK();
+    // the grid's unbinding; the wide structures whose tied radii were too many
+    // for its sort go to one wide workgroup each, on the second stream once
+    // the sort has marked them
+    wide_unbind(ctx, ws, nG, tb, maxch, gs, boff, mode, msum, vslot, P, delta_vir * rho_b, G,
+                max_iter, st, out, [&]() {
+                  HIP_CHECK(hipEventRecord(fork, st));
+                  HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
+                  k_unbind<kHTBig><<<nG, kHTBig, 0, s2>>>(
+                      out->cand_off, out->cand_cnt, out->cand, idx_a, idx_b, key_a, key_b, msum,
+                      tail, vbuf, vslot, out->centre, P, delta_vir * rho_b, G, max_iter,
+                      out->member, out->member_cnt, out->r_vir, out->m_vir, out->vel, out->iters,
+                      mode, gs);
+                  HIP_LAUNCH_CHECK();
+                });
+  }
   HIP_CHECK(hipEventRecord(join, s2));
   HIP_CHECK(hipStreamWaitEvent(st, join, 0));
   HIP_CHECK(hipStreamSynchronize(st));
