@@ -19,14 +19,16 @@
 //     is the radius of the last particle whose enclosed mean density is at
 //     least Delta_vir times the background.
 //
-// Layout: one workgroup per structure for everything that follows one halo
-// (its centre, its sphere query, its unbinding), so that every sum, sort and
-// compaction has a fixed order and reruns are bit-identical; the particle
-// lists of the leaf and isodensity patches are made per cell with atomics
-// (order-free counts and cursors) and sorted by particle index afterwards.
-// The centre does not move while a halo is unbound, so the candidates are
-// sorted by (radius, index) once; each round then keeps that order while it
-// drops the unbound particles.
+// Layout: one workgroup per structure for its centre and bound, and for the
+// sphere query and unbinding of the small structures; the few structures with
+// many possible candidates (the wide set) are collected and unbound by the
+// whole grid together (chunk kernels and per-structure segment kernels).
+// Every sum, sort and compaction has a fixed order, so reruns are
+// bit-identical; the particle lists of the leaf and isodensity patches are made
+// per cell with atomics (order-free counts and cursors, added once per wave)
+// and ordered afterwards.  The centre does not move while a halo is unbound,
+// so the candidates are sorted by (radius, index) once; each round then keeps
+// that order while it drops the unbound particles.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
