@@ -271,13 +271,18 @@ def run_batched(args):
 
 
 def run_served(args):
+    out = served_measure(args.pool, args.requests, args.streams, (0.5, 0.8, 1.2))
+    print(json.dumps(out), flush=True)
+
+
+def served_measure(npool, R, streams, fracs):
     """Poisson stream of sub-volume builds, sizes log-uniform in 1e5..5e7 (seed 4),
     admitted by the server against the HBM budget, results kept resident for
-    follow-up label queries; each arrival rate is run with several streams and
-    with one stream (the sequential per-request path)."""
+    follow-up label queries; each arrival rate (a fraction of the sequential
+    capacity) is run with several streams and with one stream (the
+    sequential per-request path)."""
     import torch
     from paper_0904_3662_amd import ahf, synth
-    npool = args.pool
     sizes = synth.subvolume_sizes(4, npool, 5.0, float(np.log10(5e7)))
     t0 = time.perf_counter()
     subs = [synth.subvolume(4000 + i, int(n)) for i, n in enumerate(sizes)]
@@ -288,7 +293,6 @@ def run_served(args):
     torch.cuda.synchronize()
     ctx = ahf.Context(0)
     rng = np.random.Generator(np.random.PCG64(44))
-    R = args.requests
     pick = rng.integers(0, npool, R)
     # sequential capacity: mean build time over the request mix
     for i in range(npool):
@@ -308,12 +312,12 @@ def run_served(args):
                                   "sub-volumes, N log-uniform 1e5..5e7",
                       "requests": R, "sequential_capacity_req_per_s": capacity},
            "rates": {}}
-    for frac in (0.5, 0.8, 1.2):
+    for frac in fracs:
         lam = frac * capacity
         gaps = rng.exponential(1.0 / lam, R)
         arrive = np.cumsum(gaps)
         res = {}
-        for k in (1, args.streams):
+        for k in (1, streams):
             with ahf.Server(ctx, n_streams=k) as srv:
                 live = []
                 lat = []
@@ -356,13 +360,14 @@ def run_served(args):
             print(f"# rate {frac} x capacity, {k} streams: {el:.2f} s, p99 "
                   f"{res[f'streams_{k}']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
         out["rates"][f"{frac}"] = {"req_per_s": lam, **res}
-    r = out["rates"]["0.8"]
-    out["value"] = r[f"streams_{args.streams}"]["value"]
-    out["p50_ms"] = r[f"streams_{args.streams}"]["p50_ms"]
-    out["p99_ms"] = r[f"streams_{args.streams}"]["p99_ms"]
-    out["n_streams"] = args.streams
+    r = out["rates"][f"{0.8 if 0.8 in fracs else fracs[0]}"]
+    out["value"] = r[f"streams_{streams}"]["value"]
+    out["p50_ms"] = r[f"streams_{streams}"]["p50_ms"]
+    out["p99_ms"] = r[f"streams_{streams}"]["p99_ms"]
+    out["n_streams"] = streams
     ctx.close()
-    print(json.dumps(out), flush=True)
+    del devs
+    return out
 
 
 # per-launch algorithmic bytes of the kernels that can be the roofline kernel
@@ -381,9 +386,7 @@ def kernel_alg_bytes(name, n, key_bits, g, lv_info, launches_per_step):
     if name == "rs_scatter":
         return sort_scatter_bytes(n, key_bits) / max(launches_per_step, 1)
     if name == "gather":
-        # 8 B word and 32 B record read, 32 B record, 4 B index and 8 B key
-        # written per particle, and the level-0 cell starts
-        return 84.0 * n + 4.0 * ((1 << (3 * g)) + 1)
+        return 68.0 * n + 4.0 * ((1 << (3 * g)) + 1)
     L = 0 if name == "tile_deposit0" else 1
     if L >= len(lv_info):
         return None
@@ -546,6 +549,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true",
+                    help="leave the short served stream out of the default line")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched sub-volume measurement of the default line")
     ap.add_argument("--cpu-cube", type=int, default=48,
@@ -634,6 +639,10 @@ def main():
     if not args.no_batched:
         # the batched form: 64 sub-volumes, sequential vs server vs batch
         rec["batched"] = batched_measure(args.warmup, chains=(1, 4), servers=(4,), runs=3)
+    if not args.no_served:
+        # the served form: a short Poisson stream at 0.8 of the sequential
+        # capacity, 4 streams against one
+        rec["served"] = served_measure(8, 300, 4, (0.8,))
     if not args.no_cpu_baseline:
         share = host_info()["affinity"]
         threads = args.cpu_threads or min(16, share)
