@@ -2030,6 +2030,8 @@ static void wide_unbind(Ctx* ctx, Ws& ws, uint32_t nG, uint64_t tb, uint64_t max
                         AfterTies after_ties) {
   int gbits = 1;
   while ((1ull << gbits) < nG) ++gbits;
+  if (kRadiusBits + gbits > 64)  // the sort key is (structure, top radius bits)
+    throw Error{AHF_ELIMIT, "too many structures for the grid's unbinding (raise large_from)"};
   const SortPlan sp = sort_plan(tb, kRadiusBits + gbits);
   uint64_t* keys = ws.get<uint64_t>(tb);
   uint32_t* ghist = ws.get<uint32_t>(kRsMaxPass * 256);
