@@ -503,15 +503,35 @@ def measure(ctx, snap, dev, stream, steps, warmup, extras=True):
         h.free()
     # the paper-literal density criterion (refine on the TSC particle number):
     # same workload and thresholds, whole builds timed
+    # these builds run on one stream, so the roofline kernel runs there
+    # alone: its HIP-event time in builds 2-4 and its own level sizes
     dens = []
+    dens_lv = None
     for i in range(4):
+        if i == 1:
+            ctx.profile_only([rk])
+            ctx.set_profiling(True)
         torch.cuda.synchronize()
         a = time.perf_counter()
         h, _ = ahf.build_snapshot(ctx, snap, dev=dev, stream=stream, density_criterion=True)
         torch.cuda.synchronize()
         dens.append((time.perf_counter() - a) * 1e3)
         dens_levels = h.num_levels()
+        if i == 0:
+            dens_lv = [dict(n_particles=v.n_particles, n_cells=v.n_cells, n_bricks=v.n_bricks)
+                       for v in (h.view(L) for L in range(h.num_levels()))]
         h.free()
+    alone_n, alone_t = ctx.kernel_time(rk)
+    ctx.set_profiling(False)
+    alone_b = kernel_alg_bytes(rk, n, key_bits, snap.g, dens_lv, max(alone_n // 3, 1))
+    if alone_n and alone_b:
+        alone_ms = alone_t / alone_n
+        out["roofline"]["alone"] = {
+            "what": "the same kernel in the one-stream builds of the density criterion, "
+                    "priced on their own level sizes",
+            "avg_launch_ms": alone_ms, "launches": alone_n, "algorithmic_bytes_per_launch": alone_b,
+            "achieved": alone_b / (alone_ms * 1e-3) / 1e9,
+            "frac": alone_b / (alone_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     out["substructure"] = {"ms": float(np.median(cls)), "structures": int(nstruct)}
     # particle collection and unbinding of every structure (needs velocities)
     if snap.vel is not None:
