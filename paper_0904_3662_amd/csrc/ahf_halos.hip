@@ -279,19 +279,55 @@ __global__ __launch_bounds__(kHT) void k_offsets(const uint32_t* __restrict__ cn
 
 // ---------------------------------------------------------------- per-halo kernels
 
+// One particle as the halo kernels read it, in input order: its position as
+// coordinates in box units (integer part plus fraction, times the quantum),
+// then its velocity and mass (0 where the particles share mass_scalar).  The
+// kernels reach particles by index, at random; one aligned 64-byte record
+// per particle makes each such access one line instead of one per array.
+struct alignas(64) PRec {
+  double x, y, z, spare;
+  float4 vm;  // vx, vy, vz, mass
+  uint32_t pad[4];
+};
+static_assert(sizeof(PRec) == 64, "one record per 64-byte line");
+
 struct PartIn {
   const uint32_t *X, *Y, *Z;
   const float *fx, *fy, *fz;  // may be null
   const float* mass;          // null: every particle has mass_scalar
   double mass_scalar;
   const float *vx, *vy, *vz;
+  const PRec* R;              // the records (k_stage), n of them
 };
 
 __device__ inline double coord(const uint32_t* X, const float* f, uint32_t i) {
   return ((double)X[i] + (f ? (double)f[i] : 0.0)) * kQuantum;
 }
+// particle i's position, velocity and mass from its record
+__device__ inline void ppos(const PartIn& P, uint32_t i, double& x, double& y, double& z) {
+  const double2 a = *reinterpret_cast<const double2*>(&P.R[i].x);
+  x = a.x;
+  y = a.y;
+  z = P.R[i].z;
+}
+__device__ inline float4 pvel(const PartIn& P, uint32_t i) { return P.R[i].vm; }
 __device__ inline double pmass(const PartIn& P, uint32_t i) {
-  return P.mass ? (double)P.mass[i] : P.mass_scalar;
+  return P.mass ? (double)P.R[i].vm.w : P.mass_scalar;
+}
+
+// the records of the n particles
+__global__ void k_stage(PartIn P, uint64_t n, PRec* __restrict__ R) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    PRec r;
+    r.x = coord(P.X, P.fx, (uint32_t)i);
+    r.y = coord(P.Y, P.fy, (uint32_t)i);
+    r.z = coord(P.Z, P.fz, (uint32_t)i);
+    r.spare = 0.0;
+    r.vm = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+    r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0u;
+    R[i] = r;
+  }
 }
 
 // centre of every structure: the leaf list sorted by particle index, then the
@@ -320,9 +356,11 @@ __global__ __launch_bounds__(kHT) void k_centre(const uint64_t* __restrict__ lea
   for (uint32_t k = threadIdx.x; k < n; k += kHT) {
     const uint32_t i = idx[k];
     const double w = pmass(P, i);
-    sx += w * mimg(coord(P.X, P.fx, i) - ref[0]);
-    sy += w * mimg(coord(P.Y, P.fy, i) - ref[1]);
-    sz += w * mimg(coord(P.Z, P.fz, i) - ref[2]);
+    double x, y, z;
+    ppos(P, i, x, y, z);
+    sx += w * mimg(x - ref[0]);
+    sy += w * mimg(y - ref[1]);
+    sz += w * mimg(z - ref[2]);
     sw += w;
   }
   sx = block_sum(sx, red);
@@ -599,9 +637,7 @@ __global__ __launch_bounds__(BT) void k_candidates(
 #pragma unroll
       for (int j = 0; j < kRows; ++j) {
         if (f0 + j * BT < total) {
-          px[j] = coord(P.X, P.fx, pi[j]);
-          py[j] = coord(P.Y, P.fy, pi[j]);
-          pz[j] = coord(P.Z, P.fz, pi[j]);
+          ppos(P, pi[j], px[j], py[j], pz[j]);
         }
       }
 #pragma unroll
@@ -646,13 +682,15 @@ __global__ void k_big_data(const uint64_t* __restrict__ cand_off,
     const uint64_t j = cand_off[s] + (p - boff[lo]);
     const uint32_t i = cand[j];
     const double* c = centre + 3 * s;
-    const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
-    const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
-    const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
+    double x, y, z;
+    ppos(P, i, x, y, z);
+    const double dx = mimg(x - c[0]);
+    const double dy = mimg(y - c[1]);
+    const double dz = mimg(z - c[2]);
     double r = sqrt(dx * dx + dy * dy + dz * dz);
     if (r < kHalfQuantum) r = kHalfQuantum;
     rad[j] = r;
-    vq[j] = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+    vq[j] = pvel(P, i);
   }
 }
 
@@ -773,9 +811,7 @@ __global__ __launch_bounds__(BT) void k_unbind(
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
       if (k0 + j * BT < n) {
-        px[j] = coord(P.X, P.fx, pi[j]);
-        py[j] = coord(P.Y, P.fy, pi[j]);
-        pz[j] = coord(P.Z, P.fz, pi[j]);
+        ppos(P, pi[j], px[j], py[j], pz[j]);
       }
     }
 #pragma unroll
@@ -819,7 +855,7 @@ __global__ __launch_bounds__(BT) void k_unbind(
       if (k0 + j * BT < n) {
         const uint32_t i = iv[j];
         qv[j] = kPre ? VS[sl[j]]
-                     : make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+                     : pvel(P, i);
       }
     }
 #pragma unroll
@@ -872,9 +908,11 @@ __global__ __launch_bounds__(BT) void k_unbind(
     uint64_t* kx = ft ? kb : ka;  // the truncated keys' buffer, now free
     for (uint32_t k = threadIdx.x; k < n; k += BT) {
       const uint32_t i = cs[k];
-      const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
-      const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
-      const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
+      double x, y, z;
+      ppos(P, i, x, y, z);
+      const double dx = mimg(x - c[0]);
+      const double dy = mimg(y - c[1]);
+      const double dz = mimg(z - c[2]);
       double r = sqrt(dx * dx + dy * dy + dz * dz);
       if (r < kHalfQuantum) r = kHalfQuantum;
       kx[k] = (uint64_t)__double_as_longlong(r);
@@ -892,7 +930,7 @@ __global__ __launch_bounds__(BT) void k_unbind(
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < n; k += BT) {
       const uint32_t i = I[k];
-      V[k] = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+      V[k] = pvel(P, i);
     }
     __syncthreads();
   }
@@ -1837,9 +1875,11 @@ __global__ void k_w_seg_mvir(const uint32_t* __restrict__ cofs, uint32_t nG,
 // a candidate's distance from the centre c, clamped below at half a position
 // quantum (as everywhere else in this file)
 __device__ inline double cand_radius(const PartIn& P, uint32_t i, const double* c) {
-  const double dx = mimg(coord(P.X, P.fx, i) - c[0]);
-  const double dy = mimg(coord(P.Y, P.fy, i) - c[1]);
-  const double dz = mimg(coord(P.Z, P.fz, i) - c[2]);
+  double x, y, z;
+  ppos(P, i, x, y, z);
+  const double dx = mimg(x - c[0]);
+  const double dy = mimg(y - c[1]);
+  const double dz = mimg(z - c[2]);
   double r = sqrt(dx * dx + dy * dy + dz * dz);
   if (r < kHalfQuantum) r = kHalfQuantum;
   return r;
@@ -1888,7 +1928,7 @@ __global__ __launch_bounds__(kWT) void k_w_collect(
         const uint32_t i = in[k];
         out[k] = i;
         ro[k] = cand_radius(P, i, ce);
-        vo[k] = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+        vo[k] = pvel(P, i);
       }
     }
     return;
@@ -1940,9 +1980,11 @@ __global__ __launch_bounds__(kWT) void k_w_collect(
       }
       const uint32_t i = order[qa[a] + (uint32_t)(k - qo[a])];
       pi[e] = i;
-      const double dx = mimg(coord(P.X, P.fx, i) - ce[0]);
-      const double dy = mimg(coord(P.Y, P.fy, i) - ce[1]);
-      const double dz = mimg(coord(P.Z, P.fz, i) - ce[2]);
+      double x, y, z;
+      ppos(P, i, x, y, z);
+      const double dx = mimg(x - ce[0]);
+      const double dy = mimg(y - ce[1]);
+      const double dz = mimg(z - ce[2]);
       if (dx * dx + dy * dy + dz * dz <= R2) {
         mask |= 1u << e;
         ++cnt;
@@ -1960,7 +2002,7 @@ __global__ __launch_bounds__(kWT) void k_w_collect(
       const uint32_t i = pi[e];
       out[at] = i;
       ro[at] = cand_radius(P, i, ce);
-      vo[at] = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+      vo[at] = pvel(P, i);
       ++at;
     }
   }
@@ -2147,7 +2189,13 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
     return;
   }
   const uint64_t n = h->n;
-  PartIn P{p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass, p.mass_scalar, vx, vy, vz};
+  PartIn P{p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass, p.mass_scalar, vx, vy, vz, nullptr};
+  {  // the particles' records: every later kernel reads particles from them
+    PRec* R = ws.get<PRec>(n ? n : 1);
+    k_stage<<<blocks_for(n ? n : 1), kHB, 0, st>>>(P, n, R);
+    HIP_LAUNCH_CHECK();
+    P.R = R;
+  }
   unsigned long long* leaf_min = ws.get<unsigned long long>(ns);
   uint32_t* leaf_cnt = ws.get<uint32_t>(ns);
   uint32_t* iso_cnt = ws.get<uint32_t>(ns);
