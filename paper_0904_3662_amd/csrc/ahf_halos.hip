@@ -315,20 +315,44 @@ __device__ inline double pmass(const PartIn& P, uint32_t i) {
   return P.mass ? (double)P.R[i].vm.w : P.mass_scalar;
 }
 
-// the records of the n particles
+// the records of the n particles (F: all three fractions are given, else
+// each may be null; M: the masses are given; as template arguments, so that
+// every load of a particle is issued at once)
+template <bool F, bool M>
 __global__ void k_stage(PartIn P, uint64_t n, PRec* __restrict__ R) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t X = P.X[i], Y = P.Y[i], Z = P.Z[i];
+    const float fx = (F || P.fx) ? P.fx[i] : 0.0f;
+    const float fy = (F || P.fy) ? P.fy[i] : 0.0f;
+    const float fz = (F || P.fz) ? P.fz[i] : 0.0f;
+    const float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+    const float m = M ? P.mass[i] : 0.0f;
     PRec r;
-    r.x = coord(P.X, P.fx, (uint32_t)i);
-    r.y = coord(P.Y, P.fy, (uint32_t)i);
-    r.z = coord(P.Z, P.fz, (uint32_t)i);
+    r.x = ((double)X + (double)fx) * kQuantum;  // as coord()
+    r.y = ((double)Y + (double)fy) * kQuantum;
+    r.z = ((double)Z + (double)fz) * kQuantum;
     r.spare = 0.0;
-    r.vm = make_float4(P.vx[i], P.vy[i], P.vz[i], P.mass ? P.mass[i] : 0.0f);
+    r.vm = make_float4(vx, vy, vz, m);
     r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0u;
     R[i] = r;
   }
 }
+
+// the fork and join events of the step's two streams, destroyed on every path
+struct StreamEvents {
+  hipEvent_t fork = nullptr, join = nullptr;
+  StreamEvents() {
+    HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  }
+  ~StreamEvents() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
+  StreamEvents(const StreamEvents&) = delete;
+  StreamEvents& operator=(const StreamEvents&) = delete;
+};
 
 // centre of every structure: the leaf list sorted by particle index, then the
 // mass-weighted mean of the minimum-image offsets from the lower corner of the
@@ -1577,7 +1601,9 @@ __device__ inline double tail_term(const uint64_t* K, const double* M, uint64_t 
 }
 
 // per chunk: the sum of its terms below v (each thread its kWE consecutive
-// ones from the top, then the workgroup's fixed tree)
+// ones from the top, then the workgroup's fixed tree); the terms are formed
+// from coalesced loads into LDS first, as in k_w_tail2 (the terms are not
+// negative, so those past v add zeros that change no sum)
 __global__ __launch_bounds__(kWT) void k_w_tail1(const uint32_t* __restrict__ cofs, uint32_t nG,
                                                  const uint64_t* __restrict__ boff,
                                                  const uint32_t* __restrict__ act,
@@ -1585,17 +1611,26 @@ __global__ __launch_bounds__(kWT) void k_w_tail1(const uint32_t* __restrict__ co
                                                  const uint64_t* __restrict__ K,
                                                  const double* __restrict__ M,
                                                  double* __restrict__ ttot) {
+  __shared__ double sv[kWPad];
   __shared__ double red[kWT / 64];
   uint32_t g, c;
   if (!chunk_of(cofs, nG, blockIdx.x, &g, &c)) return;
   if (!act[g]) return;
   const uint64_t k0 = (uint64_t)c * kWC, b0 = boff[g];
   const int64_t v = vseg[g];
-  double run = 0.0;
-  for (int e = kWE - 1; e >= 0; --e) {
-    const uint64_t k = k0 + (uint64_t)threadIdx.x * kWE + e;
-    if ((int64_t)k < v) run += tail_term(K + b0, M + b0, k);
+  if ((int64_t)k0 >= v) {  // the whole chunk at or past v (uniform): no terms
+    if (threadIdx.x == 0) ttot[blockIdx.x] = 0.0;
+    return;
   }
+  for (int e = 0; e < kWE; ++e) {
+    const int i = e * kWT + threadIdx.x;
+    const uint64_t k = k0 + i;
+    sv[wpad(i)] = (int64_t)k < v ? tail_term(K + b0, M + b0, k) : 0.0;
+  }
+  __syncthreads();
+  double run = 0.0;
+#pragma unroll
+  for (int e = kWE - 1; e >= 0; --e) run += sv[wpad(threadIdx.x * kWE + e)];
   run = block_sum<kWT>(run, red);
   if (threadIdx.x == 0) ttot[blockIdx.x] = run;
 }
@@ -2030,6 +2065,13 @@ __global__ void k_w_mode(const uint64_t* __restrict__ cand_off, uint64_t ns, uin
     mode[s] = (cand_off[s + 1] - cand_off[s] >= big) ? 1u : 0u;
 }
 
+// the candidate count of each wide structure, by its place in the wide list
+__global__ void k_w_counts(const uint32_t* __restrict__ gs, uint32_t nG,
+                           const uint32_t* __restrict__ cand_cnt, uint32_t* __restrict__ wc) {
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < nG; g += gridDim.x * blockDim.x)
+    wc[g] = cand_cnt[gs[g]];
+}
+
 // the results of the wide structures without candidates
 __global__ void k_w_empty(const uint32_t* __restrict__ gs, uint32_t nG,
                           const uint32_t* __restrict__ cand_cnt, const uint32_t* __restrict__ mode,
@@ -2118,6 +2160,9 @@ static void wide_unbind(Ctx* ctx, Ws& ws, uint32_t nG, uint64_t tb, uint64_t max
   uint32_t* cgone = ws.get<uint32_t>(maxch);
   uint32_t* koff = ws.get<uint32_t>(maxch);
   k_fill_u32<<<blocks_for(nG), kHB, 0, st>>>(nmem, nG, 0);
+  // a segment without candidates has no position to set its state from
+  k_fill_u32<<<blocks_for(nG), kHB, 0, st>>>(na, nG, 0);
+  k_fill_u32<<<blocks_for(nG), kHB, 0, st>>>(act, nG, 0);
   HIP_LAUNCH_CHECK();
   k_w_start<<<blocks_for(tb), kHB, 0, st>>>(gs, boff, nG, out->cand_off, out->cand_cnt, Ib[0],
                                             mode, out->cand, na, act);
@@ -2190,10 +2235,22 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   }
   const uint64_t n = h->n;
   PartIn P{p.x, p.y, p.z, p.fx, p.fy, p.fz, p.mass, p.mass_scalar, vx, vy, vz, nullptr};
-  {  // the particles' records: every later kernel reads particles from them
+  if (!ctx->dep_st) HIP_CHECK(hipStreamCreateWithFlags(&ctx->dep_st, hipStreamNonBlocking));
+  hipStream_t s2 = ctx->dep_st;
+  StreamEvents ev;
+  {  // the particles' records, on the second stream beside the lists below:
+     // every kernel from the centres on reads particles from them
     PRec* R = ws.get<PRec>(n ? n : 1);
-    k_stage<<<blocks_for(n ? n : 1), kHB, 0, st>>>(P, n, R);
+    HIP_CHECK(hipEventRecord(ev.fork, st));
+    HIP_CHECK(hipStreamWaitEvent(s2, ev.fork, 0));
+    const unsigned nb = blocks_for(n ? n : 1);
+    const bool F = P.fx && P.fy && P.fz;
+    if (F && P.mass) k_stage<true, true><<<nb, kHB, 0, s2>>>(P, n, R);
+    else if (F) k_stage<true, false><<<nb, kHB, 0, s2>>>(P, n, R);
+    else if (P.mass) k_stage<false, true><<<nb, kHB, 0, s2>>>(P, n, R);
+    else k_stage<false, false><<<nb, kHB, 0, s2>>>(P, n, R);
     HIP_LAUNCH_CHECK();
+    HIP_CHECK(hipEventRecord(ev.join, s2));
     P.R = R;
   }
   unsigned long long* leaf_min = ws.get<unsigned long long>(ns);
@@ -2259,6 +2316,7 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
       HIP_LAUNCH_CHECK();
     }
   }
+  HIP_CHECK(hipStreamWaitEvent(st, ev.join, 0));  // the records
   k_centre<<<(unsigned)ns, kHT, 0, st>>>(leaf_off, leaf_cnt, leaf_list, leaf_tmp, out->leafkey,
                                          leaf_min, h->prm.g, P, out->centre);
   HIP_LAUNCH_CHECK();
@@ -2322,11 +2380,17 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   // each; beside them, on st, the wide set's candidates (a workgroup of
   // kHTBig threads each), their radii and velocities found by the whole grid,
   // and their unbinding by the grid (wide_unbind).
-  if (!ctx->dep_st) HIP_CHECK(hipStreamCreateWithFlags(&ctx->dep_st, hipStreamNonBlocking));
-  hipStream_t s2 = ctx->dep_st;
-  hipEvent_t fork = nullptr, join = nullptr;
-  HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-  HIP_CHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+  hipEvent_t fork = ev.fork, join = ev.join;
+  if (nG) {
+    // the coarse substructures' candidates (one wide workgroup each) before
+    // the second stream starts: its many small workgroups would otherwise
+    // hold the compute units these need
+    k_candidates<kHTBig><<<nG, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
+                                                iso_cnt, iso_list, LC, h->order, P,
+                                                out->cand_off, out->cand, out->cand_cnt, large,
+                                                gs, coarse);
+    HIP_LAUNCH_CHECK();
+  }
   HIP_CHECK(hipEventRecord(fork, st));
   HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
   // the small structures first (the wide rounds below wait on the host)
@@ -2359,34 +2423,43 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
     k_w_setcnt<<<blocks_for(nG), kHB, 0, st>>>(gs, nG, h->s_depth, coarse, iso_cnt, wcnt,
                                                out->cand_cnt);
     HIP_LAUNCH_CHECK();
-    k_candidates<kHTBig><<<nG, kHTBig, 0, st>>>(h->s_depth, out->centre, out->radius, iso_off,
-                                                iso_cnt, iso_list, LC, h->order, P,
-                                                out->cand_off, out->cand, out->cand_cnt, large,
-                                                gs, coarse);
-    HIP_LAUNCH_CHECK();
     k_big_data<<<blocks_for(tb), kHB, 0, st>>>(out->cand_off, out->cand_cnt, out->cand, gs,
                                                boff, nG, out->centre, P, coarse, msum, vslot);
     HIP_LAUNCH_CHECK();
-    // the grid's unbinding; the wide structures whose tied radii were too many
-    // for its sort go to one wide workgroup each, on the second stream once
-    // the sort has marked them
-    wide_unbind(ctx, ws, nG, tb, maxch, gs, boff, mode, msum, vslot, P, delta_vir * rho_b, G,
-                max_iter, st, out, [&]() {
-                  HIP_CHECK(hipEventRecord(fork, st));
-                  HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
-                  k_unbind<kHTBig><<<nG, kHTBig, 0, s2>>>(
-                      out->cand_off, out->cand_cnt, out->cand, idx_a, idx_b, key_a, key_b, msum,
-                      tail, vbuf, vslot, out->centre, P, delta_vir * rho_b, G, max_iter,
-                      out->member, out->member_cnt, out->r_vir, out->m_vir, out->vel, out->iters,
-                      mode, gs);
-                  HIP_LAUNCH_CHECK();
-                });
+    // the grid's unbinding, on the wide set's candidates packed (segments
+    // as long as their counts, not their possible counts: the sort and the
+    // rounds skip the slack); the wide structures whose tied radii were too
+    // many for its sort go to one wide workgroup each, on the second stream
+    // once the sort has marked them
+    uint32_t* wc = ws.get<uint32_t>(nG);
+    uint64_t* coff = ws.get<uint64_t>(nG + 1);
+    k_w_counts<<<blocks_for(nG), kHB, 0, st>>>(gs, nG, out->cand_cnt, wc);
+    k_offsets<<<1, kHT, 0, st>>>(wc, nG, coff);
+    HIP_LAUNCH_CHECK();
+    uint64_t tc = 0;
+    HIP_CHECK(hipMemcpyAsync(&tc, coff + nG, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (tc == 0) {  // no wide structure has a candidate
+      k_w_empty<<<blocks_for(nG), kHB, 0, st>>>(gs, nG, out->cand_cnt, mode, out->member_cnt,
+                                                out->r_vir, out->m_vir, out->vel, out->iters);
+      HIP_LAUNCH_CHECK();
+    } else {
+      wide_unbind(ctx, ws, nG, tc, maxch, gs, coff, mode, msum, vslot, P, delta_vir * rho_b, G,
+                  max_iter, st, out, [&]() {
+                    HIP_CHECK(hipEventRecord(fork, st));
+                    HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
+                    k_unbind<kHTBig><<<nG, kHTBig, 0, s2>>>(
+                        out->cand_off, out->cand_cnt, out->cand, idx_a, idx_b, key_a, key_b,
+                        msum, tail, vbuf, vslot, out->centre, P, delta_vir * rho_b, G, max_iter,
+                        out->member, out->member_cnt, out->r_vir, out->m_vir, out->vel,
+                        out->iters, mode, gs);
+                    HIP_LAUNCH_CHECK();
+                  });
+    }
   }
   HIP_CHECK(hipEventRecord(join, s2));
   HIP_CHECK(hipStreamWaitEvent(st, join, 0));
   HIP_CHECK(hipStreamSynchronize(st));
-  HIP_CHECK(hipEventDestroy(fork));
-  HIP_CHECK(hipEventDestroy(join));
 }
 
 }  // namespace ahf

@@ -113,6 +113,30 @@ def test_halos_with_particle_masses_and_a_tight_overdensity():
     compare(res, ores, "masses", p)
 
 
+@pytest.mark.parametrize("given", ["none", "x-only"])
+def test_halos_without_position_fractions(given):
+    """The fraction arrays left out (all, or y and z): the build and the halo
+    step take the missing fractions as 0, the oracle runs on the same
+    particles with those fractions zeroed."""
+    import torch
+    from paper_0904_3662_amd import ahf
+    p = synth.small_mixed(1, velocities=True)
+    p.fy[:] = 0.0
+    p.fz[:] = 0.0
+    if given == "none":
+        p.fx[:] = 0.0
+    x, y, z, fx, fy, fz, m = ahf.snapshot_to_device(p)
+    dev = (x, y, z, fx if given == "x-only" else None, None, None, m)
+    vel = torch.from_numpy(p.vel).cuda()
+    with ahf.Context(0) as ctx:
+        h, _ = ahf.build_snapshot(ctx, p, dev=dev, substructure=True)
+        res = ahf.find_halos(ctx, h, dev, vel, large_from=100)
+        h.free()
+    ores, _ = oracle_halos(p)
+    assert len(ores) > 3
+    compare(res, ores, "fractions " + given, p)
+
+
 def test_halos_need_a_classified_hierarchy():
     import torch
     from paper_0904_3662_amd import ahf
