@@ -258,22 +258,99 @@ __global__ void k_extent(int L, int bits, uint64_t nS, uint64_t npatch,
   }
 }
 
-// exclusive scan of n counts into n+1 offsets, one workgroup, in order
-__global__ __launch_bounds__(kHT) void k_offsets(const uint32_t* __restrict__ cnt, uint64_t n,
-                                                 uint64_t* __restrict__ off) {
-  __shared__ double red[kHW];
-  uint64_t carry = 0;
-  for (uint64_t c0 = 0; c0 < n; c0 += kHT) {
-    const uint64_t i = c0 + threadIdx.x;
-    const uint32_t v = i < n ? cnt[i] : 0u;
-    // counts fit a double exactly (sums below 2^53)
-    double total = 0.0;
-    const double incl = block_scan((double)v, red, &total);
-    if (i < n) off[i] = carry + (uint64_t)incl - v;
-    carry += (uint64_t)total;
-    __syncthreads();
+// Device-wide exclusive scans of integer values f(0..n-1) into n+1 offsets
+// (off[n] = the total): the blocks' sums, one scan of those, then each
+// block's own prefixes.  Integer sums, so the offsets do not depend on the
+// order of the additions.
+constexpr int kSB = 256, kSI = 16, kSC = kSB * kSI;  // threads, items each, items per block
+
+struct CountOf {  // the values of a count array
+  const uint32_t* c;
+  __device__ uint64_t operator()(uint64_t i) const { return c[i]; }
+};
+
+// exclusive scan of one value per thread over a workgroup of BT threads;
+// *total = the workgroup's sum
+template <int BT>
+__device__ inline uint64_t block_escan_u64(uint64_t x, uint64_t* red, uint64_t* total) {
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  uint64_t inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
   }
-  if (threadIdx.x == 0) off[n] = carry;
+  __syncthreads();
+  if (lane == 63) red[w] = inc;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+  for (int i = 0; i < BT / 64; ++i) {
+    if (i < w) before += red[i];
+    all += red[i];
+  }
+  *total = all;
+  return before + inc - x;
+}
+
+template <class F>
+__global__ __launch_bounds__(kSB) void k_scan_part(F f, uint64_t n, uint64_t* __restrict__ part) {
+  __shared__ uint64_t red[kSB / 64];
+  const uint64_t b0 = (uint64_t)blockIdx.x * kSC;
+  uint64_t v = 0;
+  for (int e = 0; e < kSI; ++e) {
+    const uint64_t i = b0 + (uint64_t)e * kSB + threadIdx.x;
+    if (i < n) v += f(i);
+  }
+  uint64_t total = 0;
+  (void)block_escan_u64<kSB>(v, red, &total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// the blocks' sums scanned in place (one workgroup); *total = their sum
+__global__ __launch_bounds__(1024) void k_scan_top(uint64_t* __restrict__ part, uint64_t nb,
+                                                   uint64_t* __restrict__ total) {
+  __shared__ uint64_t red[1024 / 64];
+  uint64_t carry = 0;
+  for (uint64_t c0 = 0; c0 < nb; c0 += 1024) {
+    const uint64_t i = c0 + threadIdx.x;
+    const uint64_t v = i < nb ? part[i] : 0;
+    uint64_t t = 0;
+    const uint64_t ex = block_escan_u64<1024>(v, red, &t);
+    if (i < nb) part[i] = carry + ex;
+    carry += t;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+// each thread its kSI consecutive values
+template <class F>
+__global__ __launch_bounds__(kSB) void k_scan_apply(F f, uint64_t n, const uint64_t* __restrict__ part,
+                                                    uint64_t* __restrict__ off) {
+  __shared__ uint64_t red[kSB / 64];
+  const uint64_t i0 = (uint64_t)blockIdx.x * kSC + (uint64_t)threadIdx.x * kSI;
+  uint64_t v[kSI];
+  uint64_t s = 0;
+#pragma unroll
+  for (int e = 0; e < kSI; ++e) {
+    v[e] = i0 + e < n ? f(i0 + e) : 0;
+    s += v[e];
+  }
+  uint64_t total = 0;
+  uint64_t run = part[blockIdx.x] + block_escan_u64<kSB>(s, red, &total);
+#pragma unroll
+  for (int e = 0; e < kSI; ++e) {
+    if (i0 + e < n) off[i0 + e] = run;
+    run += v[e];
+  }
+}
+
+template <class F>
+static void scan_offsets(Ws& ws, F f, uint64_t n, uint64_t* off, hipStream_t st) {
+  const uint64_t nb = n ? (n + kSC - 1) / kSC : 1;
+  uint64_t* part = ws.get<uint64_t>(nb);
+  k_scan_part<F><<<(unsigned)nb, kSB, 0, st>>>(f, n, part);
+  k_scan_top<<<1, 1024, 0, st>>>(part, nb, off + n);
+  k_scan_apply<F><<<(unsigned)nb, kSB, 0, st>>>(f, n, part, off);
+  HIP_LAUNCH_CHECK();
 }
 
 
@@ -1181,6 +1258,7 @@ __global__ __launch_bounds__(BT) void k_unbind(
 constexpr int kWT = 256;                 // threads of the chunk kernels
 constexpr int kWE = 16;                  // particles per thread and chunk
 constexpr uint32_t kWC = kWT * kWE;      // particles per chunk
+constexpr uint32_t kRoundsPerCheck = 4;  // unbinding rounds per host read of the active count
 constexpr int kTruncShift = 64 - kRadiusBits;  // radius bits the sort leaves out
 
 // segment (wide structure) and chunk of block b in this round's chunk table
@@ -1199,39 +1277,38 @@ __device__ inline bool chunk_of(const uint32_t* __restrict__ cofs, uint32_t nG, 
   return true;
 }
 
-// the wide set: structures with at least `big` possible candidates, in
-// structure order (one workgroup scans the flags), their offsets in the wide
-// arrays (by their bounds) and the chunks they need at most
-__global__ __launch_bounds__(kHT) void k_w_list(const uint64_t* __restrict__ cand_off, uint64_t ns,
-                                                uint64_t big, uint32_t* __restrict__ gs,
-                                                uint64_t* __restrict__ boff,
-                                                uint64_t* __restrict__ sizes) {
-  __shared__ double red[kHW];
-  uint64_t ng = 0, tb = 0, ch = 0;
-  for (uint64_t c0 = 0; c0 < ns; c0 += kHT) {
-    const uint64_t s = c0 + threadIdx.x;
-    const uint64_t b = s < ns ? cand_off[s + 1] - cand_off[s] : 0;
-    const bool w = s < ns && b >= big;
-    double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-    const double i1 = block_scan(w ? 1.0 : 0.0, red, &t1);
-    const double i2 = block_scan(w ? (double)b : 0.0, red, &t2);
-    const double i3 = block_scan(w ? (double)((b + kWC - 1) / kWC) : 0.0, red, &t3);
-    (void)i3;
-    if (w) {
-      const uint64_t g = ng + (uint64_t)i1 - 1;
-      gs[g] = (uint32_t)s;
-      boff[g] = tb + (uint64_t)i2 - b;
-    }
-    ng += (uint64_t)t1;
-    tb += (uint64_t)t2;
-    ch += (uint64_t)t3;
-    __syncthreads();
+// The wide set: the structures with at least `big` possible candidates, in
+// structure order.  WideVal gives, for structure s, 0 below big, else 1, its
+// possible count or its chunks (what = 0, 1, 2); k_w_place puts the wide
+// ones in the list from the scans of those: gs[g] = s, boff[g] = the start
+// of its segment, and sizes = (the set's size, its possible candidates, its
+// chunks).
+struct WideVal {
+  const uint64_t* cand_off;
+  uint64_t big;
+  int what;
+  __device__ uint64_t operator()(uint64_t s) const {
+    const uint64_t b = cand_off[s + 1] - cand_off[s];
+    if (b < big) return 0;
+    return what == 0 ? 1 : (what == 1 ? b : (b + kWC - 1) / kWC);
   }
-  if (threadIdx.x == 0) {
-    boff[ng] = tb;
-    sizes[0] = ng;
-    sizes[1] = tb;
-    sizes[2] = ch;
+};
+
+__global__ void k_w_place(const uint64_t* __restrict__ fo, const uint64_t* __restrict__ bo,
+                          const uint64_t* __restrict__ co, uint64_t ns, uint32_t* __restrict__ gs,
+                          uint64_t* __restrict__ boff, uint64_t* __restrict__ sizes) {
+  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < ns;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    if (fo[s + 1] != fo[s]) {
+      gs[fo[s]] = (uint32_t)s;
+      boff[fo[s]] = bo[s];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    boff[fo[ns]] = bo[ns];
+    sizes[0] = fo[ns];
+    sizes[1] = bo[ns];
+    sizes[2] = co[ns];
   }
 }
 
@@ -2196,6 +2273,10 @@ static void wide_unbind(Ctx* ctx, Ws& ws, uint32_t nG, uint64_t tb, uint64_t max
     k_w_esc2<<<ch, kWT, 0, st>>>(cofs, nG, boff, act, kbits, koff, K, I, V, Kb[par ^ 1u],
                                  Ib[par ^ 1u], Vb[par ^ 1u]);
     HIP_LAUNCH_CHECK();
+    // the host looks at the active count every kRoundsPerCheck rounds only,
+    // so that the rounds in between go to the GPU without a wait (a round
+    // after the last segment has ended has no chunk and changes nothing)
+    if (it % kRoundsPerCheck != 0 && it != max_iter) continue;
     uint32_t still = 0;
     HIP_CHECK(hipMemcpyAsync(&still, nact, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
@@ -2299,8 +2380,8 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   // then the lists (cursor order)
   for (int fill = 0; fill < 2; ++fill) {
     if (fill) {
-      k_offsets<<<1, kHT, 0, st>>>(leaf_cnt, ns, leaf_off);
-      k_offsets<<<1, kHT, 0, st>>>(iso_cnt, ns, iso_off);
+      scan_offsets(ws, CountOf{leaf_cnt}, ns, leaf_off, st);
+      scan_offsets(ws, CountOf{iso_cnt}, ns, iso_off, st);
       k_fill_u32<<<blocks_for(ns), kHB, 0, st>>>(leaf_cnt, ns, 0);
       k_fill_u32<<<blocks_for(ns), kHB, 0, st>>>(iso_cnt, ns, 0);
       HIP_LAUNCH_CHECK();
@@ -2345,7 +2426,7 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   k_bound<<<(unsigned)ns, kHT, 0, st>>>(h->s_depth, h->s_host, ext, out->centre, iso_cnt, LC,
                                         out->radius, bound, coarse);
   HIP_LAUNCH_CHECK();
-  k_offsets<<<1, kHT, 0, st>>>(bound, ns, out->cand_off);
+  scan_offsets(ws, CountOf{bound}, ns, out->cand_off, st);
   HIP_LAUNCH_CHECK();
   // the wide set (structures with at least `large` possible candidates) and
   // every structure's mode
@@ -2353,7 +2434,15 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
   uint64_t* boff = ws.get<uint64_t>(ns + 1);
   uint64_t* wsz = ws.get<uint64_t>(3);
   uint32_t* mode = ws.get<uint32_t>(ns);
-  k_w_list<<<1, kHT, 0, st>>>(out->cand_off, ns, large, gs, boff, wsz);
+  {
+    uint64_t* fo = ws.get<uint64_t>(ns + 1);
+    uint64_t* bo = ws.get<uint64_t>(ns + 1);
+    uint64_t* co = ws.get<uint64_t>(ns + 1);
+    scan_offsets(ws, WideVal{out->cand_off, large, 0}, ns, fo, st);
+    scan_offsets(ws, WideVal{out->cand_off, large, 1}, ns, bo, st);
+    scan_offsets(ws, WideVal{out->cand_off, large, 2}, ns, co, st);
+    k_w_place<<<blocks_for(ns), kHB, 0, st>>>(fo, bo, co, ns, gs, boff, wsz);
+  }
   HIP_LAUNCH_CHECK();
   k_w_mode<<<blocks_for(ns), kHB, 0, st>>>(out->cand_off, ns, large, mode);
   HIP_LAUNCH_CHECK();
@@ -2434,7 +2523,7 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
     uint32_t* wc = ws.get<uint32_t>(nG);
     uint64_t* coff = ws.get<uint64_t>(nG + 1);
     k_w_counts<<<blocks_for(nG), kHB, 0, st>>>(gs, nG, out->cand_cnt, wc);
-    k_offsets<<<1, kHT, 0, st>>>(wc, nG, coff);
+    scan_offsets(ws, CountOf{wc}, nG, coff, st);
     HIP_LAUNCH_CHECK();
     uint64_t tc = 0;
     HIP_CHECK(hipMemcpyAsync(&tc, coff + nG, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
