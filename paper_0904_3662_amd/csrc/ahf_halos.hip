@@ -392,27 +392,54 @@ __device__ inline double pmass(const PartIn& P, uint32_t i) {
   return P.mass ? (double)P.R[i].vm.w : P.mass_scalar;
 }
 
+// LDS written by some lanes of a wave and read by others, within the wave
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // the records of the n particles (F: all three fractions are given, else
 // each may be null; M: the masses are given; as template arguments, so that
-// every load of a particle is issued at once)
+// every load of a particle is issued at once).  Each wave forms 64 records,
+// one per lane, in LDS and writes them out as 4 KB of consecutive 16-byte
+// pieces (lanes 16 bytes apart instead of 64).
+constexpr int kStageBlocks = 1024;  // half the GPU's waves: the list kernels run beside it
 template <bool F, bool M>
-__global__ void k_stage(PartIn P, uint64_t n, PRec* __restrict__ R) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t X = P.X[i], Y = P.Y[i], Z = P.Z[i];
-    const float fx = (F || P.fx) ? P.fx[i] : 0.0f;
-    const float fy = (F || P.fy) ? P.fy[i] : 0.0f;
-    const float fz = (F || P.fz) ? P.fz[i] : 0.0f;
-    const float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
-    const float m = M ? P.mass[i] : 0.0f;
-    PRec r;
-    r.x = ((double)X + (double)fx) * kQuantum;  // as coord()
-    r.y = ((double)Y + (double)fy) * kQuantum;
-    r.z = ((double)Z + (double)fz) * kQuantum;
-    r.spare = 0.0;
-    r.vm = make_float4(vx, vy, vz, m);
-    r.pad[0] = r.pad[1] = r.pad[2] = r.pad[3] = 0u;
-    R[i] = r;
+__global__ __launch_bounds__(256) void k_stage(PartIn P, uint64_t n, PRec* __restrict__ R) {
+  __shared__ uint4 buf[4][64 * 4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint4* wb = buf[w];
+  for (uint64_t base = ((uint64_t)blockIdx.x * 4 + w) * 64; base < n;
+       base += (uint64_t)gridDim.x * 256) {
+    const uint64_t i = base + lane;
+    if (i < n) {
+      const uint32_t X = P.X[i], Y = P.Y[i], Z = P.Z[i];
+      const float fx = (F || P.fx) ? P.fx[i] : 0.0f;
+      const float fy = (F || P.fy) ? P.fy[i] : 0.0f;
+      const float fz = (F || P.fz) ? P.fz[i] : 0.0f;
+      const float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+      const float m = M ? P.mass[i] : 0.0f;
+      const double x = ((double)X + (double)fx) * kQuantum;  // as coord()
+      const double y = ((double)Y + (double)fy) * kQuantum;
+      const double z = ((double)Z + (double)fz) * kQuantum;
+      const uint64_t bx = (uint64_t)__double_as_longlong(x), by = (uint64_t)__double_as_longlong(y);
+      const uint64_t bz = (uint64_t)__double_as_longlong(z);
+      wb[lane * 4 + 0] = make_uint4((uint32_t)bx, (uint32_t)(bx >> 32), (uint32_t)by,
+                                    (uint32_t)(by >> 32));
+      wb[lane * 4 + 1] = make_uint4((uint32_t)bz, (uint32_t)(bz >> 32), 0u, 0u);
+      wb[lane * 4 + 2] = make_uint4(__float_as_uint(vx), __float_as_uint(vy), __float_as_uint(vz),
+                                    __float_as_uint(m));
+      wb[lane * 4 + 3] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    wave_lds_sync();
+    uint4* out = reinterpret_cast<uint4*>(R + base);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = j * 64 + lane;  // piece q of the wave's 4 KB: record q / 4
+      if (base + (uint64_t)(q >> 2) < n) out[q] = wb[q];
+    }
+    wave_lds_sync();
   }
 }
 
@@ -2324,7 +2351,7 @@ static void find_halos(Ctx* ctx, Ws& ws, const Hier* h, const ahf_particles& p, 
     PRec* R = ws.get<PRec>(n ? n : 1);
     HIP_CHECK(hipEventRecord(ev.fork, st));
     HIP_CHECK(hipStreamWaitEvent(s2, ev.fork, 0));
-    const unsigned nb = blocks_for(n ? n : 1);
+    const unsigned nb = std::min<unsigned>(blocks_for(n ? n : 1), kStageBlocks);
     const bool F = P.fx && P.fy && P.fz;
     if (F && P.mass) k_stage<true, true><<<nb, kHB, 0, s2>>>(P, n, R);
     else if (F) k_stage<true, false><<<nb, kHB, 0, s2>>>(P, n, R);
