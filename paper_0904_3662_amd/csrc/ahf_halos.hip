@@ -1286,7 +1286,19 @@ constexpr int kWT = 256;                 // threads of the chunk kernels
 constexpr int kWE = 16;                  // particles per thread and chunk
 constexpr uint32_t kWC = kWT * kWE;      // particles per chunk
 constexpr uint32_t kRoundsPerCheck = 4;  // unbinding rounds per host read of the active count
-constexpr int kTruncShift = 64 - kRadiusBits;  // radius bits the sort leaves out
+// The grid's sort orders a radius r by (bits(r) - bits(kHalfQuantum)) >>
+// shift: radii run from kHalfQuantum (the clamp) to below 1 (a minimum-image
+// distance in the unit box), so the difference stays below 2^kRadSpan, and
+// the radius part of a key is kRadSpan - shift bits wide.  The width is the
+// widest that lets every sort pass move one packed word (key and index in 64
+// bits), at most kRadiusBits, and kRadiusBits (with pairs in the first
+// passes) where that would leave fewer than kMinRadBits.
+constexpr int kRadSpan = 57;
+static_assert(kQBits + 1 <= 32, "radii in [kHalfQuantum, 1) span at most 32 binary exponents");
+constexpr int kMinRadBits = 28;
+__device__ inline uint64_t wide_radius(double r, int shift) {
+  return ((uint64_t)__double_as_longlong(r) - (uint64_t)__double_as_longlong(kHalfQuantum)) >> shift;
+}
 
 // segment (wide structure) and chunk of block b in this round's chunk table
 // (cofs: nG + 1 exclusive chunk offsets); false past the table's end
@@ -1339,16 +1351,17 @@ __global__ void k_w_place(const uint64_t* __restrict__ fo, const uint64_t* __res
   }
 }
 
-// sort keys of the wide arrays: (segment << kRadiusBits) | top radius bits
-// for a candidate, all ones below the segment for the slack past its count
-// (it sorts to the segment's end), and the digit histograms of the sort;
+// sort keys of the wide arrays: (segment << rbits) | wide_radius for a
+// candidate, all ones below the segment for the slack past its count (it
+// sorts to the segment's end), and the digit histograms of the sort;
 // word_ib >= 0: the sort starts on packed words (key << word_ib) | position
 __global__ __launch_bounds__(256) void k_w_keys(const uint32_t* __restrict__ gs,
                                                 const uint64_t* __restrict__ boff, uint32_t nG,
                                                 const uint64_t* __restrict__ cand_off,
                                                 const uint32_t* __restrict__ cand_cnt,
-                                                const double* __restrict__ rad, int npass,
-                                                int word_ib, uint64_t* __restrict__ keys,
+                                                const double* __restrict__ rad, int rbits,
+                                                int npass, int word_ib,
+                                                uint64_t* __restrict__ keys,
                                                 uint32_t* __restrict__ ghist) {
   __shared__ uint32_t h[kRsMaxPass * 256];
   for (int i = threadIdx.x; i < kRsMaxPass * 256; i += 256) h[i] = 0u;
@@ -1367,10 +1380,9 @@ __global__ __launch_bounds__(256) void k_w_keys(const uint32_t* __restrict__ gs,
       }
       const uint64_t k = p - boff[lo];
       const uint32_t s = gs[lo];
-      const uint64_t t = k < cand_cnt[s]
-                             ? (uint64_t)__double_as_longlong(rad[cand_off[s] + k]) >> kTruncShift
-                             : (1ull << kRadiusBits) - 1ull;
-      key = ((uint64_t)lo << kRadiusBits) | t;
+      const uint64_t t = k < cand_cnt[s] ? wide_radius(rad[cand_off[s] + k], kRadSpan - rbits)
+                                         : (1ull << rbits) - 1ull;
+      key = ((uint64_t)lo << rbits) | t;
       keys[p] = word_ib >= 0 ? ((key << word_ib) | p) : key;
     }
     wave_digit_hist(key, valid, npass, h);
@@ -1383,7 +1395,7 @@ __global__ __launch_bounds__(256) void k_w_keys(const uint32_t* __restrict__ gs,
 // sorted position p: its candidate (the sort's payload is the input position,
 // whose segment is p's own): whole radius, particle, velocity and mass, and
 // the sort key for the tie runs
-__global__ void k_w_gather(const uint64_t* __restrict__ words, int ib,
+__global__ void k_w_gather(const uint64_t* __restrict__ words, int ib, int rbits,
                            const uint32_t* __restrict__ gs, const uint64_t* __restrict__ boff,
                            uint32_t nG, const uint64_t* __restrict__ cand_off,
                            const uint32_t* __restrict__ cand_cnt,
@@ -1409,7 +1421,7 @@ __global__ void k_w_gather(const uint64_t* __restrict__ words, int ib,
     K[p] = rb;
     I[p] = cand[slot];
     V[p] = vq[slot];
-    Kt[p] = ((uint64_t)lo << kRadiusBits) | (rb >> kTruncShift);
+    Kt[p] = ((uint64_t)lo << rbits) | wide_radius(rad[slot], kRadSpan - rbits);
   }
 }
 
@@ -2218,16 +2230,20 @@ static void wide_unbind(Ctx* ctx, Ws& ws, uint32_t nG, uint64_t tb, uint64_t max
                         AfterTies after_ties) {
   int gbits = 1;
   while ((1ull << gbits) < nG) ++gbits;
-  if (kRadiusBits + gbits > 64)  // the sort key is (structure, top radius bits)
+  int ib = 1;  // the index width of the sort's packed words
+  while (ib < 32 && (1ull << ib) < tb) ++ib;
+  int rbits = std::min(kRadiusBits, 64 - ib - gbits);
+  if (rbits < kMinRadBits) rbits = kRadiusBits;
+  if (rbits + gbits > 64)  // the sort key is (structure, radius part)
     throw Error{AHF_ELIMIT, "too many structures for the grid's unbinding (raise large_from)"};
-  const SortPlan sp = sort_plan(tb, kRadiusBits + gbits);
+  const SortPlan sp = sort_plan(tb, rbits + gbits);
   uint64_t* keys = ws.get<uint64_t>(tb);
   uint32_t* ghist = ws.get<uint32_t>(kRsMaxPass * 256);
   k_fill_u32<<<blocks_for(kRsMaxPass * 256), kHB, 0, st>>>(ghist, kRsMaxPass * 256, 0);
   HIP_LAUNCH_CHECK();
   const unsigned kb = std::min<unsigned>(blocks_for(tb), 2048u);
-  k_w_keys<<<kb, 256, 0, st>>>(gs, boff, nG, out->cand_off, out->cand_cnt, rad, sp.npass,
-                               sp.q == 0 ? sp.ib : -1, keys, ghist);
+  k_w_keys<<<kb, 256, 0, st>>>(gs, boff, nG, out->cand_off, out->cand_cnt, rad, rbits,
+                               sp.npass, sp.q == 0 ? sp.ib : -1, keys, ghist);
   HIP_LAUNCH_CHECK();
   const uint64_t* words = sort_keys(ctx, ws, keys, tb, sp, ghist, st, nullptr);
   uint64_t* Kb[2] = {ws.get<uint64_t>(tb), ws.get<uint64_t>(tb)};
@@ -2236,7 +2252,7 @@ static void wide_unbind(Ctx* ctx, Ws& ws, uint32_t nG, uint64_t tb, uint64_t max
   uint64_t* Kt = ws.get<uint64_t>(tb);
   double* M = ws.get<double>(tb);
   double* T = ws.get<double>(tb);
-  k_w_gather<<<blocks_for(tb), kHB, 0, st>>>(words, sp.ib, gs, boff, nG, out->cand_off,
+  k_w_gather<<<blocks_for(tb), kHB, 0, st>>>(words, sp.ib, rbits, gs, boff, nG, out->cand_off,
                                              out->cand_cnt, out->cand, rad, vslot, Kb[0], Ib[0],
                                              Vb[0], Kt);
   HIP_LAUNCH_CHECK();
