@@ -137,6 +137,27 @@ def test_halos_without_position_fractions(given):
     compare(res, ores, "fractions " + given, p)
 
 
+def test_halos_with_a_ragged_particle_count():
+    """A particle count that is not a multiple of a wave (the last wave of the
+    particle records, and of every per-particle pass, is partial): the 32k
+    mixed set less 37 particles, against the oracle on the same particles."""
+    import dataclasses
+    p = synth.small_mixed(2, velocities=True)
+    keep = slice(0, p.n - 37)
+    p = dataclasses.replace(p, X=p.X[keep].copy(), Y=p.Y[keep].copy(), Z=p.Z[keep].copy(),
+                            fx=p.fx[keep].copy(), fy=p.fy[keep].copy(), fz=p.fz[keep].copy(),
+                            mass=None if p.mass is None else p.mass[keep].copy(),
+                            vel=p.vel[keep].copy())
+    assert p.n % 64 != 0
+    for large in (0, 100):
+        res, again = device_halos(p, large_from=large)
+        ores, _ = oracle_halos(p)
+        assert len(ores) > 3
+        compare(res, ores, f"ragged, large_from {large}", p)
+        for k in ("centre", "radius", "r_vir", "m_vir", "vel", "iterations"):
+            assert np.array_equal(res[k], again[k]), k
+
+
 def test_halos_need_a_classified_hierarchy():
     import torch
     from paper_0904_3662_amd import ahf
