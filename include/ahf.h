@@ -448,7 +448,9 @@ typedef struct ahf_halos ahf_halos;
  * particles the hierarchy was built from (same device arrays or copies; n as
  * built); vx, vy, vz are device arrays of n velocities.  Waits for the work
  * on stream.  The result owns its device memory (ctx's allocator) until
- * ahf_halos_free. */
+ * ahf_halos_free.  Scratch space comes from ctx's workspace (kept for later
+ * calls): one 64-byte record per particle, and per-candidate arrays of some
+ * tens of bytes per possible candidate. */
 ahf_status ahf_find_halos(ahf_ctx *ctx, const ahf_hierarchy *h, const ahf_particles *p,
                           const float *vx, const float *vy, const float *vz,
                           const ahf_halo_params *prm, void *stream, ahf_halos **out);
