@@ -448,7 +448,11 @@ struct StreamEvents {
   hipEvent_t fork = nullptr, join = nullptr;
   StreamEvents() {
     HIP_CHECK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-    HIP_CHECK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    const hipError_t e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e != hipSuccess) {  // the destructor does not run for a constructor that throws
+      (void)hipEventDestroy(fork);
+      throw Error{AHF_EDEVICE, std::string("hipEventCreateWithFlags: ") + hipGetErrorString(e)};
+    }
   }
   ~StreamEvents() {
     if (fork) (void)hipEventDestroy(fork);
