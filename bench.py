@@ -380,6 +380,14 @@ def served_measure(npool, R, streams, fracs):
 #          cell of S_L) and the field (4 B per brick cell) -- the per-level
 #          deposit terms of the algorithmic byte count
 ROOFLINE_KERNELS = ("rs_scatter", "gather", "tile_deposit0", "tile_deposit1")
+# what holds each candidate below its HBM roofline, from the counters in profiles/
+LIMITER = {
+    "rs_scatter": "HBM traffic of the scatter passes",
+    "gather": "random 32-byte record reads, each fetching a whole line",
+    "tile_deposit0": "latency of dependent loads (ranks, cell ranges, records) and the barrier",
+    "tile_deposit1": "latency of dependent loads (ranks, cell ranges, records) and the barrier: "
+                     "0.68 of wave cycles waiting, 0.14 issuing VALU",
+}
 
 
 def kernel_alg_bytes(name, n, key_bits, g, lv_info, launches_per_step):
@@ -469,7 +477,7 @@ def measure(ctx, snap, dev, stream, steps, warmup, extras=True):
                      "traffic": traffic,
                      "traffic_over_algorithmic": None if traffic is None else traffic / alg,
                      "algorithmic_bytes_per_launch": alg, "avg_launch_ms": avg_ms,
-                     "launches": launches},
+                     "launches": launches, "limiter": LIMITER.get(rk)},
         "kernels_ms_per_step": {nm: v[1] for nm, v in ksplit.items()},
         "levels": lv_info,
         # timed builds sized ahead from the context's plan (no host wait per
